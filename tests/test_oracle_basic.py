@@ -1,0 +1,249 @@
+"""Pins of the CPU oracle's basic operations against closed forms and brute force.
+
+Generators, Laplacian (Sec. 2.2), SpMV/residual, colouring, Gauss-Seidel (the
+smoother named in Sec. 4).  None of these tests use the HIP library.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from paper_1806_07028_amd import inputs as I
+
+
+def dense_laplacian(g):
+    n, rp, ci, w = g
+    W = sp.csr_matrix((w, ci, rp), shape=(n, n)).toarray()
+    return np.diag(W.sum(1)) - W
+
+
+# ---------------------------------------------------------------------------
+# SplitMix64: published first outputs of the generator seeded with 0
+# ---------------------------------------------------------------------------
+def test_splitmix64_published_values(oracle):
+    w = I.stream_words(0, 3)
+    assert [int(x) for x in w] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    # oracle's start vector uses the same stream: xi = 2 * (top53 * 2^-53) - 1
+    xi = oracle.xi(3, 0, 0)
+    ref = 2.0 * ((w >> np.uint64(11)).astype(np.float64) * 2.0 ** -53) - 1.0
+    assert np.array_equal(xi, ref)
+    # build r uses counter (r << 32) + i + 1
+    xi2 = oracle.xi(2, 77, 3)
+    w2 = I.stream_words(77, 2, start=3 << 32)
+    assert np.array_equal(xi2, 2.0 * ((w2 >> np.uint64(11)).astype(np.float64) * 2.0 ** -53) - 1.0)
+    assert int(oracle.colour_priority(5, 2, 10)) == int(I.stream_words(5, 1, start=(2 << 32) + 10)[0])
+
+
+def test_generators_shapes():
+    n, rp, ci, w = I.grid2d(64, 64)
+    assert n == 4096 and len(ci) == 2 * 8064
+    n, rp, ci, w = I.grid3d(8, 7, 6)
+    assert len(ci) == 2 * (7 * 7 * 6 + 8 * 6 * 6 + 8 * 7 * 5)
+    # symmetric, sorted, no diagonal
+    A = sp.csr_matrix((w, ci, rp), shape=(n, n))
+    assert (A != A.T).nnz == 0
+    for i in range(n):
+        row = ci[rp[i]:rp[i + 1]]
+        assert np.all(np.diff(row) > 0) and i not in row
+    g = I.rgg(3000, 5)
+    assert g[0] > 2500
+    nrm = I.zero_mean_normal_rhs(3, 1000)
+    assert abs(nrm.sum()) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# Laplacian spectra (closed forms)
+# ---------------------------------------------------------------------------
+def _check_eig(oracle, g, lam, v):
+    n, rp, ci, w = g
+    a, d, dinv = oracle.laplacian(g)
+    q = oracle.spmv(n, rp, ci, a, d, v)
+    scale = max(abs(lam), 1.0) * np.abs(v).max()
+    assert np.abs(q - lam * v).max() <= 1e-13 * 8 * scale
+
+
+@pytest.mark.parametrize("n", [2, 5, 64, 257])
+def test_path_spectrum(oracle, n):
+    g = I.path(n)
+    j = np.arange(n)
+    for k in [0, 1, n // 2, n - 1]:
+        lam = 2 - 2 * np.cos(k * np.pi / n)
+        v = np.cos(k * np.pi * (j + 0.5) / n)
+        _check_eig(oracle, g, lam, v)
+
+
+@pytest.mark.parametrize("n,k", [(12, 2), (100, 2), (64, 4), (1024, 4)])
+def test_ring_spectrum(oracle, n, k):
+    g = I.ring(n, k)
+    j = np.arange(n)
+    for m in [0, 1, 3, n // 3]:
+        lam = sum(2 - 2 * np.cos(2 * np.pi * m * s / n) for s in range(1, k // 2 + 1))
+        v = np.cos(2 * np.pi * m * j / n)
+        _check_eig(oracle, g, lam, v)
+
+
+def test_grid_spectrum(oracle):
+    nx, ny = 9, 6
+    g = I.grid2d(nx, ny)
+    x = np.arange(nx)
+    y = np.arange(ny)
+    for p, q in [(0, 0), (1, 0), (2, 3), (8, 5)]:
+        lam = (2 - 2 * np.cos(p * np.pi / nx)) + (2 - 2 * np.cos(q * np.pi / ny))
+        v = np.outer(np.cos(q * np.pi * (y + 0.5) / ny), np.cos(p * np.pi * (x + 0.5) / nx)).ravel()
+        _check_eig(oracle, g, lam, v)
+
+
+def test_laplacian_rowsum_and_residual(oracle):
+    g = I.grid3d(5, 4, 3)
+    n, rp, ci, w = g
+    a, d, dinv = oracle.laplacian(g)
+    ones = np.ones(n)
+    assert np.all(oracle.spmv(n, rp, ci, a, d, ones) == 0.0)  # integer weights: exact
+    assert np.array_equal(dinv, 1.0 / d)
+    gw = I.grid2d(7, 5, weight_seed=3)
+    n, rp, ci, w = gw
+    a, d, dinv = oracle.laplacian(gw)
+    L = dense_laplacian(gw)
+    x = I.normal(1, n)
+    b = I.normal(2, n)
+    r = oracle.residual(n, rp, ci, a, d, b, x)
+    assert np.allclose(r, b - L @ x, rtol=0, atol=1e-12 * np.abs(L).max() * np.abs(x).max() * 10)
+
+
+# ---------------------------------------------------------------------------
+# Colouring: proper, <= Delta + 1, equals the sequential greedy in priority
+# order, and equals Jones-Plassmann rounds (the GPU algorithm)
+# ---------------------------------------------------------------------------
+def _priorities(seed, level, n):
+    return I.stream_words(seed, n, start=level << 32)
+
+
+def _greedy_colour(n, rp, ci, pr):
+    order = sorted(range(n), key=lambda v: (int(pr[v]), v), reverse=True)
+    col = -np.ones(n, dtype=int)
+    for v in order:
+        used = {col[u] for u in ci[rp[v]:rp[v + 1]] if col[u] >= 0}
+        c = 0
+        while c in used:
+            c += 1
+        col[v] = c
+    return col
+
+
+def _jones_plassmann(n, rp, ci, pr):
+    col = -np.ones(n, dtype=int)
+    key = [(int(pr[v]), v) for v in range(n)]
+    rounds = 0
+    while (col < 0).any():
+        rounds += 1
+        ready = []
+        for v in range(n):
+            if col[v] >= 0:
+                continue
+            nbrs = ci[rp[v]:rp[v + 1]]
+            if all(col[u] >= 0 for u in nbrs if key[u] > key[v]):
+                used = {col[u] for u in nbrs if key[u] > key[v]}
+                c = 0
+                while c in used:
+                    c += 1
+                ready.append((v, c))
+        for v, c in ready:
+            col[v] = c
+    return col, rounds
+
+
+@pytest.mark.parametrize("maker", [lambda: I.grid2d(13, 11), lambda: I.rgg(600, 4), lambda: I.ring(200, 4),
+                                   lambda: I.csr_from_edges(*I.ba_edges(400, 9), np.ones(len(I.ba_edges(400, 9)[1])))])
+def test_colouring(oracle, maker):
+    n, rp, ci, w = maker()
+    for level in (0, 3):
+        col, nc = oracle.colour(n, rp, ci, 0xC010, level)
+        rows = np.repeat(np.arange(n), np.diff(rp))
+        assert np.all(col[rows] != col[ci])
+        assert nc == col.max() + 1 <= np.diff(rp).max() + 1
+        pr = _priorities(0xC010, level, n)
+        assert np.array_equal(col, _greedy_colour(n, rp, ci, pr))
+        jp, _ = _jones_plassmann(n, rp, ci, pr)
+        assert np.array_equal(col, jp)
+
+
+# ---------------------------------------------------------------------------
+# Gauss-Seidel: one coloured sweep is the dense triangular solve in colour order
+# ---------------------------------------------------------------------------
+def test_gs_equals_dense_triangular(oracle):
+    g = I.grid2d(9, 8, weight_seed=5)
+    n, rp, ci, w = g
+    a, d, dinv = oracle.laplacian(g)
+    col, nc = oracle.colour(n, rp, ci, 7, 0)
+    L = dense_laplacian(g)
+    b = I.normal(11, n)
+    x0 = I.normal(12, n)
+    # forward: rows of lower colour updated first
+    lower = col[None, :] < col[:, None]
+    upper = col[None, :] > col[:, None]
+    M = np.diag(np.diag(L)) + np.where(lower, L, 0)
+    N = np.where(upper, L, 0)
+    ref = sla.solve_triangular(M[np.ix_(np.argsort(col, kind="stable"), np.argsort(col, kind="stable"))],
+                               (b - N @ x0)[np.argsort(col, kind="stable")], lower=True)
+    xf = np.empty(n)
+    xf[np.argsort(col, kind="stable")] = ref
+    got = oracle.gs(n, rp, ci, a, dinv, col, nc, b, x0, forward=True)
+    assert np.allclose(got, xf, rtol=1e-13, atol=1e-13 * np.abs(xf).max())
+    # backward: rows of higher colour first
+    Mb = np.diag(np.diag(L)) + np.where(upper, L, 0)
+    Nb = np.where(lower, L, 0)
+    xb = np.linalg.solve(Mb, b - Nb @ x0)
+    got = oracle.gs(n, rp, ci, a, dinv, col, nc, b, x0, forward=False)
+    assert np.allclose(got, xb, rtol=1e-12, atol=1e-12 * np.abs(xb).max())
+
+
+def test_symmetric_gs_is_a_symmetric(oracle):
+    g = I.grid2d(7, 6, weight_seed=2)
+    n, rp, ci, w = g
+    a, d, dinv = oracle.laplacian(g)
+    col, nc = oracle.colour(n, rp, ci, 3, 0)
+    L = dense_laplacian(g)
+    zero = np.zeros(n)
+
+    def E(x):
+        x = oracle.gs(n, rp, ci, a, dinv, col, nc, zero, x, True)
+        return oracle.gs(n, rp, ci, a, dinv, col, nc, zero, x, False)
+
+    x = I.normal(1, n)
+    y = I.normal(2, n)
+    lhs = E(x) @ L @ y
+    rhs = x @ L @ E(y)
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + abs(rhs))
+    # constants are fixed points of the homogeneous sweep
+    c = np.full(n, 0.75)
+    assert np.allclose(E(c), c, rtol=0, atol=1e-15)
+
+
+def test_smooth_error_is_smoother(oracle):
+    g = I.grid2d(32, 32)
+    n, rp, ci, w = g
+    L = dense_laplacian(g)
+    xi = oracle.xi(n, 9, 0)
+    e3 = oracle.smooth_error(g, 0xC010, 9, 3)
+    e0 = oracle.smooth_error(g, 0xC010, 9, 0)
+    assert np.array_equal(e0, xi)
+
+    def rq(v):
+        v = v - v.mean()
+        return v @ L @ v / (v @ v)
+
+    assert rq(e3) < 0.25 * rq(xi)
+    # reproducible bit for bit
+    assert np.array_equal(e3, oracle.smooth_error(g, 0xC010, 9, 3))
+
+
+def test_gs32_close_to_gs64(oracle):
+    g = I.grid2d(16, 16, weight_seed=4)
+    n, rp, ci, w = g
+    a, d, dinv = oracle.laplacian(g)
+    col, nc = oracle.colour(n, rp, ci, 3, 0)
+    b = I.normal(1, n)
+    x64 = oracle.gs(n, rp, ci, a, dinv, col, nc, b, np.zeros(n), True)
+    x32 = oracle.gs32(n, rp, ci, a.astype(np.float32), dinv.astype(np.float32), col, nc, b.astype(np.float32),
+                      np.zeros(n, np.float32), True)
+    assert np.abs(x32 - x64).max() <= 1e-5 * np.abs(x64).max()

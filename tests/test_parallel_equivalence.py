@@ -1,0 +1,235 @@
+"""The GPU builds the sequential greedy decisions of Alg. 1 (path cover) and of
+Alg. 3 Steps 9-19 (isolated vertices) with deterministic reservations, and the
+path orientation with pointer jumping.  These CPU simulations of exactly those
+parallel schedules must reproduce the sequential oracle on random inputs,
+whatever the window size.  No HIP code is involved.
+"""
+import numpy as np
+import pytest
+
+from paper_1806_07028_amd import inputs as I
+
+INF = 1 << 62
+
+
+def reservation_path_cover(n, su, sv, window):
+    """Rounds over a window of the pending edges (rank order).  An edge that is
+    not rejected reserves {u, v, far end of u, far end of v} with its rank and
+    commits iff it holds all four."""
+    m = len(su)
+    deg = np.zeros(n, int)
+    other = np.arange(n)
+    nb = -np.ones((n, 2), int)
+    pending = list(range(m))
+    rounds = 0
+    while pending:
+        rounds += 1
+        win = pending[:window]
+        res = {}
+        ends = {}
+        done = set()
+        for t in win:
+            u, v = su[t], sv[t]
+            if deg[u] >= 2 or deg[v] >= 2 or other[u] == v:
+                done.add(t)
+                continue
+            a, b = other[u], other[v]
+            ends[t] = (a, b)
+            for s in (u, v, a, b):
+                res[s] = min(res.get(s, INF), t)
+        for t, (a, b) in ends.items():
+            u, v = su[t], sv[t]
+            if all(res[s] == t for s in (u, v, a, b)):
+                nb[u, deg[u]] = v
+                nb[v, deg[v]] = u
+                deg[u] += 1
+                deg[v] += 1
+                other[a] = b
+                other[b] = a
+                done.add(t)
+        pending = [t for t in pending if t not in done]
+    return nb, rounds
+
+
+def edge_set(nb):
+    s = set()
+    for v, row in enumerate(np.asarray(nb).reshape(-1, 2)):
+        for u in row:
+            if u >= 0:
+                s.add((min(u, v), max(u, v)))
+    return s
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_reservation_path_cover_equals_greedy(oracle, seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(4, 40))
+    m = int(rng.integers(n, 4 * n))
+    a = rng.integers(0, n, m)
+    b = rng.integers(0, n, m)
+    a, b = I.canonical_edges(a, b)
+    order = rng.permutation(len(a))
+    su, sv = a[order].astype(np.int32), b[order].astype(np.int32)
+    ref = oracle.path_cover(n, su, sv)
+    for window in (1, 3, 17, 10 ** 6):
+        got, _ = reservation_path_cover(n, su, sv, window)
+        assert edge_set(got) == edge_set(ref)
+
+
+def test_reservation_path_cover_grid(oracle):
+    g = I.grid2d(30, 30, weight_seed=3)
+    n, rp, ci, w = g
+    e = oracle.smooth_error(g, 1, 5, 3)
+    rp2, ci2 = oracle.a2_pattern(n, rp, ci)
+    su, sv = oracle.sorted_edges(n, rp2, ci2, e)
+    ref = oracle.path_cover(n, su, sv)
+    got, rounds = reservation_path_cover(n, su, sv, 4096)
+    assert edge_set(got) == edge_set(ref)
+    assert rounds < len(su) // 4
+
+
+def pointer_jump_orient(nb):
+    """Half-edge list ranking: for vertex v and direction d the end reached and
+    the distance; path start = smaller end; pos = distance to the start."""
+    nb = np.asarray(nb).reshape(-1, 2)
+    n = len(nb)
+    # half-edge h = 2v + d follows nb[v][d]
+    nxt = -np.ones(2 * n, int)
+    end = -np.ones(2 * n, int)
+    dist = np.zeros(2 * n, int)
+    for v in range(n):
+        for d in range(2):
+            w = nb[v, d]
+            if w < 0:
+                continue
+            # continue from w away from v
+            dd = 0 if nb[w, 1] == v else 1
+            if nb[w, dd] < 0 or nb[w, dd] == v:
+                end[2 * v + d] = w
+                dist[2 * v + d] = 1
+            else:
+                nxt[2 * v + d] = 2 * w + dd
+                dist[2 * v + d] = 1
+    while (nxt >= 0).any():
+        nxt2, dist2, end2 = nxt.copy(), dist.copy(), end.copy()
+        for h in range(2 * n):
+            if nxt[h] >= 0:
+                j = nxt[h]
+                dist2[h] = dist[h] + dist[j]
+                nxt2[h] = nxt[j]
+                end2[h] = end[j]
+        nxt, dist, end = nxt2, dist2, end2
+    pid = -np.ones(n, int)
+    pos = -np.ones(n, int)
+    for v in range(n):
+        ends = [(v, 0)] if (nb[v] < 0).any() else []
+        for d in range(2):
+            if nb[v, d] >= 0:
+                ends.append((end[2 * v + d], dist[2 * v + d]))
+        if nb[v, 0] < 0 and nb[v, 1] < 0:
+            continue
+        s, p = min(ends)
+        pid[v] = s
+        pos[v] = p
+    return pid, pos
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_pointer_jumping_orientation(oracle, seed):
+    g = I.rgg(500, seed + 1)
+    n, rp, ci, w = g
+    e = oracle.smooth_error(g, 1, seed, 3)
+    rp2, ci2 = oracle.a2_pattern(n, rp, ci)
+    su, sv = oracle.sorted_edges(n, rp2, ci2, e)
+    nb = oracle.path_cover(n, su, sv)
+    pid, pos, plen, _ = oracle.orient(nb)
+    gp, gpos = pointer_jump_orient(nb)
+    assert np.array_equal(gp, pid) and np.array_equal(gpos, pos)
+
+
+def reservation_repair(n, grp, gci, gw, gkey, obj, members, window):
+    """Alg. 3 Steps 9-19 by reservations with priority = vertex id.  An iterate
+    u reserves its own slot, its best neighbour v and v's aggregate object."""
+    best = -np.ones(n, int)
+    for u in range(n):
+        lo, hi = grp[u], grp[u + 1]
+        if hi == lo:
+            continue
+        if gkey is not None:
+            k = min(range(lo, hi), key=lambda t: (gkey[t], gci[t]))
+        else:
+            k = min(range(lo, hi), key=lambda t: (-gw[t], gci[t]))
+        best[u] = gci[k]
+    adj = lambda a, b: b in set(gci[grp[a]:grp[a + 1]].tolist())
+    obj = list(obj)
+    members = {k: list(v) for k, v in members.items()}
+    pending = [u for u in range(n) if obj[u] < 0]
+    while pending:
+        pending = [u for u in pending if obj[u] < 0]
+        if not pending:
+            break
+        win = pending[:window]
+        rv, ro = {}, {}
+        plan = {}
+        for u in win:
+            v = best[u]
+            slots_v = [u] + ([v] if v >= 0 else [])
+            slots_o = [obj[v]] if v >= 0 and obj[v] >= 0 else []
+            plan[u] = (slots_v, slots_o)
+            for s in slots_v:
+                rv[s] = min(rv.get(s, INF), u)
+            for s in slots_o:
+                ro[s] = min(ro.get(s, INF), u)
+        for u in win:
+            sv_, so_ = plan[u]
+            if not (all(rv[s] == u for s in sv_) and all(ro[s] == u for s in so_)):
+                continue
+            v = best[u]
+            if v < 0:
+                members[u] = [u]
+                obj[u] = u
+            elif obj[v] < 0:
+                members[u] = [u, v]
+                obj[u] = obj[v] = u
+            else:
+                T = obj[v]
+                if len(members[T]) <= 2:
+                    members[T].append(u)
+                    obj[u] = T
+                else:
+                    rest = [x for x in members[T] if x != v]
+                    if adj(rest[0], rest[1]):
+                        members[T] = rest
+                        members[u] = [u, v]
+                        obj[u] = obj[v] = u
+                    else:
+                        members[u] = [u]
+                        obj[u] = u
+    # canonical ids by smallest member
+    live = sorted((min(m), k) for k, m in members.items() if m)
+    canon = {k: i for i, (_, k) in enumerate(live)}
+    return np.array([canon[obj[v]] for v in range(n)])
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_reservation_repair_equals_sequential(oracle, seed):
+    g = I.rgg(700, 50 + seed)
+    n, rp, ci, w = g
+    e = oracle.smooth_error(g, 1, seed, 3)
+    H = oracle.Hierarchy(g, e, coarse_max=8)
+    for level in range(min(3, H.nlevels - 1)):
+        grp, gci, gw = H.get_int(level, "G_rp"), H.get_int(level, "G_ci"), H.get_dbl(level, "G_v")
+        gkey = H.get_dbl(level, "gkey") if level == 0 else None
+        nb = H.get_int(level, "nb").reshape(-1, 2)
+        ref, nc, _ = oracle.aggregate(len(nb), grp, gci, gw, nb, gkey)
+        pid, pos, plen, _ = oracle.orient(nb)
+        obj = -np.ones(len(nb), int)
+        members = {}
+        for v in range(len(nb)):
+            if pid[v] >= 0 and pos[v] % 2 == 0 and pos[v] + 1 < plen[v]:
+                w_ = [u for u in nb[v] if u >= 0 and pos[u] == pos[v] + 1][0]
+                obj[v] = obj[w_] = v
+                members[v] = [v, w_]
+        for window in (1, 5, 10 ** 6):
+            got = reservation_repair(len(nb), grp, gci, gw, gkey, obj, members, window)
+            assert np.array_equal(got, ref)
