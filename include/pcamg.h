@@ -1,0 +1,270 @@
+/*
+ * pcamg.h -- C ABI of the MI355X (gfx950) path-cover adaptive AMG library.
+ *
+ * Method: Hu, Lin & Zikatanov, "An Adaptive Multigrid Method Based on Path
+ * Cover" (arXiv 1806.07028): PC-alphaAMG for weighted graph Laplacians
+ * L x = b.  Every step runs in this library's HIP kernels on the GPU.
+ *
+ * Conventions for every entry point:
+ *  - Return a pcamg_status (0 = OK, negative = error); no exception crosses
+ *    the ABI.  pcamg_last_error() gives a thread-local message for the last
+ *    failure of the calling thread.
+ *  - "device" pointers are HIP device memory (e.g. torch.cuda tensors' data
+ *    pointers) on the current device; "host" pointers are ordinary memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    work is enqueued on it; functions that return sizes or statistics
+ *    synchronise the stream before returning.
+ *  - Graphs are symmetric CSR with int32 indices: row_ptr[n+1], col_idx[nnz]
+ *    ascending within each row, no diagonal entries, no duplicates, weights
+ *    w > 0 finite and w(i,j) == w(j,i) bitwise (the paper's preprocessing,
+ *    Sec. 4.3: connected, no self loops, positive weights, undirected).
+ *  - The caller owns every array it passes; the library copies what it keeps.
+ *    Outputs are written into caller-allocated arrays of the stated sizes.
+ */
+#ifndef PCAMG_H
+#define PCAMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pcamg_status;
+enum {
+  PCAMG_OK = 0,
+  PCAMG_EINVAL = -1,        /* bad argument (NULL, size, unknown name) */
+  PCAMG_ENOTSYM = -2,       /* graph pattern or weights not symmetric */
+  PCAMG_ESELFLOOP = -3,     /* diagonal entry present */
+  PCAMG_EDUPEDGE = -4,      /* columns not strictly ascending */
+  PCAMG_EWEIGHT = -5,       /* weight <= 0 or not finite */
+  PCAMG_EDISCONNECTED = -6, /* graph has more than one component */
+  PCAMG_ERHS = -7,          /* |sum b| > 1e-12 sum |b| or not finite */
+  PCAMG_ENOMEM = -8,
+  PCAMG_EHIP = -9,          /* HIP runtime error */
+  PCAMG_ENOCONV = -10,      /* max_iter reached */
+  PCAMG_EBREAKDOWN = -11,   /* p^T A p <= 0 in the Krylov iteration */
+  PCAMG_ENAN = -12,         /* residual became NaN/Inf */
+  PCAMG_EUNSUPPORTED = -13  /* input outside this build's limits (e.g. row too long) */
+};
+
+typedef struct pcamg_ctx pcamg_ctx;
+
+typedef struct {
+  int32_t n;                /* vertices */
+  int32_t nnz;              /* stored entries = 2 |E| */
+  const int32_t* row_ptr;   /* device [n+1] */
+  const int32_t* col_idx;   /* device [nnz] */
+  const double* weight;     /* device [nnz] */
+} pcamg_graph;
+
+enum { PCAMG_OUTER_VCYCLE = 0, PCAMG_OUTER_FCG = 1 };
+enum { PCAMG_PREC_F64 = 0, PCAMG_PREC_F32 = 1 };
+enum { PCAMG_P1_SMOOTH = 0, PCAMG_P1_CONST = 1 };
+enum { PCAMG_COARSE_AUTO = 0, PCAMG_COARSE_GROUNDED = 1, PCAMG_COARSE_FULL = 2 };
+enum { PCAMG_REBUILD_ERROR_APPROX = 0, PCAMG_REBUILD_RELAX = 1 };
+
+typedef struct {
+  double tol;              /* relative residual ||b - A x|| / ||b|| (default 1e-8, Sec. 4) */
+  double theta;            /* re-setup threshold on the mean ConvR since the last re-setup (Alg. 5; 0.4) */
+  int32_t max_iter;        /* 2500 (Sec. 4: "--" beyond 2500 iterations) */
+  int32_t outer;           /* PCAMG_OUTER_VCYCLE (Alg. 5) or PCAMG_OUTER_FCG (V-cycle preconditioned FCG) */
+  int32_t cycle_prec;      /* FCG preconditioner precision: PCAMG_PREC_F64 or PCAMG_PREC_F32 */
+  int32_t coarse_max;      /* coarsest level size (64) */
+  int32_t relax_sweeps;    /* symmetric GS sweeps on A e = 0 before each build (3) */
+  int32_t rebuild_vcycles; /* V-cycles on A e = 0 (PCAMG_REBUILD_RELAX only; 2) */
+  int32_t rebuild_source;  /* PCAMG_REBUILD_ERROR_APPROX (Alg. 2, default) or PCAMG_REBUILD_RELAX */
+  int32_t p1_mode;         /* PCAMG_P1_SMOOTH (Sec. 3.3, default) or PCAMG_P1_CONST */
+  int32_t coarse_solve;    /* PCAMG_COARSE_AUTO / GROUNDED / FULL */
+  int32_t a2_hub_cap;      /* 0 = exact A^2 pattern; K > 0: two-step pairs only via degree <= K */
+  int32_t max_rebuilds;    /* 50 */
+  int32_t max_levels;      /* 40 */
+  int32_t numW, iterW, iterV; /* Alg. 2 parameters (2, 7, 4; Sec. 4) */
+  int32_t rebuild_rule;    /* 0 mean ConvR since last re-setup (Alg. 5), 1 last ConvR (Alg. 6) */
+  int32_t keep_setup;      /* 1 = keep per-level setup arrays for pcamg_level_get */
+  int32_t validate;        /* 1 = check the graph (symmetry, weights, connectivity) in pcamg_setup */
+  uint64_t seed;           /* start-vector stream */
+  uint64_t colour_seed;    /* colouring priority stream */
+} pcamg_params;
+
+typedef struct {
+  int32_t iterations, rebuilds, levels, status;
+  double relres;           /* recursive residual ratio at exit */
+  double true_relres;      /* ||b - A x|| / ||b|| recomputed at exit */
+  double rho_geo;          /* (relres)^(1/iterations) */
+  double convr_last10;     /* mean ConvR over the last 10 iterations (Sec. 4) */
+  double op_complexity;    /* mean operator complexity over all hierarchies (Sec. 4) */
+  double t_setup_ms;       /* first hierarchy (pcamg_setup) */
+  double t_solve_ms;       /* whole pcamg_solve call */
+  double t_rebuild_ms;     /* re-setups inside the solve (Alg. 2 + Alg. 4) */
+  int32_t vcycles64, vcycles32, wcycles; /* cycle applications by kind */
+  int32_t hist_len;        /* entries written to relres_hist */
+  double* relres_hist;     /* host, optional: relres after each iteration (index 0 = 1.0) */
+  int32_t hist_cap;        /* capacity of relres_hist */
+} pcamg_stats;
+
+const char* pcamg_status_str(pcamg_status s);
+const char* pcamg_last_error(void);
+
+/* Defaults listed above. */
+pcamg_status pcamg_params_default(pcamg_params* p);
+
+/* ------------------------------------------------------------------------
+ * Solver (Alg. 5)
+ * ------------------------------------------------------------------------ */
+
+/* Validate the graph (if p->validate), build the Laplacian A = D - W
+ * (Sec. 2.2), colour the finest level and build the first hierarchy (Alg. 4)
+ * from a start vector relaxed by relax_sweeps symmetric GS sweeps on A e = 0.
+ * rhs (device [n], nullable) must be zero-sum (PCAMG_ERHS otherwise); it can
+ * be given later with pcamg_set_rhs.  On success *out owns all device memory
+ * of the solver until pcamg_destroy. */
+pcamg_status pcamg_setup(const pcamg_graph* g, const double* rhs, const pcamg_params* p, void* stream,
+                         pcamg_ctx** out);
+
+/* Replace the right-hand side (device [n], zero-sum). */
+pcamg_status pcamg_set_rhs(pcamg_ctx* c, const double* rhs);
+
+/* Adaptive solve (Alg. 5): V(1,1)-cycles (or FCG with a V-cycle
+ * preconditioner), x made orthogonal to 1 after each step, ConvR =
+ * ||r_{k+1}|| / ||r_k||, re-setup when the mean ConvR since the last re-setup
+ * exceeds theta: error approximation (Alg. 2) over all hierarchies so far,
+ * relaxation, new hierarchy (Alg. 4), x <- x + e.  x: device [n], input x0,
+ * output x.  st: host, nullable.  Returns PCAMG_ENOCONV if tol is not
+ * reached in max_iter iterations (x still holds the last iterate). */
+pcamg_status pcamg_solve(pcamg_ctx* c, double* x, pcamg_stats* st);
+
+/* Build one more hierarchy (Alg. 4) from the smooth error e (device [n],
+ * natural order) after relax_sweeps symmetric sweeps on A e = 0 (e is not
+ * modified); e == NULL uses the next start vector of the seed stream.  The
+ * new hierarchy becomes current and joins the history. */
+pcamg_status pcamg_rebuild(pcamg_ctx* c, const double* e);
+
+void pcamg_destroy(pcamg_ctx* c);
+
+/* ------------------------------------------------------------------------
+ * Hierarchy access (inspection and stage tests)
+ * ------------------------------------------------------------------------ */
+
+/* Number of hierarchies built so far (history, Alg. 5 P_hist). */
+pcamg_status pcamg_num_hierarchies(pcamg_ctx* c, int32_t* count);
+pcamg_status pcamg_num_levels(pcamg_ctx* c, int32_t h, int32_t* levels);
+
+/* info[16] (host): n, nnz(A_l off-diagonal), ncolours, n_next, nnz(level
+ * graph), paths, unaggregated after pairing, case1, case2, case3, middle,
+ * singleton, p1 fallbacks, coarsest grounded, coarsest fallback, path vertices.
+ * The level-graph and path counts need keep_setup. */
+pcamg_status pcamg_level_info(pcamg_ctx* c, int32_t h, int32_t level, int64_t* info);
+
+/* Copy a per-level array, natural vertex order, to host memory `out`.
+ * Names (int32): "colour"[n], "agg"[n], "A_rp"[n+1], "A_ci"[nnz],
+ * "path_id"[n], "pos"[n], "nb"[2n], "G_rp"[n+1], "G_ci"[nnz_G];
+ * (double): "A_v"[nnz], "d"[n], "dinv"[n], "pval"[n], "G_v"[nnz_G],
+ * "gkey"[nnz_G] (level 0).  Setup arrays (path_id, pos, nb, G_*, gkey) need
+ * keep_setup = 1.  Returns PCAMG_EINVAL for an unknown or absent name. */
+pcamg_status pcamg_level_get(pcamg_ctx* c, int32_t h, int32_t level, const char* name, void* out);
+
+/* One multigrid cycle of hierarchy h (gamma 1 = V(1,1), 2 = W) on A x = b at
+ * the finest level, natural order, device [n] vectors, in FP64. */
+pcamg_status pcamg_cycle(pcamg_ctx* c, int32_t h, const double* b, double* x, int32_t gamma);
+
+/* The V(1,1)-cycle in FP32 on FP32 copies of the operators (coarsest solve in
+ * FP64), device [n] float vectors. */
+pcamg_status pcamg_cycle32(pcamg_ctx* c, int32_t h, const float* b, float* x);
+
+/* Error approximation (Alg. 2) with hierarchies 0..count-1 as the history
+ * (Re = count): PCG steps on A e = r from e = 0, W-cycle preconditioner of the
+ * latest while Re <= numW, else the symmetric composite of all V-cycles;
+ * result made orthogonal to 1.  r, e: device [n] natural order. */
+pcamg_status pcamg_approx_error(pcamg_ctx* c, int32_t count, const double* r, double* e);
+
+/* Time `sweeps` symmetric multicoloured Gauss-Seidel sweeps (the smoother of
+ * every V-cycle) on the finest level of the current hierarchy, in the solve
+ * layout and launch configuration used by the cycles, with HIP events on the
+ * context's stream.  prec: PCAMG_PREC_F64 or PCAMG_PREC_F32.  Uses internal
+ * scratch vectors only.  Outputs (host): total milliseconds, kernel launches,
+ * algorithmic bytes (per row pass: matrix values and columns, row pointers,
+ * x written, x read once, b, dinv). */
+pcamg_status pcamg_bench_smoother(pcamg_ctx* c, int32_t prec, int32_t sweeps, double* ms, int64_t* launches,
+                                  double* bytes);
+
+/* Smooth error of the first build: start vector of build 0 (SplitMix64
+ * stream p->seed) and relax_sweeps symmetric sweeps on A e = 0. device [n]. */
+pcamg_status pcamg_initial_error(pcamg_ctx* c, double* e);
+
+/* ------------------------------------------------------------------------
+ * Stage entry points: single steps of the method on caller arrays (device
+ * unless stated).  Used for parity tests and benchmarks.
+ * ------------------------------------------------------------------------ */
+
+/* Laplacian (Sec. 2.2): aval[nnz] = -w, d[n] = row sums in CSR order, dinv = 1/d. */
+pcamg_status pcamg_laplacian(int32_t n, const int32_t* rp, const int32_t* ci, const double* w, double* aval,
+                             double* d, double* dinv, void* stream);
+
+/* Multicolouring used by the Gauss-Seidel smoother: Jones-Plassmann rounds
+ * with SplitMix64 priorities (seed, level) = greedy first-fit in descending
+ * priority order.  colour: device int32 [n]; *ncolours: host. */
+pcamg_status pcamg_colour(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed, int32_t level,
+                          int32_t* colour, int32_t* ncolours, void* stream);
+
+/* `count` multicoloured GS passes (forward: colours 0..C-1, backward:
+ * C-1..0) on A x = b with A = off-diagonal (rp, ci, aval) + diagonal dinv^-1. */
+pcamg_status pcamg_gs(int32_t n, const int32_t* rp, const int32_t* ci, const double* aval, const double* dinv,
+                      const int32_t* colour, int32_t ncolours, const double* b, double* x, int32_t forward,
+                      int32_t count, void* stream);
+
+/* r = b - (D + offdiag) x, sum order d_i x_i then CSR order. */
+pcamg_status pcamg_residual(int32_t n, const int32_t* rp, const int32_t* ci, const double* aval, const double* d,
+                            const double* b, const double* x, double* r, void* stream);
+
+/* Off-diagonal A^2 pattern (Alg. 4, Step 2), two calls: rp2[n+1] and *nnz2
+ * (host), then ci2[nnz2]. */
+pcamg_status pcamg_a2_count(int32_t n, const int32_t* rp, const int32_t* ci, int32_t hub_cap, int32_t* rp2,
+                            int64_t* nnz2, void* stream);
+pcamg_status pcamg_a2_fill(int32_t n, const int32_t* rp, const int32_t* ci, int32_t hub_cap, const int32_t* rp2,
+                           int32_t* ci2, void* stream);
+
+/* Undirected edges (i < j) of a symmetric pattern sorted by (|e_i - e_j|
+ * ascending, lexicographic edge index ascending) = heaviest reweighted edge
+ * first (Alg. 4 Step 2, Alg. 1 Step 3).  su, sv: device int32 [nnz2/2]. */
+pcamg_status pcamg_sort_edges(int32_t n, const int32_t* rp2, const int32_t* ci2, const double* e, int32_t* su,
+                              int32_t* sv, void* stream);
+
+/* Greedy path cover (Alg. 1) visiting the m edges (su[t], sv[t]) in order t.
+ * nb: device int32 [2n], the cover neighbours of each vertex (-1 = none). */
+pcamg_status pcamg_path_cover(int32_t n, int32_t m, const int32_t* su, const int32_t* sv, int32_t* nb,
+                              void* stream);
+
+/* Paths of a cover: start at the smaller endpoint; path_id (= start vertex),
+ * pos, path length; -1/-1/0 for vertices on no path.  device int32 [n] each. */
+pcamg_status pcamg_orient(int32_t n, const int32_t* nb, int32_t* path_id, int32_t* pos, int32_t* plen,
+                          void* stream);
+
+/* Aggregation along a cover (Alg. 3): pairing along paths, isolated vertices
+ * in ascending id (Cases 1-3), aggregates numbered by smallest member.
+ * Level graph (grp, gci, gw) with optional keys gkey (finest level: smaller
+ * key = heavier).  agg: device [n]; *nc and stats[6] (host): unaggregated,
+ * case1, case2, case3, middle, singleton. */
+pcamg_status pcamg_aggregate(int32_t n, const int32_t* grp, const int32_t* gci, const double* gw,
+                             const double* gkey, const int32_t* nb, int32_t* agg, int32_t* nc, int32_t* stats,
+                             void* stream);
+
+/* Galerkin product P^T A P (Alg. 4, Step 8) for P with one value pval[k] in
+ * column agg[k].  Two calls: rpc[nc+1] and *nnzc (host), then cic[nnzc],
+ * vc[nnzc], dc[nc]. */
+pcamg_status pcamg_galerkin_count(int32_t n, const int32_t* rp, const int32_t* ci, int32_t nc,
+                                  const int32_t* agg, int32_t* rpc, int64_t* nnzc, void* stream);
+pcamg_status pcamg_galerkin_fill(int32_t n, const int32_t* rp, const int32_t* ci, const double* aval,
+                                 const double* d, int32_t nc, const int32_t* agg, const double* pval,
+                                 const int32_t* rpc, int32_t* cic, double* vc, double* dc, void* stream);
+
+/* Path shortening (Alg. 4, Step 7): coarse cover nbc[2 nc] from a cover and
+ * an aggregation. */
+pcamg_status pcamg_shorten(int32_t n, const int32_t* nb, int32_t nc, const int32_t* agg, int32_t* nbc,
+                           void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCAMG_H */

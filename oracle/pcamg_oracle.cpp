@@ -33,9 +33,9 @@
 //  * Path shortening (Alg. 4, Step 7): contract, collapse repeats, keep only the
 //    first occurrence of a coarse vertex (paths ordered by start id) and cut there.
 //  * Coarsest level: n <= coarse_max, or stall (n_c > 0.9 n), or max levels;
-//    dense LDL^T, grounded (last vertex pinned, mean removed) iff every
-//    prolongation is boolean, full otherwise; a non-positive pivot falls back to
-//    grounded.
+//    dense LDL^T, grounded (last vertex pinned, mean removed) iff the coarsest
+//    operator is a Laplacian (every prolongation boolean, or a single level),
+//    full otherwise; a non-positive pivot falls back to grounded.
 //  * Outer loop (Alg. 5): V(1,1) with forward GS before and backward GS after
 //    the coarse correction; x made orthogonal to 1 after each cycle; ConvR =
 //    ||r_{k+1}||/||r_k||; rebuild when the mean ConvR since the last rebuild
@@ -777,7 +777,6 @@ bool build_hierarchy(const Level& fine, const std::vector<double>& e_raw, const 
     sorted_edges(L0.G, L0.gkey, su, sv);
     path_cover(L0.n, su, sv, L0.nb);
   }
-  bool all_boolean = P.p1_mode == 1;
   for (int l = 0;; ++l) {
     Level& L = H.lv[l];
     if (L.n <= P.coarse_max || l + 1 >= P.max_levels) break;
@@ -802,7 +801,10 @@ bool build_hierarchy(const Level& fine, const std::vector<double>& e_raw, const 
   }
   Level& Lc = H.lv.back();
   if (Lc.n > 4096) { g_err = "coarsest level larger than 4096 vertices"; return false; }
-  if (!factor_coarsest(Lc, all_boolean, P.coarse_solve, H.cs)) return false;
+  // the coarsest operator is a (singular) Laplacian when no prolongation carries
+  // smooth-error values: boolean mode, or no coarsening at all
+  const bool laplacian_op = P.p1_mode == 1 || H.lv.size() == 1;
+  if (!factor_coarsest(Lc, laplacian_op, P.coarse_solve, H.cs)) return false;
   // operator complexity: nonzeros of all levels (diagonal included) / finest
   double tot = 0.0;
   for (auto& L : H.lv) tot += (double)L.A.nnz() + L.n;

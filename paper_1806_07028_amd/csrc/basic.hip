@@ -1,0 +1,407 @@
+// Laplacian, multicolouring, Gauss-Seidel passes, residual, transfers and the
+// vector kernels of the outer iterations.  Floating-point sums follow a fixed
+// order (fma chains in CSR order) so results are reproducible bit for bit.
+#include <algorithm>
+
+#include "internal.hpp"
+
+namespace pcamg {
+
+// SplitMix64 counter stream (Steele, Lea & Flood 2014): word k of stream seed
+// is mix(seed + k * 0x9E3779B97F4A7C15).
+__host__ __device__ inline uint64_t sm64_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__host__ __device__ inline uint64_t sm64_word(uint64_t seed, uint64_t k) {
+  return sm64_mix(seed + k * 0x9E3779B97F4A7C15ull);
+}
+
+// ---------------------------------------------------------------------------
+// Laplacian A = D - W (Sec. 2.2): one thread per row.
+// ---------------------------------------------------------------------------
+__global__ void laplacian_kernel(int32_t n, const int32_t* __restrict__ rp, const double* __restrict__ w,
+                                 double* __restrict__ aval, double* __restrict__ d, double* __restrict__ dinv) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+    double x = w[k];
+    s = s + x;
+    aval[k] = -x;
+  }
+  d[i] = s;
+  dinv[i] = 1.0 / s;
+}
+
+void laplacian(int32_t n, const int32_t* rp, const double* w, double* aval, double* d, double* dinv, size_t,
+               hipStream_t s) {
+  if (n <= 0) return;
+  laplacian_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, rp, w, aval, d, dinv);
+  PCAMG_LAUNCHED();
+}
+
+// ---------------------------------------------------------------------------
+// Jones-Plassmann colouring: a vertex is coloured in the first round in which
+// all its higher-priority neighbours are coloured, with the smallest colour
+// none of them has.  This equals sequential first-fit in descending
+// (priority, id) order.
+// ---------------------------------------------------------------------------
+__global__ void jp_round_kernel(int32_t nw, const int32_t* __restrict__ work, const int32_t* __restrict__ rp,
+                                const int32_t* __restrict__ ci, uint64_t seed, uint64_t lvl,
+                                int32_t* __restrict__ colour, uint8_t* __restrict__ still) {
+  int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nw) return;
+  const int32_t v = work[t];
+  const uint64_t pv = sm64_word(seed, lvl + (uint64_t)v + 1ull);
+  unsigned long long used = 0ull;
+  bool big = false;
+  for (int32_t k = rp[v]; k < rp[v + 1]; ++k) {
+    int32_t u = ci[k];
+    uint64_t pu = sm64_word(seed, lvl + (uint64_t)u + 1ull);
+    if (pu > pv || (pu == pv && u > v)) {
+      int32_t cu = __atomic_load_n(&colour[u], __ATOMIC_RELAXED);
+      if (cu < 0) {
+        still[t] = 1;
+        return;
+      }
+      if (cu < 64) used |= 1ull << cu;
+      else big = true;
+    }
+  }
+  int32_t c;
+  if (~used != 0ull && !big) {
+    c = __ffsll((long long)~used) - 1;
+  } else {
+    // more than 64 colours around: search the smallest free colour directly
+    c = 0;
+    for (;;) {
+      bool taken = c < 64 ? ((used >> c) & 1ull) : false;
+      if (!taken && c >= 64) {
+        for (int32_t k = rp[v]; k < rp[v + 1]; ++k) {
+          int32_t u = ci[k];
+          uint64_t pu = sm64_word(seed, lvl + (uint64_t)u + 1ull);
+          if ((pu > pv || (pu == pv && u > v)) && colour[u] == c) { taken = true; break; }
+        }
+      }
+      if (!taken) break;
+      ++c;
+    }
+  }
+  __atomic_store_n(&colour[v], c, __ATOMIC_RELAXED);
+  still[t] = 0;
+}
+
+__global__ void max_i32_kernel(const int32_t* a, int32_t n, int32_t* out) {
+  int32_t m = -1;
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) m = max(m, a[i]);
+  for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_down(m, o, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, m);
+}
+
+int32_t colour_jp(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed, int32_t level, int32_t* colour,
+                  hipStream_t s) {
+  if (n <= 0) return 0;
+  fill_i32(colour, -1, n, s);
+  DVec<int32_t> wa(n), wb(n), cnt(1);
+  DVec<uint8_t> still(n);
+  iota_i32(wa.p, n, s);
+  int32_t nw = n;
+  const uint64_t lvl = (uint64_t)(uint32_t)level << 32;
+  int rounds = 0;
+  while (nw > 0) {
+    jp_round_kernel<<<grid_for(nw, 256), 256, 0, s>>>(nw, wa.p, rp, ci, seed, lvl, colour, still.p);
+    PCAMG_LAUNCHED();
+    compact_i32(wa.p, still.p, wb.p, cnt.p, nw, s);
+    nw = read_scalar(cnt.p, s);
+    std::swap(wa, wb);
+    require(++rounds <= n + 1, PCAMG_EHIP, "colouring did not terminate");
+  }
+  DVec<int32_t> mx(1);
+  fill_i32(mx.p, -1, 1, s);
+  max_i32_kernel<<<std::min<unsigned>(grid_for(n, 256), 1024), 256, 0, s>>>(colour, n, mx.p);
+  PCAMG_LAUNCHED();
+  return read_scalar(mx.p, s) + 1;
+}
+
+// ---------------------------------------------------------------------------
+// Gauss-Seidel pass over the rows of one colour (rows row0..row1-1 of a
+// colour-sorted matrix): s = sum_j a_ij x_j as an fma chain in CSR order,
+// x_i = (b_i - s) * dinv_i.  Rows of one colour are independent.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void gs_kernel(int32_t row0, int32_t row1, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                          const T* __restrict__ av, const T* __restrict__ dinv, const T* __restrict__ b,
+                          T* __restrict__ x) {
+  int32_t i = row0 + (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= row1) return;
+  T s = 0;
+  const int32_t k1 = rp[i + 1];
+  for (int32_t k = rp[i]; k < k1; ++k) s = fma(av[k], x[ci[k]], s);
+  x[i] = (b[i] - s) * dinv[i];
+}
+
+template <typename T>
+void gs_colour(int32_t row0, int32_t row1, const int32_t* rp, const int32_t* ci, const T* av, const T* dinv,
+               const T* b, T* x, hipStream_t s) {
+  if (row1 <= row0) return;
+  gs_kernel<T><<<grid_for(row1 - row0, 256), 256, 0, s>>>(row0, row1, rp, ci, av, dinv, b, x);
+  PCAMG_LAUNCHED();
+}
+
+// Same over an explicit row list (natural-order stage entry point).
+template <typename T>
+__global__ void gs_rows_kernel(int32_t nrows, const int32_t* __restrict__ rows, const int32_t* __restrict__ rp,
+                               const int32_t* __restrict__ ci, const T* __restrict__ av, const T* __restrict__ dinv,
+                               const T* __restrict__ b, T* __restrict__ x) {
+  int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrows) return;
+  int32_t i = rows[t];
+  T s = 0;
+  for (int32_t k = rp[i]; k < rp[i + 1]; ++k) s = fma(av[k], x[ci[k]], s);
+  x[i] = (b[i] - s) * dinv[i];
+}
+
+template <typename T>
+void gs_colour_rows(int32_t nrows, const int32_t* rows, const int32_t* rp, const int32_t* ci, const T* av,
+                    const T* dinv, const T* b, T* x, hipStream_t s) {
+  if (nrows <= 0) return;
+  gs_rows_kernel<T><<<grid_for(nrows, 256), 256, 0, s>>>(nrows, rows, rp, ci, av, dinv, b, x);
+  PCAMG_LAUNCHED();
+}
+
+// r = b - A x with s = d_i x_i, then the off-diagonal fma chain.
+template <typename T>
+__global__ void residual_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                const T* __restrict__ av, const T* __restrict__ d, const T* __restrict__ b,
+                                const T* __restrict__ x, T* __restrict__ r) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T s = d[i] * x[i];
+  const int32_t k1 = rp[i + 1];
+  for (int32_t k = rp[i]; k < k1; ++k) s = fma(av[k], x[ci[k]], s);
+  r[i] = b[i] - s;
+}
+
+template <typename T>
+void residual(int32_t n, const int32_t* rp, const int32_t* ci, const T* av, const T* d, const T* b, const T* x,
+              T* r, hipStream_t s) {
+  if (n <= 0) return;
+  residual_kernel<T><<<grid_for(n, 256), 256, 0, s>>>(n, rp, ci, av, d, b, x, r);
+  PCAMG_LAUNCHED();
+}
+
+template <typename T>
+__global__ void spmv_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                            const T* __restrict__ av, const T* __restrict__ d, const T* __restrict__ x,
+                            T* __restrict__ y) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T s = d[i] * x[i];
+  const int32_t k1 = rp[i + 1];
+  for (int32_t k = rp[i]; k < k1; ++k) s = fma(av[k], x[ci[k]], s);
+  y[i] = s;
+}
+
+template <typename T>
+void spmv(int32_t n, const int32_t* rp, const int32_t* ci, const T* av, const T* d, const T* x, T* y,
+          hipStream_t s) {
+  if (n <= 0) return;
+  spmv_kernel<T><<<grid_for(n, 256), 256, 0, s>>>(n, rp, ci, av, d, x, y);
+  PCAMG_LAUNCHED();
+}
+
+// Restriction b_c = P^T r: fma chain over the members of each aggregate in
+// ascending (natural) order.  pval == nullptr: boolean P.
+template <typename T>
+__global__ void restrict_kernel(int32_t nc, const int32_t* __restrict__ moff, const int32_t* __restrict__ mem,
+                                const T* __restrict__ pval, const T* __restrict__ r, T* __restrict__ bc) {
+  int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nc) return;
+  T s = 0;
+  for (int32_t t = moff[q]; t < moff[q + 1]; ++t) {
+    int32_t k = mem[t];
+    s = fma(pval ? pval[k] : (T)1, r[k], s);
+  }
+  bc[q] = s;
+}
+
+template <typename T>
+void restrict_members(int32_t nc, const int32_t* moff, const int32_t* mem, const T* pval, const T* r, T* bc,
+                      hipStream_t s) {
+  if (nc <= 0) return;
+  restrict_kernel<T><<<grid_for(nc, 256), 256, 0, s>>>(nc, moff, mem, pval, r, bc);
+  PCAMG_LAUNCHED();
+}
+
+// Prolongation x_k += p_k x_c[agg_k].
+template <typename T>
+__global__ void prolong_kernel(int32_t n, const int32_t* __restrict__ agg, const T* __restrict__ pval,
+                               const T* __restrict__ xc, T* __restrict__ x) {
+  int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  x[k] = fma(pval ? pval[k] : (T)1, xc[agg[k]], x[k]);
+}
+
+template <typename T>
+void prolong_add(int32_t n, const int32_t* agg, const T* pval, const T* xc, T* x, hipStream_t s) {
+  if (n <= 0) return;
+  prolong_kernel<T><<<grid_for(n, 256), 256, 0, s>>>(n, agg, pval, xc, x);
+  PCAMG_LAUNCHED();
+}
+
+#define INSTANTIATE(T)                                                                                          \
+  template void gs_colour<T>(int32_t, int32_t, const int32_t*, const int32_t*, const T*, const T*, const T*,   \
+                             T*, hipStream_t);                                                                  \
+  template void gs_colour_rows<T>(int32_t, const int32_t*, const int32_t*, const int32_t*, const T*, const T*, \
+                                  const T*, T*, hipStream_t);                                                   \
+  template void residual<T>(int32_t, const int32_t*, const int32_t*, const T*, const T*, const T*, const T*,   \
+                            T*, hipStream_t);                                                                   \
+  template void spmv<T>(int32_t, const int32_t*, const int32_t*, const T*, const T*, const T*, T*, hipStream_t); \
+  template void restrict_members<T>(int32_t, const int32_t*, const int32_t*, const T*, const T*, T*,          \
+                                    hipStream_t);                                                               \
+  template void prolong_add<T>(int32_t, const int32_t*, const T*, const T*, T*, hipStream_t);
+INSTANTIATE(double)
+INSTANTIATE(float)
+#undef INSTANTIATE
+
+// ---------------------------------------------------------------------------
+// Vector kernels
+// ---------------------------------------------------------------------------
+__global__ void axpy_kernel(double a, const double* __restrict__ x, double* __restrict__ y, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = fma(a, x[i], y[i]);
+}
+void axpy_f64(double a, const double* x, double* y, size_t n, hipStream_t s) {
+  if (!n) return;
+  axpy_kernel<<<grid_for(n, 256), 256, 0, s>>>(a, x, y, n);
+  PCAMG_LAUNCHED();
+}
+
+__global__ void axpy_dev_kernel(const double* __restrict__ a, int sign, const double* __restrict__ x,
+                                double* __restrict__ y, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double al = sign < 0 ? -*a : *a;
+  if (i < n) y[i] = fma(al, x[i], y[i]);
+}
+void axpy_dev_f64(const double* a, int sign, const double* x, double* y, size_t n, hipStream_t s) {
+  if (!n) return;
+  axpy_dev_kernel<<<grid_for(n, 256), 256, 0, s>>>(a, sign, x, y, n);
+  PCAMG_LAUNCHED();
+}
+
+__global__ void xpby_kernel(const double* __restrict__ z, const double* __restrict__ beta, double* __restrict__ p,
+                            size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = fma(*beta, p[i], z[i]);
+}
+void xpby_dev_f64(const double* z, const double* beta, double* p, size_t n, hipStream_t s) {
+  if (!n) return;
+  xpby_kernel<<<grid_for(n, 256), 256, 0, s>>>(z, beta, p, n);
+  PCAMG_LAUNCHED();
+}
+
+__global__ void sub_mean_kernel(double* __restrict__ x, const double* __restrict__ sum, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double mu = *sum / (double)n;
+  if (i < n) x[i] = x[i] - mu;
+}
+void sub_mean_f64(double* x, const double* sum, size_t n, hipStream_t s) {
+  if (!n) return;
+  sub_mean_kernel<<<grid_for(n, 256), 256, 0, s>>>(x, sum, n);
+  PCAMG_LAUNCHED();
+}
+
+template <typename T>
+__global__ void gather_kernel(const T* __restrict__ src, const int32_t* __restrict__ idx, T* __restrict__ dst,
+                              size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[idx[i]];
+}
+template <typename T>
+__global__ void scatter_kernel(const T* __restrict__ src, const int32_t* __restrict__ idx, T* __restrict__ dst,
+                               size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[idx[i]] = src[i];
+}
+void gather_f64(const double* src, const int32_t* idx, double* dst, size_t n, hipStream_t s) {
+  if (!n) return;
+  gather_kernel<double><<<grid_for(n, 256), 256, 0, s>>>(src, idx, dst, n);
+  PCAMG_LAUNCHED();
+}
+void scatter_f64(const double* src, const int32_t* idx, double* dst, size_t n, hipStream_t s) {
+  if (!n) return;
+  scatter_kernel<double><<<grid_for(n, 256), 256, 0, s>>>(src, idx, dst, n);
+  PCAMG_LAUNCHED();
+}
+void gather_f32(const float* src, const int32_t* idx, float* dst, size_t n, hipStream_t s) {
+  if (!n) return;
+  gather_kernel<float><<<grid_for(n, 256), 256, 0, s>>>(src, idx, dst, n);
+  PCAMG_LAUNCHED();
+}
+void scatter_f32(const float* src, const int32_t* idx, float* dst, size_t n, hipStream_t s) {
+  if (!n) return;
+  scatter_kernel<float><<<grid_for(n, 256), 256, 0, s>>>(src, idx, dst, n);
+  PCAMG_LAUNCHED();
+}
+void gather_i32(const int32_t* src, const int32_t* idx, int32_t* dst, size_t n, hipStream_t s) {
+  if (!n) return;
+  gather_kernel<int32_t><<<grid_for(n, 256), 256, 0, s>>>(src, idx, dst, n);
+  PCAMG_LAUNCHED();
+}
+
+__global__ void cast_d2f_kernel(const double* __restrict__ a, float* __restrict__ b, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+__global__ void cast_f2d_kernel(const float* __restrict__ a, double* __restrict__ b, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (double)a[i];
+}
+void cast_f64_f32(const double* a, float* b, size_t n, hipStream_t s) {
+  if (!n) return;
+  cast_d2f_kernel<<<grid_for(n, 256), 256, 0, s>>>(a, b, n);
+  PCAMG_LAUNCHED();
+}
+void cast_f32_f64(const float* a, double* b, size_t n, hipStream_t s) {
+  if (!n) return;
+  cast_f2d_kernel<<<grid_for(n, 256), 256, 0, s>>>(a, b, n);
+  PCAMG_LAUNCHED();
+}
+
+// Start vector of build r: xi_i = 2u - 1, u = top 53 bits of word
+// (r << 32) + i + 1 times 2^-53; out[p] = xi_{perm[p]} (perm may be null).
+__global__ void xi_kernel(uint64_t seed, uint64_t rbase, const int32_t* __restrict__ perm, double* __restrict__ out,
+                          size_t n) {
+  size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  uint64_t i = perm ? (uint64_t)(uint32_t)perm[p] : (uint64_t)p;
+  uint64_t w = sm64_word(seed, rbase + i + 1ull);
+  double u = (double)(w >> 11) * 0x1.0p-53;
+  out[p] = 2.0 * u - 1.0;
+}
+void xi_fill(uint64_t seed, int32_t r, const int32_t* perm, double* out, size_t n, hipStream_t s) {
+  if (!n) return;
+  xi_kernel<<<grid_for(n, 256), 256, 0, s>>>(seed, (uint64_t)(uint32_t)r << 32, perm, out, n);
+  PCAMG_LAUNCHED();
+}
+
+__global__ void sub_kernel(const double* a, const double* b, double* o, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) o[i] = a[i] - b[i];
+}
+void sub_f64(const double* a, const double* b, double* out, size_t n, hipStream_t s) {
+  if (!n) return;
+  sub_kernel<<<grid_for(n, 256), 256, 0, s>>>(a, b, out, n);
+  PCAMG_LAUNCHED();
+}
+
+// out = z . (rn - r), deterministic
+void zsub_dot_f64(const double* z, const double* rn, const double* r, size_t n, double* out, hipStream_t s) {
+  DVec<double> t(n);
+  sub_f64(rn, r, t.p, n, s);
+  dot_f64(z, t.p, n, out, s);
+}
+
+}  // namespace pcamg

@@ -1,0 +1,563 @@
+// C ABI of the library (declared in include/pcamg.h).  Every entry point
+// catches exceptions and returns a status; the message is kept per thread.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "solver.hpp"
+
+using namespace pcamg;
+
+namespace {
+thread_local std::string g_last_error;
+
+template <typename F>
+pcamg_status guarded(F&& f) {
+  try {
+    f();
+    g_last_error.clear();
+    return PCAMG_OK;
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return PCAMG_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return PCAMG_EINVAL;
+  }
+}
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+// ---------------------------------------------------------------------------
+// Graph validation (the paper's preprocessing, Sec. 4.3): no self loops,
+// strictly ascending columns, positive finite symmetric weights, connected.
+// ---------------------------------------------------------------------------
+__global__ void validate_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                const double* __restrict__ w, int32_t* __restrict__ flags) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+    const int32_t j = ci[k];
+    if (j < 0 || j >= n) { atomicOr(&flags[0], 1); continue; }
+    if (j == i) atomicOr(&flags[0], 2);
+    if (k > rp[i] && ci[k - 1] >= j) atomicOr(&flags[0], 4);
+    const double x = w[k];
+    if (!(x > 0.0) || !isfinite(x)) atomicOr(&flags[0], 8);
+    // symmetric partner
+    int32_t lo = rp[j], hi = rp[j + 1];
+    bool found = false;
+    while (lo < hi) {
+      int32_t mid = (lo + hi) >> 1;
+      if (ci[mid] == i) { found = true; lo = mid; break; }
+      if (ci[mid] < i) lo = mid + 1;
+      else hi = mid;
+    }
+    if (!found || __double_as_longlong(w[lo]) != __double_as_longlong(x)) atomicOr(&flags[0], 16);
+  }
+}
+
+__global__ void rp_check_kernel(int32_t n, int32_t nnz, const int32_t* __restrict__ rp, int32_t* __restrict__ flags) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n) return;
+  if (i == 0 && rp[0] != 0) atomicOr(&flags[0], 32);
+  if (i == n && rp[n] != nnz) atomicOr(&flags[0], 32);
+  if (i < n && rp[i + 1] < rp[i]) atomicOr(&flags[0], 32);
+}
+
+__global__ void cc_hook_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                               int32_t* __restrict__ label, int32_t* __restrict__ changed) {
+  int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  for (int32_t k = rp[v]; k < rp[v + 1]; ++k) {
+    int32_t a = __atomic_load_n(&label[v], __ATOMIC_RELAXED);
+    int32_t b = __atomic_load_n(&label[ci[k]], __ATOMIC_RELAXED);
+    if (a != b) {
+      atomicMin(&label[max(a, b)], min(a, b));
+      atomicMin(&label[v], min(a, b));
+      *changed = 1;
+    }
+  }
+}
+
+__global__ void cc_compress_kernel(int32_t n, int32_t* __restrict__ label) {
+  int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  int32_t l = label[v];
+  for (int it = 0; it < 64; ++it) {
+    int32_t ll = __atomic_load_n(&label[l], __ATOMIC_RELAXED);
+    if (ll == l) break;
+    l = ll;
+  }
+  label[v] = l;
+}
+
+__global__ void cc_nonzero_kernel(int32_t n, const int32_t* __restrict__ label, int32_t* __restrict__ flags) {
+  int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n && label[v] != 0) atomicOr(&flags[0], 64);
+}
+
+void validate_graph(const pcamg_graph* g, hipStream_t s) {
+  require(g && g->n > 0 && g->nnz >= 0 && g->row_ptr && (g->nnz == 0 || (g->col_idx && g->weight)), PCAMG_EINVAL,
+          "graph: null pointer or bad size");
+  const int32_t n = g->n;
+  DVec<int32_t> flags(1), label(n), changed(1);
+  fill_i32(flags.p, 0, 1, s);
+  rp_check_kernel<<<grid_for(n + 1, 256), 256, 0, s>>>(n, g->nnz, g->row_ptr, flags.p);
+  PCAMG_LAUNCHED();
+  int32_t f = read_scalar(flags.p, s);
+  require(!(f & 32), PCAMG_EINVAL, "graph: row pointers not monotone or not ending at nnz");
+  validate_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, g->row_ptr, g->col_idx, g->weight, flags.p);
+  PCAMG_LAUNCHED();
+  f = read_scalar(flags.p, s);
+  require(!(f & 1), PCAMG_EINVAL, "graph: column index out of range");
+  require(!(f & 2), PCAMG_ESELFLOOP, "graph: self loop");
+  require(!(f & 4), PCAMG_EDUPEDGE, "graph: columns not strictly ascending (duplicate edge?)");
+  require(!(f & 8), PCAMG_EWEIGHT, "graph: weight not positive and finite");
+  require(!(f & 16), PCAMG_ENOTSYM, "graph: pattern or weights not symmetric");
+  iota_i32(label.p, n, s);
+  for (int32_t round = 0; round <= n; ++round) {
+    fill_i32(changed.p, 0, 1, s);
+    cc_hook_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, g->row_ptr, g->col_idx, label.p, changed.p);
+    PCAMG_LAUNCHED();
+    cc_compress_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, label.p);
+    PCAMG_LAUNCHED();
+    if (!read_scalar(changed.p, s)) break;
+  }
+  cc_nonzero_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, label.p, flags.p);
+  PCAMG_LAUNCHED();
+  f = read_scalar(flags.p, s);
+  require(!(f & 64), PCAMG_EDISCONNECTED, "graph: not connected (extract the largest component)");
+}
+
+__global__ void abs_kernel(const double* a, double* b, int32_t n) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = fabs(a[i]);
+}
+
+void validate_rhs(const double* b, int32_t n, hipStream_t s) {
+  DVec<double> t(n), sums(2);
+  abs_kernel<<<grid_for(n, 256), 256, 0, s>>>(b, t.p, n);
+  PCAMG_LAUNCHED();
+  sum_f64(b, n, sums.p, s);
+  sum_f64(t.p, n, sums.p + 1, s);
+  auto h = to_host(sums.p, 2, s);
+  require(std::isfinite(h[0]) && std::isfinite(h[1]), PCAMG_ERHS, "rhs not finite");
+  require(std::fabs(h[0]) <= 1e-12 * h[1], PCAMG_ERHS, "rhs does not sum to zero (graph Laplacians are singular)");
+}
+
+Hierarchy& hier(pcamg_ctx* c, int32_t h) {
+  require(c && h >= 0 && h < (int32_t)c->hist.size(), PCAMG_EINVAL, "hierarchy index out of range");
+  return *c->hist[h];
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pcamg_status_str(pcamg_status s) {
+  switch (s) {
+    case PCAMG_OK: return "ok";
+    case PCAMG_EINVAL: return "invalid argument";
+    case PCAMG_ENOTSYM: return "graph not symmetric";
+    case PCAMG_ESELFLOOP: return "self loop";
+    case PCAMG_EDUPEDGE: return "duplicate edge";
+    case PCAMG_EWEIGHT: return "bad weight";
+    case PCAMG_EDISCONNECTED: return "graph not connected";
+    case PCAMG_ERHS: return "rhs not zero-sum";
+    case PCAMG_ENOMEM: return "out of memory";
+    case PCAMG_EHIP: return "HIP error";
+    case PCAMG_ENOCONV: return "no convergence within max_iter";
+    case PCAMG_EBREAKDOWN: return "breakdown";
+    case PCAMG_ENAN: return "NaN or Inf";
+    case PCAMG_EUNSUPPORTED: return "unsupported input";
+    default: return "unknown status";
+  }
+}
+
+const char* pcamg_last_error(void) { return g_last_error.c_str(); }
+
+pcamg_status pcamg_params_default(pcamg_params* p) {
+  if (!p) return PCAMG_EINVAL;
+  std::memset(p, 0, sizeof(*p));
+  p->tol = 1e-8;
+  p->theta = 0.4;
+  p->max_iter = 2500;
+  p->outer = PCAMG_OUTER_VCYCLE;
+  p->cycle_prec = PCAMG_PREC_F64;
+  p->coarse_max = 64;
+  p->relax_sweeps = 3;
+  p->rebuild_vcycles = 2;
+  p->rebuild_source = PCAMG_REBUILD_ERROR_APPROX;
+  p->p1_mode = PCAMG_P1_SMOOTH;
+  p->coarse_solve = PCAMG_COARSE_AUTO;
+  p->a2_hub_cap = 0;
+  p->max_rebuilds = 50;
+  p->max_levels = 40;
+  p->numW = 2;
+  p->iterW = 7;
+  p->iterV = 4;
+  p->rebuild_rule = 0;
+  p->keep_setup = 0;
+  p->validate = 1;
+  p->seed = 0x5EED;
+  p->colour_seed = 0xC010;
+  return PCAMG_OK;
+}
+
+pcamg_status pcamg_setup(const pcamg_graph* g, const double* rhs, const pcamg_params* p, void* stream,
+                         pcamg_ctx** out) {
+  return guarded([&] {
+    require(g && p && out, PCAMG_EINVAL, "null argument");
+    *out = nullptr;
+    hipStream_t s = as_stream(stream);
+    if (p->validate) validate_graph(g, s);
+    require(g->n >= 1, PCAMG_EINVAL, "empty graph");
+    auto c = std::make_unique<pcamg_ctx>();
+    c->s = s;
+    ctx_init(c.get(), g, p);
+    if (rhs) {
+      validate_rhs(rhs, g->n, s);
+      c->rhs.resize(g->n);
+      copy_d2d(c->rhs.p, rhs, g->n, s);
+      c->have_rhs = true;
+    }
+    Timer t(s);
+    DVec<double> e(g->n);
+    initial_error(c.get(), 0, e.p);
+    c->hist.push_back(build_hierarchy(c.get(), e.p));
+    c->t_build_ms = t.ms();
+    *out = c.release();
+  });
+}
+
+pcamg_status pcamg_set_rhs(pcamg_ctx* c, const double* rhs) {
+  return guarded([&] {
+    require(c && rhs, PCAMG_EINVAL, "null argument");
+    validate_rhs(rhs, c->n, c->s);
+    c->rhs.resize(c->n);
+    copy_d2d(c->rhs.p, rhs, c->n, c->s);
+    c->have_rhs = true;
+  });
+}
+
+pcamg_status pcamg_solve(pcamg_ctx* c, double* x, pcamg_stats* st) {
+  return guarded([&] {
+    require(c && x, PCAMG_EINVAL, "null argument");
+    pcamg::solve(c, x, st);
+  });
+}
+
+pcamg_status pcamg_rebuild(pcamg_ctx* c, const double* e) {
+  return guarded([&] {
+    require(c, PCAMG_EINVAL, "null context");
+    DVec<double> eb(c->n);
+    if (e) {
+      copy_d2d(eb.p, e, c->n, c->s);
+      relax_homogeneous(c, eb.p, c->P.relax_sweeps);
+    } else {
+      initial_error(c, (int32_t)c->hist.size(), eb.p);
+    }
+    c->hist.push_back(build_hierarchy(c, eb.p));
+  });
+}
+
+void pcamg_destroy(pcamg_ctx* c) {
+  if (!c) return;
+  try {
+    (void)hipStreamSynchronize(c->s);
+    delete c;
+  } catch (...) {
+  }
+}
+
+pcamg_status pcamg_num_hierarchies(pcamg_ctx* c, int32_t* count) {
+  return guarded([&] {
+    require(c && count, PCAMG_EINVAL, "null argument");
+    *count = (int32_t)c->hist.size();
+  });
+}
+
+pcamg_status pcamg_num_levels(pcamg_ctx* c, int32_t h, int32_t* levels) {
+  return guarded([&] {
+    require(levels, PCAMG_EINVAL, "null argument");
+    *levels = (int32_t)hier(c, h).lv.size();
+  });
+}
+
+pcamg_status pcamg_level_info(pcamg_ctx* c, int32_t h, int32_t level, int64_t* info) {
+  return guarded([&] {
+    Hierarchy& H = hier(c, h);
+    require(info && level >= 0 && level < (int32_t)H.lv.size(), PCAMG_EINVAL, "level out of range");
+    std::memcpy(info, H.lv[level].info.data(), 16 * sizeof(int64_t));
+  });
+}
+
+pcamg_status pcamg_level_get(pcamg_ctx* c, int32_t h, int32_t level, const char* name, void* out) {
+  return guarded([&] {
+    Hierarchy& H = hier(c, h);
+    require(out && name && level >= 0 && level < (int32_t)H.lv.size(), PCAMG_EINVAL, "bad argument");
+    require(!H.setup.empty(), PCAMG_EINVAL, "level arrays need keep_setup = 1");
+    SetupLevel& S = H.setup[level];
+    const std::string nm(name);
+    auto gi = [&](const DVec<int32_t>& v, size_t cnt) {
+      require(v.p != nullptr, PCAMG_EINVAL, "array '" + nm + "' not present on this level");
+      if (cnt) PCAMG_HIP(hipMemcpyAsync(out, v.p, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, c->s));
+    };
+    auto gd = [&](const DVec<double>& v, size_t cnt) {
+      require(v.p != nullptr, PCAMG_EINVAL, "array '" + nm + "' not present on this level");
+      if (cnt) PCAMG_HIP(hipMemcpyAsync(out, v.p, cnt * sizeof(double), hipMemcpyDeviceToHost, c->s));
+    };
+    if (nm == "colour") gi(S.colour, S.n);
+    else if (nm == "agg") gi(S.agg, S.n);
+    else if (nm == "A_rp") gi(S.rp, S.n + 1);
+    else if (nm == "A_ci") gi(S.ci, S.nnz);
+    else if (nm == "path_id") gi(S.path_id, S.n);
+    else if (nm == "pos") gi(S.pos, S.n);
+    else if (nm == "nb") gi(S.nb, 2 * (size_t)S.n);
+    else if (nm == "G_rp") gi(S.grp, S.n + 1);
+    else if (nm == "G_ci") gi(S.gci, S.nnz_g);
+    else if (nm == "A_v") gd(S.av, S.nnz);
+    else if (nm == "d") gd(S.d, S.n);
+    else if (nm == "dinv") gd(S.dinv, S.n);
+    else if (nm == "pval") gd(S.pval, S.n);
+    else if (nm == "G_v") gd(S.gv, S.nnz_g);
+    else if (nm == "gkey") gd(S.gkey, S.nnz_g);
+    else throw Error(PCAMG_EINVAL, "unknown array name '" + nm + "'");
+    PCAMG_HIP(hipStreamSynchronize(c->s));
+  });
+}
+
+pcamg_status pcamg_cycle(pcamg_ctx* c, int32_t h, const double* b, double* x, int32_t gamma) {
+  return guarded([&] {
+    Hierarchy& H = hier(c, h);
+    require(b && x && gamma >= 1 && gamma <= 2, PCAMG_EINVAL, "bad argument");
+    const int32_t n = c->n;
+    DVec<double> bp(n), xp(n);
+    gather_f64(b, c->M0->perm.p, bp.p, n, c->s);
+    gather_f64(x, c->M0->perm.p, xp.p, n, c->s);
+    cycle64(c, H, 0, bp.p, xp.p, gamma);
+    scatter_f64(xp.p, c->M0->perm.p, x, n, c->s);
+    PCAMG_HIP(hipStreamSynchronize(c->s));
+  });
+}
+
+pcamg_status pcamg_cycle32(pcamg_ctx* c, int32_t h, const float* b, float* x) {
+  return guarded([&] {
+    Hierarchy& H = hier(c, h);
+    require(b && x, PCAMG_EINVAL, "bad argument");
+    const int32_t n = c->n;
+    DVec<float> bp(n), xp(n);
+    gather_f32(b, c->M0->perm.p, bp.p, n, c->s);
+    gather_f32(x, c->M0->perm.p, xp.p, n, c->s);
+    cycle32(c, H, 0, bp.p, xp.p);
+    scatter_f32(xp.p, c->M0->perm.p, x, n, c->s);
+    PCAMG_HIP(hipStreamSynchronize(c->s));
+  });
+}
+
+pcamg_status pcamg_approx_error(pcamg_ctx* c, int32_t count, const double* r, double* e) {
+  return guarded([&] {
+    require(c && r && e && count >= 1 && count <= (int32_t)c->hist.size(), PCAMG_EINVAL, "bad argument");
+    const int32_t n = c->n;
+    DVec<double> rp(n), ep(n);
+    gather_f64(r, c->M0->perm.p, rp.p, n, c->s);
+    approx_error(c, count, rp.p, ep.p, nullptr, nullptr);
+    scatter_f64(ep.p, c->M0->perm.p, e, n, c->s);
+    PCAMG_HIP(hipStreamSynchronize(c->s));
+  });
+}
+
+pcamg_status pcamg_bench_smoother(pcamg_ctx* c, int32_t prec, int32_t sweeps, double* ms, int64_t* launches,
+                                  double* bytes) {
+  return guarded([&] {
+    require(c && ms && launches && bytes && sweeps >= 1, PCAMG_EINVAL, "bad argument");
+    bench_smoother(c, prec, sweeps, ms, launches, bytes);
+  });
+}
+
+pcamg_status pcamg_initial_error(pcamg_ctx* c, double* e) {
+  return guarded([&] {
+    require(c && e, PCAMG_EINVAL, "null argument");
+    initial_error(c, 0, e);
+    PCAMG_HIP(hipStreamSynchronize(c->s));
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Stage entry points
+// ---------------------------------------------------------------------------
+pcamg_status pcamg_laplacian(int32_t n, const int32_t* rp, const int32_t* ci, const double* w, double* aval,
+                             double* d, double* dinv, void* stream) {
+  return guarded([&] {
+    require(n >= 0 && rp && d && dinv, PCAMG_EINVAL, "null argument");
+    laplacian(n, rp, w, aval, d, dinv, 0, as_stream(stream));
+    PCAMG_HIP(hipStreamSynchronize(as_stream(stream)));
+  });
+}
+
+pcamg_status pcamg_colour(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed, int32_t level,
+                          int32_t* colour, int32_t* ncolours, void* stream) {
+  return guarded([&] {
+    require(n >= 0 && rp && colour && ncolours, PCAMG_EINVAL, "null argument");
+    *ncolours = colour_jp(n, rp, ci, seed, level, colour, as_stream(stream));
+  });
+}
+
+pcamg_status pcamg_gs(int32_t n, const int32_t* rp, const int32_t* ci, const double* aval, const double* dinv,
+                      const int32_t* colour, int32_t ncolours, const double* b, double* x, int32_t forward,
+                      int32_t count, void* stream) {
+  return guarded([&] {
+    require(n > 0 && rp && colour && b && x && ncolours >= 1, PCAMG_EINVAL, "bad argument");
+    hipStream_t s = as_stream(stream);
+    DVec<int32_t> perm(n), iperm(n);
+    std::vector<int32_t> coff;
+    build_perm(n, colour, ncolours, perm.p, iperm.p, coff, s);
+    require((int32_t)coff.size() == ncolours + 1, PCAMG_EINVAL, "colour array inconsistent with ncolours");
+    for (int q = 0; q < count; ++q)
+      for (int t = 0; t < ncolours; ++t) {
+        const int32_t col = forward ? t : ncolours - 1 - t;
+        gs_colour_rows<double>(coff[col + 1] - coff[col], perm.p + coff[col], rp, ci, aval, dinv, b, x, s);
+      }
+    PCAMG_HIP(hipStreamSynchronize(s));
+  });
+}
+
+pcamg_status pcamg_residual(int32_t n, const int32_t* rp, const int32_t* ci, const double* aval, const double* d,
+                            const double* b, const double* x, double* r, void* stream) {
+  return guarded([&] {
+    require(n >= 0 && rp && d && b && x && r, PCAMG_EINVAL, "null argument");
+    residual<double>(n, rp, ci, aval, d, b, x, r, as_stream(stream));
+    PCAMG_HIP(hipStreamSynchronize(as_stream(stream)));
+  });
+}
+
+pcamg_status pcamg_a2_count(int32_t n, const int32_t* rp, const int32_t* ci, int32_t hub_cap, int32_t* rp2,
+                            int64_t* nnz2, void* stream) {
+  return guarded([&] {
+    require(n > 0 && rp && rp2 && nnz2 && hub_cap >= 0, PCAMG_EINVAL, "bad argument");
+    *nnz2 = a2_count(n, rp, ci, hub_cap, rp2, as_stream(stream));
+  });
+}
+
+pcamg_status pcamg_a2_fill(int32_t n, const int32_t* rp, const int32_t* ci, int32_t hub_cap, const int32_t* rp2,
+                           int32_t* ci2, void* stream) {
+  return guarded([&] {
+    require(n > 0 && rp && rp2 && ci2, PCAMG_EINVAL, "null argument");
+    a2_fill(n, rp, ci, hub_cap, rp2, ci2, as_stream(stream));
+    PCAMG_HIP(hipStreamSynchronize(as_stream(stream)));
+  });
+}
+
+pcamg_status pcamg_sort_edges(int32_t n, const int32_t* rp2, const int32_t* ci2, const double* e, int32_t* su,
+                              int32_t* sv, void* stream) {
+  return guarded([&] {
+    require(n > 0 && rp2 && ci2 && e && su && sv, PCAMG_EINVAL, "null argument");
+    hipStream_t s = as_stream(stream);
+    const int32_t nnz2 = read_scalar(rp2 + n, s);
+    const int32_t m2 = std::max(nnz2 / 2, 1);
+    DVec<double> gk(std::max(nnz2, 1)), gv(std::max(nnz2, 1));
+    DVec<int32_t> eu(m2), ev(m2);
+    DVec<uint64_t> ek(m2), ks(m2);
+    DVec<uint32_t> idx(m2), order(m2);
+    const int32_t m = a2_keys(n, rp2, ci2, e, gk.p, gv.p, eu.p, ev.p, ek.p, s);
+    iota_i32((int32_t*)idx.p, m, s);
+    radix_sort_u64_u32(ek.p, idx.p, ks.p, order.p, m, s);
+    sorted_endpoints(m, order.p, eu.p, ev.p, su, sv, s);
+    PCAMG_HIP(hipStreamSynchronize(s));
+  });
+}
+
+pcamg_status pcamg_path_cover(int32_t n, int32_t m, const int32_t* su, const int32_t* sv, int32_t* nb,
+                              void* stream) {
+  return guarded([&] {
+    require(n > 0 && m >= 0 && nb && (m == 0 || (su && sv)), PCAMG_EINVAL, "bad argument");
+    path_cover(n, m, su, sv, nb, as_stream(stream));
+    PCAMG_HIP(hipStreamSynchronize(as_stream(stream)));
+  });
+}
+
+pcamg_status pcamg_orient(int32_t n, const int32_t* nb, int32_t* path_id, int32_t* pos, int32_t* plen,
+                          void* stream) {
+  return guarded([&] {
+    require(n > 0 && nb && path_id && pos && plen, PCAMG_EINVAL, "null argument");
+    orient_paths(n, nb, path_id, pos, plen, as_stream(stream));
+    PCAMG_HIP(hipStreamSynchronize(as_stream(stream)));
+  });
+}
+
+pcamg_status pcamg_aggregate(int32_t n, const int32_t* grp, const int32_t* gci, const double* gw,
+                             const double* gkey, const int32_t* nb, int32_t* agg, int32_t* nc, int32_t* stats,
+                             void* stream) {
+  return guarded([&] {
+    require(n > 0 && grp && gw && nb && agg && nc, PCAMG_EINVAL, "null argument");
+    hipStream_t s = as_stream(stream);
+    DVec<int32_t> pid(n), pos(n), plen(n), moff(n + 1), mem(n);
+    orient_paths(n, nb, pid.p, pos.p, plen.p, s);
+    AggStats st;
+    *nc = aggregate_level(n, grp, gci, gw, gkey, nb, pid.p, pos.p, plen.p, agg, moff.p, mem.p, st, s);
+    if (stats) {
+      stats[0] = st.n_unagg;
+      stats[1] = st.case1;
+      stats[2] = st.case2;
+      stats[3] = st.case3;
+      stats[4] = st.middle;
+      stats[5] = st.singleton;
+    }
+  });
+}
+
+namespace {
+void members_from_agg(int32_t n, int32_t nc, const int32_t* agg, DVec<int32_t>& moff, DVec<int32_t>& mem,
+                      hipStream_t s) {
+  DVec<int32_t> inv(n);
+  std::vector<int32_t> off;
+  mem.resize(n);
+  build_perm(n, agg, nc, mem.p, inv.p, off, s);
+  require((int32_t)off.size() == nc + 1, PCAMG_EINVAL, "aggregate ids must cover 0..nc-1");
+  moff.resize(nc + 1);
+  copy_h2d(moff.p, off.data(), nc + 1, s);
+  PCAMG_HIP(hipStreamSynchronize(s));
+}
+}  // namespace
+
+pcamg_status pcamg_galerkin_count(int32_t n, const int32_t* rp, const int32_t* ci, int32_t nc,
+                                  const int32_t* agg, int32_t* rpc, int64_t* nnzc, void* stream) {
+  return guarded([&] {
+    require(n > 0 && nc > 0 && rp && agg && rpc && nnzc, PCAMG_EINVAL, "bad argument");
+    hipStream_t s = as_stream(stream);
+    DVec<int32_t> moff, mem;
+    members_from_agg(n, nc, agg, moff, mem, s);
+    *nnzc = galerkin_count(n, rp, ci, nc, moff.p, mem.p, agg, rpc, false, s);
+  });
+}
+
+pcamg_status pcamg_galerkin_fill(int32_t n, const int32_t* rp, const int32_t* ci, const double* aval,
+                                 const double* d, int32_t nc, const int32_t* agg, const double* pval,
+                                 const int32_t* rpc, int32_t* cic, double* vc, double* dc, void* stream) {
+  return guarded([&] {
+    require(n > 0 && nc > 0 && rp && d && agg && rpc && dc, PCAMG_EINVAL, "bad argument");
+    hipStream_t s = as_stream(stream);
+    DVec<int32_t> moff, mem;
+    members_from_agg(n, nc, agg, moff, mem, s);
+    DVec<double> dinvc(nc);
+    galerkin_fill(n, rp, ci, aval, d, nc, moff.p, mem.p, agg, pval, rpc, cic, vc, dc, dinvc.p, false, s);
+    PCAMG_HIP(hipStreamSynchronize(s));
+  });
+}
+
+pcamg_status pcamg_shorten(int32_t n, const int32_t* nb, int32_t nc, const int32_t* agg, int32_t* nbc,
+                           void* stream) {
+  return guarded([&] {
+    require(n > 0 && nc > 0 && nb && agg && nbc, PCAMG_EINVAL, "null argument");
+    hipStream_t s = as_stream(stream);
+    DVec<int32_t> pid(n), pos(n), plen(n);
+    orient_paths(n, nb, pid.p, pos.p, plen.p, s);
+    shorten_paths(n, nb, pid.p, pos.p, nc, agg, nbc, s);
+    PCAMG_HIP(hipStreamSynchronize(s));
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,699 @@
+// Host orchestration: hierarchy construction (Alg. 4), multigrid cycles, the
+// error approximation (Alg. 2) and the adaptive loop (Alg. 5, plus the FCG
+// variant).  All arithmetic runs in the kernels of this library; the host only
+// sequences launches and reads back scalars (sizes, norms, step lengths).
+#include <algorithm>
+#include <cmath>
+
+#include "solver.hpp"
+
+namespace pcamg {
+
+namespace {
+
+std::shared_ptr<LevelMatrix> make_level_matrix(int32_t n, int32_t nnz, const int32_t* rp, const int32_t* ci,
+                                               const double* av, const double* d, const double* dinv,
+                                               const int32_t* colour, int32_t ncol, hipStream_t s) {
+  auto M = std::make_shared<LevelMatrix>();
+  M->n = n;
+  M->nnz = nnz;
+  M->perm.resize(n);
+  M->iperm.resize(n);
+  if (colour) {
+    build_perm(n, colour, ncol, M->perm.p, M->iperm.p, M->coff, s);
+    M->ncol = ncol;
+  } else {
+    iota_i32(M->perm.p, n, s);
+    iota_i32(M->iperm.p, n, s);
+    M->coff = {0, n};
+    M->ncol = 1;
+  }
+  M->rp.resize(n + 1);
+  M->ci.resize(nnz);
+  M->av.resize(nnz);
+  M->av32.resize(nnz);
+  M->d.resize(n);
+  M->dinv.resize(n);
+  M->d32.resize(n);
+  M->dinv32.resize(n);
+  permute_csr(n, M->perm.p, M->iperm.p, rp, ci, av, d, dinv, M->rp.p, M->ci.p, M->av.p, M->av32.p, M->d.p,
+              M->dinv.p, M->d32.p, M->dinv32.p, s);
+  return M;
+}
+
+// One level of the setup in natural numbering.
+struct NatLevel {
+  int32_t n = 0, nnz = 0, ncol = 0, nnz_g = 0;
+  const int32_t *rp = nullptr, *ci = nullptr, *colour = nullptr, *grp = nullptr, *gci = nullptr, *nb = nullptr;
+  const double *av = nullptr, *d = nullptr, *dinv = nullptr, *gv = nullptr, *gkey = nullptr;
+  DVec<int32_t> o_rp, o_ci, o_colour, o_grp, o_gci, o_nb;
+  DVec<double> o_av, o_d, o_dinv, o_gv;
+  // transfer
+  int32_t nc = 0;
+  DVec<int32_t> agg, moff, mem, pid, pos, plen;
+  DVec<double> pval;
+  AggStats st;
+};
+
+void sync(hipStream_t s) { PCAMG_HIP(hipStreamSynchronize(s)); }
+
+}  // namespace
+
+void ctx_init(pcamg_ctx* c, const pcamg_graph* g, const pcamg_params* p) {
+  hipStream_t s = c->s;
+  c->P = *p;
+  c->n = g->n;
+  c->nnz = g->nnz;
+  const int32_t n = g->n, nnz = g->nnz;
+  c->rp.resize(n + 1);
+  c->ci.resize(nnz);
+  c->av.resize(nnz);
+  c->d.resize(n);
+  c->dinv.resize(n);
+  c->colour.resize(n);
+  copy_d2d(c->rp.p, g->row_ptr, n + 1, s);
+  copy_d2d(c->ci.p, g->col_idx, nnz, s);
+  laplacian(n, c->rp.p, g->weight, c->av.p, c->d.p, c->dinv.p, nnz, s);
+  c->ncol = colour_jp(n, c->rp.p, c->ci.p, c->P.colour_seed, 0, c->colour.p, s);
+  c->M0 = make_level_matrix(n, nnz, c->rp.p, c->ci.p, c->av.p, c->d.p, c->dinv.p, c->colour.p, c->ncol, s);
+  sync(s);
+}
+
+std::unique_ptr<Hierarchy> build_hierarchy(pcamg_ctx* c, const double* e_nat) {
+  hipStream_t s = c->s;
+  const pcamg_params& P = c->P;
+  const int32_t n = c->n;
+  auto H = std::make_unique<Hierarchy>();
+  // Step 2: the A^2 pattern depends on the graph only -- built once per context
+  if (!c->a2_ready) {
+    c->rp2.resize(n + 1);
+    int64_t nnz2 = a2_count(n, c->rp.p, c->ci.p, P.a2_hub_cap, c->rp2.p, s);
+    c->ci2.resize(std::max<int64_t>(nnz2, 1));
+    a2_fill(n, c->rp.p, c->ci.p, P.a2_hub_cap, c->rp2.p, c->ci2.p, s);
+    c->nnz2 = (int32_t)nnz2;
+    c->m2 = (int32_t)(nnz2 / 2);
+    c->a2_ready = true;
+  }
+  std::vector<NatLevel> nat(1);
+  DVec<double> gv0(std::max(c->nnz2, 1)), gkey0(std::max(c->nnz2, 1));
+  DVec<int32_t> nb0(2 * (size_t)n);
+  {
+    // reweighting, sort (Alg. 1 Step 3) and path cover (Alg. 1) on the finest level
+    const int32_t m2 = std::max(c->m2, 1);
+    DVec<int32_t> eu(m2), ev(m2);
+    DVec<uint64_t> ekey(m2), ksorted(m2);
+    const int32_t m = a2_keys(n, c->rp2.p, c->ci2.p, e_nat, gkey0.p, gv0.p, eu.p, ev.p, ekey.p, s);
+    DVec<uint32_t> idx(m2), order(m2);
+    iota_i32((int32_t*)idx.p, m, s);
+    radix_sort_u64_u32(ekey.p, idx.p, ksorted.p, order.p, m, s);
+    DVec<int32_t> su(m2), sv(m2);
+    sorted_endpoints(m, order.p, eu.p, ev.p, su.p, sv.p, s);
+    H->cover_rounds = path_cover(n, m, su.p, sv.p, nb0.p, s);
+  }
+  {
+    NatLevel& L0 = nat[0];
+    L0.n = n;
+    L0.nnz = c->nnz;
+    L0.rp = c->rp.p;
+    L0.ci = c->ci.p;
+    L0.av = c->av.p;
+    L0.d = c->d.p;
+    L0.dinv = c->dinv.p;
+    L0.colour = c->colour.p;
+    L0.ncol = c->ncol;
+    L0.grp = c->rp2.p;
+    L0.gci = c->ci2.p;
+    L0.gv = gv0.p;
+    L0.gkey = gkey0.p;
+    L0.nnz_g = c->nnz2;
+    L0.nb = nb0.p;
+  }
+  // level loop (Alg. 4, Steps 5-9)
+  for (int l = 0;; ++l) {
+    NatLevel& L = nat[l];
+    if (L.n <= P.coarse_max || l + 1 >= P.max_levels) break;
+    L.pid.resize(L.n);
+    L.pos.resize(L.n);
+    L.plen.resize(L.n);
+    orient_paths(L.n, L.nb, L.pid.p, L.pos.p, L.plen.p, s);
+    L.agg.resize(L.n);
+    L.moff.resize(L.n + 1);
+    L.mem.resize(L.n);
+    const int32_t nc = aggregate_level(L.n, L.grp, L.gci, L.gv, L.gkey, L.nb, L.pid.p, L.pos.p, L.plen.p, L.agg.p,
+                                       L.moff.p, L.mem.p, L.st, s);
+    if (nc > 0.9 * L.n) {  // stall: this level becomes the coarsest
+      L.agg.release();
+      L.moff.release();
+      L.mem.release();
+      break;
+    }
+    L.nc = nc;
+    if (l == 0 && P.p1_mode == PCAMG_P1_SMOOTH) {
+      L.pval.resize(L.n);
+      L.st.p1_fallback = smooth_pval(L.n, e_nat, nc, L.moff.p, L.mem.p, L.pval.p, s);
+    }
+    NatLevel C;
+    C.n = nc;
+    C.o_rp.resize(nc + 1);
+    int64_t nnzc = galerkin_count(L.n, L.rp, L.ci, nc, L.moff.p, L.mem.p, L.agg.p, C.o_rp.p, false, s);
+    C.nnz = (int32_t)nnzc;
+    C.o_ci.resize(std::max<int64_t>(nnzc, 1));
+    C.o_av.resize(std::max<int64_t>(nnzc, 1));
+    C.o_d.resize(nc);
+    C.o_dinv.resize(nc);
+    galerkin_fill(L.n, L.rp, L.ci, L.av, L.d, nc, L.moff.p, L.mem.p, L.agg.p, L.pval.p, C.o_rp.p, C.o_ci.p,
+                  C.o_av.p, C.o_d.p, C.o_dinv.p, false, s);
+    C.o_grp.resize(nc + 1);
+    int64_t nnzg = galerkin_count(L.n, L.grp, L.gci, nc, L.moff.p, L.mem.p, L.agg.p, C.o_grp.p, true, s);
+    C.nnz_g = (int32_t)nnzg;
+    C.o_gci.resize(std::max<int64_t>(nnzg, 1));
+    C.o_gv.resize(std::max<int64_t>(nnzg, 1));
+    galerkin_fill(L.n, L.grp, L.gci, L.gv, nullptr, nc, L.moff.p, L.mem.p, L.agg.p, nullptr, C.o_grp.p, C.o_gci.p,
+                  C.o_gv.p, nullptr, nullptr, true, s);
+    C.o_nb.resize(2 * (size_t)nc);
+    shorten_paths(L.n, L.nb, L.pid.p, L.pos.p, nc, L.agg.p, C.o_nb.p, s);
+    C.o_colour.resize(nc);
+    C.ncol = colour_jp(nc, C.o_rp.p, C.o_ci.p, P.colour_seed, l + 1, C.o_colour.p, s);
+    C.rp = C.o_rp.p;
+    C.ci = C.o_ci.p;
+    C.av = C.o_av.p;
+    C.d = C.o_d.p;
+    C.dinv = C.o_dinv.p;
+    C.grp = C.o_grp.p;
+    C.gci = C.o_gci.p;
+    C.gv = C.o_gv.p;
+    C.nb = C.o_nb.p;
+    C.colour = C.o_colour.p;
+    nat.push_back(std::move(C));
+  }
+  const int nl = (int)nat.size();
+  NatLevel& Lc = nat.back();
+  require(Lc.n <= 4096, PCAMG_EUNSUPPORTED, "coarsest level larger than 4096 vertices");
+
+  // solve layout
+  H->lv.resize(nl);
+  for (int l = 0; l < nl; ++l) {
+    NatLevel& L = nat[l];
+    Level& V = H->lv[l];
+    if (l == 0) V.A = c->M0;
+    else if (l + 1 < nl) V.A = make_level_matrix(L.n, L.nnz, L.rp, L.ci, L.av, L.d, L.dinv, L.colour, L.ncol, s);
+    else V.A = make_level_matrix(L.n, L.nnz, L.rp, L.ci, L.av, L.d, L.dinv, nullptr, 1, s);
+    V.x.resize(L.n);
+    V.b.resize(L.n);
+    V.r.resize(L.n);
+    V.x32.resize(L.n);
+    V.b32.resize(L.n);
+    V.r32.resize(L.n);
+  }
+  for (int l = 0; l + 1 < nl; ++l) {
+    NatLevel& L = nat[l];
+    Level& V = H->lv[l];
+    const LevelMatrix& Af = *V.A;
+    const LevelMatrix& Ac = *H->lv[l + 1].A;
+    const bool coarsest_next = l + 2 == nl;
+    V.T.nc = L.nc;
+    V.T.agg.resize(L.n);
+    V.T.moff.resize(L.nc + 1);
+    V.T.mem.resize(L.n);
+    if (L.pval.p) {
+      V.T.pval.resize(L.n);
+      V.T.pval32.resize(L.n);
+    }
+    permute_transfer(L.n, Af.perm.p, Af.iperm.p, L.nc, coarsest_next ? nullptr : Ac.perm.p,
+                     coarsest_next ? nullptr : Ac.iperm.p, L.agg.p, L.pval.p, L.moff.p, L.mem.p, V.T.agg.p,
+                     V.T.pval.p, V.T.pval32.p, V.T.moff.p, V.T.mem.p, s);
+  }
+  // coarsest level: dense LDL^T; grounded iff the operator is a Laplacian
+  // (boolean prolongations everywhere, or no coarsening at all)
+  {
+    const bool laplacian_op = P.p1_mode == PCAMG_P1_CONST || nl == 1;
+    bool grounded = P.coarse_solve == PCAMG_COARSE_GROUNDED ? true
+                    : P.coarse_solve == PCAMG_COARSE_FULL   ? false
+                                                            : laplacian_op;
+    const int32_t cn = Lc.n;
+    DVec<double> Ad((size_t)cn * cn);
+    dense_from_csr(cn, Lc.rp, Lc.ci, Lc.av, Lc.d, Ad.p, s);
+    H->cn = cn;
+    H->cL.resize((size_t)cn * cn);
+    H->cD.resize(cn);
+    bool ok = false;
+    if (!grounded) {
+      H->cm = cn;
+      ok = ldlt_factor(cn, cn, Ad.p, H->cL.p, H->cD.p, s);
+      if (!ok) H->fallback = true;
+    }
+    if (!ok) {
+      grounded = true;
+      H->cm = cn - 1;
+      ok = ldlt_factor(cn, cn - 1, Ad.p, H->cL.p, H->cD.p, s);
+      require(ok, PCAMG_EBREAKDOWN, "coarsest level: non-positive pivot in grounded LDL^T");
+    }
+    H->grounded = grounded;
+  }
+  // statistics
+  double tot = 0.0;
+  for (int l = 0; l < nl; ++l) tot += (double)nat[l].nnz + nat[l].n;
+  H->op_complexity = tot / ((double)nat[0].nnz + nat[0].n);
+  for (int l = 0; l < nl; ++l) {
+    NatLevel& L = nat[l];
+    int64_t npaths = 0, npv = 0;
+    if (L.pid.p) {
+      auto pid = to_host(L.pid.p, L.n, s);
+      for (int32_t v = 0; v < L.n; ++v) {
+        npaths += pid[v] == v;
+        npv += pid[v] >= 0;
+      }
+    }
+    H->lv[l].info = {L.n, L.nnz, L.ncol, L.nc, L.nnz_g, npaths, L.st.n_unagg, L.st.case1, L.st.case2,
+                     L.st.case3, L.st.middle, L.st.singleton, L.st.p1_fallback, H->grounded ? 1 : 0,
+                     H->fallback ? 1 : 0, npv};
+  }
+  H->st0 = nat[0].st;
+  if (P.keep_setup) {
+    H->setup.resize(nl);
+    for (int l = 0; l < nl; ++l) {
+      NatLevel& L = nat[l];
+      SetupLevel& S = H->setup[l];
+      S.n = L.n;
+      S.nnz = L.nnz;
+      S.ncol = L.ncol;
+      S.nnz_g = L.nnz_g;
+      auto cp_i = [&](DVec<int32_t>& dst, const int32_t* src, size_t cnt) {
+        if (!src) return;
+        dst.resize(std::max<size_t>(cnt, 1));
+        copy_d2d(dst.p, src, cnt, s);
+      };
+      auto cp_d = [&](DVec<double>& dst, const double* src, size_t cnt) {
+        if (!src) return;
+        dst.resize(std::max<size_t>(cnt, 1));
+        copy_d2d(dst.p, src, cnt, s);
+      };
+      cp_i(S.rp, L.rp, L.n + 1);
+      cp_i(S.ci, L.ci, L.nnz);
+      cp_i(S.colour, L.colour, L.n);
+      cp_i(S.grp, L.grp, L.n + 1);
+      cp_i(S.gci, L.gci, L.nnz_g);
+      cp_i(S.nb, L.nb, 2 * (size_t)L.n);
+      cp_i(S.path_id, L.pid.p, L.n);
+      cp_i(S.pos, L.pos.p, L.n);
+      cp_i(S.agg, L.agg.p, L.n);
+      cp_d(S.av, L.av, L.nnz);
+      cp_d(S.d, L.d, L.n);
+      cp_d(S.dinv, L.dinv, L.n);
+      cp_d(S.gv, L.gv, L.nnz_g);
+      if (l == 0) cp_d(S.gkey, L.gkey, L.nnz_g);
+      cp_d(S.pval, L.pval.p, L.n);
+    }
+  }
+  sync(s);
+  return H;
+}
+
+// ---------------------------------------------------------------------------
+// Cycles (Alg. 5 V_cycle, Alg. 2 W_cycle), solve layout.
+// ---------------------------------------------------------------------------
+void cycle64(pcamg_ctx* c, Hierarchy& H, int l, const double* b, double* x, int gamma) {
+  hipStream_t s = c->s;
+  const int nl = (int)H.lv.size();
+  if (l + 1 == nl) {
+    if (l == 0) {  // no coarsening: the dense factor is in natural order, level 0 is colour-permuted
+      Level& L = H.lv[0];
+      scatter_f64(b, L.A->perm.p, L.b.p, H.cn, s);
+      ldlt_solve(H.cn, H.cm, H.grounded, H.cL.p, H.cD.p, L.b.p, L.x.p, s);
+      gather_f64(L.x.p, L.A->perm.p, x, H.cn, s);
+      return;
+    }
+    ldlt_solve(H.cn, H.cm, H.grounded, H.cL.p, H.cD.p, b, x, s);
+    return;
+  }
+  Level& L = H.lv[l];
+  const LevelMatrix& A = *L.A;
+  for (int k = 0; k < A.ncol; ++k)
+    gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s);
+  residual<double>(A.n, A.rp.p, A.ci.p, A.av.p, A.d.p, b, x, L.r.p, s);
+  Level& N = H.lv[l + 1];
+  restrict_members<double>(L.T.nc, L.T.moff.p, L.T.mem.p, L.T.pval.p, L.r.p, N.b.p, s);
+  fill_f64(N.x.p, 0.0, N.A->n, s);
+  const int calls = (gamma > 1 && l + 2 < nl) ? gamma : 1;
+  for (int q = 0; q < calls; ++q) cycle64(c, H, l + 1, N.b.p, N.x.p, gamma);
+  prolong_add<double>(A.n, L.T.agg.p, L.T.pval.p, N.x.p, x, s);
+  for (int k = A.ncol - 1; k >= 0; --k)
+    gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s);
+}
+
+void cycle32(pcamg_ctx* c, Hierarchy& H, int l, const float* b, float* x) {
+  hipStream_t s = c->s;
+  const int nl = (int)H.lv.size();
+  if (l + 1 == nl) {
+    if (l == 0) {  // no coarsening: natural-order factor, colour-permuted vectors
+      Level& L = H.lv[0];
+      scatter_f32(b, L.A->perm.p, L.b32.p, H.cn, s);
+      ldlt_solve32(H.cn, H.cm, H.grounded, H.cL.p, H.cD.p, L.b32.p, L.x32.p, s);
+      gather_f32(L.x32.p, L.A->perm.p, x, H.cn, s);
+      return;
+    }
+    ldlt_solve32(H.cn, H.cm, H.grounded, H.cL.p, H.cD.p, b, x, s);
+    return;
+  }
+  Level& L = H.lv[l];
+  const LevelMatrix& A = *L.A;
+  for (int k = 0; k < A.ncol; ++k)
+    gs_colour<float>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s);
+  residual<float>(A.n, A.rp.p, A.ci.p, A.av32.p, A.d32.p, b, x, L.r32.p, s);
+  Level& N = H.lv[l + 1];
+  restrict_members<float>(L.T.nc, L.T.moff.p, L.T.mem.p, L.T.pval32.p, L.r32.p, N.b32.p, s);
+  fill_f32(N.x32.p, 0.0f, N.A->n, s);
+  cycle32(c, H, l + 1, N.b32.p, N.x32.p);
+  prolong_add<float>(A.n, L.T.agg.p, L.T.pval32.p, N.x32.p, x, s);
+  for (int k = A.ncol - 1; k >= 0; --k)
+    gs_colour<float>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s);
+}
+
+// ---------------------------------------------------------------------------
+// Smooth errors
+// ---------------------------------------------------------------------------
+namespace {
+void relax_perm(pcamg_ctx* c, double* e_perm, const double* zero, int sweeps) {
+  const LevelMatrix& A = *c->M0;
+  for (int q = 0; q < sweeps; ++q) {
+    for (int k = 0; k < A.ncol; ++k)
+      gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, zero, e_perm, c->s);
+    for (int k = A.ncol - 1; k >= 0; --k)
+      gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, zero, e_perm, c->s);
+  }
+}
+}  // namespace
+
+void relax_homogeneous(pcamg_ctx* c, double* e_nat, int sweeps) {
+  const int32_t n = c->n;
+  DVec<double> ep(n), zero(n);
+  fill_f64(zero.p, 0.0, n, c->s);
+  gather_f64(e_nat, c->M0->perm.p, ep.p, n, c->s);
+  relax_perm(c, ep.p, zero.p, sweeps);
+  scatter_f64(ep.p, c->M0->perm.p, e_nat, n, c->s);
+}
+
+void initial_error(pcamg_ctx* c, int32_t r, double* e_nat) {
+  xi_fill(c->P.seed, r, nullptr, e_nat, c->n, c->s);
+  relax_homogeneous(c, e_nat, c->P.relax_sweeps);
+}
+
+// ---------------------------------------------------------------------------
+// Error approximation (Alg. 2), permuted vectors: PCG on A e = r from e = 0;
+// preconditioner = W-cycle of the latest hierarchy while Re <= numW, else the
+// symmetric composite B_1 .. B_Re, B_Re .. B_1 of V-cycles; preconditioned
+// vectors and the result made orthogonal to 1.
+// ---------------------------------------------------------------------------
+void approx_error(pcamg_ctx* c, int Re, const double* r, double* e, int* wcycles, int* vcycles) {
+  hipStream_t s = c->s;
+  const int32_t n = c->n;
+  const pcamg_params& P = c->P;
+  const LevelMatrix& A = *c->M0;
+  const bool wcyc = Re <= P.numW;
+  const int steps = wcyc ? P.iterW : P.iterV;
+  DVec<double> rr(n), z(n), p(n), q(n), scal(2);
+  auto dot = [&](const double* a, const double* b) {
+    dot_f64(a, b, n, scal.p, s);
+    return read_scalar(scal.p, s);
+  };
+  auto prec = [&](const double* v, double* zz) {
+    fill_f64(zz, 0.0, n, s);
+    if (wcyc) {
+      cycle64(c, *c->hist[Re - 1], 0, v, zz, 2);
+      if (wcycles) *wcycles += 1;
+    } else {
+      for (int j = 0; j < Re; ++j) cycle64(c, *c->hist[j], 0, v, zz, 1);
+      for (int j = Re - 1; j >= 0; --j) cycle64(c, *c->hist[j], 0, v, zz, 1);
+      if (vcycles) *vcycles += 2 * Re;
+    }
+    sum_f64(zz, n, scal.p + 1, s);
+    sub_mean_f64(zz, scal.p + 1, n, s);
+  };
+  fill_f64(e, 0.0, n, s);
+  copy_d2d(rr.p, r, n, s);
+  prec(rr.p, z.p);
+  copy_d2d(p.p, z.p, n, s);
+  double rz = dot(rr.p, z.p);
+  for (int t = 0; t < steps; ++t) {
+    spmv<double>(n, A.rp.p, A.ci.p, A.av.p, A.d.p, p.p, q.p, s);
+    const double pq = dot(p.p, q.p);
+    if (!(pq > 0.0)) break;
+    const double alpha = rz / pq;
+    axpy_f64(alpha, p.p, e, n, s);
+    if (t + 1 == steps) break;
+    axpy_f64(-alpha, q.p, rr.p, n, s);
+    prec(rr.p, z.p);
+    const double rz2 = dot(rr.p, z.p);
+    const double beta = rz2 / rz;
+    DVec<double> bd(1);
+    copy_h2d(bd.p, &beta, 1, s);
+    xpby_dev_f64(z.p, bd.p, p.p, n, s);
+    sync(s);  // `beta` is a host temporary
+    rz = rz2;
+  }
+  sum_f64(e, n, scal.p + 1, s);
+  sub_mean_f64(e, scal.p + 1, n, s);
+}
+
+// ---------------------------------------------------------------------------
+// Adaptive solve (Alg. 5): standalone V-cycles or FCG(1) with a V-cycle
+// preconditioner (FP64 or FP32), in the solve layout of the finest level.
+// ---------------------------------------------------------------------------
+void solve(pcamg_ctx* c, double* x_nat, pcamg_stats* st) {
+  hipStream_t s = c->s;
+  const pcamg_params& P = c->P;
+  const int32_t n = c->n;
+  const LevelMatrix& A = *c->M0;
+  require(c->have_rhs, PCAMG_EINVAL, "no right-hand side");
+  require(!c->hist.empty(), PCAMG_EINVAL, "no hierarchy");
+  Timer total(s);
+  double t_rebuild = 0.0;
+  int vc64 = 0, vc32 = 0, wc = 0;
+  DVec<double> b(n), x(n), r(n), scal(4);
+  gather_f64(c->rhs.p, A.perm.p, b.p, n, s);
+  gather_f64(x_nat, A.perm.p, x.p, n, s);
+  auto dot = [&](const double* a, const double* bb) {
+    dot_f64(a, bb, n, scal.p, s);
+    return read_scalar(scal.p, s);
+  };
+  auto remove_mean = [&](double* v) {
+    sum_f64(v, n, scal.p + 1, s);
+    sub_mean_f64(v, scal.p + 1, n, s);
+  };
+  auto res_of = [&](const double* xx, double* rr) { residual<double>(n, A.rp.p, A.ci.p, A.av.p, A.d.p, b.p, xx, rr, s); };
+  std::vector<double> hist{1.0};
+  std::vector<double> conv, conv_all;
+  int rebuilds = 0, k = 0, status = PCAMG_OK;
+  double oc_sum = 0.0;
+  for (auto& h : c->hist) oc_sum += h->op_complexity;
+  int nh = (int)c->hist.size();
+  res_of(x.p, r.p);
+  const double nr0 = std::sqrt(dot(r.p, r.p));
+  double nr = nr0, nr_prev = nr0;
+  auto triggered = [&]() {
+    if (rebuilds >= P.max_rebuilds) return false;
+    if (P.rebuild_rule == 1) return conv.back() > P.theta;
+    double mean = 0.0;
+    for (double q : conv) mean = mean + q;
+    mean = mean / (double)conv.size();
+    return mean > P.theta;
+  };
+  // re-setup (Alg. 5, Steps 13-16); corr is the correction for x (0 for the relaxation source)
+  auto rebuild = [&](const double* res, double* corr) {
+    Timer tr(s);
+    const int Re = (int)c->hist.size();
+    DVec<double> eb(n), enat(n), zero(n);
+    if (P.rebuild_source == PCAMG_REBUILD_ERROR_APPROX) {
+      int nw = 0, nv = 0;
+      approx_error(c, Re, res, corr, &nw, &nv);
+      wc += nw;
+      vc64 += nv;
+      copy_d2d(eb.p, corr, n, s);
+    } else {
+      xi_fill(P.seed, Re, A.perm.p, eb.p, n, s);
+      fill_f64(zero.p, 0.0, n, s);
+      for (int q = 0; q < P.rebuild_vcycles; ++q) cycle64(c, *c->hist.back(), 0, zero.p, eb.p, 1);
+      vc64 += P.rebuild_vcycles;
+      fill_f64(corr, 0.0, n, s);
+    }
+    fill_f64(zero.p, 0.0, n, s);
+    relax_perm(c, eb.p, zero.p, P.relax_sweeps);
+    scatter_f64(eb.p, A.perm.p, enat.p, n, s);
+    c->hist.push_back(build_hierarchy(c, enat.p));
+    oc_sum += c->hist.back()->op_complexity;
+    ++nh;
+    ++rebuilds;
+    conv.clear();
+    t_rebuild += tr.ms();
+  };
+  if (nr0 > 0.0) {
+    if (P.outer == PCAMG_OUTER_VCYCLE) {
+      DVec<double> corr(n);
+      while (k < P.max_iter) {
+        cycle64(c, *c->hist.back(), 0, b.p, x.p, 1);
+        ++vc64;
+        remove_mean(x.p);
+        res_of(x.p, r.p);
+        nr = std::sqrt(dot(r.p, r.p));
+        ++k;
+        const double cr = nr / nr_prev;
+        conv.push_back(cr);
+        conv_all.push_back(cr);
+        nr_prev = nr;
+        hist.push_back(nr / nr0);
+        if (!std::isfinite(nr)) { status = PCAMG_ENAN; break; }
+        if (nr / nr0 <= P.tol) break;
+        if (triggered()) {
+          rebuild(r.p, corr.p);
+          if (P.rebuild_source == PCAMG_REBUILD_ERROR_APPROX) {
+            axpy_f64(1.0, corr.p, x.p, n, s);
+            res_of(x.p, r.p);
+            nr_prev = std::sqrt(dot(r.p, r.p));
+          }
+        }
+      }
+    } else {
+      DVec<double> z(n), p(n), q(n), rn(n), zn(n), corr(n), x32buf(1);
+      DVec<float> r32(n), z32(n);
+      auto precond = [&](const double* rr, double* zz) {
+        Hierarchy& H = *c->hist.back();
+        if (P.cycle_prec == PCAMG_PREC_F32) {
+          cast_f64_f32(rr, r32.p, n, s);
+          fill_f32(z32.p, 0.0f, n, s);
+          cycle32(c, H, 0, r32.p, z32.p);
+          cast_f32_f64(z32.p, zz, n, s);
+          ++vc32;
+        } else {
+          fill_f64(zz, 0.0, n, s);
+          cycle64(c, H, 0, rr, zz, 1);
+          ++vc64;
+        }
+        remove_mean(zz);
+      };
+      precond(r.p, z.p);
+      copy_d2d(p.p, z.p, n, s);
+      double rz = dot(r.p, z.p);
+      while (k < P.max_iter) {
+        spmv<double>(n, A.rp.p, A.ci.p, A.av.p, A.d.p, p.p, q.p, s);
+        const double pq = dot(p.p, q.p);
+        if (!(pq > 0.0)) { status = PCAMG_EBREAKDOWN; break; }
+        const double alpha = rz / pq;
+        axpy_f64(alpha, p.p, x.p, n, s);
+        copy_d2d(rn.p, r.p, n, s);
+        axpy_f64(-alpha, q.p, rn.p, n, s);
+        nr = std::sqrt(dot(rn.p, rn.p));
+        ++k;
+        const double cr = nr / nr_prev;
+        conv.push_back(cr);
+        conv_all.push_back(cr);
+        nr_prev = nr;
+        hist.push_back(nr / nr0);
+        if (!std::isfinite(nr)) { status = PCAMG_ENAN; break; }
+        if (nr / nr0 <= P.tol) { copy_d2d(r.p, rn.p, n, s); break; }
+        bool restart = false;
+        if (triggered()) {
+          rebuild(rn.p, corr.p);
+          if (P.rebuild_source == PCAMG_REBUILD_ERROR_APPROX) {
+            axpy_f64(1.0, corr.p, x.p, n, s);
+            res_of(x.p, rn.p);
+            nr_prev = std::sqrt(dot(rn.p, rn.p));
+          }
+          restart = true;
+        }
+        precond(rn.p, zn.p);
+        if (restart) {
+          copy_d2d(p.p, zn.p, n, s);
+        } else {
+          zsub_dot_f64(zn.p, rn.p, r.p, n, scal.p + 2, s);
+          const double num = read_scalar(scal.p + 2, s);
+          const double beta = num / rz;
+          DVec<double> bd(1);
+          copy_h2d(bd.p, &beta, 1, s);
+          xpby_dev_f64(zn.p, bd.p, p.p, n, s);
+          sync(s);
+        }
+        rz = dot(rn.p, zn.p);
+        std::swap(r, rn);
+        std::swap(z, zn);
+      }
+      remove_mean(x.p);
+    }
+  }
+  if (status == PCAMG_OK && nr0 > 0.0 && nr / nr0 > P.tol) status = PCAMG_ENOCONV;
+  // true residual
+  res_of(x.p, r.p);
+  const double true_rel = nr0 > 0.0 ? std::sqrt(dot(r.p, r.p)) / nr0 : 0.0;
+  scatter_f64(x.p, A.perm.p, x_nat, n, s);
+  sync(s);
+  if (st) {
+    st->iterations = k;
+    st->rebuilds = rebuilds;
+    st->levels = (int32_t)c->hist.back()->lv.size();
+    st->status = status;
+    st->relres = nr0 > 0.0 ? nr / nr0 : 0.0;
+    st->true_relres = true_rel;
+    st->rho_geo = k > 0 ? std::pow(st->relres, 1.0 / k) : 0.0;
+    const int m10 = std::min<int>(10, (int)conv_all.size());
+    double s10 = 0.0;
+    for (int t = (int)conv_all.size() - m10; t < (int)conv_all.size(); ++t) s10 = s10 + conv_all[t];
+    st->convr_last10 = m10 ? s10 / m10 : 0.0;
+    st->op_complexity = oc_sum / nh;
+    st->t_solve_ms = total.ms();
+    st->t_rebuild_ms = t_rebuild;
+    st->t_setup_ms = c->t_build_ms;
+    st->vcycles64 = vc64;
+    st->vcycles32 = vc32;
+    st->wcycles = wc;
+    st->hist_len = 0;
+    if (st->relres_hist && st->hist_cap > 0) {
+      const int h = std::min<int>(st->hist_cap, (int)hist.size());
+      for (int t = 0; t < h; ++t) st->relres_hist[t] = hist[t];
+      st->hist_len = h;
+    }
+  }
+  if (status != PCAMG_OK) throw Error(status, std::string(pcamg_status_str(status)) + " after " + std::to_string(k) +
+                                                  " iterations");
+}
+
+// Smoother timing on the finest level of the current hierarchy.
+void bench_smoother(pcamg_ctx* c, int prec, int sweeps, double* ms, int64_t* launches, double* bytes) {
+  hipStream_t s = c->s;
+  const LevelMatrix& A = *c->M0;
+  const int32_t n = A.n;
+  const size_t vs = prec == PCAMG_PREC_F32 ? 4 : 8;
+  std::vector<int32_t> rp = to_host(A.rp.p, n + 1, s);
+  double per_sweep = 0.0;
+  for (int k = 0; k < A.ncol; ++k) {
+    const double rows = A.coff[k + 1] - A.coff[k];
+    const double nz = rp[A.coff[k + 1]] - rp[A.coff[k]];
+    per_sweep += (vs + 4.0) * nz + 4.0 * (rows + 1.0) + 4.0 * vs * rows;
+  }
+  DVec<double> b(n), x(n);
+  DVec<float> b32(n), x32(n);
+  xi_fill(c->P.seed, 7, nullptr, b.p, n, s);
+  xi_fill(c->P.seed, 8, nullptr, x.p, n, s);
+  cast_f64_f32(b.p, b32.p, n, s);
+  cast_f64_f32(x.p, x32.p, n, s);
+  auto sweep = [&]() {
+    for (int k = 0; k < A.ncol; ++k) {
+      if (prec == PCAMG_PREC_F32)
+        gs_colour<float>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b32.p, x32.p, s);
+      else
+        gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b.p, x.p, s);
+    }
+    for (int k = A.ncol - 1; k >= 0; --k) {
+      if (prec == PCAMG_PREC_F32)
+        gs_colour<float>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b32.p, x32.p, s);
+      else
+        gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b.p, x.p, s);
+    }
+  };
+  sweep();  // warm-up
+  Timer t(s);
+  for (int q = 0; q < sweeps; ++q) sweep();
+  *ms = t.ms();
+  *launches = (int64_t)sweeps * 2 * A.ncol;
+  *bytes = per_sweep * 2.0 * sweeps;
+}
+
+}  // namespace pcamg

@@ -1,0 +1,38 @@
+"""The C-ABI library loads and exports every function include/pcamg.h declares
+(no GPU needed: no compute call is made)."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "pcamg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pcamg_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_matches_binding():
+    from paper_1806_07028_amd import _lib
+
+    assert declared() == _lib.EXPORTED
+
+
+def test_library_exports_everything():
+    from paper_1806_07028_amd import _lib
+
+    L = ctypes.CDLL(_lib.LIB_PATH)
+    missing = [f for f in declared() if not hasattr(L, f)]
+    assert not missing, missing
+
+
+def test_params_default_and_struct_layout():
+    from paper_1806_07028_amd import _lib
+
+    p = _lib.default_params()
+    assert p.tol == 1e-8 and p.max_iter == 2500 and p.coarse_max == 64 and p.relax_sweeps == 3
+    assert (p.numW, p.iterW, p.iterV) == (2, 7, 4)
+    assert p.seed == 0x5EED and p.colour_seed == 0xC010
+    assert ctypes.sizeof(_lib.Params) == 8 + 8 + 18 * 4 + 8 + 8
+    assert _lib.lib().pcamg_status_str(-6) == b"graph not connected"

@@ -1,0 +1,371 @@
+"""GPU parity: every stage of the HIP library against the CPU oracle on the same
+seeded inputs.
+
+Bars (written per assertion):
+ * integer / index outputs (colours, A^2 pattern, edge order, path cover,
+   orientation, aggregates, coarse covers): bit-exact;
+ * FP64 kernels whose summation order is defined (Laplacian, Gauss-Seidel,
+   residual, Galerkin, prolongation values, cycles, coarsest solve): bit-exact;
+ * quantities that pass through global reductions (Alg. 2 PCG steps, norms,
+   means, the adaptive loop): relative 1e-12 per vector, iteration counts equal.
+"""
+import numpy as np
+import pytest
+
+from paper_1806_07028_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1806_07028_amd as P
+
+    P.lib()
+    return P
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def same(a, b):
+    """Bit-for-bit equality (floats compared as their bit patterns)."""
+    a, b = np.asarray(a), np.asarray(b)
+    assert a.shape == b.shape, (a.shape, b.shape)
+    if a.dtype.kind == "f":
+        assert a.dtype == b.dtype, (a.dtype, b.dtype)
+        u = np.uint64 if a.itemsize == 8 else np.uint32
+        ne = a.view(u) != b.view(u)
+    else:
+        ne = a != b
+    if ne.any():
+        i = np.flatnonzero(ne)[:5]
+        raise AssertionError(f"{int(ne.sum())} of {a.size} differ, e.g. idx {i}: {a.ravel()[i]} vs {b.ravel()[i]}")
+
+
+GRAPHS = {
+    "grid64": lambda: I.grid2d(64, 64),
+    "grid3d_w": lambda: I.grid3d(17, 13, 11, weight_seed=3),
+    "rgg": lambda: I.rgg(5000, 11),
+    "ring": lambda: I.ring(3001, 4),
+    "ba": lambda: I.csr_from_edges(*I.ba_edges(2000, 5), I.log_uniform_weights(6, len(I.ba_edges(2000, 5)[1]),
+                                                                               -2, 2)),
+    "hub": lambda: hub_graph(),
+}
+
+
+def hub_graph():
+    """Ring lattice plus one hub joined to every 5th vertex: its A^2 row and the
+    coarse rows around it take the long-row paths."""
+    n0, a, b = I.ring_edges(3000, 4)
+    hub = np.full(600, 3000)
+    a2, b2 = I.canonical_edges(np.concatenate([a, hub]), np.concatenate([b, np.arange(0, 3000, 5)]))
+    return I.csr_from_edges(3001, a2, b2, I.log_uniform_weights(4, len(a2), -1, 1))
+
+
+@pytest.fixture(scope="module", params=list(GRAPHS))
+def graph(request):
+    return request.param, GRAPHS[request.param]()
+
+
+def test_laplacian_colour_gs_residual(gpu, oracle, graph):
+    name, g = graph
+    n, rp, ci, w = g
+    S = gpu.stages
+    a, d, dinv = S.laplacian(rp, ci, w)
+    ra, rd, rdinv = oracle.laplacian(g)
+    same(host(a), ra)
+    same(host(d), rd)
+    same(host(dinv), rdinv)
+    for level in (0, 5):
+        col, nc = S.colour(rp, ci, 0xC010, level)
+        rcol, rnc = oracle.colour(n, rp, ci, 0xC010, level)
+        assert nc == rnc
+        same(host(col), rcol)
+    col, nc = oracle.colour(n, rp, ci, 0xC010, 0)
+    b = I.normal(1, n)
+    x0 = I.normal(2, n)
+    for fwd in (True, False):
+        got = S.gs(rp, ci, ra, rdinv, col, nc, b, x0, forward=fwd, count=2)
+        ref = oracle.gs(n, rp, ci, ra, rdinv, col, nc, b, x0, forward=fwd, count=2)
+        same(host(got), ref)
+    same(host(S.residual(rp, ci, ra, rd, b, x0)), oracle.residual(n, rp, ci, ra, rd, b, x0))
+
+
+def test_a2_sort_cover_orient(gpu, oracle, graph):
+    name, g = graph
+    n, rp, ci, w = g
+    S = gpu.stages
+    rp2, ci2 = S.a2_pattern(rp, ci)
+    orp2, oci2 = oracle.a2_pattern(n, rp, ci)
+    same(host(rp2), orp2)
+    same(host(ci2), oci2)
+    e = oracle.smooth_error(g, 0xC010, 7, 3)
+    su, sv = S.sort_edges(orp2, oci2, e)
+    osu, osv = oracle.sorted_edges(n, orp2, oci2, e)
+    same(host(su), osu)
+    same(host(sv), osv)
+    nb = S.path_cover(n, osu, osv)
+    onb = oracle.path_cover(n, osu, osv)
+    same(np.sort(host(nb), axis=1), np.sort(onb, axis=1))
+    pid, pos, plen = S.orient(onb)
+    opid, opos, oplen, _ = oracle.orient(onb)
+    same(host(pid), opid)
+    same(host(pos), opos)
+    same(host(plen), oplen)
+
+
+def test_a2_hub_cap(gpu, oracle):
+    g = GRAPHS["ba"]()
+    n, rp, ci, w = g
+    rp2, ci2 = gpu.stages.a2_pattern(rp, ci, hub_cap=20)
+    orp2, oci2 = oracle.a2_pattern(n, rp, ci, 20)
+    same(host(rp2), orp2)
+    same(host(ci2), oci2)
+
+
+def test_path_cover_adversarial_orders(gpu, oracle):
+    """Random edge orders on dense random graphs: many conflicts per round."""
+    rng = np.random.default_rng(0)
+    for t in range(6):
+        n = int(rng.integers(50, 3000))
+        m = int(rng.integers(n, 8 * n))
+        a, b = I.canonical_edges(rng.integers(0, n, m), rng.integers(0, n, m))
+        order = rng.permutation(len(a))
+        su, sv = a[order].astype(np.int32), b[order].astype(np.int32)
+        nb = gpu.stages.path_cover(n, su, sv)
+        onb = oracle.path_cover(n, su, sv)
+        same(np.sort(host(nb), axis=1), np.sort(onb, axis=1))
+
+
+def test_aggregate_galerkin_shorten(gpu, oracle, graph):
+    name, g = graph
+    n = g[0]
+    H = oracle.Hierarchy(g, None, coarse_max=16)
+    S = gpu.stages
+    for level in range(min(H.nlevels - 1, 4)):
+        grp, gci, gv = H.get_int(level, "G_rp"), H.get_int(level, "G_ci"), H.get_dbl(level, "G_v")
+        gkey = H.get_dbl(level, "gkey") if level == 0 else None
+        nb = H.get_int(level, "nb")
+        agg, nc, st = S.aggregate(grp, gci, gv, nb, gkey)
+        ragg, rnc, rst = oracle.aggregate(len(grp) - 1, grp, gci, gv, nb, gkey)
+        assert nc == rnc and st == rst
+        same(host(agg), ragg)
+        same(ragg, H.get_int(level, "agg"))
+        rp, ci, av, d = H.level_matrix(level)
+        pv = H.get_dbl(level, "pval")
+        rpc, cic, vc, dc = S.galerkin(rp, ci, av, d, nc, ragg, pv)
+        orpc, ocic, ovc, odc = oracle.galerkin(len(rp) - 1, rp, ci, av, d, nc, ragg, pv)
+        same(host(rpc), orpc)
+        same(host(cic), ocic)
+        same(host(vc), ovc)
+        same(host(dc), odc)
+        nbc = S.shorten(nb, nc, ragg)
+        same(host(nbc), oracle.shorten(nb, nc, ragg))
+
+
+def solver_for(gpu, g, b=None, **kw):
+    n, rp, ci, w = g
+    if b is None:
+        b = I.zero_mean_normal_rhs(99, n)
+    return gpu.Solver(rp, ci, w, b, keep_setup=1, **kw)
+
+
+def compare_hierarchy(s, H, h=-1):
+    assert s.num_levels(h) == H.nlevels
+    for l in range(H.nlevels):
+        gi, oi = s.level_info(l, h), H.info(l)
+        for k in ("n", "nnz", "ncolours", "nc", "nnz_G", "npaths", "n_unagg", "case1", "case2", "case3", "middle",
+                  "singleton", "p1_fallback", "grounded", "coarse_fallback", "n_path_vertices"):
+            if l == H.nlevels - 1 and k in ("nnz_G",):
+                continue
+            assert gi[k] == oi[k], (l, k, gi[k], oi[k])
+        for name in ("colour", "A_rp", "A_ci", "A_v", "d", "dinv"):
+            same(s.level_get(l, name, h), H.get_int(l, name) if name[0] in "cA" and name != "A_v" else
+                 H.get_dbl(l, name))
+        if l + 1 < H.nlevels:
+            for name in ("agg", "path_id", "pos", "G_rp", "G_ci"):
+                same(s.level_get(l, name, h), H.get_int(l, name))
+            same(s.level_get(l, "G_v", h), H.get_dbl(l, "G_v"))
+            same(np.sort(s.level_get(l, "nb", h).reshape(-1, 2), axis=1),
+                 np.sort(H.get_int(l, "nb").reshape(-1, 2), axis=1))
+            opv = H.get_dbl(l, "pval")
+            if l == 0 and not np.all(opv == 1.0):  # smooth prolongation values on level 1
+                same(s.level_get(l, "pval", h), opv)
+            else:  # boolean levels: the library stores no values
+                assert np.all(opv == 1.0)
+    same(s.level_get(0, "gkey", h), H.get_dbl(0, "gkey"))
+
+
+@pytest.mark.parametrize("p1", ["smooth", "const"])
+def test_first_hierarchy_bit_exact(gpu, oracle, graph, p1):
+    name, g = graph
+    s = solver_for(gpu, g, p1_mode=p1)
+    H = oracle.Hierarchy(g, None, p1_mode=0 if p1 == "smooth" else 1)
+    same(host(s.initial_error()), H.get_dbl(0, "e"))
+    compare_hierarchy(s, H)
+
+
+def test_rebuild_from_given_error(gpu, oracle):
+    g = GRAPHS["grid3d_w"]()
+    n = g[0]
+    e = I.normal(5, n)
+    s = solver_for(gpu, g)
+    s.rebuild(torch.as_tensor(e, device="cuda"))
+    # the library relaxes e (3 symmetric sweeps on A e = 0) before building
+    H = oracle.Hierarchy(g, e_relaxed(oracle, g, e))
+    compare_hierarchy(s, H, h=1)
+
+
+@pytest.mark.parametrize("gname", ["grid64", "grid3d_w", "rgg"])
+def test_cycles_bit_exact(gpu, oracle, gname):
+    g = GRAPHS[gname]()
+    n = g[0]
+    s = solver_for(gpu, g)
+    H = oracle.Hierarchy(g, None)
+    b = I.zero_mean_normal_rhs(3, n)
+    x0 = I.normal(4, n)
+    for gamma in (1, 2):
+        same(host(s.cycle(b, x0, gamma)), H.cycle(b, x0, gamma))
+    b32 = b.astype(np.float32)
+    same(host(s.cycle32(b32)), H.vcycle32(b32))
+    # coarsest grounded case (boolean prolongations)
+    sc = solver_for(gpu, g, p1_mode="const")
+    Hc = oracle.Hierarchy(g, None, p1_mode=1)
+    same(host(sc.cycle(b, None, 1)), Hc.vcycle(b))
+
+
+def test_approx_error(gpu, oracle):
+    """Alg. 2 with one hierarchy (W-cycle preconditioner), relative 1e-12."""
+    g = GRAPHS["grid3d_w"]()
+    n = g[0]
+    s = solver_for(gpu, g)
+    H1 = oracle.Hierarchy(g, None)
+    r = I.zero_mean_normal_rhs(8, n)
+    e1 = host(s.approx_error(r, count=1))
+    o1 = oracle.approximate_error([H1], r)
+    assert np.linalg.norm(e1 - o1) <= 1e-12 * np.linalg.norm(o1)
+
+
+def e_relaxed(oracle, g, e):
+    n, rp, ci, w = g
+    a, d, dinv = oracle.laplacian(g)
+    col, nc = oracle.colour(n, rp, ci, 0xC010, 0)
+    z = np.zeros(n)
+    e = np.array(e, float)
+    for _ in range(3):
+        e = oracle.gs(n, rp, ci, a, dinv, col, nc, z, e, True)
+        e = oracle.gs(n, rp, ci, a, dinv, col, nc, z, e, False)
+    return e
+
+
+def test_composite_approx_error(gpu, oracle):
+    g = GRAPHS["grid64"]()
+    n = g[0]
+    s = solver_for(gpu, g)
+    e2, e3 = I.normal(31, n), I.normal(32, n)
+    s.rebuild(torch.as_tensor(e2, device="cuda"))
+    s.rebuild(torch.as_tensor(e3, device="cuda"))
+    Hs = [oracle.Hierarchy(g, None), oracle.Hierarchy(g, e_relaxed(oracle, g, e2)),
+          oracle.Hierarchy(g, e_relaxed(oracle, g, e3))]
+    r = I.zero_mean_normal_rhs(9, n)
+    for count in (1, 2, 3):
+        got = host(s.approx_error(r, count=count))
+        ref = oracle.approximate_error(Hs[:count], r)
+        assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref), count
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(p1_mode="const"), dict(outer="fcg", cycle_prec="f32", theta=0.5),
+                                dict(outer="fcg", cycle_prec="f64", theta=0.5), dict(theta=1e-6)])
+def test_solve_matches_oracle(gpu, oracle, kw):
+    g, b = I.config1()
+    okw = {k: {"const": 1, "smooth": 0, "fcg": 1, "f32": 1, "f64": 0}.get(v, v) for k, v in kw.items()}
+    ref = oracle.solve(g, b, **okw)
+    s = solver_for(gpu, g, b, **kw)
+    x, st = s.solve()
+    assert st["status"] == 0
+    assert st["iterations"] == ref.stats["iterations"]
+    assert st["rebuilds"] == ref.stats["rebuilds"]
+    assert st["true_relres"] <= 1.0001e-8
+    # Until the first re-setup every step is reproduced (reductions aside); a
+    # re-setup's smooth error comes from Alg. 2's PCG, whose dot products feed
+    # the key order, so later hierarchies may differ at near-ties of the keys.
+    hist = st["relres_hist"]
+    k1 = (int(ref.rebuild_at[0]) if len(ref.rebuild_at) else len(hist) - 1) + 1
+    assert np.allclose(hist[:k1], ref.relres_hist[:k1], rtol=1e-10, atol=0)
+    xs = host(x)
+    assert np.linalg.norm(xs - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
+
+
+def test_solve_3d_weighted(gpu, oracle):
+    g = I.grid3d(24, 24, 24, weight_seed=1)
+    b = I.zero_mean_normal_rhs(5, g[0])
+    for kw, okw in [(dict(theta=0.5), dict(theta=0.5)),
+                    (dict(outer="fcg", cycle_prec="f32", theta=0.5), dict(outer=1, cycle_prec=1, theta=0.5))]:
+        ref = oracle.solve(g, b, **okw)
+        s = solver_for(gpu, g, b, **kw)
+        x, st = s.solve()
+        assert st["status"] == 0 and st["true_relres"] <= 1.0001e-8
+        assert abs(st["iterations"] - ref.stats["iterations"]) <= 1
+        assert abs(st["rebuilds"] - ref.stats["rebuilds"]) <= 1
+
+
+def test_edge_cases(gpu, oracle):
+    # tiny graphs: a single level (n <= coarse_max) is a direct grounded solve
+    for g in (I.path(2), I.path(3), I.grid2d(3, 3)):
+        n = g[0]
+        b = I.zero_mean_normal_rhs(1, n)
+        s = solver_for(gpu, g, b)
+        x, st = s.solve()
+        assert st["iterations"] == 1 and st["true_relres"] <= 1e-12
+        same(host(x), oracle.solve(g, b).x)
+    # forced coarsening of the worked example
+    g = I.grid2d(3, 3)
+    s = solver_for(gpu, g, coarse_max=1)
+    e = np.array([x + y for y in range(3) for x in range(3)], float)
+    s.rebuild(torch.as_tensor(e, device="cuda"))
+    H = oracle.Hierarchy(g, e_relaxed(oracle, g, e), coarse_max=1)
+    compare_hierarchy(s, H, h=1)
+    # zero rhs returns at once
+    g = I.grid2d(10, 10)
+    s = solver_for(gpu, g, np.zeros(100))
+    x, st = s.solve()
+    assert st["iterations"] == 0 and float(x.abs().max()) == 0.0
+
+
+def test_errors(gpu):
+    import paper_1806_07028_amd as P
+
+    n, rp, ci, w = I.grid2d(5, 5)
+    b = I.zero_mean_normal_rhs(1, n)
+    with pytest.raises(P.PcamgError) as ei:
+        P.Solver(rp, ci, w, b + 1.0)
+    assert ei.value.status == -7
+    w2 = w.copy()
+    w2[3] = -1.0
+    with pytest.raises(P.PcamgError) as ei:
+        P.Solver(rp, ci, w2, b)
+    assert ei.value.status in (-5, -2)
+    w3 = w.copy()
+    w3[0] *= 2.0
+    with pytest.raises(P.PcamgError) as ei:
+        P.Solver(rp, ci, w3, b)
+    assert ei.value.status == -2
+    # two components
+    n2, a2, b2 = I.grid2d_edges(4, 4)
+    a2 = np.concatenate([a2, a2 + 16])
+    b2 = np.concatenate([b2, b2 + 16])
+    g = I.csr_from_edges(32, a2, b2, np.ones(len(a2)))
+    with pytest.raises(P.PcamgError) as ei:
+        P.Solver(g[1], g[2], g[3], I.zero_mean_normal_rhs(1, 32))
+    assert ei.value.status == -6
+    # max_iter reached
+    g, b = I.config1()
+    s = P.Solver(g[1], g[2], g[3], b, max_iter=2, theta=1e9)
+    x, st = s.solve(raise_on_noconv=False)
+    assert st["status"] == -10 and st["iterations"] == 2
