@@ -113,6 +113,7 @@ def lib():
     L.or_hier_vcycle32.argtypes = [C.c_void_p, _f32p, _f32p]
     L.or_hier_coarsest_solve.argtypes = [C.c_void_p, _f64p, _f64p]
     L.or_hier_cycle.argtypes = [C.c_void_p, _f64p, _f64p, C.c_int]
+    L.or_hier_cycle32.argtypes = [C.c_void_p, _f32p, _f32p, C.c_int]
     L.or_approx_error.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.POINTER(OracleParams), _f64p, _f64p]
     L.or_hier_relax_error.argtypes = [C.c_void_p, C.POINTER(OracleParams), C.c_int, _f64p]
     L.or_galerkin.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, C.c_int, _i32p, _f64p, _i32p, C.c_void_p,
@@ -354,6 +355,11 @@ class Hierarchy:
     def cycle(self, b, x=None, gamma: int = 1) -> np.ndarray:
         x = np.zeros(self.n) if x is None else _f64(x).copy()
         lib().or_hier_cycle(self.h, _f64(b), x, gamma)
+        return x
+
+    def cycle32(self, b32, x32=None, gamma: int = 1) -> np.ndarray:
+        x = np.zeros(self.n, np.float32) if x32 is None else np.ascontiguousarray(x32, np.float32).copy()
+        lib().or_hier_cycle32(self.h, np.ascontiguousarray(b32, np.float32), x, gamma)
         return x
 
     def relax_error(self, r: int) -> np.ndarray:

@@ -40,7 +40,8 @@
 //    the coarse correction; x made orthogonal to 1 after each cycle; ConvR =
 //    ||r_{k+1}||/||r_k||; rebuild when the mean ConvR since the last rebuild
 //    exceeds theta; relative residual tolerance.  FCG(1) variant with an FP32
-//    V-cycle preconditioner (not in the paper).
+//    V-cycle preconditioner (not in the paper); the FP32 setting applies to
+//    every cycle used as a preconditioner inside an FP64 PCG, i.e. to Alg. 2 too.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -99,7 +100,7 @@ struct Params {
   double theta;
   int max_iter;
   int outer;           // 0 standalone V-cycle, 1 FCG
-  int cycle_prec;      // 0 FP64, 1 FP32 (FCG preconditioner only)
+  int cycle_prec;      // 0 FP64, 1 FP32 (every preconditioning cycle: outer FCG and Alg. 2's PCG)
   int coarse_max;
   int relax_sweeps;
   int rebuild_vcycles; // V-cycles on A e = 0 before the sweeps (rebuild_source 1)
@@ -730,9 +731,10 @@ void cycle64(const Hierarchy& H, int l, const double* b, double* x, int gamma) {
 
 void vcycle64(const Hierarchy& H, int l, const double* b, double* x) { cycle64(H, l, b, x, 1); }
 
-// The V-cycle in FP32 on FP32 copies of A_l, d_l, dinv_l and P; the coarsest
-// solve stays FP64 (inputs widened, result rounded to nearest).
-void vcycle32(const Hierarchy& H, int l, const float* b, float* x) {
+// The same cycle in FP32 on FP32 copies of A_l, d_l, dinv_l and P (gamma = 1
+// V, 2 W); the coarsest solve stays FP64 (inputs widened, result rounded to
+// nearest).
+void cycle32(const Hierarchy& H, int l, const float* b, float* x, int gamma) {
   const Level& L = H.lv[l];
   if (l + 1 == (int)H.lv.size()) {
     std::vector<double> b64(L.n), x64(L.n, 0.0);
@@ -749,10 +751,13 @@ void vcycle32(const Hierarchy& H, int l, const float* b, float* x) {
     for (int t = L.moff[I]; t < L.moff[I + 1]; ++t) s = std::fma(H.p32[l][L.mem[t]], r[L.mem[t]], s);
     bc[I] = s;
   }
-  vcycle32(H, l + 1, bc.data(), xc.data());
+  const int calls = (gamma > 1 && l + 2 < (int)H.lv.size()) ? gamma : 1;
+  for (int c = 0; c < calls; ++c) cycle32(H, l + 1, bc.data(), xc.data(), gamma);
   for (int k = 0; k < L.n; ++k) x[k] = std::fma(H.p32[l][k], xc[L.agg[k]], x[k]);
   gs_sweep_t<float>(L, H.a32[l], H.dinv32[l], b, x, false);
 }
+
+void vcycle32(const Hierarchy& H, int l, const float* b, float* x) { cycle32(H, l, b, x, 1); }
 
 // ---------------------------------------------------------------------------
 // Hierarchy construction (Alg. 4) from the finest level (A, d, dinv, colours)
@@ -882,9 +887,21 @@ void approximate_error(const Level& fine, const std::vector<Hierarchy>& hist, in
   const int n = fine.n;
   const bool wcyc = Re <= P.numW;
   const int steps = wcyc ? P.iterW : P.iterV;
+  // cycle_prec = FP32: the preconditioning cycles run in FP32 on FP32 copies,
+  // their input rounded and their result widened once
   auto prec = [&](const std::vector<double>& v, std::vector<double>& z) {
     z.assign(n, 0.0);
-    if (wcyc) {
+    if (P.cycle_prec == 1) {
+      std::vector<float> v32(n), z32(n, 0.0f);
+      for (int i = 0; i < n; ++i) v32[i] = (float)v[i];
+      if (wcyc) {
+        cycle32(hist.back(), 0, v32.data(), z32.data(), 2);
+      } else {
+        for (int j = 0; j < Re; ++j) cycle32(hist[j], 0, v32.data(), z32.data(), 1);
+        for (int j = Re - 1; j >= 0; --j) cycle32(hist[j], 0, v32.data(), z32.data(), 1);
+      }
+      for (int i = 0; i < n; ++i) z[i] = (double)z32[i];
+    } else if (wcyc) {
       cycle64(hist.back(), 0, v.data(), z.data(), 2);
     } else {
       for (int j = 0; j < Re; ++j) cycle64(hist[j], 0, v.data(), z.data(), 1);
@@ -1366,6 +1383,12 @@ void or_hier_vcycle32(void* hp, const float* b, float* x) {
 void or_hier_coarsest_solve(void* hp, const double* b, double* x) {
   auto* h = static_cast<HierHandle*>(hp);
   coarsest_solve(h->H.cs, b, x);
+}
+
+// One FP32 cycle (gamma = 1 V, 2 W) of this hierarchy at level 0.
+void or_hier_cycle32(void* hp, const float* b, float* x, int gamma) {
+  auto* h = static_cast<HierHandle*>(hp);
+  cycle32(h->H, 0, b, x, gamma);
 }
 
 // One cycle (gamma = 1 V, 2 W) of this hierarchy at level 0.

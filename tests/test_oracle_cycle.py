@@ -151,6 +151,38 @@ def test_fp32_cycle_close(oracle):
     x64 = H.vcycle(b)
     x32 = H.vcycle32(b.astype(np.float32))
     assert np.linalg.norm(x32 - x64) <= 1e-5 * np.linalg.norm(x64)
+    # the FP32 W-cycle is the FP64 W-cycle up to single-precision rounding
+    w64 = H.cycle(b, None, 2)
+    w32 = H.cycle32(b.astype(np.float32), None, 2)
+    assert np.linalg.norm(w32 - w64) <= 1e-5 * np.linalg.norm(w64)
+    assert np.array_equal(H.cycle32(b.astype(np.float32), None, 1), x32)
+
+
+def test_approximate_error_fp32_cycles(oracle):
+    """Alg. 2 with FP32 preconditioning cycles: one PCG step with the FP32
+    W-cycle is the step-length-scaled widened W-cycle; with more steps the
+    result agrees with the FP64-cycle one to single-precision accuracy."""
+    g = I.grid2d(20, 20, weight_seed=4)
+    n = g[0]
+    A = dense_laplacian(g)
+    r = I.zero_mean_normal_rhs(8, n)
+    H1 = oracle.Hierarchy(g, None)
+    w1 = H1.cycle32(r.astype(np.float32), None, 2).astype(np.float64)
+    w1 -= w1.mean()
+    alpha = (r @ w1) / (w1 @ A @ w1)
+    e_one = oracle.approximate_error([H1], r, iterW=1, cycle_prec=1)
+    assert np.allclose(e_one, alpha * w1 - (alpha * w1).mean(), rtol=0, atol=1e-12 * np.abs(e_one).max())
+    H2 = oracle.Hierarchy(g, None, seed=77)
+    H3 = oracle.Hierarchy(g, None, seed=78)
+    es = np.linalg.lstsq(A, r, rcond=None)[0]
+    errA = lambda e: np.sqrt((e - es) @ A @ (e - es)) / np.sqrt(es @ A @ es)
+    for hs in ([H1], [H1, H2, H3]):
+        e64 = oracle.approximate_error(hs, r)
+        e32 = oracle.approximate_error(hs, r, cycle_prec=1)
+        # a perturbed preconditioner: PCG amplifies the rounding over its
+        # steps, but the approximation quality is the same
+        assert 0 < np.linalg.norm(e32 - e64) <= 1e-3 * np.linalg.norm(e64)
+        assert errA(e32) <= 1.01 * errA(e64) + 1e-6
 
 
 def test_approximate_error_alg2(oracle):
