@@ -43,33 +43,39 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(g, b, st_gpu, side):
+def cpu_baseline(g, b, st_gpu, side, numW):
     """Oracle (single-threaded CPU) on a bounded sample of the same workload:
-    one hierarchy build and two FP32 and one FP64 V-cycles on the full problem,
-    extrapolated with the solve's own build and cycle counts."""
+    one hierarchy build, FP32 V-cycles (and an FP32 W-cycle / FP64 V-cycle when
+    the solve used them) on the full problem, extrapolated with the solve's own
+    build and cycle counts."""
     import numpy as np
 
     import oracle
 
     t0 = time.perf_counter()
-    H = oracle.Hierarchy(g, None, theta=0.5, outer=1, cycle_prec=1)
+    H = oracle.Hierarchy(g, None, theta=0.5, outer=1, cycle_prec=1, numW=numW)
     t_build = time.perf_counter() - t0
     b32 = b.astype(np.float32)
     t0 = time.perf_counter()
     for _ in range(2):
-        H.vcycle32(b32)
+        H.cycle32(b32, None, 1)
     t_v32 = (time.perf_counter() - t0) / 2
-    t0 = time.perf_counter()
-    H.vcycle(b)
-    t_v64 = time.perf_counter() - t0
+    t_w32 = t_v64 = 0.0
+    if st_gpu["wcycles"]:
+        t0 = time.perf_counter()
+        H.cycle32(b32, None, 2)
+        t_w32 = time.perf_counter() - t0
+    if st_gpu["vcycles64"]:
+        t0 = time.perf_counter()
+        H.cycle(b, None, 1)
+        t_v64 = time.perf_counter() - t0
     builds = 1 + st_gpu["rebuilds"]
-    est = (t_build * builds + t_v32 * st_gpu["vcycles32"] + t_v64 * st_gpu["vcycles64"]
-           + 2.0 * t_v64 * st_gpu["wcycles"])
-    return {"value": est, "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle on the full {side}^3 problem: 1 hierarchy build ({t_build:.1f} s), 2 FP32 V-cycles "
-                       f"({t_v32:.2f} s each), 1 FP64 V-cycle ({t_v64:.2f} s); extrapolated with the GPU solve's "
-                       f"{builds} builds, {st_gpu['vcycles32']} FP32 / {st_gpu['vcycles64']} FP64 V-cycles and "
-                       f"{st_gpu['wcycles']} W-cycles (W counted as 2 V)")}
+    est = t_build * builds + t_v32 * st_gpu["vcycles32"] + t_v64 * st_gpu["vcycles64"] + t_w32 * st_gpu["wcycles"]
+    return {"value": round(est, 3), "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle on the full {side}^3 problem: 1 hierarchy build ({t_build:.2f} s), FP32 V-cycle "
+                       f"{t_v32:.3f} s, FP32 W-cycle {t_w32:.3f} s, FP64 V-cycle {t_v64:.3f} s (timed once each); "
+                       f"extrapolated with the GPU solve's {builds} builds, {st_gpu['vcycles32']} FP32 V-, "
+                       f"{st_gpu['wcycles']} FP32 W- and {st_gpu['vcycles64']} FP64 V-cycles")}
 
 
 def main():
@@ -162,7 +168,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
-        cpu = cpu_baseline(g, b, st, side)
+        cpu = cpu_baseline(g, b, st, side, args.numW)
 
     out = {
         "metric": "time to 1e-8 rel. residual",
@@ -190,6 +196,8 @@ def main():
         "setup_ms": round(st["t_setup_ms"], 2),
         "solve_ms": round(st["t_solve_ms"], 2),
         "rebuild_ms": round(st["t_rebuild_ms"], 2),
+        "approx_ms": round(st["t_approx_ms"], 2),
+        "build_ms": round(st["t_build_ms"], 2),
         "cycles": {"v32": st["vcycles32"], "v64": st["vcycles64"], "w": st["wcycles"]},
         "smoother_gbps": round(r32["gbs"], 1),
         "fp64_vcycle_variant": fp64,

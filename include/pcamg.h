@@ -69,7 +69,8 @@ typedef struct {
   double theta;            /* re-setup threshold on the mean ConvR since the last re-setup (Alg. 5; 0.4) */
   int32_t max_iter;        /* 2500 (Sec. 4: "--" beyond 2500 iterations) */
   int32_t outer;           /* PCAMG_OUTER_VCYCLE (Alg. 5) or PCAMG_OUTER_FCG (V-cycle preconditioned FCG) */
-  int32_t cycle_prec;      /* FCG preconditioner precision: PCAMG_PREC_F64 or PCAMG_PREC_F32 */
+  int32_t cycle_prec;      /* precision of every preconditioning cycle (outer FCG and Alg. 2's PCG):
+                              PCAMG_PREC_F64 or PCAMG_PREC_F32 */
   int32_t coarse_max;      /* coarsest level size (64) */
   int32_t relax_sweeps;    /* symmetric GS sweeps on A e = 0 before each build (3) */
   int32_t rebuild_vcycles; /* V-cycles on A e = 0 (PCAMG_REBUILD_RELAX only; 2) */
@@ -83,6 +84,11 @@ typedef struct {
   int32_t rebuild_rule;    /* 0 mean ConvR since last re-setup (Alg. 5), 1 last ConvR (Alg. 6) */
   int32_t keep_setup;      /* 1 = keep per-level setup arrays for pcamg_level_get */
   int32_t validate;        /* 1 = check the graph (symmetry, weights, connectivity) in pcamg_setup */
+  int32_t tail_max_n;      /* levels with at most this many vertices run as one single-workgroup
+                              launch per cycle (6144; 0 = per-step launches everywhere) */
+  int32_t use_graphs;      /* 1 = replay whole cycles from captured HIP graphs */
+  int32_t row_lanes;       /* lanes per matrix row in the smoother/residual kernels: 0 = by the
+                              level's mean row length, else 1, 4, 16 or 64 (results identical) */
   uint64_t seed;           /* start-vector stream */
   uint64_t colour_seed;    /* colouring priority stream */
 } pcamg_params;
@@ -97,6 +103,8 @@ typedef struct {
   double t_setup_ms;       /* first hierarchy (pcamg_setup) */
   double t_solve_ms;       /* whole pcamg_solve call */
   double t_rebuild_ms;     /* re-setups inside the solve (Alg. 2 + Alg. 4) */
+  double t_approx_ms;      /* of which error approximation (Alg. 2) */
+  double t_build_ms;       /* of which hierarchy builds (Alg. 4) */
   int32_t vcycles64, vcycles32, wcycles; /* cycle applications by kind */
   int32_t hist_len;        /* entries written to relres_hist */
   double* relres_hist;     /* host, optional: relres after each iteration (index 0 = 1.0) */
@@ -168,14 +176,15 @@ pcamg_status pcamg_level_get(pcamg_ctx* c, int32_t h, int32_t level, const char*
  * the finest level, natural order, device [n] vectors, in FP64. */
 pcamg_status pcamg_cycle(pcamg_ctx* c, int32_t h, const double* b, double* x, int32_t gamma);
 
-/* The V(1,1)-cycle in FP32 on FP32 copies of the operators (coarsest solve in
+/* The same cycle in FP32 on FP32 copies of the operators (coarsest solve in
  * FP64), device [n] float vectors. */
-pcamg_status pcamg_cycle32(pcamg_ctx* c, int32_t h, const float* b, float* x);
+pcamg_status pcamg_cycle32(pcamg_ctx* c, int32_t h, const float* b, float* x, int32_t gamma);
 
 /* Error approximation (Alg. 2) with hierarchies 0..count-1 as the history
  * (Re = count): PCG steps on A e = r from e = 0, W-cycle preconditioner of the
- * latest while Re <= numW, else the symmetric composite of all V-cycles;
- * result made orthogonal to 1.  r, e: device [n] natural order. */
+ * latest while Re <= numW, else the symmetric composite of all V-cycles
+ * (cycles in the precision cycle_prec); result made orthogonal to 1.  r, e:
+ * device [n] natural order. */
 pcamg_status pcamg_approx_error(pcamg_ctx* c, int32_t count, const double* r, double* e);
 
 /* Time `sweeps` symmetric multicoloured Gauss-Seidel sweeps (the smoother of

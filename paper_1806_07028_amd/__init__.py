@@ -146,10 +146,10 @@ class Solver:
         _lib.check(lib().pcamg_cycle(self.h, self._h(h), _ptr(b), _ptr(x), gamma))
         return x
 
-    def cycle32(self, b, x=None, h: int = -1) -> torch.Tensor:
+    def cycle32(self, b, x=None, gamma: int = 1, h: int = -1) -> torch.Tensor:
         b = _dev(b, torch.float32)
         x = torch.zeros_like(b) if x is None else _dev(x, torch.float32).clone()
-        _lib.check(lib().pcamg_cycle32(self.h, self._h(h), _ptr(b), _ptr(x)))
+        _lib.check(lib().pcamg_cycle32(self.h, self._h(h), _ptr(b), _ptr(x), gamma))
         return x
 
     def approx_error(self, r, count: int | None = None) -> torch.Tensor:

@@ -44,6 +44,9 @@ class Params(C.Structure):
         ("rebuild_rule", _i32),
         ("keep_setup", _i32),
         ("validate", _i32),
+        ("tail_max_n", _i32),
+        ("use_graphs", _i32),
+        ("row_lanes", _i32),
         ("seed", _u64),
         ("colour_seed", _u64),
     ]
@@ -63,6 +66,8 @@ class Stats(C.Structure):
         ("t_setup_ms", C.c_double),
         ("t_solve_ms", C.c_double),
         ("t_rebuild_ms", C.c_double),
+        ("t_approx_ms", C.c_double),
+        ("t_build_ms", C.c_double),
         ("vcycles64", _i32),
         ("vcycles32", _i32),
         ("wcycles", _i32),
@@ -101,7 +106,7 @@ _SIGS = {
     "pcamg_level_info": ([_p, _i32, _i32, C.POINTER(_i64)], _i32),
     "pcamg_level_get": ([_p, _i32, _i32, C.c_char_p, _p], _i32),
     "pcamg_cycle": ([_p, _i32, _p, _p, _i32], _i32),
-    "pcamg_cycle32": ([_p, _i32, _p, _p], _i32),
+    "pcamg_cycle32": ([_p, _i32, _p, _p, _i32], _i32),
     "pcamg_approx_error": ([_p, _i32, _p, _p], _i32),
     "pcamg_initial_error": ([_p, _p], _i32),
     "pcamg_bench_smoother": ([_p, _i32, _i32, C.POINTER(C.c_double), C.POINTER(_i64), C.POINTER(C.c_double)], _i32),

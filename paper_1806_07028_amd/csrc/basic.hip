@@ -4,6 +4,7 @@
 #include <algorithm>
 
 #include "internal.hpp"
+#include "rowchain.hpp"
 
 namespace pcamg {
 
@@ -48,41 +49,59 @@ void laplacian(int32_t n, const int32_t* rp, const double* w, double* aval, doub
 // none of them has.  This equals sequential first-fit in descending
 // (priority, id) order.
 // ---------------------------------------------------------------------------
-__global__ void jp_round_kernel(int32_t nw, const int32_t* __restrict__ work, const int32_t* __restrict__ rp,
-                                const int32_t* __restrict__ ci, uint64_t seed, uint64_t lvl,
-                                int32_t* __restrict__ colour, uint8_t* __restrict__ still) {
-  int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nw) return;
-  const int32_t v = work[t];
-  const uint64_t pv = sm64_word(seed, lvl + (uint64_t)v + 1ull);
+// Priorities of the colouring order: word (level << 32) + v + 1 of the stream.
+__global__ void jp_prio_kernel(int32_t n, uint64_t seed, uint64_t lvl, uint64_t* __restrict__ prio) {
+  const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) prio[v] = sm64_word(seed, lvl + (uint64_t)v + 1ull);
+}
+
+// Colour v if all its higher-priority neighbours are coloured; returns true if
+// v is still uncoloured afterwards.  Reading a neighbour coloured in the same
+// round is harmless either way: its colour is final once written.  Neighbours
+// are examined in batches of eight with independent loads.
+__device__ bool jp_try(int32_t v, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                       const uint64_t* __restrict__ prio, int32_t* colour) {
+  constexpr int U = 8;
+  const uint64_t pv = prio[v];
+  const int32_t k0 = rp[v], k1 = rp[v + 1];
   unsigned long long used = 0ull;
   bool big = false;
-  for (int32_t k = rp[v]; k < rp[v + 1]; ++k) {
-    int32_t u = ci[k];
-    uint64_t pu = sm64_word(seed, lvl + (uint64_t)u + 1ull);
-    if (pu > pv || (pu == pv && u > v)) {
-      int32_t cu = __atomic_load_n(&colour[u], __ATOMIC_RELAXED);
-      if (cu < 0) {
-        still[t] = 1;
-        return;
+  for (int32_t k = k0; k < k1; k += U) {
+    int32_t u[U];
+    uint64_t pu[U];
+    int32_t cu[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) u[j] = k + j < k1 ? ci[k + j] : v;
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      pu[j] = prio[u[j]];
+      cu[j] = __atomic_load_n(&colour[u[j]], __ATOMIC_RELAXED);
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      if (u[j] == v) continue;  // padding (no self loops in the pattern)
+      if (pu[j] > pv || (pu[j] == pv && u[j] > v)) {
+        if (cu[j] < 0) return true;
+        if (cu[j] < 64) used |= 1ull << cu[j];
+        else big = true;
       }
-      if (cu < 64) used |= 1ull << cu;
-      else big = true;
     }
   }
   int32_t c;
   if (~used != 0ull && !big) {
     c = __ffsll((long long)~used) - 1;
-  } else {
-    // more than 64 colours around: search the smallest free colour directly
+  } else {  // more than 64 colours around: search the smallest free colour directly
     c = 0;
     for (;;) {
       bool taken = c < 64 ? ((used >> c) & 1ull) : false;
       if (!taken && c >= 64) {
-        for (int32_t k = rp[v]; k < rp[v + 1]; ++k) {
-          int32_t u = ci[k];
-          uint64_t pu = sm64_word(seed, lvl + (uint64_t)u + 1ull);
-          if ((pu > pv || (pu == pv && u > v)) && colour[u] == c) { taken = true; break; }
+        for (int32_t k = k0; k < k1; ++k) {
+          const int32_t w = ci[k];
+          const uint64_t pw = prio[w];
+          if ((pw > pv || (pw == pv && w > v)) && __atomic_load_n(&colour[w], __ATOMIC_RELAXED) == c) {
+            taken = true;
+            break;
+          }
         }
       }
       if (!taken) break;
@@ -90,7 +109,67 @@ __global__ void jp_round_kernel(int32_t nw, const int32_t* __restrict__ work, co
     }
   }
   __atomic_store_n(&colour[v], c, __ATOMIC_RELAXED);
-  still[t] = 0;
+  return false;
+}
+
+// all rounds in one workgroup (small graphs)
+constexpr int JP_SMALL_THREADS = 1024;
+constexpr int32_t JP_SMALL_MAX = 4096;
+__global__ void __launch_bounds__(JP_SMALL_THREADS)
+    jp_small_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                    const uint64_t* __restrict__ prio, int32_t* colour, int32_t* __restrict__ rounds_out) {
+  __shared__ int32_t remaining;
+  int32_t rounds = 0;
+  for (;;) {
+    if (threadIdx.x == 0) remaining = 0;
+    __syncthreads();
+    int32_t mine = 0;
+    for (int32_t v = threadIdx.x; v < n; v += JP_SMALL_THREADS)
+      if (colour[v] < 0 && jp_try(v, rp, ci, prio, colour)) ++mine;
+    if (mine) atomicAdd(&remaining, mine);
+    __syncthreads();
+    const int32_t r = remaining;
+    ++rounds;
+    __syncthreads();
+    if (r == 0 || rounds > n + 1) break;
+  }
+  if (threadIdx.x == 0) *rounds_out = rounds;
+}
+
+// One round over a worklist of uncoloured vertices; the ones still uncoloured
+// go to the next list (in any order: the colouring does not depend on it).
+__global__ void __launch_bounds__(256)
+    jp_list_kernel(const int32_t* __restrict__ cnt_in, const int32_t* __restrict__ in, int32_t* __restrict__ cnt_out,
+                   int32_t* __restrict__ out, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                   const uint64_t* __restrict__ prio, int32_t* colour) {
+  const int32_t m = *cnt_in;
+  const int32_t stride = gridDim.x * blockDim.x;
+  for (int32_t base = blockIdx.x * blockDim.x; base < m; base += stride) {
+    const int32_t t = base + threadIdx.x;
+    const int32_t v = t < m ? in[t] : -1;
+    const bool left = v >= 0 && jp_try(v, rp, ci, prio, colour);
+    const unsigned long long bal = __ballot(left);
+    if (!bal) continue;
+    const int lane = threadIdx.x & 63;
+    int32_t at = 0;
+    if (lane == __ffsll((long long)bal) - 1) at = atomicAdd(cnt_out, __popcll(bal));
+    at = __shfl(at, __ffsll((long long)bal) - 1, 64);
+    if (left) out[at + __popcll(bal & ((1ull << lane) - 1ull))] = v;
+  }
+}
+
+// counts of the next batch: cnt[0] = cnt[last], the others zero
+__global__ void jp_carry_kernel(int32_t* cnt, int32_t last) {
+  const int32_t c = cnt[last];
+  __syncthreads();
+  for (int32_t i = threadIdx.x; i <= last; i += blockDim.x) cnt[i] = i == 0 ? c : 0;
+}
+
+__global__ void min_i32_kernel(const int32_t* a, int32_t n, int32_t* out) {
+  int32_t m = INT32_MAX;
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) m = min(m, a[i]);
+  for (int o = 32; o > 0; o >>= 1) m = min(m, __shfl_down(m, o, 64));
+  if ((threadIdx.x & 63) == 0) atomicMin(out, m);
 }
 
 __global__ void max_i32_kernel(const int32_t* a, int32_t n, int32_t* out) {
@@ -104,50 +183,97 @@ int32_t colour_jp(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed
                   hipStream_t s) {
   if (n <= 0) return 0;
   fill_i32(colour, -1, n, s);
-  DVec<int32_t> wa(n), wb(n), cnt(1);
-  DVec<uint8_t> still(n);
-  iota_i32(wa.p, n, s);
-  int32_t nw = n;
   const uint64_t lvl = (uint64_t)(uint32_t)level << 32;
-  int rounds = 0;
-  while (nw > 0) {
-    jp_round_kernel<<<grid_for(nw, 256), 256, 0, s>>>(nw, wa.p, rp, ci, seed, lvl, colour, still.p);
+  DVec<uint64_t> prio(n);
+  jp_prio_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, seed, lvl, prio.p);
+  PCAMG_LAUNCHED();
+  if (n <= JP_SMALL_MAX) {
+    DVec<int32_t> rounds(1);
+    jp_small_kernel<<<1, JP_SMALL_THREADS, 0, s>>>(n, rp, ci, prio.p, colour, rounds.p);
     PCAMG_LAUNCHED();
-    compact_i32(wa.p, still.p, wb.p, cnt.p, nw, s);
-    nw = read_scalar(cnt.p, s);
-    std::swap(wa, wb);
-    require(++rounds <= n + 1, PCAMG_EHIP, "colouring did not terminate");
+  } else {
+    // batches of R rounds over shrinking worklists; the host checks the count
+    // after each batch (every round removes at least the highest-priority
+    // uncoloured vertex, so at most n rounds)
+    constexpr int R = 8;
+    DVec<int32_t> list0(n), list1(n), cnt(R + 1);
+    iota_i32(list0.p, n, s);
+    fill_i32(cnt.p, 0, R + 1, s);
+    fill_i32(cnt.p, n, 1, s);
+    const unsigned grid = std::min<unsigned>(grid_for(n, 256), 2048);
+    int64_t rounds = 0;
+    for (;;) {
+      for (int r = 0; r < R; ++r) {
+        const int32_t* in = (r & 1) ? list1.p : list0.p;
+        int32_t* out = (r & 1) ? list0.p : list1.p;
+        jp_list_kernel<<<grid, 256, 0, s>>>(cnt.p + r, in, cnt.p + r + 1, out, rp, ci, prio.p, colour);
+        PCAMG_LAUNCHED();
+      }
+      rounds += R;
+      if (read_scalar(cnt.p + R, s) == 0) break;
+      require(rounds <= (int64_t)n + R, PCAMG_EHIP, "colouring made no progress");
+      // R is even: the survivors are in list0 again
+      jp_carry_kernel<<<1, 64, 0, s>>>(cnt.p, R);
+      PCAMG_LAUNCHED();
+    }
   }
   DVec<int32_t> mx(1);
   fill_i32(mx.p, -1, 1, s);
   max_i32_kernel<<<std::min<unsigned>(grid_for(n, 256), 1024), 256, 0, s>>>(colour, n, mx.p);
   PCAMG_LAUNCHED();
-  return read_scalar(mx.p, s) + 1;
+  const int32_t nc = read_scalar(mx.p, s) + 1;
+  // every vertex must be coloured: the smallest colour is then 0, and -1 never appears
+  DVec<int32_t> mn(1);
+  fill_i32(mn.p, 1, 1, s);
+  min_i32_kernel<<<std::min<unsigned>(grid_for(n, 256), 1024), 256, 0, s>>>(colour, n, mn.p);
+  PCAMG_LAUNCHED();
+  require(read_scalar(mn.p, s) >= 0, PCAMG_EHIP, "colouring left a vertex uncoloured");
+  return nc;
 }
 
 // ---------------------------------------------------------------------------
 // Gauss-Seidel pass over the rows of one colour (rows row0..row1-1 of a
 // colour-sorted matrix): s = sum_j a_ij x_j as an fma chain in CSR order,
-// x_i = (b_i - s) * dinv_i.  Rows of one colour are independent.
+// x_i = (b_i - s) * dinv_i.  Rows of one colour are independent.  G lanes per
+// row (G = 1: one thread per row); the row sums come from rowchain.hpp.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void gs_kernel(int32_t row0, int32_t row1, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                          const T* __restrict__ av, const T* __restrict__ dinv, const T* __restrict__ b,
-                          T* __restrict__ x) {
-  int32_t i = row0 + (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (i >= row1) return;
-  T s = 0;
-  const int32_t k1 = rp[i + 1];
-  for (int32_t k = rp[i]; k < k1; ++k) s = fma(av[k], x[ci[k]], s);
-  x[i] = (b[i] - s) * dinv[i];
+template <typename T, int G>
+__global__ void __launch_bounds__(256)
+    gs_kernel(int32_t row0, int32_t row1, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+              const T* __restrict__ av, const T* __restrict__ dinv, const T* __restrict__ b, T* __restrict__ x) {
+  const int32_t i = row0 + (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) / G);
+  if constexpr (G == 1) {
+    if (i >= row1) return;
+    const T s = row_chain1<T>(rp[i], rp[i + 1], ci, av, x, (T)0);
+    x[i] = (b[i] - s) * dinv[i];
+  } else {
+    const bool ok = i < row1;
+    const int32_t k0 = ok ? rp[i] : 0;
+    const int32_t len = ok ? rp[i + 1] - k0 : 0;
+    const T s = row_chain_g<T, G>(k0, len, ci, av, x, (T)0);
+    if (ok && (threadIdx.x & (G - 1)) == 0) x[i] = (b[i] - s) * dinv[i];
+  }
+}
+
+// rows per launch of lanes-per-row G: the grid covers (row1 - row0) * G threads
+template <typename T, int G>
+void gs_launch(int32_t row0, int32_t row1, const int32_t* rp, const int32_t* ci, const T* av, const T* dinv,
+               const T* b, T* x, hipStream_t s) {
+  gs_kernel<T, G><<<grid_for((size_t)(row1 - row0) * G, 256), 256, 0, s>>>(row0, row1, rp, ci, av, dinv, b, x);
+  PCAMG_LAUNCHED();
 }
 
 template <typename T>
 void gs_colour(int32_t row0, int32_t row1, const int32_t* rp, const int32_t* ci, const T* av, const T* dinv,
-               const T* b, T* x, hipStream_t s) {
+               const T* b, T* x, hipStream_t s, int lanes) {
   if (row1 <= row0) return;
-  gs_kernel<T><<<grid_for(row1 - row0, 256), 256, 0, s>>>(row0, row1, rp, ci, av, dinv, b, x);
-  PCAMG_LAUNCHED();
+  switch (lanes) {
+    case 1: gs_launch<T, 1>(row0, row1, rp, ci, av, dinv, b, x, s); break;
+    case 4: gs_launch<T, 4>(row0, row1, rp, ci, av, dinv, b, x, s); break;
+    case 16: gs_launch<T, 16>(row0, row1, rp, ci, av, dinv, b, x, s); break;
+    case 64: gs_launch<T, 64>(row0, row1, rp, ci, av, dinv, b, x, s); break;
+    default: throw Error(PCAMG_EINVAL, "lanes per row must be 1, 4, 16 or 64");
+  }
 }
 
 // Same over an explicit row list (natural-order stage entry point).
@@ -158,8 +284,7 @@ __global__ void gs_rows_kernel(int32_t nrows, const int32_t* __restrict__ rows, 
   int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nrows) return;
   int32_t i = rows[t];
-  T s = 0;
-  for (int32_t k = rp[i]; k < rp[i + 1]; ++k) s = fma(av[k], x[ci[k]], s);
+  const T s = row_chain1<T>(rp[i], rp[i + 1], ci, av, x, (T)0);
   x[i] = (b[i] - s) * dinv[i];
 }
 
@@ -171,45 +296,51 @@ void gs_colour_rows(int32_t nrows, const int32_t* rows, const int32_t* rp, const
   PCAMG_LAUNCHED();
 }
 
-// r = b - A x with s = d_i x_i, then the off-diagonal fma chain.
-template <typename T>
-__global__ void residual_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                const T* __restrict__ av, const T* __restrict__ d, const T* __restrict__ b,
-                                const T* __restrict__ x, T* __restrict__ r) {
-  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  T s = d[i] * x[i];
-  const int32_t k1 = rp[i + 1];
-  for (int32_t k = rp[i]; k < k1; ++k) s = fma(av[k], x[ci[k]], s);
-  r[i] = b[i] - s;
+// y = A x (off-diagonal entries in CSR order after s = d_i x_i); with b, the
+// residual r = b - A x.
+template <typename T, int G>
+__global__ void __launch_bounds__(256)
+    residual_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                    const T* __restrict__ av, const T* __restrict__ d, const T* __restrict__ b,
+                    const T* __restrict__ x, T* __restrict__ r) {
+  const int32_t i = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) / G);
+  if constexpr (G == 1) {
+    if (i >= n) return;
+    const T s = row_chain1<T>(rp[i], rp[i + 1], ci, av, x, d[i] * x[i]);
+    r[i] = b ? b[i] - s : s;
+  } else {
+    const bool ok = i < n;
+    const int32_t k0 = ok ? rp[i] : 0;
+    const int32_t len = ok ? rp[i + 1] - k0 : 0;
+    const T s = row_chain_g<T, G>(k0, len, ci, av, x, ok ? d[i] * x[i] : (T)0);
+    if (ok && (threadIdx.x & (G - 1)) == 0) r[i] = b ? b[i] - s : s;
+  }
+}
+
+template <typename T, int G>
+void residual_launch(int32_t n, const int32_t* rp, const int32_t* ci, const T* av, const T* d, const T* b,
+                     const T* x, T* r, hipStream_t s) {
+  residual_kernel<T, G><<<grid_for((size_t)n * G, 256), 256, 0, s>>>(n, rp, ci, av, d, b, x, r);
+  PCAMG_LAUNCHED();
 }
 
 template <typename T>
 void residual(int32_t n, const int32_t* rp, const int32_t* ci, const T* av, const T* d, const T* b, const T* x,
-              T* r, hipStream_t s) {
+              T* r, hipStream_t s, int lanes) {
   if (n <= 0) return;
-  residual_kernel<T><<<grid_for(n, 256), 256, 0, s>>>(n, rp, ci, av, d, b, x, r);
-  PCAMG_LAUNCHED();
-}
-
-template <typename T>
-__global__ void spmv_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                            const T* __restrict__ av, const T* __restrict__ d, const T* __restrict__ x,
-                            T* __restrict__ y) {
-  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  T s = d[i] * x[i];
-  const int32_t k1 = rp[i + 1];
-  for (int32_t k = rp[i]; k < k1; ++k) s = fma(av[k], x[ci[k]], s);
-  y[i] = s;
+  switch (lanes) {
+    case 1: residual_launch<T, 1>(n, rp, ci, av, d, b, x, r, s); break;
+    case 4: residual_launch<T, 4>(n, rp, ci, av, d, b, x, r, s); break;
+    case 16: residual_launch<T, 16>(n, rp, ci, av, d, b, x, r, s); break;
+    case 64: residual_launch<T, 64>(n, rp, ci, av, d, b, x, r, s); break;
+    default: throw Error(PCAMG_EINVAL, "lanes per row must be 1, 4, 16 or 64");
+  }
 }
 
 template <typename T>
 void spmv(int32_t n, const int32_t* rp, const int32_t* ci, const T* av, const T* d, const T* x, T* y,
-          hipStream_t s) {
-  if (n <= 0) return;
-  spmv_kernel<T><<<grid_for(n, 256), 256, 0, s>>>(n, rp, ci, av, d, x, y);
-  PCAMG_LAUNCHED();
+          hipStream_t s, int lanes) {
+  residual<T>(n, rp, ci, av, d, nullptr, x, y, s, lanes);
 }
 
 // Restriction b_c = P^T r: fma chain over the members of each aggregate in
@@ -253,12 +384,13 @@ void prolong_add(int32_t n, const int32_t* agg, const T* pval, const T* xc, T* x
 
 #define INSTANTIATE(T)                                                                                          \
   template void gs_colour<T>(int32_t, int32_t, const int32_t*, const int32_t*, const T*, const T*, const T*,   \
-                             T*, hipStream_t);                                                                  \
+                             T*, hipStream_t, int);                                                             \
   template void gs_colour_rows<T>(int32_t, const int32_t*, const int32_t*, const int32_t*, const T*, const T*, \
                                   const T*, T*, hipStream_t);                                                   \
   template void residual<T>(int32_t, const int32_t*, const int32_t*, const T*, const T*, const T*, const T*,   \
-                            T*, hipStream_t);                                                                   \
-  template void spmv<T>(int32_t, const int32_t*, const int32_t*, const T*, const T*, const T*, T*, hipStream_t); \
+                            T*, hipStream_t, int);                                                              \
+  template void spmv<T>(int32_t, const int32_t*, const int32_t*, const T*, const T*, const T*, T*, hipStream_t, \
+                        int);                                                                                   \
   template void restrict_members<T>(int32_t, const int32_t*, const int32_t*, const T*, const T*, T*,          \
                                     hipStream_t);                                                               \
   template void prolong_add<T>(int32_t, const int32_t*, const T*, const T*, T*, hipStream_t);

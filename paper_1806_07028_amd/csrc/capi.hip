@@ -202,6 +202,9 @@ pcamg_status pcamg_params_default(pcamg_params* p) {
   p->rebuild_rule = 0;
   p->keep_setup = 0;
   p->validate = 1;
+  p->tail_max_n = 6144;
+  p->use_graphs = 1;
+  p->row_lanes = 0;
   p->seed = 0x5EED;
   p->colour_seed = 0xC010;
   return PCAMG_OK;
@@ -212,6 +215,9 @@ pcamg_status pcamg_setup(const pcamg_graph* g, const double* rhs, const pcamg_pa
   return guarded([&] {
     require(g && p && out, PCAMG_EINVAL, "null argument");
     *out = nullptr;
+    require(p->row_lanes == 0 || p->row_lanes == 1 || p->row_lanes == 4 || p->row_lanes == 16 ||
+                p->row_lanes == 64,
+            PCAMG_EINVAL, "row_lanes must be 0, 1, 4, 16 or 64");
     hipStream_t s = as_stream(stream);
     if (p->validate) validate_graph(g, s);
     require(g->n >= 1, PCAMG_EINVAL, "empty graph");
@@ -338,21 +344,21 @@ pcamg_status pcamg_cycle(pcamg_ctx* c, int32_t h, const double* b, double* x, in
     DVec<double> bp(n), xp(n);
     gather_f64(b, c->M0->perm.p, bp.p, n, c->s);
     gather_f64(x, c->M0->perm.p, xp.p, n, c->s);
-    cycle64(c, H, 0, bp.p, xp.p, gamma);
+    run_cycle64(c, H, bp.p, xp.p, gamma);
     scatter_f64(xp.p, c->M0->perm.p, x, n, c->s);
     PCAMG_HIP(hipStreamSynchronize(c->s));
   });
 }
 
-pcamg_status pcamg_cycle32(pcamg_ctx* c, int32_t h, const float* b, float* x) {
+pcamg_status pcamg_cycle32(pcamg_ctx* c, int32_t h, const float* b, float* x, int32_t gamma) {
   return guarded([&] {
     Hierarchy& H = hier(c, h);
-    require(b && x, PCAMG_EINVAL, "bad argument");
+    require(b && x && gamma >= 1 && gamma <= 2, PCAMG_EINVAL, "bad argument");
     const int32_t n = c->n;
     DVec<float> bp(n), xp(n);
     gather_f32(b, c->M0->perm.p, bp.p, n, c->s);
     gather_f32(x, c->M0->perm.p, xp.p, n, c->s);
-    cycle32(c, H, 0, bp.p, xp.p);
+    run_cycle32(c, H, bp.p, xp.p, gamma);
     scatter_f32(xp.p, c->M0->perm.p, x, n, c->s);
     PCAMG_HIP(hipStreamSynchronize(c->s));
   });
@@ -364,7 +370,7 @@ pcamg_status pcamg_approx_error(pcamg_ctx* c, int32_t count, const double* r, do
     const int32_t n = c->n;
     DVec<double> rp(n), ep(n);
     gather_f64(r, c->M0->perm.p, rp.p, n, c->s);
-    approx_error(c, count, rp.p, ep.p, nullptr, nullptr);
+    approx_error(c, count, rp.p, ep.p, nullptr, nullptr, nullptr);
     scatter_f64(ep.p, c->M0->perm.p, e, n, c->s);
     PCAMG_HIP(hipStreamSynchronize(c->s));
   });

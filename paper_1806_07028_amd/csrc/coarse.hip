@@ -9,7 +9,7 @@
 namespace pcamg {
 
 constexpr int LDLT_THREADS = 256;
-constexpr int LDLT_LDS_MAX = 4096;
+constexpr int LDLT_LDS_MAX = 4096;  // equals LDLT_MAX of the tail kernel
 
 __global__ void dense_zero_kernel(double* A, size_t nn) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;

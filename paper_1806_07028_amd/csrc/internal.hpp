@@ -168,16 +168,16 @@ int32_t colour_jp(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed
 
 template <typename T>
 void gs_colour(int32_t row0, int32_t row1, const int32_t* rp, const int32_t* ci, const T* av, const T* dinv,
-               const T* b, T* x, hipStream_t s);
+               const T* b, T* x, hipStream_t s, int lanes = 1);  // lanes per row: 1, 4, 16, 64
 template <typename T>
 void gs_colour_rows(int32_t nrows, const int32_t* rows, const int32_t* rp, const int32_t* ci, const T* av,
                     const T* dinv, const T* b, T* x, hipStream_t s);
 template <typename T>
 void residual(int32_t n, const int32_t* rp, const int32_t* ci, const T* av, const T* d, const T* b, const T* x,
-              T* r, hipStream_t s);
+              T* r, hipStream_t s, int lanes = 1);
 template <typename T>
 void spmv(int32_t n, const int32_t* rp, const int32_t* ci, const T* av, const T* d, const T* x, T* y,
-          hipStream_t s);
+          hipStream_t s, int lanes = 1);
 template <typename T>
 void restrict_members(int32_t nc, const int32_t* moff, const int32_t* mem, const T* pval, const T* r, T* bc,
                       hipStream_t s);

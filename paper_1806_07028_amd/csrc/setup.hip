@@ -849,101 +849,137 @@ int32_t smooth_pval(int32_t n, const double* e_raw, int32_t nc, const int32_t* m
 }
 
 // ---------------------------------------------------------------------------
-// Galerkin product (Alg. 4, Step 8): one thread per coarse row I with a small
-// (column, sum) list in LDS.  Terms arrive in the defined order -- members k
-// of I ascending; for each k the diagonal term, then row k in CSR order -- and
-// each entry accumulates them in that order (fma(p_k a_kl, p_l, acc)).  The
-// reweighted graph is coarsened with boolean P, diagonal dropped, plain sums.
+// Galerkin product (Alg. 4, Step 8): one wavefront per coarse row I.  The
+// row's terms arrive in the defined order -- members k of I ascending; for
+// each k the diagonal term, then row k in CSR order -- and are gathered into
+// LDS with their sequence number t, bitonic-sorted by (column J, t), and each
+// run of equal J is summed by one lane in t order (fma(p_k a_kl, p_l, acc)).
+// The reweighted graph is coarsened with boolean P, diagonal dropped, plain
+// sums.  Rows with more than GAL_T terms take the long-row path.
 // ---------------------------------------------------------------------------
-constexpr int GAL_BLOCK = 32;
-constexpr int GAL_MAXJ = 160;
+constexpr int GAL_WAVES = 4;   // rows per block
+constexpr int GAL_T = 256;     // terms per row held in LDS
 
-__global__ void __launch_bounds__(GAL_BLOCK)
+__global__ void __launch_bounds__(64 * GAL_WAVES)
     galerkin_kernel(int32_t nc, const int32_t* __restrict__ moff, const int32_t* __restrict__ mem,
                     const int32_t* __restrict__ agg, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                     const double* __restrict__ av, const double* __restrict__ d, const double* __restrict__ pval,
                     bool graph_mode, const int32_t* __restrict__ rpc, int32_t* __restrict__ count,
                     int32_t* __restrict__ cic, double* __restrict__ vc, double* __restrict__ dc,
                     double* __restrict__ dinvc, uint8_t* __restrict__ overflow) {
-  __shared__ int32_t Js[GAL_BLOCK][GAL_MAXJ + 1];
-  __shared__ double As[GAL_BLOCK][GAL_MAXJ + 1];
-  const int t = threadIdx.x;
-  const int32_t I = blockIdx.x * GAL_BLOCK + t;
-  if (I >= nc) return;
-  int32_t* J = Js[t];
-  double* A = As[t];
-  int m = 0;
-  bool ovf = false;
+  __shared__ uint64_t K[GAL_WAVES][GAL_T];
+  __shared__ double TV[GAL_WAVES][GAL_T];
+  __shared__ double TP[GAL_WAVES][GAL_T];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int32_t I = blockIdx.x * GAL_WAVES + w;
+  if (I >= nc) return;  // whole wave leaves together
   const bool fill = rpc != nullptr;
-  for (int32_t q = moff[I]; q < moff[I + 1]; ++q) {
+  const int32_t q0 = moff[I], q1 = moff[I + 1];
+  // term count and per-member offsets (at most a handful of members)
+  int T = 0;
+  for (int32_t q = q0; q < q1; ++q) {
+    const int32_t k = mem[q];
+    T += (graph_mode ? 0 : 1) + rp[k + 1] - rp[k];
+  }
+  if (T > GAL_T) {
+    if (lane == 0) {
+      overflow[I] = 1;
+      if (!fill) count[I] = 0;
+    }
+    return;
+  }
+  uint64_t* Kw = K[w];
+  double* TVw = TV[w];
+  double* TPw = TP[w];
+  int base = 0;
+  for (int32_t q = q0; q < q1; ++q) {
     const int32_t k = mem[q];
     const double pk = pval ? pval[k] : 1.0;
     if (!graph_mode) {
-      // diagonal term first
-      int f = -1;
-      for (int s = 0; s < m; ++s)
-        if (J[s] == I) { f = s; break; }
-      if (f < 0) {
-        if (m == GAL_MAXJ) { ovf = true; break; }
-        f = m++;
-        J[f] = I;
-        A[f] = 0.0;
+      if (lane == 0) {
+        Kw[base] = ((uint64_t)(uint32_t)I << 32) | (uint32_t)base;
+        if (fill) {
+          TVw[base] = pk * d[k];
+          TPw[base] = pk;
+        }
       }
-      if (fill) A[f] = fma(pk * d[k], pk, A[f]);
+      ++base;
     }
-    for (int32_t e = rp[k]; e < rp[k + 1]; ++e) {
+    const int32_t e0 = rp[k], e1 = rp[k + 1];
+    for (int32_t e = e0 + lane; e < e1; e += 64) {
       const int32_t l = ci[e];
-      const int32_t Jc = agg[l];
-      if (graph_mode && Jc == I) continue;
-      int f = -1;
-      for (int s = 0; s < m; ++s)
-        if (J[s] == Jc) { f = s; break; }
-      if (f < 0) {
-        if (m == GAL_MAXJ) { ovf = true; break; }
-        f = m++;
-        J[f] = Jc;
-        A[f] = 0.0;
-      }
+      const int t = base + (e - e0);
+      Kw[t] = ((uint64_t)(uint32_t)agg[l] << 32) | (uint32_t)t;
       if (fill) {
-        if (graph_mode) A[f] = A[f] + av[e];
-        else A[f] = fma(pk * av[e], pval ? pval[l] : 1.0, A[f]);
+        if (graph_mode) {
+          TVw[t] = av[e];
+        } else {
+          TVw[t] = pk * av[e];
+          TPw[t] = pval ? pval[l] : 1.0;
+        }
       }
     }
-    if (ovf) break;
+    base += e1 - e0;
   }
-  if (ovf) {  // handled by the long-row path
-    overflow[I] = 1;
-    if (!fill) count[I] = 0;
-    return;
-  }
-  if (!fill) {
-    count[I] = graph_mode ? m : m - 1;
-    return;
-  }
-  // insertion sort by column
-  for (int a = 1; a < m; ++a) {
-    int32_t kj = J[a];
-    double ka = A[a];
-    int b = a - 1;
-    while (b >= 0 && J[b] > kj) {
-      J[b + 1] = J[b];
-      A[b + 1] = A[b];
-      --b;
+  int S = 1;
+  while (S < T) S <<= 1;
+  for (int t = T + lane; t < S; t += 64) Kw[t] = ~0ull;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  for (int k = 2; k <= S; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = lane; t < S; t += 64) {
+        const int ixj = t ^ j;
+        if (ixj > t) {
+          const uint64_t a = Kw[t], b = Kw[ixj];
+          const bool up = (t & k) == 0;
+          if ((a > b) == up) {
+            Kw[t] = b;
+            Kw[ixj] = a;
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
-    J[b + 1] = kj;
-    A[b + 1] = ka;
   }
-  int32_t o = rpc[I];
-  for (int a = 0; a < m; ++a) {
-    if (!graph_mode && J[a] == I) {
-      dc[I] = A[a];
-      dinvc[I] = 1.0 / A[a];
-      continue;
+  // runs of equal column: one lane sums each run in sequence order
+  int32_t written = 0;
+  const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  for (int p0 = 0; p0 < T; p0 += 64) {
+    const int p = p0 + lane;
+    bool start = false, counted = false;
+    int32_t J = -1;
+    double acc = 0.0;
+    if (p < T) {
+      const uint64_t kp = Kw[p];
+      J = (int32_t)(kp >> 32);
+      start = p == 0 || (Kw[p - 1] >> 32) != (kp >> 32);
+      counted = start && J != I;
+      if (start && fill) {
+        for (int u = p; u < T && (Kw[u] >> 32) == (kp >> 32); ++u) {
+          const int t = (int)(uint32_t)Kw[u];
+          acc = graph_mode ? acc + TVw[t] : fma(TVw[t], TPw[t], acc);
+        }
+      }
     }
-    cic[o] = J[a];
-    vc[o] = A[a];
-    ++o;
+    const unsigned long long m = __ballot(counted);
+    if (fill) {
+      if (start && J == I && !graph_mode) {
+        dc[I] = acc;
+        dinvc[I] = 1.0 / acc;
+      }
+      if (counted) {
+        const int32_t o = rpc[I] + written + __popcll(m & lt);
+        cic[o] = J;
+        vc[o] = acc;
+      }
+    }
+    written += __popcll(m);
   }
+  if (!fill && lane == 0) count[I] = written;
 }
 
 // Long coarse rows (more distinct columns than the LDS list holds): all terms
@@ -1084,9 +1120,9 @@ int64_t galerkin_count(int32_t n, const int32_t* rp, const int32_t* ci, int32_t 
   DVec<int32_t> cnt(nc);
   DVec<uint8_t> ovf(nc);
   PCAMG_HIP(hipMemsetAsync(ovf.p, 0, nc, s));
-  galerkin_kernel<<<grid_for(nc, GAL_BLOCK), GAL_BLOCK, 0, s>>>(nc, moff, mem, agg, rp, ci, nullptr, nullptr,
-                                                                 nullptr, graph_mode, nullptr, cnt.p, nullptr,
-                                                                 nullptr, nullptr, nullptr, ovf.p);
+  galerkin_kernel<<<grid_for(nc, GAL_WAVES), 64 * GAL_WAVES, 0, s>>>(nc, moff, mem, agg, rp, ci, nullptr, nullptr,
+                                                                      nullptr, graph_mode, nullptr, cnt.p, nullptr,
+                                                                      nullptr, nullptr, nullptr, ovf.p);
   PCAMG_LAUNCHED();
   galerkin_long_rows(nc, ovf.p, moff, mem, agg, rp, ci, nullptr, nullptr, nullptr, graph_mode, nullptr, cnt.p,
                      nullptr, nullptr, nullptr, nullptr, s);
@@ -1105,8 +1141,9 @@ void galerkin_fill(int32_t n, const int32_t* rp, const int32_t* ci, const double
   if (nc <= 0) return;
   DVec<uint8_t> ovf(nc);
   PCAMG_HIP(hipMemsetAsync(ovf.p, 0, nc, s));
-  galerkin_kernel<<<grid_for(nc, GAL_BLOCK), GAL_BLOCK, 0, s>>>(nc, moff, mem, agg, rp, ci, av, d, pval, graph_mode,
-                                                                 rpc, nullptr, cic, vc, dc, dinvc, ovf.p);
+  galerkin_kernel<<<grid_for(nc, GAL_WAVES), 64 * GAL_WAVES, 0, s>>>(nc, moff, mem, agg, rp, ci, av, d, pval,
+                                                                      graph_mode, rpc, nullptr, cic, vc, dc, dinvc,
+                                                                      ovf.p);
   PCAMG_LAUNCHED();
   galerkin_long_rows(nc, ovf.p, moff, mem, agg, rp, ci, av, d, pval, graph_mode, rpc, nullptr, cic, vc, dc, dinvc, s);
 }

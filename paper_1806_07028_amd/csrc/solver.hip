@@ -11,12 +11,24 @@ namespace pcamg {
 
 namespace {
 
+// Lanes per row for the smoother and residual kernels: one thread per row for
+// short rows, cooperating lane groups for the long rows of coarse operators,
+// where the launch is latency-bound and a row's entries should arrive in one
+// or two round trips (measured on the 3D grid hierarchies).
+int32_t pick_lanes(int32_t n, int32_t nnz, int32_t forced) {
+  if (forced) return forced;
+  const double avg = n > 0 ? (double)nnz / n : 0.0;
+  return avg <= 10.0 ? 1 : avg <= 24.0 ? 4 : 16;
+}
+
 std::shared_ptr<LevelMatrix> make_level_matrix(int32_t n, int32_t nnz, const int32_t* rp, const int32_t* ci,
                                                const double* av, const double* d, const double* dinv,
-                                               const int32_t* colour, int32_t ncol, hipStream_t s) {
+                                               const int32_t* colour, int32_t ncol, int32_t row_lanes,
+                                               hipStream_t s) {
   auto M = std::make_shared<LevelMatrix>();
   M->n = n;
   M->nnz = nnz;
+  M->lanes = pick_lanes(n, nnz, row_lanes);
   M->perm.resize(n);
   M->iperm.resize(n);
   if (colour) {
@@ -75,7 +87,8 @@ void ctx_init(pcamg_ctx* c, const pcamg_graph* g, const pcamg_params* p) {
   copy_d2d(c->ci.p, g->col_idx, nnz, s);
   laplacian(n, c->rp.p, g->weight, c->av.p, c->d.p, c->dinv.p, nnz, s);
   c->ncol = colour_jp(n, c->rp.p, c->ci.p, c->P.colour_seed, 0, c->colour.p, s);
-  c->M0 = make_level_matrix(n, nnz, c->rp.p, c->ci.p, c->av.p, c->d.p, c->dinv.p, c->colour.p, c->ncol, s);
+  c->M0 = make_level_matrix(n, nnz, c->rp.p, c->ci.p, c->av.p, c->d.p, c->dinv.p, c->colour.p, c->ncol,
+                            c->P.row_lanes, s);
   sync(s);
 }
 
@@ -196,8 +209,10 @@ std::unique_ptr<Hierarchy> build_hierarchy(pcamg_ctx* c, const double* e_nat) {
     NatLevel& L = nat[l];
     Level& V = H->lv[l];
     if (l == 0) V.A = c->M0;
-    else if (l + 1 < nl) V.A = make_level_matrix(L.n, L.nnz, L.rp, L.ci, L.av, L.d, L.dinv, L.colour, L.ncol, s);
-    else V.A = make_level_matrix(L.n, L.nnz, L.rp, L.ci, L.av, L.d, L.dinv, nullptr, 1, s);
+    else if (l + 1 < nl)
+      V.A = make_level_matrix(L.n, L.nnz, L.rp, L.ci, L.av, L.d, L.dinv, L.colour, L.ncol, P.row_lanes, s);
+    else
+      V.A = make_level_matrix(L.n, L.nnz, L.rp, L.ci, L.av, L.d, L.dinv, nullptr, 1, P.row_lanes, s);
     V.x.resize(L.n);
     V.b.resize(L.n);
     V.r.resize(L.n);
@@ -269,6 +284,95 @@ std::unique_ptr<Hierarchy> build_hierarchy(pcamg_ctx* c, const double* e_nat) {
                      H->fallback ? 1 : 0, npv};
   }
   H->st0 = nat[0].st;
+  // tail: the levels of at most tail_max_n vertices and the coarsest run in one
+  // workgroup launch.  LDS takes the vectors of the coarsest and of as many
+  // levels above it as fit (FP64 layout, the larger one); the levels above
+  // those keep theirs in global memory.
+  {
+    const int32_t tail_n = c->P.tail_max_n > 0 ? c->P.tail_max_n : 0;
+    const int64_t budget = TAIL_LDS_BYTES / 8;  // doubles
+    const int64_t fixed = (int64_t)H->cm + (H->cm <= 64 ? (int64_t)H->cm * H->cm : 0);
+    const bool coarsest_fits = 3 * (int64_t)H->cn + fixed <= budget;
+    int ts = nl - 1;
+    int64_t nco = 0;
+    while (tail_n > 0 && ts > 0 && H->lv[ts - 1].A->n <= tail_n && nl - (ts - 1) <= TAIL_MAX_LEVELS &&
+           nco + H->lv[ts - 1].A->ncol + 1 <= TAIL_COFF_MAX) {
+      --ts;
+      nco += H->lv[ts].A->ncol + 1;
+    }
+    H->tail_start = (tail_n > 0 && coarsest_fits && !(ts == 0 && nl == 1)) ? ts : -1;
+    if (H->tail_start >= 0) {
+      TailDesc D;
+      std::memset(&D, 0, sizeof(D));
+      D.nlev = nl - H->tail_start;
+      D.cn = H->cn;
+      D.cm = H->cm;
+      D.grounded = H->grounded ? 1 : 0;
+      D.L = H->cL.p;
+      D.D = H->cD.p;
+      // LDS from the coarsest upwards
+      int first_lds = nl - 1;
+      int64_t used = 3 * (int64_t)H->cn + fixed;
+      while (first_lds > H->tail_start && used + 3 * (int64_t)H->lv[first_lds - 1].A->n <= budget) {
+        --first_lds;
+        used += 3 * (int64_t)H->lv[first_lds].A->n;
+      }
+      H->coff_dev.resize(nl);
+      int32_t o64 = 0, o32 = 0, oco = 0;
+      for (int l = H->tail_start; l < nl; ++l) {
+        Level& V = H->lv[l];
+        const LevelMatrix& A = *V.A;
+        TailLevel& T = D.lv[l - H->tail_start];
+        T.n = A.n;
+        T.ncol = A.ncol;
+        T.lds = l >= first_lds ? 1 : 0;
+        T.lanes = 1;  // one workgroup: one thread per row measured fastest
+        if (T.lds) {
+          for (int j = 0; j < 3; ++j) {
+            T.o64[j] = o64 + j * A.n;
+            T.o32[j] = o32 + j * A.n;
+          }
+          o64 += 3 * A.n;
+          o32 += 3 * A.n;
+        }
+        if (l + 1 < nl) {
+          T.ocoff = oco;
+          oco += A.ncol + 1;
+          H->coff_dev[l].resize(A.ncol + 1);
+          copy_h2d(H->coff_dev[l].p, A.coff.data(), A.ncol + 1, s);
+          T.coff = H->coff_dev[l].p;
+        }
+        T.rp = A.rp.p;
+        T.ci = A.ci.p;
+        T.av = A.av.p;
+        T.d = A.d.p;
+        T.dinv = A.dinv.p;
+        T.av32 = A.av32.p;
+        T.d32 = A.d32.p;
+        T.dinv32 = A.dinv32.p;
+        T.agg = V.T.agg.p;
+        T.moff = V.T.moff.p;
+        T.mem = V.T.mem.p;
+        T.pval = V.T.pval.p;
+        T.pval32 = V.T.pval32.p;
+        T.x = V.x.p;
+        T.b = V.b.p;
+        T.r = V.r.p;
+        T.x32 = V.x32.p;
+        T.b32 = V.b32.p;
+        T.r32 = V.r32.p;
+      }
+      D.ncoff = oco;
+      D.oacc64 = o64;
+      D.oacc32 = (o32 + 1) / 2;
+      const bool lds_L = H->cm <= 64;
+      D.oL64 = lds_L ? D.oacc64 + H->cm : -1;
+      D.oL32 = lds_L ? D.oacc32 + H->cm : -1;
+      H->tail_desc.resize(1);
+      copy_h2d(H->tail_desc.p, &D, 1, s);
+      sync(s);  // D is a host temporary
+    }
+  }
   if (P.keep_setup) {
     H->setup.resize(nl);
     for (int l = 0; l < nl; ++l) {
@@ -315,6 +419,10 @@ std::unique_ptr<Hierarchy> build_hierarchy(pcamg_ctx* c, const double* e_nat) {
 void cycle64(pcamg_ctx* c, Hierarchy& H, int l, const double* b, double* x, int gamma) {
   hipStream_t s = c->s;
   const int nl = (int)H.lv.size();
+  if (l == H.tail_start && !(l == 0 && nl == 1)) {
+    tail_cycle64(H, b, x, gamma, s);
+    return;
+  }
   if (l + 1 == nl) {
     if (l == 0) {  // no coarsening: the dense factor is in natural order, level 0 is colour-permuted
       Level& L = H.lv[0];
@@ -329,8 +437,8 @@ void cycle64(pcamg_ctx* c, Hierarchy& H, int l, const double* b, double* x, int 
   Level& L = H.lv[l];
   const LevelMatrix& A = *L.A;
   for (int k = 0; k < A.ncol; ++k)
-    gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s);
-  residual<double>(A.n, A.rp.p, A.ci.p, A.av.p, A.d.p, b, x, L.r.p, s);
+    gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s, A.lanes);
+  residual<double>(A.n, A.rp.p, A.ci.p, A.av.p, A.d.p, b, x, L.r.p, s, A.lanes);
   Level& N = H.lv[l + 1];
   restrict_members<double>(L.T.nc, L.T.moff.p, L.T.mem.p, L.T.pval.p, L.r.p, N.b.p, s);
   fill_f64(N.x.p, 0.0, N.A->n, s);
@@ -338,12 +446,16 @@ void cycle64(pcamg_ctx* c, Hierarchy& H, int l, const double* b, double* x, int 
   for (int q = 0; q < calls; ++q) cycle64(c, H, l + 1, N.b.p, N.x.p, gamma);
   prolong_add<double>(A.n, L.T.agg.p, L.T.pval.p, N.x.p, x, s);
   for (int k = A.ncol - 1; k >= 0; --k)
-    gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s);
+    gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s, A.lanes);
 }
 
-void cycle32(pcamg_ctx* c, Hierarchy& H, int l, const float* b, float* x) {
+void cycle32(pcamg_ctx* c, Hierarchy& H, int l, const float* b, float* x, int gamma) {
   hipStream_t s = c->s;
   const int nl = (int)H.lv.size();
+  if (l == H.tail_start && !(l == 0 && nl == 1)) {
+    tail_cycle32(H, b, x, gamma, s);
+    return;
+  }
   if (l + 1 == nl) {
     if (l == 0) {  // no coarsening: natural-order factor, colour-permuted vectors
       Level& L = H.lv[0];
@@ -358,15 +470,90 @@ void cycle32(pcamg_ctx* c, Hierarchy& H, int l, const float* b, float* x) {
   Level& L = H.lv[l];
   const LevelMatrix& A = *L.A;
   for (int k = 0; k < A.ncol; ++k)
-    gs_colour<float>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s);
-  residual<float>(A.n, A.rp.p, A.ci.p, A.av32.p, A.d32.p, b, x, L.r32.p, s);
+    gs_colour<float>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s, A.lanes);
+  residual<float>(A.n, A.rp.p, A.ci.p, A.av32.p, A.d32.p, b, x, L.r32.p, s, A.lanes);
   Level& N = H.lv[l + 1];
   restrict_members<float>(L.T.nc, L.T.moff.p, L.T.mem.p, L.T.pval32.p, L.r32.p, N.b32.p, s);
   fill_f32(N.x32.p, 0.0f, N.A->n, s);
-  cycle32(c, H, l + 1, N.b32.p, N.x32.p);
+  const int calls = (gamma > 1 && l + 2 < nl) ? gamma : 1;
+  for (int q = 0; q < calls; ++q) cycle32(c, H, l + 1, N.b32.p, N.x32.p, gamma);
   prolong_add<float>(A.n, L.T.agg.p, L.T.pval32.p, N.x32.p, x, s);
   for (int k = A.ncol - 1; k >= 0; --k)
-    gs_colour<float>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s);
+    gs_colour<float>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s, A.lanes);
+}
+
+// ---------------------------------------------------------------------------
+// Whole cycles from captured graphs.  A cycle's launch sequence is fixed for a
+// hierarchy, so it is captured once (per precision and cycle type) on fixed
+// input/output buffers and replayed; inputs are copied in and results out.
+// ---------------------------------------------------------------------------
+namespace {
+// Records the launches of body() into a graph.  Capture is not allowed on the
+// legacy null stream, so the launches are redirected to the context's private
+// capture stream (nothing executes during capture); the graph is then replayed
+// on the caller's stream.
+template <typename F>
+hipGraphExec_t capture(pcamg_ctx* c, F&& body) {
+  if (!c->capture_stream) PCAMG_HIP(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+  hipStream_t user = c->s;
+  hipGraph_t g = nullptr;
+  PCAMG_HIP(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+  c->s = c->capture_stream;
+  try {
+    body();
+  } catch (...) {
+    c->s = user;
+    hipGraph_t tmp = nullptr;
+    (void)hipStreamEndCapture(c->capture_stream, &tmp);
+    if (tmp) (void)hipGraphDestroy(tmp);
+    throw;
+  }
+  c->s = user;
+  PCAMG_HIP(hipStreamEndCapture(c->capture_stream, &g));
+  hipGraphExec_t e = nullptr;
+  hipError_t err = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  PCAMG_HIP(err);
+  return e;
+}
+}  // namespace
+
+void run_cycle64(pcamg_ctx* c, Hierarchy& H, const double* b, double* x, int gamma) {
+  hipStream_t s = c->s;
+  const int32_t n = c->n;
+  if (!c->P.use_graphs) {
+    cycle64(c, H, 0, b, x, gamma);
+    return;
+  }
+  if (!H.gb.p) {
+    H.gb.resize(n);
+    H.gx.resize(n);
+  }
+  hipGraphExec_t& g = gamma > 1 ? H.g64w : H.g64v;
+  if (!g) g = capture(c, [&] { cycle64(c, H, 0, H.gb.p, H.gx.p, gamma); });
+  copy_d2d(H.gb.p, b, n, s);
+  copy_d2d(H.gx.p, x, n, s);
+  PCAMG_HIP(hipGraphLaunch(g, s));
+  copy_d2d(x, H.gx.p, n, s);
+}
+
+void run_cycle32(pcamg_ctx* c, Hierarchy& H, const float* b, float* x, int gamma) {
+  hipStream_t s = c->s;
+  const int32_t n = c->n;
+  if (!c->P.use_graphs) {
+    cycle32(c, H, 0, b, x, gamma);
+    return;
+  }
+  if (!H.gb32.p) {
+    H.gb32.resize(n);
+    H.gx32.resize(n);
+  }
+  hipGraphExec_t& g = gamma > 1 ? H.g32w : H.g32v;
+  if (!g) g = capture(c, [&] { cycle32(c, H, 0, H.gb32.p, H.gx32.p, gamma); });
+  copy_d2d(H.gb32.p, b, n, s);
+  copy_d2d(H.gx32.p, x, n, s);
+  PCAMG_HIP(hipGraphLaunch(g, s));
+  copy_d2d(x, H.gx32.p, n, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -377,9 +564,9 @@ void relax_perm(pcamg_ctx* c, double* e_perm, const double* zero, int sweeps) {
   const LevelMatrix& A = *c->M0;
   for (int q = 0; q < sweeps; ++q) {
     for (int k = 0; k < A.ncol; ++k)
-      gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, zero, e_perm, c->s);
+      gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, zero, e_perm, c->s, A.lanes);
     for (int k = A.ncol - 1; k >= 0; --k)
-      gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, zero, e_perm, c->s);
+      gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, zero, e_perm, c->s, A.lanes);
   }
 }
 }  // namespace
@@ -404,7 +591,7 @@ void initial_error(pcamg_ctx* c, int32_t r, double* e_nat) {
 // symmetric composite B_1 .. B_Re, B_Re .. B_1 of V-cycles; preconditioned
 // vectors and the result made orthogonal to 1.
 // ---------------------------------------------------------------------------
-void approx_error(pcamg_ctx* c, int Re, const double* r, double* e, int* wcycles, int* vcycles) {
+void approx_error(pcamg_ctx* c, int Re, const double* r, double* e, int* wcycles, int* vcycles, int* vcycles32) {
   hipStream_t s = c->s;
   const int32_t n = c->n;
   const pcamg_params& P = c->P;
@@ -412,18 +599,34 @@ void approx_error(pcamg_ctx* c, int Re, const double* r, double* e, int* wcycles
   const bool wcyc = Re <= P.numW;
   const int steps = wcyc ? P.iterW : P.iterV;
   DVec<double> rr(n), z(n), p(n), q(n), scal(2);
+  const bool f32 = P.cycle_prec == PCAMG_PREC_F32;
+  DVec<float> v32(f32 ? n : 0), z32(f32 ? n : 0);
   auto dot = [&](const double* a, const double* b) {
     dot_f64(a, b, n, scal.p, s);
     return read_scalar(scal.p, s);
   };
+  // FP32 setting: the preconditioning cycles run in FP32, input rounded once,
+  // result widened once
   auto prec = [&](const double* v, double* zz) {
     fill_f64(zz, 0.0, n, s);
-    if (wcyc) {
-      cycle64(c, *c->hist[Re - 1], 0, v, zz, 2);
+    if (f32) {
+      cast_f64_f32(v, v32.p, n, s);
+      fill_f32(z32.p, 0.0f, n, s);
+      if (wcyc) {
+        run_cycle32(c, *c->hist[Re - 1], v32.p, z32.p, 2);
+        if (wcycles) *wcycles += 1;
+      } else {
+        for (int j = 0; j < Re; ++j) run_cycle32(c, *c->hist[j], v32.p, z32.p, 1);
+        for (int j = Re - 1; j >= 0; --j) run_cycle32(c, *c->hist[j], v32.p, z32.p, 1);
+        if (vcycles32) *vcycles32 += 2 * Re;
+      }
+      cast_f32_f64(z32.p, zz, n, s);
+    } else if (wcyc) {
+      run_cycle64(c, *c->hist[Re - 1], v, zz, 2);
       if (wcycles) *wcycles += 1;
     } else {
-      for (int j = 0; j < Re; ++j) cycle64(c, *c->hist[j], 0, v, zz, 1);
-      for (int j = Re - 1; j >= 0; --j) cycle64(c, *c->hist[j], 0, v, zz, 1);
+      for (int j = 0; j < Re; ++j) run_cycle64(c, *c->hist[j], v, zz, 1);
+      for (int j = Re - 1; j >= 0; --j) run_cycle64(c, *c->hist[j], v, zz, 1);
       if (vcycles) *vcycles += 2 * Re;
     }
     sum_f64(zz, n, scal.p + 1, s);
@@ -435,7 +638,7 @@ void approx_error(pcamg_ctx* c, int Re, const double* r, double* e, int* wcycles
   copy_d2d(p.p, z.p, n, s);
   double rz = dot(rr.p, z.p);
   for (int t = 0; t < steps; ++t) {
-    spmv<double>(n, A.rp.p, A.ci.p, A.av.p, A.d.p, p.p, q.p, s);
+    spmv<double>(n, A.rp.p, A.ci.p, A.av.p, A.d.p, p.p, q.p, s, A.lanes);
     const double pq = dot(p.p, q.p);
     if (!(pq > 0.0)) break;
     const double alpha = rz / pq;
@@ -467,7 +670,7 @@ void solve(pcamg_ctx* c, double* x_nat, pcamg_stats* st) {
   require(c->have_rhs, PCAMG_EINVAL, "no right-hand side");
   require(!c->hist.empty(), PCAMG_EINVAL, "no hierarchy");
   Timer total(s);
-  double t_rebuild = 0.0;
+  double t_rebuild = 0.0, t_approx = 0.0, t_build = 0.0;
   int vc64 = 0, vc32 = 0, wc = 0;
   DVec<double> b(n), x(n), r(n), scal(4);
   gather_f64(c->rhs.p, A.perm.p, b.p, n, s);
@@ -480,7 +683,7 @@ void solve(pcamg_ctx* c, double* x_nat, pcamg_stats* st) {
     sum_f64(v, n, scal.p + 1, s);
     sub_mean_f64(v, scal.p + 1, n, s);
   };
-  auto res_of = [&](const double* xx, double* rr) { residual<double>(n, A.rp.p, A.ci.p, A.av.p, A.d.p, b.p, xx, rr, s); };
+  auto res_of = [&](const double* xx, double* rr) { residual<double>(n, A.rp.p, A.ci.p, A.av.p, A.d.p, b.p, xx, rr, s, A.lanes); };
   std::vector<double> hist{1.0};
   std::vector<double> conv, conv_all;
   int rebuilds = 0, k = 0, status = PCAMG_OK;
@@ -504,22 +707,27 @@ void solve(pcamg_ctx* c, double* x_nat, pcamg_stats* st) {
     const int Re = (int)c->hist.size();
     DVec<double> eb(n), enat(n), zero(n);
     if (P.rebuild_source == PCAMG_REBUILD_ERROR_APPROX) {
-      int nw = 0, nv = 0;
-      approx_error(c, Re, res, corr, &nw, &nv);
+      int nw = 0, nv = 0, nv32 = 0;
+      Timer ta(s);
+      approx_error(c, Re, res, corr, &nw, &nv, &nv32);
+      t_approx += ta.ms();
       wc += nw;
       vc64 += nv;
+      vc32 += nv32;
       copy_d2d(eb.p, corr, n, s);
     } else {
       xi_fill(P.seed, Re, A.perm.p, eb.p, n, s);
       fill_f64(zero.p, 0.0, n, s);
-      for (int q = 0; q < P.rebuild_vcycles; ++q) cycle64(c, *c->hist.back(), 0, zero.p, eb.p, 1);
+      for (int q = 0; q < P.rebuild_vcycles; ++q) run_cycle64(c, *c->hist.back(), zero.p, eb.p, 1);
       vc64 += P.rebuild_vcycles;
       fill_f64(corr, 0.0, n, s);
     }
     fill_f64(zero.p, 0.0, n, s);
     relax_perm(c, eb.p, zero.p, P.relax_sweeps);
     scatter_f64(eb.p, A.perm.p, enat.p, n, s);
+    Timer tb(s);
     c->hist.push_back(build_hierarchy(c, enat.p));
+    t_build += tb.ms();
     oc_sum += c->hist.back()->op_complexity;
     ++nh;
     ++rebuilds;
@@ -530,7 +738,7 @@ void solve(pcamg_ctx* c, double* x_nat, pcamg_stats* st) {
     if (P.outer == PCAMG_OUTER_VCYCLE) {
       DVec<double> corr(n);
       while (k < P.max_iter) {
-        cycle64(c, *c->hist.back(), 0, b.p, x.p, 1);
+        run_cycle64(c, *c->hist.back(), b.p, x.p, 1);
         ++vc64;
         remove_mean(x.p);
         res_of(x.p, r.p);
@@ -560,12 +768,12 @@ void solve(pcamg_ctx* c, double* x_nat, pcamg_stats* st) {
         if (P.cycle_prec == PCAMG_PREC_F32) {
           cast_f64_f32(rr, r32.p, n, s);
           fill_f32(z32.p, 0.0f, n, s);
-          cycle32(c, H, 0, r32.p, z32.p);
+          run_cycle32(c, H, r32.p, z32.p, 1);
           cast_f32_f64(z32.p, zz, n, s);
           ++vc32;
         } else {
           fill_f64(zz, 0.0, n, s);
-          cycle64(c, H, 0, rr, zz, 1);
+          run_cycle64(c, H, rr, zz, 1);
           ++vc64;
         }
         remove_mean(zz);
@@ -574,7 +782,7 @@ void solve(pcamg_ctx* c, double* x_nat, pcamg_stats* st) {
       copy_d2d(p.p, z.p, n, s);
       double rz = dot(r.p, z.p);
       while (k < P.max_iter) {
-        spmv<double>(n, A.rp.p, A.ci.p, A.av.p, A.d.p, p.p, q.p, s);
+        spmv<double>(n, A.rp.p, A.ci.p, A.av.p, A.d.p, p.p, q.p, s, A.lanes);
         const double pq = dot(p.p, q.p);
         if (!(pq > 0.0)) { status = PCAMG_EBREAKDOWN; break; }
         const double alpha = rz / pq;
@@ -640,6 +848,8 @@ void solve(pcamg_ctx* c, double* x_nat, pcamg_stats* st) {
     st->op_complexity = oc_sum / nh;
     st->t_solve_ms = total.ms();
     st->t_rebuild_ms = t_rebuild;
+    st->t_approx_ms = t_approx;
+    st->t_build_ms = t_build;
     st->t_setup_ms = c->t_build_ms;
     st->vcycles64 = vc64;
     st->vcycles32 = vc32;
@@ -677,15 +887,15 @@ void bench_smoother(pcamg_ctx* c, int prec, int sweeps, double* ms, int64_t* lau
   auto sweep = [&]() {
     for (int k = 0; k < A.ncol; ++k) {
       if (prec == PCAMG_PREC_F32)
-        gs_colour<float>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b32.p, x32.p, s);
+        gs_colour<float>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b32.p, x32.p, s, A.lanes);
       else
-        gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b.p, x.p, s);
+        gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b.p, x.p, s, A.lanes);
     }
     for (int k = A.ncol - 1; k >= 0; --k) {
       if (prec == PCAMG_PREC_F32)
-        gs_colour<float>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b32.p, x32.p, s);
+        gs_colour<float>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b32.p, x32.p, s, A.lanes);
       else
-        gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b.p, x.p, s);
+        gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b.p, x.p, s, A.lanes);
     }
   };
   sweep();  // warm-up

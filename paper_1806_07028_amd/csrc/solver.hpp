@@ -12,6 +12,7 @@ namespace pcamg {
 // A level operator in the solve layout (rows grouped by colour).
 struct LevelMatrix {
   int32_t n = 0, nnz = 0, ncol = 0;
+  int32_t lanes = 1;          // lanes per row in the smoother and residual kernels
   std::vector<int32_t> coff;  // host, ncol + 1
   DVec<int32_t> rp, ci;
   DVec<double> av, d, dinv;
@@ -43,8 +44,50 @@ struct Level {
   std::array<int64_t, 16> info{};
 };
 
+// Level descriptor for the single-workgroup tail kernel (device memory).  The
+// vectors (x, b, r) of the smaller tail levels, the dense solve's accumulator
+// and, when it fits, the coarsest factor live in the workgroup's LDS for the
+// duration of a launch (o64 / o32: element offsets in the LDS pool seen as
+// double / float); the larger tail levels keep theirs in global memory.
+constexpr int TAIL_MAX_LEVELS = 40;
+constexpr int LDLT_MAX = 4096;
+constexpr int TAIL_LDS_BYTES = 128 * 1024;
+constexpr int TAIL_COFF_MAX = 2048;
+struct TailLevel {
+  int32_t n, ncol, lds, ocoff, lanes;  // lanes per row: 1 or 4
+  int32_t o64[3], o32[3];  // x, b, r in LDS (lds = 1)
+  const int32_t *coff, *rp, *ci, *agg, *moff, *mem;
+  const double *av, *d, *dinv, *pval;
+  const float *av32, *d32, *dinv32, *pval32;
+  double *x, *b, *r;       // in global memory (lds = 0)
+  float *x32, *b32, *r32;
+};
+struct TailDesc {
+  int32_t nlev;  // tail levels including the coarsest
+  int32_t cn, cm, grounded;
+  int32_t oacc64, oacc32;  // accumulator offsets (doubles) in the two layouts
+  int32_t oL64, oL32;      // factor L offsets (doubles), -1 = read from global memory
+  int32_t ncoff;
+  const double *L, *D;
+  TailLevel lv[TAIL_MAX_LEVELS];
+};
+
 struct Hierarchy {
   std::vector<Level> lv;
+  // tail: levels tail_start.. run in one workgroup launch
+  int tail_start = -1;
+  DVec<TailDesc> tail_desc;
+  std::vector<DVec<int32_t>> coff_dev;
+  // captured top-level cycles (fixed input/output buffers)
+  hipGraphExec_t g64v = nullptr, g64w = nullptr, g32v = nullptr, g32w = nullptr;
+  DVec<double> gb, gx;
+  DVec<float> gb32, gx32;
+  ~Hierarchy() {
+    if (g64v) (void)hipGraphExecDestroy(g64v);
+    if (g64w) (void)hipGraphExecDestroy(g64w);
+    if (g32v) (void)hipGraphExecDestroy(g32v);
+    if (g32w) (void)hipGraphExecDestroy(g32w);
+  }
   // coarsest dense factor (natural order of the coarsest level)
   int32_t cn = 0, cm = 0;
   bool grounded = false, fallback = false;
@@ -80,6 +123,10 @@ struct Timer {
 
 struct pcamg_ctx {
   hipStream_t s = nullptr;
+  hipStream_t capture_stream = nullptr;  // private stream used only to capture cycle graphs
+  ~pcamg_ctx() {
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
+  }
   pcamg_params P{};
   int32_t n = 0, nnz = 0;
   // finest level, natural numbering
@@ -109,9 +156,14 @@ void relax_homogeneous(pcamg_ctx* c, double* e_nat, int sweeps);
 void initial_error(pcamg_ctx* c, int32_t r, double* e_nat);
 // Cycles on the solve layout (level-0 vectors in permuted order).
 void cycle64(pcamg_ctx* c, Hierarchy& H, int l, const double* b, double* x, int gamma);
-void cycle32(pcamg_ctx* c, Hierarchy& H, int l, const float* b, float* x);
+void cycle32(pcamg_ctx* c, Hierarchy& H, int l, const float* b, float* x, int gamma);
+// Whole cycles on level-0 vectors (solve layout), replayed from captured graphs.
+void run_cycle64(pcamg_ctx* c, Hierarchy& H, const double* b, double* x, int gamma);
+void run_cycle32(pcamg_ctx* c, Hierarchy& H, const float* b, float* x, int gamma);
+void tail_cycle64(const Hierarchy& H, const double* b, double* x, int gamma, hipStream_t s);
+void tail_cycle32(const Hierarchy& H, const float* b, float* x, int gamma, hipStream_t s);
 // Alg. 2 on permuted vectors.
-void approx_error(pcamg_ctx* c, int Re, const double* r, double* e, int* wcycles, int* vcycles);
+void approx_error(pcamg_ctx* c, int Re, const double* r, double* e, int* wcycles, int* vcycles, int* vcycles32);
 void bench_smoother(pcamg_ctx* c, int prec, int sweeps, double* ms, int64_t* launches, double* bytes);
 void solve(pcamg_ctx* c, double* x_nat, pcamg_stats* st);
 }  // namespace pcamg

@@ -1,0 +1,288 @@
+// Tail of a multigrid cycle in one workgroup.  The small levels of a
+// hierarchy (and the dense coarsest solve) are visited many times per cycle --
+// 2^l times in a W-cycle -- and each visit of a multicoloured level is a long
+// chain of tiny steps.  Here the whole sub-cycle from the first small level
+// down to the coarsest runs in a single launch of 1024 threads, with a
+// workgroup barrier between dependent steps.  All vectors of the sub-cycle sit
+// in LDS for the launch, so a step's only global reads are matrix entries,
+// which do not depend on the previous step.  Every row and every sum uses the
+// same arithmetic and order as the per-step kernels, so results are identical
+// bit for bit.
+#include "rowchain.hpp"
+#include "solver.hpp"
+
+namespace pcamg {
+
+constexpr int TAIL_THREADS = 1024;
+
+template <typename T>
+using GP = const PCAMG_GLOBAL T*;
+template <typename T>
+using GW = PCAMG_GLOBAL T*;
+template <typename T>
+__device__ __forceinline__ GW<T> gptr_w(T* p) {
+  return (GW<T>)p;
+}
+
+template <typename T>
+struct TailOps;
+template <>
+struct TailOps<double> {
+  __device__ static GP<double> av(const TailLevel& L) { return gptr(L.av); }
+  __device__ static GP<double> d(const TailLevel& L) { return gptr(L.d); }
+  __device__ static GP<double> dinv(const TailLevel& L) { return gptr(L.dinv); }
+  __device__ static GP<double> pval(const TailLevel& L) { return gptr(L.pval); }
+  __device__ static GW<double> gx(const TailLevel& L) { return gptr_w(L.x); }
+  __device__ static GW<double> gb(const TailLevel& L) { return gptr_w(L.b); }
+  __device__ static GW<double> gr(const TailLevel& L) { return gptr_w(L.r); }
+  __device__ static int32_t off(const TailLevel& L, int j) { return L.o64[j]; }
+  __device__ static int32_t oacc(const TailDesc& D) { return D.oacc64; }
+  __device__ static int32_t oL(const TailDesc& D) { return D.oL64; }
+};
+template <>
+struct TailOps<float> {
+  __device__ static GP<float> av(const TailLevel& L) { return gptr(L.av32); }
+  __device__ static GP<float> d(const TailLevel& L) { return gptr(L.d32); }
+  __device__ static GP<float> dinv(const TailLevel& L) { return gptr(L.dinv32); }
+  __device__ static GP<float> pval(const TailLevel& L) { return gptr(L.pval32); }
+  __device__ static GW<float> gx(const TailLevel& L) { return gptr_w(L.x32); }
+  __device__ static GW<float> gb(const TailLevel& L) { return gptr_w(L.b32); }
+  __device__ static GW<float> gr(const TailLevel& L) { return gptr_w(L.r32); }
+  __device__ static int32_t off(const TailLevel& L, int j) { return L.o32[j]; }
+  __device__ static int32_t oacc(const TailDesc& D) { return D.oacc32; }
+  __device__ static int32_t oL(const TailDesc& D) { return D.oL32; }
+};
+
+// One Gauss-Seidel sweep over the colours of a level (forward or backward), G
+// lanes per row (1 or 4).  The vector pointer types carry the address space
+// (LDS or global), so each combination compiles to direct LDS or global
+// accesses.  With G = 4 all threads take part in every pass (uniform bounds),
+// as row_chain_g requires.
+template <typename T, int G, typename PB, typename PX>
+__device__ __forceinline__ void tail_gs_g(const TailLevel& L, const int32_t* coff, PB b, PX x, bool forward) {
+  constexpr int ROWS = TAIL_THREADS / G;
+  const GP<T> av = TailOps<T>::av(L), dinv = TailOps<T>::dinv(L);
+  const GP<int32_t> rp = gptr(L.rp), ci = gptr(L.ci);
+  const int32_t g = (int32_t)(threadIdx.x / G);
+  for (int t = 0; t < L.ncol; ++t) {
+    const int c = forward ? t : L.ncol - 1 - t;
+    const int32_t r0 = coff[c], r1 = coff[c + 1];
+    for (int32_t i0 = r0; i0 < r1; i0 += ROWS) {
+      const int32_t i = i0 + g;
+      if constexpr (G == 1) {
+        if (i < r1) {
+          const T s = row_chain1<T>(rp[i], rp[i + 1], ci, av, x, (T)0);
+          x[i] = (b[i] - s) * dinv[i];
+        }
+      } else {
+        const bool ok = i < r1;
+        const int32_t k0 = ok ? rp[i] : 0;
+        const int32_t len = ok ? rp[i + 1] - k0 : 0;
+        const T s = row_chain_g<T, G>(k0, len, ci, av, x, (T)0);
+        if (ok && (threadIdx.x & (G - 1)) == 0) x[i] = (b[i] - s) * dinv[i];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int G, typename PB, typename PX, typename PR>
+__device__ __forceinline__ void tail_res_g(const TailLevel& L, PB b, PX x, PR r) {
+  constexpr int ROWS = TAIL_THREADS / G;
+  const GP<T> av = TailOps<T>::av(L), d = TailOps<T>::d(L);
+  const GP<int32_t> rp = gptr(L.rp), ci = gptr(L.ci);
+  const int32_t g = (int32_t)(threadIdx.x / G);
+  for (int32_t i0 = 0; i0 < L.n; i0 += ROWS) {
+    const int32_t i = i0 + g;
+    if constexpr (G == 1) {
+      if (i < L.n) {
+        const T s = row_chain1<T>(rp[i], rp[i + 1], ci, av, x, d[i] * x[i]);
+        r[i] = b[i] - s;
+      }
+    } else {
+      const bool ok = i < L.n;
+      const int32_t k0 = ok ? rp[i] : 0;
+      const int32_t len = ok ? rp[i + 1] - k0 : 0;
+      const T s = row_chain_g<T, G>(k0, len, ci, av, x, ok ? d[i] * x[i] : (T)0);
+      if (ok && (threadIdx.x & (G - 1)) == 0) r[i] = b[i] - s;
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, typename PB, typename PX>
+__device__ __forceinline__ void tail_gs(const TailLevel& L, const int32_t* coff, PB b, PX x, bool forward) {
+  if (L.lanes == 1) tail_gs_g<T, 1>(L, coff, b, x, forward);
+  else tail_gs_g<T, 4>(L, coff, b, x, forward);
+}
+
+// pre-smoothing, residual, restriction; the child's x starts at zero
+template <typename T, typename PB, typename PX, typename PR, typename PBC, typename PXC>
+__device__ __forceinline__ void tail_down(const TailLevel& L, const int32_t* coff, PB b, PX x, PR r, PBC bc, PXC xc,
+                                          int32_t nc) {
+  tail_gs<T>(L, coff, b, x, true);
+  if (L.lanes == 1) tail_res_g<T, 1>(L, b, x, r);
+  else tail_res_g<T, 4>(L, b, x, r);
+  const GP<T> pv = TailOps<T>::pval(L);
+  const GP<int32_t> moff = gptr(L.moff), mem = gptr(L.mem);
+  for (int32_t q = threadIdx.x; q < nc; q += TAIL_THREADS) {
+    T s = 0;
+    for (int32_t t = moff[q]; t < moff[q + 1]; ++t) {
+      const int32_t k = mem[t];
+      s = fma(pv ? pv[k] : (T)1, r[k], s);
+    }
+    bc[q] = s;
+    xc[q] = 0;
+  }
+  __syncthreads();
+}
+
+// prolongation, post-smoothing
+template <typename T, typename PB, typename PX, typename PXC>
+__device__ __forceinline__ void tail_up(const TailLevel& L, const int32_t* coff, PB b, PX x, PXC xc) {
+  const GP<T> pv = TailOps<T>::pval(L);
+  const GP<int32_t> agg = gptr(L.agg);
+  for (int32_t k = threadIdx.x; k < L.n; k += TAIL_THREADS) x[k] = fma(pv ? pv[k] : (T)1, xc[agg[k]], x[k]);
+  __syncthreads();
+  tail_gs<T>(L, coff, b, x, false);
+}
+
+template <typename T, typename PB, typename PX, typename PR, typename PBC, typename PXC>
+__device__ __forceinline__ void tail_visit(bool down, const TailLevel& L, const int32_t* coff, PB b, PX x, PR r,
+                                           PBC bc, PXC xc, int32_t nc) {
+  if (down) tail_down<T>(L, coff, b, x, r, bc, xc, nc);
+  else tail_up<T>(L, coff, b, x, xc);
+}
+
+// dense coarsest solve (same order as ldlt_solve_kernel), result in x
+template <typename T>
+__device__ __forceinline__ void tail_coarsest(const TailDesc& D, const double* Lf, const T* b, T* x, double* acc,
+                                              double* mu) {
+  const int32_t n = D.cn, m = D.cm;
+  const GP<double> Dg = gptr(D.D);
+  for (int32_t i = threadIdx.x; i < m; i += TAIL_THREADS) acc[i] = (double)b[i];
+  __syncthreads();
+  for (int32_t k = 0; k < m; ++k) {
+    const double yk = acc[k];
+    for (int32_t i = k + 1 + threadIdx.x; i < m; i += TAIL_THREADS) acc[i] = fma(-Lf[(size_t)i * m + k], yk, acc[i]);
+    __syncthreads();
+  }
+  for (int32_t i = threadIdx.x; i < m; i += TAIL_THREADS) acc[i] = acc[i] / Dg[i];
+  __syncthreads();
+  for (int32_t k = m - 1; k >= 0; --k) {
+    const double xk = acc[k];
+    for (int32_t i = threadIdx.x; i < k; i += TAIL_THREADS) acc[i] = fma(-Lf[(size_t)k * m + i], xk, acc[i]);
+    __syncthreads();
+  }
+  if (D.grounded) {
+    if (threadIdx.x == 0) {
+      acc[n - 1] = 0.0;
+      double s = 0.0;
+      for (int32_t i = 0; i < n; ++i) s = s + acc[i];
+      *mu = s / (double)n;
+    }
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < n; i += TAIL_THREADS) x[i] = (T)(acc[i] - *mu);
+  } else {
+    for (int32_t i = threadIdx.x; i < n; i += TAIL_THREADS) x[i] = (T)acc[i];
+  }
+  __syncthreads();
+}
+
+// Cycle from tail level 0 (b0/x0 in global memory) to the coarsest: gamma
+// recursive calls per level (one when the next level is the coarsest),
+// iteratively; bit l of `again` records that level l still owes its second
+// call (gamma <= 2).  LDS holds the vectors of a bottom run of levels (always
+// including the coarsest); level 0's are staged in and out when it is one of
+// them.
+template <typename T>
+__global__ void __launch_bounds__(TAIL_THREADS) tail_kernel(const TailDesc* __restrict__ Dp, const T* __restrict__ b0,
+                                                             T* __restrict__ x0, int gamma) {
+  __shared__ double pool[TAIL_LDS_BYTES / 8];
+  __shared__ int32_t coffs[TAIL_COFF_MAX];
+  __shared__ double mu;
+  const TailDesc& D = *Dp;
+  T* V = reinterpret_cast<T*>(pool);
+  const int last = D.nlev - 1;  // coarsest, relative index
+  for (int l = 0; l < last; ++l) {
+    const TailLevel& L = D.lv[l];
+    const GP<int32_t> cf = gptr(L.coff);
+    for (int32_t c = threadIdx.x; c <= L.ncol; c += TAIL_THREADS) coffs[L.ocoff + c] = cf[c];
+  }
+  const bool stage0 = D.lv[0].lds != 0;
+  if (stage0) {
+    const TailLevel& L = D.lv[0];
+    T* xs = V + TailOps<T>::off(L, 0);
+    T* bs = V + TailOps<T>::off(L, 1);
+    for (int32_t i = threadIdx.x; i < L.n; i += TAIL_THREADS) {
+      xs[i] = x0[i];
+      bs[i] = b0[i];
+    }
+  }
+  const int32_t oL = TailOps<T>::oL(D);
+  if (oL >= 0) {
+    const GP<double> Lg = gptr(D.L);
+    for (int32_t i = threadIdx.x; i < D.cm * D.cm; i += TAIL_THREADS) pool[oL + i] = Lg[i];
+  }
+  const double* Lf = oL >= 0 ? pool + oL : D.L;
+  double* acc = pool + TailOps<T>::oacc(D);
+  __syncthreads();
+
+  uint64_t again = 0;
+  int l = 0;
+  int ph = 0;  // 0: descend into l, 1: returning to l from its child
+  while (l >= 0) {
+    const TailLevel& L = D.lv[l];
+    if (l == last) {  // the coarsest level's vectors are always in LDS
+      tail_coarsest<T>(D, Lf, V + TailOps<T>::off(L, 1), V + TailOps<T>::off(L, 0), acc, &mu);
+      --l;
+      ph = 1;
+      continue;
+    }
+    if (ph == 1 && (again & (1ull << l))) {  // second call continues from the child's current x
+      again &= ~(1ull << l);
+      ++l;
+      ph = 0;
+      continue;
+    }
+    const TailLevel& N = D.lv[l + 1];
+    const int32_t* coff = coffs + L.ocoff;
+    const bool down = ph == 0;
+    if (L.lds) {
+      tail_visit<T>(down, L, coff, (const T*)(V + TailOps<T>::off(L, 1)), V + TailOps<T>::off(L, 0),
+                    V + TailOps<T>::off(L, 2), V + TailOps<T>::off(N, 1), V + TailOps<T>::off(N, 0), N.n);
+    } else {
+      const GP<T> b = l == 0 ? gptr(b0) : (GP<T>)TailOps<T>::gb(L);
+      const GW<T> x = l == 0 ? gptr_w(x0) : TailOps<T>::gx(L);
+      if (N.lds)
+        tail_visit<T>(down, L, coff, b, x, TailOps<T>::gr(L), V + TailOps<T>::off(N, 1), V + TailOps<T>::off(N, 0),
+                      N.n);
+      else
+        tail_visit<T>(down, L, coff, b, x, TailOps<T>::gr(L), TailOps<T>::gb(N), TailOps<T>::gx(N), N.n);
+    }
+    if (down) {
+      if (gamma > 1 && l + 1 < last) again |= 1ull << l;
+      else again &= ~(1ull << l);
+      ++l;
+    } else {
+      --l;
+    }
+  }
+  if (stage0) {
+    const TailLevel& L = D.lv[0];
+    const T* xs = V + TailOps<T>::off(L, 0);
+    for (int32_t i = threadIdx.x; i < L.n; i += TAIL_THREADS) x0[i] = xs[i];
+  }
+}
+
+void tail_cycle64(const Hierarchy& H, const double* b, double* x, int gamma, hipStream_t s) {
+  tail_kernel<double><<<1, TAIL_THREADS, 0, s>>>(H.tail_desc.p, b, x, gamma);
+  PCAMG_LAUNCHED();
+}
+
+void tail_cycle32(const Hierarchy& H, const float* b, float* x, int gamma, hipStream_t s) {
+  tail_kernel<float><<<1, TAIL_THREADS, 0, s>>>(H.tail_desc.p, b, x, gamma);
+  PCAMG_LAUNCHED();
+}
+
+}  // namespace pcamg

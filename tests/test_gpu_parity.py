@@ -234,6 +234,8 @@ def test_cycles_bit_exact(gpu, oracle, gname):
         same(host(s.cycle(b, x0, gamma)), H.cycle(b, x0, gamma))
     b32 = b.astype(np.float32)
     same(host(s.cycle32(b32)), H.vcycle32(b32))
+    x32 = x0.astype(np.float32)
+    same(host(s.cycle32(b32, x32, 2)), H.cycle32(b32, x32, 2))
     # coarsest grounded case (boolean prolongations)
     sc = solver_for(gpu, g, p1_mode="const")
     Hc = oracle.Hierarchy(g, None, p1_mode=1)
@@ -278,6 +280,15 @@ def test_composite_approx_error(gpu, oracle):
         got = host(s.approx_error(r, count=count))
         ref = oracle.approximate_error(Hs[:count], r)
         assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref), count
+    # FP32 preconditioning cycles (W for Re <= numW, composite after): the FP32
+    # cycles are bit-exact, the PCG scalars go through reductions
+    s32 = solver_for(gpu, g, cycle_prec="f32")
+    s32.rebuild(torch.as_tensor(e2, device="cuda"))
+    s32.rebuild(torch.as_tensor(e3, device="cuda"))
+    for count in (1, 3):
+        got = host(s32.approx_error(r, count=count))
+        ref = oracle.approximate_error(Hs[:count], r, cycle_prec=1)
+        assert np.linalg.norm(got - ref) <= 1e-10 * np.linalg.norm(ref), count
 
 
 @pytest.mark.parametrize("kw", [dict(), dict(p1_mode="const"), dict(outer="fcg", cycle_prec="f32", theta=0.5),
@@ -369,3 +380,27 @@ def test_errors(gpu):
     s = P.Solver(g[1], g[2], g[3], b, max_iter=2, theta=1e9)
     x, st = s.solve(raise_on_noconv=False)
     assert st["status"] == -10 and st["iterations"] == 2
+
+
+@pytest.mark.parametrize("gname", ["grid3d_w", "hub"])
+def test_graph_and_tail_equal_eager(gpu, gname):
+    """Whole cycles replayed from captured graphs, with the small levels in the
+    single-workgroup tail kernel, equal the eager per-step launches bit for bit
+    on every replay (eager work and synchronisations between replays)."""
+    g = GRAPHS[gname]() if gname != "grid3d_w" else I.grid3d(20, 20, 20, weight_seed=7)
+    n = g[0]
+    b = I.zero_mean_normal_rhs(3, n)
+    x0 = I.normal(4, n)
+    eager = solver_for(gpu, g, use_graphs=0, tail_max_n=0)
+    fused = solver_for(gpu, g)
+    ref1 = host(eager.cycle(b, x0, 1))
+    ref2 = host(eager.cycle(b, x0, 2))
+    ref32 = host(eager.cycle32(b.astype(np.float32)))
+    ref32w = host(eager.cycle32(b.astype(np.float32), None, 2))
+    for rep in range(4):
+        same(host(fused.cycle(b, x0, 1)), ref1)
+        eager.cycle(b, None, 1)
+        torch.cuda.synchronize()
+        same(host(fused.cycle(b, x0, 2)), ref2)
+        same(host(fused.cycle32(b.astype(np.float32))), ref32)
+        same(host(fused.cycle32(b.astype(np.float32), None, 2)), ref32w)
