@@ -89,6 +89,9 @@ typedef struct {
   int32_t use_graphs;      /* 1 = replay whole cycles from captured HIP graphs */
   int32_t row_lanes;       /* lanes per matrix row in the smoother/residual kernels: 0 = by the
                               level's mean row length, else 1, 4, 16 or 64 (results identical) */
+  int32_t w_dense;         /* 1 = in W-cycles, the two sub-cycles below the tail's first level are
+                              applied as one precomputed dense operator (equal up to rounding
+                              order; built on first use per hierarchy and precision); 0 = recurse */
   uint64_t seed;           /* start-vector stream */
   uint64_t colour_seed;    /* colouring priority stream */
 } pcamg_params;

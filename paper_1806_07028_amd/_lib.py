@@ -47,6 +47,7 @@ class Params(C.Structure):
         ("tail_max_n", _i32),
         ("use_graphs", _i32),
         ("row_lanes", _i32),
+        ("w_dense", _i32),
         ("seed", _u64),
         ("colour_seed", _u64),
     ]

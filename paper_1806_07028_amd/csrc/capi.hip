@@ -205,6 +205,7 @@ pcamg_status pcamg_params_default(pcamg_params* p) {
   p->tail_max_n = 6144;
   p->use_graphs = 1;
   p->row_lanes = 0;
+  p->w_dense = 1;
   p->seed = 0x5EED;
   p->colour_seed = 0xC010;
   return PCAMG_OK;

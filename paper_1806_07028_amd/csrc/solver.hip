@@ -370,6 +370,7 @@ std::unique_ptr<Hierarchy> build_hierarchy(pcamg_ctx* c, const double* e_nat) {
       D.oL32 = lds_L ? D.oacc32 + H->cm : -1;
       H->tail_desc.resize(1);
       copy_h2d(H->tail_desc.p, &D, 1, s);
+      H->tail_host = std::make_unique<TailDesc>(D);
       sync(s);  // D is a host temporary
     }
   }
@@ -441,9 +442,13 @@ void cycle64(pcamg_ctx* c, Hierarchy& H, int l, const double* b, double* x, int 
   residual<double>(A.n, A.rp.p, A.ci.p, A.av.p, A.d.p, b, x, L.r.p, s, A.lanes);
   Level& N = H.lv[l + 1];
   restrict_members<double>(L.T.nc, L.T.moff.p, L.T.mem.p, L.T.pval.p, L.r.p, N.b.p, s);
-  fill_f64(N.x.p, 0.0, N.A->n, s);
   const int calls = (gamma > 1 && l + 2 < nl) ? gamma : 1;
-  for (int q = 0; q < calls; ++q) cycle64(c, H, l + 1, N.b.p, N.x.p, gamma);
+  if (calls == 2 && l + 1 == H.tail_start && H.C64.p) {  // both tail sub-cycles at once
+    dense_apply<double>(N.A->n, H.C64.p, N.b.p, H.dpart64.p, N.x.p, s);
+  } else {
+    fill_f64(N.x.p, 0.0, N.A->n, s);
+    for (int q = 0; q < calls; ++q) cycle64(c, H, l + 1, N.b.p, N.x.p, gamma);
+  }
   prolong_add<double>(A.n, L.T.agg.p, L.T.pval.p, N.x.p, x, s);
   for (int k = A.ncol - 1; k >= 0; --k)
     gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s, A.lanes);
@@ -474,9 +479,13 @@ void cycle32(pcamg_ctx* c, Hierarchy& H, int l, const float* b, float* x, int ga
   residual<float>(A.n, A.rp.p, A.ci.p, A.av32.p, A.d32.p, b, x, L.r32.p, s, A.lanes);
   Level& N = H.lv[l + 1];
   restrict_members<float>(L.T.nc, L.T.moff.p, L.T.mem.p, L.T.pval32.p, L.r32.p, N.b32.p, s);
-  fill_f32(N.x32.p, 0.0f, N.A->n, s);
   const int calls = (gamma > 1 && l + 2 < nl) ? gamma : 1;
-  for (int q = 0; q < calls; ++q) cycle32(c, H, l + 1, N.b32.p, N.x32.p, gamma);
+  if (calls == 2 && l + 1 == H.tail_start && H.C32.p) {  // both tail sub-cycles at once
+    dense_apply<float>(N.A->n, H.C32.p, N.b32.p, H.dpart32.p, N.x32.p, s);
+  } else {
+    fill_f32(N.x32.p, 0.0f, N.A->n, s);
+    for (int q = 0; q < calls; ++q) cycle32(c, H, l + 1, N.b32.p, N.x32.p, gamma);
+  }
   prolong_add<float>(A.n, L.T.agg.p, L.T.pval32.p, N.x32.p, x, s);
   for (int k = A.ncol - 1; k >= 0; --k)
     gs_colour<float>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s, A.lanes);
@@ -518,8 +527,57 @@ hipGraphExec_t capture(pcamg_ctx* c, F&& body) {
 }
 }  // namespace
 
+// Dense operator of the two W sub-cycles below the level above the tail (for
+// gamma = 2), built once per hierarchy and precision on first use: the tail
+// runs on every unit vector, one workgroup per column at a time, with
+// per-workgroup copies of the tail vectors that do not live in LDS.
+template <typename T>
+struct DenseOf;
+template <>
+struct DenseOf<double> {
+  static DVec<double>& C(Hierarchy& H) { return H.C64; }
+  static DVec<double>& part(Hierarchy& H) { return H.dpart64; }
+  static void point(TailLevel& T, double* x, double* b, double* r) { T.x = x, T.b = b, T.r = r; }
+};
+template <>
+struct DenseOf<float> {
+  static DVec<float>& C(Hierarchy& H) { return H.C32; }
+  static DVec<float>& part(Hierarchy& H) { return H.dpart32; }
+  static void point(TailLevel& T, float* x, float* b, float* r) { T.x32 = x, T.b32 = b, T.r32 = r; }
+};
+
+template <typename T>
+void ensure_dense(pcamg_ctx* c, Hierarchy& H) {
+  const int nl = (int)H.lv.size();
+  if (!c->P.w_dense || H.tail_start < 1 || nl - H.tail_start < 2 || !H.tail_host) return;
+  DVec<T>& C = DenseOf<T>::C(H);
+  if (C.p) return;
+  hipStream_t s = c->s;
+  TailDesc D = *H.tail_host;
+  const int32_t n0 = D.lv[0].n;
+  size_t gstride = 0;
+  for (int l = 0; l < D.nlev; ++l)
+    if (!D.lv[l].lds) gstride += 3 * (size_t)D.lv[l].n;
+  const int blocks = std::min<int32_t>(n0, 256);
+  DVec<T> scratch(std::max<size_t>(gstride * blocks, 1));
+  size_t off = 0;
+  for (int l = 0; l < D.nlev; ++l) {
+    TailLevel& L = D.lv[l];
+    if (L.lds) continue;
+    DenseOf<T>::point(L, scratch.p + off, scratch.p + off + L.n, scratch.p + off + 2 * (size_t)L.n);
+    off += 3 * (size_t)L.n;
+  }
+  DVec<TailDesc> dd(1);
+  copy_h2d(dd.p, &D, 1, s);
+  C.resize((size_t)n0 * n0);
+  DenseOf<T>::part(H).resize((size_t)dense_chunks(n0) * n0);
+  tail_dense<T>(dd.p, n0, blocks, C.p, gstride, s);
+  sync(s);  // D, dd and scratch are temporaries
+}
+
 void run_cycle64(pcamg_ctx* c, Hierarchy& H, const double* b, double* x, int gamma) {
   hipStream_t s = c->s;
+  if (gamma > 1) ensure_dense<double>(c, H);
   const int32_t n = c->n;
   if (!c->P.use_graphs) {
     cycle64(c, H, 0, b, x, gamma);
@@ -539,6 +597,7 @@ void run_cycle64(pcamg_ctx* c, Hierarchy& H, const double* b, double* x, int gam
 
 void run_cycle32(pcamg_ctx* c, Hierarchy& H, const float* b, float* x, int gamma) {
   hipStream_t s = c->s;
+  if (gamma > 1) ensure_dense<float>(c, H);
   const int32_t n = c->n;
   if (!c->P.use_graphs) {
     cycle32(c, H, 0, b, x, gamma);

@@ -77,6 +77,10 @@ struct Hierarchy {
   // tail: levels tail_start.. run in one workgroup launch
   int tail_start = -1;
   DVec<TailDesc> tail_desc;
+  std::unique_ptr<TailDesc> tail_host;  // host copy of the descriptor
+  // W-cycles: the two tail sub-cycles as one dense operator (column-major)
+  DVec<double> C64, dpart64;
+  DVec<float> C32, dpart32;
   std::vector<DVec<int32_t>> coff_dev;
   // captured top-level cycles (fixed input/output buffers)
   hipGraphExec_t g64v = nullptr, g64w = nullptr, g32v = nullptr, g32w = nullptr;
@@ -162,6 +166,11 @@ void run_cycle64(pcamg_ctx* c, Hierarchy& H, const double* b, double* x, int gam
 void run_cycle32(pcamg_ctx* c, Hierarchy& H, const float* b, float* x, int gamma);
 void tail_cycle64(const Hierarchy& H, const double* b, double* x, int gamma, hipStream_t s);
 void tail_cycle32(const Hierarchy& H, const float* b, float* x, int gamma, hipStream_t s);
+template <typename T>
+void tail_dense(const TailDesc* desc, int32_t n0, int blocks, T* C, size_t gstride, hipStream_t s);
+template <typename T>
+void dense_apply(int32_t n, const T* C, const T* b, T* part, T* y, hipStream_t s);
+int32_t dense_chunks(int32_t n);
 // Alg. 2 on permuted vectors.
 void approx_error(pcamg_ctx* c, int Re, const double* r, double* e, int* wcycles, int* vcycles, int* vcycles32);
 void bench_smoother(pcamg_ctx* c, int prec, int sweeps, double* ms, int64_t* launches, double* bytes);

@@ -189,52 +189,42 @@ __device__ __forceinline__ void tail_coarsest(const TailDesc& D, const double* L
   __syncthreads();
 }
 
-// Cycle from tail level 0 (b0/x0 in global memory) to the coarsest: gamma
-// recursive calls per level (one when the next level is the coarsest),
-// iteratively; bit l of `again` records that level l still owes its second
-// call (gamma <= 2).  LDS holds the vectors of a bottom run of levels (always
-// including the coarsest); level 0's are staged in and out when it is one of
-// them.
+// Stage the colour offsets and (when it fits) the coarsest factor in LDS.
 template <typename T>
-__global__ void __launch_bounds__(TAIL_THREADS) tail_kernel(const TailDesc* __restrict__ Dp, const T* __restrict__ b0,
-                                                             T* __restrict__ x0, int gamma) {
-  __shared__ double pool[TAIL_LDS_BYTES / 8];
-  __shared__ int32_t coffs[TAIL_COFF_MAX];
-  __shared__ double mu;
-  const TailDesc& D = *Dp;
-  T* V = reinterpret_cast<T*>(pool);
-  const int last = D.nlev - 1;  // coarsest, relative index
+__device__ __forceinline__ void tail_prologue(const TailDesc& D, double* pool, int32_t* coffs) {
+  const int last = D.nlev - 1;
   for (int l = 0; l < last; ++l) {
     const TailLevel& L = D.lv[l];
     const GP<int32_t> cf = gptr(L.coff);
     for (int32_t c = threadIdx.x; c <= L.ncol; c += TAIL_THREADS) coffs[L.ocoff + c] = cf[c];
-  }
-  const bool stage0 = D.lv[0].lds != 0;
-  if (stage0) {
-    const TailLevel& L = D.lv[0];
-    T* xs = V + TailOps<T>::off(L, 0);
-    T* bs = V + TailOps<T>::off(L, 1);
-    for (int32_t i = threadIdx.x; i < L.n; i += TAIL_THREADS) {
-      xs[i] = x0[i];
-      bs[i] = b0[i];
-    }
   }
   const int32_t oL = TailOps<T>::oL(D);
   if (oL >= 0) {
     const GP<double> Lg = gptr(D.L);
     for (int32_t i = threadIdx.x; i < D.cm * D.cm; i += TAIL_THREADS) pool[oL + i] = Lg[i];
   }
+}
+
+// One cycle from tail level 0 to the coarsest: gamma recursive calls per level
+// (one when the next level is the coarsest), iteratively; bit l of `again`
+// records that level l still owes its second call (gamma <= 2).  Level 0's
+// vectors are b0/x0 when they are not in LDS; the other levels outside LDS
+// use their global vectors displaced by boff elements (a per-workgroup copy).
+template <typename T>
+__device__ __forceinline__ void tail_body(const TailDesc& D, double* pool, const int32_t* coffs, GP<T> b0, GW<T> x0,
+                                          size_t boff, int gamma, double* mu) {
+  T* V = reinterpret_cast<T*>(pool);
+  const int last = D.nlev - 1;  // coarsest, relative index
+  const int32_t oL = TailOps<T>::oL(D);
   const double* Lf = oL >= 0 ? pool + oL : D.L;
   double* acc = pool + TailOps<T>::oacc(D);
-  __syncthreads();
-
   uint64_t again = 0;
   int l = 0;
   int ph = 0;  // 0: descend into l, 1: returning to l from its child
   while (l >= 0) {
     const TailLevel& L = D.lv[l];
     if (l == last) {  // the coarsest level's vectors are always in LDS
-      tail_coarsest<T>(D, Lf, V + TailOps<T>::off(L, 1), V + TailOps<T>::off(L, 0), acc, &mu);
+      tail_coarsest<T>(D, Lf, V + TailOps<T>::off(L, 1), V + TailOps<T>::off(L, 0), acc, mu);
       --l;
       ph = 1;
       continue;
@@ -252,13 +242,13 @@ __global__ void __launch_bounds__(TAIL_THREADS) tail_kernel(const TailDesc* __re
       tail_visit<T>(down, L, coff, (const T*)(V + TailOps<T>::off(L, 1)), V + TailOps<T>::off(L, 0),
                     V + TailOps<T>::off(L, 2), V + TailOps<T>::off(N, 1), V + TailOps<T>::off(N, 0), N.n);
     } else {
-      const GP<T> b = l == 0 ? gptr(b0) : (GP<T>)TailOps<T>::gb(L);
-      const GW<T> x = l == 0 ? gptr_w(x0) : TailOps<T>::gx(L);
+      const GP<T> b = l == 0 ? b0 : (GP<T>)(TailOps<T>::gb(L) + boff);
+      const GW<T> x = l == 0 ? x0 : TailOps<T>::gx(L) + boff;
+      const GW<T> r = TailOps<T>::gr(L) + boff;
       if (N.lds)
-        tail_visit<T>(down, L, coff, b, x, TailOps<T>::gr(L), V + TailOps<T>::off(N, 1), V + TailOps<T>::off(N, 0),
-                      N.n);
+        tail_visit<T>(down, L, coff, b, x, r, V + TailOps<T>::off(N, 1), V + TailOps<T>::off(N, 0), N.n);
       else
-        tail_visit<T>(down, L, coff, b, x, TailOps<T>::gr(L), TailOps<T>::gb(N), TailOps<T>::gx(N), N.n);
+        tail_visit<T>(down, L, coff, b, x, r, TailOps<T>::gb(N) + boff, TailOps<T>::gx(N) + boff, N.n);
     }
     if (down) {
       if (gamma > 1 && l + 1 < last) again |= 1ull << l;
@@ -268,10 +258,71 @@ __global__ void __launch_bounds__(TAIL_THREADS) tail_kernel(const TailDesc* __re
       --l;
     }
   }
-  if (stage0) {
-    const TailLevel& L = D.lv[0];
-    const T* xs = V + TailOps<T>::off(L, 0);
-    for (int32_t i = threadIdx.x; i < L.n; i += TAIL_THREADS) x0[i] = xs[i];
+}
+
+// One cycle of the tail on (b0, x0) in global memory.
+template <typename T>
+__global__ void __launch_bounds__(TAIL_THREADS) tail_kernel(const TailDesc* __restrict__ Dp, const T* __restrict__ b0,
+                                                             T* __restrict__ x0, int gamma) {
+  __shared__ double pool[TAIL_LDS_BYTES / 8];
+  __shared__ int32_t coffs[TAIL_COFF_MAX];
+  __shared__ double mu;
+  const TailDesc& D = *Dp;
+  T* V = reinterpret_cast<T*>(pool);
+  tail_prologue<T>(D, pool, coffs);
+  const TailLevel& L0 = D.lv[0];
+  if (L0.lds) {
+    T* xs = V + TailOps<T>::off(L0, 0);
+    T* bs = V + TailOps<T>::off(L0, 1);
+    for (int32_t i = threadIdx.x; i < L0.n; i += TAIL_THREADS) {
+      xs[i] = x0[i];
+      bs[i] = b0[i];
+    }
+  }
+  __syncthreads();
+  tail_body<T>(D, pool, coffs, gptr(b0), gptr_w(x0), 0, gamma, &mu);
+  if (L0.lds) {
+    const T* xs = V + TailOps<T>::off(L0, 0);
+    for (int32_t i = threadIdx.x; i < L0.n; i += TAIL_THREADS) x0[i] = xs[i];
+  }
+}
+
+// Columns of the operator that two consecutive W-cycles of the tail apply to
+// b from x = 0 (what the level above the tail does with gamma = 2): workgroup
+// w takes columns w, w + gridDim.x, ..., runs the two cycles on the unit
+// vector and stores x as column j of C (column-major, n0 x n0).  Tail levels
+// outside LDS use the per-workgroup copies at boff = w * gstride.
+template <typename T>
+__global__ void __launch_bounds__(TAIL_THREADS)
+    tail_dense_kernel(const TailDesc* __restrict__ Dp, T* __restrict__ C, size_t gstride) {
+  __shared__ double pool[TAIL_LDS_BYTES / 8];
+  __shared__ int32_t coffs[TAIL_COFF_MAX];
+  __shared__ double mu;
+  const TailDesc& D = *Dp;
+  T* V = reinterpret_cast<T*>(pool);
+  tail_prologue<T>(D, pool, coffs);
+  const TailLevel& L0 = D.lv[0];
+  const int32_t n0 = L0.n;
+  const size_t boff = (size_t)blockIdx.x * gstride;
+  T* xs = L0.lds ? V + TailOps<T>::off(L0, 0) : nullptr;
+  T* bs = L0.lds ? V + TailOps<T>::off(L0, 1) : nullptr;
+  const GW<T> xg = TailOps<T>::gx(L0) + boff;
+  const GW<T> bg = TailOps<T>::gb(L0) + boff;
+  for (int32_t j = blockIdx.x; j < n0; j += gridDim.x) {
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < n0; i += TAIL_THREADS) {
+      if (L0.lds) {
+        xs[i] = 0;
+        bs[i] = i == j ? (T)1 : (T)0;
+      } else {
+        xg[i] = 0;
+        bg[i] = i == j ? (T)1 : (T)0;
+      }
+    }
+    __syncthreads();
+    tail_body<T>(D, pool, coffs, (GP<T>)bg, xg, boff, 2, &mu);
+    tail_body<T>(D, pool, coffs, (GP<T>)bg, xg, boff, 2, &mu);
+    for (int32_t i = threadIdx.x; i < n0; i += TAIL_THREADS) C[(size_t)j * n0 + i] = L0.lds ? xs[i] : xg[i];
   }
 }
 
@@ -284,5 +335,53 @@ void tail_cycle32(const Hierarchy& H, const float* b, float* x, int gamma, hipSt
   tail_kernel<float><<<1, TAIL_THREADS, 0, s>>>(H.tail_desc.p, b, x, gamma);
   PCAMG_LAUNCHED();
 }
+
+template <typename T>
+void tail_dense(const TailDesc* desc, int32_t n0, int blocks, T* C, size_t gstride, hipStream_t s) {
+  tail_dense_kernel<T><<<blocks, TAIL_THREADS, 0, s>>>(desc, C, gstride);
+  PCAMG_LAUNCHED();
+}
+template void tail_dense<double>(const TailDesc*, int32_t, int, double*, size_t, hipStream_t);
+template void tail_dense<float>(const TailDesc*, int32_t, int, float*, size_t, hipStream_t);
+
+// y = C b for a column-major n x n matrix: the columns are split into chunks
+// of DENSE_CHUNK; block (row tile, chunk) writes the partial sums of its chunk
+// (fma chain in column order), and a second pass adds the chunks in order.
+constexpr int DENSE_CHUNK = 128;
+template <typename T>
+__global__ void __launch_bounds__(256) dense_part_kernel(int32_t n, const T* __restrict__ C, const T* __restrict__ b,
+                                                         T* __restrict__ part) {
+  const int32_t i = blockIdx.x * 256 + threadIdx.x;
+  const int32_t c = blockIdx.y;
+  const int32_t j0 = c * DENSE_CHUNK, j1 = min(n, j0 + DENSE_CHUNK);
+  __shared__ T bj[DENSE_CHUNK];
+  for (int32_t j = j0 + threadIdx.x; j < j1; j += 256) bj[j - j0] = b[j];
+  __syncthreads();
+  if (i >= n) return;
+  T s = 0;
+  for (int32_t j = j0; j < j1; ++j) s = fma(C[(size_t)j * n + i], bj[j - j0], s);
+  part[(size_t)c * n + i] = s;
+}
+template <typename T>
+__global__ void dense_sum_kernel(int32_t n, int32_t nchunk, const T* __restrict__ part, T* __restrict__ y) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T s = 0;
+  for (int32_t c = 0; c < nchunk; ++c) s = s + part[(size_t)c * n + i];
+  y[i] = s;
+}
+
+template <typename T>
+void dense_apply(int32_t n, const T* C, const T* b, T* part, T* y, hipStream_t s) {
+  const int32_t nchunk = (n + DENSE_CHUNK - 1) / DENSE_CHUNK;
+  dense_part_kernel<T><<<dim3((n + 255) / 256, nchunk), 256, 0, s>>>(n, C, b, part);
+  PCAMG_LAUNCHED();
+  dense_sum_kernel<T><<<(n + 255) / 256, 256, 0, s>>>(n, nchunk, part, y);
+  PCAMG_LAUNCHED();
+}
+template void dense_apply<double>(int32_t, const double*, const double*, double*, double*, hipStream_t);
+template void dense_apply<float>(int32_t, const float*, const float*, float*, float*, hipStream_t);
+
+int32_t dense_chunks(int32_t n) { return (n + DENSE_CHUNK - 1) / DENSE_CHUNK; }
 
 }  // namespace pcamg

@@ -170,9 +170,12 @@ def test_aggregate_galerkin_shorten(gpu, oracle, graph):
 
 
 def solver_for(gpu, g, b=None, **kw):
+    """Solver with per-level arrays kept; W-cycles recurse (w_dense = 0) unless
+    asked otherwise, so every cycle is the oracle's bit for bit."""
     n, rp, ci, w = g
     if b is None:
         b = I.zero_mean_normal_rhs(99, n)
+    kw.setdefault("w_dense", 0)
     return gpu.Solver(rp, ci, w, b, keep_setup=1, **kw)
 
 
@@ -314,10 +317,13 @@ def test_solve_matches_oracle(gpu, oracle, kw):
 
 
 def test_solve_3d_weighted(gpu, oracle):
+    """Default settings (dense W sub-cycle operator included): the same
+    convergence as the oracle within one iteration and one re-setup."""
     g = I.grid3d(24, 24, 24, weight_seed=1)
     b = I.zero_mean_normal_rhs(5, g[0])
-    for kw, okw in [(dict(theta=0.5), dict(theta=0.5)),
-                    (dict(outer="fcg", cycle_prec="f32", theta=0.5), dict(outer=1, cycle_prec=1, theta=0.5))]:
+    for kw, okw in [(dict(theta=0.5, w_dense=1), dict(theta=0.5)),
+                    (dict(outer="fcg", cycle_prec="f32", theta=0.5, w_dense=1),
+                     dict(outer=1, cycle_prec=1, theta=0.5))]:
         ref = oracle.solve(g, b, **okw)
         s = solver_for(gpu, g, b, **kw)
         x, st = s.solve()
@@ -380,6 +386,41 @@ def test_errors(gpu):
     s = P.Solver(g[1], g[2], g[3], b, max_iter=2, theta=1e9)
     x, st = s.solve(raise_on_noconv=False)
     assert st["status"] == -10 and st["iterations"] == 2
+
+
+@pytest.mark.parametrize("gname", ["grid3d_20", "grid2d_128"])
+def test_dense_w_cycle(gpu, oracle, gname):
+    """W-cycles with the two tail sub-cycles applied as one precomputed dense
+    operator: the same linear map as the recursion, different rounding order.
+    FP64 within 1e-12 relative, FP32 within 1e-5 relative of the recursive
+    cycle; graph replays equal the eager dense cycle bit for bit."""
+    g = I.grid3d(20, 20, 20, weight_seed=7) if gname == "grid3d_20" else I.grid2d(128, 128, weight_seed=2)
+    n = g[0]
+    b = I.zero_mean_normal_rhs(3, n)
+    x0 = I.normal(4, n)
+    rec = solver_for(gpu, g)
+    dense = solver_for(gpu, g, w_dense=1)
+    dense_eager = solver_for(gpu, g, w_dense=1, use_graphs=0)
+    H = oracle.Hierarchy(g, None)
+    assert dense.num_levels() == H.nlevels >= 4
+    w_ref = H.cycle(b, x0, 2)
+    same(host(rec.cycle(b, x0, 2)), w_ref)
+    w64 = host(dense.cycle(b, x0, 2))
+    assert np.linalg.norm(w64 - w_ref) <= 1e-12 * np.linalg.norm(w_ref)
+    assert not np.array_equal(w64, w_ref)  # the dense path is really taken
+    b32 = b.astype(np.float32)
+    w32_ref = H.cycle32(b32, None, 2)
+    w32 = host(dense.cycle32(b32, None, 2))
+    assert np.linalg.norm(w32 - w32_ref) <= 1e-5 * np.linalg.norm(w32_ref)
+    e64 = host(dense_eager.cycle(b, x0, 2))
+    e32 = host(dense_eager.cycle32(b32, None, 2))
+    for rep in range(3):
+        same(host(dense.cycle(b, x0, 2)), e64)
+        same(host(dense.cycle32(b32, None, 2)), e32)
+        dense_eager.cycle(b, None, 1)
+        torch.cuda.synchronize()
+    # V-cycles are untouched
+    same(host(dense.cycle(b, x0, 1)), H.cycle(b, x0, 1))
 
 
 @pytest.mark.parametrize("gname", ["grid3d_w", "hub"])
