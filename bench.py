@@ -6,8 +6,9 @@ log-uniform on [1e-3, 1e3], zero-mean N(0,1) right-hand side -- set up from
 scratch (validation, Laplacian, colouring, A^2 pattern, first hierarchy) and
 solved to 1e-8 relative residual by FCG(1) in FP64 with an FP32 V(1,1)-cycle
 preconditioner, re-setup when the mean convergence factor since the last
-re-setup exceeds 0.5.  Inputs are synthetic and already resident in HBM when
-the timed region starts.
+re-setup exceeds 0.5, each re-setup's error from Alg. 2 with the paper's
+numW = 2, iterW = 7, iterV = 4 (FP32 cycles).  Inputs are synthetic and
+already resident in HBM when the timed region starts.
 
 Prints one JSON line.  Also reported: the convergence factor, the FP64
 standalone V-cycle variant, the smoother's HBM roofline fraction (HIP-event
@@ -36,6 +37,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-variant", action="store_true")
     ap.add_argument("--numW", type=int, default=2, help="re-setups whose error approximation uses W-cycles (Alg. 2)")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="set up, time the finest-level smoother sweeps and a 256 MiB device copy (the reference "
+                         "kernel for counter calibration), print one JSON line and exit")
     return ap.parse_args()
 
 
@@ -78,17 +82,99 @@ def cpu_baseline(g, b, st_gpu, side, numW):
                        f"{st_gpu['wcycles']} FP32 W- and {st_gpu['vcycles64']} FP64 V-cycles")}
 
 
+SMOOTHER_SWEEPS = 20
+
+
+def smoother_roofline(s):
+    """HIP-event timed symmetric multicoloured GS sweeps on the finest level
+    (same kernels and launch configuration as inside the cycles), FP32 and
+    FP64: algorithmic bytes per launch and GB/s."""
+    import ctypes as C
+
+    from paper_1806_07028_amd import _lib
+    roof = {}
+    for prec, name in ((1, "f32"), (0, "f64")):
+        msv, nl, by = C.c_double(), C.c_int64(), C.c_double()
+        _lib.check(_lib.lib().pcamg_bench_smoother(s.h, prec, SMOOTHER_SWEEPS, C.byref(msv), C.byref(nl), C.byref(by)))
+        gbs = by.value / (msv.value * 1e-3) / 1e9
+        roof[name] = {"gbs": gbs, "ms": msv.value, "launches": nl.value, "bytes": by.value}
+    return roof
+
+
+def kernel_source_digest():
+    """Digest of the sources the finest-level smoother kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("paper_1806_07028_amd/csrc/rowchain.hpp", "paper_1806_07028_amd/csrc/basic.hip"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gs_kernel_f32_128cube_hbm_traffic.md")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the finest-level FP32 smoother pass, from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by the same
+    counters on a copy of known size); None when the kernel sources changed
+    since the counters were taken or no such record exists."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_digest") != kernel_source_digest():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def roofline_only(args):
+    """Setup, smoother sweeps and a 256 MiB device-to-device copy."""
+    import torch
+
+    import paper_1806_07028_amd as P
+    from paper_1806_07028_amd import inputs as I
+    dev = torch.device("cuda", 0)
+    g, b = I.config2(side=args.side)
+    n, rp, ci, w = g
+    s = P.Solver(*(torch.as_tensor(a, device=dev) for a in (rp, ci, w)), torch.as_tensor(b, device=dev),
+                 outer="fcg", cycle_prec="f32", theta=0.5)
+    roof = smoother_roofline(s)
+    src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    r32 = roof["f32"]
+    print(json.dumps({"kernel": "gs_kernel<float, 1>", "launches": r32["launches"],
+                      "avg_launch_us": 1e3 * r32["ms"] / r32["launches"],
+                      "bytes_per_launch": r32["bytes"] / r32["launches"], "gbs": r32["gbs"],
+                      "f64_gbs": roof["f64"]["gbs"], "copy_bytes": 2 * src.numel() * 4, "copies": 3,
+                      "source_digest": kernel_source_digest()}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is described "
               "but not built", file=sys.stderr)
         sys.exit(2)
+    if args.roofline_only:
+        roofline_only(args)
+        return
     import numpy as np
     import torch
 
     import paper_1806_07028_amd as P
-    from paper_1806_07028_amd import _lib
     from paper_1806_07028_amd import inputs as I
 
     assert torch.cuda.is_available(), "needs a GPU"
@@ -135,19 +221,11 @@ def main():
     L = L - sp.diags(np.asarray(L.sum(axis=1)).ravel())
     host_relres = float(np.linalg.norm(b - L @ xh) / np.linalg.norm(b))
 
-    # smoother roofline: HIP-event timed multicoloured GS sweeps on the finest level,
-    # same kernels and launch configuration as inside the cycles
-    import ctypes as C
-    roof = {}
-    for prec, name in ((1, "f32"), (0, "f64")):
-        msv, nl, by = C.c_double(), C.c_int64(), C.c_double()
-        _lib.check(_lib.lib().pcamg_bench_smoother(s.h, prec, 20, C.byref(msv), C.byref(nl), C.byref(by)))
-        gbs = by.value / (msv.value * 1e-3) / 1e9
-        roof[name] = {"gbs": gbs, "ms": msv.value, "launches": nl.value, "bytes": by.value}
+    roof = smoother_roofline(s)
     r32 = roof["f32"]
     roofline = {"bound": "hbm", "achieved": round(r32["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(r32["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "gs_kernel<float> (finest-level multicolour Gauss-Seidel pass)",
+                "frac": round(r32["gbs"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+                "kernel": "gs_kernel<float, 1> (finest-level multicolour Gauss-Seidel pass, one thread per row)",
                 "avg_launch_us": round(1e3 * r32["ms"] / r32["launches"], 2),
                 "bytes_per_launch": round(r32["bytes"] / r32["launches"]),
                 "f64_gbs": round(roof["f64"]["gbs"], 1)}
