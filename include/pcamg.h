@@ -153,6 +153,20 @@ pcamg_status pcamg_rebuild(pcamg_ctx* c, const double* e);
 
 void pcamg_destroy(pcamg_ctx* c);
 
+/* Batched setup and solve of independent graphs (the batching extension;
+ * per graph exactly Alg. 5 as pcamg_setup + pcamg_solve).  A pool of
+ * `workers` host threads (1..64), each with its own HIP stream of default
+ * priority, takes the graphs largest first; each graph is set up, solved and
+ * released on its worker's stream, so x[g] and stats[g] equal those of the
+ * individual calls bit for bit.  graphs[count]: device CSR as for
+ * pcamg_setup; rhs[g]: device [n_g] (must sum to 0); x[g]: device [n_g],
+ * initial guess in, solution out; stats: host [count] or NULL (each entry's
+ * relres_hist/hist_cap are used as in pcamg_solve; status holds the graph's
+ * own result).  Returns PCAMG_OK if every graph converged, else the status of
+ * the lowest-numbered failing graph (the others are still solved). */
+pcamg_status pcamg_batch_solve(const pcamg_graph* graphs, const double* const* rhs, double* const* x, int32_t count,
+                               const pcamg_params* p, int32_t workers, pcamg_stats* stats);
+
 /* ------------------------------------------------------------------------
  * Hierarchy access (inspection and stage tests)
  * ------------------------------------------------------------------------ */

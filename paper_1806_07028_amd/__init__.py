@@ -18,7 +18,7 @@ import torch
 from . import _lib
 from ._lib import PcamgError, default_params, lib
 
-__all__ = ["Solver", "PcamgError", "lib", "default_params", "stages"]
+__all__ = ["Solver", "batch_solve", "PcamgError", "lib", "default_params", "stages"]
 
 _OUTER = {"vcycle": 0, "fcg": 1}
 _PREC = {"f64": 0, "f32": 1}
@@ -162,6 +162,39 @@ class Solver:
         e = torch.empty(self.n, dtype=torch.float64, device="cuda")
         _lib.check(lib().pcamg_initial_error(self.h, _ptr(e)))
         return e
+
+
+def batch_solve(graphs, rhs, x0=None, workers: int = 4, raise_on_error: bool = True, **params):
+    """Set up and solve many independent graphs (pcamg_batch_solve): graphs is a
+    list of (row_ptr, col_idx, weight), rhs a list of right-hand sides.
+    Returns (list of solutions, list of statistics dicts)."""
+    count = len(graphs)
+    p = _params(params)
+    keep = []
+    garr = (_lib.Graph * max(count, 1))()
+    barr = (C.c_void_p * max(count, 1))()
+    xarr = (C.c_void_p * max(count, 1))()
+    xs = []
+    hists = []
+    starr = (_lib.Stats * max(count, 1))()
+    for g, ((rp, ci, w), b) in enumerate(zip(graphs, rhs)):
+        rp, ci, w, b = _dev(rp, torch.int32), _dev(ci, torch.int32), _dev(w, torch.float64), _dev(b, torch.float64)
+        n = rp.numel() - 1
+        x = torch.zeros(n, dtype=torch.float64, device="cuda") if x0 is None else _dev(x0[g], torch.float64).clone()
+        keep += [rp, ci, w, b]
+        xs.append(x)
+        garr[g] = _lib.Graph(n, ci.numel(), _ptr(rp), _ptr(ci), _ptr(w))
+        barr[g] = _ptr(b)
+        xarr[g] = _ptr(x)
+        hist = np.zeros(p.max_iter + 2)
+        hists.append(hist)
+        starr[g].relres_hist = hist.ctypes.data_as(C.POINTER(C.c_double))
+        starr[g].hist_cap = p.max_iter + 2
+    torch.cuda.synchronize()  # inputs are read on the library's own streams
+    status = lib().pcamg_batch_solve(garr, barr, xarr, count, C.byref(p), workers, starr)
+    if status != 0 and raise_on_error:
+        _lib.check(status)
+    return xs, [_lib.stats_dict(starr[g], hists[g]) for g in range(count)]
 
 
 from . import stages  # noqa: E402

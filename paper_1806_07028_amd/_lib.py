@@ -102,6 +102,8 @@ _SIGS = {
     "pcamg_solve": ([_p, _p, C.POINTER(Stats)], _i32),
     "pcamg_rebuild": ([_p, _p], _i32),
     "pcamg_destroy": ([_p], None),
+    "pcamg_batch_solve": ([C.POINTER(Graph), C.POINTER(_p), C.POINTER(_p), _i32, C.POINTER(Params), _i32,
+                           C.POINTER(Stats)], _i32),
     "pcamg_num_hierarchies": ([_p, C.POINTER(_i32)], _i32),
     "pcamg_num_levels": ([_p, _i32, C.POINTER(_i32)], _i32),
     "pcamg_level_info": ([_p, _i32, _i32, C.POINTER(_i64)], _i32),

@@ -136,6 +136,73 @@ __global__ void __launch_bounds__(JP_SMALL_THREADS)
   if (threadIdx.x == 0) *rounds_out = rounds;
 }
 
+// Greedy first-fit in descending (priority, id) order, one vertex at a time with
+// the neighbour scan spread over the workgroup -- the same colouring as the
+// Jones-Plassmann rounds (a vertex's already coloured neighbours are exactly
+// its higher-priority ones).  For small near-dense levels, where the rounds
+// degenerate to about one vertex each.
+constexpr int32_t SEQ_MAX = 8192;
+__global__ void __launch_bounds__(1024)
+    greedy_seq_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                      const uint64_t* __restrict__ prio, int32_t* __restrict__ colour) {
+  __shared__ uint64_t key[SEQ_MAX];
+  __shared__ int32_t id[SEQ_MAX];
+  __shared__ int32_t col[SEQ_MAX];
+  __shared__ uint32_t used[SEQ_MAX / 32];
+  __shared__ int32_t pick;
+  int32_t N = 1;
+  while (N < n) N <<= 1;
+  for (int32_t i = threadIdx.x; i < N; i += blockDim.x) {
+    key[i] = i < n ? prio[i] : 0ull;
+    id[i] = i < n ? i : -1;
+    if (i < n) col[i] = -1;
+  }
+  for (int32_t w = threadIdx.x; w < SEQ_MAX / 32; w += blockDim.x) used[w] = 0u;
+  if (threadIdx.x == 0) pick = INT32_MAX;
+  __syncthreads();
+  // bitonic sort, first = highest (priority, id)
+  for (int32_t k = 2; k <= N; k <<= 1) {
+    for (int32_t j = k >> 1; j > 0; j >>= 1) {
+      for (int32_t i = threadIdx.x; i < N; i += blockDim.x) {
+        const int32_t l = i ^ j;
+        if (l > i) {
+          const bool first_before = key[i] > key[l] || (key[i] == key[l] && id[i] > id[l]);
+          const bool up = (i & k) == 0;
+          if (up ? !first_before : first_before) {
+            const uint64_t tk = key[i];
+            key[i] = key[l];
+            key[l] = tk;
+            const int32_t ti = id[i];
+            id[i] = id[l];
+            id[l] = ti;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int32_t t = 0; t < n; ++t) {
+    const int32_t v = id[t];
+    for (int32_t k = rp[v] + threadIdx.x; k < rp[v + 1]; k += blockDim.x) {
+      const int32_t cu = col[ci[k]];
+      if (cu >= 0) atomicOr(&used[cu >> 5], 1u << (cu & 31));
+    }
+    __syncthreads();
+    for (int32_t w = threadIdx.x; w < SEQ_MAX / 32; w += blockDim.x) {
+      const uint32_t fr = ~used[w];
+      if (fr) atomicMin(&pick, w * 32 + __ffs((int)fr) - 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      col[v] = pick;
+      pick = INT32_MAX;
+    }
+    for (int32_t w = threadIdx.x; w < SEQ_MAX / 32; w += blockDim.x) used[w] = 0u;
+    __syncthreads();
+  }
+  for (int32_t i = threadIdx.x; i < n; i += blockDim.x) colour[i] = col[i];
+}
+
 // One round over a worklist of uncoloured vertices; the ones still uncoloured
 // go to the next list (in any order: the colouring does not depend on it).
 __global__ void __launch_bounds__(256)
@@ -187,7 +254,11 @@ int32_t colour_jp(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed
   DVec<uint64_t> prio(n);
   jp_prio_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, seed, lvl, prio.p);
   PCAMG_LAUNCHED();
-  if (n <= JP_SMALL_MAX) {
+  const int64_t nnz = n > 0 ? (int64_t)read_scalar(rp + n, s) : 0;
+  if (n <= SEQ_MAX && nnz > 64ll * n) {  // near-dense: one vertex per round
+    greedy_seq_kernel<<<1, 1024, 0, s>>>(n, rp, ci, prio.p, colour);
+    PCAMG_LAUNCHED();
+  } else if (n <= JP_SMALL_MAX) {
     DVec<int32_t> rounds(1);
     jp_small_kernel<<<1, JP_SMALL_THREADS, 0, s>>>(n, rp, ci, prio.p, colour, rounds.p);
     PCAMG_LAUNCHED();

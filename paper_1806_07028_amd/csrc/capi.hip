@@ -1,8 +1,11 @@
 // C ABI of the library (declared in include/pcamg.h).  Every entry point
 // catches exceptions and returns a status; the message is kept per thread.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <thread>
+#include <vector>
 
 #include "solver.hpp"
 
@@ -30,6 +33,13 @@ pcamg_status guarded(F&& f) {
 }
 
 hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+// the same, with the thread's allocations tagged to stream s
+template <typename F>
+pcamg_status guarded_s(hipStream_t s, F&& f) {
+  StreamScope scope(s);
+  return guarded(std::forward<F>(f));
+}
 
 // ---------------------------------------------------------------------------
 // Graph validation (the paper's preprocessing, Sec. 4.3): no self loops,
@@ -213,7 +223,7 @@ pcamg_status pcamg_params_default(pcamg_params* p) {
 
 pcamg_status pcamg_setup(const pcamg_graph* g, const double* rhs, const pcamg_params* p, void* stream,
                          pcamg_ctx** out) {
-  return guarded([&] {
+  return guarded_s(as_stream(stream), [&] {
     require(g && p && out, PCAMG_EINVAL, "null argument");
     *out = nullptr;
     require(p->row_lanes == 0 || p->row_lanes == 1 || p->row_lanes == 4 || p->row_lanes == 16 ||
@@ -241,7 +251,7 @@ pcamg_status pcamg_setup(const pcamg_graph* g, const double* rhs, const pcamg_pa
 }
 
 pcamg_status pcamg_set_rhs(pcamg_ctx* c, const double* rhs) {
-  return guarded([&] {
+  return guarded_s(c ? c->s : nullptr, [&] {
     require(c && rhs, PCAMG_EINVAL, "null argument");
     validate_rhs(rhs, c->n, c->s);
     c->rhs.resize(c->n);
@@ -251,14 +261,14 @@ pcamg_status pcamg_set_rhs(pcamg_ctx* c, const double* rhs) {
 }
 
 pcamg_status pcamg_solve(pcamg_ctx* c, double* x, pcamg_stats* st) {
-  return guarded([&] {
+  return guarded_s(c ? c->s : nullptr, [&] {
     require(c && x, PCAMG_EINVAL, "null argument");
     pcamg::solve(c, x, st);
   });
 }
 
 pcamg_status pcamg_rebuild(pcamg_ctx* c, const double* e) {
-  return guarded([&] {
+  return guarded_s(c ? c->s : nullptr, [&] {
     require(c, PCAMG_EINVAL, "null context");
     DVec<double> eb(c->n);
     if (e) {
@@ -274,28 +284,101 @@ pcamg_status pcamg_rebuild(pcamg_ctx* c, const double* e) {
 void pcamg_destroy(pcamg_ctx* c) {
   if (!c) return;
   try {
-    (void)hipStreamSynchronize(c->s);
-    delete c;
+    hipStream_t s = c->s;
+    (void)hipStreamSynchronize(s);
+    {
+      StreamScope scope(s);
+      delete c;
+    }
+    dev_cache_idle(s);  // everything enqueued on s has completed
   } catch (...) {
   }
 }
 
-pcamg_status pcamg_num_hierarchies(pcamg_ctx* c, int32_t* count) {
+// ---------------------------------------------------------------------------
+// Batches of independent graphs: a pool of host threads, each with its own
+// stream, takes graphs largest first and runs setup + solve on each exactly as
+// the single-graph entry points do.
+// ---------------------------------------------------------------------------
+pcamg_status pcamg_batch_solve(const pcamg_graph* graphs, const double* const* rhs, double* const* x, int32_t count,
+                               const pcamg_params* p, int32_t workers, pcamg_stats* stats) {
   return guarded([&] {
+    require(p && count >= 0 && workers >= 1 && workers <= 64, PCAMG_EINVAL, "bad argument");
+    if (count == 0) return;
+    require(graphs && rhs && x, PCAMG_EINVAL, "null argument");
+    int dev = 0;
+    PCAMG_HIP(hipGetDevice(&dev));
+    std::vector<int32_t> order(count);
+    for (int32_t g = 0; g < count; ++g) order[g] = g;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+      return (int64_t)graphs[a].nnz + graphs[a].n > (int64_t)graphs[b].nnz + graphs[b].n;
+    });
+    std::atomic<int32_t> next{0};
+    std::vector<pcamg_status> status(count, PCAMG_OK);
+    std::vector<std::string> msg(count);
+    auto worker = [&]() {
+      hipStream_t s = nullptr;
+      if (hipSetDevice(dev) != hipSuccess || hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        s = nullptr;
+      }
+      for (;;) {
+        const int32_t k = next.fetch_add(1);
+        if (k >= count) break;
+        const int32_t g = order[k];
+        if (!s) {
+          status[g] = PCAMG_EHIP;
+          msg[g] = "could not create a stream";
+          continue;
+        }
+        pcamg_ctx* c = nullptr;
+        pcamg_status r = pcamg_setup(&graphs[g], rhs[g], p, s, &c);
+        pcamg_stats local{};
+        pcamg_stats* so = stats ? &stats[g] : &local;
+        if (r == PCAMG_OK) {
+          r = pcamg_solve(c, x[g], so);
+        } else if (stats) {
+          pcamg_stats keep = stats[g];
+          std::memset(so, 0, sizeof(*so));
+          so->relres_hist = keep.relres_hist;
+          so->hist_cap = keep.hist_cap;
+        }
+        so->status = r;
+        if (r != PCAMG_OK) msg[g] = pcamg_last_error();
+        status[g] = r;
+        pcamg_destroy(c);
+      }
+      if (s) {
+        (void)hipStreamSynchronize(s);
+        dev_cache_idle(s);
+        (void)hipStreamDestroy(s);
+      }
+    };
+    std::vector<std::thread> pool;
+    const int32_t nw = std::min(workers, count);
+    for (int32_t w = 0; w < nw; ++w) pool.emplace_back(worker);
+    for (auto& t : pool) t.join();
+    for (int32_t g = 0; g < count; ++g)
+      if (status[g] != PCAMG_OK) throw Error(status[g], "graph " + std::to_string(g) + ": " + msg[g]);
+  });
+}
+
+pcamg_status pcamg_num_hierarchies(pcamg_ctx* c, int32_t* count) {
+  return guarded_s(c ? c->s : nullptr, [&] {
     require(c && count, PCAMG_EINVAL, "null argument");
     *count = (int32_t)c->hist.size();
   });
 }
 
 pcamg_status pcamg_num_levels(pcamg_ctx* c, int32_t h, int32_t* levels) {
-  return guarded([&] {
+  return guarded_s(c ? c->s : nullptr, [&] {
     require(levels, PCAMG_EINVAL, "null argument");
     *levels = (int32_t)hier(c, h).lv.size();
   });
 }
 
 pcamg_status pcamg_level_info(pcamg_ctx* c, int32_t h, int32_t level, int64_t* info) {
-  return guarded([&] {
+  return guarded_s(c ? c->s : nullptr, [&] {
     Hierarchy& H = hier(c, h);
     require(info && level >= 0 && level < (int32_t)H.lv.size(), PCAMG_EINVAL, "level out of range");
     std::memcpy(info, H.lv[level].info.data(), 16 * sizeof(int64_t));
@@ -303,7 +386,7 @@ pcamg_status pcamg_level_info(pcamg_ctx* c, int32_t h, int32_t level, int64_t* i
 }
 
 pcamg_status pcamg_level_get(pcamg_ctx* c, int32_t h, int32_t level, const char* name, void* out) {
-  return guarded([&] {
+  return guarded_s(c ? c->s : nullptr, [&] {
     Hierarchy& H = hier(c, h);
     require(out && name && level >= 0 && level < (int32_t)H.lv.size(), PCAMG_EINVAL, "bad argument");
     require(!H.setup.empty(), PCAMG_EINVAL, "level arrays need keep_setup = 1");
@@ -338,7 +421,7 @@ pcamg_status pcamg_level_get(pcamg_ctx* c, int32_t h, int32_t level, const char*
 }
 
 pcamg_status pcamg_cycle(pcamg_ctx* c, int32_t h, const double* b, double* x, int32_t gamma) {
-  return guarded([&] {
+  return guarded_s(c ? c->s : nullptr, [&] {
     Hierarchy& H = hier(c, h);
     require(b && x && gamma >= 1 && gamma <= 2, PCAMG_EINVAL, "bad argument");
     const int32_t n = c->n;
@@ -352,7 +435,7 @@ pcamg_status pcamg_cycle(pcamg_ctx* c, int32_t h, const double* b, double* x, in
 }
 
 pcamg_status pcamg_cycle32(pcamg_ctx* c, int32_t h, const float* b, float* x, int32_t gamma) {
-  return guarded([&] {
+  return guarded_s(c ? c->s : nullptr, [&] {
     Hierarchy& H = hier(c, h);
     require(b && x && gamma >= 1 && gamma <= 2, PCAMG_EINVAL, "bad argument");
     const int32_t n = c->n;
@@ -366,7 +449,7 @@ pcamg_status pcamg_cycle32(pcamg_ctx* c, int32_t h, const float* b, float* x, in
 }
 
 pcamg_status pcamg_approx_error(pcamg_ctx* c, int32_t count, const double* r, double* e) {
-  return guarded([&] {
+  return guarded_s(c ? c->s : nullptr, [&] {
     require(c && r && e && count >= 1 && count <= (int32_t)c->hist.size(), PCAMG_EINVAL, "bad argument");
     const int32_t n = c->n;
     DVec<double> rp(n), ep(n);
@@ -379,14 +462,14 @@ pcamg_status pcamg_approx_error(pcamg_ctx* c, int32_t count, const double* r, do
 
 pcamg_status pcamg_bench_smoother(pcamg_ctx* c, int32_t prec, int32_t sweeps, double* ms, int64_t* launches,
                                   double* bytes) {
-  return guarded([&] {
+  return guarded_s(c ? c->s : nullptr, [&] {
     require(c && ms && launches && bytes && sweeps >= 1, PCAMG_EINVAL, "bad argument");
     bench_smoother(c, prec, sweeps, ms, launches, bytes);
   });
 }
 
 pcamg_status pcamg_initial_error(pcamg_ctx* c, double* e) {
-  return guarded([&] {
+  return guarded_s(c ? c->s : nullptr, [&] {
     require(c && e, PCAMG_EINVAL, "null argument");
     initial_error(c, 0, e);
     PCAMG_HIP(hipStreamSynchronize(c->s));
@@ -398,7 +481,7 @@ pcamg_status pcamg_initial_error(pcamg_ctx* c, double* e) {
 // ---------------------------------------------------------------------------
 pcamg_status pcamg_laplacian(int32_t n, const int32_t* rp, const int32_t* ci, const double* w, double* aval,
                              double* d, double* dinv, void* stream) {
-  return guarded([&] {
+  return guarded_s(as_stream(stream), [&] {
     require(n >= 0 && rp && d && dinv, PCAMG_EINVAL, "null argument");
     laplacian(n, rp, w, aval, d, dinv, 0, as_stream(stream));
     PCAMG_HIP(hipStreamSynchronize(as_stream(stream)));
@@ -407,7 +490,7 @@ pcamg_status pcamg_laplacian(int32_t n, const int32_t* rp, const int32_t* ci, co
 
 pcamg_status pcamg_colour(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed, int32_t level,
                           int32_t* colour, int32_t* ncolours, void* stream) {
-  return guarded([&] {
+  return guarded_s(as_stream(stream), [&] {
     require(n >= 0 && rp && colour && ncolours, PCAMG_EINVAL, "null argument");
     *ncolours = colour_jp(n, rp, ci, seed, level, colour, as_stream(stream));
   });
@@ -416,7 +499,7 @@ pcamg_status pcamg_colour(int32_t n, const int32_t* rp, const int32_t* ci, uint6
 pcamg_status pcamg_gs(int32_t n, const int32_t* rp, const int32_t* ci, const double* aval, const double* dinv,
                       const int32_t* colour, int32_t ncolours, const double* b, double* x, int32_t forward,
                       int32_t count, void* stream) {
-  return guarded([&] {
+  return guarded_s(as_stream(stream), [&] {
     require(n > 0 && rp && colour && b && x && ncolours >= 1, PCAMG_EINVAL, "bad argument");
     hipStream_t s = as_stream(stream);
     DVec<int32_t> perm(n), iperm(n);
@@ -434,7 +517,7 @@ pcamg_status pcamg_gs(int32_t n, const int32_t* rp, const int32_t* ci, const dou
 
 pcamg_status pcamg_residual(int32_t n, const int32_t* rp, const int32_t* ci, const double* aval, const double* d,
                             const double* b, const double* x, double* r, void* stream) {
-  return guarded([&] {
+  return guarded_s(as_stream(stream), [&] {
     require(n >= 0 && rp && d && b && x && r, PCAMG_EINVAL, "null argument");
     residual<double>(n, rp, ci, aval, d, b, x, r, as_stream(stream));
     PCAMG_HIP(hipStreamSynchronize(as_stream(stream)));
@@ -443,7 +526,7 @@ pcamg_status pcamg_residual(int32_t n, const int32_t* rp, const int32_t* ci, con
 
 pcamg_status pcamg_a2_count(int32_t n, const int32_t* rp, const int32_t* ci, int32_t hub_cap, int32_t* rp2,
                             int64_t* nnz2, void* stream) {
-  return guarded([&] {
+  return guarded_s(as_stream(stream), [&] {
     require(n > 0 && rp && rp2 && nnz2 && hub_cap >= 0, PCAMG_EINVAL, "bad argument");
     *nnz2 = a2_count(n, rp, ci, hub_cap, rp2, as_stream(stream));
   });
@@ -451,7 +534,7 @@ pcamg_status pcamg_a2_count(int32_t n, const int32_t* rp, const int32_t* ci, int
 
 pcamg_status pcamg_a2_fill(int32_t n, const int32_t* rp, const int32_t* ci, int32_t hub_cap, const int32_t* rp2,
                            int32_t* ci2, void* stream) {
-  return guarded([&] {
+  return guarded_s(as_stream(stream), [&] {
     require(n > 0 && rp && rp2 && ci2, PCAMG_EINVAL, "null argument");
     a2_fill(n, rp, ci, hub_cap, rp2, ci2, as_stream(stream));
     PCAMG_HIP(hipStreamSynchronize(as_stream(stream)));
@@ -460,7 +543,7 @@ pcamg_status pcamg_a2_fill(int32_t n, const int32_t* rp, const int32_t* ci, int3
 
 pcamg_status pcamg_sort_edges(int32_t n, const int32_t* rp2, const int32_t* ci2, const double* e, int32_t* su,
                               int32_t* sv, void* stream) {
-  return guarded([&] {
+  return guarded_s(as_stream(stream), [&] {
     require(n > 0 && rp2 && ci2 && e && su && sv, PCAMG_EINVAL, "null argument");
     hipStream_t s = as_stream(stream);
     const int32_t nnz2 = read_scalar(rp2 + n, s);
@@ -479,7 +562,7 @@ pcamg_status pcamg_sort_edges(int32_t n, const int32_t* rp2, const int32_t* ci2,
 
 pcamg_status pcamg_path_cover(int32_t n, int32_t m, const int32_t* su, const int32_t* sv, int32_t* nb,
                               void* stream) {
-  return guarded([&] {
+  return guarded_s(as_stream(stream), [&] {
     require(n > 0 && m >= 0 && nb && (m == 0 || (su && sv)), PCAMG_EINVAL, "bad argument");
     path_cover(n, m, su, sv, nb, as_stream(stream));
     PCAMG_HIP(hipStreamSynchronize(as_stream(stream)));
@@ -488,7 +571,7 @@ pcamg_status pcamg_path_cover(int32_t n, int32_t m, const int32_t* su, const int
 
 pcamg_status pcamg_orient(int32_t n, const int32_t* nb, int32_t* path_id, int32_t* pos, int32_t* plen,
                           void* stream) {
-  return guarded([&] {
+  return guarded_s(as_stream(stream), [&] {
     require(n > 0 && nb && path_id && pos && plen, PCAMG_EINVAL, "null argument");
     orient_paths(n, nb, path_id, pos, plen, as_stream(stream));
     PCAMG_HIP(hipStreamSynchronize(as_stream(stream)));
@@ -498,7 +581,7 @@ pcamg_status pcamg_orient(int32_t n, const int32_t* nb, int32_t* path_id, int32_
 pcamg_status pcamg_aggregate(int32_t n, const int32_t* grp, const int32_t* gci, const double* gw,
                              const double* gkey, const int32_t* nb, int32_t* agg, int32_t* nc, int32_t* stats,
                              void* stream) {
-  return guarded([&] {
+  return guarded_s(as_stream(stream), [&] {
     require(n > 0 && grp && gw && nb && agg && nc, PCAMG_EINVAL, "null argument");
     hipStream_t s = as_stream(stream);
     DVec<int32_t> pid(n), pos(n), plen(n), moff(n + 1), mem(n);
@@ -532,7 +615,7 @@ void members_from_agg(int32_t n, int32_t nc, const int32_t* agg, DVec<int32_t>& 
 
 pcamg_status pcamg_galerkin_count(int32_t n, const int32_t* rp, const int32_t* ci, int32_t nc,
                                   const int32_t* agg, int32_t* rpc, int64_t* nnzc, void* stream) {
-  return guarded([&] {
+  return guarded_s(as_stream(stream), [&] {
     require(n > 0 && nc > 0 && rp && agg && rpc && nnzc, PCAMG_EINVAL, "bad argument");
     hipStream_t s = as_stream(stream);
     DVec<int32_t> moff, mem;
@@ -544,7 +627,7 @@ pcamg_status pcamg_galerkin_count(int32_t n, const int32_t* rp, const int32_t* c
 pcamg_status pcamg_galerkin_fill(int32_t n, const int32_t* rp, const int32_t* ci, const double* aval,
                                  const double* d, int32_t nc, const int32_t* agg, const double* pval,
                                  const int32_t* rpc, int32_t* cic, double* vc, double* dc, void* stream) {
-  return guarded([&] {
+  return guarded_s(as_stream(stream), [&] {
     require(n > 0 && nc > 0 && rp && d && agg && rpc && dc, PCAMG_EINVAL, "bad argument");
     hipStream_t s = as_stream(stream);
     DVec<int32_t> moff, mem;
@@ -557,7 +640,7 @@ pcamg_status pcamg_galerkin_fill(int32_t n, const int32_t* rp, const int32_t* ci
 
 pcamg_status pcamg_shorten(int32_t n, const int32_t* nb, int32_t nc, const int32_t* agg, int32_t* nbc,
                            void* stream) {
-  return guarded([&] {
+  return guarded_s(as_stream(stream), [&] {
     require(n > 0 && nc > 0 && nb && agg && nbc, PCAMG_EINVAL, "null argument");
     hipStream_t s = as_stream(stream);
     DVec<int32_t> pid(n), pos(n), plen(n);

@@ -39,11 +39,20 @@ inline void require(bool ok, pcamg_status code, const std::string& msg) {
 }
 
 // ---------------------------------------------------------------------------
-// Device memory: a size-bucketed cache so rebuilds reuse allocations.
+// Device memory: a size-bucketed cache so rebuilds reuse allocations.  Blocks
+// freed while a StreamScope is active are reused only on that stream.
 // ---------------------------------------------------------------------------
 void* dev_alloc(size_t bytes);
 void dev_free(void* p);
-void dev_cache_release();  // return cached blocks to the runtime
+void dev_cache_release();             // return cached blocks to the runtime
+void dev_cache_idle(hipStream_t s);   // s is synchronised: its blocks may serve any stream
+struct StreamScope {                  // the stream this thread's allocations belong to
+  explicit StreamScope(hipStream_t s);
+  ~StreamScope();
+  StreamScope(const StreamScope&) = delete;
+  StreamScope& operator=(const StreamScope&) = delete;
+  hipStream_t prev;
+};
 
 template <typename T>
 struct DVec {

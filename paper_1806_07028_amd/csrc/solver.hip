@@ -304,6 +304,7 @@ std::unique_ptr<Hierarchy> build_hierarchy(pcamg_ctx* c, const double* e_nat) {
     if (H->tail_start >= 0) {
       TailDesc D;
       std::memset(&D, 0, sizeof(D));
+      D.dense_rel = -1;
       D.nlev = nl - H->tail_start;
       D.cn = H->cn;
       D.cm = H->cm;
@@ -326,7 +327,10 @@ std::unique_ptr<Hierarchy> build_hierarchy(pcamg_ctx* c, const double* e_nat) {
         T.n = A.n;
         T.ncol = A.ncol;
         T.lds = l >= first_lds ? 1 : 0;
-        T.lanes = 1;  // one workgroup: one thread per row measured fastest
+        // one workgroup: one thread per row measured fastest for rows of up to
+        // ~50 entries (grid hierarchies); the near-dense coarse rows of
+        // power-law graphs take 16 lanes per row
+        T.lanes = (double)A.nnz > 48.0 * std::max(A.n, 1) ? 16 : 1;
         if (T.lds) {
           for (int j = 0; j < 3; ++j) {
             T.o64[j] = o64 + j * A.n;
@@ -538,22 +542,20 @@ struct DenseOf<double> {
   static DVec<double>& C(Hierarchy& H) { return H.C64; }
   static DVec<double>& part(Hierarchy& H) { return H.dpart64; }
   static void point(TailLevel& T, double* x, double* b, double* r) { T.x = x, T.b = b, T.r = r; }
+  static void inner(TailDesc& D, const double* C) { D.C64 = C; }
 };
 template <>
 struct DenseOf<float> {
   static DVec<float>& C(Hierarchy& H) { return H.C32; }
   static DVec<float>& part(Hierarchy& H) { return H.dpart32; }
   static void point(TailLevel& T, float* x, float* b, float* r) { T.x32 = x, T.b32 = b, T.r32 = r; }
+  static void inner(TailDesc& D, const float* C) { D.C32 = C; }
 };
 
+// Columns of the dense operator for the tail described by D (levels rel..),
+// into C (n0 x n0); tail levels outside LDS get per-workgroup copies.
 template <typename T>
-void ensure_dense(pcamg_ctx* c, Hierarchy& H) {
-  const int nl = (int)H.lv.size();
-  if (!c->P.w_dense || H.tail_start < 1 || nl - H.tail_start < 2 || !H.tail_host) return;
-  DVec<T>& C = DenseOf<T>::C(H);
-  if (C.p) return;
-  hipStream_t s = c->s;
-  TailDesc D = *H.tail_host;
+void dense_columns(TailDesc D, T* C, hipStream_t s) {
   const int32_t n0 = D.lv[0].n;
   size_t gstride = 0;
   for (int l = 0; l < D.nlev; ++l)
@@ -569,10 +571,46 @@ void ensure_dense(pcamg_ctx* c, Hierarchy& H) {
   }
   DVec<TailDesc> dd(1);
   copy_h2d(dd.p, &D, 1, s);
+  tail_dense<T>(dd.p, n0, blocks, C, gstride, s);
+  sync(s);  // D, dd and scratch are temporaries
+}
+
+// A tail level below which the dense construction nests a smaller dense
+// operator: the first level of at most DENSE_INNER_MAX vertices with at least
+// two levels under it.
+constexpr int32_t DENSE_INNER_MAX = 1024;
+
+template <typename T>
+void ensure_dense(pcamg_ctx* c, Hierarchy& H) {
+  const int nl = (int)H.lv.size();
+  if (!c->P.w_dense || H.tail_start < 1 || nl - H.tail_start < 2 || !H.tail_host) return;
+  DVec<T>& C = DenseOf<T>::C(H);
+  if (C.p) return;
+  hipStream_t s = c->s;
+  TailDesc D = *H.tail_host;
+  const int32_t n0 = D.lv[0].n;
+  int inner = -1;
+  if (n0 > DENSE_INNER_MAX)
+    for (int l = 1; l + 2 < D.nlev; ++l)
+      if (D.lv[l].n <= DENSE_INNER_MAX) {
+        inner = l;
+        break;
+      }
+  DVec<T> Cin;
+  if (inner > 0) {  // the inner operator first, on the tail from level `inner`
+    TailDesc Di = D;
+    Di.nlev = D.nlev - inner;
+    for (int l = 0; l < Di.nlev; ++l) Di.lv[l] = D.lv[l + inner];
+    Di.dense_rel = -1;
+    const int32_t ni = Di.lv[0].n;
+    Cin.resize((size_t)ni * ni);
+    dense_columns<T>(Di, Cin.p, s);
+    D.dense_rel = inner;
+    DenseOf<T>::inner(D, Cin.p);
+  }
   C.resize((size_t)n0 * n0);
   DenseOf<T>::part(H).resize((size_t)dense_chunks(n0) * n0);
-  tail_dense<T>(dd.p, n0, blocks, C.p, gstride, s);
-  sync(s);  // D, dd and scratch are temporaries
+  dense_columns<T>(D, C.p, s);
 }
 
 void run_cycle64(pcamg_ctx* c, Hierarchy& H, const double* b, double* x, int gamma) {

@@ -54,7 +54,7 @@ constexpr int LDLT_MAX = 4096;
 constexpr int TAIL_LDS_BYTES = 128 * 1024;
 constexpr int TAIL_COFF_MAX = 2048;
 struct TailLevel {
-  int32_t n, ncol, lds, ocoff, lanes;  // lanes per row: 1 or 4
+  int32_t n, ncol, lds, ocoff, lanes;  // lanes per row: 1 or 16
   int32_t o64[3], o32[3];  // x, b, r in LDS (lds = 1)
   const int32_t *coff, *rp, *ci, *agg, *moff, *mem;
   const double *av, *d, *dinv, *pval;
@@ -68,6 +68,11 @@ struct TailDesc {
   int32_t oacc64, oacc32;  // accumulator offsets (doubles) in the two layouts
   int32_t oL64, oL32;      // factor L offsets (doubles), -1 = read from global memory
   int32_t ncoff;
+  // optional inner dense operator (construction of a dense tail operator only):
+  // at relative level dense_rel the two W sub-cycles are one product with C
+  int32_t dense_rel;
+  const double* C64;
+  const float* C32;
   const double *L, *D;
   TailLevel lv[TAIL_MAX_LEVELS];
 };

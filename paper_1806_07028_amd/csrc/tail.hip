@@ -38,6 +38,7 @@ struct TailOps<double> {
   __device__ static int32_t off(const TailLevel& L, int j) { return L.o64[j]; }
   __device__ static int32_t oacc(const TailDesc& D) { return D.oacc64; }
   __device__ static int32_t oL(const TailDesc& D) { return D.oL64; }
+  __device__ static GP<double> C(const TailDesc& D) { return gptr(D.C64); }
 };
 template <>
 struct TailOps<float> {
@@ -51,12 +52,13 @@ struct TailOps<float> {
   __device__ static int32_t off(const TailLevel& L, int j) { return L.o32[j]; }
   __device__ static int32_t oacc(const TailDesc& D) { return D.oacc32; }
   __device__ static int32_t oL(const TailDesc& D) { return D.oL32; }
+  __device__ static GP<float> C(const TailDesc& D) { return gptr(D.C32); }
 };
 
 // One Gauss-Seidel sweep over the colours of a level (forward or backward), G
-// lanes per row (1 or 4).  The vector pointer types carry the address space
+// lanes per row (1 or 16).  The vector pointer types carry the address space
 // (LDS or global), so each combination compiles to direct LDS or global
-// accesses.  With G = 4 all threads take part in every pass (uniform bounds),
+// accesses.  With G > 1 all threads take part in every pass (uniform bounds),
 // as row_chain_g requires.
 template <typename T, int G, typename PB, typename PX>
 __device__ __forceinline__ void tail_gs_g(const TailLevel& L, const int32_t* coff, PB b, PX x, bool forward) {
@@ -113,16 +115,18 @@ __device__ __forceinline__ void tail_res_g(const TailLevel& L, PB b, PX x, PR r)
 template <typename T, typename PB, typename PX>
 __device__ __forceinline__ void tail_gs(const TailLevel& L, const int32_t* coff, PB b, PX x, bool forward) {
   if (L.lanes == 1) tail_gs_g<T, 1>(L, coff, b, x, forward);
-  else tail_gs_g<T, 4>(L, coff, b, x, forward);
+  else tail_gs_g<T, 16>(L, coff, b, x, forward);
 }
 
-// pre-smoothing, residual, restriction; the child's x starts at zero
+// pre-smoothing, residual, restriction; the child's x starts at zero, or, with
+// a dense operator Cd (nc x nc, column-major), is Cd times the restricted
+// right-hand side (fma chain over the columns in order).
 template <typename T, typename PB, typename PX, typename PR, typename PBC, typename PXC>
 __device__ __forceinline__ void tail_down(const TailLevel& L, const int32_t* coff, PB b, PX x, PR r, PBC bc, PXC xc,
-                                          int32_t nc) {
+                                          int32_t nc, GP<T> Cd) {
   tail_gs<T>(L, coff, b, x, true);
   if (L.lanes == 1) tail_res_g<T, 1>(L, b, x, r);
-  else tail_res_g<T, 4>(L, b, x, r);
+  else tail_res_g<T, 16>(L, b, x, r);
   const GP<T> pv = TailOps<T>::pval(L);
   const GP<int32_t> moff = gptr(L.moff), mem = gptr(L.mem);
   for (int32_t q = threadIdx.x; q < nc; q += TAIL_THREADS) {
@@ -135,6 +139,14 @@ __device__ __forceinline__ void tail_down(const TailLevel& L, const int32_t* cof
     xc[q] = 0;
   }
   __syncthreads();
+  if (Cd) {
+    for (int32_t i = threadIdx.x; i < nc; i += TAIL_THREADS) {
+      T s = 0;
+      for (int32_t j = 0; j < nc; ++j) s = fma(Cd[(size_t)j * nc + i], bc[j], s);
+      xc[i] = s;
+    }
+    __syncthreads();
+  }
 }
 
 // prolongation, post-smoothing
@@ -149,8 +161,8 @@ __device__ __forceinline__ void tail_up(const TailLevel& L, const int32_t* coff,
 
 template <typename T, typename PB, typename PX, typename PR, typename PBC, typename PXC>
 __device__ __forceinline__ void tail_visit(bool down, const TailLevel& L, const int32_t* coff, PB b, PX x, PR r,
-                                           PBC bc, PXC xc, int32_t nc) {
-  if (down) tail_down<T>(L, coff, b, x, r, bc, xc, nc);
+                                           PBC bc, PXC xc, int32_t nc, GP<T> Cd) {
+  if (down) tail_down<T>(L, coff, b, x, r, bc, xc, nc, Cd);
   else tail_up<T>(L, coff, b, x, xc);
 }
 
@@ -238,19 +250,25 @@ __device__ __forceinline__ void tail_body(const TailDesc& D, double* pool, const
     const TailLevel& N = D.lv[l + 1];
     const int32_t* coff = coffs + L.ocoff;
     const bool down = ph == 0;
+    // both sub-cycles of the child at once through the inner dense operator
+    const bool dense = down && gamma > 1 && l + 1 == D.dense_rel && l + 1 < last;
+    const GP<T> Cd = dense ? TailOps<T>::C(D) : (GP<T>)nullptr;
     if (L.lds) {
       tail_visit<T>(down, L, coff, (const T*)(V + TailOps<T>::off(L, 1)), V + TailOps<T>::off(L, 0),
-                    V + TailOps<T>::off(L, 2), V + TailOps<T>::off(N, 1), V + TailOps<T>::off(N, 0), N.n);
+                    V + TailOps<T>::off(L, 2), V + TailOps<T>::off(N, 1), V + TailOps<T>::off(N, 0), N.n, Cd);
     } else {
       const GP<T> b = l == 0 ? b0 : (GP<T>)(TailOps<T>::gb(L) + boff);
       const GW<T> x = l == 0 ? x0 : TailOps<T>::gx(L) + boff;
       const GW<T> r = TailOps<T>::gr(L) + boff;
       if (N.lds)
-        tail_visit<T>(down, L, coff, b, x, r, V + TailOps<T>::off(N, 1), V + TailOps<T>::off(N, 0), N.n);
+        tail_visit<T>(down, L, coff, b, x, r, V + TailOps<T>::off(N, 1), V + TailOps<T>::off(N, 0), N.n, Cd);
       else
-        tail_visit<T>(down, L, coff, b, x, r, TailOps<T>::gb(N) + boff, TailOps<T>::gx(N) + boff, N.n);
+        tail_visit<T>(down, L, coff, b, x, r, TailOps<T>::gb(N) + boff, TailOps<T>::gx(N) + boff, N.n, Cd);
     }
-    if (down) {
+    if (dense) {  // stay at l as if returning from the child's second call
+      again &= ~(1ull << l);
+      ph = 1;
+    } else if (down) {
       if (gamma > 1 && l + 1 < last) again |= 1ull << l;
       else again &= ~(1ull << l);
       ++l;

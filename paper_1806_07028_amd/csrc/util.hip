@@ -1,6 +1,7 @@
 // Fills, prefix sums, deterministic reductions, compaction and a stable LSD
 // radix sort for gfx950 (wave64).
 #include <algorithm>
+#include <map>
 #include <mutex>
 
 #include "internal.hpp"
@@ -8,14 +9,19 @@
 namespace pcamg {
 
 // ---------------------------------------------------------------------------
-// Device memory cache.  Blocks are bucketed to 1/8-octave sizes and kept for
-// reuse; every context works on a single stream, so a block freed on the host
-// after its last use was enqueued is safe to hand out again on that stream.
+// Device memory cache.  Blocks are bucketed to 1/16-octave sizes and kept for
+// reuse.  A freed block is tagged with the stream the freeing thread works on
+// (StreamScope): work enqueued on that stream may still use it, so it is
+// handed out again only on the same stream, where later work is ordered after
+// that use.  Blocks of a stream the caller has synchronised return to a
+// shared pool (dev_cache_idle).
 // ---------------------------------------------------------------------------
 namespace {
 std::mutex g_mem_mu;
-std::multimap<size_t, void*> g_free;
+const hipStream_t kIdle = reinterpret_cast<hipStream_t>(~uintptr_t(0));
+std::multimap<std::pair<hipStream_t, size_t>, void*> g_free;
 std::map<void*, size_t> g_size;
+thread_local hipStream_t tl_stream = nullptr;
 
 size_t bucket(size_t bytes) {
   if (bytes <= 4096) return 4096;
@@ -26,15 +32,20 @@ size_t bucket(size_t bytes) {
 }
 }  // namespace
 
+StreamScope::StreamScope(hipStream_t s) : prev(tl_stream) { tl_stream = s; }
+StreamScope::~StreamScope() { tl_stream = prev; }
+
 void* dev_alloc(size_t bytes) {
   size_t b = bucket(bytes);
   {
     std::lock_guard<std::mutex> lk(g_mem_mu);
-    auto it = g_free.find(b);
-    if (it != g_free.end()) {
-      void* p = it->second;
-      g_free.erase(it);
-      return p;
+    for (hipStream_t tag : {tl_stream, kIdle}) {
+      auto it = g_free.find({tag, b});
+      if (it != g_free.end()) {
+        void* p = it->second;
+        g_free.erase(it);
+        return p;
+      }
     }
   }
   void* p = nullptr;
@@ -58,7 +69,19 @@ void dev_free(void* p) {
   std::lock_guard<std::mutex> lk(g_mem_mu);
   auto it = g_size.find(p);
   if (it == g_size.end()) return;
-  g_free.insert({it->second, p});
+  g_free.insert({{tl_stream, it->second}, p});
+}
+
+void dev_cache_idle(hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_mem_mu);
+  for (auto it = g_free.begin(); it != g_free.end();) {
+    if (it->first.first == s) {
+      g_free.insert({{kIdle, it->first.second}, it->second});
+      it = g_free.erase(it);
+    } else {
+      ++it;
+    }
+  }
 }
 
 void dev_cache_release() {

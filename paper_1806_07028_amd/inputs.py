@@ -338,3 +338,29 @@ def config2(seed: int = 1, side: int = 128):
     """side^3 7-point grid, log-uniform weights on [1e-3, 1e3], zero-mean N(0,1) rhs."""
     g = grid3d(side, side, side, weight_seed=seed, lo=-3.0, hi=3.0)
     return g, zero_mean_normal_rhs(seed + 1000, g[0])
+
+
+def config4(seed: int = 1, count: int = 512, n_lo: float = 1e3, n_hi: float = 2e5):
+    """Batch of `count` graphs of uneven size: n_g log-uniform on [n_lo, n_hi];
+    type by an equal-probability draw among a 2D grid (nx = round(sqrt(n)),
+    ny = round(n / nx)), a random geometric graph in the unit square with mean
+    degree 8 (largest component) and a Barabasi-Albert graph (m = 4); edge
+    weights 10^(-2 + 4u); zero-mean N(0,1) right-hand side per graph.
+    Returns a list of (graph, rhs, kind)."""
+    u = uniform(seed * 7 + 3, 2 * count)
+    out = []
+    for g in range(count):
+        n = int(round(np.exp(np.log(n_lo) + u[2 * g] * np.log(n_hi / n_lo))))
+        kind = ("grid", "rgg", "ba")[min(2, int(u[2 * g + 1] * 3))]
+        s = seed * 1_000_003 + 17 * g
+        if kind == "grid":
+            nx = max(2, int(round(np.sqrt(n))))
+            ny = max(2, int(round(n / nx)))
+            nv, a, b = grid2d_edges(nx, ny)
+        elif kind == "rgg":
+            nv, a, b = rgg_edges(n, s)
+        else:
+            nv, a, b = ba_edges(n, s)
+        gr = csr_from_edges(nv, a, b, log_uniform_weights(s + 1, len(a), -2.0, 2.0))
+        out.append((gr, zero_mean_normal_rhs(s + 2, nv), kind))
+    return out

@@ -445,3 +445,98 @@ def test_graph_and_tail_equal_eager(gpu, gname):
         same(host(fused.cycle(b, x0, 2)), ref2)
         same(host(fused.cycle32(b.astype(np.float32))), ref32)
         same(host(fused.cycle32(b.astype(np.float32), None, 2)), ref32w)
+
+
+def test_batch_equals_individual(gpu, oracle):
+    """Batched setup + solve of uneven graphs on four worker streams: every
+    graph's solution and statistics equal its own single-graph solve bit for
+    bit, on a first and a second batch (the second reuses cached memory across
+    streams); the small graphs also match the oracle's counts."""
+    batch = I.config4(seed=3, count=12, n_lo=400, n_hi=20000)
+    graphs = [(g[1], g[2], g[3]) for g, b, k in batch]
+    rhs = [b for g, b, k in batch]
+    ref = []
+    for (g, b, k) in batch:
+        s = gpu.Solver(g[1], g[2], g[3], b)
+        x, st = s.solve()
+        ref.append((host(x), st))
+        s.close()
+    for rep in range(2):
+        xs, sts = gpu.batch_solve(graphs, rhs, workers=4)
+        for i, ((xr, sr), x, st) in enumerate(zip(ref, xs, sts)):
+            same(host(x), xr)
+            for key in ("iterations", "rebuilds", "levels", "status"):
+                assert st[key] == sr[key], (i, key)
+            assert st["true_relres"] <= 1.0001e-8
+    for (g, b, k), (xr, sr) in zip(batch, ref):
+        if g[0] <= 3000:
+            o = oracle.solve(g, b)
+            assert o.stats["iterations"] == sr["iterations"] and o.stats["rebuilds"] == sr["rebuilds"]
+
+
+def test_batch_errors(gpu):
+    """A disconnected graph fails on its own (its status), the others are solved."""
+    batch = I.config4(seed=5, count=5, n_lo=300, n_hi=3000)
+    graphs = [(g[1], g[2], g[3]) for g, b, k in batch]
+    rhs = [b for g, b, k in batch]
+    n2, a2, b2 = I.grid2d_edges(4, 4)
+    bad = I.csr_from_edges(32, np.concatenate([a2, a2 + 16]), np.concatenate([b2, b2 + 16]), np.ones(2 * len(a2)))
+    graphs.insert(2, (bad[1], bad[2], bad[3]))
+    rhs.insert(2, I.zero_mean_normal_rhs(1, 32))
+    xs, sts = gpu.batch_solve(graphs, rhs, workers=3, raise_on_error=False)
+    assert sts[2]["status"] == -6
+    for i, st in enumerate(sts):
+        if i != 2:
+            assert st["status"] == 0 and st["true_relres"] <= 1.0001e-8
+    import paper_1806_07028_amd as P
+    with pytest.raises(P.PcamgError) as ei:
+        gpu.batch_solve(graphs, rhs, workers=2)
+    assert ei.value.status == -6
+    xs, sts = gpu.batch_solve([], [], workers=2)
+    assert xs == [] and sts == []
+
+
+def test_colour_dense_levels(gpu, oracle):
+    """Near-dense small graphs take the one-vertex-at-a-time greedy kernel;
+    sparse ones of the same size the Jones-Plassmann rounds: both equal the
+    oracle's first-fit in priority order."""
+    S = gpu.stages
+    cases = []
+    n = 300  # complete graph
+    a, b = np.triu_indices(n, 1)
+    cases.append(I.csr_from_edges(n, a, b, np.ones(len(a))))
+    n = 2500  # random dense graph, mean degree ~150
+    u = I.uniform(77, 2 * 190000)
+    a = np.minimum((u[0::2] * n).astype(np.int64), n - 1)
+    b = np.minimum((u[1::2] * n).astype(np.int64), n - 1)
+    m = a != b
+    a2, b2 = I.canonical_edges(a[m], b[m])
+    cases.append(I.csr_from_edges(n, a2, b2, np.ones(len(a2))))
+    cases.append(I.grid2d(50, 50))  # sparse, same size range
+    for g in cases:
+        n, rp, ci, w = g
+        for level in (0, 3):
+            col, nc = S.colour(rp, ci, 0xC010, level)
+            rcol, rnc = oracle.colour(n, rp, ci, 0xC010, level)
+            assert nc == rnc
+            same(host(col), rcol)
+
+
+def test_dense_w_cycle_nested(gpu, oracle):
+    """A tail whose first level exceeds the inner size: the dense operator is
+    built with an inner dense operator nested in its columns' sub-cycles; still
+    the W-cycle up to rounding (FP64 1e-12, FP32 1e-5 relative)."""
+    g = I.grid3d(24, 24, 16, weight_seed=11)
+    n = g[0]
+    b = I.zero_mean_normal_rhs(3, n)
+    s = solver_for(gpu, g, w_dense=1)
+    H = oracle.Hierarchy(g, None)
+    sizes = [s.level_info(l)["n"] for l in range(s.num_levels())]
+    assert any(1024 < m <= 6144 for m in sizes) and any(m <= 1024 for m in sizes)
+    w_ref = H.cycle(b, None, 2)
+    w64 = host(s.cycle(b, None, 2))
+    assert np.linalg.norm(w64 - w_ref) <= 1e-12 * np.linalg.norm(w_ref)
+    b32 = b.astype(np.float32)
+    w32_ref = H.cycle32(b32, None, 2)
+    w32 = host(s.cycle32(b32, None, 2))
+    assert np.linalg.norm(w32 - w32_ref) <= 1e-5 * np.linalg.norm(w32_ref)

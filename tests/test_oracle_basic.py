@@ -247,3 +247,18 @@ def test_gs32_close_to_gs64(oracle):
     x32 = oracle.gs32(n, rp, ci, a.astype(np.float32), dinv.astype(np.float32), col, nc, b.astype(np.float32),
                       np.zeros(n, np.float32), True)
     assert np.abs(x32 - x64).max() <= 1e-5 * np.abs(x64).max()
+
+
+def test_batch_workload_recipe():
+    """The uneven batch: sizes within the log-uniform range (up to the
+    rounding of the grid sides and the largest RGG component), all three kinds,
+    connected graphs, zero-mean right-hand sides."""
+    batch = I.config4(seed=2, count=30, n_lo=200, n_hi=4000)
+    kinds = {k for g, b, k in batch}
+    assert kinds == {"grid", "rgg", "ba"}
+    for g, b, k in batch:
+        n, rp, ci, w = g
+        assert 100 <= n <= 4200 and len(b) == n and abs(b.sum()) < 1e-9
+        assert np.all(w >= 1e-2) and np.all(w <= 1e2)
+        n_lcc, _, _, keep = I.largest_component(n, *I.upper_edges(rp, ci))
+        assert n_lcc == n and keep.all()
