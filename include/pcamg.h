@@ -49,6 +49,7 @@ enum {
 };
 
 typedef struct pcamg_ctx pcamg_ctx;
+typedef struct pcamg_net pcamg_net;  /* learned smooth-error network (extension) */
 
 typedef struct {
   int32_t n;                /* vertices */
@@ -92,6 +93,8 @@ typedef struct {
   int32_t w_dense;         /* 1 = in W-cycles, the two sub-cycles below the tail's first level are
                               applied as one precomputed dense operator (equal up to rounding
                               order; built on first use per hierarchy and precision); 0 = recurse */
+  int32_t first_sweeps;    /* symmetric sweeps before the first build: -1 = relax_sweeps; with
+                              pcamg_setup_learned the sweeps of the network's input (-1: 2) */
   uint64_t seed;           /* start-vector stream */
   uint64_t colour_seed;    /* colouring priority stream */
 } pcamg_params;
@@ -217,6 +220,60 @@ pcamg_status pcamg_bench_smoother(pcamg_ctx* c, int32_t prec, int32_t sweeps, do
 /* Smooth error of the first build: start vector of build 0 (SplitMix64
  * stream p->seed) and relax_sweeps symmetric sweeps on A e = 0. device [n]. */
 pcamg_status pcamg_initial_error(pcamg_ctx* c, double* e);
+
+/* ------------------------------------------------------------------------
+ * Learned smooth-error proposals (extension).  The path cover orders edges by
+ * |e_i - e_j| of a smooth error e (Alg. 4, Step 2; Sec. 3.2); a three-layer
+ * message-passing network maps a vector relaxed by two sweeps to a smoother
+ * one, in place of the first build's relaxation:
+ *   u = normalise(e2) (mean 0, RMS 1), l = log d - mean(log d), Ahat = D^-1 W,
+ *   F = [u, Ahat u, l, Ahat l];  h0 = relu(F W0 + b0);
+ *   h_k = relu(bf16([h_{k-1} | Ahat h_{k-1}]) bf16(W_k) + b_k), k = 1..3;
+ *   y = h3 wo + bo + u;  loss = 0.5 mean((y - normalise(t))^2).
+ * Hidden width 64; parameters (float32, host order) W0 [4][64], b0 [64],
+ * then for k = 1..3 W_k [128][64] and b_k [64], then wo [64], bo [1].  The
+ * hidden-layer products and their backward products use bf16 MFMA with float32
+ * accumulation; sums over nodes are ordered, so results are reproducible.
+ * ------------------------------------------------------------------------ */
+
+/* Number of float32 parameters (25,153). */
+int32_t pcamg_net_num_params(void);
+
+/* New network (parameters unset). Owns device memory until pcamg_net_destroy. */
+pcamg_status pcamg_net_create(pcamg_net** out);
+void pcamg_net_destroy(pcamg_net* net);
+
+/* Parameters from / to host float32 [pcamg_net_num_params()]; setting them
+ * also resets the Adam state. */
+pcamg_status pcamg_net_set_params(pcamg_net* net, const float* theta, void* stream);
+pcamg_status pcamg_net_get_params(pcamg_net* net, float* theta, void* stream);
+
+/* Forward pass: y (device float [n]) from the graph (as for pcamg_setup) and
+ * the relaxed vector e2 (device double [n], natural order). */
+pcamg_status pcamg_net_forward(pcamg_net* net, const pcamg_graph* g, const double* e2, float* y, void* stream);
+
+/* Loss against target t (device double [n]; any scale and offset) and its
+ * gradient, kept in the network for pcamg_net_adam_step and copied to grad
+ * (host float [num_params]) when grad is not NULL; *loss on the host. */
+pcamg_status pcamg_net_loss_grad(pcamg_net* net, const pcamg_graph* g, const double* e2, const double* target,
+                                 double* loss, float* grad, void* stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with the
+ * last gradient. */
+pcamg_status pcamg_net_adam_step(pcamg_net* net, float lr, void* stream);
+
+/* The start vector of the first build: SplitMix64 xi (stream p->seed, build 0)
+ * relaxed by `sweeps` symmetric multicolour Gauss-Seidel sweeps on A e = 0
+ * (Sec. 3.2), device double [n], natural order. */
+pcamg_status pcamg_start_vector(const pcamg_graph* g, const pcamg_params* p, int32_t sweeps, double* e,
+                                void* stream);
+
+/* pcamg_setup with the first hierarchy built from the network's proposal for
+ * the start vector relaxed by p->first_sweeps sweeps (-1: 2); re-setups as in
+ * Alg. 5 (the measured convergence factor decides, the relaxation stays the
+ * fallback). */
+pcamg_status pcamg_setup_learned(const pcamg_graph* g, const double* rhs, const pcamg_params* p, pcamg_net* net,
+                                 void* stream, pcamg_ctx** out);
 
 /* ------------------------------------------------------------------------
  * Stage entry points: single steps of the method on caller arrays (device

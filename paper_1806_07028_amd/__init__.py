@@ -18,7 +18,7 @@ import torch
 from . import _lib
 from ._lib import PcamgError, default_params, lib
 
-__all__ = ["Solver", "batch_solve", "PcamgError", "lib", "default_params", "stages"]
+__all__ = ["Solver", "batch_solve", "PcamgError", "lib", "default_params", "stages", "learned"]
 
 _OUTER = {"vcycle": 0, "fcg": 1}
 _PREC = {"f64": 0, "f32": 1}
@@ -63,7 +63,8 @@ def _dev(a, dtype) -> torch.Tensor:
 class Solver:
     """One graph Laplacian: setup on construction (first hierarchy), then solve."""
 
-    def __init__(self, row_ptr, col_idx, weight, rhs=None, **params):
+    def __init__(self, row_ptr, col_idx, weight, rhs=None, net=None, **params):
+        """net: a learned.Net whose proposal replaces the first build's relaxation."""
         self.row_ptr = _dev(row_ptr, torch.int32)
         self.col_idx = _dev(col_idx, torch.int32)
         self.weight = _dev(weight, torch.float64)
@@ -72,7 +73,11 @@ class Solver:
         g = _lib.Graph(self.n, self.col_idx.numel(), _ptr(self.row_ptr), _ptr(self.col_idx), _ptr(self.weight))
         self.rhs = None if rhs is None else _dev(rhs, torch.float64)
         h = C.c_void_p()
-        _lib.check(lib().pcamg_setup(C.byref(g), _ptr(self.rhs), C.byref(self.p), _stream(), C.byref(h)))
+        if net is None:
+            _lib.check(lib().pcamg_setup(C.byref(g), _ptr(self.rhs), C.byref(self.p), _stream(), C.byref(h)))
+        else:
+            _lib.check(lib().pcamg_setup_learned(C.byref(g), _ptr(self.rhs), C.byref(self.p), net.h, _stream(),
+                                                 C.byref(h)))
         self.h = h
 
     def close(self):
@@ -197,4 +202,4 @@ def batch_solve(graphs, rhs, x0=None, workers: int = 4, raise_on_error: bool = T
     return xs, [_lib.stats_dict(starr[g], hists[g]) for g in range(count)]
 
 
-from . import stages  # noqa: E402
+from . import learned, stages  # noqa: E402

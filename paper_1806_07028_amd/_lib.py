@@ -48,6 +48,7 @@ class Params(C.Structure):
         ("use_graphs", _i32),
         ("row_lanes", _i32),
         ("w_dense", _i32),
+        ("first_sweeps", _i32),
         ("seed", _u64),
         ("colour_seed", _u64),
     ]
@@ -102,6 +103,16 @@ _SIGS = {
     "pcamg_solve": ([_p, _p, C.POINTER(Stats)], _i32),
     "pcamg_rebuild": ([_p, _p], _i32),
     "pcamg_destroy": ([_p], None),
+    "pcamg_net_num_params": ([], _i32),
+    "pcamg_net_create": ([C.POINTER(_p)], _i32),
+    "pcamg_net_destroy": ([_p], None),
+    "pcamg_net_set_params": ([_p, _p, _p], _i32),
+    "pcamg_net_get_params": ([_p, _p, _p], _i32),
+    "pcamg_net_forward": ([_p, C.POINTER(Graph), _p, _p, _p], _i32),
+    "pcamg_net_loss_grad": ([_p, C.POINTER(Graph), _p, _p, C.POINTER(C.c_double), _p, _p], _i32),
+    "pcamg_net_adam_step": ([_p, C.c_float, _p], _i32),
+    "pcamg_start_vector": ([C.POINTER(Graph), C.POINTER(Params), _i32, _p, _p], _i32),
+    "pcamg_setup_learned": ([C.POINTER(Graph), _p, C.POINTER(Params), _p, _p, C.POINTER(_p)], _i32),
     "pcamg_batch_solve": ([C.POINTER(Graph), C.POINTER(_p), C.POINTER(_p), _i32, C.POINTER(Params), _i32,
                            C.POINTER(Stats)], _i32),
     "pcamg_num_hierarchies": ([_p, C.POINTER(_i32)], _i32),

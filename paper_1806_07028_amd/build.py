@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libpcamg.so")
-SOURCES = ["util.hip", "basic.hip", "setup.hip", "coarse.hip", "layout.hip", "tail.hip", "solver.hip", "capi.hip"]
+SOURCES = ["util.hip", "basic.hip", "setup.hip", "coarse.hip", "layout.hip", "tail.hip", "solver.hip", "learned.hip",
+           "capi.hip"]
 ARCH = "gfx950"
 
 

@@ -216,37 +216,126 @@ pcamg_status pcamg_params_default(pcamg_params* p) {
   p->use_graphs = 1;
   p->row_lanes = 0;
   p->w_dense = 1;
+  p->first_sweeps = -1;
   p->seed = 0x5EED;
   p->colour_seed = 0xC010;
   return PCAMG_OK;
 }
 
+namespace {
+// Shared by pcamg_setup and pcamg_setup_learned: context, right-hand side, and
+// the first hierarchy from e_first (natural order), or from the relaxed start
+// vector when e_first is null.
+void setup_impl(const pcamg_graph* g, const double* rhs, const pcamg_params* p, void* stream, pcamg_ctx** out,
+                pcamg_net* net) {
+  require(g && p && out, PCAMG_EINVAL, "null argument");
+  *out = nullptr;
+  require(p->row_lanes == 0 || p->row_lanes == 1 || p->row_lanes == 4 || p->row_lanes == 16 || p->row_lanes == 64,
+          PCAMG_EINVAL, "row_lanes must be 0, 1, 4, 16 or 64");
+  require(p->first_sweeps >= -1 && p->first_sweeps <= 1000, PCAMG_EINVAL, "first_sweeps out of range");
+  hipStream_t s = as_stream(stream);
+  if (p->validate) validate_graph(g, s);
+  require(g->n >= 1, PCAMG_EINVAL, "empty graph");
+  auto c = std::make_unique<pcamg_ctx>();
+  c->s = s;
+  ctx_init(c.get(), g, p);
+  if (rhs) {
+    validate_rhs(rhs, g->n, s);
+    c->rhs.resize(g->n);
+    copy_d2d(c->rhs.p, rhs, g->n, s);
+    c->have_rhs = true;
+  }
+  Timer t(s);
+  DVec<double> e(g->n);
+  if (net) {  // the network's proposal from first_sweeps (default 2) sweeps
+    DVec<double> e2(g->n);
+    initial_error(c.get(), 0, e2.p, p->first_sweeps >= 0 ? p->first_sweeps : 2);
+    net_forward_f64(net, g, e2.p, e.p, s);
+  } else {
+    initial_error(c.get(), 0, e.p, p->first_sweeps);
+  }
+  c->hist.push_back(build_hierarchy(c.get(), e.p));
+  c->t_build_ms = t.ms();
+  *out = c.release();
+}
+}  // namespace
+
 pcamg_status pcamg_setup(const pcamg_graph* g, const double* rhs, const pcamg_params* p, void* stream,
                          pcamg_ctx** out) {
+  return guarded_s(as_stream(stream), [&] { setup_impl(g, rhs, p, stream, out, nullptr); });
+}
+
+pcamg_status pcamg_setup_learned(const pcamg_graph* g, const double* rhs, const pcamg_params* p, pcamg_net* net,
+                                 void* stream, pcamg_ctx** out) {
   return guarded_s(as_stream(stream), [&] {
-    require(g && p && out, PCAMG_EINVAL, "null argument");
-    *out = nullptr;
-    require(p->row_lanes == 0 || p->row_lanes == 1 || p->row_lanes == 4 || p->row_lanes == 16 ||
-                p->row_lanes == 64,
-            PCAMG_EINVAL, "row_lanes must be 0, 1, 4, 16 or 64");
+    require(net, PCAMG_EINVAL, "null network");
+    setup_impl(g, rhs, p, stream, out, net);
+  });
+}
+
+pcamg_status pcamg_start_vector(const pcamg_graph* g, const pcamg_params* p, int32_t sweeps, double* e,
+                                void* stream) {
+  return guarded_s(as_stream(stream), [&] {
+    require(g && p && e && sweeps >= 0, PCAMG_EINVAL, "bad argument");
     hipStream_t s = as_stream(stream);
     if (p->validate) validate_graph(g, s);
     require(g->n >= 1, PCAMG_EINVAL, "empty graph");
-    auto c = std::make_unique<pcamg_ctx>();
-    c->s = s;
-    ctx_init(c.get(), g, p);
-    if (rhs) {
-      validate_rhs(rhs, g->n, s);
-      c->rhs.resize(g->n);
-      copy_d2d(c->rhs.p, rhs, g->n, s);
-      c->have_rhs = true;
-    }
-    Timer t(s);
-    DVec<double> e(g->n);
-    initial_error(c.get(), 0, e.p);
-    c->hist.push_back(build_hierarchy(c.get(), e.p));
-    c->t_build_ms = t.ms();
-    *out = c.release();
+    pcamg_ctx c;
+    c.s = s;
+    ctx_init(&c, g, p);
+    initial_error(&c, 0, e, sweeps);
+    PCAMG_HIP(hipStreamSynchronize(s));
+  });
+}
+
+int32_t pcamg_net_num_params(void) { return net_num_params(); }
+
+pcamg_status pcamg_net_create(pcamg_net** out) {
+  return guarded([&] {
+    require(out, PCAMG_EINVAL, "null argument");
+    net_create(out);
+  });
+}
+
+void pcamg_net_destroy(pcamg_net* net) {
+  if (net) net_destroy(net);
+}
+
+pcamg_status pcamg_net_set_params(pcamg_net* net, const float* theta, void* stream) {
+  return guarded_s(as_stream(stream), [&] {
+    require(net && theta, PCAMG_EINVAL, "null argument");
+    net_set_params(net, theta, as_stream(stream));
+  });
+}
+
+pcamg_status pcamg_net_get_params(pcamg_net* net, float* theta, void* stream) {
+  return guarded_s(as_stream(stream), [&] {
+    require(net && theta, PCAMG_EINVAL, "null argument");
+    net_get_params(net, theta, as_stream(stream));
+  });
+}
+
+pcamg_status pcamg_net_forward(pcamg_net* net, const pcamg_graph* g, const double* e2, float* y, void* stream) {
+  return guarded_s(as_stream(stream), [&] {
+    require(net && g && e2 && y && g->n >= 1, PCAMG_EINVAL, "bad argument");
+    net_forward_f32(net, g, e2, y, as_stream(stream));
+  });
+}
+
+pcamg_status pcamg_net_loss_grad(pcamg_net* net, const pcamg_graph* g, const double* e2, const double* target,
+                                 double* loss, float* grad, void* stream) {
+  return guarded_s(as_stream(stream), [&] {
+    require(net && g && e2 && target && g->n >= 1, PCAMG_EINVAL, "bad argument");
+    const double L = net_loss_grad(net, g, e2, target, grad, as_stream(stream));
+    if (loss) *loss = L;
+  });
+}
+
+pcamg_status pcamg_net_adam_step(pcamg_net* net, float lr, void* stream) {
+  return guarded_s(as_stream(stream), [&] {
+    require(net && lr > 0.0f, PCAMG_EINVAL, "bad argument");
+    net_adam(net, lr, as_stream(stream));
+    PCAMG_HIP(hipStreamSynchronize(as_stream(stream)));
   });
 }
 

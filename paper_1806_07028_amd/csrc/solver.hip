@@ -677,9 +677,9 @@ void relax_homogeneous(pcamg_ctx* c, double* e_nat, int sweeps) {
   scatter_f64(ep.p, c->M0->perm.p, e_nat, n, c->s);
 }
 
-void initial_error(pcamg_ctx* c, int32_t r, double* e_nat) {
+void initial_error(pcamg_ctx* c, int32_t r, double* e_nat, int32_t sweeps) {
   xi_fill(c->P.seed, r, nullptr, e_nat, c->n, c->s);
-  relax_homogeneous(c, e_nat, c->P.relax_sweeps);
+  relax_homogeneous(c, e_nat, sweeps < 0 ? c->P.relax_sweeps : sweeps);
 }
 
 // ---------------------------------------------------------------------------

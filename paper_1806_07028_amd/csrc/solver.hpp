@@ -162,7 +162,19 @@ void ctx_validate(pcamg_ctx* c);
 std::unique_ptr<Hierarchy> build_hierarchy(pcamg_ctx* c, const double* e_nat);
 // Relax A e = 0 with `sweeps` symmetric sweeps, natural-order device vector in place.
 void relax_homogeneous(pcamg_ctx* c, double* e_nat, int sweeps);
-void initial_error(pcamg_ctx* c, int32_t r, double* e_nat);
+void initial_error(pcamg_ctx* c, int32_t r, double* e_nat, int32_t sweeps = -1);  // sweeps < 0: relax_sweeps
+
+// learned smooth-error network (learned.hip)
+int32_t net_num_params();
+void net_create(pcamg_net** out);
+void net_destroy(pcamg_net* net);
+void net_set_params(pcamg_net* net, const float* host, hipStream_t s);
+void net_get_params(pcamg_net* net, float* host, hipStream_t s);
+void net_forward_f32(pcamg_net* net, const pcamg_graph* g, const double* e2, float* y, hipStream_t s);
+void net_forward_f64(pcamg_net* net, const pcamg_graph* g, const double* e2, double* e, hipStream_t s);
+double net_loss_grad(pcamg_net* net, const pcamg_graph* g, const double* e2, const double* target, float* grad_host,
+                     hipStream_t s);
+void net_adam(pcamg_net* net, float lr, hipStream_t s);
 // Cycles on the solve layout (level-0 vectors in permuted order).
 void cycle64(pcamg_ctx* c, Hierarchy& H, int l, const double* b, double* x, int gamma);
 void cycle32(pcamg_ctx* c, Hierarchy& H, int l, const float* b, float* x, int gamma);

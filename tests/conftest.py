@@ -19,3 +19,16 @@ def oracle():
 
     O.lib()
     return O
+
+
+@pytest.fixture(scope="session")
+def gpu():
+    """The HIP library on cuda:0 (loading fails loudly if it is not built)."""
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1806_07028_amd as P
+
+    P.lib()
+    return P

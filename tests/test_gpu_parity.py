@@ -19,16 +19,6 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-@pytest.fixture(scope="module")
-def gpu():
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
-    import paper_1806_07028_amd as P
-
-    P.lib()
-    return P
-
-
 def host(t):
     return t.detach().cpu().numpy()
 
