@@ -37,11 +37,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-variant", action="store_true")
     ap.add_argument("--numW", type=int, default=2, help="re-setups whose error approximation uses W-cycles (Alg. 2)")
-    ap.add_argument("--workload", choices=["grid3d", "batch"], default="grid3d",
+    ap.add_argument("--workload", choices=["grid3d", "batch", "learned"], default="grid3d",
                     help="grid3d: the 128^3 weighted grid (the benchmark line); batch: uneven graphs solved "
                          "together (separate JSON line)")
     ap.add_argument("--count", type=int, default=512, help="batch: number of graphs")
     ap.add_argument("--workers", type=int, default=4, help="batch: worker streams")
+    ap.add_argument("--train-count", type=int, default=64, help="learned: training graphs")
+    ap.add_argument("--epochs", type=int, default=10, help="learned: training epochs")
+    ap.add_argument("--eval-n", type=int, default=1_000_000, help="learned: vertices of the evaluation graph")
     ap.add_argument("--roofline-only", action="store_true",
                     help="set up, time the finest-level smoother sweeps and a 256 MiB device copy (the reference "
                          "kernel for counter calibration), print one JSON line and exit")
@@ -245,6 +248,80 @@ def batch_bench(args):
         "converged": sum(st["status"] == 0 for st in sts), "cpu_baseline": cpu}), flush=True)
 
 
+def learned_bench(args):
+    """Learned smooth-error proposals: train the network on random geometric
+    graphs (n log-uniform on [1e4, 1e5], mean degree 8, weights 10^(-3+6u))
+    to turn the two-sweep start vector into its twenty-sweep relaxation, then
+    solve a held-out graph (radius 1.596e-3 on eval_n points, largest
+    component) three ways: learned (2 sweeps + network), plain (3 sweeps) and
+    the ablation (2 sweeps, no network)."""
+    import numpy as np
+    import torch
+
+    import paper_1806_07028_amd as P
+    from oracle import mpnn as M
+    from paper_1806_07028_amd import inputs as I
+    from paper_1806_07028_amd import learned as L
+    params = dict(outer="fcg", cycle_prec="f32", theta=0.5)
+    u = I.uniform(4242, args.train_count)
+    pairs, nsum = [], 0
+    log(f"generating {args.train_count} training graphs")
+    for k in range(args.train_count):
+        n = int(round(np.exp(np.log(1e4) + u[k] * np.log(10.0))))
+        g = I.rgg(n, 1000 + k, lo=-3.0, hi=3.0)
+        gg = tuple(torch.as_tensor(a, device="cuda") for a in (g[1], g[2], g[3]))
+        pairs.append((gg, L.start_vector(gg, 2), L.relaxed_target(gg, 20)))
+        nsum += g[0]
+    net = L.Net(M.init_params(7))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = L.train(net, pairs, epochs=args.epochs, lr=2e-3, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    steps = args.epochs * len(pairs)
+    flops = 3 * 3 * 2 * 128 * 64 * nsum * args.epochs  # hidden-layer MFMA products, forward + backward
+    log(f"evaluation graph: {args.eval_n} points")
+    g = I.rgg(args.eval_n, 101, lo=-3.0, hi=3.0, radius=1.596e-3 * (1e6 / args.eval_n) ** 0.5)
+    gg = tuple(torch.as_tensor(a, device="cuda") for a in (g[1], g[2], g[3]))
+    b = torch.as_tensor(I.zero_mean_normal_rhs(102, g[0]), device="cuda")
+
+    def cosine(a, c):
+        a, c = M.normalise(a), M.normalise(c)
+        return float(abs(a @ c) / (np.linalg.norm(a) * np.linalg.norm(c)))
+
+    t20 = L.relaxed_target(gg, 20).cpu().numpy()
+    e2 = L.start_vector(gg, 2)
+    y = net.forward(gg, e2).cpu().numpy()
+    e3 = L.start_vector(gg, 3).cpu().numpy()
+    arms = {}
+    for name, kw in (("learned", dict(net=net)), ("plain", dict()), ("ablation_2_sweeps", dict(first_sweeps=2))):
+        for rep in range(2):  # the first run warms up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s = P.Solver(*gg, b, **kw, **params)
+            x, st = s.solve()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            s.close()
+        arms[name] = {"time_s": round(dt, 4), "iterations": st["iterations"], "rebuilds": st["rebuilds"],
+                      "rho_geo": round(st["rho_geo"], 4), "true_relres": st["true_relres"]}
+        log(f"{name}: {arms[name]}")
+    print(json.dumps({
+        "metric": "time to 1e-8 rel. residual, learned vs plain first build", "unit": "s",
+        "value": arms["learned"]["time_s"], "higher_is_better": False, "dtype": "f64+f32 (network bf16/f32)",
+        "data": "synthetic",
+        "config": {"workload": f"random geometric graph, {g[0]} vertices (largest component of {args.eval_n} "
+                               "points), weights 10^(-3+6u), zero-mean N(0,1) rhs; FCG(FP64) + FP32 cycles, "
+                               "theta 0.5, numW 2",
+                   "train_graphs": args.train_count, "train_vertices": nsum, "epochs": args.epochs},
+        "arms": arms,
+        "proxy_cosine_to_20_sweeps": {"network": round(cosine(y, t20), 4), "two_sweeps": round(cosine(e2.cpu().numpy(), t20), 4),
+                                      "three_sweeps": round(cosine(e3, t20), 4)},
+        "training": {"loss_first_epoch": round(hist[0], 5), "loss_last_epoch": round(hist[-1], 5),
+                     "seconds": round(t_train, 3), "steps": steps, "ms_per_step": round(1e3 * t_train / steps, 3),
+                     "mfma_tflops": round(flops / t_train / 1e12, 3)}}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -256,6 +333,9 @@ def main():
         return
     if args.workload == "batch":
         batch_bench(args)
+        return
+    if args.workload == "learned":
+        learned_bench(args)
         return
     import numpy as np
     import torch
