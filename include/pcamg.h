@@ -86,7 +86,7 @@ typedef struct {
   int32_t keep_setup;      /* 1 = keep per-level setup arrays for pcamg_level_get */
   int32_t validate;        /* 1 = check the graph (symmetry, weights, connectivity) in pcamg_setup */
   int32_t tail_max_n;      /* levels with at most this many vertices run as one single-workgroup
-                              launch per cycle (6144; 0 = per-step launches everywhere) */
+                              launch per cycle (2048; 0 = per-step launches everywhere) */
   int32_t use_graphs;      /* 1 = replay whole cycles from captured HIP graphs */
   int32_t row_lanes;       /* lanes per matrix row in the smoother/residual kernels: 0 = by the
                               level's mean row length, else 1, 4, 16 or 64 (results identical) */

@@ -212,7 +212,7 @@ pcamg_status pcamg_params_default(pcamg_params* p) {
   p->rebuild_rule = 0;
   p->keep_setup = 0;
   p->validate = 1;
-  p->tail_max_n = 6144;
+  p->tail_max_n = 2048;
   p->use_graphs = 1;
   p->row_lanes = 0;
   p->w_dense = 1;

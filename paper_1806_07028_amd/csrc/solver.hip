@@ -92,6 +92,87 @@ void ctx_init(pcamg_ctx* c, const pcamg_graph* g, const pcamg_params* p) {
   sync(s);
 }
 
+// Descriptor of the sub-hierarchy from level `start` to the coarsest for the
+// single-workgroup kernels.  LDS takes the vectors of the coarsest and of as
+// many levels above it as fit (FP64 layout, the larger one); the levels above
+// those keep theirs in global memory.  False if the coarsest does not fit.
+static bool make_tail_desc(Hierarchy& H, int start, TailDesc& D, hipStream_t s) {
+  const int nl = (int)H.lv.size();
+  const int64_t budget = TAIL_LDS_BYTES / 8;  // doubles
+  const int64_t fixed = (int64_t)H.cm + (H.cm <= 64 ? (int64_t)H.cm * H.cm : 0);
+  if (3 * (int64_t)H.cn + fixed > budget) return false;
+  std::memset(&D, 0, sizeof(D));
+  D.dense_rel = -1;
+  D.nlev = nl - start;
+  D.cn = H.cn;
+  D.cm = H.cm;
+  D.grounded = H.grounded ? 1 : 0;
+  D.L = H.cL.p;
+  D.D = H.cD.p;
+  int first_lds = nl - 1;
+  int64_t used = 3 * (int64_t)H.cn + fixed;
+  while (first_lds > start && used + 3 * (int64_t)H.lv[first_lds - 1].A->n <= budget) {
+    --first_lds;
+    used += 3 * (int64_t)H.lv[first_lds].A->n;
+  }
+  int32_t o64 = 0, o32 = 0, oco = 0;
+  for (int l = start; l < nl; ++l) {
+    Level& V = H.lv[l];
+    const LevelMatrix& A = *V.A;
+    TailLevel& T = D.lv[l - start];
+    T.n = A.n;
+    T.ncol = A.ncol;
+    T.lds = l >= first_lds ? 1 : 0;
+    // one workgroup: one thread per row measured fastest for rows of up to
+    // ~50 entries (grid hierarchies); the near-dense coarse rows of
+    // power-law graphs take 16 lanes per row
+    T.lanes = (double)A.nnz > 48.0 * std::max(A.n, 1) ? 16 : 1;
+    if (T.lds) {
+      for (int j = 0; j < 3; ++j) {
+        T.o64[j] = o64 + j * A.n;
+        T.o32[j] = o32 + j * A.n;
+      }
+      o64 += 3 * A.n;
+      o32 += 3 * A.n;
+    }
+    if (l + 1 < nl) {
+      T.ocoff = oco;
+      oco += A.ncol + 1;
+      if (!H.coff_dev[l].p) {
+        H.coff_dev[l].resize(A.ncol + 1);
+        copy_h2d(H.coff_dev[l].p, A.coff.data(), A.ncol + 1, s);
+      }
+      T.coff = H.coff_dev[l].p;
+    }
+    T.rp = A.rp.p;
+    T.ci = A.ci.p;
+    T.av = A.av.p;
+    T.d = A.d.p;
+    T.dinv = A.dinv.p;
+    T.av32 = A.av32.p;
+    T.d32 = A.d32.p;
+    T.dinv32 = A.dinv32.p;
+    T.agg = V.T.agg.p;
+    T.moff = V.T.moff.p;
+    T.mem = V.T.mem.p;
+    T.pval = V.T.pval.p;
+    T.pval32 = V.T.pval32.p;
+    T.x = V.x.p;
+    T.b = V.b.p;
+    T.r = V.r.p;
+    T.x32 = V.x32.p;
+    T.b32 = V.b32.p;
+    T.r32 = V.r32.p;
+  }
+  D.ncoff = oco;
+  D.oacc64 = o64;
+  D.oacc32 = (o32 + 1) / 2;
+  const bool lds_L = H.cm <= 64;
+  D.oL64 = lds_L ? D.oacc64 + H.cm : -1;
+  D.oL32 = lds_L ? D.oacc32 + H.cm : -1;
+  return true;
+}
+
 std::unique_ptr<Hierarchy> build_hierarchy(pcamg_ctx* c, const double* e_nat) {
   hipStream_t s = c->s;
   const pcamg_params& P = c->P;
@@ -285,97 +366,37 @@ std::unique_ptr<Hierarchy> build_hierarchy(pcamg_ctx* c, const double* e_nat) {
   }
   H->st0 = nat[0].st;
   // tail: the levels of at most tail_max_n vertices and the coarsest run in one
-  // workgroup launch.  LDS takes the vectors of the coarsest and of as many
-  // levels above it as fit (FP64 layout, the larger one); the levels above
-  // those keep theirs in global memory.
+  // workgroup launch (tail_desc).  W-cycles apply the two sub-cycles below the
+  // first level of at most DENSE_START_MAX vertices as one dense operator,
+  // built from the host descriptor dense_host of that sub-hierarchy.
   {
     const int32_t tail_n = c->P.tail_max_n > 0 ? c->P.tail_max_n : 0;
-    const int64_t budget = TAIL_LDS_BYTES / 8;  // doubles
-    const int64_t fixed = (int64_t)H->cm + (H->cm <= 64 ? (int64_t)H->cm * H->cm : 0);
-    const bool coarsest_fits = 3 * (int64_t)H->cn + fixed <= budget;
-    int ts = nl - 1;
-    int64_t nco = 0;
-    while (tail_n > 0 && ts > 0 && H->lv[ts - 1].A->n <= tail_n && nl - (ts - 1) <= TAIL_MAX_LEVELS &&
-           nco + H->lv[ts - 1].A->ncol + 1 <= TAIL_COFF_MAX) {
-      --ts;
-      nco += H->lv[ts].A->ncol + 1;
-    }
-    H->tail_start = (tail_n > 0 && coarsest_fits && !(ts == 0 && nl == 1)) ? ts : -1;
+    auto first_small = [&](int32_t limit) {
+      int ts = nl - 1;
+      int64_t nco = 0;
+      while (limit > 0 && ts > 0 && H->lv[ts - 1].A->n <= limit && nl - (ts - 1) <= TAIL_MAX_LEVELS &&
+             nco + H->lv[ts - 1].A->ncol + 1 <= TAIL_COFF_MAX) {
+        --ts;
+        nco += H->lv[ts].A->ncol + 1;
+      }
+      return ts;
+    };
+    H->coff_dev.resize(nl);
+    TailDesc D;
+    int ts = first_small(tail_n);
+    H->tail_start = (tail_n > 0 && !(ts == 0 && nl == 1) && make_tail_desc(*H, ts, D, s)) ? ts : -1;
     if (H->tail_start >= 0) {
-      TailDesc D;
-      std::memset(&D, 0, sizeof(D));
-      D.dense_rel = -1;
-      D.nlev = nl - H->tail_start;
-      D.cn = H->cn;
-      D.cm = H->cm;
-      D.grounded = H->grounded ? 1 : 0;
-      D.L = H->cL.p;
-      D.D = H->cD.p;
-      // LDS from the coarsest upwards
-      int first_lds = nl - 1;
-      int64_t used = 3 * (int64_t)H->cn + fixed;
-      while (first_lds > H->tail_start && used + 3 * (int64_t)H->lv[first_lds - 1].A->n <= budget) {
-        --first_lds;
-        used += 3 * (int64_t)H->lv[first_lds].A->n;
-      }
-      H->coff_dev.resize(nl);
-      int32_t o64 = 0, o32 = 0, oco = 0;
-      for (int l = H->tail_start; l < nl; ++l) {
-        Level& V = H->lv[l];
-        const LevelMatrix& A = *V.A;
-        TailLevel& T = D.lv[l - H->tail_start];
-        T.n = A.n;
-        T.ncol = A.ncol;
-        T.lds = l >= first_lds ? 1 : 0;
-        // one workgroup: one thread per row measured fastest for rows of up to
-        // ~50 entries (grid hierarchies); the near-dense coarse rows of
-        // power-law graphs take 16 lanes per row
-        T.lanes = (double)A.nnz > 48.0 * std::max(A.n, 1) ? 16 : 1;
-        if (T.lds) {
-          for (int j = 0; j < 3; ++j) {
-            T.o64[j] = o64 + j * A.n;
-            T.o32[j] = o32 + j * A.n;
-          }
-          o64 += 3 * A.n;
-          o32 += 3 * A.n;
-        }
-        if (l + 1 < nl) {
-          T.ocoff = oco;
-          oco += A.ncol + 1;
-          H->coff_dev[l].resize(A.ncol + 1);
-          copy_h2d(H->coff_dev[l].p, A.coff.data(), A.ncol + 1, s);
-          T.coff = H->coff_dev[l].p;
-        }
-        T.rp = A.rp.p;
-        T.ci = A.ci.p;
-        T.av = A.av.p;
-        T.d = A.d.p;
-        T.dinv = A.dinv.p;
-        T.av32 = A.av32.p;
-        T.d32 = A.d32.p;
-        T.dinv32 = A.dinv32.p;
-        T.agg = V.T.agg.p;
-        T.moff = V.T.moff.p;
-        T.mem = V.T.mem.p;
-        T.pval = V.T.pval.p;
-        T.pval32 = V.T.pval32.p;
-        T.x = V.x.p;
-        T.b = V.b.p;
-        T.r = V.r.p;
-        T.x32 = V.x32.p;
-        T.b32 = V.b32.p;
-        T.r32 = V.r32.p;
-      }
-      D.ncoff = oco;
-      D.oacc64 = o64;
-      D.oacc32 = (o32 + 1) / 2;
-      const bool lds_L = H->cm <= 64;
-      D.oL64 = lds_L ? D.oacc64 + H->cm : -1;
-      D.oL32 = lds_L ? D.oacc32 + H->cm : -1;
       H->tail_desc.resize(1);
       copy_h2d(H->tail_desc.p, &D, 1, s);
-      H->tail_host = std::make_unique<TailDesc>(D);
       sync(s);  // D is a host temporary
+    }
+    // not below the tail's first level: the dense product is applied from a
+    // level launched step by step
+    int ds = first_small(DENSE_START_MAX);
+    if (H->tail_start >= 0) ds = std::min(ds, H->tail_start);
+    if (ds >= 1 && nl - ds >= 2 && make_tail_desc(*H, ds, D, s)) {
+      H->dense_start = ds;
+      H->dense_host = std::make_unique<TailDesc>(D);
     }
   }
   if (P.keep_setup) {
@@ -447,7 +468,7 @@ void cycle64(pcamg_ctx* c, Hierarchy& H, int l, const double* b, double* x, int 
   Level& N = H.lv[l + 1];
   restrict_members<double>(L.T.nc, L.T.moff.p, L.T.mem.p, L.T.pval.p, L.r.p, N.b.p, s);
   const int calls = (gamma > 1 && l + 2 < nl) ? gamma : 1;
-  if (calls == 2 && l + 1 == H.tail_start && H.C64.p) {  // both tail sub-cycles at once
+  if (calls == 2 && l + 1 == H.dense_start && H.C64.p) {  // both sub-cycles below at once
     dense_apply<double>(N.A->n, H.C64.p, N.b.p, H.dpart64.p, N.x.p, s);
   } else {
     fill_f64(N.x.p, 0.0, N.A->n, s);
@@ -484,7 +505,7 @@ void cycle32(pcamg_ctx* c, Hierarchy& H, int l, const float* b, float* x, int ga
   Level& N = H.lv[l + 1];
   restrict_members<float>(L.T.nc, L.T.moff.p, L.T.mem.p, L.T.pval32.p, L.r32.p, N.b32.p, s);
   const int calls = (gamma > 1 && l + 2 < nl) ? gamma : 1;
-  if (calls == 2 && l + 1 == H.tail_start && H.C32.p) {  // both tail sub-cycles at once
+  if (calls == 2 && l + 1 == H.dense_start && H.C32.p) {  // both sub-cycles below at once
     dense_apply<float>(N.A->n, H.C32.p, N.b32.p, H.dpart32.p, N.x32.p, s);
   } else {
     fill_f32(N.x32.p, 0.0f, N.A->n, s);
@@ -580,14 +601,15 @@ void dense_columns(TailDesc D, T* C, hipStream_t s) {
 // two levels under it.
 constexpr int32_t DENSE_INNER_MAX = 1024;
 
+
 template <typename T>
 void ensure_dense(pcamg_ctx* c, Hierarchy& H) {
   const int nl = (int)H.lv.size();
-  if (!c->P.w_dense || H.tail_start < 1 || nl - H.tail_start < 2 || !H.tail_host) return;
+  if (!c->P.w_dense || H.dense_start < 1 || nl - H.dense_start < 2 || !H.dense_host) return;
   DVec<T>& C = DenseOf<T>::C(H);
   if (C.p) return;
   hipStream_t s = c->s;
-  TailDesc D = *H.tail_host;
+  TailDesc D = *H.dense_host;
   const int32_t n0 = D.lv[0].n;
   int inner = -1;
   if (n0 > DENSE_INNER_MAX)

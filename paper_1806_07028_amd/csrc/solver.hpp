@@ -53,6 +53,7 @@ constexpr int TAIL_MAX_LEVELS = 40;
 constexpr int LDLT_MAX = 4096;
 constexpr int TAIL_LDS_BYTES = 128 * 1024;
 constexpr int TAIL_COFF_MAX = 2048;
+constexpr int32_t DENSE_START_MAX = 6144;  // first level of the W-cycle's dense operator
 struct TailLevel {
   int32_t n, ncol, lds, ocoff, lanes;  // lanes per row: 1 or 16
   int32_t o64[3], o32[3];  // x, b, r in LDS (lds = 1)
@@ -82,7 +83,9 @@ struct Hierarchy {
   // tail: levels tail_start.. run in one workgroup launch
   int tail_start = -1;
   DVec<TailDesc> tail_desc;
-  std::unique_ptr<TailDesc> tail_host;  // host copy of the descriptor
+  // W-cycles: the sub-hierarchy whose two sub-cycles are one dense operator
+  int dense_start = -1;
+  std::unique_ptr<TailDesc> dense_host;  // host descriptor of levels dense_start..
   // W-cycles: the two tail sub-cycles as one dense operator (column-major)
   DVec<double> C64, dpart64;
   DVec<float> C32, dpart32;

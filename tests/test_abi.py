@@ -36,5 +36,5 @@ def test_params_default_and_struct_layout():
     assert p.seed == 0x5EED and p.colour_seed == 0xC010
     assert ctypes.sizeof(_lib.Params) == 8 + 8 + 23 * 4 + 4 + 8 + 8
     assert p.first_sweeps == -1
-    assert p.tail_max_n == 6144 and p.use_graphs == 1 and p.row_lanes == 0 and p.w_dense == 1
+    assert p.tail_max_n == 2048 and p.use_graphs == 1 and p.row_lanes == 0 and p.w_dense == 1
     assert _lib.lib().pcamg_status_str(-6) == b"graph not connected"
