@@ -415,10 +415,14 @@ void spmv(int32_t n, const int32_t* rp, const int32_t* ci, const T* av, const T*
 }
 
 // Restriction b_c = P^T r: fma chain over the members of each aggregate in
-// ascending (natural) order.  pval == nullptr: boolean P.
+// ascending (natural) order.  pval == nullptr: boolean P.  With xc, the
+// coarse x is started too: mode 1 zero; mode 2 the coarse level's first
+// Gauss-Seidel pass from x = 0 for its colour-0 rows (q < c1), xc = bc * dinvc
+// -- from x = 0 that pass's row chains are +0 (each product a signed zero).
 template <typename T>
 __global__ void restrict_kernel(int32_t nc, const int32_t* __restrict__ moff, const int32_t* __restrict__ mem,
-                                const T* __restrict__ pval, const T* __restrict__ r, T* __restrict__ bc) {
+                                const T* __restrict__ pval, const T* __restrict__ r, T* __restrict__ bc,
+                                T* __restrict__ xc, const T* __restrict__ dinvc, int32_t c1, int mode) {
   int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nc) return;
   T s = 0;
@@ -427,13 +431,15 @@ __global__ void restrict_kernel(int32_t nc, const int32_t* __restrict__ moff, co
     s = fma(pval ? pval[k] : (T)1, r[k], s);
   }
   bc[q] = s;
+  if (mode == 1) xc[q] = 0;
+  else if (mode == 2) xc[q] = q < c1 ? s * dinvc[q] : (T)0;
 }
 
 template <typename T>
 void restrict_members(int32_t nc, const int32_t* moff, const int32_t* mem, const T* pval, const T* r, T* bc,
-                      hipStream_t s) {
+                      hipStream_t s, T* xc, const T* dinvc, int32_t c1, int mode) {
   if (nc <= 0) return;
-  restrict_kernel<T><<<grid_for(nc, 256), 256, 0, s>>>(nc, moff, mem, pval, r, bc);
+  restrict_kernel<T><<<grid_for(nc, 256), 256, 0, s>>>(nc, moff, mem, pval, r, bc, xc, dinvc, c1, xc ? mode : 0);
   PCAMG_LAUNCHED();
 }
 
@@ -463,7 +469,7 @@ void prolong_add(int32_t n, const int32_t* agg, const T* pval, const T* xc, T* x
   template void spmv<T>(int32_t, const int32_t*, const int32_t*, const T*, const T*, const T*, T*, hipStream_t, \
                         int);                                                                                   \
   template void restrict_members<T>(int32_t, const int32_t*, const int32_t*, const T*, const T*, T*,          \
-                                    hipStream_t);                                                               \
+                                    hipStream_t, T*, const T*, int32_t, int);                                   \
   template void prolong_add<T>(int32_t, const int32_t*, const T*, const T*, T*, hipStream_t);
 INSTANTIATE(double)
 INSTANTIATE(float)

@@ -187,11 +187,14 @@ void residual(int32_t n, const int32_t* rp, const int32_t* ci, const T* av, cons
 template <typename T>
 void spmv(int32_t n, const int32_t* rp, const int32_t* ci, const T* av, const T* d, const T* x, T* y,
           hipStream_t s, int lanes = 1);
+// with xc: mode 1 also zeroes xc, mode 2 also does the coarse first colour
+// pass from zero (rows < c1: xc = bc * dinvc, others 0)
 template <typename T>
 void restrict_members(int32_t nc, const int32_t* moff, const int32_t* mem, const T* pval, const T* r, T* bc,
-                      hipStream_t s);
+                      hipStream_t s, T* xc = nullptr, const T* dinvc = nullptr, int32_t c1 = 0, int mode = 0);
 template <typename T>
 void prolong_add(int32_t n, const int32_t* agg, const T* pval, const T* xc, T* x, hipStream_t s);
+
 
 // ---------------------------------------------------------------------------
 // setup.hip: hierarchy construction kernels (natural numbering)

@@ -442,7 +442,7 @@ std::unique_ptr<Hierarchy> build_hierarchy(pcamg_ctx* c, const double* e_nat) {
 // ---------------------------------------------------------------------------
 // Cycles (Alg. 5 V_cycle, Alg. 2 W_cycle), solve layout.
 // ---------------------------------------------------------------------------
-void cycle64(pcamg_ctx* c, Hierarchy& H, int l, const double* b, double* x, int gamma) {
+void cycle64(pcamg_ctx* c, Hierarchy& H, int l, const double* b, double* x, int gamma, int skip) {
   hipStream_t s = c->s;
   const int nl = (int)H.lv.size();
   if (l == H.tail_start && !(l == 0 && nl == 1)) {
@@ -462,24 +462,30 @@ void cycle64(pcamg_ctx* c, Hierarchy& H, int l, const double* b, double* x, int 
   }
   Level& L = H.lv[l];
   const LevelMatrix& A = *L.A;
-  for (int k = 0; k < A.ncol; ++k)
+  for (int k = skip; k < A.ncol; ++k)
     gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s, A.lanes);
-  residual<double>(A.n, A.rp.p, A.ci.p, A.av.p, A.d.p, b, x, L.r.p, s, A.lanes);
   Level& N = H.lv[l + 1];
-  restrict_members<double>(L.T.nc, L.T.moff.p, L.T.mem.p, L.T.pval.p, L.r.p, N.b.p, s);
+  const LevelMatrix& AN = *N.A;
   const int calls = (gamma > 1 && l + 2 < nl) ? gamma : 1;
-  if (calls == 2 && l + 1 == H.dense_start && H.C64.p) {  // both sub-cycles below at once
-    dense_apply<double>(N.A->n, H.C64.p, N.b.p, H.dpart64.p, N.x.p, s);
+  const bool dense = calls == 2 && l + 1 == H.dense_start && H.C64.p;
+  // the child's x: written by the dense product or the coarsest solve, zero
+  // for the tail, else zero with its first colour pass done here
+  const bool launched_child = !dense && l + 2 < nl && l + 1 != H.tail_start;
+  const int mode = dense || l + 2 == nl ? 0 : launched_child ? 2 : 1;
+  residual<double>(A.n, A.rp.p, A.ci.p, A.av.p, A.d.p, b, x, L.r.p, s, A.lanes);
+  restrict_members<double>(L.T.nc, L.T.moff.p, L.T.mem.p, L.T.pval.p, L.r.p, N.b.p, s, N.x.p, AN.dinv.p,
+                        AN.coff.size() > 1 ? AN.coff[1] : 0, mode);
+  if (dense) {  // both sub-cycles below at once
+    dense_apply<double>(AN.n, H.C64.p, N.b.p, H.dpart64.p, N.x.p, s);
   } else {
-    fill_f64(N.x.p, 0.0, N.A->n, s);
-    for (int q = 0; q < calls; ++q) cycle64(c, H, l + 1, N.b.p, N.x.p, gamma);
+    for (int q = 0; q < calls; ++q) cycle64(c, H, l + 1, N.b.p, N.x.p, gamma, q == 0 && mode == 2 ? 1 : 0);
   }
   prolong_add<double>(A.n, L.T.agg.p, L.T.pval.p, N.x.p, x, s);
   for (int k = A.ncol - 1; k >= 0; --k)
     gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s, A.lanes);
 }
 
-void cycle32(pcamg_ctx* c, Hierarchy& H, int l, const float* b, float* x, int gamma) {
+void cycle32(pcamg_ctx* c, Hierarchy& H, int l, const float* b, float* x, int gamma, int skip) {
   hipStream_t s = c->s;
   const int nl = (int)H.lv.size();
   if (l == H.tail_start && !(l == 0 && nl == 1)) {
@@ -499,17 +505,23 @@ void cycle32(pcamg_ctx* c, Hierarchy& H, int l, const float* b, float* x, int ga
   }
   Level& L = H.lv[l];
   const LevelMatrix& A = *L.A;
-  for (int k = 0; k < A.ncol; ++k)
+  for (int k = skip; k < A.ncol; ++k)
     gs_colour<float>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s, A.lanes);
-  residual<float>(A.n, A.rp.p, A.ci.p, A.av32.p, A.d32.p, b, x, L.r32.p, s, A.lanes);
   Level& N = H.lv[l + 1];
-  restrict_members<float>(L.T.nc, L.T.moff.p, L.T.mem.p, L.T.pval32.p, L.r32.p, N.b32.p, s);
+  const LevelMatrix& AN = *N.A;
   const int calls = (gamma > 1 && l + 2 < nl) ? gamma : 1;
-  if (calls == 2 && l + 1 == H.dense_start && H.C32.p) {  // both sub-cycles below at once
-    dense_apply<float>(N.A->n, H.C32.p, N.b32.p, H.dpart32.p, N.x32.p, s);
+  const bool dense = calls == 2 && l + 1 == H.dense_start && H.C32.p;
+  // the child's x: written by the dense product or the coarsest solve, zero
+  // for the tail, else zero with its first colour pass done here
+  const bool launched_child = !dense && l + 2 < nl && l + 1 != H.tail_start;
+  const int mode = dense || l + 2 == nl ? 0 : launched_child ? 2 : 1;
+  residual<float>(A.n, A.rp.p, A.ci.p, A.av32.p, A.d32.p, b, x, L.r32.p, s, A.lanes);
+  restrict_members<float>(L.T.nc, L.T.moff.p, L.T.mem.p, L.T.pval32.p, L.r32.p, N.b32.p, s, N.x32.p, AN.dinv32.p,
+                        AN.coff.size() > 1 ? AN.coff[1] : 0, mode);
+  if (dense) {  // both sub-cycles below at once
+    dense_apply<float>(AN.n, H.C32.p, N.b32.p, H.dpart32.p, N.x32.p, s);
   } else {
-    fill_f32(N.x32.p, 0.0f, N.A->n, s);
-    for (int q = 0; q < calls; ++q) cycle32(c, H, l + 1, N.b32.p, N.x32.p, gamma);
+    for (int q = 0; q < calls; ++q) cycle32(c, H, l + 1, N.b32.p, N.x32.p, gamma, q == 0 && mode == 2 ? 1 : 0);
   }
   prolong_add<float>(A.n, L.T.agg.p, L.T.pval32.p, N.x32.p, x, s);
   for (int k = A.ncol - 1; k >= 0; --k)

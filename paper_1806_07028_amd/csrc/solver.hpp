@@ -179,8 +179,8 @@ double net_loss_grad(pcamg_net* net, const pcamg_graph* g, const double* e2, con
                      hipStream_t s);
 void net_adam(pcamg_net* net, float lr, hipStream_t s);
 // Cycles on the solve layout (level-0 vectors in permuted order).
-void cycle64(pcamg_ctx* c, Hierarchy& H, int l, const double* b, double* x, int gamma);
-void cycle32(pcamg_ctx* c, Hierarchy& H, int l, const float* b, float* x, int gamma);
+void cycle64(pcamg_ctx* c, Hierarchy& H, int l, const double* b, double* x, int gamma, int skip = 0);
+void cycle32(pcamg_ctx* c, Hierarchy& H, int l, const float* b, float* x, int gamma, int skip = 0);
 // Whole cycles on level-0 vectors (solve layout), replayed from captured graphs.
 void run_cycle64(pcamg_ctx* c, Hierarchy& H, const double* b, double* x, int gamma);
 void run_cycle32(pcamg_ctx* c, Hierarchy& H, const float* b, float* x, int gamma);
