@@ -59,8 +59,10 @@ __global__ void jp_prio_kernel(int32_t n, uint64_t seed, uint64_t lvl, uint64_t*
 // v is still uncoloured afterwards.  Reading a neighbour coloured in the same
 // round is harmless either way: its colour is final once written.  Neighbours
 // are examined in batches of eight with independent loads.
-__device__ bool jp_try(int32_t v, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                       const uint64_t* __restrict__ prio, int32_t* colour) {
+// prio / colour may point to global memory or LDS.
+template <typename PP, typename PC>
+__device__ __forceinline__ bool jp_try(int32_t v, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                       PP prio, PC colour) {
   constexpr int U = 8;
   const uint64_t pv = prio[v];
   const int32_t k0 = rp[v], k1 = rp[v + 1];
@@ -112,27 +114,43 @@ __device__ bool jp_try(int32_t v, const int32_t* __restrict__ rp, const int32_t*
   return false;
 }
 
-// all rounds in one workgroup (small graphs)
+// All rounds in one workgroup (small graphs): priorities, colours and the
+// shrinking worklist of uncoloured vertices in LDS.
 constexpr int JP_SMALL_THREADS = 1024;
 constexpr int32_t JP_SMALL_MAX = 4096;
 __global__ void __launch_bounds__(JP_SMALL_THREADS)
     jp_small_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                     const uint64_t* __restrict__ prio, int32_t* colour, int32_t* __restrict__ rounds_out) {
-  __shared__ int32_t remaining;
+  __shared__ uint64_t pr[JP_SMALL_MAX];
+  __shared__ int32_t col[JP_SMALL_MAX];
+  __shared__ int32_t wl[2][JP_SMALL_MAX];
+  __shared__ int32_t cnt[2];
+  for (int32_t v = threadIdx.x; v < n; v += JP_SMALL_THREADS) {
+    pr[v] = prio[v];
+    col[v] = -1;
+    wl[0][v] = v;
+  }
+  if (threadIdx.x == 0) {
+    cnt[0] = n;
+    cnt[1] = 0;
+  }
+  __syncthreads();
+  int cur = 0;
   int32_t rounds = 0;
   for (;;) {
-    if (threadIdx.x == 0) remaining = 0;
+    const int32_t m = cnt[cur];
+    if (m == 0 || rounds > n + 1) break;
+    for (int32_t t = threadIdx.x; t < m; t += JP_SMALL_THREADS) {
+      const int32_t v = wl[cur][t];
+      if (jp_try(v, rp, ci, (const uint64_t*)pr, (int32_t*)col)) wl[cur ^ 1][atomicAdd(&cnt[cur ^ 1], 1)] = v;
+    }
     __syncthreads();
-    int32_t mine = 0;
-    for (int32_t v = threadIdx.x; v < n; v += JP_SMALL_THREADS)
-      if (colour[v] < 0 && jp_try(v, rp, ci, prio, colour)) ++mine;
-    if (mine) atomicAdd(&remaining, mine);
-    __syncthreads();
-    const int32_t r = remaining;
+    if (threadIdx.x == 0) cnt[cur] = 0;
+    cur ^= 1;
     ++rounds;
     __syncthreads();
-    if (r == 0 || rounds > n + 1) break;
   }
+  for (int32_t v = threadIdx.x; v < n; v += JP_SMALL_THREADS) colour[v] = col[v];
   if (threadIdx.x == 0) *rounds_out = rounds;
 }
 
@@ -271,9 +289,10 @@ int32_t colour_jp(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed
     iota_i32(list0.p, n, s);
     fill_i32(cnt.p, 0, R + 1, s);
     fill_i32(cnt.p, n, 1, s);
-    const unsigned grid = std::min<unsigned>(grid_for(n, 256), 2048);
+    int32_t pending = n;  // upper bound of the worklist: the grid of the next batch
     int64_t rounds = 0;
     for (;;) {
+      const unsigned grid = std::min<unsigned>(grid_for(pending, 256), 2048);
       for (int r = 0; r < R; ++r) {
         const int32_t* in = (r & 1) ? list1.p : list0.p;
         int32_t* out = (r & 1) ? list0.p : list1.p;
@@ -281,7 +300,8 @@ int32_t colour_jp(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed
         PCAMG_LAUNCHED();
       }
       rounds += R;
-      if (read_scalar(cnt.p + R, s) == 0) break;
+      pending = read_scalar(cnt.p + R, s);
+      if (pending == 0) break;
       require(rounds <= (int64_t)n + R, PCAMG_EHIP, "colouring made no progress");
       // R is even: the survivors are in list0 again
       jp_carry_kernel<<<1, 64, 0, s>>>(cnt.p, R);
