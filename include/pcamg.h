@@ -95,6 +95,8 @@ typedef struct {
                               order; built on first use per hierarchy and precision); 0 = recurse */
   int32_t first_sweeps;    /* symmetric sweeps before the first build: -1 = relax_sweeps; with
                               pcamg_setup_learned the sweeps of the network's input (-1: 2) */
+  int32_t dense_max_n;     /* w_dense: the dense operator starts at the first level of at most this
+                              many vertices below the finest (12288) */
   uint64_t seed;           /* start-vector stream */
   uint64_t colour_seed;    /* colouring priority stream */
 } pcamg_params;

@@ -49,6 +49,7 @@ class Params(C.Structure):
         ("row_lanes", _i32),
         ("w_dense", _i32),
         ("first_sweeps", _i32),
+        ("dense_max_n", _i32),
         ("seed", _u64),
         ("colour_seed", _u64),
     ]

@@ -217,6 +217,7 @@ pcamg_status pcamg_params_default(pcamg_params* p) {
   p->row_lanes = 0;
   p->w_dense = 1;
   p->first_sweeps = -1;
+  p->dense_max_n = 12288;
   p->seed = 0x5EED;
   p->colour_seed = 0xC010;
   return PCAMG_OK;

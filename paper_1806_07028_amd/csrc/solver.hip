@@ -367,7 +367,7 @@ std::unique_ptr<Hierarchy> build_hierarchy(pcamg_ctx* c, const double* e_nat) {
   H->st0 = nat[0].st;
   // tail: the levels of at most tail_max_n vertices and the coarsest run in one
   // workgroup launch (tail_desc).  W-cycles apply the two sub-cycles below the
-  // first level of at most DENSE_START_MAX vertices as one dense operator,
+  // first level of at most dense_max_n vertices as one dense operator,
   // built from the host descriptor dense_host of that sub-hierarchy.
   {
     const int32_t tail_n = c->P.tail_max_n > 0 ? c->P.tail_max_n : 0;
@@ -392,7 +392,7 @@ std::unique_ptr<Hierarchy> build_hierarchy(pcamg_ctx* c, const double* e_nat) {
     }
     // not below the tail's first level: the dense product is applied from a
     // level launched step by step
-    int ds = first_small(DENSE_START_MAX);
+    int ds = first_small(std::max<int32_t>(c->P.dense_max_n, 1));
     if (H->tail_start >= 0) ds = std::min(ds, H->tail_start);
     if (ds >= 1 && nl - ds >= 2 && make_tail_desc(*H, ds, D, s)) {
       H->dense_start = ds;

@@ -53,7 +53,6 @@ constexpr int TAIL_MAX_LEVELS = 40;
 constexpr int LDLT_MAX = 4096;
 constexpr int TAIL_LDS_BYTES = 128 * 1024;
 constexpr int TAIL_COFF_MAX = 2048;
-constexpr int32_t DENSE_START_MAX = 6144;  // first level of the W-cycle's dense operator
 struct TailLevel {
   int32_t n, ncol, lds, ocoff, lanes;  // lanes per row: 1 or 16
   int32_t o64[3], o32[3];  // x, b, r in LDS (lds = 1)

@@ -389,8 +389,8 @@ def test_dense_w_cycle(gpu, oracle, gname):
     b = I.zero_mean_normal_rhs(3, n)
     x0 = I.normal(4, n)
     rec = solver_for(gpu, g)
-    dense = solver_for(gpu, g, w_dense=1)
-    dense_eager = solver_for(gpu, g, w_dense=1, use_graphs=0)
+    dense = solver_for(gpu, g, w_dense=1, dense_max_n=6144)
+    dense_eager = solver_for(gpu, g, w_dense=1, use_graphs=0, dense_max_n=6144)
     H = oracle.Hierarchy(g, None)
     assert dense.num_levels() == H.nlevels >= 4
     w_ref = H.cycle(b, x0, 2)
@@ -512,17 +512,19 @@ def test_colour_dense_levels(gpu, oracle):
             same(host(col), rcol)
 
 
-def test_dense_w_cycle_nested(gpu, oracle):
-    """A tail whose first level exceeds the inner size: the dense operator is
-    built with an inner dense operator nested in its columns' sub-cycles; still
-    the W-cycle up to rounding (FP64 1e-12, FP32 1e-5 relative)."""
-    g = I.grid3d(24, 24, 16, weight_seed=11)
+@pytest.mark.parametrize("shape,dmax", [((24, 24, 16), 6144), ((32, 32, 32), 12288)])
+def test_dense_w_cycle_nested(gpu, oracle, shape, dmax):
+    """A dense operator whose first level exceeds the inner size is built with
+    an inner dense operator nested in its columns' sub-cycles (its first level
+    launched step by step above the tail); still the W-cycle up to rounding
+    (FP64 1e-12, FP32 1e-5 relative)."""
+    g = I.grid3d(*shape, weight_seed=11)
     n = g[0]
     b = I.zero_mean_normal_rhs(3, n)
-    s = solver_for(gpu, g, w_dense=1)
+    s = solver_for(gpu, g, w_dense=1, dense_max_n=dmax)
     H = oracle.Hierarchy(g, None)
     sizes = [s.level_info(l)["n"] for l in range(s.num_levels())]
-    assert any(1024 < m <= 6144 for m in sizes) and any(m <= 1024 for m in sizes)
+    assert any(1024 < m <= dmax for m in sizes[1:]) and any(m <= 1024 for m in sizes)
     w_ref = H.cycle(b, None, 2)
     w64 = host(s.cycle(b, None, 2))
     assert np.linalg.norm(w64 - w_ref) <= 1e-12 * np.linalg.norm(w_ref)
