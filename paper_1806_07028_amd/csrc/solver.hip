@@ -99,7 +99,8 @@ void ctx_init(pcamg_ctx* c, const pcamg_graph* g, const pcamg_params* p) {
 static bool make_tail_desc(Hierarchy& H, int start, TailDesc& D, hipStream_t s) {
   const int nl = (int)H.lv.size();
   const int64_t budget = TAIL_LDS_BYTES / 8;  // doubles
-  const int64_t fixed = (int64_t)H.cm + (H.cm <= 64 ? (int64_t)H.cm * H.cm : 0);
+  // accumulator of cn doubles (the grounded solve sets its last entry), factor
+  const int64_t fixed = (int64_t)H.cn + (H.cm <= 64 ? (int64_t)H.cm * H.cm : 0);
   if (3 * (int64_t)H.cn + fixed > budget) return false;
   std::memset(&D, 0, sizeof(D));
   D.dense_rel = -1;
@@ -168,8 +169,8 @@ static bool make_tail_desc(Hierarchy& H, int start, TailDesc& D, hipStream_t s) 
   D.oacc64 = o64;
   D.oacc32 = (o32 + 1) / 2;
   const bool lds_L = H.cm <= 64;
-  D.oL64 = lds_L ? D.oacc64 + H.cm : -1;
-  D.oL32 = lds_L ? D.oacc32 + H.cm : -1;
+  D.oL64 = lds_L ? D.oacc64 + H.cn : -1;
+  D.oL32 = lds_L ? D.oacc32 + H.cn : -1;
   return true;
 }
 
@@ -590,6 +591,26 @@ struct DenseOf<float> {
 template <typename T>
 void dense_columns(TailDesc D, T* C, hipStream_t s) {
   const int32_t n0 = D.lv[0].n;
+  const int K = dense_mc_columns();
+  if (dense_mc_lds_bytes(D.cn, D.cm, sizeof(T)) <= (size_t)TAIL_LDS_BYTES) {
+    // several columns per workgroup: every non-coarsest level in per-workgroup
+    // scratch as rows of K values
+    size_t gstride = 0;
+    for (int l = 0; l + 1 < D.nlev; ++l) gstride += 3 * (size_t)D.lv[l].n * K;
+    const int blocks = std::min<int32_t>((n0 + K - 1) / K, 256);
+    DVec<T> scratch(std::max<size_t>(gstride * blocks, 1));
+    size_t off = 0;
+    for (int l = 0; l + 1 < D.nlev; ++l) {
+      const size_t m = (size_t)D.lv[l].n * K;
+      DenseOf<T>::point(D.lv[l], scratch.p + off, scratch.p + off + m, scratch.p + off + 2 * m);
+      off += 3 * m;
+    }
+    DVec<TailDesc> dd(1);
+    copy_h2d(dd.p, &D, 1, s);
+    tail_dense_mc<T>(dd.p, blocks, C, gstride, s);
+    sync(s);  // D, dd and scratch are temporaries
+    return;
+  }
   size_t gstride = 0;
   for (int l = 0; l < D.nlev; ++l)
     if (!D.lv[l].lds) gstride += 3 * (size_t)D.lv[l].n;

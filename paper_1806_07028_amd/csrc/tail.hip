@@ -344,6 +344,258 @@ __global__ void __launch_bounds__(TAIL_THREADS)
   }
 }
 
+// ---------------------------------------------------------------------------
+// Multi-column construction of the dense operator: each workgroup carries
+// DMC_K unit vectors through the tail recursion at once.  Vectors of the
+// non-coarsest levels are rows of DMC_K values in per-workgroup global scratch,
+// the coarsest level's in LDS; every (row, column) item follows exactly the
+// single-vector arithmetic and order, so each column equals the one-vector
+// construction bit for bit while the step latency is shared by DMC_K columns.
+// ---------------------------------------------------------------------------
+constexpr int DMC_K = 8;
+
+// fma chain of a CSR row against column j of a row-major n x DMC_K block
+// (x points at column j), in batches of eight as row_chain1
+template <typename T, typename PX>
+__device__ __forceinline__ T chain_mc(int32_t k0, int32_t k1, GP<int32_t> ci, GP<T> av, PX x, T s) {
+  constexpr int U = 8;
+  for (int32_t k = k0; k < k1; k += U) {
+    int32_t c[U];
+    T a[U], v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      c[u] = k + u < k1 ? ci[k + u] : 0;
+      a[u] = k + u < k1 ? av[k + u] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = k + u < k1 ? x[(size_t)c[u] * DMC_K] : (T)0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (k + u < k1) s = fma(a[u], v[u], s);
+  }
+  return s;
+}
+
+template <typename T>
+__device__ __forceinline__ void gs_mc(const TailLevel& L, const int32_t* coff, GW<T> b, GW<T> x, bool forward) {
+  const GP<T> av = TailOps<T>::av(L), dinv = TailOps<T>::dinv(L);
+  const GP<int32_t> rp = gptr(L.rp), ci = gptr(L.ci);
+  for (int t = 0; t < L.ncol; ++t) {
+    const int c = forward ? t : L.ncol - 1 - t;
+    const int32_t r0 = coff[c], r1 = coff[c + 1];
+    const int32_t items = (r1 - r0) * DMC_K;
+    for (int32_t it = threadIdx.x; it < items; it += TAIL_THREADS) {
+      const int32_t i = r0 + it / DMC_K, j = it % DMC_K;
+      const T sum = chain_mc<T>(rp[i], rp[i + 1], ci, av, x + j, (T)0);
+      x[(size_t)i * DMC_K + j] = (b[(size_t)i * DMC_K + j] - sum) * dinv[i];
+    }
+    __syncthreads();
+  }
+}
+
+// pre-smoothing, residual, restriction into the child (bc, xc: LDS pointers
+// for the coarsest child, else global), optionally the inner dense product
+template <typename T, typename PC>
+__device__ __forceinline__ void down_mc(const TailLevel& L, const int32_t* coff, GW<T> b, GW<T> x, GW<T> r, PC bc,
+                                        PC xc, int32_t nc, GP<T> Cd) {
+  gs_mc<T>(L, coff, b, x, true);
+  {
+    const GP<T> av = TailOps<T>::av(L), d = TailOps<T>::d(L);
+    const GP<int32_t> rp = gptr(L.rp), ci = gptr(L.ci);
+    for (int32_t it = threadIdx.x; it < L.n * DMC_K; it += TAIL_THREADS) {
+      const int32_t i = it / DMC_K, j = it % DMC_K;
+      const T sum = chain_mc<T>(rp[i], rp[i + 1], ci, av, x + j, d[i] * x[(size_t)i * DMC_K + j]);
+      r[(size_t)i * DMC_K + j] = b[(size_t)i * DMC_K + j] - sum;
+    }
+    __syncthreads();
+  }
+  const GP<T> pv = TailOps<T>::pval(L);
+  const GP<int32_t> moff = gptr(L.moff), mem = gptr(L.mem);
+  for (int32_t it = threadIdx.x; it < nc * DMC_K; it += TAIL_THREADS) {
+    const int32_t q = it / DMC_K, j = it % DMC_K;
+    T sum = 0;
+    for (int32_t t = moff[q]; t < moff[q + 1]; ++t) {
+      const int32_t k = mem[t];
+      sum = fma(pv ? pv[k] : (T)1, r[(size_t)k * DMC_K + j], sum);
+    }
+    bc[(size_t)q * DMC_K + j] = sum;
+    xc[(size_t)q * DMC_K + j] = 0;
+  }
+  __syncthreads();
+  if (Cd) {
+    for (int32_t it = threadIdx.x; it < nc * DMC_K; it += TAIL_THREADS) {
+      const int32_t i = it / DMC_K, j = it % DMC_K;
+      T sum = 0;
+      for (int32_t m = 0; m < nc; ++m) sum = fma(Cd[(size_t)m * nc + i], bc[(size_t)m * DMC_K + j], sum);
+      xc[(size_t)i * DMC_K + j] = sum;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, typename PC>
+__device__ __forceinline__ void up_mc(const TailLevel& L, const int32_t* coff, GW<T> b, GW<T> x, PC xc) {
+  const GP<T> pv = TailOps<T>::pval(L);
+  const GP<int32_t> agg = gptr(L.agg);
+  for (int32_t it = threadIdx.x; it < L.n * DMC_K; it += TAIL_THREADS) {
+    const int32_t k = it / DMC_K, j = it % DMC_K;
+    x[(size_t)k * DMC_K + j] = fma(pv ? pv[k] : (T)1, xc[(size_t)agg[k] * DMC_K + j], x[(size_t)k * DMC_K + j]);
+  }
+  __syncthreads();
+  gs_mc<T>(L, coff, b, x, false);
+}
+
+// dense coarsest solve per column (the order of tail_coarsest)
+template <typename T>
+__device__ __forceinline__ void coarsest_mc(const TailDesc& D, const double* Lf, const T* b, T* x, double* acc,
+                                            double* mu) {
+  const int32_t n = D.cn, m = D.cm;
+  const GP<double> Dg = gptr(D.D);
+  for (int32_t it = threadIdx.x; it < m * DMC_K; it += TAIL_THREADS) acc[it] = (double)b[it];
+  __syncthreads();
+  for (int32_t k = 0; k < m; ++k) {
+    for (int32_t it = threadIdx.x; it < (m - k - 1) * DMC_K; it += TAIL_THREADS) {
+      const int32_t i = k + 1 + it / DMC_K, j = it % DMC_K;
+      acc[i * DMC_K + j] = fma(-Lf[(size_t)i * m + k], acc[k * DMC_K + j], acc[i * DMC_K + j]);
+    }
+    __syncthreads();
+  }
+  for (int32_t it = threadIdx.x; it < m * DMC_K; it += TAIL_THREADS) acc[it] = acc[it] / Dg[it / DMC_K];
+  __syncthreads();
+  for (int32_t k = m - 1; k >= 0; --k) {
+    for (int32_t it = threadIdx.x; it < k * DMC_K; it += TAIL_THREADS) {
+      const int32_t i = it / DMC_K, j = it % DMC_K;
+      acc[i * DMC_K + j] = fma(-Lf[(size_t)k * m + i], acc[k * DMC_K + j], acc[i * DMC_K + j]);
+    }
+    __syncthreads();
+  }
+  if (D.grounded) {
+    if (threadIdx.x < DMC_K) {
+      const int j = threadIdx.x;
+      acc[(n - 1) * DMC_K + j] = 0.0;
+      double sum = 0.0;
+      for (int32_t i = 0; i < n; ++i) sum = sum + acc[i * DMC_K + j];
+      mu[j] = sum / (double)n;
+    }
+    __syncthreads();
+    for (int32_t it = threadIdx.x; it < n * DMC_K; it += TAIL_THREADS) x[it] = (T)(acc[it] - mu[it % DMC_K]);
+  } else {
+    for (int32_t it = threadIdx.x; it < n * DMC_K; it += TAIL_THREADS) x[it] = (T)acc[it];
+  }
+  __syncthreads();
+}
+
+// One cycle of the multi-column tail (gamma = 2 recursion with the optional
+// inner dense operator), level 0's vectors in global memory at boff.
+template <typename T>
+__device__ __forceinline__ void body_mc(const TailDesc& D, T* cx, T* cb, const int32_t* coffs, const double* Lf,
+                                        double* acc, double* mu, size_t boff) {
+  const int last = D.nlev - 1;
+  uint64_t again = 0;
+  int l = 0, ph = 0;
+  while (l >= 0) {
+    const TailLevel& L = D.lv[l];
+    if (l == last) {
+      coarsest_mc<T>(D, Lf, cb, cx, acc, mu);
+      --l;
+      ph = 1;
+      continue;
+    }
+    if (ph == 1 && (again & (1ull << l))) {
+      again &= ~(1ull << l);
+      ++l;
+      ph = 0;
+      continue;
+    }
+    const TailLevel& N = D.lv[l + 1];
+    const int32_t* coff = coffs + L.ocoff;
+    const bool down = ph == 0;
+    const bool dense = down && l + 1 == D.dense_rel && l + 1 < last;
+    const GP<T> Cd = dense ? TailOps<T>::C(D) : (GP<T>)nullptr;
+    const GW<T> b = TailOps<T>::gb(L) + boff, x = TailOps<T>::gx(L) + boff, r = TailOps<T>::gr(L) + boff;
+    if (l + 1 == last) {
+      if (down) down_mc<T>(L, coff, b, x, r, cb, cx, N.n, Cd);
+      else up_mc<T>(L, coff, b, x, (const T*)cx);
+    } else {
+      const GW<T> nb = TailOps<T>::gb(N) + boff, nx = TailOps<T>::gx(N) + boff;
+      if (down) down_mc<T>(L, coff, b, x, r, nb, nx, N.n, Cd);
+      else up_mc<T>(L, coff, b, x, (GP<T>)nx);
+    }
+    if (dense) {
+      again &= ~(1ull << l);
+      ph = 1;
+    } else if (down) {
+      if (l + 1 < last) again |= 1ull << l;
+      else again &= ~(1ull << l);
+      ++l;
+    } else {
+      --l;
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TAIL_THREADS)
+    tail_dense_mc_kernel(const TailDesc* __restrict__ Dp, T* __restrict__ C, size_t gstride) {
+  __shared__ double pool[TAIL_LDS_BYTES / 8];
+  __shared__ int32_t coffs[TAIL_COFF_MAX];
+  __shared__ double mu[DMC_K];
+  const TailDesc& D = *Dp;
+  const int last = D.nlev - 1;
+  for (int l = 0; l < last; ++l) {
+    const TailLevel& L = D.lv[l];
+    const GP<int32_t> cf = gptr(L.coff);
+    for (int32_t c = threadIdx.x; c <= L.ncol; c += TAIL_THREADS) coffs[L.ocoff + c] = cf[c];
+  }
+  // LDS: coarsest x and b (cn x K of T), accumulator (cn x K doubles: the
+  // grounded solve sets its last row), factor (cm x cm)
+  const int32_t cn = D.cn, cm = D.cm;
+  T* cx = reinterpret_cast<T*>(pool);
+  T* cb = cx + (size_t)cn * DMC_K;
+  const size_t tb = ((size_t)2 * cn * DMC_K * sizeof(T) + 7) / 8;
+  double* acc = pool + tb;
+  const bool lds_L = cm <= 64;
+  if (lds_L) {
+    const GP<double> Lg = gptr(D.L);
+    for (int32_t i = threadIdx.x; i < cm * cm; i += TAIL_THREADS) pool[tb + (size_t)cn * DMC_K + i] = Lg[i];
+  }
+  const double* Lf = lds_L ? pool + tb + (size_t)cn * DMC_K : D.L;
+  const TailLevel& L0 = D.lv[0];
+  const int32_t n0 = L0.n;
+  const size_t boff = (size_t)blockIdx.x * gstride;
+  const GW<T> x0 = TailOps<T>::gx(L0) + boff, b0 = TailOps<T>::gb(L0) + boff;
+  for (int32_t j0 = blockIdx.x * DMC_K; j0 < n0; j0 += gridDim.x * DMC_K) {
+    __syncthreads();
+    for (int32_t it = threadIdx.x; it < n0 * DMC_K; it += TAIL_THREADS) {
+      const int32_t i = it / DMC_K, j = it % DMC_K;
+      x0[it] = 0;
+      b0[it] = i == j0 + j ? (T)1 : (T)0;
+    }
+    __syncthreads();
+    body_mc<T>(D, cx, cb, coffs, Lf, acc, mu, boff);
+    body_mc<T>(D, cx, cb, coffs, Lf, acc, mu, boff);
+    for (int32_t it = threadIdx.x; it < n0 * DMC_K; it += TAIL_THREADS) {
+      const int32_t i = it % n0, j = it / n0;  // coalesced over i in C
+      if (j0 + j < n0) C[(size_t)(j0 + j) * n0 + i] = x0[(size_t)i * DMC_K + j];
+    }
+  }
+}
+
+// LDS bytes the multi-column construction needs for the coarsest level
+size_t dense_mc_lds_bytes(int32_t cn, int32_t cm, size_t tsize) {
+  return ((size_t)2 * cn * DMC_K * tsize + 7) / 8 * 8 + (size_t)cn * DMC_K * 8 + (cm <= 64 ? (size_t)cm * cm * 8 : 0);
+}
+
+int dense_mc_columns() { return DMC_K; }
+
+template <typename T>
+void tail_dense_mc(const TailDesc* desc, int blocks, T* C, size_t gstride, hipStream_t s) {
+  tail_dense_mc_kernel<T><<<blocks, TAIL_THREADS, 0, s>>>(desc, C, gstride);
+  PCAMG_LAUNCHED();
+}
+template void tail_dense_mc<double>(const TailDesc*, int, double*, size_t, hipStream_t);
+template void tail_dense_mc<float>(const TailDesc*, int, float*, size_t, hipStream_t);
+
 void tail_cycle64(const Hierarchy& H, const double* b, double* x, int gamma, hipStream_t s) {
   tail_kernel<double><<<1, TAIL_THREADS, 0, s>>>(H.tail_desc.p, b, x, gamma);
   PCAMG_LAUNCHED();
