@@ -83,6 +83,8 @@ def lib():
     L.or_laplacian.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p]
     L.or_colour.argtypes = [C.c_int, _i32p, _i32p, C.c_ulonglong, C.c_int, _i32p]
     L.or_colour.restype = C.c_int
+    L.or_colour_greedy.argtypes = [C.c_int, _i32p, _i32p, C.c_ulonglong, C.c_int, _i32p]
+    L.or_colour_greedy.restype = C.c_int
     L.or_gs.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, _i32p, C.c_int, _f64p, _f64p, C.c_int, C.c_int]
     L.or_gs32.argtypes = [C.c_int, _i32p, _i32p, _f32p, _f32p, _i32p, C.c_int, _f32p, _f32p, C.c_int]
     L.or_residual.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p, _f64p]
@@ -163,8 +165,17 @@ def laplacian(g):
 
 
 def colour(n, rp, ci, seed: int, level: int = 0):
+    """The smoother's colouring of a level graph: red-black on a connected
+    bipartite graph, greedy first-fit in priority order otherwise."""
     c = np.empty(n, dtype=np.int32)
     nc = lib().or_colour(n, _i32(rp), _i32(ci), seed, level, c)
+    return c, nc
+
+
+def colour_greedy(n, rp, ci, seed: int, level: int = 0):
+    """Greedy first-fit in descending (priority, id) order, whatever the graph."""
+    c = np.empty(n, dtype=np.int32)
+    nc = lib().or_colour_greedy(n, _i32(rp), _i32(ci), seed, level, c)
     return c, nc
 
 

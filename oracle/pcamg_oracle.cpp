@@ -36,6 +36,10 @@
 //    dense LDL^T, grounded (last vertex pinned, mean removed) iff the coarsest
 //    operator is a Laplacian (every prolongation boolean, or a single level),
 //    full otherwise; a non-positive pivot falls back to grounded.
+//  * Gauss-Seidel ordering (the paper names only Gauss-Seidel): multicolour,
+//    red-black (parity of the breadth-first distance from vertex 0) on a
+//    connected bipartite level graph, else greedy first-fit in descending
+//    SplitMix64 priority order.
 //  * Outer loop (Alg. 5): V(1,1) with forward GS before and backward GS after
 //    the coarse correction; x made orthogonal to 1 after each cycle; ConvR =
 //    ||r_{k+1}||/||r_k||; rebuild when the mean ConvR since the last rebuild
@@ -202,6 +206,45 @@ int colour_greedy(const Csr& G, uint64_t seed, int level, std::vector<int>& colo
     ncol = std::max(ncol, c + 1);
   }
   return ncol;
+}
+
+// Connected bipartite level graphs (2D/3D grids, paths, trees) get the
+// red-black ordering instead: colour = parity of the breadth-first distance
+// from vertex 0.  A connected graph is bipartite exactly when no edge joins two
+// vertices of equal parity; a proper two-colouring with vertex 0 coloured 0 is
+// then unique.  Returns false (colouring untouched) for graphs that are not
+// connected or not bipartite.
+bool colour_bipartite(const Csr& G, std::vector<int>& colour) {
+  const int n = G.n;
+  if (n == 0) return false;
+  std::vector<int> depth(n, -1), queue;
+  queue.reserve(n);
+  depth[0] = 0;
+  queue.push_back(0);
+  for (size_t h = 0; h < queue.size(); ++h) {
+    const int v = queue[h];
+    for (int k = G.rp[v]; k < G.rp[v + 1]; ++k) {
+      const int u = G.ci[k];
+      if (depth[u] < 0) {
+        depth[u] = depth[v] + 1;
+        queue.push_back(u);
+      }
+    }
+  }
+  if ((int)queue.size() != n) return false;
+  for (int v = 0; v < n; ++v)
+    for (int k = G.rp[v]; k < G.rp[v + 1]; ++k)
+      if ((depth[v] & 1) == (depth[G.ci[k]] & 1)) return false;
+  colour.assign(n, 0);
+  for (int v = 0; v < n; ++v) colour[v] = depth[v] & 1;
+  return true;
+}
+
+// The smoother's colouring of a level graph: red-black when the graph is
+// connected and bipartite, greedy first-fit in priority order otherwise.
+int colour_level(const Csr& G, uint64_t seed, int level, std::vector<int>& colour) {
+  if (colour_bipartite(G, colour)) return G.n > 1 ? 2 : 1;
+  return colour_greedy(G, seed, level, colour);
 }
 
 void group_by_colour(Level& L) {
@@ -800,7 +843,7 @@ bool build_hierarchy(const Level& fine, const std::vector<double>& e_raw, const 
     galerkin(L, C);
     coarsen_graph(L, C);
     shorten_paths(L, C.nb);
-    C.ncolours = colour_greedy(C.A, P.colour_seed, l + 1, C.colour);
+    C.ncolours = colour_level(C.A, P.colour_seed, l + 1, C.colour);
     group_by_colour(C);
     H.lv.push_back(std::move(C));
   }
@@ -949,7 +992,7 @@ int solve(const Csr& W, const std::vector<double>& b, const Params& P, std::vect
   Level fine;
   fine.n = n;
   laplacian(W, fine.A, fine.d, fine.dinv);
-  fine.ncolours = colour_greedy(fine.A, P.colour_seed, 0, fine.colour);
+  fine.ncolours = colour_level(fine.A, P.colour_seed, 0, fine.colour);
   group_by_colour(fine);
   std::vector<Hierarchy> hist(1);
   std::vector<double> e;
@@ -1148,6 +1191,14 @@ void or_laplacian(int n, const int* rp, const int* ci, const double* w, double* 
 int or_colour(int n, const int* rp, const int* ci, unsigned long long seed, int level, int* colour) {
   Csr G = make_csr(n, rp, ci, nullptr);
   std::vector<int> c;
+  int nc = colour_level(G, seed, level, c);
+  std::copy(c.begin(), c.end(), colour);
+  return nc;
+}
+
+int or_colour_greedy(int n, const int* rp, const int* ci, unsigned long long seed, int level, int* colour) {
+  Csr G = make_csr(n, rp, ci, nullptr);
+  std::vector<int> c;
   int nc = colour_greedy(G, seed, level, c);
   std::copy(c.begin(), c.end(), colour);
   return nc;
@@ -1194,7 +1245,7 @@ void or_smooth_error(int n, const int* rp, const int* ci, const double* w, unsig
   Level fine;
   fine.n = n;
   laplacian(make_csr(n, rp, ci, w), fine.A, fine.d, fine.dinv);
-  fine.ncolours = colour_greedy(fine.A, colour_seed, 0, fine.colour);
+  fine.ncolours = colour_level(fine.A, colour_seed, 0, fine.colour);
   group_by_colour(fine);
   Params P{};
   P.seed = seed;
@@ -1303,7 +1354,7 @@ void* or_hier_build(int n, const int* rp, const int* ci, const double* w, const 
   auto* h = new HierHandle();
   h->fine.n = n;
   laplacian(make_csr(n, rp, ci, w), h->fine.A, h->fine.d, h->fine.dinv);
-  h->fine.ncolours = colour_greedy(h->fine.A, P.colour_seed, 0, h->fine.colour);
+  h->fine.ncolours = colour_level(h->fine.A, P.colour_seed, 0, h->fine.colour);
   group_by_colour(h->fine);
   if (e) {
     h->e.assign(e, e + n);

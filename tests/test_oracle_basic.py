@@ -157,7 +157,7 @@ def _jones_plassmann(n, rp, ci, pr):
 def test_colouring(oracle, maker):
     n, rp, ci, w = maker()
     for level in (0, 3):
-        col, nc = oracle.colour(n, rp, ci, 0xC010, level)
+        col, nc = oracle.colour_greedy(n, rp, ci, 0xC010, level)
         rows = np.repeat(np.arange(n), np.diff(rp))
         assert np.all(col[rows] != col[ci])
         assert nc == col.max() + 1 <= np.diff(rp).max() + 1
@@ -165,6 +165,85 @@ def test_colouring(oracle, maker):
         assert np.array_equal(col, _greedy_colour(n, rp, ci, pr))
         jp, _ = _jones_plassmann(n, rp, ci, pr)
         assert np.array_equal(col, jp)
+
+
+def _bipartite_spectral(n, rp, ci):
+    """A connected graph is bipartite exactly when the largest eigenvalue of its
+    normalised Laplacian I - D^-1/2 W D^-1/2 equals 2 (the adjacency spectrum
+    is then symmetric); connectivity from the multiplicity of eigenvalue 0."""
+    W = np.zeros((n, n))
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    W[rows, ci] = 1.0
+    d = W.sum(axis=1)
+    if np.any(d == 0):
+        return n == 1, n == 1
+    s = 1.0 / np.sqrt(d)
+    ev = np.linalg.eigvalsh(np.eye(n) - s[:, None] * W * s[None, :])
+    connected = int(np.sum(np.abs(ev) < 1e-9)) == 1
+    return connected, connected and abs(ev[-1] - 2.0) < 1e-9
+
+
+def _random_graph(seed, n, m, bipartite):
+    u = I.uniform(seed, 2 * m)
+    a = np.minimum((u[0::2] * n).astype(np.int64), n - 1)
+    b = np.minimum((u[1::2] * n).astype(np.int64), n - 1)
+    if bipartite:  # edges only between even and odd ids
+        b = np.where((a - b) % 2 == 0, np.where(b + 1 < n, b + 1, b - 1), b)
+    keep = a != b
+    a2, b2 = I.canonical_edges(a[keep], b[keep])
+    return I.csr_from_edges(n, a2, b2, np.ones(len(a2)))
+
+
+def test_colouring_red_black(oracle):
+    """Connected bipartite graphs: two colours, the parity of the breadth-first
+    distance from vertex 0 (closed forms on grids, paths and even rings);
+    everything else: the greedy first-fit colouring."""
+    n, rp, ci, w = I.grid2d(13, 11)
+    col, nc = oracle.colour(n, rp, ci, 0xC010, 4)
+    v = np.arange(n)
+    assert nc == 2 and np.array_equal(col, (v % 13 + v // 13) % 2)
+    n, rp, ci, w = I.grid3d(8, 7, 6)
+    col, nc = oracle.colour(n, rp, ci, 0xC010, 0)
+    v = np.arange(n)
+    assert nc == 2 and np.array_equal(col, (v % 8 + (v // 8) % 7 + v // 56) % 2)
+    n, rp, ci, w = I.path(9)
+    col, nc = oracle.colour(n, rp, ci, 1, 0)
+    assert nc == 2 and np.array_equal(col, np.arange(9) % 2)
+    n, rp, ci, w = I.ring(10, 2)  # even cycle
+    col, nc = oracle.colour(n, rp, ci, 1, 0)
+    assert nc == 2 and np.array_equal(col, np.arange(10) % 2)
+    n, rp, ci, w = I.path(1)
+    col, nc = oracle.colour(n, rp, ci, 1, 0)
+    assert nc == 1 and list(col) == [0]
+    # odd cycle, triangles, two components: the greedy colouring
+    for g in (I.ring(11, 2), I.ring(40, 4), I.rgg(300, 2)):
+        n, rp, ci, w = g
+        col, nc = oracle.colour(n, rp, ci, 0xC010, 2)
+        gcol, gnc = oracle.colour_greedy(n, rp, ci, 0xC010, 2)
+        assert nc == gnc and np.array_equal(col, gcol)
+    n1, a1, b1 = I.grid2d_edges(4, 4)
+    a = np.concatenate([a1, a1 + 16]); b = np.concatenate([b1, b1 + 16])
+    n, rp, ci, w = I.csr_from_edges(32, a, b, np.ones(len(a)))
+    col, nc = oracle.colour(n, rp, ci, 5, 1)
+    gcol, gnc = oracle.colour_greedy(n, rp, ci, 5, 1)
+    assert np.array_equal(col, gcol) and nc == gnc
+    # random graphs against the spectral test
+    seen = set()
+    for seed in range(40):
+        n = 8 + seed % 23
+        g = _random_graph(100 + seed, n, int(n * (1.0 + (seed % 5) * 0.4)), bipartite=seed % 2 == 0)
+        n, rp, ci, w = g
+        connected, bip = _bipartite_spectral(n, rp, ci)
+        col, nc = oracle.colour(n, rp, ci, 9, seed)
+        rows = np.repeat(np.arange(n), np.diff(rp))
+        assert np.all(col[rows] != col[ci])
+        if bip:
+            assert nc == 2 and col[0] == 0
+        else:
+            gcol, gnc = oracle.colour_greedy(n, rp, ci, 9, seed)
+            assert nc == gnc and np.array_equal(col, gcol)
+        seen.add((connected, bip))
+    assert {(True, True), (True, False), (False, False)} <= seen
 
 
 # ---------------------------------------------------------------------------
