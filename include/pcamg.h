@@ -286,9 +286,14 @@ pcamg_status pcamg_setup_learned(const pcamg_graph* g, const double* rhs, const 
 pcamg_status pcamg_laplacian(int32_t n, const int32_t* rp, const int32_t* ci, const double* w, double* aval,
                              double* d, double* dinv, void* stream);
 
-/* Multicolouring used by the Gauss-Seidel smoother: Jones-Plassmann rounds
- * with SplitMix64 priorities (seed, level) = greedy first-fit in descending
- * priority order.  colour: device int32 [n]; *ncolours: host. */
+/* Multicolouring used by the Gauss-Seidel smoother (Sec. 4 names the smoother
+ * only as Gauss-Seidel; the ordering is this library's).  A connected
+ * bipartite graph gets the red-black colouring: parity of the breadth-first
+ * distance from vertex 0 (2 colours, 1 if n = 1).  Any other graph gets
+ * Jones-Plassmann rounds with SplitMix64 priorities (seed, level) = greedy
+ * first-fit in descending (priority, id) order.  rp, ci: device CSR of a
+ * symmetric pattern without self loops; colour: device int32 [n], written;
+ * *ncolours: host.  PCAMG_EINVAL on null arguments or n < 0. */
 pcamg_status pcamg_colour(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed, int32_t level,
                           int32_t* colour, int32_t* ncolours, void* stream);
 

@@ -323,6 +323,99 @@ int32_t colour_jp(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed
 }
 
 // ---------------------------------------------------------------------------
+// Red-black colouring of a connected bipartite graph: colour = parity of the
+// breadth-first depth from vertex 0.  Breadth-first search in frontier rounds;
+// round d expands the vertices of depth d, claiming unvisited neighbours for
+// depth d + 1 with a compare-and-swap (the frontier order is irrelevant).  An
+// edge between two vertices of depth d closes an odd cycle: every such edge is
+// seen while depth d is expanded, so the graph is bipartite exactly when no
+// round sees one.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+    bfs_round_kernel(const int32_t* __restrict__ cnt_in, const int32_t* __restrict__ in, int32_t* __restrict__ cnt_out,
+                     int32_t* __restrict__ out, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                     int32_t* depth, int32_t d, int32_t* odd_flag) {
+  const int32_t m = *cnt_in;
+  const int32_t stride = gridDim.x * blockDim.x;
+  const int lane = threadIdx.x & 63;
+  bool odd = false;
+  for (int32_t base = blockIdx.x * blockDim.x; base < m; base += stride) {
+    const int32_t t = base + threadIdx.x;
+    const bool act = t < m;
+    const int32_t v = act ? in[t] : 0;
+    const int32_t k0 = act ? rp[v] : 0;
+    const int32_t len = act ? rp[v + 1] - k0 : 0;
+    const int32_t span = wave_max_len(len);
+    for (int32_t j = 0; j < span; ++j) {
+      bool claim = false;
+      int32_t u = 0;
+      if (j < len) {
+        u = ci[k0 + j];
+        const int32_t du = depth[u];  // depths below d + 1 were set by earlier rounds
+        if (du == d) odd = true;
+        else if (du < 0) claim = atomicCAS(&depth[u], -1, d + 1) == -1;
+      }
+      const unsigned long long bal = __ballot(claim);
+      if (!bal) continue;
+      const int first = __ffsll((long long)bal) - 1;
+      int32_t at = 0;
+      if (lane == first) at = atomicAdd(cnt_out, __popcll(bal));
+      at = __shfl(at, first, 64);
+      if (claim) out[at + __popcll(bal & ((1ull << lane) - 1ull))] = u;
+    }
+  }
+  if (odd) *odd_flag = 1;
+}
+
+__global__ void parity_kernel(int32_t n, const int32_t* __restrict__ depth, int32_t* __restrict__ colour) {
+  const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) colour[v] = depth[v] & 1;
+}
+
+bool colour_bipartite(int32_t n, const int32_t* rp, const int32_t* ci, int32_t* colour, hipStream_t s) {
+  if (n <= 0) return false;
+  // st[0..RMAX]: frontier sizes of the rounds of one batch; st[RMAX + 1]: odd cycle seen
+  constexpr int RMAX = 16;
+  DVec<int32_t> depth(n), list0(n), list1(n), st(RMAX + 2);
+  fill_i32(depth.p, -1, n, s);
+  fill_i32(depth.p, 0, 1, s);
+  fill_i32(list0.p, 0, 1, s);
+  fill_i32(st.p, 0, RMAX + 2, s);
+  fill_i32(st.p, 1, 1, s);
+  const unsigned grid = std::min<unsigned>(grid_for(n, 256), 1024);
+  int64_t reached = 1;
+  int32_t d = 0;
+  // batches of R rounds (R even, non-decreasing: the frontier is in list0 after
+  // each batch and counters beyond R are still zero); the first batches are
+  // short so that a non-bipartite graph is rejected after few rounds
+  for (int R = 2;; R = std::min(2 * R, RMAX)) {
+    for (int r = 0; r < R; ++r, ++d) {
+      const int32_t* in = (r & 1) ? list1.p : list0.p;
+      int32_t* out = (r & 1) ? list0.p : list1.p;
+      bfs_round_kernel<<<grid, 256, 0, s>>>(st.p + r, in, st.p + r + 1, out, rp, ci, depth.p, d, st.p + RMAX + 1);
+      PCAMG_LAUNCHED();
+    }
+    const std::vector<int32_t> h = to_host(st.p, RMAX + 2, s);
+    if (h[RMAX + 1]) return false;
+    for (int r = 1; r <= R; ++r) reached += h[r];
+    if (h[R] == 0) break;
+    require(d <= n + RMAX, PCAMG_EHIP, "breadth-first search made no progress");
+    jp_carry_kernel<<<1, 64, 0, s>>>(st.p, R);
+    PCAMG_LAUNCHED();
+  }
+  if (reached != n) return false;
+  parity_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, depth.p, colour);
+  PCAMG_LAUNCHED();
+  return true;
+}
+
+int32_t colour_level(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed, int32_t level, int32_t* colour,
+                     hipStream_t s) {
+  if (colour_bipartite(n, rp, ci, colour, s)) return n > 1 ? 2 : 1;
+  return colour_jp(n, rp, ci, seed, level, colour, s);
+}
+
+// ---------------------------------------------------------------------------
 // Gauss-Seidel pass over the rows of one colour (rows row0..row1-1 of a
 // colour-sorted matrix): s = sum_j a_ij x_j as an fma chain in CSR order,
 // x_i = (b_i - s) * dinv_i.  Rows of one colour are independent.  G lanes per
@@ -332,7 +425,7 @@ template <typename T, int G>
 __global__ void __launch_bounds__(256)
     gs_kernel(int32_t row0, int32_t row1, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
               const T* __restrict__ av, const T* __restrict__ dinv, const T* __restrict__ b, T* __restrict__ x) {
-  const int32_t i = row0 + (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) / G);
+  const int32_t i = row0 + (int32_t)((xcd_block() * blockDim.x + threadIdx.x) / G);
   if constexpr (G == 1) {
     if (i >= row1) return;
     const T s = row_chain1<T>(rp[i], rp[i + 1], ci, av, x, (T)0);
@@ -394,7 +487,7 @@ __global__ void __launch_bounds__(256)
     residual_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                     const T* __restrict__ av, const T* __restrict__ d, const T* __restrict__ b,
                     const T* __restrict__ x, T* __restrict__ r) {
-  const int32_t i = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) / G);
+  const int32_t i = (int32_t)((xcd_block() * blockDim.x + threadIdx.x) / G);
   if constexpr (G == 1) {
     if (i >= n) return;
     const T s = row_chain1<T>(rp[i], rp[i + 1], ci, av, x, d[i] * x[i]);

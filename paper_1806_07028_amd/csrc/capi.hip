@@ -582,7 +582,7 @@ pcamg_status pcamg_colour(int32_t n, const int32_t* rp, const int32_t* ci, uint6
                           int32_t* colour, int32_t* ncolours, void* stream) {
   return guarded_s(as_stream(stream), [&] {
     require(n >= 0 && rp && colour && ncolours, PCAMG_EINVAL, "null argument");
-    *ncolours = colour_jp(n, rp, ci, seed, level, colour, as_stream(stream));
+    *ncolours = colour_level(n, rp, ci, seed, level, colour, as_stream(stream));
   });
 }
 

@@ -173,7 +173,14 @@ void zsub_dot_f64(const double* z, const double* rn, const double* r, size_t n, 
 void laplacian(int32_t n, const int32_t* rp, const double* w, double* aval, double* d, double* dinv,
                size_t nnz, hipStream_t s);
 int32_t colour_jp(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed, int32_t level, int32_t* colour,
-                  hipStream_t s);  // synchronises; returns number of colours
+                  hipStream_t s);
+// Red-black colouring (parity of the breadth-first depth from vertex 0) when
+// the graph is connected and bipartite; returns false otherwise.
+bool colour_bipartite(int32_t n, const int32_t* rp, const int32_t* ci, int32_t* colour, hipStream_t s);
+// The smoother's colouring of a level graph: red-black if connected and
+// bipartite, Jones-Plassmann otherwise.  Returns the number of colours.
+int32_t colour_level(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed, int32_t level, int32_t* colour,
+                     hipStream_t s);  // synchronises; returns number of colours
 
 template <typename T>
 void gs_colour(int32_t row0, int32_t row1, const int32_t* rp, const int32_t* ci, const T* av, const T* dinv,

@@ -30,6 +30,17 @@ __device__ __forceinline__ const PCAMG_GLOBAL T* gptr(const T* p) {
   return (const PCAMG_GLOBAL T*)p;
 }
 
+// Workgroups of a launch are dispatched round-robin over the 8 XCDs, each
+// with its own L2.  This maps the launch's workgroups to tiles so that each XCD
+// takes a contiguous range of tiles (XCD x: tiles x*q + min(x, r) + [0, q + (x < r)),
+// q = nb / 8, r = nb % 8), which keeps the vector gathers of neighbouring rows
+// in one L2.  A bijection on [0, nb) for every nb.
+__device__ __forceinline__ uint32_t xcd_block() {
+  const uint32_t nb = gridDim.x, b = blockIdx.x;
+  const uint32_t q = nb >> 3, r = nb & 7, x = b & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
+
 // The index, value and vector pointers are template parameters so callers can
 // pass pointers qualified with an address space (global or LDS) and get the
 // matching load instructions.

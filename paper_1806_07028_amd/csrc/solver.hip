@@ -86,7 +86,7 @@ void ctx_init(pcamg_ctx* c, const pcamg_graph* g, const pcamg_params* p) {
   copy_d2d(c->rp.p, g->row_ptr, n + 1, s);
   copy_d2d(c->ci.p, g->col_idx, nnz, s);
   laplacian(n, c->rp.p, g->weight, c->av.p, c->d.p, c->dinv.p, nnz, s);
-  c->ncol = colour_jp(n, c->rp.p, c->ci.p, c->P.colour_seed, 0, c->colour.p, s);
+  c->ncol = colour_level(n, c->rp.p, c->ci.p, c->P.colour_seed, 0, c->colour.p, s);
   c->M0 = make_level_matrix(n, nnz, c->rp.p, c->ci.p, c->av.p, c->d.p, c->dinv.p, c->colour.p, c->ncol,
                             c->P.row_lanes, s);
   sync(s);
@@ -268,7 +268,7 @@ std::unique_ptr<Hierarchy> build_hierarchy(pcamg_ctx* c, const double* e_nat) {
     C.o_nb.resize(2 * (size_t)nc);
     shorten_paths(L.n, L.nb, L.pid.p, L.pos.p, nc, L.agg.p, C.o_nb.p, s);
     C.o_colour.resize(nc);
-    C.ncol = colour_jp(nc, C.o_rp.p, C.o_ci.p, P.colour_seed, l + 1, C.o_colour.p, s);
+    C.ncol = colour_level(nc, C.o_rp.p, C.o_ci.p, P.colour_seed, l + 1, C.o_colour.p, s);
     C.rp = C.o_rp.p;
     C.ci = C.o_ci.p;
     C.av = C.o_av.p;

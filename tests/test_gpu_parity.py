@@ -502,7 +502,7 @@ def test_colour_dense_levels(gpu, oracle):
     m = a != b
     a2, b2 = I.canonical_edges(a[m], b[m])
     cases.append(I.csr_from_edges(n, a2, b2, np.ones(len(a2))))
-    cases.append(I.grid2d(50, 50))  # sparse, same size range
+    cases.append(I.rgg(2500, 5))  # sparse, same size range
     for g in cases:
         n, rp, ci, w = g
         for level in (0, 3):
@@ -510,6 +510,39 @@ def test_colour_dense_levels(gpu, oracle):
             rcol, rnc = oracle.colour(n, rp, ci, 0xC010, level)
             assert nc == rnc
             same(host(col), rcol)
+
+
+def _star(n):
+    a = np.zeros(n - 1, dtype=np.int64)
+    b = np.arange(1, n, dtype=np.int64)
+    return I.csr_from_edges(n, a, b, np.ones(n - 1))
+
+
+def _two_grids():
+    n1, a1, b1 = I.grid2d_edges(30, 20)
+    a = np.concatenate([a1, a1 + n1])
+    b = np.concatenate([b1, b1 + n1])
+    return I.csr_from_edges(2 * n1, a, b, np.ones(len(a)))
+
+
+@pytest.mark.parametrize("name,make", [
+    ("grid3d_64", lambda: I.grid3d(64, 64, 64)),   # bipartite, 190 frontier rounds
+    ("path_3000", lambda: I.path(3000)),           # bipartite, 2999 rounds
+    ("star_5000", lambda: _star(5000)),            # one round claims n - 1 vertices
+    ("ring_4001", lambda: I.ring(4001, 2)),         # odd cycle seen only at depth 2000
+    ("two_grids", _two_grids),                     # bipartite but not connected
+    ("single", lambda: I.path(1)),
+])
+def test_colour_red_black(gpu, oracle, name, make):
+    """Red-black colouring of connected bipartite graphs (breadth-first depth
+    parity) and the Jones-Plassmann fallback otherwise: bit-exact with the
+    oracle."""
+    n, rp, ci, w = make()
+    print(f"colour_red_black {name} n={n}", flush=True)
+    col, nc = gpu.stages.colour(rp, ci, 0xC010, 1)
+    rcol, rnc = oracle.colour(n, rp, ci, 0xC010, 1)
+    assert nc == rnc
+    same(host(col), rcol)
 
 
 @pytest.mark.parametrize("shape,dmax", [((24, 24, 16), 6144), ((32, 32, 32), 12288)])
