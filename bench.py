@@ -124,7 +124,7 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gs_kernel_f32_128cube_hbm_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gs_sell_kernel_f32_128cube_hbm_traffic.md")
 
 
 def measured_traffic():
@@ -168,7 +168,7 @@ def roofline_only(args):
         dst.copy_(src)
     torch.cuda.synchronize()
     r32 = roof["f32"]
-    print(json.dumps({"kernel": "gs_kernel<float, 1>", "launches": r32["launches"],
+    print(json.dumps({"kernel": "gs_sell_kernel<float>", "launches": r32["launches"],
                       "avg_launch_us": 1e3 * r32["ms"] / r32["launches"],
                       "bytes_per_launch": r32["bytes"] / r32["launches"], "gbs": r32["gbs"],
                       "f64_gbs": roof["f64"]["gbs"], "copy_bytes": 2 * src.numel() * 4, "copies": 3,
@@ -396,7 +396,7 @@ def main():
     r32 = roof["f32"]
     roofline = {"bound": "hbm", "achieved": round(r32["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(r32["gbs"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                "kernel": "gs_kernel<float, 1> (finest-level multicolour Gauss-Seidel pass, one thread per row)",
+                "kernel": "gs_sell_kernel<float> (finest-level Gauss-Seidel colour pass, red-black order, sliced-ELL matrix, one thread per row)",
                 "avg_launch_us": round(1e3 * r32["ms"] / r32["launches"], 2),
                 "bytes_per_launch": round(r32["bytes"] / r32["launches"]),
                 "f64_gbs": round(roof["f64"]["gbs"], 1)}

@@ -460,6 +460,26 @@ void gs_colour(int32_t row0, int32_t row1, const int32_t* rp, const int32_t* ci,
   }
 }
 
+// Same on the sliced-ELL copy of the matrix (one thread per row).
+template <typename T>
+__global__ void __launch_bounds__(256)
+    gs_sell_kernel(int32_t row0, int32_t row1, const int32_t* __restrict__ rp, const int32_t* __restrict__ woff,
+                   const int32_t* __restrict__ sci, const T* __restrict__ sav, const T* __restrict__ dinv,
+                   const T* __restrict__ b, T* __restrict__ x) {
+  const int32_t i = row0 + (int32_t)(xcd_block() * blockDim.x + threadIdx.x);
+  if (i >= row1) return;
+  const T s = sell_chain<T>(64 * woff[i >> 6] + (i & 63), rp[i + 1] - rp[i], sci, sav, x, (T)0);
+  x[i] = (b[i] - s) * dinv[i];
+}
+
+template <typename T>
+void gs_colour_sell(int32_t row0, int32_t row1, const int32_t* rp, const int32_t* woff, const int32_t* sci,
+                    const T* sav, const T* dinv, const T* b, T* x, hipStream_t s) {
+  if (row1 <= row0) return;
+  gs_sell_kernel<T><<<grid_for(row1 - row0, 256), 256, 0, s>>>(row0, row1, rp, woff, sci, sav, dinv, b, x);
+  PCAMG_LAUNCHED();
+}
+
 // Same over an explicit row list (natural-order stage entry point).
 template <typename T>
 __global__ void gs_rows_kernel(int32_t nrows, const int32_t* __restrict__ rows, const int32_t* __restrict__ rp,
@@ -527,6 +547,78 @@ void spmv(int32_t n, const int32_t* rp, const int32_t* ci, const T* av, const T*
   residual<T>(n, rp, ci, av, d, nullptr, x, y, s, lanes);
 }
 
+// Residual (b != nullptr) or product on the sliced-ELL copy.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    residual_sell_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ woff,
+                         const int32_t* __restrict__ sci, const T* __restrict__ sav, const T* __restrict__ d,
+                         const T* __restrict__ b, const T* __restrict__ x, T* __restrict__ r) {
+  const int32_t i = (int32_t)(xcd_block() * blockDim.x + threadIdx.x);
+  if (i >= n) return;
+  const T s = sell_chain<T>(64 * woff[i >> 6] + (i & 63), rp[i + 1] - rp[i], sci, sav, x, d[i] * x[i]);
+  r[i] = b ? b[i] - s : s;
+}
+
+template <typename T>
+void residual_sell(int32_t n, const int32_t* rp, const int32_t* woff, const int32_t* sci, const T* sav, const T* d,
+                   const T* b, const T* x, T* r, hipStream_t s) {
+  if (n <= 0) return;
+  residual_sell_kernel<T><<<grid_for(n, 256), 256, 0, s>>>(n, rp, woff, sci, sav, d, b, x, r);
+  PCAMG_LAUNCHED();
+}
+
+// ---------------------------------------------------------------------------
+// Sliced-ELL copy (SELL-64) of a level matrix with short rows: slice q holds
+// rows 64q .. 64q + 63, entry j of row 64q + l at 64 woff[q] + 64 j + l, each
+// slice padded to its longest row (woff = exclusive sum of the slice widths;
+// padding slots are never read).  With CSR rows of a few entries a
+// wavefront's load of one entry per row spreads over a dozen cache lines;
+// here it is one contiguous segment.  Entries keep their CSR order.
+// ---------------------------------------------------------------------------
+__global__ void sell_width_kernel(int32_t n, const int32_t* __restrict__ rp, int32_t* __restrict__ width) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;  // blockDim a multiple of 64: wave = slice
+  const int32_t w = wave_max_len(i < n ? rp[i + 1] - rp[i] : 0);
+  if ((threadIdx.x & 63) == 0 && i < n) width[i >> 6] = w;
+}
+
+__global__ void sell_fill_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                 const double* __restrict__ av, const float* __restrict__ av32,
+                                 const int32_t* __restrict__ woff, int32_t* __restrict__ sci,
+                                 double* __restrict__ sav, float* __restrict__ sav32) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t base = 64 * woff[i >> 6] + (i & 63);
+  const int32_t k0 = rp[i], len = rp[i + 1] - k0;
+  for (int32_t j = 0; j < len; ++j) {
+    sci[base + 64 * j] = ci[k0 + j];
+    sav[base + 64 * j] = av[k0 + j];
+    sav32[base + 64 * j] = av32[k0 + j];
+  }
+}
+
+bool sell_build(int32_t n, int32_t nnz, const int32_t* rp, const int32_t* ci, const double* av, const float* av32,
+                DVec<int32_t>& woff, DVec<int32_t>& sci, DVec<double>& sav, DVec<float>& sav32, hipStream_t s) {
+  if (n <= 0 || nnz <= 0) return false;
+  const int32_t ns = (n + 63) / 64;
+  DVec<int32_t> width(ns), total(1);
+  sell_width_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, rp, width.p);
+  PCAMG_LAUNCHED();
+  // a slice's width is at most the sum of its rows' lengths: the total fits int32
+  woff.resize(ns);
+  scan_exclusive_i32(width.p, woff.p, ns, total.p, s);
+  const int64_t padded = 64ll * read_scalar(total.p, s);
+  if (padded > 2ll * nnz || padded > (int64_t)INT32_MAX) {
+    woff.resize(0);
+    return false;
+  }
+  sci.resize(padded);
+  sav.resize(padded);
+  sav32.resize(padded);
+  sell_fill_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, rp, ci, av, av32, woff.p, sci.p, sav.p, sav32.p);
+  PCAMG_LAUNCHED();
+  return true;
+}
+
 // Restriction b_c = P^T r: fma chain over the members of each aggregate in
 // ascending (natural) order.  pval == nullptr: boolean P.  With xc, the
 // coarse x is started too: mode 1 zero; mode 2 the coarse level's first
@@ -581,6 +673,10 @@ void prolong_add(int32_t n, const int32_t* agg, const T* pval, const T* xc, T* x
                             T*, hipStream_t, int);                                                              \
   template void spmv<T>(int32_t, const int32_t*, const int32_t*, const T*, const T*, const T*, T*, hipStream_t, \
                         int);                                                                                   \
+  template void gs_colour_sell<T>(int32_t, int32_t, const int32_t*, const int32_t*, const int32_t*, const T*,  \
+                                  const T*, const T*, T*, hipStream_t);                                         \
+  template void residual_sell<T>(int32_t, const int32_t*, const int32_t*, const int32_t*, const T*, const T*,  \
+                                 const T*, const T*, T*, hipStream_t);                                          \
   template void restrict_members<T>(int32_t, const int32_t*, const int32_t*, const T*, const T*, T*,          \
                                     hipStream_t, T*, const T*, int32_t, int);                                   \
   template void prolong_add<T>(int32_t, const int32_t*, const T*, const T*, T*, hipStream_t);

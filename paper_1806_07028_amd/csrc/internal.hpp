@@ -194,6 +194,21 @@ void residual(int32_t n, const int32_t* rp, const int32_t* ci, const T* av, cons
 template <typename T>
 void spmv(int32_t n, const int32_t* rp, const int32_t* ci, const T* av, const T* d, const T* x, T* y,
           hipStream_t s, int lanes = 1);
+// Sliced-ELL (SELL-64) copy of a matrix with short rows: slice q = rows
+// 64q .. 64q + 63, entry j of row 64q + l at 64 woff[q] + 64 j + l.  Returns
+// false (woff emptied, nothing else allocated) when the padded slots would be
+// more than twice the entries (padding is never read, so it costs memory, not
+// bandwidth).  Synchronises.
+bool sell_build(int32_t n, int32_t nnz, const int32_t* rp, const int32_t* ci, const double* av, const float* av32,
+                DVec<int32_t>& woff, DVec<int32_t>& sci, DVec<double>& sav, DVec<float>& sav32, hipStream_t s);
+// Gauss-Seidel colour pass and residual (b == nullptr: product) on that copy;
+// rp still gives the row lengths.  Same results as the CSR kernels.
+template <typename T>
+void gs_colour_sell(int32_t row0, int32_t row1, const int32_t* rp, const int32_t* woff, const int32_t* sci,
+                    const T* sav, const T* dinv, const T* b, T* x, hipStream_t s);
+template <typename T>
+void residual_sell(int32_t n, const int32_t* rp, const int32_t* woff, const int32_t* sci, const T* sav, const T* d,
+                   const T* b, const T* x, T* r, hipStream_t s);
 // with xc: mode 1 also zeroes xc, mode 2 also does the coarse first colour
 // pass from zero (rows < c1: xc = bc * dinvc, others 0)
 template <typename T>

@@ -79,6 +79,45 @@ __device__ __forceinline__ T row_chain1(int32_t k0, int32_t k1, PI ci, PA av, PX
   return s;
 }
 
+// Row of a sliced-ELL matrix (slices of 64 rows, entry j of a row at
+// base + 64 j): the same batches of eight and the same fma order as
+// row_chain1, so the row sum is identical; a wavefront's load of entry j of
+// its 64 rows is one contiguous segment.
+template <typename T, typename PI, typename PA, typename PX>
+__device__ __forceinline__ T sell_chain(int32_t base, int32_t len, PI ci, PA av, PX x, T s) {
+  constexpr int U = 8;
+  int32_t j = 0;
+  for (; j + U <= len; j += U) {
+    int32_t c[U];
+    T a[U], v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      c[u] = ci[base + 64 * (j + u)];
+      a[u] = av[base + 64 * (j + u)];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = x[c[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) s = fma(a[u], v[u], s);
+  }
+  const int32_t rem = len - j;
+  if (rem > 0) {
+    int32_t c[U];
+    T a[U], v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      c[u] = u < rem ? ci[base + 64 * (j + u)] : 0;
+      a[u] = u < rem ? av[base + 64 * (j + u)] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = u < rem ? x[c[u]] : (T)0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (u < rem) s = fma(a[u], v[u], s);
+  }
+  return s;
+}
+
 // Largest len over the wavefront, as a wave-uniform value.
 __device__ __forceinline__ int32_t wave_max_len(int32_t len) {
 #pragma unroll

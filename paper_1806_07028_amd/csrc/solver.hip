@@ -21,6 +21,10 @@ int32_t pick_lanes(int32_t n, int32_t nnz, int32_t forced) {
   return avg <= 10.0 ? 1 : avg <= 24.0 ? 4 : 16;
 }
 
+// Levels at most this size run in the single-workgroup tail or are latency
+// bound: no sliced-ELL copy.
+constexpr int32_t SELL_MIN_N = 4096;
+
 std::shared_ptr<LevelMatrix> make_level_matrix(int32_t n, int32_t nnz, const int32_t* rp, const int32_t* ci,
                                                const double* av, const double* d, const double* dinv,
                                                const int32_t* colour, int32_t ncol, int32_t row_lanes,
@@ -50,6 +54,9 @@ std::shared_ptr<LevelMatrix> make_level_matrix(int32_t n, int32_t nnz, const int
   M->dinv32.resize(n);
   permute_csr(n, M->perm.p, M->iperm.p, rp, ci, av, d, dinv, M->rp.p, M->ci.p, M->av.p, M->av32.p, M->d.p,
               M->dinv.p, M->d32.p, M->dinv32.p, s);
+  // short rows on a level large enough for launched passes: sliced-ELL copy
+  if (M->lanes == 1 && n > SELL_MIN_N)
+    sell_build(n, nnz, M->rp.p, M->ci.p, M->av.p, M->av32.p, M->woff, M->sci, M->sav, M->sav32, s);
   return M;
 }
 
@@ -70,6 +77,30 @@ struct NatLevel {
 void sync(hipStream_t s) { PCAMG_HIP(hipStreamSynchronize(s)); }
 
 }  // namespace
+
+void smooth_colour(const LevelMatrix& A, int k, const double* b, double* x, hipStream_t s) {
+  if (A.sell())
+    gs_colour_sell<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.woff.p, A.sci.p, A.sav.p, A.dinv.p, b, x, s);
+  else
+    gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s, A.lanes);
+}
+
+void smooth_colour(const LevelMatrix& A, int k, const float* b, float* x, hipStream_t s) {
+  if (A.sell())
+    gs_colour_sell<float>(A.coff[k], A.coff[k + 1], A.rp.p, A.woff.p, A.sci.p, A.sav32.p, A.dinv32.p, b, x, s);
+  else
+    gs_colour<float>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s, A.lanes);
+}
+
+void level_residual(const LevelMatrix& A, const double* b, const double* x, double* r, hipStream_t s) {
+  if (A.sell()) residual_sell<double>(A.n, A.rp.p, A.woff.p, A.sci.p, A.sav.p, A.d.p, b, x, r, s);
+  else residual<double>(A.n, A.rp.p, A.ci.p, A.av.p, A.d.p, b, x, r, s, A.lanes);
+}
+
+void level_residual(const LevelMatrix& A, const float* b, const float* x, float* r, hipStream_t s) {
+  if (A.sell()) residual_sell<float>(A.n, A.rp.p, A.woff.p, A.sci.p, A.sav32.p, A.d32.p, b, x, r, s);
+  else residual<float>(A.n, A.rp.p, A.ci.p, A.av32.p, A.d32.p, b, x, r, s, A.lanes);
+}
 
 void ctx_init(pcamg_ctx* c, const pcamg_graph* g, const pcamg_params* p) {
   hipStream_t s = c->s;
@@ -464,7 +495,7 @@ void cycle64(pcamg_ctx* c, Hierarchy& H, int l, const double* b, double* x, int 
   Level& L = H.lv[l];
   const LevelMatrix& A = *L.A;
   for (int k = skip; k < A.ncol; ++k)
-    gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s, A.lanes);
+    smooth_colour(A, k, b, x, s);
   Level& N = H.lv[l + 1];
   const LevelMatrix& AN = *N.A;
   const int calls = (gamma > 1 && l + 2 < nl) ? gamma : 1;
@@ -473,7 +504,7 @@ void cycle64(pcamg_ctx* c, Hierarchy& H, int l, const double* b, double* x, int 
   // for the tail, else zero with its first colour pass done here
   const bool launched_child = !dense && l + 2 < nl && l + 1 != H.tail_start;
   const int mode = dense || l + 2 == nl ? 0 : launched_child ? 2 : 1;
-  residual<double>(A.n, A.rp.p, A.ci.p, A.av.p, A.d.p, b, x, L.r.p, s, A.lanes);
+  level_residual(A, b, x, L.r.p, s);
   restrict_members<double>(L.T.nc, L.T.moff.p, L.T.mem.p, L.T.pval.p, L.r.p, N.b.p, s, N.x.p, AN.dinv.p,
                         AN.coff.size() > 1 ? AN.coff[1] : 0, mode);
   if (dense) {  // both sub-cycles below at once
@@ -483,7 +514,7 @@ void cycle64(pcamg_ctx* c, Hierarchy& H, int l, const double* b, double* x, int 
   }
   prolong_add<double>(A.n, L.T.agg.p, L.T.pval.p, N.x.p, x, s);
   for (int k = A.ncol - 1; k >= 0; --k)
-    gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s, A.lanes);
+    smooth_colour(A, k, b, x, s);
 }
 
 void cycle32(pcamg_ctx* c, Hierarchy& H, int l, const float* b, float* x, int gamma, int skip) {
@@ -507,7 +538,7 @@ void cycle32(pcamg_ctx* c, Hierarchy& H, int l, const float* b, float* x, int ga
   Level& L = H.lv[l];
   const LevelMatrix& A = *L.A;
   for (int k = skip; k < A.ncol; ++k)
-    gs_colour<float>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s, A.lanes);
+    smooth_colour(A, k, b, x, s);
   Level& N = H.lv[l + 1];
   const LevelMatrix& AN = *N.A;
   const int calls = (gamma > 1 && l + 2 < nl) ? gamma : 1;
@@ -516,7 +547,7 @@ void cycle32(pcamg_ctx* c, Hierarchy& H, int l, const float* b, float* x, int ga
   // for the tail, else zero with its first colour pass done here
   const bool launched_child = !dense && l + 2 < nl && l + 1 != H.tail_start;
   const int mode = dense || l + 2 == nl ? 0 : launched_child ? 2 : 1;
-  residual<float>(A.n, A.rp.p, A.ci.p, A.av32.p, A.d32.p, b, x, L.r32.p, s, A.lanes);
+  level_residual(A, b, x, L.r32.p, s);
   restrict_members<float>(L.T.nc, L.T.moff.p, L.T.mem.p, L.T.pval32.p, L.r32.p, N.b32.p, s, N.x32.p, AN.dinv32.p,
                         AN.coff.size() > 1 ? AN.coff[1] : 0, mode);
   if (dense) {  // both sub-cycles below at once
@@ -526,7 +557,7 @@ void cycle32(pcamg_ctx* c, Hierarchy& H, int l, const float* b, float* x, int ga
   }
   prolong_add<float>(A.n, L.T.agg.p, L.T.pval32.p, N.x32.p, x, s);
   for (int k = A.ncol - 1; k >= 0; --k)
-    gs_colour<float>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s, A.lanes);
+    smooth_colour(A, k, b, x, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -716,9 +747,9 @@ void relax_perm(pcamg_ctx* c, double* e_perm, const double* zero, int sweeps) {
   const LevelMatrix& A = *c->M0;
   for (int q = 0; q < sweeps; ++q) {
     for (int k = 0; k < A.ncol; ++k)
-      gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, zero, e_perm, c->s, A.lanes);
+      smooth_colour(A, k, zero, e_perm, c->s);
     for (int k = A.ncol - 1; k >= 0; --k)
-      gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, zero, e_perm, c->s, A.lanes);
+      smooth_colour(A, k, zero, e_perm, c->s);
   }
 }
 }  // namespace
@@ -790,7 +821,7 @@ void approx_error(pcamg_ctx* c, int Re, const double* r, double* e, int* wcycles
   copy_d2d(p.p, z.p, n, s);
   double rz = dot(rr.p, z.p);
   for (int t = 0; t < steps; ++t) {
-    spmv<double>(n, A.rp.p, A.ci.p, A.av.p, A.d.p, p.p, q.p, s, A.lanes);
+    level_residual(A, nullptr, p.p, q.p, s);
     const double pq = dot(p.p, q.p);
     if (!(pq > 0.0)) break;
     const double alpha = rz / pq;
@@ -835,7 +866,7 @@ void solve(pcamg_ctx* c, double* x_nat, pcamg_stats* st) {
     sum_f64(v, n, scal.p + 1, s);
     sub_mean_f64(v, scal.p + 1, n, s);
   };
-  auto res_of = [&](const double* xx, double* rr) { residual<double>(n, A.rp.p, A.ci.p, A.av.p, A.d.p, b.p, xx, rr, s, A.lanes); };
+  auto res_of = [&](const double* xx, double* rr) { level_residual(A, b.p, xx, rr, s); };
   std::vector<double> hist{1.0};
   std::vector<double> conv, conv_all;
   int rebuilds = 0, k = 0, status = PCAMG_OK;
@@ -934,7 +965,7 @@ void solve(pcamg_ctx* c, double* x_nat, pcamg_stats* st) {
       copy_d2d(p.p, z.p, n, s);
       double rz = dot(r.p, z.p);
       while (k < P.max_iter) {
-        spmv<double>(n, A.rp.p, A.ci.p, A.av.p, A.d.p, p.p, q.p, s, A.lanes);
+        level_residual(A, nullptr, p.p, q.p, s);
         const double pq = dot(p.p, q.p);
         if (!(pq > 0.0)) { status = PCAMG_EBREAKDOWN; break; }
         const double alpha = rz / pq;
@@ -1039,15 +1070,15 @@ void bench_smoother(pcamg_ctx* c, int prec, int sweeps, double* ms, int64_t* lau
   auto sweep = [&]() {
     for (int k = 0; k < A.ncol; ++k) {
       if (prec == PCAMG_PREC_F32)
-        gs_colour<float>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b32.p, x32.p, s, A.lanes);
+        smooth_colour(A, k, b32.p, x32.p, s);
       else
-        gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b.p, x.p, s, A.lanes);
+        smooth_colour(A, k, b.p, x.p, s);
     }
     for (int k = A.ncol - 1; k >= 0; --k) {
       if (prec == PCAMG_PREC_F32)
-        gs_colour<float>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b32.p, x32.p, s, A.lanes);
+        smooth_colour(A, k, b32.p, x32.p, s);
       else
-        gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b.p, x.p, s, A.lanes);
+        smooth_colour(A, k, b.p, x.p, s);
     }
   };
   sweep();  // warm-up

@@ -18,7 +18,20 @@ struct LevelMatrix {
   DVec<double> av, d, dinv;
   DVec<float> av32, d32, dinv32;
   DVec<int32_t> perm, iperm;  // position -> natural id, natural id -> position
+  // sliced-ELL copy for the launched passes of short-row levels (woff empty:
+  // none); rp still gives the row lengths
+  DVec<int32_t> woff, sci;
+  DVec<double> sav;
+  DVec<float> sav32;
+  bool sell() const { return woff.p != nullptr; }
 };
+
+// Gauss-Seidel pass over colour k and residual (b == nullptr: product) of a
+// level matrix, on its sliced-ELL copy when it has one.
+void smooth_colour(const LevelMatrix& A, int k, const double* b, double* x, hipStream_t s);
+void smooth_colour(const LevelMatrix& A, int k, const float* b, float* x, hipStream_t s);
+void level_residual(const LevelMatrix& A, const double* b, const double* x, double* r, hipStream_t s);
+void level_residual(const LevelMatrix& A, const float* b, const float* x, float* r, hipStream_t s);
 
 // Transfer from a level to the next one (permuted numbering on both sides).
 struct Transfer {
