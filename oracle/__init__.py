@@ -80,6 +80,8 @@ def lib():
     L.or_xi.argtypes = [C.c_int, C.c_ulonglong, C.c_int, _f64p]
     L.or_colour_priority.argtypes = [C.c_ulonglong, C.c_int, C.c_int]
     L.or_colour_priority.restype = C.c_ulonglong
+    L.or_colour_key.argtypes = [C.c_ulonglong, C.c_int, C.c_int, C.c_int]
+    L.or_colour_key.restype = C.c_ulonglong
     L.or_laplacian.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p]
     L.or_colour.argtypes = [C.c_int, _i32p, _i32p, C.c_ulonglong, C.c_int, _i32p]
     L.or_colour.restype = C.c_int
@@ -155,6 +157,10 @@ def colour_priority(seed: int, level: int, v: int) -> int:
     return int(lib().or_colour_priority(seed, level, v))
 
 
+def colour_key(seed: int, level: int, v: int, deg: int) -> int:
+    return int(lib().or_colour_key(seed, level, v, deg))
+
+
 def laplacian(g):
     n, rp, ci, w = g
     a = np.empty(len(ci))
@@ -173,7 +179,8 @@ def colour(n, rp, ci, seed: int, level: int = 0):
 
 
 def colour_greedy(n, rp, ci, seed: int, level: int = 0):
-    """Greedy first-fit in descending (priority, id) order, whatever the graph."""
+    """Greedy first-fit in descending (key, id) order, whatever the graph
+    (key: degree, then the random word)."""
     c = np.empty(n, dtype=np.int32)
     nc = lib().or_colour_greedy(n, _i32(rp), _i32(ci), seed, level, c)
     return c, nc

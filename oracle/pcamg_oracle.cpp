@@ -39,7 +39,7 @@
 //  * Gauss-Seidel ordering (the paper names only Gauss-Seidel): multicolour,
 //    red-black (parity of the breadth-first distance from vertex 0) on a
 //    connected bipartite level graph, else greedy first-fit in descending
-//    SplitMix64 priority order.
+//    (degree, SplitMix64 word) order, largest degree first.
 //  * Outer loop (Alg. 5): V(1,1) with forward GS before and backward GS after
 //    the coarse correction; x made orthogonal to 1 after each cycle; ConvR =
 //    ||r_{k+1}||/||r_k||; rebuild when the mean ConvR since the last rebuild
@@ -82,9 +82,16 @@ double xi_value(uint64_t seed, int r, int i) {
   return 2.0 * u - 1.0;
 }
 
-// Colouring priority of vertex v on level l.
+// Random word of vertex v on level l for the colouring order.
 uint64_t colour_priority(uint64_t seed, int level, int v) {
   return stream_word(seed, ((uint64_t)(uint32_t)level << 32) + (uint64_t)(uint32_t)v + 1ull);
+}
+
+// Colouring order key: largest degree first (degree capped at 2^24 - 1 in the
+// top 24 bits), then the top 40 bits of the random word.
+uint64_t colour_key(uint64_t seed, int level, int v, int deg) {
+  const uint64_t dg = (uint64_t)std::min(deg, (1 << 24) - 1);
+  return (dg << 40) | (colour_priority(seed, level, v) >> 24);
 }
 
 // ---------------------------------------------------------------------------
@@ -178,13 +185,14 @@ void laplacian(const Csr& W, Csr& A, std::vector<double>& d, std::vector<double>
 
 // ---------------------------------------------------------------------------
 // Multicolouring for the Gauss-Seidel smoother (the paper only says
-// "Gauss-Seidel").  Greedy first-fit in descending (priority, id) order: each
-// vertex takes the smallest colour unused by its already coloured neighbours.
+// "Gauss-Seidel").  Greedy first-fit in descending (key, id) order, key =
+// largest degree first then a random word: each vertex takes the smallest
+// colour unused by its already coloured neighbours.
 // ---------------------------------------------------------------------------
 int colour_greedy(const Csr& G, uint64_t seed, int level, std::vector<int>& colour) {
   const int n = G.n;
   std::vector<uint64_t> pr(n);
-  for (int v = 0; v < n; ++v) pr[v] = colour_priority(seed, level, v);
+  for (int v = 0; v < n; ++v) pr[v] = colour_key(seed, level, v, G.deg(v));
   std::vector<int> order(n);
   std::iota(order.begin(), order.end(), 0);
   std::sort(order.begin(), order.end(), [&](int a, int b) {
@@ -1178,6 +1186,7 @@ void or_xi(int n, unsigned long long seed, int r, double* out) {
 }
 
 unsigned long long or_colour_priority(unsigned long long seed, int level, int v) { return colour_priority(seed, level, v); }
+unsigned long long or_colour_key(unsigned long long seed, int level, int v, int deg) { return colour_key(seed, level, v, deg); }
 
 void or_laplacian(int n, const int* rp, const int* ci, const double* w, double* aval, double* d, double* dinv) {
   Csr W = make_csr(n, rp, ci, w), A;

@@ -32,6 +32,9 @@ def test_splitmix64_published_values(oracle):
     w2 = I.stream_words(77, 2, start=3 << 32)
     assert np.array_equal(xi2, 2.0 * ((w2 >> np.uint64(11)).astype(np.float64) * 2.0 ** -53) - 1.0)
     assert int(oracle.colour_priority(5, 2, 10)) == int(I.stream_words(5, 1, start=(2 << 32) + 10)[0])
+    w = int(I.stream_words(5, 1, start=(2 << 32) + 10)[0])
+    assert oracle.colour_key(5, 2, 10, 7) == (7 << 40) | (w >> 24)
+    assert oracle.colour_key(5, 2, 10, 1 << 30) == (((1 << 24) - 1) << 40) | (w >> 24)
 
 
 def test_generators_shapes():
@@ -114,8 +117,12 @@ def test_laplacian_rowsum_and_residual(oracle):
 # Colouring: proper, <= Delta + 1, equals the sequential greedy in priority
 # order, and equals Jones-Plassmann rounds (the GPU algorithm)
 # ---------------------------------------------------------------------------
-def _priorities(seed, level, n):
-    return I.stream_words(seed, n, start=level << 32)
+def _priorities(seed, level, n, deg):
+    """Largest degree first (capped at 2^24 - 1, top 24 bits), then the top 40
+    bits of word (level << 32) + v + 1 of the SplitMix64 stream."""
+    w = I.stream_words(seed, n, start=level << 32)
+    d = np.minimum(np.asarray(deg, dtype=np.uint64), np.uint64((1 << 24) - 1))
+    return (d << np.uint64(40)) | (w >> np.uint64(24))
 
 
 def _greedy_colour(n, rp, ci, pr):
@@ -161,7 +168,7 @@ def test_colouring(oracle, maker):
         rows = np.repeat(np.arange(n), np.diff(rp))
         assert np.all(col[rows] != col[ci])
         assert nc == col.max() + 1 <= np.diff(rp).max() + 1
-        pr = _priorities(0xC010, level, n)
+        pr = _priorities(0xC010, level, n, np.diff(rp))
         assert np.array_equal(col, _greedy_colour(n, rp, ci, pr))
         jp, _ = _jones_plassmann(n, rp, ci, pr)
         assert np.array_equal(col, jp)
