@@ -290,8 +290,9 @@ pcamg_status pcamg_laplacian(int32_t n, const int32_t* rp, const int32_t* ci, co
  * only as Gauss-Seidel; the ordering is this library's).  A connected
  * bipartite graph gets the red-black colouring: parity of the breadth-first
  * distance from vertex 0 (2 colours, 1 if n = 1).  Any other graph gets
- * Jones-Plassmann rounds with SplitMix64 priorities (seed, level) = greedy
- * first-fit in descending (priority, id) order.  rp, ci: device CSR of a
+ * Jones-Plassmann rounds = greedy first-fit in descending (key, id) order,
+ * key = min(degree, 2^24 - 1) << 40 | (SplitMix64 word (level << 32) + v + 1
+ * of stream seed) >> 24: largest degree first, random among equal degrees.  rp, ci: device CSR of a
  * symmetric pattern without self loops; colour: device int32 [n], written;
  * *ncolours: host.  PCAMG_EINVAL on null arguments or n < 0. */
 pcamg_status pcamg_colour(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed, int32_t level,

@@ -617,18 +617,24 @@ struct DenseOf<float> {
   static void inner(TailDesc& D, const float* C) { D.C32 = C; }
 };
 
+// Workgroups of the multi-column construction: 256 CUs, up to 3 resident each.
+constexpr int32_t DENSE_MC_BLOCKS = 768;
+
 // Columns of the dense operator for the tail described by D (levels rel..),
 // into C (n0 x n0); tail levels outside LDS get per-workgroup copies.
 template <typename T>
 void dense_columns(TailDesc D, T* C, hipStream_t s) {
   const int32_t n0 = D.lv[0].n;
   const int K = dense_mc_columns();
-  if (dense_mc_lds_bytes(D.cn, D.cm, sizeof(T)) <= (size_t)TAIL_LDS_BYTES) {
+  const size_t lds = dense_mc_lds_bytes(D.cn, D.cm, sizeof(T));
+  if (lds <= (size_t)TAIL_LDS_BYTES) {
     // several columns per workgroup: every non-coarsest level in per-workgroup
-    // scratch as rows of K values
+    // scratch as rows of K values; as many workgroups as fit on the chip
+    // (3 per CU when the coarsest level is small), each taking column groups
+    // in turn
     size_t gstride = 0;
     for (int l = 0; l + 1 < D.nlev; ++l) gstride += 3 * (size_t)D.lv[l].n * K;
-    const int blocks = std::min<int32_t>((n0 + K - 1) / K, 256);
+    const int blocks = std::min<int32_t>((n0 + K - 1) / K, DENSE_MC_BLOCKS);
     DVec<T> scratch(std::max<size_t>(gstride * blocks, 1));
     size_t off = 0;
     for (int l = 0; l + 1 < D.nlev; ++l) {
@@ -638,7 +644,7 @@ void dense_columns(TailDesc D, T* C, hipStream_t s) {
     }
     DVec<TailDesc> dd(1);
     copy_h2d(dd.p, &D, 1, s);
-    tail_dense_mc<T>(dd.p, blocks, C, gstride, s);
+    tail_dense_mc<T>(dd.p, blocks, C, gstride, lds, s);
     sync(s);  // D, dd and scratch are temporaries
     return;
   }
@@ -663,7 +669,7 @@ void dense_columns(TailDesc D, T* C, hipStream_t s) {
 // A tail level below which the dense construction nests a smaller dense
 // operator: the first level of at most DENSE_INNER_MAX vertices with at least
 // two levels under it.
-constexpr int32_t DENSE_INNER_MAX = 1024;
+constexpr int32_t DENSE_INNER_MAX = 2048;
 
 
 template <typename T>

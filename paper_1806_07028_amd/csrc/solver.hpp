@@ -201,9 +201,10 @@ void tail_cycle32(const Hierarchy& H, const float* b, float* x, int gamma, hipSt
 template <typename T>
 void tail_dense(const TailDesc* desc, int32_t n0, int blocks, T* C, size_t gstride, hipStream_t s);
 template <typename T>
-void tail_dense_mc(const TailDesc* desc, int blocks, T* C, size_t gstride, hipStream_t s);
+void tail_dense_mc(const TailDesc* desc, int blocks, T* C, size_t gstride, size_t lds, hipStream_t s);
 size_t dense_mc_lds_bytes(int32_t cn, int32_t cm, size_t tsize);
 int dense_mc_columns();
+int dense_mc_threads();
 template <typename T>
 void dense_apply(int32_t n, const T* C, const T* b, T* part, T* y, hipStream_t s);
 int32_t dense_chunks(int32_t n);

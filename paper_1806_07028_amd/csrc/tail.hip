@@ -8,6 +8,7 @@
 // which do not depend on the previous step.  Every row and every sum uses the
 // same arithmetic and order as the per-step kernels, so results are identical
 // bit for bit.
+#include <type_traits>
 #include "rowchain.hpp"
 #include "solver.hpp"
 
@@ -353,27 +354,84 @@ __global__ void __launch_bounds__(TAIL_THREADS)
 // construction bit for bit while the step latency is shared by DMC_K columns.
 // ---------------------------------------------------------------------------
 constexpr int DMC_K = 8;
+// Threads per workgroup of the construction: with the LDS sized to what the
+// coarsest level needs, several workgroups share a CU (the steps are
+// latency-bound, so more resident workgroups means more columns in flight).
+constexpr int DMC_THREADS = 512;
 
-// fma chain of a CSR row against column j of a row-major n x DMC_K block
-// (x points at column j), in batches of eight as row_chain1
+// One row of a row-major n x DMC_K block (the DMC_K columns' values of a
+// vertex) moved as 16-byte vectors: every block starts at a multiple of DMC_K
+// elements of an allocation aligned to 256 bytes (global scratch) or of the
+// 16-byte aligned LDS pool, so every row is 16-byte aligned.
+template <typename T>
+struct Row4;
+template <>
+struct Row4<float> {
+  typedef float v __attribute__((ext_vector_type(4)));
+};
+template <>
+struct Row4<double> {
+  typedef double v __attribute__((ext_vector_type(4)));
+};
+
+template <typename T, typename P>
+__device__ __forceinline__ void ld_row(P p, T (&v)[DMC_K]) {
+  typedef typename Row4<T>::v V;
+  typedef typename std::conditional<std::is_same<P, GP<T>>::value || std::is_same<P, GW<T>>::value,
+                                    const PCAMG_GLOBAL V*, const V*>::type VP;
+  const VP q = (VP)p;
+#pragma unroll
+  for (int h = 0; h < DMC_K / 4; ++h) {
+    const V t = q[h];
+    v[4 * h] = t.x;
+    v[4 * h + 1] = t.y;
+    v[4 * h + 2] = t.z;
+    v[4 * h + 3] = t.w;
+  }
+}
+
+template <typename T, typename P>
+__device__ __forceinline__ void st_row(P p, const T (&v)[DMC_K]) {
+  typedef typename Row4<T>::v V;
+  typedef typename std::conditional<std::is_same<P, GW<T>>::value, PCAMG_GLOBAL V*, V*>::type VP;
+  VP q = (VP)p;
+#pragma unroll
+  for (int h = 0; h < DMC_K / 4; ++h) {
+    V t;
+    t.x = v[4 * h];
+    t.y = v[4 * h + 1];
+    t.z = v[4 * h + 2];
+    t.w = v[4 * h + 3];
+    q[h] = t;
+  }
+}
+
+// The DMC_K fma chains of a CSR row against the columns of a row-major
+// n x DMC_K block at once: one index and value load per entry feeds DMC_K
+// independent chains, each in CSR order as row_chain1 (so each column's sum is
+// the single-vector one bit for bit).  Entries past the row end load row 0
+// (in bounds) and are not summed.
 template <typename T, typename PX>
-__device__ __forceinline__ T chain_mc(int32_t k0, int32_t k1, GP<int32_t> ci, GP<T> av, PX x, T s) {
-  constexpr int U = 8;
+__device__ __forceinline__ void chain_rows_mc(int32_t k0, int32_t k1, GP<int32_t> ci, GP<T> av, PX x,
+                                              T (&s)[DMC_K]) {
+  constexpr int U = sizeof(T) == 8 ? 2 : 4;  // gathered values stay in registers
   for (int32_t k = k0; k < k1; k += U) {
     int32_t c[U];
-    T a[U], v[U];
+    T a[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       c[u] = k + u < k1 ? ci[k + u] : 0;
       a[u] = k + u < k1 ? av[k + u] : (T)0;
     }
+    T v[U][DMC_K];
 #pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = k + u < k1 ? x[(size_t)c[u] * DMC_K] : (T)0;
+    for (int u = 0; u < U; ++u) ld_row<T>(x + (size_t)c[u] * DMC_K, v[u]);
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (k + u < k1) s = fma(a[u], v[u], s);
+      if (k + u < k1)
+#pragma unroll
+        for (int j = 0; j < DMC_K; ++j) s[j] = fma(a[u], v[u][j], s[j]);
   }
-  return s;
 }
 
 template <typename T>
@@ -382,12 +440,16 @@ __device__ __forceinline__ void gs_mc(const TailLevel& L, const int32_t* coff, G
   const GP<int32_t> rp = gptr(L.rp), ci = gptr(L.ci);
   for (int t = 0; t < L.ncol; ++t) {
     const int c = forward ? t : L.ncol - 1 - t;
-    const int32_t r0 = coff[c], r1 = coff[c + 1];
-    const int32_t items = (r1 - r0) * DMC_K;
-    for (int32_t it = threadIdx.x; it < items; it += TAIL_THREADS) {
-      const int32_t i = r0 + it / DMC_K, j = it % DMC_K;
-      const T sum = chain_mc<T>(rp[i], rp[i + 1], ci, av, x + j, (T)0);
-      x[(size_t)i * DMC_K + j] = (b[(size_t)i * DMC_K + j] - sum) * dinv[i];
+    for (int32_t i = coff[c] + threadIdx.x; i < coff[c + 1]; i += DMC_THREADS) {
+      T s[DMC_K], bi[DMC_K];
+#pragma unroll
+      for (int j = 0; j < DMC_K; ++j) s[j] = 0;
+      chain_rows_mc<T>(rp[i], rp[i + 1], ci, av, (GP<T>)x, s);
+      ld_row<T>(b + (size_t)i * DMC_K, bi);
+      const T di = dinv[i];
+#pragma unroll
+      for (int j = 0; j < DMC_K; ++j) s[j] = (bi[j] - s[j]) * di;
+      st_row<T>(x + (size_t)i * DMC_K, s);
     }
     __syncthreads();
   }
@@ -402,32 +464,51 @@ __device__ __forceinline__ void down_mc(const TailLevel& L, const int32_t* coff,
   {
     const GP<T> av = TailOps<T>::av(L), d = TailOps<T>::d(L);
     const GP<int32_t> rp = gptr(L.rp), ci = gptr(L.ci);
-    for (int32_t it = threadIdx.x; it < L.n * DMC_K; it += TAIL_THREADS) {
-      const int32_t i = it / DMC_K, j = it % DMC_K;
-      const T sum = chain_mc<T>(rp[i], rp[i + 1], ci, av, x + j, d[i] * x[(size_t)i * DMC_K + j]);
-      r[(size_t)i * DMC_K + j] = b[(size_t)i * DMC_K + j] - sum;
+    for (int32_t i = threadIdx.x; i < L.n; i += DMC_THREADS) {
+      T s[DMC_K], bi[DMC_K];
+      ld_row<T>(x + (size_t)i * DMC_K, s);
+      const T di = d[i];
+#pragma unroll
+      for (int j = 0; j < DMC_K; ++j) s[j] = di * s[j];
+      chain_rows_mc<T>(rp[i], rp[i + 1], ci, av, (GP<T>)x, s);
+      ld_row<T>(b + (size_t)i * DMC_K, bi);
+#pragma unroll
+      for (int j = 0; j < DMC_K; ++j) s[j] = bi[j] - s[j];
+      st_row<T>(r + (size_t)i * DMC_K, s);
     }
     __syncthreads();
   }
   const GP<T> pv = TailOps<T>::pval(L);
   const GP<int32_t> moff = gptr(L.moff), mem = gptr(L.mem);
-  for (int32_t it = threadIdx.x; it < nc * DMC_K; it += TAIL_THREADS) {
-    const int32_t q = it / DMC_K, j = it % DMC_K;
-    T sum = 0;
+  for (int32_t q = threadIdx.x; q < nc; q += DMC_THREADS) {
+    T s[DMC_K], z[DMC_K];
+#pragma unroll
+    for (int j = 0; j < DMC_K; ++j) s[j] = z[j] = 0;
     for (int32_t t = moff[q]; t < moff[q + 1]; ++t) {
       const int32_t k = mem[t];
-      sum = fma(pv ? pv[k] : (T)1, r[(size_t)k * DMC_K + j], sum);
+      const T p = pv ? pv[k] : (T)1;
+      T rk[DMC_K];
+      ld_row<T>((GP<T>)r + (size_t)k * DMC_K, rk);
+#pragma unroll
+      for (int j = 0; j < DMC_K; ++j) s[j] = fma(p, rk[j], s[j]);
     }
-    bc[(size_t)q * DMC_K + j] = sum;
-    xc[(size_t)q * DMC_K + j] = 0;
+    st_row<T>(bc + (size_t)q * DMC_K, s);
+    st_row<T>(xc + (size_t)q * DMC_K, z);
   }
   __syncthreads();
   if (Cd) {
-    for (int32_t it = threadIdx.x; it < nc * DMC_K; it += TAIL_THREADS) {
-      const int32_t i = it / DMC_K, j = it % DMC_K;
-      T sum = 0;
-      for (int32_t m = 0; m < nc; ++m) sum = fma(Cd[(size_t)m * nc + i], bc[(size_t)m * DMC_K + j], sum);
-      xc[(size_t)i * DMC_K + j] = sum;
+    for (int32_t i = threadIdx.x; i < nc; i += DMC_THREADS) {
+      T s[DMC_K];
+#pragma unroll
+      for (int j = 0; j < DMC_K; ++j) s[j] = 0;
+      for (int32_t m = 0; m < nc; ++m) {
+        const T cmi = Cd[(size_t)m * nc + i];
+        T bm[DMC_K];
+        ld_row<T>(bc + (size_t)m * DMC_K, bm);
+#pragma unroll
+        for (int j = 0; j < DMC_K; ++j) s[j] = fma(cmi, bm[j], s[j]);
+      }
+      st_row<T>(xc + (size_t)i * DMC_K, s);
     }
     __syncthreads();
   }
@@ -437,9 +518,14 @@ template <typename T, typename PC>
 __device__ __forceinline__ void up_mc(const TailLevel& L, const int32_t* coff, GW<T> b, GW<T> x, PC xc) {
   const GP<T> pv = TailOps<T>::pval(L);
   const GP<int32_t> agg = gptr(L.agg);
-  for (int32_t it = threadIdx.x; it < L.n * DMC_K; it += TAIL_THREADS) {
-    const int32_t k = it / DMC_K, j = it % DMC_K;
-    x[(size_t)k * DMC_K + j] = fma(pv ? pv[k] : (T)1, xc[(size_t)agg[k] * DMC_K + j], x[(size_t)k * DMC_K + j]);
+  for (int32_t k = threadIdx.x; k < L.n; k += DMC_THREADS) {
+    const T p = pv ? pv[k] : (T)1;
+    T xk[DMC_K], cq[DMC_K];
+    ld_row<T>(x + (size_t)k * DMC_K, xk);
+    ld_row<T>(xc + (size_t)agg[k] * DMC_K, cq);
+#pragma unroll
+    for (int j = 0; j < DMC_K; ++j) xk[j] = fma(p, cq[j], xk[j]);
+    st_row<T>(x + (size_t)k * DMC_K, xk);
   }
   __syncthreads();
   gs_mc<T>(L, coff, b, x, false);
@@ -451,19 +537,19 @@ __device__ __forceinline__ void coarsest_mc(const TailDesc& D, const double* Lf,
                                             double* mu) {
   const int32_t n = D.cn, m = D.cm;
   const GP<double> Dg = gptr(D.D);
-  for (int32_t it = threadIdx.x; it < m * DMC_K; it += TAIL_THREADS) acc[it] = (double)b[it];
+  for (int32_t it = threadIdx.x; it < m * DMC_K; it += DMC_THREADS) acc[it] = (double)b[it];
   __syncthreads();
   for (int32_t k = 0; k < m; ++k) {
-    for (int32_t it = threadIdx.x; it < (m - k - 1) * DMC_K; it += TAIL_THREADS) {
+    for (int32_t it = threadIdx.x; it < (m - k - 1) * DMC_K; it += DMC_THREADS) {
       const int32_t i = k + 1 + it / DMC_K, j = it % DMC_K;
       acc[i * DMC_K + j] = fma(-Lf[(size_t)i * m + k], acc[k * DMC_K + j], acc[i * DMC_K + j]);
     }
     __syncthreads();
   }
-  for (int32_t it = threadIdx.x; it < m * DMC_K; it += TAIL_THREADS) acc[it] = acc[it] / Dg[it / DMC_K];
+  for (int32_t it = threadIdx.x; it < m * DMC_K; it += DMC_THREADS) acc[it] = acc[it] / Dg[it / DMC_K];
   __syncthreads();
   for (int32_t k = m - 1; k >= 0; --k) {
-    for (int32_t it = threadIdx.x; it < k * DMC_K; it += TAIL_THREADS) {
+    for (int32_t it = threadIdx.x; it < k * DMC_K; it += DMC_THREADS) {
       const int32_t i = it / DMC_K, j = it % DMC_K;
       acc[i * DMC_K + j] = fma(-Lf[(size_t)k * m + i], acc[k * DMC_K + j], acc[i * DMC_K + j]);
     }
@@ -478,9 +564,9 @@ __device__ __forceinline__ void coarsest_mc(const TailDesc& D, const double* Lf,
       mu[j] = sum / (double)n;
     }
     __syncthreads();
-    for (int32_t it = threadIdx.x; it < n * DMC_K; it += TAIL_THREADS) x[it] = (T)(acc[it] - mu[it % DMC_K]);
+    for (int32_t it = threadIdx.x; it < n * DMC_K; it += DMC_THREADS) x[it] = (T)(acc[it] - mu[it % DMC_K]);
   } else {
-    for (int32_t it = threadIdx.x; it < n * DMC_K; it += TAIL_THREADS) x[it] = (T)acc[it];
+    for (int32_t it = threadIdx.x; it < n * DMC_K; it += DMC_THREADS) x[it] = (T)acc[it];
   }
   __syncthreads();
 }
@@ -535,9 +621,9 @@ __device__ __forceinline__ void body_mc(const TailDesc& D, T* cx, T* cb, const i
 }
 
 template <typename T>
-__global__ void __launch_bounds__(TAIL_THREADS)
+__global__ void __launch_bounds__(DMC_THREADS)
     tail_dense_mc_kernel(const TailDesc* __restrict__ Dp, T* __restrict__ C, size_t gstride) {
-  __shared__ double pool[TAIL_LDS_BYTES / 8];
+  extern __shared__ __attribute__((aligned(16))) double pool[];  // dense_mc_lds_bytes(cn, cm, sizeof(T))
   __shared__ int32_t coffs[TAIL_COFF_MAX];
   __shared__ double mu[DMC_K];
   const TailDesc& D = *Dp;
@@ -545,7 +631,7 @@ __global__ void __launch_bounds__(TAIL_THREADS)
   for (int l = 0; l < last; ++l) {
     const TailLevel& L = D.lv[l];
     const GP<int32_t> cf = gptr(L.coff);
-    for (int32_t c = threadIdx.x; c <= L.ncol; c += TAIL_THREADS) coffs[L.ocoff + c] = cf[c];
+    for (int32_t c = threadIdx.x; c <= L.ncol; c += DMC_THREADS) coffs[L.ocoff + c] = cf[c];
   }
   // LDS: coarsest x and b (cn x K of T), accumulator (cn x K doubles: the
   // grounded solve sets its last row), factor (cm x cm)
@@ -557,7 +643,7 @@ __global__ void __launch_bounds__(TAIL_THREADS)
   const bool lds_L = cm <= 64;
   if (lds_L) {
     const GP<double> Lg = gptr(D.L);
-    for (int32_t i = threadIdx.x; i < cm * cm; i += TAIL_THREADS) pool[tb + (size_t)cn * DMC_K + i] = Lg[i];
+    for (int32_t i = threadIdx.x; i < cm * cm; i += DMC_THREADS) pool[tb + (size_t)cn * DMC_K + i] = Lg[i];
   }
   const double* Lf = lds_L ? pool + tb + (size_t)cn * DMC_K : D.L;
   const TailLevel& L0 = D.lv[0];
@@ -566,7 +652,7 @@ __global__ void __launch_bounds__(TAIL_THREADS)
   const GW<T> x0 = TailOps<T>::gx(L0) + boff, b0 = TailOps<T>::gb(L0) + boff;
   for (int32_t j0 = blockIdx.x * DMC_K; j0 < n0; j0 += gridDim.x * DMC_K) {
     __syncthreads();
-    for (int32_t it = threadIdx.x; it < n0 * DMC_K; it += TAIL_THREADS) {
+    for (int32_t it = threadIdx.x; it < n0 * DMC_K; it += DMC_THREADS) {
       const int32_t i = it / DMC_K, j = it % DMC_K;
       x0[it] = 0;
       b0[it] = i == j0 + j ? (T)1 : (T)0;
@@ -574,7 +660,7 @@ __global__ void __launch_bounds__(TAIL_THREADS)
     __syncthreads();
     body_mc<T>(D, cx, cb, coffs, Lf, acc, mu, boff);
     body_mc<T>(D, cx, cb, coffs, Lf, acc, mu, boff);
-    for (int32_t it = threadIdx.x; it < n0 * DMC_K; it += TAIL_THREADS) {
+    for (int32_t it = threadIdx.x; it < n0 * DMC_K; it += DMC_THREADS) {
       const int32_t i = it % n0, j = it / n0;  // coalesced over i in C
       if (j0 + j < n0) C[(size_t)(j0 + j) * n0 + i] = x0[(size_t)i * DMC_K + j];
     }
@@ -588,13 +674,18 @@ size_t dense_mc_lds_bytes(int32_t cn, int32_t cm, size_t tsize) {
 
 int dense_mc_columns() { return DMC_K; }
 
+int dense_mc_threads() { return DMC_THREADS; }
+
 template <typename T>
-void tail_dense_mc(const TailDesc* desc, int blocks, T* C, size_t gstride, hipStream_t s) {
-  tail_dense_mc_kernel<T><<<blocks, TAIL_THREADS, 0, s>>>(desc, C, gstride);
+void tail_dense_mc(const TailDesc* desc, int blocks, T* C, size_t gstride, size_t lds, hipStream_t s) {
+  require(lds <= (size_t)TAIL_LDS_BYTES, PCAMG_EINVAL, "dense construction LDS exceeds the pool size");
+  PCAMG_HIP(hipFuncSetAttribute((const void*)tail_dense_mc_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds));
+  tail_dense_mc_kernel<T><<<blocks, DMC_THREADS, lds, s>>>(desc, C, gstride);
   PCAMG_LAUNCHED();
 }
-template void tail_dense_mc<double>(const TailDesc*, int, double*, size_t, hipStream_t);
-template void tail_dense_mc<float>(const TailDesc*, int, float*, size_t, hipStream_t);
+template void tail_dense_mc<double>(const TailDesc*, int, double*, size_t, size_t, hipStream_t);
+template void tail_dense_mc<float>(const TailDesc*, int, float*, size_t, size_t, hipStream_t);
 
 void tail_cycle64(const Hierarchy& H, const double* b, double* x, int gamma, hipStream_t s) {
   tail_kernel<double><<<1, TAIL_THREADS, 0, s>>>(H.tail_desc.p, b, x, gamma);

@@ -557,7 +557,7 @@ def test_dense_w_cycle_nested(gpu, oracle, shape, dmax):
     s = solver_for(gpu, g, w_dense=1, dense_max_n=dmax)
     H = oracle.Hierarchy(g, None)
     sizes = [s.level_info(l)["n"] for l in range(s.num_levels())]
-    assert any(1024 < m <= dmax for m in sizes[1:]) and any(m <= 1024 for m in sizes)
+    assert any(2048 < m <= dmax for m in sizes[1:]) and any(m <= 2048 for m in sizes)
     w_ref = H.cycle(b, None, 2)
     w64 = host(s.cycle(b, None, 2))
     assert np.linalg.norm(w64 - w_ref) <= 1e-12 * np.linalg.norm(w_ref)
