@@ -153,6 +153,7 @@ static bool make_tail_desc(Hierarchy& H, int start, TailDesc& D, hipStream_t s) 
     const LevelMatrix& A = *V.A;
     TailLevel& T = D.lv[l - start];
     T.n = A.n;
+    T.nnz = A.nnz;
     T.ncol = A.ncol;
     T.lds = l >= first_lds ? 1 : 0;
     // one workgroup: one thread per row measured fastest for rows of up to

@@ -68,6 +68,7 @@ constexpr int TAIL_LDS_BYTES = 128 * 1024;
 constexpr int TAIL_COFF_MAX = 2048;
 struct TailLevel {
   int32_t n, ncol, lds, ocoff, lanes;  // lanes per row: 1 or 16
+  int32_t nnz;
   int32_t o64[3], o32[3];  // x, b, r in LDS (lds = 1)
   const int32_t *coff, *rp, *ci, *agg, *moff, *mem;
   const double *av, *d, *dinv, *pval;
