@@ -25,6 +25,24 @@ __device__ __forceinline__ GW<T> gptr_w(T* p) {
   return (GW<T>)p;
 }
 
+// sum_j C[j * n + i] * v[j] as one fma chain in j order (C column-major), the
+// column entries loaded sixteen ahead of the chain
+template <typename T, typename PC, typename PV>
+__device__ __forceinline__ T dense_row_dot(int32_t n, PC C, int32_t i, PV v) {
+  constexpr int U = 16;
+  T s = 0;
+  int32_t j = 0;
+  for (; j + U <= n; j += U) {
+    T c[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) c[u] = C[(size_t)(j + u) * n + i];
+#pragma unroll
+    for (int u = 0; u < U; ++u) s = fma(c[u], v[j + u], s);
+  }
+  for (; j < n; ++j) s = fma(C[(size_t)j * n + i], v[j], s);
+  return s;
+}
+
 template <typename T>
 struct TailOps;
 template <>
@@ -141,11 +159,7 @@ __device__ __forceinline__ void tail_down(const TailLevel& L, const int32_t* cof
   }
   __syncthreads();
   if (Cd) {
-    for (int32_t i = threadIdx.x; i < nc; i += TAIL_THREADS) {
-      T s = 0;
-      for (int32_t j = 0; j < nc; ++j) s = fma(Cd[(size_t)j * nc + i], bc[j], s);
-      xc[i] = s;
-    }
+    for (int32_t i = threadIdx.x; i < nc; i += TAIL_THREADS) xc[i] = dense_row_dot<T>(nc, Cd, i, bc);
     __syncthreads();
   }
 }
@@ -540,7 +554,22 @@ __device__ __forceinline__ void down_mc(const TailLevel& L, const int32_t* coff,
       T s[DMC_K];
 #pragma unroll
       for (int j = 0; j < DMC_K; ++j) s[j] = 0;
-      for (int32_t m = 0; m < nc; ++m) {
+      // column entries of row i loaded eight ahead of the fma chains
+      constexpr int U = 8;
+      int32_t m = 0;
+      for (; m + U <= nc; m += U) {
+        T cm[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) cm[u] = Cd[(size_t)(m + u) * nc + i];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          T bm[DMC_K];
+          ld_row<T>(bc + (size_t)(m + u) * DMC_K, bm);
+#pragma unroll
+          for (int j = 0; j < DMC_K; ++j) s[j] = fma(cm[u], bm[j], s[j]);
+        }
+      }
+      for (; m < nc; ++m) {
         const T cmi = Cd[(size_t)m * nc + i];
         T bm[DMC_K];
         ld_row<T>(bc + (size_t)m * DMC_K, bm);
@@ -758,8 +787,18 @@ __global__ void __launch_bounds__(256) dense_part_kernel(int32_t n, const T* __r
   for (int32_t j = j0 + threadIdx.x; j < j1; j += 256) bj[j - j0] = b[j];
   __syncthreads();
   if (i >= n) return;
+  // the chunk's column entries loaded sixteen ahead of the fma chain
+  constexpr int U = 16;
   T s = 0;
-  for (int32_t j = j0; j < j1; ++j) s = fma(C[(size_t)j * n + i], bj[j - j0], s);
+  int32_t j = j0;
+  for (; j + U <= j1; j += U) {
+    T cv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) cv[u] = C[(size_t)(j + u) * n + i];
+#pragma unroll
+    for (int u = 0; u < U; ++u) s = fma(cv[u], bj[j + u - j0], s);
+  }
+  for (; j < j1; ++j) s = fma(C[(size_t)j * n + i], bj[j - j0], s);
   part[(size_t)c * n + i] = s;
 }
 template <typename T>
