@@ -16,8 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libpcamg.so")
-SOURCES = ["util.hip", "basic.hip", "setup.hip", "coarse.hip", "layout.hip", "tail.hip", "solver.hip", "learned.hip",
-           "capi.hip"]
+SOURCES = ["util.hip", "basic.hip", "setup.hip", "coarse.hip", "layout.hip", "tail.hip", "dense.hip", "solver.hip",
+           "learned.hip", "capi.hip"]
 ARCH = "gfx950"
 
 
@@ -47,7 +47,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + ["-lrocblas"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -1,0 +1,303 @@
+// Bottom-up construction of the dense W operator.
+//
+// With gamma = 2 the level above the dense region d calls the cycle of level d
+// twice from x = 0: a fixed linear map 2 W_d - W_d A_d W_d of its right-hand
+// side, W_d the operator of one call (dense_apply applies it).  Instead of
+// running that recursion on every unit vector, the operator of every level l
+// of the region is built from the one of level l + 1 as a matrix, all columns
+// at once:
+//
+//   Z        = coarsest solve applied to the identity (FP64, as the cycle does it)
+//   C_{l+1}  = Z                       if l + 1 is the coarsest level (one call)
+//            = 2 W_{l+1} - W_{l+1} A_{l+1} W_{l+1}   otherwise (second call
+//              starts from the first one's result: x1 = x0 + W (b - A x0))
+//   W_l      = S_bwd o (I + P C_{l+1} P^T (.. residual ..)) o S_fwd on the
+//              identity: forward colour passes from X = 0, R = I - A X,
+//              B_c = P^T R, X += P (C_{l+1} B_c), backward colour passes.
+//
+// The colour passes, residuals and transfers are the cycle's own row
+// formulas (fma chains in CSR / member order) evaluated for all columns; the
+// two products with dense matrices are GEMMs.  The result is the same linear
+// map as the recursion with a different rounding order.
+#include <rocblas/rocblas.h>
+
+#include "rowchain.hpp"
+#include "solver.hpp"
+
+namespace pcamg {
+namespace {
+
+#define PCAMG_BLAS(expr)                                                                               \
+  do {                                                                                                 \
+    const rocblas_status st_ = (expr);                                                                 \
+    if (st_ != rocblas_status_success)                                                                 \
+      throw Error(PCAMG_EHIP, std::string("rocBLAS: ") + rocblas_status_to_string(st_) + " in " #expr); \
+  } while (0)
+
+// Z[i * n + j] = (coarsest solve of e_j)_i: one workgroup per column, the
+// arithmetic and order of the cycle's coarsest solve (FP64 accumulator in
+// LDS, n doubles; the grounded solve pins the last vertex and removes the mean).
+template <typename T>
+__global__ void __launch_bounds__(256)
+    coarsest_cols_kernel(int32_t n, int32_t m, int grounded, const double* __restrict__ L,
+                         const double* __restrict__ D, T* __restrict__ Z) {
+  extern __shared__ double acc[];
+  __shared__ double mu;
+  const int32_t j = blockIdx.x;
+  for (int32_t i = threadIdx.x; i < m; i += blockDim.x) acc[i] = i == j ? 1.0 : 0.0;
+  __syncthreads();
+  for (int32_t k = 0; k < m; ++k) {
+    const double yk = acc[k];
+    for (int32_t i = k + 1 + threadIdx.x; i < m; i += blockDim.x) acc[i] = fma(-L[(size_t)i * m + k], yk, acc[i]);
+    __syncthreads();
+  }
+  for (int32_t i = threadIdx.x; i < m; i += blockDim.x) acc[i] = acc[i] / D[i];
+  __syncthreads();
+  for (int32_t k = m - 1; k >= 0; --k) {
+    const double xk = acc[k];
+    for (int32_t i = threadIdx.x; i < k; i += blockDim.x) acc[i] = fma(-L[(size_t)k * m + i], xk, acc[i]);
+    __syncthreads();
+  }
+  if (grounded) {
+    if (threadIdx.x == 0) {
+      acc[n - 1] = 0.0;
+      double s = 0.0;
+      for (int32_t i = 0; i < n; ++i) s = s + acc[i];
+      mu = s / (double)n;
+    }
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) Z[(size_t)i * n + j] = (T)(acc[i] - mu);
+  } else {
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) Z[(size_t)i * n + j] = (T)acc[i];
+  }
+}
+
+// sum_e a_e Y[c_e, j] over a CSR row as one fma chain from s, entries loaded
+// eight ahead (row-major Y with ld columns; the row's indices and values are
+// the same for the whole workgroup)
+template <typename T>
+__device__ __forceinline__ T row_block_chain(int32_t k0, int32_t k1, const int32_t* __restrict__ ci,
+                                             const T* __restrict__ av, const T* __restrict__ Y, size_t ld,
+                                             int32_t j, T s) {
+  constexpr int U = 8;
+  int32_t k = k0;
+  for (; k + U <= k1; k += U) {
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = Y[(size_t)ci[k + u] * ld + j];
+#pragma unroll
+    for (int u = 0; u < U; ++u) s = fma(av[k + u], v[u], s);
+  }
+  for (; k < k1; ++k) s = fma(av[k], Y[(size_t)ci[k] * ld + j], s);
+  return s;
+}
+
+// One Gauss-Seidel colour pass on all columns, right-hand side the identity:
+// X[i, j] = (delta_ij - sum_e a_ie X[c_e, j]) * dinv_i for rows r0 + blockIdx.y.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    blk_gs_kernel(int32_t r0, int32_t nc, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                  const T* __restrict__ av, const T* __restrict__ dinv, T* __restrict__ X) {
+  const int32_t i = r0 + (int32_t)blockIdx.y;
+  const int32_t j = (int32_t)(blockIdx.x * 256 + threadIdx.x);
+  if (j >= nc) return;
+  const T s = row_block_chain<T>(rp[i], rp[i + 1], ci, av, X, (size_t)nc, j, (T)0);
+  X[(size_t)i * nc + j] = ((i == j ? (T)1 : (T)0) - s) * dinv[i];
+}
+
+// Y = A X (identity = 0) or R = I - A X (identity = 1) on all columns, the
+// residual's order (s starts from d_i x_i).
+template <typename T>
+__global__ void __launch_bounds__(256)
+    blk_apply_kernel(int32_t nc, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                     const T* __restrict__ av, const T* __restrict__ d, const T* __restrict__ X, T* __restrict__ Y,
+                     int identity) {
+  const int32_t i = (int32_t)blockIdx.y;
+  const int32_t j = (int32_t)(blockIdx.x * 256 + threadIdx.x);
+  if (j >= nc) return;
+  const size_t o = (size_t)i * nc + j;
+  const T s = row_block_chain<T>(rp[i], rp[i + 1], ci, av, X, (size_t)nc, j, d[i] * X[o]);
+  Y[o] = identity ? (i == j ? (T)1 : (T)0) - s : s;
+}
+
+// B_c[q, j] = sum over members k of aggregate q (ascending) of p_k R[k, j]
+template <typename T>
+__global__ void __launch_bounds__(256)
+    blk_restrict_kernel(int32_t nc, const int32_t* __restrict__ moff, const int32_t* __restrict__ mem,
+                        const T* __restrict__ pval, const T* __restrict__ R, T* __restrict__ Bc) {
+  const int32_t q = (int32_t)blockIdx.y;
+  const int32_t j = (int32_t)(blockIdx.x * 256 + threadIdx.x);
+  if (j >= nc) return;
+  T s = 0;
+  for (int32_t t = moff[q]; t < moff[q + 1]; ++t) {
+    const int32_t k = mem[t];
+    s = fma(pval ? pval[k] : (T)1, R[(size_t)k * nc + j], s);
+  }
+  Bc[(size_t)q * nc + j] = s;
+}
+
+// X[k, j] += p_k Xc[agg_k, j]
+template <typename T>
+__global__ void __launch_bounds__(256)
+    blk_prolong_kernel(int32_t nc, const int32_t* __restrict__ agg, const T* __restrict__ pval,
+                       const T* __restrict__ Xc, T* __restrict__ X) {
+  const int32_t k = (int32_t)blockIdx.y;
+  const int32_t j = (int32_t)(blockIdx.x * 256 + threadIdx.x);
+  if (j >= nc) return;
+  const size_t o = (size_t)k * nc + j;
+  X[o] = fma(pval ? pval[k] : (T)1, Xc[(size_t)agg[k] * nc + j], X[o]);
+}
+
+// C[j * n + i] = X[i * n + j] through 32 x 32 LDS tiles
+template <typename T>
+__global__ void __launch_bounds__(256) blk_transpose_kernel(int32_t n, const T* __restrict__ X, T* __restrict__ C) {
+  __shared__ T tile[32][33];
+  const int32_t bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  const int32_t tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int32_t r = ty; r < 32; r += 8) {
+    const int32_t i = by + r, j = bx + tx;
+    if (i < n && j < n) tile[r][tx] = X[(size_t)i * n + j];
+  }
+  __syncthreads();
+  for (int32_t r = ty; r < 32; r += 8) {
+    const int32_t j = bx + r, i = by + tx;
+    if (i < n && j < n) C[(size_t)j * n + i] = tile[tx][r];
+  }
+}
+
+inline dim3 rows_grid(int32_t ncols, int32_t rows) { return dim3((unsigned)((ncols + 255) / 256), (unsigned)rows); }
+
+template <typename T>
+struct LevelOf;
+template <>
+struct LevelOf<double> {
+  static const double* av(const LevelMatrix& A) { return A.av.p; }
+  static const double* d(const LevelMatrix& A) { return A.d.p; }
+  static const double* dinv(const LevelMatrix& A) { return A.dinv.p; }
+  static const double* pval(const Transfer& T) { return T.pval.p; }
+  static rocblas_status gemm(rocblas_handle h, int m, int n, int k, double alpha, const double* A, int lda,
+                             const double* B, int ldb, double beta, double* C, int ldc) {
+    return rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, m, n, k, &alpha, A, lda, B, ldb, &beta, C,
+                         ldc);
+  }
+};
+template <>
+struct LevelOf<float> {
+  static const float* av(const LevelMatrix& A) { return A.av32.p; }
+  static const float* d(const LevelMatrix& A) { return A.d32.p; }
+  static const float* dinv(const LevelMatrix& A) { return A.dinv32.p; }
+  static const float* pval(const Transfer& T) { return T.pval32.p; }
+  static rocblas_status gemm(rocblas_handle h, int m, int n, int k, float alpha, const float* A, int lda,
+                             const float* B, int ldb, float beta, float* C, int ldc) {
+    return rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_none, m, n, k, &alpha, A, lda, B, ldb, &beta, C,
+                         ldc);
+  }
+};
+
+// Row-major P = Q R (p x q times q x r) through the column-major GEMM:
+// P^T = R^T Q^T, every matrix dense with its own column count as stride.
+template <typename T>
+void gemm_rows(rocblas_handle h, int32_t p, int32_t q, int32_t r, T alpha, const T* Q, const T* R, T beta, T* P) {
+  PCAMG_BLAS(LevelOf<T>::gemm(h, r, p, q, alpha, R, r, Q, q, beta, P, r));
+}
+
+struct BlasHandle {
+  rocblas_handle h = nullptr;
+  explicit BlasHandle(hipStream_t s) {
+    PCAMG_BLAS(rocblas_create_handle(&h));
+    PCAMG_BLAS(rocblas_set_stream(h, s));
+    // no split-k atomics: the same operator on every run
+    PCAMG_BLAS(rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed));
+  }
+  ~BlasHandle() {
+    if (h) (void)rocblas_destroy_handle(h);
+  }
+};
+
+// Operator of two consecutive calls of a level's cycle from x = 0, whose single
+// call is W (m x m, row-major): x0 = W b, x1 = x0 + W (b - A x0), i.e.
+// 2 W - W (A W).
+template <typename T>
+DVec<T> two_calls(rocblas_handle h, const LevelMatrix& A, const DVec<T>& W, hipStream_t s) {
+  const int32_t m = A.n;
+  DVec<T> AW((size_t)m * m), Cop((size_t)m * m);
+  blk_apply_kernel<T><<<rows_grid(m, m), 256, 0, s>>>(m, A.rp.p, A.ci.p, LevelOf<T>::av(A), LevelOf<T>::d(A), W.p,
+                                                       AW.p, 0);
+  PCAMG_LAUNCHED();
+  copy_d2d(Cop.p, W.p, (size_t)m * m, s);
+  gemm_rows<T>(h, m, m, m, (T)-1, W.p, AW.p, (T)2, Cop.p);
+  return Cop;
+}
+
+}  // namespace
+
+bool dense_bottom_up_fits(const Hierarchy& H) {
+  const int nl = (int)H.lv.size();
+  if (H.dense_start < 0) return false;
+  for (int l = H.dense_start; l < nl; ++l)
+    if (H.lv[l].A->n > 65535) return false;  // rows of a pass are a grid dimension
+  return H.cn <= 4096;
+}
+
+template <typename T>
+void dense_bottom_up(Hierarchy& H, T* C, hipStream_t s) {
+  const int nl = (int)H.lv.size();
+  const int d = H.dense_start;
+  require(d >= 0 && nl - d >= 2 && dense_bottom_up_fits(H), PCAMG_EINVAL, "no dense region for the bottom-up build");
+  BlasHandle blas(s);
+  // Z: the coarsest operator on the identity
+  const int32_t cn = H.cn;
+  DVec<T> W(std::max<size_t>((size_t)cn * cn, 1));
+  coarsest_cols_kernel<T><<<cn, 256, (size_t)cn * sizeof(double), s>>>(cn, H.cm, H.grounded ? 1 : 0, H.cL.p,
+                                                                          H.cD.p, W.p);
+  PCAMG_LAUNCHED();
+  for (int l = nl - 2; l >= d; --l) {
+    const LevelMatrix& A = *H.lv[l].A;
+    const Transfer& Tr = H.lv[l].T;
+    const int32_t n = A.n, m = Tr.nc;
+    require(m == H.lv[l + 1].A->n, PCAMG_EINVAL, "transfer size does not match the next level");
+    // coarse operator: Z, or 2 W - W A W for the two calls of a non-coarsest level
+    DVec<T> Cop;
+    const T* Cl = W.p;
+    if (l + 2 < nl) {
+      Cop = two_calls<T>(blas.h, *H.lv[l + 1].A, W, s);
+      Cl = Cop.p;
+    }
+    // the cycle of level l on the identity
+    DVec<T> X((size_t)n * n), R((size_t)n * n), Bc((size_t)m * n), Xc((size_t)m * n);
+    PCAMG_HIP(hipMemsetAsync(X.p, 0, X.bytes(), s));  // all-zero bits: +0
+    const T* av = LevelOf<T>::av(A);
+    const T* dinv = LevelOf<T>::dinv(A);
+    for (int k = 0; k < A.ncol; ++k) {
+      const int32_t r0 = A.coff[k], r1 = A.coff[k + 1];
+      if (r1 <= r0) continue;
+      blk_gs_kernel<T><<<rows_grid(n, r1 - r0), 256, 0, s>>>(r0, n, A.rp.p, A.ci.p, av, dinv, X.p);
+      PCAMG_LAUNCHED();
+    }
+    blk_apply_kernel<T><<<rows_grid(n, n), 256, 0, s>>>(n, A.rp.p, A.ci.p, av, LevelOf<T>::d(A), X.p, R.p, 1);
+    PCAMG_LAUNCHED();
+    blk_restrict_kernel<T><<<rows_grid(n, m), 256, 0, s>>>(n, Tr.moff.p, Tr.mem.p, LevelOf<T>::pval(Tr), R.p, Bc.p);
+    PCAMG_LAUNCHED();
+    gemm_rows<T>(blas.h, m, m, n, (T)1, Cl, Bc.p, (T)0, Xc.p);
+    blk_prolong_kernel<T><<<rows_grid(n, n), 256, 0, s>>>(n, Tr.agg.p, LevelOf<T>::pval(Tr), Xc.p, X.p);
+    PCAMG_LAUNCHED();
+    for (int k = A.ncol - 1; k >= 0; --k) {
+      const int32_t r0 = A.coff[k], r1 = A.coff[k + 1];
+      if (r1 <= r0) continue;
+      blk_gs_kernel<T><<<rows_grid(n, r1 - r0), 256, 0, s>>>(r0, n, A.rp.p, A.ci.p, av, dinv, X.p);
+      PCAMG_LAUNCHED();
+    }
+    W = std::move(X);
+  }
+  // the level above applies two calls of level d's cycle from x = 0
+  const int32_t nd = H.lv[d].A->n;
+  DVec<T> Cd = two_calls<T>(blas.h, *H.lv[d].A, W, s);
+  blk_transpose_kernel<T><<<dim3((nd + 31) / 32, (nd + 31) / 32), 256, 0, s>>>(nd, Cd.p, C);
+  PCAMG_LAUNCHED();
+  PCAMG_HIP(hipStreamSynchronize(s));  // temporaries are freed on return
+}
+
+template void dense_bottom_up<double>(Hierarchy&, double*, hipStream_t);
+template void dense_bottom_up<float>(Hierarchy&, float*, hipStream_t);
+
+}  // namespace pcamg

@@ -680,6 +680,13 @@ void ensure_dense(pcamg_ctx* c, Hierarchy& H) {
   DVec<T>& C = DenseOf<T>::C(H);
   if (C.p) return;
   hipStream_t s = c->s;
+  if (dense_bottom_up_fits(H)) {  // level by level from the coarsest, products as GEMMs
+    const int32_t nd = H.lv[H.dense_start].A->n;
+    C.resize((size_t)nd * nd);
+    DenseOf<T>::part(H).resize((size_t)dense_chunks(nd) * nd);
+    dense_bottom_up<T>(H, C.p, s);
+    return;
+  }
   TailDesc D = *H.dense_host;
   const int32_t n0 = D.lv[0].n;
   int inner = -1;

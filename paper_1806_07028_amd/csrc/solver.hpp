@@ -203,6 +203,11 @@ template <typename T>
 void tail_dense(const TailDesc* desc, int32_t n0, int blocks, T* C, size_t gstride, hipStream_t s);
 template <typename T>
 void tail_dense_mc(const TailDesc* desc, int blocks, T* C, size_t gstride, size_t lds, hipStream_t s);
+// dense.hip: the dense W operator built level by level from the coarsest up
+// (GEMMs for the products with dense operators); column-major into C (n_d^2).
+bool dense_bottom_up_fits(const Hierarchy& H);
+template <typename T>
+void dense_bottom_up(Hierarchy& H, T* C, hipStream_t s);
 size_t dense_mc_lds_bytes(int32_t cn, int32_t cm, size_t tsize);
 int dense_mc_columns();
 int dense_mc_threads();
