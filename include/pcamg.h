@@ -90,13 +90,16 @@ typedef struct {
   int32_t use_graphs;      /* 1 = replay whole cycles from captured HIP graphs */
   int32_t row_lanes;       /* lanes per matrix row in the smoother/residual kernels: 0 = by the
                               level's mean row length, else 1, 4, 16 or 64 (results identical) */
-  int32_t w_dense;         /* 1 = in W-cycles, the two sub-cycles below the tail's first level are
-                              applied as one precomputed dense operator (equal up to rounding
-                              order; built on first use per hierarchy and precision); 0 = recurse */
+  int32_t w_dense;         /* 1 = in W-cycles, the two sub-cycles of the first level of at most
+                              dense_max_n vertices are applied as one precomputed dense operator
+                              (equal up to rounding order; built level by level from the coarsest
+                              on first use per hierarchy and precision, GEMMs through rocBLAS);
+                              0 = recurse */
   int32_t first_sweeps;    /* symmetric sweeps before the first build: -1 = relax_sweeps; with
                               pcamg_setup_learned the sweeps of the network's input (-1: 2) */
   int32_t dense_max_n;     /* w_dense: the dense operator starts at the first level of at most this
-                              many vertices below the finest (12288) */
+                              many vertices below the finest (12288); levels above 65535 vertices
+                              are not built (the W-cycle then recurses) */
   uint64_t seed;           /* start-vector stream */
   uint64_t colour_seed;    /* colouring priority stream */
 } pcamg_params;

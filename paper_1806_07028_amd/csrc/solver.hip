@@ -134,7 +134,6 @@ static bool make_tail_desc(Hierarchy& H, int start, TailDesc& D, hipStream_t s) 
   const int64_t fixed = (int64_t)H.cn + (H.cm <= 64 ? (int64_t)H.cm * H.cm : 0);
   if (3 * (int64_t)H.cn + fixed > budget) return false;
   std::memset(&D, 0, sizeof(D));
-  D.dense_rel = -1;
   D.nlev = nl - start;
   D.cn = H.cn;
   D.cm = H.cm;
@@ -399,9 +398,8 @@ std::unique_ptr<Hierarchy> build_hierarchy(pcamg_ctx* c, const double* e_nat) {
   }
   H->st0 = nat[0].st;
   // tail: the levels of at most tail_max_n vertices and the coarsest run in one
-  // workgroup launch (tail_desc).  W-cycles apply the two sub-cycles below the
-  // first level of at most dense_max_n vertices as one dense operator,
-  // built from the host descriptor dense_host of that sub-hierarchy.
+  // workgroup launch (tail_desc).  W-cycles apply the two sub-cycles of the
+  // first level of at most dense_max_n vertices as one dense operator.
   {
     const int32_t tail_n = c->P.tail_max_n > 0 ? c->P.tail_max_n : 0;
     auto first_small = [&](int32_t limit) {
@@ -427,10 +425,7 @@ std::unique_ptr<Hierarchy> build_hierarchy(pcamg_ctx* c, const double* e_nat) {
     // level launched step by step
     int ds = first_small(std::max<int32_t>(c->P.dense_max_n, 1));
     if (H->tail_start >= 0) ds = std::min(ds, H->tail_start);
-    if (ds >= 1 && nl - ds >= 2 && make_tail_desc(*H, ds, D, s)) {
-      H->dense_start = ds;
-      H->dense_host = std::make_unique<TailDesc>(D);
-    }
+    if (ds >= 1 && nl - ds >= 2) H->dense_start = ds;
   }
   if (P.keep_setup) {
     H->setup.resize(nl);
@@ -597,120 +592,32 @@ hipGraphExec_t capture(pcamg_ctx* c, F&& body) {
 }
 }  // namespace
 
-// Dense operator of the two W sub-cycles below the level above the tail (for
-// gamma = 2), built once per hierarchy and precision on first use: the tail
-// runs on every unit vector, one workgroup per column at a time, with
-// per-workgroup copies of the tail vectors that do not live in LDS.
+// The dense operator of the two W sub-cycles of level dense_start (gamma = 2),
+// built once per hierarchy and precision on first use.
 template <typename T>
 struct DenseOf;
 template <>
 struct DenseOf<double> {
   static DVec<double>& C(Hierarchy& H) { return H.C64; }
   static DVec<double>& part(Hierarchy& H) { return H.dpart64; }
-  static void point(TailLevel& T, double* x, double* b, double* r) { T.x = x, T.b = b, T.r = r; }
-  static void inner(TailDesc& D, const double* C) { D.C64 = C; }
 };
 template <>
 struct DenseOf<float> {
   static DVec<float>& C(Hierarchy& H) { return H.C32; }
   static DVec<float>& part(Hierarchy& H) { return H.dpart32; }
-  static void point(TailLevel& T, float* x, float* b, float* r) { T.x32 = x, T.b32 = b, T.r32 = r; }
-  static void inner(TailDesc& D, const float* C) { D.C32 = C; }
 };
-
-// Workgroups of the multi-column construction: 256 CUs, up to 3 resident each.
-constexpr int32_t DENSE_MC_BLOCKS = 768;
-
-// Columns of the dense operator for the tail described by D (levels rel..),
-// into C (n0 x n0); tail levels outside LDS get per-workgroup copies.
-template <typename T>
-void dense_columns(TailDesc D, T* C, hipStream_t s) {
-  const int32_t n0 = D.lv[0].n;
-  const int K = dense_mc_columns();
-  const size_t lds = dense_mc_lds_bytes(D.cn, D.cm, sizeof(T));
-  if (lds <= (size_t)TAIL_LDS_BYTES) {
-    // several columns per workgroup: every non-coarsest level in per-workgroup
-    // scratch as rows of K values; as many workgroups as fit on the chip
-    // (3 per CU when the coarsest level is small), each taking column groups
-    // in turn
-    size_t gstride = 0;
-    for (int l = 0; l + 1 < D.nlev; ++l) gstride += 3 * (size_t)D.lv[l].n * K;
-    const int blocks = std::min<int32_t>((n0 + K - 1) / K, DENSE_MC_BLOCKS);
-    DVec<T> scratch(std::max<size_t>(gstride * blocks, 1));
-    size_t off = 0;
-    for (int l = 0; l + 1 < D.nlev; ++l) {
-      const size_t m = (size_t)D.lv[l].n * K;
-      DenseOf<T>::point(D.lv[l], scratch.p + off, scratch.p + off + m, scratch.p + off + 2 * m);
-      off += 3 * m;
-    }
-    DVec<TailDesc> dd(1);
-    copy_h2d(dd.p, &D, 1, s);
-    tail_dense_mc<T>(dd.p, blocks, C, gstride, lds, s);
-    sync(s);  // D, dd and scratch are temporaries
-    return;
-  }
-  size_t gstride = 0;
-  for (int l = 0; l < D.nlev; ++l)
-    if (!D.lv[l].lds) gstride += 3 * (size_t)D.lv[l].n;
-  const int blocks = std::min<int32_t>(n0, 256);
-  DVec<T> scratch(std::max<size_t>(gstride * blocks, 1));
-  size_t off = 0;
-  for (int l = 0; l < D.nlev; ++l) {
-    TailLevel& L = D.lv[l];
-    if (L.lds) continue;
-    DenseOf<T>::point(L, scratch.p + off, scratch.p + off + L.n, scratch.p + off + 2 * (size_t)L.n);
-    off += 3 * (size_t)L.n;
-  }
-  DVec<TailDesc> dd(1);
-  copy_h2d(dd.p, &D, 1, s);
-  tail_dense<T>(dd.p, n0, blocks, C, gstride, s);
-  sync(s);  // D, dd and scratch are temporaries
-}
-
-// A tail level below which the dense construction nests a smaller dense
-// operator: the first level of at most DENSE_INNER_MAX vertices with at least
-// two levels under it.
-constexpr int32_t DENSE_INNER_MAX = 2048;
-
 
 template <typename T>
 void ensure_dense(pcamg_ctx* c, Hierarchy& H) {
   const int nl = (int)H.lv.size();
-  if (!c->P.w_dense || H.dense_start < 1 || nl - H.dense_start < 2 || !H.dense_host) return;
+  // without a dense operator the W-cycle recurses (levels too large for the build)
+  if (!c->P.w_dense || H.dense_start < 1 || nl - H.dense_start < 2 || !dense_bottom_up_fits(H)) return;
   DVec<T>& C = DenseOf<T>::C(H);
   if (C.p) return;
-  hipStream_t s = c->s;
-  if (dense_bottom_up_fits(H)) {  // level by level from the coarsest, products as GEMMs
-    const int32_t nd = H.lv[H.dense_start].A->n;
-    C.resize((size_t)nd * nd);
-    DenseOf<T>::part(H).resize((size_t)dense_chunks(nd) * nd);
-    dense_bottom_up<T>(H, C.p, s);
-    return;
-  }
-  TailDesc D = *H.dense_host;
-  const int32_t n0 = D.lv[0].n;
-  int inner = -1;
-  if (n0 > DENSE_INNER_MAX)
-    for (int l = 1; l + 2 < D.nlev; ++l)
-      if (D.lv[l].n <= DENSE_INNER_MAX) {
-        inner = l;
-        break;
-      }
-  DVec<T> Cin;
-  if (inner > 0) {  // the inner operator first, on the tail from level `inner`
-    TailDesc Di = D;
-    Di.nlev = D.nlev - inner;
-    for (int l = 0; l < Di.nlev; ++l) Di.lv[l] = D.lv[l + inner];
-    Di.dense_rel = -1;
-    const int32_t ni = Di.lv[0].n;
-    Cin.resize((size_t)ni * ni);
-    dense_columns<T>(Di, Cin.p, s);
-    D.dense_rel = inner;
-    DenseOf<T>::inner(D, Cin.p);
-  }
-  C.resize((size_t)n0 * n0);
-  DenseOf<T>::part(H).resize((size_t)dense_chunks(n0) * n0);
-  dense_columns<T>(D, C.p, s);
+  const int32_t nd = H.lv[H.dense_start].A->n;
+  C.resize((size_t)nd * nd);
+  DenseOf<T>::part(H).resize((size_t)dense_chunks(nd) * nd);
+  dense_bottom_up<T>(H, C.p, c->s);
 }
 
 void run_cycle64(pcamg_ctx* c, Hierarchy& H, const double* b, double* x, int gamma) {

@@ -82,11 +82,6 @@ struct TailDesc {
   int32_t oacc64, oacc32;  // accumulator offsets (doubles) in the two layouts
   int32_t oL64, oL32;      // factor L offsets (doubles), -1 = read from global memory
   int32_t ncoff;
-  // optional inner dense operator (construction of a dense tail operator only):
-  // at relative level dense_rel the two W sub-cycles are one product with C
-  int32_t dense_rel;
-  const double* C64;
-  const float* C32;
   const double *L, *D;
   TailLevel lv[TAIL_MAX_LEVELS];
 };
@@ -96,10 +91,9 @@ struct Hierarchy {
   // tail: levels tail_start.. run in one workgroup launch
   int tail_start = -1;
   DVec<TailDesc> tail_desc;
-  // W-cycles: the sub-hierarchy whose two sub-cycles are one dense operator
+  // W-cycles: the level whose two sub-cycles the level above applies as one
+  // dense operator (column-major, built on first use)
   int dense_start = -1;
-  std::unique_ptr<TailDesc> dense_host;  // host descriptor of levels dense_start..
-  // W-cycles: the two tail sub-cycles as one dense operator (column-major)
   DVec<double> C64, dpart64;
   DVec<float> C32, dpart32;
   std::vector<DVec<int32_t>> coff_dev;
@@ -199,18 +193,13 @@ void run_cycle64(pcamg_ctx* c, Hierarchy& H, const double* b, double* x, int gam
 void run_cycle32(pcamg_ctx* c, Hierarchy& H, const float* b, float* x, int gamma);
 void tail_cycle64(const Hierarchy& H, const double* b, double* x, int gamma, hipStream_t s);
 void tail_cycle32(const Hierarchy& H, const float* b, float* x, int gamma, hipStream_t s);
-template <typename T>
-void tail_dense(const TailDesc* desc, int32_t n0, int blocks, T* C, size_t gstride, hipStream_t s);
-template <typename T>
-void tail_dense_mc(const TailDesc* desc, int blocks, T* C, size_t gstride, size_t lds, hipStream_t s);
+
 // dense.hip: the dense W operator built level by level from the coarsest up
 // (GEMMs for the products with dense operators); column-major into C (n_d^2).
 bool dense_bottom_up_fits(const Hierarchy& H);
 template <typename T>
 void dense_bottom_up(Hierarchy& H, T* C, hipStream_t s);
-size_t dense_mc_lds_bytes(int32_t cn, int32_t cm, size_t tsize);
-int dense_mc_columns();
-int dense_mc_threads();
+
 template <typename T>
 void dense_apply(int32_t n, const T* C, const T* b, T* part, T* y, hipStream_t s);
 int32_t dense_chunks(int32_t n);

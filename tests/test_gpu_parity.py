@@ -547,10 +547,10 @@ def test_colour_red_black(gpu, oracle, name, make):
 
 @pytest.mark.parametrize("shape,dmax", [((24, 24, 16), 6144), ((32, 32, 32), 12288)])
 def test_dense_w_cycle_nested(gpu, oracle, shape, dmax):
-    """A dense operator whose first level exceeds the inner size is built with
-    an inner dense operator nested in its columns' sub-cycles (its first level
-    launched step by step above the tail); still the W-cycle up to rounding
-    (FP64 1e-12, FP32 1e-5 relative)."""
+    """A dense operator several levels above the coarsest (built level by
+    level, each level's coarse correction a GEMM with the operator below; its
+    first level launched step by step above the tail): still the W-cycle up to
+    rounding (FP64 1e-12, FP32 1e-5 relative)."""
     g = I.grid3d(*shape, weight_seed=11)
     n = g[0]
     b = I.zero_mean_normal_rhs(3, n)
