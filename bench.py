@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-variant", action="store_true")
     ap.add_argument("--numW", type=int, default=2, help="re-setups whose error approximation uses W-cycles (Alg. 2)")
+    ap.add_argument("--row-lanes", type=int, default=None,
+                    help="lanes per matrix row (-1 autotuned, 0 by mean row length); default: the library's")
     ap.add_argument("--workload", choices=["grid3d", "batch", "learned"], default="grid3d",
                     help="grid3d: the 128^3 weighted grid (the benchmark line); batch: uneven graphs solved "
                          "together (separate JSON line)")
@@ -360,6 +362,8 @@ def main():
     b_d = torch.as_tensor(b, device=dev)
     P.lib()
     params = dict(outer="fcg", cycle_prec="f32", theta=0.5, numW=args.numW)
+    if args.row_lanes is not None:
+        params["row_lanes"] = args.row_lanes
 
     def step(pp):
         s = P.Solver(rp_d, ci_d, w_d, b_d, **pp)

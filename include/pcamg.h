@@ -89,7 +89,11 @@ typedef struct {
                               launch per cycle (2048; 0 = per-step launches everywhere) */
   int32_t use_graphs;      /* 1 = replay whole cycles from captured HIP graphs */
   int32_t row_lanes;       /* lanes per matrix row in the smoother/residual kernels: 0 = by the
-                              level's mean row length, else 1, 4, 16 or 64 (results identical) */
+                              level's mean row length; -1 = autotuned: each launched level
+                              (more than 2048 vertices) times one sweep with 1 (sliced-ELL
+                              when available), 4 and 16 lanes and keeps the fastest, cached
+                              per level shape for the process; else 1, 4, 16 or 64.  Results
+                              are identical for every setting */
   int32_t w_dense;         /* 1 = in W-cycles, the two sub-cycles of the first level of at most
                               dense_max_n vertices are applied as one precomputed dense operator
                               (equal up to rounding order; built level by level from the coarsest

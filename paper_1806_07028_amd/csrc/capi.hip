@@ -231,8 +231,9 @@ void setup_impl(const pcamg_graph* g, const double* rhs, const pcamg_params* p, 
                 pcamg_net* net) {
   require(g && p && out, PCAMG_EINVAL, "null argument");
   *out = nullptr;
-  require(p->row_lanes == 0 || p->row_lanes == 1 || p->row_lanes == 4 || p->row_lanes == 16 || p->row_lanes == 64,
-          PCAMG_EINVAL, "row_lanes must be 0, 1, 4, 16 or 64");
+  require(p->row_lanes == -1 || p->row_lanes == 0 || p->row_lanes == 1 || p->row_lanes == 4 || p->row_lanes == 16 ||
+              p->row_lanes == 64,
+          PCAMG_EINVAL, "row_lanes must be -1, 0, 1, 4, 16 or 64");
   require(p->first_sweeps >= -1 && p->first_sweeps <= 1000, PCAMG_EINVAL, "first_sweeps out of range");
   hipStream_t s = as_stream(stream);
   if (p->validate) validate_graph(g, s);

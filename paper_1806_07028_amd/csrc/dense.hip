@@ -21,6 +21,9 @@
 // map as the recursion with a different rounding order.
 #include <rocblas/rocblas.h>
 
+#include <map>
+#include <mutex>
+
 #include "rowchain.hpp"
 #include "solver.hpp"
 
@@ -201,16 +204,32 @@ void gemm_rows(rocblas_handle h, int32_t p, int32_t q, int32_t r, T alpha, const
   PCAMG_BLAS(LevelOf<T>::gemm(h, r, p, q, alpha, R, r, Q, q, beta, P, r));
 }
 
-struct BlasHandle {
-  rocblas_handle h = nullptr;
-  explicit BlasHandle(hipStream_t s) {
-    PCAMG_BLAS(rocblas_create_handle(&h));
-    PCAMG_BLAS(rocblas_set_stream(h, s));
-    // no split-k atomics: the same operator on every run
-    PCAMG_BLAS(rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed));
+// One rocBLAS handle per device for the life of the process, used by one
+// build at a time: builds from concurrent solves (the batch entry point's
+// worker threads) take turns, and no handle is created or destroyed -- no
+// allocation or free inside rocBLAS -- while other threads capture graphs.
+struct BlasLease {
+  static std::mutex& mu() {
+    static std::mutex m;
+    return m;
   }
-  ~BlasHandle() {
-    if (h) (void)rocblas_destroy_handle(h);
+  std::lock_guard<std::mutex> lk;
+  rocblas_handle h = nullptr;
+  explicit BlasLease(hipStream_t s) : lk(mu()) {
+    static std::map<int, rocblas_handle> handles;  // guarded by mu()
+    int dev = 0;
+    PCAMG_HIP(hipGetDevice(&dev));
+    auto it = handles.find(dev);
+    if (it == handles.end()) {
+      rocblas_initialize();
+      rocblas_handle nh = nullptr;
+      PCAMG_BLAS(rocblas_create_handle(&nh));
+      // no split-k atomics: the same operator on every run
+      PCAMG_BLAS(rocblas_set_atomics_mode(nh, rocblas_atomics_not_allowed));
+      it = handles.emplace(dev, nh).first;
+    }
+    h = it->second;
+    PCAMG_BLAS(rocblas_set_stream(h, s));
   }
 };
 
@@ -244,7 +263,7 @@ void dense_bottom_up(Hierarchy& H, T* C, hipStream_t s) {
   const int nl = (int)H.lv.size();
   const int d = H.dense_start;
   require(d >= 0 && nl - d >= 2 && dense_bottom_up_fits(H), PCAMG_EINVAL, "no dense region for the bottom-up build");
-  BlasHandle blas(s);
+  BlasLease blas(s);  // held until the build has completed on s
   // Z: the coarsest operator on the identity
   const int32_t cn = H.cn;
   DVec<T> W(std::max<size_t>((size_t)cn * cn, 1));

@@ -4,6 +4,8 @@
 // sequences launches and reads back scalars (sizes, norms, step lengths).
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 
 #include "solver.hpp"
 
@@ -24,6 +26,64 @@ int32_t pick_lanes(int32_t n, int32_t nnz, int32_t forced) {
 // Levels at most this size run in the single-workgroup tail or are latency
 // bound: no sliced-ELL copy.
 constexpr int32_t SELL_MIN_N = 4096;
+// Levels at most this size are not timed by the lanes autotuner (they run in
+// the tail kernel by default).
+constexpr int32_t TUNE_MIN_N = 2048;
+
+// Autotuned lanes per row (row_lanes = -1).  Candidates: one thread per row
+// (on the sliced-ELL copy when the level has one), 4 and 16 lanes per row.
+// Each runs one symmetric FP32 sweep of the level as a warm-up and two timed
+// with HIP events on the level's stream; the fastest is kept.  Every candidate
+// sums each row in the same order, so the choice changes the time only.
+// Decisions are cached for the life of the process by level shape: size in
+// quarter octaves, mean row length in halves, number of colours.
+struct LaneShape {
+  int32_t logn4, mean2, ncol;
+  bool operator<(const LaneShape& o) const {
+    return logn4 != o.logn4 ? logn4 < o.logn4 : mean2 != o.mean2 ? mean2 < o.mean2 : ncol < o.ncol;
+  }
+};
+std::mutex g_lane_mu;
+std::map<LaneShape, int32_t> g_lane_cache;
+
+int32_t tune_lanes(const LevelMatrix& M, hipStream_t s) {
+  const LaneShape key{(int32_t)std::lround(4.0 * std::log2((double)M.n)),
+                      (int32_t)std::lround(2.0 * (double)M.nnz / M.n), M.ncol};
+  {
+    std::lock_guard<std::mutex> lk(g_lane_mu);
+    auto it = g_lane_cache.find(key);
+    if (it != g_lane_cache.end()) return it->second;
+  }
+  DVec<float> b(M.n), x(M.n);
+  fill_f32(b.p, 1.0f, M.n, s);
+  fill_f32(x.p, 0.0f, M.n, s);
+  auto pass = [&](int k, int lanes) {
+    if (lanes == 1 && M.sell())
+      gs_colour_sell<float>(M.coff[k], M.coff[k + 1], M.rp.p, M.woff.p, M.sci.p, M.sav32.p, M.dinv32.p, b.p, x.p, s);
+    else
+      gs_colour<float>(M.coff[k], M.coff[k + 1], M.rp.p, M.ci.p, M.av32.p, M.dinv32.p, b.p, x.p, s, lanes);
+  };
+  auto sweep = [&](int lanes) {
+    for (int k = 0; k < M.ncol; ++k) pass(k, lanes);
+    for (int k = M.ncol - 1; k >= 0; --k) pass(k, lanes);
+  };
+  int32_t best = 1;
+  double best_ms = 0.0;
+  for (int lanes : {1, 4, 16}) {
+    sweep(lanes);
+    Timer t(s);
+    sweep(lanes);
+    sweep(lanes);
+    const double ms = t.ms();
+    if (lanes == 1 || ms < best_ms) {
+      best = lanes;
+      best_ms = ms;
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_lane_mu);
+  g_lane_cache.emplace(key, best);
+  return best;
+}
 
 std::shared_ptr<LevelMatrix> make_level_matrix(int32_t n, int32_t nnz, const int32_t* rp, const int32_t* ci,
                                                const double* av, const double* d, const double* dinv,
@@ -32,7 +92,8 @@ std::shared_ptr<LevelMatrix> make_level_matrix(int32_t n, int32_t nnz, const int
   auto M = std::make_shared<LevelMatrix>();
   M->n = n;
   M->nnz = nnz;
-  M->lanes = pick_lanes(n, nnz, row_lanes);
+  const bool tune = row_lanes < 0 && n > TUNE_MIN_N && ncol >= 1;
+  M->lanes = pick_lanes(n, nnz, row_lanes < 0 ? 0 : row_lanes);
   M->perm.resize(n);
   M->iperm.resize(n);
   if (colour) {
@@ -55,8 +116,18 @@ std::shared_ptr<LevelMatrix> make_level_matrix(int32_t n, int32_t nnz, const int
   permute_csr(n, M->perm.p, M->iperm.p, rp, ci, av, d, dinv, M->rp.p, M->ci.p, M->av.p, M->av32.p, M->d.p,
               M->dinv.p, M->d32.p, M->dinv32.p, s);
   // short rows on a level large enough for launched passes: sliced-ELL copy
-  if (M->lanes == 1 && n > SELL_MIN_N)
+  // (the autotuner tries it on every level it times)
+  if ((M->lanes == 1 || tune) && n > SELL_MIN_N)
     sell_build(n, nnz, M->rp.p, M->ci.p, M->av.p, M->av32.p, M->woff, M->sci, M->sav, M->sav32, s);
+  if (tune) {
+    M->lanes = tune_lanes(*M, s);
+    if (M->lanes != 1 && M->sell()) {
+      M->woff.resize(0);
+      M->sci.resize(0);
+      M->sav.resize(0);
+      M->sav32.resize(0);
+    }
+  }
   return M;
 }
 
