@@ -204,10 +204,13 @@ void gemm_rows(rocblas_handle h, int32_t p, int32_t q, int32_t r, T alpha, const
   PCAMG_BLAS(LevelOf<T>::gemm(h, r, p, q, alpha, R, r, Q, q, beta, P, r));
 }
 
-// One rocBLAS handle per device for the life of the process, used by one
-// build at a time: builds from concurrent solves (the batch entry point's
-// worker threads) take turns, and no handle is created or destroyed -- no
-// allocation or free inside rocBLAS -- while other threads capture graphs.
+// One rocBLAS handle per device for the life of the process, with a
+// workspace of ours, used by one build at a time: builds from concurrent
+// solves (the batch entry point's worker threads) take turns, and no handle
+// or workspace is created or destroyed -- no allocation or free inside
+// rocBLAS -- while other threads capture graphs.
+constexpr size_t BLAS_WORKSPACE = (size_t)128 << 20;
+
 struct BlasLease {
   static std::mutex& mu() {
     static std::mutex m;
@@ -226,6 +229,11 @@ struct BlasLease {
       PCAMG_BLAS(rocblas_create_handle(&nh));
       // no split-k atomics: the same operator on every run
       PCAMG_BLAS(rocblas_set_atomics_mode(nh, rocblas_atomics_not_allowed));
+      // a workspace of our own, allocated once: rocBLAS then never allocates
+      // or frees device memory during a solve
+      void* ws = nullptr;
+      PCAMG_HIP(hipMalloc(&ws, BLAS_WORKSPACE));
+      PCAMG_BLAS(rocblas_set_workspace(nh, ws, BLAS_WORKSPACE));
       it = handles.emplace(dev, nh).first;
     }
     h = it->second;
