@@ -209,12 +209,23 @@ def ba_edges(n: int, seed: int, m: int = 4):
     return n, *canonical_edges(np.array(src), np.array(dst))
 
 
+def uniform_at(seed: int, k: np.ndarray) -> np.ndarray:
+    """Uniform doubles in [0, 1) from stream words k (any uint64 counters)."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + np.asarray(k, dtype=np.uint64) * np.uint64(GAMMA)
+    return (mix64(z) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
 def chung_lu_edges(n0: int, seed: int, gamma: float = 2.1, mean_degree: float = 16.0,
                    max_degree: float | None = None):
     """Chung-Lu graph with expected degrees w_i = c (i + i0)^(-1/(gamma-1)).
 
-    Edges are independent with p_ij = min(1, w_i w_j / sum(w)); sampled by the
-    O(n + m) skipping method of Miller & Hagberg (2011).  Largest component kept.
+    Edges are independent with p_ij = min(1, w_i w_j / sum(w)); each source a
+    walks its candidates b > a with the skipping method of Miller & Hagberg
+    (2011): a geometric jump with the current probability p, then acceptance
+    with q/p.  Draw t of source a is word (a << 24) + t + 1 of the stream, so
+    all sources advance together, one step per numpy pass.  Largest component
+    kept.
     """
     if max_degree is None:
         max_degree = float(np.sqrt(mean_degree * n0))
@@ -233,41 +244,39 @@ def chung_lu_edges(n0: int, seed: int, gamma: float = 2.1, mean_degree: float = 
     wv = (i + np.sqrt(lo * hi)) ** (-ex)
     wv *= mean_degree / wv.mean()
     S = wv.sum()
-    ustream = _UniformStream(seed)
+    a = np.arange(n0 - 1, dtype=np.int64)
+    b = a + 1
+    p = np.minimum(1.0, wv[a] * wv[b] / S)
+    t = np.zeros(n0 - 1, dtype=np.int64)
+    act = (b < n0) & (p > 0)
+    a, b, p, t = a[act], b[act], p[act], t[act]
     src, dst = [], []
-    for a in range(n0 - 1):
-        b = a + 1
-        p = min(1.0, wv[a] * wv[b] / S)
-        while b < n0 and p > 0:
-            if p != 1.0:
-                r = ustream.next()
-                b += int(np.floor(np.log(r) / np.log1p(-p))) if r > 0 else n0
-            if b < n0:
-                q = min(1.0, wv[a] * wv[b] / S)
-                if ustream.next() < q / p:
-                    src.append(a)
-                    dst.append(b)
-                p = q
-                b += 1
-    a_, b_ = canonical_edges(np.array(src, dtype=np.int64), np.array(dst, dtype=np.int64))
+    while len(a):
+        # geometric jump over the candidates rejected with probability p each
+        jump = p < 1.0
+        if jump.any():
+            r = 1.0 - uniform_at(seed, (a[jump] << 24) + t[jump] + 1)  # in (0, 1]
+            t[jump] += 1
+            b[jump] += np.floor(np.log(r) / np.log1p(-p[jump])).astype(np.int64)
+        live = b < n0
+        a, b, p, t = a[live], b[live], p[live], t[live]
+        if not len(a):
+            break
+        q = np.minimum(1.0, wv[a] * wv[b] / S)
+        u = 1.0 - uniform_at(seed, (a << 24) + t + 1)
+        t += 1
+        acc = u < q / p
+        src.append(a[acc])
+        dst.append(b[acc])
+        p = q
+        b = b + 1
+        live = (b < n0) & (p > 0)
+        a, b, p, t = a[live], b[live], p[live], t[live]
+    src = np.concatenate(src) if src else np.zeros(0, np.int64)
+    dst = np.concatenate(dst) if dst else np.zeros(0, np.int64)
+    a_, b_ = canonical_edges(src, dst)
     n2, a2, b2, _ = largest_component(n0, a_, b_)
     return n2, *canonical_edges(a2, b2)
-
-
-class _UniformStream:
-    def __init__(self, seed: int, block: int = 1 << 20):
-        self.seed, self.block, self.start = seed, block, 0
-        self.buf = uniform(seed, block, 0)
-        self.pos = 0
-
-    def next(self) -> float:
-        if self.pos >= self.block:
-            self.start += self.block
-            self.buf = uniform(self.seed, self.block, self.start)
-            self.pos = 0
-        x = self.buf[self.pos]
-        self.pos += 1
-        return 1.0 - x  # in (0, 1]
 
 
 # ----------------------------------------------------------------------------
@@ -338,6 +347,16 @@ def config2(seed: int = 1, side: int = 128):
     """side^3 7-point grid, log-uniform weights on [1e-3, 1e3], zero-mean N(0,1) rhs."""
     g = grid3d(side, side, side, weight_seed=seed, lo=-3.0, hi=3.0)
     return g, zero_mean_normal_rhs(seed + 1000, g[0])
+
+
+def config3(seed: int = 1, n0: int = 4_000_000):
+    """Chung-Lu power-law graph: n0 vertices, degree exponent 2.1, mean degree
+    16, largest component kept; weights uniform in (0, 1]; zero-mean N(0,1)
+    rhs.  Solved with the A^2 hub cap (2-hop pairs only through pivots of
+    degree <= 64)."""
+    n, a, b = chung_lu_edges(n0, seed)
+    g = csr_from_edges(n, a, b, unit_interval_weights(seed + 1, len(a)))
+    return g, zero_mean_normal_rhs(seed + 2000, n)
 
 
 def config4(seed: int = 1, count: int = 512, n_lo: float = 1e3, n_hi: float = 2e5):

@@ -516,9 +516,11 @@ def test_batch_errors(gpu):
 
 
 def test_colour_dense_levels(gpu, oracle):
-    """Near-dense small graphs take the one-vertex-at-a-time greedy kernel;
-    sparse ones of the same size the Jones-Plassmann rounds: both equal the
-    oracle's first-fit in priority order."""
+    """Near-dense graphs (more than 48 entries per row) take the
+    one-vertex-at-a-time greedy kernels (order sorted in LDS, or by a device
+    sort for larger ones), dense ones (more than 32) counted rounds, sparse ones
+    the Jones-Plassmann rounds: all equal the oracle's first-fit in priority
+    order."""
     S = gpu.stages
     cases = []
     n = 300  # complete graph
@@ -532,6 +534,13 @@ def test_colour_dense_levels(gpu, oracle):
     a2, b2 = I.canonical_edges(a[m], b[m])
     cases.append(I.csr_from_edges(n, a2, b2, np.ones(len(a2))))
     cases.append(I.rgg(2500, 5))  # sparse, same size range
+    for n, deg, seed in ((3000, 60, 78), (20000, 60, 79), (20000, 40, 80)):  # LDS order, sorted, counted
+        u = I.uniform(seed, 2 * n * deg // 2)
+        a = np.minimum((u[0::2] * n).astype(np.int64), n - 1)
+        b = np.minimum((u[1::2] * n).astype(np.int64), n - 1)
+        m = a != b
+        a2, b2 = I.canonical_edges(a[m], b[m])
+        cases.append(I.csr_from_edges(n, a2, b2, np.ones(len(a2))))
     for g in cases:
         n, rp, ci, w = g
         for level in (0, 3):
@@ -571,6 +580,43 @@ def test_colour_red_black(gpu, oracle, name, make):
     col, nc = gpu.stages.colour(rp, ci, 0xC010, 1)
     rcol, rnc = oracle.colour(n, rp, ci, 0xC010, 1)
     assert nc == rnc
+    same(host(col), rcol)
+
+
+def _cliques_plus_random(n, ncliques, size, deg, seed):
+    """ncliques disjoint cliques of `size` vertices, plus random edges of mean
+    degree `deg` over all n vertices and a ring (connected)."""
+    a, b = [], []
+    for q in range(ncliques):
+        i, j = np.triu_indices(size, 1)
+        a.append(q * size + i)
+        b.append(q * size + j)
+    m = n * deg // 2
+    u = I.uniform(seed, 2 * m)
+    a.append(np.minimum((u[0::2] * n).astype(np.int64), n - 1))
+    b.append(np.minimum((u[1::2] * n).astype(np.int64), n - 1))
+    a.append(np.arange(n))
+    b.append((np.arange(n) + 1) % n)
+    a, b = np.concatenate(a), np.concatenate(b)
+    keep = a != b
+    a2, b2 = I.canonical_edges(a[keep], b[keep])
+    return I.csr_from_edges(n, a2, b2, np.ones(len(a2)))
+
+
+@pytest.mark.parametrize("n,ncl,size,deg", [(20000, 1, 100, 2),    # rounds over worklists
+                                            (3000, 1, 80, 2),      # rounds in one workgroup
+                                            (4000, 10, 80, 50),    # near-dense: one vertex at a time, LDS
+                                            (12000, 20, 80, 50),   # near-dense: one at a time, sorted order
+                                            (12000, 20, 80, 34),   # dense: counted rounds
+                                            (140000, 20, 80, 50)])  # near-dense and large: counted rounds
+def test_colour_many_colours(gpu, oracle, n, ncl, size, deg):
+    """More than 64 colours (every vertex of a clique of 80-100 takes its own):
+    the first-fit search beyond the first 64 colours, on every colouring path,
+    equals the oracle."""
+    n_, rp, ci, w = _cliques_plus_random(n, ncl, size, deg, 90 + n)
+    col, nc = gpu.stages.colour(rp, ci, 0xC010, 2)
+    rcol, rnc = oracle.colour(n, rp, ci, 0xC010, 2)
+    assert nc == rnc > 64
     same(host(col), rcol)
 
 
