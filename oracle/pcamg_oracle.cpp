@@ -32,7 +32,9 @@
 //    Levels > 1 are boolean.  Reweighted graph coarsened with the boolean matrix.
 //  * Path shortening (Alg. 4, Step 7): contract, collapse repeats, keep only the
 //    first occurrence of a coarse vertex (paths ordered by start id) and cut there.
-//  * Coarsest level: n <= coarse_max, or stall (n_c > 0.9 n), or max levels;
+//  * Coarsest level: n <= coarse_max, or stall (n_c > 0.9 n) on a level of at
+//    most 4096 vertices (a larger stalled level keeps coarsening while
+//    n_c < n), or max levels;
 //    dense LDL^T, grounded (last vertex pinned, mean removed) iff the coarsest
 //    operator is a Laplacian (every prolongation boolean, or a single level),
 //    full otherwise; a non-positive pivot falls back to grounded.
@@ -838,7 +840,10 @@ bool build_hierarchy(const Level& fine, const std::vector<double>& e_raw, const 
     if (L.n <= P.coarse_max || l + 1 >= P.max_levels) break;
     orient_paths(L.n, L.nb, L.path_id, L.pos, L.plen, L.n_paths);
     aggregate(L);
-    if (L.nc > 0.9 * L.n) {  // stall: this level becomes the coarsest
+    // stall (n_c > 0.9 n): this level becomes the coarsest, if the dense
+    // coarsest solve can take it; a larger level keeps coarsening while it
+    // still shrinks
+    if (L.nc > 0.9 * L.n && (L.n <= 4096 || L.nc >= L.n)) {
       L.nc = 0;
       L.agg.clear();
       L.moff.clear();
