@@ -154,37 +154,6 @@ __global__ void __launch_bounds__(JP_SMALL_THREADS)
   if (threadIdx.x == 0) *rounds_out = rounds;
 }
 
-// Number of higher-priority neighbours of v (a vertex waits for all of them).
-template <typename PP>
-__device__ __forceinline__ int32_t jp_higher(int32_t v, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                             PP prio) {
-  constexpr int U = 8;
-  const uint64_t pv = prio[v];
-  const int32_t k0 = rp[v], k1 = rp[v + 1];
-  int32_t c = 0;
-  for (int32_t k = k0; k < k1; k += U) {
-    int32_t u[U];
-    uint64_t pu[U];
-#pragma unroll
-    for (int j = 0; j < U; ++j) u[j] = k + j < k1 ? ci[k + j] : v;
-#pragma unroll
-    for (int j = 0; j < U; ++j) pu[j] = prio[u[j]];
-#pragma unroll
-    for (int j = 0; j < U; ++j) c += (u[j] != v && (pu[j] > pv || (pu[j] == pv && u[j] > v))) ? 1 : 0;
-  }
-  return c;
-}
-
-// Rounds with counts (large dense levels).  Rescanning every pending vertex's
-// row in every round costs rounds x edges, which on the near-dense coarse
-// operators of power-law graphs (hundreds of entries per row) dominates the
-// setup.  Here each vertex keeps the count of its uncoloured higher-priority
-// neighbours; a round colours the vertices whose count is zero (first-fit over
-// their higher-priority neighbours, all coloured) and decrements their
-// lower-priority neighbours, which join the next round at zero.  Every edge is
-// touched a bounded number of times; the colouring is the same first-fit in
-// priority order.
-
 // Greedy first-fit in descending (priority, id) order, one vertex at a time with
 // the neighbour scan spread over the workgroup -- the same colouring as the
 // Jones-Plassmann rounds (a vertex's already coloured neighbours are exactly
@@ -256,7 +225,7 @@ __global__ void __launch_bounds__(1024)
 // device radix sort (ascending (key, id), walked backwards), the colours in
 // global memory and the bitmask of the colours around the current vertex in
 // LDS (a vertex's colour is at most its degree, so max degree + 1 bits).
-constexpr int32_t SEQ_LARGE_MAX = 131072;
+constexpr int32_t SEQ_LARGE_MAX = 1 << 20;
 constexpr int32_t SEQ_BITS_MAX = 65536;
 __global__ void __launch_bounds__(1024)
     greedy_seq_large_kernel(int32_t n, int32_t nwords, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
@@ -317,62 +286,14 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// Appends v (where flag is set) to out with one atomic per wavefront; every
-// lane of the wavefront calls it.
-__device__ __forceinline__ void wave_append(bool flag, int32_t v, int32_t* __restrict__ cnt_out,
-                                            int32_t* __restrict__ out) {
-  const unsigned long long bal = __ballot(flag);
-  if (!bal) return;
-  const int lane = threadIdx.x & 63;
-  const int first = __ffsll((long long)bal) - 1;
-  int32_t at = 0;
-  if (lane == first) at = atomicAdd(cnt_out, __popcll(bal));
-  at = __shfl(at, first, 64);
-  if (flag) out[at + __popcll(bal & ((1ull << lane) - 1ull))] = v;
-}
-
-// Counted rounds on large dense levels: the counts, and the first ready list.
-__global__ void __launch_bounds__(256)
-    jp_count_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                    const uint64_t* __restrict__ prio, int32_t* __restrict__ pend, int32_t* __restrict__ cnt_out,
-                    int32_t* __restrict__ out) {
-  const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  int32_t c = -1;
-  if (v < n) {
-    c = jp_higher(v, rp, ci, prio);
-    pend[v] = c;
-  }
-  wave_append(c == 0, v, cnt_out, out);
-}
-
-// One counted round: colour the ready vertices, release their lower-priority
-// neighbours (a neighbour whose count reaches zero joins the next list).
-__global__ void __launch_bounds__(256)
-    jp_ready_kernel(const int32_t* __restrict__ cnt_in, const int32_t* __restrict__ in, int32_t* __restrict__ cnt_out,
-                    int32_t* __restrict__ out, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                    const uint64_t* __restrict__ prio, int32_t* colour, int32_t* pend) {
-  const int32_t m = *cnt_in;
-  const int32_t stride = gridDim.x * blockDim.x;
-  for (int32_t base = blockIdx.x * blockDim.x; base < m; base += stride) {  // uniform per workgroup
-    const int32_t t = base + threadIdx.x;
-    const bool act = t < m;
-    const int32_t v = act ? in[t] : 0;
-    if (act) (void)jp_try(v, rp, ci, prio, colour);
-    const uint64_t pv = act ? prio[v] : 0ull;
-    const int32_t k0 = act ? rp[v] : 0;
-    const int32_t len = act ? rp[v + 1] - k0 : 0;
-    const int32_t span = wave_max_len(len);
-    for (int32_t j = 0; j < span; ++j) {
-      bool ready = false;
-      int32_t u = 0;
-      if (j < len) {
-        u = ci[k0 + j];
-        const uint64_t pu = prio[u];
-        if (pu < pv || (pu == pv && u < v)) ready = atomicSub(&pend[u], 1) == 1;
-      }
-      wave_append(ready, u, cnt_out, out);
-    }
-  }
+// Priority keys and ids of the m vertices of a list (for sorting them).
+__global__ void list_keys_kernel(int32_t m, const int32_t* __restrict__ list, const uint64_t* __restrict__ prio,
+                                 uint64_t* __restrict__ keys, uint32_t* __restrict__ ids) {
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m) return;
+  const int32_t v = list[t];
+  keys[t] = prio[v];
+  ids[t] = (uint32_t)v;
 }
 
 // counts of the next batch: cnt[0] = cnt[last], the others zero
@@ -396,10 +317,32 @@ __global__ void max_i32_kernel(const int32_t* a, int32_t n, int32_t* out) {
   if ((threadIdx.x & 63) == 0) atomicMax(out, m);
 }
 
-// Mean row lengths above which levels are coloured one vertex at a time
-// (JP_SEQ_DEG) or in counted rounds (JP_COUNT_DEG).
+// Mean row length above which levels are coloured one vertex at a time.
 constexpr int64_t JP_SEQ_DEG = 48;
-constexpr int64_t JP_COUNT_DEG = 32;
+
+// The vertices of `list` (m of them, the uncoloured ones) coloured one at a time
+// in descending (priority, id) order.  Every uncoloured vertex's lower-priority
+// neighbours are uncoloured too (a vertex is coloured only after all its
+// higher-priority neighbours), so first-fit over the coloured neighbours is
+// first-fit over the higher-priority ones: the same colouring as the rounds.
+void colour_rest_seq(int32_t m, const int32_t* list, const int32_t* rp, const int32_t* ci, const uint64_t* prio,
+                     int32_t maxdeg, int32_t* colour, hipStream_t s) {
+  DVec<uint64_t> keys(m), skeys(m);
+  DVec<uint32_t> ids(m), asc(m);
+  list_keys_kernel<<<grid_for(m, 256), 256, 0, s>>>(m, list, prio, keys.p, ids.p);
+  PCAMG_LAUNCHED();
+  radix_sort_u64_u32(keys.p, ids.p, skeys.p, asc.p, m, s);
+  greedy_seq_large_kernel<<<1, 1024, 0, s>>>(m, (maxdeg + 1 + 31) / 32, rp, ci, asc.p, colour);
+  PCAMG_LAUNCHED();
+}
+
+int32_t max_row_len(int32_t n, const int32_t* rp, hipStream_t s) {
+  DVec<int32_t> mx(1);
+  fill_i32(mx.p, 0, 1, s);
+  row_len_max_kernel<<<std::min<unsigned>(grid_for(n, 256), 1024), 256, 0, s>>>(n, rp, mx.p);
+  PCAMG_LAUNCHED();
+  return read_scalar(mx.p, s);
+}
 
 int32_t colour_jp(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed, int32_t level, int32_t* colour,
                   hipStream_t s) {
@@ -412,59 +355,25 @@ int32_t colour_jp(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed
   const int64_t nnz = n > 0 ? (int64_t)read_scalar(rp + n, s) : 0;
   // near-dense levels (more than JP_SEQ_DEG entries per row): the priority
   // chains are about as long as the level, so rounds would colour a few
-  // vertices each; colour one vertex at a time in one workgroup up to
-  // SEQ_LARGE_MAX vertices.  Dense levels otherwise (more than JP_COUNT_DEG
-  // entries per row): counted rounds.  Sparse levels (all grid levels):
-  // rounds over worklists.
-  const bool dense = nnz > JP_COUNT_DEG * (int64_t)n;
+  // vertices each: colour one vertex at a time in one workgroup.  Other levels
+  // (every grid level): rounds over worklists, switching to one vertex at a
+  // time for the rest when a batch of R rounds colours fewer than 4R vertices
+  // (a round costs a launch, a few microseconds, about what one vertex costs
+  // one at a time, so below a few vertices a round the rest is cheaper
+  // one at a time).
   const bool seq = nnz > JP_SEQ_DEG * (int64_t)n && n <= SEQ_LARGE_MAX;
-  int32_t maxdeg = 0;
-  if (seq && n > SEQ_MAX) {
-    DVec<int32_t> mx(1);
-    fill_i32(mx.p, 0, 1, s);
-    row_len_max_kernel<<<std::min<unsigned>(grid_for(n, 256), 1024), 256, 0, s>>>(n, rp, mx.p);
-    PCAMG_LAUNCHED();
-    maxdeg = read_scalar(mx.p, s);
-  }
+  const int32_t maxdeg = seq && n > SEQ_MAX ? max_row_len(n, rp, s) : 0;
   if (seq && n <= SEQ_MAX) {
     greedy_seq_kernel<<<1, 1024, 0, s>>>(n, rp, ci, prio.p, colour);
     PCAMG_LAUNCHED();
   } else if (seq && maxdeg + 1 <= SEQ_BITS_MAX) {
-    DVec<uint32_t> ids(n), asc(n);
-    DVec<uint64_t> keys(n);
-    iota_i32(reinterpret_cast<int32_t*>(ids.p), n, s);
-    radix_sort_u64_u32(prio.p, ids.p, keys.p, asc.p, n, s);
-    greedy_seq_large_kernel<<<1, 1024, 0, s>>>(n, (maxdeg + 1 + 31) / 32, rp, ci, asc.p, colour);
-    PCAMG_LAUNCHED();
+    DVec<int32_t> all(n);
+    iota_i32(all.p, n, s);
+    colour_rest_seq(n, all.p, rp, ci, prio.p, maxdeg, colour, s);
   } else if (n <= JP_SMALL_MAX) {
     DVec<int32_t> rounds(1);
     jp_small_kernel<<<1, JP_SMALL_THREADS, 0, s>>>(n, rp, ci, prio.p, colour, rounds.p);
     PCAMG_LAUNCHED();
-  } else if (dense) {
-    // counted rounds over ready lists in batches of R; the host checks the
-    // count after each batch (each round colours at least the highest-priority
-    // uncoloured vertex, so at most n rounds)
-    constexpr int R = 8;
-    DVec<int32_t> pend(n), list0(n), list1(n), cnt(R + 1);
-    fill_i32(cnt.p, 0, R + 1, s);
-    jp_count_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, rp, ci, prio.p, pend.p, cnt.p, list0.p);
-    PCAMG_LAUNCHED();
-    const unsigned grid = std::min<unsigned>(grid_for(n, 256), 1024);
-    int64_t rounds = 0;
-    for (;;) {
-      for (int r = 0; r < R; ++r) {
-        const int32_t* in = (r & 1) ? list1.p : list0.p;
-        int32_t* out = (r & 1) ? list0.p : list1.p;
-        jp_ready_kernel<<<grid, 256, 0, s>>>(cnt.p + r, in, cnt.p + r + 1, out, rp, ci, prio.p, colour, pend.p);
-        PCAMG_LAUNCHED();
-      }
-      rounds += R;
-      if (read_scalar(cnt.p + R, s) == 0) break;
-      require(rounds <= (int64_t)n + R, PCAMG_EHIP, "colouring made no progress");
-      // R is even: the next ready list is in list0 again
-      jp_carry_kernel<<<1, 64, 0, s>>>(cnt.p, R);
-      PCAMG_LAUNCHED();
-    }
   } else {
     // batches of R rounds over shrinking worklists; the host checks the count
     // after each batch (every round removes at least the highest-priority
@@ -475,6 +384,7 @@ int32_t colour_jp(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed
     fill_i32(cnt.p, 0, R + 1, s);
     fill_i32(cnt.p, n, 1, s);
     int32_t pending = n;  // upper bound of the worklist: the grid of the next batch
+    int32_t maxdeg_all = -1;
     int64_t rounds = 0;
     for (;;) {
       const unsigned grid = std::min<unsigned>(grid_for(pending, 256), 2048);
@@ -485,10 +395,18 @@ int32_t colour_jp(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed
         PCAMG_LAUNCHED();
       }
       rounds += R;
+      const int32_t before = pending;
       pending = read_scalar(cnt.p + R, s);
       if (pending == 0) break;
       require(rounds <= (int64_t)n + R, PCAMG_EHIP, "colouring made no progress");
       // R is even: the survivors are in list0 again
+      if (before - pending < 4 * R && pending <= SEQ_LARGE_MAX) {
+        if (maxdeg_all < 0) maxdeg_all = max_row_len(n, rp, s);
+        if (maxdeg_all + 1 <= SEQ_BITS_MAX) {
+          colour_rest_seq(pending, list0.p, rp, ci, prio.p, maxdeg_all, colour, s);
+          break;
+        }
+      }
       jp_carry_kernel<<<1, 64, 0, s>>>(cnt.p, R);
       PCAMG_LAUNCHED();
     }

@@ -338,7 +338,9 @@ std::unique_ptr<Hierarchy> build_hierarchy(pcamg_ctx* c, const double* e_nat) {
     L.mem.resize(L.n);
     const int32_t nc = aggregate_level(L.n, L.grp, L.gci, L.gv, L.gkey, L.nb, L.pid.p, L.pos.p, L.plen.p, L.agg.p,
                                        L.moff.p, L.mem.p, L.st, s);
-    if (nc > 0.9 * L.n) {  // stall: this level becomes the coarsest
+    // stall (n_c > 0.9 n): this level becomes the coarsest if the dense solve
+    // can take it; a larger level keeps coarsening while it still shrinks
+    if (nc > 0.9 * L.n && (L.n <= LDLT_MAX || nc >= L.n)) {
       L.agg.release();
       L.moff.release();
       L.mem.release();

@@ -518,9 +518,8 @@ def test_batch_errors(gpu):
 def test_colour_dense_levels(gpu, oracle):
     """Near-dense graphs (more than 48 entries per row) take the
     one-vertex-at-a-time greedy kernels (order sorted in LDS, or by a device
-    sort for larger ones), dense ones (more than 32) counted rounds, sparse ones
-    the Jones-Plassmann rounds: all equal the oracle's first-fit in priority
-    order."""
+    sort for larger ones), the others the Jones-Plassmann rounds: all equal
+    the oracle's first-fit in priority order."""
     S = gpu.stages
     cases = []
     n = 300  # complete graph
@@ -607,8 +606,9 @@ def _cliques_plus_random(n, ncliques, size, deg, seed):
                                             (3000, 1, 80, 2),      # rounds in one workgroup
                                             (4000, 10, 80, 50),    # near-dense: one vertex at a time, LDS
                                             (12000, 20, 80, 50),   # near-dense: one at a time, sorted order
-                                            (12000, 20, 80, 34),   # dense: counted rounds
-                                            (140000, 20, 80, 50)])  # near-dense and large: counted rounds
+                                            (12000, 20, 80, 34),   # denser: rounds over worklists
+                                            (140000, 20, 80, 34),  # denser and large: rounds over worklists
+                                            (6000, 1, 480, 2)])    # rounds, then one at a time for the rest
 def test_colour_many_colours(gpu, oracle, n, ncl, size, deg):
     """More than 64 colours (every vertex of a clique of 80-100 takes its own):
     the first-fit search beyond the first 64 colours, on every colouring path,
