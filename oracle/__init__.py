@@ -56,7 +56,7 @@ class OracleParams(C.Structure):
 
 DEFAULTS = dict(tol=1e-8, theta=0.4, max_iter=2500, outer=0, cycle_prec=0, coarse_max=64, relax_sweeps=3,
                 rebuild_vcycles=2, rebuild_source=0, p1_mode=0, coarse_solve=0, a2_hub_cap=0, max_rebuilds=50,
-                max_levels=40, numW=2, iterW=7, iterV=4, rebuild_rule=0, seed=0x5EED, colour_seed=0xC010)
+                max_levels=64, numW=2, iterW=7, iterV=4, rebuild_rule=0, seed=0x5EED, colour_seed=0xC010)
 
 
 def params(**kw) -> OracleParams:

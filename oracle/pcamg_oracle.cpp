@@ -24,8 +24,12 @@
 //    endpoint id; positions (2t, 2t+1) are paired; an odd tail is left over.
 //  * Isolated vertices (Alg. 3, Steps 9-19): ascending vertex id; best
 //    neighbour by weight, ties to the smaller id; size-1 aggregates take Case 2;
-//    Case 3 when v is the middle of a 3-chain makes u a singleton; a vertex with
-//    no neighbour is a singleton.
+//    Case 3 takes v out of its aggregate only if the rest stays connected: when
+//    v is the middle of a 3-chain, or the centre of a star that grew that way,
+//    u joins v's aggregate instead (no vertex is left isolated, Sec. 3.3, and
+//    the aggregate keeps diameter <= 2, within the bound of three of the
+//    matching-based aggregation of Sec. 2.1); a vertex with no neighbour is a
+//    singleton.
 //  * Prolongation (Sec. 3.3, Alg. 3 Steps 20-24): level 1 uses e normalised by a
 //    power of two (max|e| in [0.5,1)) and centred by its mean measured in fixed
 //    point at resolution 2^-32; an aggregate whose |e| stays below 2^-26 uses 1.
@@ -465,6 +469,7 @@ void aggregate(Level& L) {
   const int n = L.n;
   std::vector<int> obj(n, -1);
   std::vector<std::vector<int>> members;
+  std::vector<int> centre;  // per aggregate: the vertex it grew at past three members, else -1
   // Steps 5-7: pair along paths
   L.n_path_vertices = 0;
   for (int v = 0; v < n; ++v) {
@@ -478,6 +483,7 @@ void aggregate(Level& L) {
       }
       obj[v] = obj[w] = (int)members.size();
       members.push_back({v, w});
+      centre.push_back(-1);
     }
   }
   // Steps 9-19: vertices not yet aggregated, ascending id
@@ -491,12 +497,14 @@ void aggregate(Level& L) {
     if (v < 0) {  // no neighbour at all
       obj[u] = (int)members.size();
       members.push_back({u});
+      centre.push_back(-1);
       L.singleton++;
       continue;
     }
     if (obj[v] < 0) {  // Case 1
       obj[u] = obj[v] = (int)members.size();
       members.push_back({u, v});
+      centre.push_back(-1);
       L.case1++;
       continue;
     }
@@ -507,17 +515,29 @@ void aggregate(Level& L) {
       L.case2++;
       continue;
     }
-    // Case 3: size 3
-    std::vector<int> rest;
-    for (int m : members[T]) if (m != v) rest.push_back(m);
-    if (adjacent(L.G, rest[0], rest[1])) {
+    // Case 3: take v out of its aggregate, unless that would disconnect it:
+    // a 3-chain whose middle is v, or a star (grown past three members, every
+    // member adjacent to its centre) whose centre is v.  Then u joins it at v.
+    bool take_out;
+    if (members[T].size() == 3) {
+      std::vector<int> rest;
+      for (int m : members[T]) if (m != v) rest.push_back(m);
+      take_out = adjacent(L.G, rest[0], rest[1]);
+    } else {
+      take_out = v != centre[T];
+    }
+    if (take_out) {
+      std::vector<int> rest;
+      for (int m : members[T]) if (m != v) rest.push_back(m);
       members[T] = rest;
       obj[u] = obj[v] = (int)members.size();
       members.push_back({u, v});
+      centre.push_back(-1);
       L.case3++;
-    } else {  // v is the middle of its aggregate: u stays alone
-      obj[u] = (int)members.size();
-      members.push_back({u});
+    } else {
+      members[T].push_back(u);
+      obj[u] = T;
+      centre[T] = v;
       L.middle++;
     }
   }

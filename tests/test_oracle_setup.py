@@ -271,14 +271,36 @@ def test_aggregation_cases(oracle):
     assert st["case2"] == 1 and st["case3"] == 1
     assert agg.tolist() == [0, 0, 1, 2, 1, 2]
 
-    # middle: triple 2-3-4 as a chain (2 !~ 4); u=5's best neighbour is the middle 3 -> singleton
+    # middle: triple 2-3-4 as a chain (2 !~ 4); u=5's best neighbour is the
+    # middle 3: taking 3 out would leave {2, 4} disconnected, so 5 joins
+    # (no isolated vertex, Sec. 3.3)
     edges = [(0, 1), (1, 2), (2, 3), (3, 4), (3, 5)]
     wts = [1, 1, 1, 1, 9]
     n, rp, ci, gw = level_graph(6, edges, wts)
     nb = nb_from_paths(6, [[0, 1], [2, 3, 4]])
     agg, nc, st = oracle.aggregate(n, rp, ci, gw, nb)
-    assert st["case2"] == 1 and st["middle"] == 1
-    assert agg.tolist() == [0, 0, 1, 1, 1, 2]
+    assert st["case2"] == 1 and st["middle"] == 1 and st["singleton"] == 0
+    assert agg.tolist() == [0, 0, 1, 1, 1, 1]
+
+    # star: 5 and then 6 join at the centre 3; 7's best neighbour is the leaf
+    # 5, which leaves the star (the rest stays connected through 3): {5, 7}
+    edges = [(0, 1), (1, 2), (2, 3), (3, 4), (3, 5), (3, 6), (5, 7)]
+    wts = [1, 1, 1, 1, 9, 9, 1]
+    n, rp, ci, gw = level_graph(8, edges, wts)
+    nb = nb_from_paths(8, [[0, 1], [2, 3, 4]])
+    agg, nc, st = oracle.aggregate(n, rp, ci, gw, nb)
+    assert st["case2"] == 1 and st["middle"] == 2 and st["case3"] == 1
+    assert agg.tolist() == [0, 0, 1, 1, 1, 2, 1, 2] and nc == 3
+
+    # the centre stays: 8's best neighbour is the centre 3 of the star {2,3,4,5,6}
+    # (after 7 took 5 out it is {2,3,4,6}): 8 joins it
+    edges = [(0, 1), (1, 2), (2, 3), (3, 4), (3, 5), (3, 6), (5, 7), (3, 8)]
+    wts = [1, 1, 1, 1, 9, 9, 1, 9]
+    n, rp, ci, gw = level_graph(9, edges, wts)
+    nb = nb_from_paths(9, [[0, 1], [2, 3, 4]])
+    agg, nc, st = oracle.aggregate(n, rp, ci, gw, nb)
+    assert st["middle"] == 3 and st["case3"] == 1
+    assert agg.tolist() == [0, 0, 1, 1, 1, 2, 1, 2, 1]
 
     # a vertex without neighbours is a singleton
     n, rp, ci, gw = level_graph(3, [(0, 1)], [1.0])
@@ -306,8 +328,10 @@ def agg_checks(H, level):
     agg = H.get_int(level, "agg")
     nc = inf["nc"]
     sizes = np.bincount(agg, minlength=nc)
-    assert sizes.min() >= 1 and sizes.max() <= 3
-    assert (sizes == 1).sum() == inf["middle"] + inf["singleton"]
+    assert sizes.min() >= 1
+    assert (sizes == 1).sum() == inf["singleton"]
+    # every member past the third joined at the middle or centre
+    assert np.maximum(sizes - 3, 0).sum() <= inf["middle"]
     # connected in the level graph
     grp, gci = H.get_int(level, "G_rp"), H.get_int(level, "G_ci")
     adj = lambda a, b: b in set(gci[grp[a]:grp[a + 1]].tolist())
@@ -320,13 +344,16 @@ def agg_checks(H, level):
         if len(m) == 3:
             links = adj(m[0], m[1]) + adj(m[0], m[2]) + adj(m[1], m[2])
             assert links >= 2
+        if len(m) > 3:  # a star: one member adjacent to all the others
+            assert any(all(adj(c, x) for x in m if x != c) for c in m)
     # ids ordered by smallest member
     mins = [min(m) for m in members]
     assert mins == sorted(mins)
 
 
 @pytest.mark.parametrize("maker", [lambda: I.grid2d(40, 33), lambda: I.rgg(3000, 7),
-                                   lambda: I.grid3d(12, 11, 10, weight_seed=2)])
+                                   lambda: I.grid3d(12, 11, 10, weight_seed=2),
+                                   lambda: I.config3(n0=5000)[0]])
 def test_hierarchy_invariants(oracle, maker):
     g = maker()
     n = g[0]

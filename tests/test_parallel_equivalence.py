@@ -163,6 +163,7 @@ def reservation_repair(n, grp, gci, gw, gkey, obj, members, window):
     adj = lambda a, b: b in set(gci[grp[a]:grp[a + 1]].tolist())
     obj = list(obj)
     members = {k: list(v) for k, v in members.items()}
+    centre = {}
     pending = [u for u in range(n) if obj[u] < 0]
     while pending:
         pending = [u for u in pending if obj[u] < 0]
@@ -198,25 +199,30 @@ def reservation_repair(n, grp, gci, gw, gkey, obj, members, window):
                     obj[u] = T
                 else:
                     rest = [x for x in members[T] if x != v]
-                    if adj(rest[0], rest[1]):
+                    take_out = adj(rest[0], rest[1]) if len(rest) == 2 else v != centre[T]
+                    if take_out:
                         members[T] = rest
                         members[u] = [u, v]
                         obj[u] = obj[v] = u
-                    else:
-                        members[u] = [u]
-                        obj[u] = u
+                    else:  # v is the middle or the centre: u joins at v
+                        members[T].append(u)
+                        obj[u] = T
+                        centre[T] = v
     # canonical ids by smallest member
     live = sorted((min(m), k) for k, m in members.items() if m)
     canon = {k: i for i, (_, k) in enumerate(live)}
     return np.array([canon[obj[v]] for v in range(n)])
 
 
-@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("seed", range(10))
 def test_reservation_repair_equals_sequential(oracle, seed):
-    g = I.rgg(700, 50 + seed)
+    # random geometric graphs, and power-law graphs whose hubs grow stars
+    g = I.rgg(700, 50 + seed) if seed < 8 else I.config3(seed=seed, n0=3000)[0]
     n, rp, ci, w = g
     e = oracle.smooth_error(g, 1, seed, 3)
     H = oracle.Hierarchy(g, e, coarse_max=8)
+    if seed >= 8:
+        assert sum(H.info(l)["middle"] for l in range(H.nlevels - 1)) > 0
     for level in range(min(3, H.nlevels - 1)):
         grp, gci, gw = H.get_int(level, "G_rp"), H.get_int(level, "G_ci"), H.get_dbl(level, "G_v")
         gkey = H.get_dbl(level, "gkey") if level == 0 else None
