@@ -80,7 +80,7 @@ typedef struct {
   int32_t coarse_solve;    /* PCAMG_COARSE_AUTO / GROUNDED / FULL */
   int32_t a2_hub_cap;      /* 0 = exact A^2 pattern; K > 0: two-step pairs only via degree <= K */
   int32_t max_rebuilds;    /* 50 */
-  int32_t max_levels;      /* 40 */
+  int32_t max_levels;      /* 64 */
   int32_t numW, iterW, iterV; /* Alg. 2 parameters (2, 7, 4; Sec. 4) */
   int32_t rebuild_rule;    /* 0 mean ConvR since last re-setup (Alg. 5), 1 last ConvR (Alg. 6) */
   int32_t keep_setup;      /* 1 = keep per-level setup arrays for pcamg_level_get */
@@ -339,10 +339,15 @@ pcamg_status pcamg_orient(int32_t n, const int32_t* nb, int32_t* path_id, int32_
                           void* stream);
 
 /* Aggregation along a cover (Alg. 3): pairing along paths, isolated vertices
- * in ascending id (Cases 1-3), aggregates numbered by smallest member.
+ * in ascending id (Cases 1-3), aggregates numbered by smallest member.  In
+ * Case 3 the best neighbour v leaves its aggregate only if the rest stays
+ * connected; when v is the middle of a 3-chain or the centre of a star grown
+ * that way, u joins v's aggregate ("middle"), so aggregates may exceed three
+ * members (stars, diameter 2; Sec. 3.3 leaves no vertex isolated).
  * Level graph (grp, gci, gw) with optional keys gkey (finest level: smaller
  * key = heavier).  agg: device [n]; *nc and stats[6] (host): unaggregated,
- * case1, case2, case3, middle, singleton. */
+ * case1, case2, case3, middle (joins at the middle or centre), singleton
+ * (no neighbour). */
 pcamg_status pcamg_aggregate(int32_t n, const int32_t* grp, const int32_t* gci, const double* gw,
                              const double* gkey, const int32_t* nb, int32_t* agg, int32_t* nc, int32_t* stats,
                              void* stream);

@@ -205,7 +205,7 @@ pcamg_status pcamg_params_default(pcamg_params* p) {
   p->coarse_solve = PCAMG_COARSE_AUTO;
   p->a2_hub_cap = 0;
   p->max_rebuilds = 50;
-  p->max_levels = 40;
+  p->max_levels = 64;
   p->numW = 2;
   p->iterW = 7;
   p->iterV = 4;

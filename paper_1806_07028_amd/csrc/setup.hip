@@ -534,12 +534,54 @@ void orient_paths(int32_t n, const int32_t* nb, int32_t* path_id, int32_t* pos, 
 
 // ---------------------------------------------------------------------------
 // Aggregation along the cover (Alg. 3).  Aggregate objects are identified by
-// the vertex that created them; obj[v] = object of v, osz/omem = size and
-// members (at most 3).
+// the vertex that created them; obj[v] = object of v.  An object keeps its
+// size, its centre (the vertex it grew at past three members, else -1) and
+// its members as a doubly linked list through the vertices (head, next, prev),
+// so that members join and leave in O(1).
 // ---------------------------------------------------------------------------
+struct AggObjs {
+  int32_t* obj;
+  int32_t* size;
+  int32_t* centre;
+  int32_t* head;
+  int32_t* next;
+  int32_t* prev;
+};
+
+__device__ void obj_new2(const AggObjs& o, int32_t u, int32_t v) {  // {u, v}, or {u} when v < 0
+  o.obj[u] = u;
+  o.size[u] = v >= 0 ? 2 : 1;
+  o.centre[u] = -1;
+  o.head[u] = u;
+  o.prev[u] = -1;
+  o.next[u] = v;
+  if (v >= 0) {
+    o.obj[v] = u;
+    o.prev[v] = u;
+    o.next[v] = -1;
+  }
+}
+
+__device__ void obj_push(const AggObjs& o, int32_t T, int32_t u) {
+  const int32_t h = o.head[T];
+  o.obj[u] = T;
+  o.prev[u] = -1;
+  o.next[u] = h;
+  if (h >= 0) o.prev[h] = u;
+  o.head[T] = u;
+  o.size[T] += 1;
+}
+
+__device__ void obj_remove(const AggObjs& o, int32_t T, int32_t v) {
+  const int32_t p = o.prev[v], q = o.next[v];
+  if (p >= 0) o.next[p] = q;
+  else o.head[T] = q;
+  if (q >= 0) o.prev[q] = p;
+  o.size[T] -= 1;
+}
+
 __global__ void pair_kernel(int32_t n, const int32_t* __restrict__ nb, const int32_t* __restrict__ pid,
-                            const int32_t* __restrict__ pos, const int32_t* __restrict__ plen,
-                            int32_t* __restrict__ obj, int32_t* __restrict__ osz, int32_t* __restrict__ omem) {
+                            const int32_t* __restrict__ pos, const int32_t* __restrict__ plen, AggObjs o) {
   int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   if (pid[v] < 0) return;
@@ -547,12 +589,7 @@ __global__ void pair_kernel(int32_t n, const int32_t* __restrict__ nb, const int
   if ((p & 1) == 0 && p + 1 < plen[v]) {
     int32_t w = nb[2 * v];
     if (w < 0 || pos[w] != p + 1) w = nb[2 * v + 1];
-    obj[v] = v;
-    obj[w] = v;
-    osz[v] = 2;
-    omem[3 * (size_t)v] = v;
-    omem[3 * (size_t)v + 1] = w;
-    omem[3 * (size_t)v + 2] = -1;
+    obj_new2(o, v, w);
   }
 }
 
@@ -614,8 +651,9 @@ __device__ bool adjacent(const int32_t* grp, const int32_t* gci, int32_t a, int3
   return false;
 }
 
-__global__ void rp_commit_kernel(int32_t w, const int32_t* __restrict__ win, int32_t* __restrict__ obj,
-                                 int32_t* __restrict__ osz, int32_t* __restrict__ omem,
+// A winner owns u, v and v's object T for the round: every list link it
+// touches belongs to u, v or a member of T.
+__global__ void rp_commit_kernel(int32_t w, const int32_t* __restrict__ win, AggObjs o,
                                  const uint32_t* __restrict__ resV, const uint32_t* __restrict__ resO,
                                  const int2* __restrict__ plan, uint8_t* __restrict__ state,
                                  const int32_t* __restrict__ grp, const int32_t* __restrict__ gci,
@@ -626,46 +664,40 @@ __global__ void rp_commit_kernel(int32_t w, const int32_t* __restrict__ win, int
   const int32_t v = plan[x].x, T = plan[x].y;
   if (resV[u] != u || (v >= 0 && resV[v] != u) || (T >= 0 && resO[T] != u)) return;
   state[x] = 2;
-  int32_t* mu = omem + 3 * (size_t)u;
   if (v < 0) {  // no neighbour
-    obj[u] = u;
-    osz[u] = 1;
-    mu[0] = u; mu[1] = -1; mu[2] = -1;
+    obj_new2(o, u, -1);
     atomicAdd(&stats[ST_SINGLETON], 1);
     return;
   }
   if (T < 0) {  // Case 1
-    obj[u] = u;
-    obj[v] = u;
-    osz[u] = 2;
-    mu[0] = u; mu[1] = v; mu[2] = -1;
+    obj_new2(o, u, v);
     atomicAdd(&stats[ST_CASE1], 1);
     return;
   }
-  int32_t* mt = omem + 3 * (size_t)T;
-  const int32_t sz = osz[T];
+  const int32_t sz = o.size[T];
   if (sz <= 2) {  // Case 2
-    mt[sz] = u;
-    osz[T] = sz + 1;
-    obj[u] = T;
+    obj_push(o, T, u);
     atomicAdd(&stats[ST_CASE2], 1);
     return;
   }
-  int32_t rest[2], k = 0;
-  for (int q = 0; q < 3; ++q)
-    if (mt[q] != v) rest[k++] = mt[q];
-  if (adjacent(grp, gci, rest[0], rest[1])) {  // Case 3: take v out of T
-    mt[0] = rest[0]; mt[1] = rest[1]; mt[2] = -1;
-    osz[T] = 2;
-    obj[u] = u;
-    obj[v] = u;
-    osz[u] = 2;
-    mu[0] = u; mu[1] = v; mu[2] = -1;
+  // Case 3: v leaves T unless that disconnects it (v the middle of a 3-chain,
+  // or the centre of a star); then u joins T at v
+  bool take_out;
+  if (sz == 3) {
+    int32_t rest[2] = {-1, -1}, k = 0;
+    for (int32_t m = o.head[T], c = 0; m >= 0 && c < 3; m = o.next[m], ++c)
+      if (m != v && k < 2) rest[k++] = m;
+    take_out = k == 2 && adjacent(grp, gci, rest[0], rest[1]);
+  } else {
+    take_out = v != o.centre[T];
+  }
+  if (take_out) {
+    obj_remove(o, T, v);
+    obj_new2(o, u, v);
     atomicAdd(&stats[ST_CASE3], 1);
-  } else {  // v is the middle of T: u stays alone
-    obj[u] = u;
-    osz[u] = 1;
-    mu[0] = u; mu[1] = -1; mu[2] = -1;
+  } else {
+    obj_push(o, T, u);
+    o.centre[T] = v;
     atomicAdd(&stats[ST_MIDDLE], 1);
   }
 }
@@ -683,57 +715,48 @@ __global__ void rp_reset_kernel(int32_t w, const int32_t* __restrict__ win, uint
   state[x] = st == 1 ? 1 : 0;
 }
 
-// canonical numbering by smallest member
-__global__ void rootmin_kernel(int32_t n, const int32_t* __restrict__ obj, const int32_t* __restrict__ osz,
-                               const int32_t* __restrict__ omem, int32_t* __restrict__ rmin,
-                               int32_t* __restrict__ isroot, int32_t* __restrict__ bad) {
+// canonical numbering by smallest member: the smallest member of every object
+__global__ void objmin_kernel(int32_t n, const int32_t* __restrict__ obj, int32_t* __restrict__ omin,
+                              int32_t* __restrict__ bad) {
   int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   const int32_t T = obj[v];
   if (T < 0 || T >= n) {  // every vertex is aggregated after the repair; guard anyway
     atomicOr(bad, 1);
-    rmin[v] = v;
-    isroot[v] = 1;
     return;
   }
-  const int32_t* m = omem + 3 * (size_t)T;
-  int32_t mn = m[0];
-  for (int q = 1; q < osz[T]; ++q) mn = min(mn, m[q]);
-  rmin[v] = mn;
-  isroot[v] = mn == v;
+  atomicMin(&omin[T], v);
+}
+
+__global__ void isroot_kernel(int32_t n, const int32_t* __restrict__ obj, const int32_t* __restrict__ omin,
+                              int32_t* __restrict__ isroot) {
+  int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  isroot[v] = omin[obj[v]] == v;
 }
 
 __global__ void canon_kernel(int32_t n, const int32_t* __restrict__ obj, const int32_t* __restrict__ osz,
-                             const int32_t* __restrict__ rmin, const int32_t* __restrict__ cpos,
-                             int32_t* __restrict__ agg, int32_t* __restrict__ msz) {
-  int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  const int32_t I = cpos[rmin[v]];
-  agg[v] = I;
-  if (rmin[v] == v) msz[I] = osz[obj[v]];
-}
-
-__global__ void members_kernel(int32_t n, const int32_t* __restrict__ obj, const int32_t* __restrict__ osz,
-                               const int32_t* __restrict__ omem, const int32_t* __restrict__ agg,
-                               const int32_t* __restrict__ moff, int32_t* __restrict__ mem) {
+                             const int32_t* __restrict__ omin, const int32_t* __restrict__ cpos,
+                             int32_t* __restrict__ agg, uint32_t* __restrict__ aggu, int32_t* __restrict__ msz) {
   int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   const int32_t T = obj[v];
-  const int32_t* m = omem + 3 * (size_t)T;
-  int32_t r = 0;
-  for (int q = 0; q < osz[T]; ++q) r += m[q] < v;
-  mem[moff[agg[v]] + r] = v;
+  const int32_t I = cpos[omin[T]];
+  agg[v] = I;
+  aggu[v] = (uint32_t)I;
+  if (omin[T] == v) msz[I] = osz[T];
 }
 
 int32_t aggregate_level(int32_t n, const int32_t* grp, const int32_t* gci, const double* gw, const double* gkey,
                         const int32_t* nb, const int32_t* path_id, const int32_t* pos, const int32_t* plen,
                         int32_t* agg, int32_t* moff, int32_t* mem, AggStats& st, hipStream_t s) {
-  DVec<int32_t> obj(n), osz(n), omem(3 * (size_t)n), best(n), pend(n), cnt(1), stats(ST_COUNT);
+  DVec<int32_t> obj(n), osz(n), ocen(n), ohead(n), onext(n), oprev(n), best(n), pend(n), cnt(1), stats(ST_COUNT);
   DVec<uint8_t> unagg(n);
+  const AggObjs o{obj.p, osz.p, ocen.p, ohead.p, onext.p, oprev.p};
   fill_i32(obj.p, -1, n, s);
   fill_i32(osz.p, 0, n, s);
   fill_i32(stats.p, 0, ST_COUNT, s);
-  pair_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, nb, path_id, pos, plen, obj.p, osz.p, omem.p);
+  pair_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, nb, path_id, pos, plen, o);
   PCAMG_LAUNCHED();
   best_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, obj.p, grp, gci, gw, gkey, best.p, unagg.p);
   PCAMG_LAUNCHED();
@@ -758,8 +781,7 @@ int32_t aggregate_level(int32_t n, const int32_t* grp, const int32_t* gci, const
       const unsigned g = grid_for(w, 256);
       rp_reserve_kernel<<<g, 256, 0, s>>>(w, win.p, obj.p, best.p, resV.p, resO.p, plan.p, state.p);
       PCAMG_LAUNCHED();
-      rp_commit_kernel<<<g, 256, 0, s>>>(w, win.p, obj.p, osz.p, omem.p, resV.p, resO.p, plan.p, state.p, grp, gci,
-                                         stats.p);
+      rp_commit_kernel<<<g, 256, 0, s>>>(w, win.p, o, resV.p, resO.p, plan.p, state.p, grp, gci, stats.p);
       PCAMG_LAUNCHED();
       rp_reset_kernel<<<g, 256, 0, s>>>(w, win.p, resV.p, resO.p, plan.p, state.p);
       PCAMG_LAUNCHED();
@@ -776,18 +798,25 @@ int32_t aggregate_level(int32_t n, const int32_t* grp, const int32_t* gci, const
   st.case2 = hs[ST_CASE2];
   st.case3 = hs[ST_CASE3];
   st.middle = hs[ST_MIDDLE];
-  DVec<int32_t> rmin(n), isroot(n), cpos(n), msz(n), ncd(1), bad(1);
+  DVec<int32_t> omin(n), isroot(n), cpos(n), msz(n), ncd(1), bad(1), vid(n);
+  DVec<uint32_t> aggu(n), skeys(n);
   fill_i32(bad.p, 0, 1, s);
-  rootmin_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, obj.p, osz.p, omem.p, rmin.p, isroot.p, bad.p);
+  fill_i32(omin.p, INT32_MAX, n, s);
+  objmin_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, obj.p, omin.p, bad.p);
   PCAMG_LAUNCHED();
   require(read_scalar(bad.p, s) == 0, PCAMG_EHIP, "aggregation left a vertex without aggregate");
+  isroot_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, obj.p, omin.p, isroot.p);
+  PCAMG_LAUNCHED();
   scan_exclusive_i32(isroot.p, cpos.p, n, ncd.p, s);
   const int32_t nc = read_scalar(ncd.p, s);
-  canon_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, obj.p, osz.p, rmin.p, cpos.p, agg, msz.p);
+  canon_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, obj.p, osz.p, omin.p, cpos.p, agg, aggu.p, msz.p);
   PCAMG_LAUNCHED();
   scan_exclusive_i32(msz.p, moff, nc, moff + nc, s);
-  members_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, obj.p, osz.p, omem.p, agg, moff, mem);
-  PCAMG_LAUNCHED();
+  // members of every aggregate in ascending id: a stable sort of the ids by aggregate
+  iota_i32(vid.p, n, s);
+  int key_bits = 1;
+  while (key_bits < 32 && (1ll << key_bits) < (int64_t)nc) ++key_bits;
+  radix_sort_u32_u32(aggu.p, (const uint32_t*)vid.p, skeys.p, (uint32_t*)mem, n, key_bits, s);
   PCAMG_HIP(hipStreamSynchronize(s));
   return nc;
 }

@@ -85,17 +85,19 @@ def csr_from_edges(n: int, a: np.ndarray, b: np.ndarray, w: np.ndarray):
     a = np.asarray(a, dtype=np.int64)
     b = np.asarray(b, dtype=np.int64)
     w = np.asarray(w, dtype=np.float64)
+    import scipy.sparse as sp
+
+    if 2 * len(a) >= 2 ** 31:
+        raise ValueError("graph too large for int32 row pointers")
     rows = np.concatenate([a, b])
     cols = np.concatenate([b, a])
     vals = np.concatenate([w, w])
-    order = np.lexsort((cols, rows))
-    rows, cols, vals = rows[order], cols[order], vals[order]
-    counts = np.bincount(rows, minlength=n)
-    row_ptr = np.zeros(n + 1, dtype=np.int64)
-    np.cumsum(counts, out=row_ptr[1:])
-    if row_ptr[-1] >= 2 ** 31:
-        raise ValueError("graph too large for int32 row pointers")
-    return n, row_ptr.astype(np.int32), cols.astype(np.int32), vals
+    # bucket by row, then sort each row by column (the edges are unique, so
+    # nothing is summed)
+    m = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+    m.sort_indices()
+    assert m.nnz == len(rows), "duplicate edges"
+    return n, m.indptr.astype(np.int32), m.indices.astype(np.int32), m.data.astype(np.float64)
 
 
 def upper_edges(row_ptr, col):
