@@ -104,6 +104,11 @@ typedef struct {
   int32_t dense_max_n;     /* w_dense: the dense operator starts at the first level of at most this
                               many vertices below the finest (12288); levels above 65535 vertices
                               are not built (the W-cycle then recurses) */
+  int32_t long_row_min;    /* rows of at least this many entries take one workgroup each in the
+                              cycles' smoother and residual kernels, with a fixed summation tree
+                              instead of the single chain in stored order (equal up to rounding
+                              order; hubs of power-law graphs).  The relaxation of the start
+                              vector before a build always keeps the chain.  0 = off (512) */
   uint64_t seed;           /* start-vector stream */
   uint64_t colour_seed;    /* colouring priority stream */
 } pcamg_params;

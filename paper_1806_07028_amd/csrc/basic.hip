@@ -605,20 +605,28 @@ void gs_colour_rows(int32_t nrows, const int32_t* rows, const int32_t* rp, const
 
 // y = A x (off-diagonal entries in CSR order after s = d_i x_i); with b, the
 // residual r = b - A x.
+// long_min > 0: rows of long_min entries or more are left to the long-row
+// kernel (skipped here, so they do not hold up their wavefront).
 template <typename T, int G>
 __global__ void __launch_bounds__(256)
     residual_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                     const T* __restrict__ av, const T* __restrict__ d, const T* __restrict__ b,
-                    const T* __restrict__ x, T* __restrict__ r) {
+                    const T* __restrict__ x, T* __restrict__ r, int32_t long_min) {
   const int32_t i = (int32_t)((xcd_block() * blockDim.x + threadIdx.x) / G);
   if constexpr (G == 1) {
     if (i >= n) return;
-    const T s = row_chain1<T>(rp[i], rp[i + 1], ci, av, x, d[i] * x[i]);
+    const int32_t k0 = rp[i], k1 = rp[i + 1];
+    if (long_min > 0 && k1 - k0 >= long_min) return;
+    const T s = row_chain1<T>(k0, k1, ci, av, x, d[i] * x[i]);
     r[i] = b ? b[i] - s : s;
   } else {
-    const bool ok = i < n;
+    bool ok = i < n;
     const int32_t k0 = ok ? rp[i] : 0;
-    const int32_t len = ok ? rp[i + 1] - k0 : 0;
+    int32_t len = ok ? rp[i + 1] - k0 : 0;
+    if (long_min > 0 && len >= long_min) {
+      ok = false;
+      len = 0;
+    }
     const T s = row_chain_g<T, G>(k0, len, ci, av, x, ok ? d[i] * x[i] : (T)0);
     if (ok && (threadIdx.x & (G - 1)) == 0) r[i] = b ? b[i] - s : s;
   }
@@ -626,28 +634,107 @@ __global__ void __launch_bounds__(256)
 
 template <typename T, int G>
 void residual_launch(int32_t n, const int32_t* rp, const int32_t* ci, const T* av, const T* d, const T* b,
-                     const T* x, T* r, hipStream_t s) {
-  residual_kernel<T, G><<<grid_for((size_t)n * G, 256), 256, 0, s>>>(n, rp, ci, av, d, b, x, r);
+                     const T* x, T* r, int32_t long_min, hipStream_t s) {
+  residual_kernel<T, G><<<grid_for((size_t)n * G, 256), 256, 0, s>>>(n, rp, ci, av, d, b, x, r, long_min);
   PCAMG_LAUNCHED();
 }
 
 template <typename T>
 void residual(int32_t n, const int32_t* rp, const int32_t* ci, const T* av, const T* d, const T* b, const T* x,
-              T* r, hipStream_t s, int lanes) {
+              T* r, hipStream_t s, int lanes, int32_t long_min) {
   if (n <= 0) return;
   switch (lanes) {
-    case 1: residual_launch<T, 1>(n, rp, ci, av, d, b, x, r, s); break;
-    case 4: residual_launch<T, 4>(n, rp, ci, av, d, b, x, r, s); break;
-    case 16: residual_launch<T, 16>(n, rp, ci, av, d, b, x, r, s); break;
-    case 64: residual_launch<T, 64>(n, rp, ci, av, d, b, x, r, s); break;
+    case 1: residual_launch<T, 1>(n, rp, ci, av, d, b, x, r, long_min, s); break;
+    case 4: residual_launch<T, 4>(n, rp, ci, av, d, b, x, r, long_min, s); break;
+    case 16: residual_launch<T, 16>(n, rp, ci, av, d, b, x, r, long_min, s); break;
+    case 64: residual_launch<T, 64>(n, rp, ci, av, d, b, x, r, long_min, s); break;
     default: throw Error(PCAMG_EINVAL, "lanes per row must be 1, 4, 16 or 64");
   }
+}
+
+// ---------------------------------------------------------------------------
+// Long rows (hubs of power-law graphs): one workgroup per row.  Thread t takes
+// entries t, t + 256, t + 512, ... of the row in a chain of its own (four
+// loads in flight), the 64 chains of a wavefront are added by a butterfly
+// (every lane ends with the same bits: IEEE addition commutes), and the four
+// wavefront sums in order.  Deterministic, but a different summation order
+// from the single chain of shorter rows.
+// ---------------------------------------------------------------------------
+constexpr int LONG_T = 256;
+
+template <typename T>
+__device__ __forceinline__ T long_row_sum(int32_t k0, int32_t k1, const int32_t* __restrict__ ci,
+                                          const T* __restrict__ av, const T* __restrict__ x) {
+  __shared__ T part[LONG_T / 64];
+  constexpr int U = 4;
+  T s = (T)0;
+  int32_t k = k0 + (int32_t)threadIdx.x;
+  for (; k + (U - 1) * LONG_T < k1; k += U * LONG_T) {
+    int32_t c[U];
+    T a[U], v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      c[u] = ci[k + u * LONG_T];
+      a[u] = av[k + u * LONG_T];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = x[c[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) s = fma(a[u], v[u], s);
+  }
+  for (; k < k1; k += LONG_T) s = fma(av[k], x[ci[k]], s);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  T t = part[0];
+#pragma unroll
+  for (int w = 1; w < LONG_T / 64; ++w) t += part[w];
+  return t;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(LONG_T)
+    gs_long_kernel(int32_t row0, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                   const T* __restrict__ av, const T* __restrict__ dinv, const T* __restrict__ b, T* x) {
+  const int32_t i = row0 + (int32_t)blockIdx.x;
+  const T s = long_row_sum<T>(rp[i], rp[i + 1], ci, av, x);
+  if (threadIdx.x == 0) x[i] = (b[i] - s) * dinv[i];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(LONG_T)
+    residual_long_kernel(const int32_t* __restrict__ rows, const int32_t* __restrict__ rp,
+                         const int32_t* __restrict__ ci, const T* __restrict__ av, const T* __restrict__ d,
+                         const T* __restrict__ b, const T* __restrict__ x, T* __restrict__ r) {
+  const int32_t i = rows[blockIdx.x];
+  const T t = long_row_sum<T>(rp[i], rp[i + 1], ci, av, x);
+  if (threadIdx.x == 0) {
+    const T s = d[i] * x[i] + t;
+    r[i] = b ? b[i] - s : s;
+  }
+}
+
+template <typename T>
+void gs_colour_long(int32_t row0, int32_t row1, const int32_t* rp, const int32_t* ci, const T* av, const T* dinv,
+                    const T* b, T* x, hipStream_t s) {
+  if (row1 <= row0) return;
+  gs_long_kernel<T><<<row1 - row0, LONG_T, 0, s>>>(row0, rp, ci, av, dinv, b, x);
+  PCAMG_LAUNCHED();
+}
+
+template <typename T>
+void residual_long(int32_t nrows, const int32_t* rows, const int32_t* rp, const int32_t* ci, const T* av,
+                   const T* d, const T* b, const T* x, T* r, hipStream_t s) {
+  if (nrows <= 0) return;
+  residual_long_kernel<T><<<nrows, LONG_T, 0, s>>>(rows, rp, ci, av, d, b, x, r);
+  PCAMG_LAUNCHED();
 }
 
 template <typename T>
 void spmv(int32_t n, const int32_t* rp, const int32_t* ci, const T* av, const T* d, const T* x, T* y,
           hipStream_t s, int lanes) {
-  residual<T>(n, rp, ci, av, d, nullptr, x, y, s, lanes);
+  residual<T>(n, rp, ci, av, d, nullptr, x, y, s, lanes, 0);
 }
 
 // Residual (b != nullptr) or product on the sliced-ELL copy.
@@ -773,7 +860,11 @@ void prolong_add(int32_t n, const int32_t* agg, const T* pval, const T* xc, T* x
   template void gs_colour_rows<T>(int32_t, const int32_t*, const int32_t*, const int32_t*, const T*, const T*, \
                                   const T*, T*, hipStream_t);                                                   \
   template void residual<T>(int32_t, const int32_t*, const int32_t*, const T*, const T*, const T*, const T*,   \
-                            T*, hipStream_t, int);                                                              \
+                            T*, hipStream_t, int, int32_t);                                                     \
+  template void gs_colour_long<T>(int32_t, int32_t, const int32_t*, const int32_t*, const T*, const T*,        \
+                                  const T*, T*, hipStream_t);                                                   \
+  template void residual_long<T>(int32_t, const int32_t*, const int32_t*, const int32_t*, const T*, const T*,  \
+                                 const T*, const T*, T*, hipStream_t);                                          \
   template void spmv<T>(int32_t, const int32_t*, const int32_t*, const T*, const T*, const T*, T*, hipStream_t, \
                         int);                                                                                   \
   template void gs_colour_sell<T>(int32_t, int32_t, const int32_t*, const int32_t*, const int32_t*, const T*,  \

@@ -188,9 +188,18 @@ void gs_colour(int32_t row0, int32_t row1, const int32_t* rp, const int32_t* ci,
 template <typename T>
 void gs_colour_rows(int32_t nrows, const int32_t* rows, const int32_t* rp, const int32_t* ci, const T* av,
                     const T* dinv, const T* b, T* x, hipStream_t s);
+// long_min > 0: rows of long_min entries or more are skipped (residual_long)
 template <typename T>
 void residual(int32_t n, const int32_t* rp, const int32_t* ci, const T* av, const T* d, const T* b, const T* x,
-              T* r, hipStream_t s, int lanes = 1);
+              T* r, hipStream_t s, int lanes = 1, int32_t long_min = 0);
+// Long rows, one workgroup each (a fixed summation tree instead of the single
+// chain): Gauss-Seidel over rows row0..row1-1, residual over a row list.
+template <typename T>
+void gs_colour_long(int32_t row0, int32_t row1, const int32_t* rp, const int32_t* ci, const T* av, const T* dinv,
+                    const T* b, T* x, hipStream_t s);
+template <typename T>
+void residual_long(int32_t nrows, const int32_t* rows, const int32_t* rp, const int32_t* ci, const T* av,
+                   const T* d, const T* b, const T* x, T* r, hipStream_t s);
 template <typename T>
 void spmv(int32_t n, const int32_t* rp, const int32_t* ci, const T* av, const T* d, const T* x, T* y,
           hipStream_t s, int lanes = 1);
@@ -267,6 +276,13 @@ void shorten_paths(int32_t n, const int32_t* nb, const int32_t* path_id, const i
 // ---------------------------------------------------------------------------
 void build_perm(int32_t n, const int32_t* colour, int32_t ncol, int32_t* perm, int32_t* iperm,
                 std::vector<int32_t>& coff, hipStream_t s);
+// Largest row length of a CSR matrix (synchronises).
+int32_t max_row_len(int32_t n, const int32_t* rp, hipStream_t s);
+// Same with the rows of long_min entries or more first within each colour:
+// lend[c] = end of colour c's long rows (coff[c] <= lend[c] <= coff[c + 1]).
+void build_perm_long(int32_t n, const int32_t* colour, int32_t ncol, const int32_t* rp, int32_t long_min,
+                     int32_t* perm, int32_t* iperm, std::vector<int32_t>& coff, std::vector<int32_t>& lend,
+                     hipStream_t s);
 void permute_csr(int32_t n, const int32_t* perm, const int32_t* iperm, const int32_t* rp, const int32_t* ci,
                  const double* av, const double* d, const double* dinv, int32_t* rpp, int32_t* cip, double* avp,
                  float* avp32, double* dp, double* dinvp, float* dp32, float* dinvp32, hipStream_t s);

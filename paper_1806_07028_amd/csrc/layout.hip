@@ -51,6 +51,63 @@ void build_perm(int32_t n, const int32_t* colour, int32_t ncol, int32_t* perm, i
   require(ok, PCAMG_EINVAL, "keys must take every value 0..ncol-1");
 }
 
+__global__ void long_key_kernel(int32_t n, const int32_t* __restrict__ colour, const int32_t* __restrict__ rp,
+                                int32_t long_min, uint32_t* __restrict__ key) {
+  int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) key[v] = 2u * (uint32_t)colour[v] + (rp[v + 1] - rp[v] >= long_min ? 0u : 1u);
+}
+
+// first position of every key present (start[k] = -1 for keys absent)
+__global__ void key_start_kernel(int32_t n, int32_t nkeys, const uint32_t* __restrict__ keys,
+                                 int32_t* __restrict__ start, int32_t* __restrict__ bad) {
+  int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const uint32_t k = keys[p];
+  if (k >= (uint32_t)nkeys) {
+    atomicOr(bad, 1);
+    return;
+  }
+  if (p == 0 || keys[p - 1] != k) start[k] = p;
+}
+
+void build_perm_long(int32_t n, const int32_t* colour, int32_t ncol, const int32_t* rp, int32_t long_min,
+                     int32_t* perm, int32_t* iperm, std::vector<int32_t>& coff, std::vector<int32_t>& lend,
+                     hipStream_t s) {
+  require(n > 0 && ncol >= 1 && long_min > 0, PCAMG_EINVAL, "build_perm_long: bad input");
+  const int32_t nkeys = 2 * ncol;
+  DVec<uint32_t> ks(n), vs(n), ko(n);
+  long_key_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, colour, rp, long_min, ks.p);
+  PCAMG_LAUNCHED();
+  iota_i32((int32_t*)vs.p, n, s);
+  int bits = 1;
+  while ((1ll << bits) < nkeys) ++bits;
+  radix_sort_u32_u32(ks.p, vs.p, ko.p, (uint32_t*)perm, n, bits, s);
+  DVec<int32_t> st(nkeys), bad(1);
+  fill_i32(st.p, -1, nkeys, s);
+  fill_i32(bad.p, 0, 1, s);
+  key_start_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, nkeys, ko.p, st.p, bad.p);
+  PCAMG_LAUNCHED();
+  require(read_scalar(bad.p, s) == 0, PCAMG_EINVAL, "colour out of range");
+  iperm_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, perm, iperm);
+  PCAMG_LAUNCHED();
+  std::vector<int32_t> start = to_host(st.p, nkeys, s);
+  // absent keys start where the next present one does
+  int32_t next = n;
+  for (int32_t k = nkeys - 1; k >= 0; --k) {
+    if (start[k] < 0) start[k] = next;
+    next = start[k];
+  }
+  coff.assign(ncol + 1, n);
+  lend.assign(ncol, n);
+  for (int32_t c = 0; c < ncol; ++c) {
+    coff[c] = start[2 * c];
+    lend[c] = start[2 * c + 1];
+  }
+  bool ok = coff[0] == 0;
+  for (int32_t c = 0; c < ncol && ok; ++c) ok = coff[c] <= lend[c] && lend[c] <= coff[c + 1] && coff[c] < coff[c + 1];
+  require(ok, PCAMG_EINVAL, "colours must take every value 0..ncol-1");
+}
+
 __global__ void perm_deg_kernel(int32_t n, const int32_t* __restrict__ perm, const int32_t* __restrict__ rp,
                                 int32_t* __restrict__ deg) {
   int32_t p = blockIdx.x * blockDim.x + threadIdx.x;

@@ -60,8 +60,9 @@ int32_t tune_lanes(const LevelMatrix& M, hipStream_t s) {
   auto pass = [&](int k, int lanes) {
     if (lanes == 1 && M.sell())
       gs_colour_sell<float>(M.coff[k], M.coff[k + 1], M.rp.p, M.woff.p, M.sci.p, M.sav32.p, M.dinv32.p, b.p, x.p, s);
-    else
-      gs_colour<float>(M.coff[k], M.coff[k + 1], M.rp.p, M.ci.p, M.av32.p, M.dinv32.p, b.p, x.p, s, lanes);
+    else  // the long rows (if any) take their own kernel whatever the lanes
+      gs_colour<float>(M.long_min > 0 ? M.lend[k] : M.coff[k], M.coff[k + 1], M.rp.p, M.ci.p, M.av32.p,
+                       M.dinv32.p, b.p, x.p, s, lanes);
   };
   auto sweep = [&](int lanes) {
     for (int k = 0; k < M.ncol; ++k) pass(k, lanes);
@@ -88,7 +89,7 @@ int32_t tune_lanes(const LevelMatrix& M, hipStream_t s) {
 std::shared_ptr<LevelMatrix> make_level_matrix(int32_t n, int32_t nnz, const int32_t* rp, const int32_t* ci,
                                                const double* av, const double* d, const double* dinv,
                                                const int32_t* colour, int32_t ncol, int32_t row_lanes,
-                                               hipStream_t s) {
+                                               int32_t long_min, hipStream_t s) {
   auto M = std::make_shared<LevelMatrix>();
   M->n = n;
   M->nnz = nnz;
@@ -96,7 +97,20 @@ std::shared_ptr<LevelMatrix> make_level_matrix(int32_t n, int32_t nnz, const int
   M->lanes = pick_lanes(n, nnz, row_lanes < 0 ? 0 : row_lanes);
   M->perm.resize(n);
   M->iperm.resize(n);
-  if (colour) {
+  // levels with long rows (and launched passes: the single-workgroup tail
+  // keeps its own loops) put them first in each colour
+  if (colour && long_min > 0 && n > TUNE_MIN_N && max_row_len(n, rp, s) >= long_min) {
+    build_perm_long(n, colour, ncol, rp, long_min, M->perm.p, M->iperm.p, M->coff, M->lend, s);
+    M->ncol = ncol;
+    M->long_min = long_min;
+    std::vector<int32_t> rows;
+    for (int32_t c = 0; c < ncol; ++c)
+      for (int32_t r = M->coff[c]; r < M->lend[c]; ++r) rows.push_back(r);
+    M->nlong = (int32_t)rows.size();
+    M->long_rows.resize(rows.size());
+    copy_h2d(M->long_rows.p, rows.data(), rows.size(), s);
+    PCAMG_HIP(hipStreamSynchronize(s));  // rows is a host temporary
+  } else if (colour) {
     build_perm(n, colour, ncol, M->perm.p, M->iperm.p, M->coff, s);
     M->ncol = ncol;
   } else {
@@ -117,7 +131,7 @@ std::shared_ptr<LevelMatrix> make_level_matrix(int32_t n, int32_t nnz, const int
               M->dinv.p, M->d32.p, M->dinv32.p, s);
   // short rows on a level large enough for launched passes: sliced-ELL copy
   // (the autotuner tries it on every level it times)
-  if ((M->lanes == 1 || tune) && n > SELL_MIN_N)
+  if ((M->lanes == 1 || tune) && n > SELL_MIN_N && M->long_min == 0)
     sell_build(n, nnz, M->rp.p, M->ci.p, M->av.p, M->av32.p, M->woff, M->sci, M->sav, M->sav32, s);
   if (tune) {
     M->lanes = tune_lanes(*M, s);
@@ -149,28 +163,44 @@ void sync(hipStream_t s) { PCAMG_HIP(hipStreamSynchronize(s)); }
 
 }  // namespace
 
-void smooth_colour(const LevelMatrix& A, int k, const double* b, double* x, hipStream_t s) {
-  if (A.sell())
+void smooth_colour(const LevelMatrix& A, int k, const double* b, double* x, hipStream_t s, bool chain) {
+  if (A.sell()) {
     gs_colour_sell<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.woff.p, A.sci.p, A.sav.p, A.dinv.p, b, x, s);
-  else
+  } else if (A.long_min > 0 && !chain) {
+    gs_colour_long<double>(A.coff[k], A.lend[k], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s);
+    gs_colour<double>(A.lend[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s, A.lanes);
+  } else {
     gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s, A.lanes);
+  }
 }
 
-void smooth_colour(const LevelMatrix& A, int k, const float* b, float* x, hipStream_t s) {
-  if (A.sell())
+void smooth_colour(const LevelMatrix& A, int k, const float* b, float* x, hipStream_t s, bool chain) {
+  if (A.sell()) {
     gs_colour_sell<float>(A.coff[k], A.coff[k + 1], A.rp.p, A.woff.p, A.sci.p, A.sav32.p, A.dinv32.p, b, x, s);
-  else
+  } else if (A.long_min > 0 && !chain) {
+    gs_colour_long<float>(A.coff[k], A.lend[k], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s);
+    gs_colour<float>(A.lend[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s, A.lanes);
+  } else {
     gs_colour<float>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s, A.lanes);
+  }
 }
 
 void level_residual(const LevelMatrix& A, const double* b, const double* x, double* r, hipStream_t s) {
-  if (A.sell()) residual_sell<double>(A.n, A.rp.p, A.woff.p, A.sci.p, A.sav.p, A.d.p, b, x, r, s);
-  else residual<double>(A.n, A.rp.p, A.ci.p, A.av.p, A.d.p, b, x, r, s, A.lanes);
+  if (A.sell()) {
+    residual_sell<double>(A.n, A.rp.p, A.woff.p, A.sci.p, A.sav.p, A.d.p, b, x, r, s);
+  } else {
+    residual<double>(A.n, A.rp.p, A.ci.p, A.av.p, A.d.p, b, x, r, s, A.lanes, A.long_min);
+    residual_long<double>(A.nlong, A.long_rows.p, A.rp.p, A.ci.p, A.av.p, A.d.p, b, x, r, s);
+  }
 }
 
 void level_residual(const LevelMatrix& A, const float* b, const float* x, float* r, hipStream_t s) {
-  if (A.sell()) residual_sell<float>(A.n, A.rp.p, A.woff.p, A.sci.p, A.sav32.p, A.d32.p, b, x, r, s);
-  else residual<float>(A.n, A.rp.p, A.ci.p, A.av32.p, A.d32.p, b, x, r, s, A.lanes);
+  if (A.sell()) {
+    residual_sell<float>(A.n, A.rp.p, A.woff.p, A.sci.p, A.sav32.p, A.d32.p, b, x, r, s);
+  } else {
+    residual<float>(A.n, A.rp.p, A.ci.p, A.av32.p, A.d32.p, b, x, r, s, A.lanes, A.long_min);
+    residual_long<float>(A.nlong, A.long_rows.p, A.rp.p, A.ci.p, A.av32.p, A.d32.p, b, x, r, s);
+  }
 }
 
 void ctx_init(pcamg_ctx* c, const pcamg_graph* g, const pcamg_params* p) {
@@ -190,7 +220,7 @@ void ctx_init(pcamg_ctx* c, const pcamg_graph* g, const pcamg_params* p) {
   laplacian(n, c->rp.p, g->weight, c->av.p, c->d.p, c->dinv.p, nnz, s);
   c->ncol = colour_level(n, c->rp.p, c->ci.p, c->P.colour_seed, 0, c->colour.p, s);
   c->M0 = make_level_matrix(n, nnz, c->rp.p, c->ci.p, c->av.p, c->d.p, c->dinv.p, c->colour.p, c->ncol,
-                            c->P.row_lanes, s);
+                            c->P.row_lanes, c->P.long_row_min, s);
   sync(s);
 }
 
@@ -396,9 +426,10 @@ std::unique_ptr<Hierarchy> build_hierarchy(pcamg_ctx* c, const double* e_nat) {
     Level& V = H->lv[l];
     if (l == 0) V.A = c->M0;
     else if (l + 1 < nl)
-      V.A = make_level_matrix(L.n, L.nnz, L.rp, L.ci, L.av, L.d, L.dinv, L.colour, L.ncol, P.row_lanes, s);
+      V.A = make_level_matrix(L.n, L.nnz, L.rp, L.ci, L.av, L.d, L.dinv, L.colour, L.ncol, P.row_lanes,
+                              P.long_row_min, s);
     else
-      V.A = make_level_matrix(L.n, L.nnz, L.rp, L.ci, L.av, L.d, L.dinv, nullptr, 1, P.row_lanes, s);
+      V.A = make_level_matrix(L.n, L.nnz, L.rp, L.ci, L.av, L.d, L.dinv, nullptr, 1, P.row_lanes, 0, s);
     V.x.resize(L.n);
     V.b.resize(L.n);
     V.r.resize(L.n);
@@ -741,9 +772,9 @@ void relax_perm(pcamg_ctx* c, double* e_perm, const double* zero, int sweeps) {
   const LevelMatrix& A = *c->M0;
   for (int q = 0; q < sweeps; ++q) {
     for (int k = 0; k < A.ncol; ++k)
-      smooth_colour(A, k, zero, e_perm, c->s);
+      smooth_colour(A, k, zero, e_perm, c->s, true);
     for (int k = A.ncol - 1; k >= 0; --k)
-      smooth_colour(A, k, zero, e_perm, c->s);
+      smooth_colour(A, k, zero, e_perm, c->s, true);
   }
 }
 }  // namespace

@@ -24,12 +24,19 @@ struct LevelMatrix {
   DVec<double> sav;
   DVec<float> sav32;
   bool sell() const { return woff.p != nullptr; }
+  // rows of at least long_min entries (0: none), first within their colour:
+  // lend[c] = end of colour c's long rows; long_rows = all of them
+  int32_t long_min = 0, nlong = 0;
+  std::vector<int32_t> lend;
+  DVec<int32_t> long_rows;
 };
 
 // Gauss-Seidel pass over colour k and residual (b == nullptr: product) of a
 // level matrix, on its sliced-ELL copy when it has one.
-void smooth_colour(const LevelMatrix& A, int k, const double* b, double* x, hipStream_t s);
-void smooth_colour(const LevelMatrix& A, int k, const float* b, float* x, hipStream_t s);
+// chain: every row by the single fma chain in stored order (the relaxation
+// before a build), long rows included.
+void smooth_colour(const LevelMatrix& A, int k, const double* b, double* x, hipStream_t s, bool chain = false);
+void smooth_colour(const LevelMatrix& A, int k, const float* b, float* x, hipStream_t s, bool chain = false);
 void level_residual(const LevelMatrix& A, const double* b, const double* x, double* r, hipStream_t s);
 void level_residual(const LevelMatrix& A, const float* b, const float* x, float* r, hipStream_t s);
 

@@ -235,6 +235,44 @@ def test_cycles_bit_exact(gpu, oracle, gname):
     same(host(sc.cycle(b, None, 1)), Hc.vcycle(b))
 
 
+@pytest.mark.parametrize("gname", ["hub", "powerlaw"])
+def test_long_rows_cycles(gpu, oracle, gname):
+    """Rows of 512 entries or more (hubs) take one workgroup each in the
+    cycles, with a fixed summation tree: the same hierarchy (the relaxation
+    before a build keeps the single chain), cycles within rounding of the
+    oracle (FP64 1e-12, FP32 1e-5 relative); with long_row_min = 0 the cycles
+    are the oracle's bit for bit."""
+    g = GRAPHS["hub"]() if gname == "hub" else I.config3(n0=30000)[0]
+    n = g[0]
+    H = oracle.Hierarchy(g, None)
+    s0 = solver_for(gpu, g, long_row_min=0)
+    s = solver_for(gpu, g)
+    compare_hierarchy(s, H)
+    long_levels = 0
+    for l in range(s.num_levels()):
+        m = s.level_info(l)["n"]
+        if m > 2048 and np.diff(s.level_get(l, "A_rp")).max() >= 512:
+            long_levels += 1
+    assert long_levels >= 1
+    b = I.zero_mean_normal_rhs(3, n)
+    x0 = I.normal(4, n)
+    b32, x32 = b.astype(np.float32), x0.astype(np.float32)
+    for gamma in (1, 2):
+        ref = H.cycle(b, x0, gamma)
+        same(host(s0.cycle(b, x0, gamma)), ref)
+        got = host(s.cycle(b, x0, gamma))
+        assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref), gamma
+        ref32 = H.cycle32(b32, x32, gamma).astype(np.float64)
+        same(host(s0.cycle32(b32, x32, gamma)).astype(np.float64), ref32)
+        got32 = host(s.cycle32(b32, x32, gamma)).astype(np.float64)
+        assert np.linalg.norm(got32 - ref32) <= 1e-5 * np.linalg.norm(ref32), gamma
+    # the solve converges the same way
+    xs, st = s.solve()
+    x0s, st0 = s0.solve()
+    assert st["status"] == 0 and st["true_relres"] <= 1.0001e-8
+    assert abs(st["iterations"] - st0["iterations"]) <= 1
+
+
 def test_approx_error(gpu, oracle):
     """Alg. 2 with one hierarchy (W-cycle preconditioner), relative 1e-12."""
     g = GRAPHS["grid3d_w"]()
