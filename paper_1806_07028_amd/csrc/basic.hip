@@ -225,7 +225,7 @@ __global__ void __launch_bounds__(1024)
 // device radix sort (ascending (key, id), walked backwards), the colours in
 // global memory and the bitmask of the colours around the current vertex in
 // LDS (a vertex's colour is at most its degree, so max degree + 1 bits).
-constexpr int32_t SEQ_LARGE_MAX = 1 << 20;
+constexpr int32_t SEQ_LARGE_MAX = 1 << 16;
 constexpr int32_t SEQ_BITS_MAX = 65536;
 __global__ void __launch_bounds__(1024)
     greedy_seq_large_kernel(int32_t n, int32_t nwords, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
@@ -264,18 +264,85 @@ __global__ void row_len_max_kernel(int32_t n, const int32_t* __restrict__ rp, in
   if ((threadIdx.x & 63) == 0) atomicMax(out, m);
 }
 
+// The higher-priority neighbours of every vertex (larger (priority, id)), in
+// column order: the only ones its first-fit colour depends on.  A blocked
+// hub then checks its few higher neighbours, not its whole row.
+__global__ void higher_count_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                    const uint64_t* __restrict__ prio, int32_t* __restrict__ cnt) {
+  const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const uint64_t pv = prio[v];
+  int32_t c = 0;
+  for (int32_t k = rp[v]; k < rp[v + 1]; ++k) {
+    const int32_t u = ci[k];
+    const uint64_t pu = prio[u];
+    c += pu > pv || (pu == pv && u > v);
+  }
+  cnt[v] = c;
+}
+
+__global__ void higher_fill_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                   const uint64_t* __restrict__ prio, const int32_t* __restrict__ hrp,
+                                   int32_t* __restrict__ hci) {
+  const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const uint64_t pv = prio[v];
+  int32_t o = hrp[v];
+  for (int32_t k = rp[v]; k < rp[v + 1]; ++k) {
+    const int32_t u = ci[k];
+    const uint64_t pu = prio[u];
+    if (pu > pv || (pu == pv && u > v)) hci[o++] = u;
+  }
+}
+
+// jp_try over the higher-priority list: true if a higher neighbour is still
+// uncoloured; else v takes the smallest colour none of them has.
+__device__ __forceinline__ bool jp_try_h(int32_t v, const int32_t* __restrict__ hrp, const int32_t* __restrict__ hci,
+                                         int32_t* colour) {
+  constexpr int U = 8;
+  const int32_t k0 = hrp[v], k1 = hrp[v + 1];
+  unsigned long long used = 0ull;
+  for (int32_t k = k0; k < k1; k += U) {
+    int32_t cu[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j)  // padding: a colour that neither blocks nor takes a slot
+      cu[j] = k + j < k1 ? __atomic_load_n(&colour[hci[k + j]], __ATOMIC_RELAXED) : INT32_MAX;
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      if (cu[j] < 0) return true;
+      if (cu[j] < 64) used |= 1ull << cu[j];
+    }
+  }
+  int32_t c;
+  if (~used != 0ull) {  // a free colour below 64 (colours above do not matter)
+    c = __ffsll((long long)~used) - 1;
+  } else {  // colours 0..63 all taken: the next windows of 64, one list scan each
+    c = -1;
+    for (int32_t base = 64; c < 0; base += 64) {
+      unsigned long long win = 0ull;
+      for (int32_t k = k0; k < k1; ++k) {
+        const int32_t cw = __atomic_load_n(&colour[hci[k]], __ATOMIC_RELAXED) - base;
+        if (cw >= 0 && cw < 64) win |= 1ull << cw;
+      }
+      if (~win != 0ull) c = base + __ffsll((long long)~win) - 1;
+    }
+  }
+  __atomic_store_n(&colour[v], c, __ATOMIC_RELAXED);
+  return false;
+}
+
 // One round over a worklist of uncoloured vertices; the ones still uncoloured
 // go to the next list (in any order: the colouring does not depend on it).
 __global__ void __launch_bounds__(256)
     jp_list_kernel(const int32_t* __restrict__ cnt_in, const int32_t* __restrict__ in, int32_t* __restrict__ cnt_out,
-                   int32_t* __restrict__ out, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                   const uint64_t* __restrict__ prio, int32_t* colour) {
+                   int32_t* __restrict__ out, const int32_t* __restrict__ hrp, const int32_t* __restrict__ hci,
+                   int32_t* colour) {
   const int32_t m = *cnt_in;
   const int32_t stride = gridDim.x * blockDim.x;
   for (int32_t base = blockIdx.x * blockDim.x; base < m; base += stride) {
     const int32_t t = base + threadIdx.x;
     const int32_t v = t < m ? in[t] : -1;
-    const bool left = v >= 0 && jp_try(v, rp, ci, prio, colour);
+    const bool left = v >= 0 && __atomic_load_n(&colour[v], __ATOMIC_RELAXED) < 0 && jp_try_h(v, hrp, hci, colour);
     const unsigned long long bal = __ballot(left);
     if (!bal) continue;
     const int lane = threadIdx.x & 63;
@@ -317,22 +384,26 @@ __global__ void max_i32_kernel(const int32_t* a, int32_t n, int32_t* out) {
   if ((threadIdx.x & 63) == 0) atomicMax(out, m);
 }
 
-// Mean row length above which levels are coloured one vertex at a time.
+// Mean row length above which levels are coloured one vertex at a time; the
+// vertices taken one at a time when the rounds stall.
 constexpr int64_t JP_SEQ_DEG = 48;
+constexpr int32_t SEQ_CHUNK = 8192;
 
-// The vertices of `list` (m of them, the uncoloured ones) coloured one at a time
-// in descending (priority, id) order.  Every uncoloured vertex's lower-priority
-// neighbours are uncoloured too (a vertex is coloured only after all its
-// higher-priority neighbours), so first-fit over the coloured neighbours is
-// first-fit over the higher-priority ones: the same colouring as the rounds.
-void colour_rest_seq(int32_t m, const int32_t* list, const int32_t* rp, const int32_t* ci, const uint64_t* prio,
-                     int32_t maxdeg, int32_t* colour, hipStream_t s) {
+// The top k (by (priority, id)) of the m uncoloured vertices of `list`
+// coloured one at a time in descending order.  Every uncoloured vertex's
+// lower-priority neighbours are uncoloured too (a vertex is coloured only
+// after all its higher-priority neighbours), and the pending higher-priority
+// neighbours of a top-k vertex are in the top k before it; so first-fit over
+// the coloured neighbours is first-fit over the higher-priority ones: the same
+// colouring as the rounds, which then go on with the rest.
+void colour_top_seq(int32_t m, int32_t k, const int32_t* list, const int32_t* rp, const int32_t* ci,
+                    const uint64_t* prio, int32_t maxdeg, int32_t* colour, hipStream_t s) {
   DVec<uint64_t> keys(m), skeys(m);
   DVec<uint32_t> ids(m), asc(m);
   list_keys_kernel<<<grid_for(m, 256), 256, 0, s>>>(m, list, prio, keys.p, ids.p);
   PCAMG_LAUNCHED();
   radix_sort_u64_u32(keys.p, ids.p, skeys.p, asc.p, m, s);
-  greedy_seq_large_kernel<<<1, 1024, 0, s>>>(m, (maxdeg + 1 + 31) / 32, rp, ci, asc.p, colour);
+  greedy_seq_large_kernel<<<1, 1024, 0, s>>>(k, (maxdeg + 1 + 31) / 32, rp, ci, asc.p + (m - k), colour);
   PCAMG_LAUNCHED();
 }
 
@@ -353,23 +424,21 @@ int32_t colour_jp(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed
   jp_prio_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, rp, seed, lvl, prio.p);
   PCAMG_LAUNCHED();
   const int64_t nnz = n > 0 ? (int64_t)read_scalar(rp + n, s) : 0;
-  // near-dense levels (more than JP_SEQ_DEG entries per row): the priority
-  // chains are about as long as the level, so rounds would colour a few
-  // vertices each: colour one vertex at a time in one workgroup.  Other levels
-  // (every grid level): rounds over worklists, switching to one vertex at a
-  // time for the rest when a batch of R rounds colours fewer than 4R vertices
-  // (a round costs a launch, a few microseconds, about what one vertex costs
-  // one at a time, so below a few vertices a round the rest is cheaper
-  // one at a time).
-  const bool seq = nnz > JP_SEQ_DEG * (int64_t)n && n <= SEQ_LARGE_MAX;
-  const int32_t maxdeg = seq && n > SEQ_MAX ? max_row_len(n, rp, s) : 0;
-  if (seq && n <= SEQ_MAX) {
+  // near-dense levels (more than JP_SEQ_DEG entries per row) of up to
+  // SEQ_LARGE_MAX vertices: the priority chains are about as long as the
+  // level and a round's first-fit scans long rows once per window of 64
+  // colours, so colour one vertex at a time in one workgroup.  Other levels
+  // (every grid level): rounds over worklists, with the stalls taken one
+  // vertex at a time (below).
+  const bool dense_rows = nnz > JP_SEQ_DEG * (int64_t)n;
+  const int32_t maxdeg = dense_rows && n > SEQ_MAX && n <= SEQ_LARGE_MAX ? max_row_len(n, rp, s) : 0;
+  if (dense_rows && n <= SEQ_MAX) {
     greedy_seq_kernel<<<1, 1024, 0, s>>>(n, rp, ci, prio.p, colour);
     PCAMG_LAUNCHED();
-  } else if (seq && maxdeg + 1 <= SEQ_BITS_MAX) {
+  } else if (dense_rows && n <= SEQ_LARGE_MAX && maxdeg + 1 <= SEQ_BITS_MAX) {
     DVec<int32_t> all(n);
     iota_i32(all.p, n, s);
-    colour_rest_seq(n, all.p, rp, ci, prio.p, maxdeg, colour, s);
+    colour_top_seq(n, n, all.p, rp, ci, prio.p, maxdeg, colour, s);
   } else if (n <= JP_SMALL_MAX) {
     DVec<int32_t> rounds(1);
     jp_small_kernel<<<1, JP_SMALL_THREADS, 0, s>>>(n, rp, ci, prio.p, colour, rounds.p);
@@ -379,6 +448,14 @@ int32_t colour_jp(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed
     // after each batch (every round removes at least the highest-priority
     // uncoloured vertex, so at most n rounds)
     constexpr int R = 8;
+    DVec<int32_t> hcnt(n), hrp(n + 1);
+    higher_count_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, rp, ci, prio.p, hcnt.p);
+    PCAMG_LAUNCHED();
+    scan_exclusive_i32(hcnt.p, hrp.p, n, hrp.p + n, s);
+    const int32_t htot = read_scalar(hrp.p + n, s);  // nnz / 2 on a symmetric pattern
+    DVec<int32_t> hci(std::max<int32_t>(htot, 1));
+    higher_fill_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, rp, ci, prio.p, hrp.p, hci.p);
+    PCAMG_LAUNCHED();
     DVec<int32_t> list0(n), list1(n), cnt(R + 1);
     iota_i32(list0.p, n, s);
     fill_i32(cnt.p, 0, R + 1, s);
@@ -391,7 +468,7 @@ int32_t colour_jp(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed
       for (int r = 0; r < R; ++r) {
         const int32_t* in = (r & 1) ? list1.p : list0.p;
         int32_t* out = (r & 1) ? list0.p : list1.p;
-        jp_list_kernel<<<grid, 256, 0, s>>>(cnt.p + r, in, cnt.p + r + 1, out, rp, ci, prio.p, colour);
+        jp_list_kernel<<<grid, 256, 0, s>>>(cnt.p + r, in, cnt.p + r + 1, out, hrp.p, hci.p, colour);
         PCAMG_LAUNCHED();
       }
       rounds += R;
@@ -399,12 +476,16 @@ int32_t colour_jp(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed
       pending = read_scalar(cnt.p + R, s);
       if (pending == 0) break;
       require(rounds <= (int64_t)n + R, PCAMG_EHIP, "colouring made no progress");
-      // R is even: the survivors are in list0 again
-      if (before - pending < 4 * R && pending <= SEQ_LARGE_MAX) {
+      // R is even: the survivors are in list0 again.  A batch that colours
+      // few vertices is held up by a long priority chain (the dense core of a
+      // power-law level): the top SEQ_CHUNK pending vertices go one at a time
+      // (the rounds then drop them), the rest back to the rounds.
+      if (before - pending < 4 * R) {
         if (maxdeg_all < 0) maxdeg_all = max_row_len(n, rp, s);
         if (maxdeg_all + 1 <= SEQ_BITS_MAX) {
-          colour_rest_seq(pending, list0.p, rp, ci, prio.p, maxdeg_all, colour, s);
-          break;
+          const int32_t k = pending <= 2 * SEQ_CHUNK ? pending : SEQ_CHUNK;
+          colour_top_seq(pending, k, list0.p, rp, ci, prio.p, maxdeg_all, colour, s);
+          if (k == pending) break;
         }
       }
       jp_carry_kernel<<<1, 64, 0, s>>>(cnt.p, R);

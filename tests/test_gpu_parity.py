@@ -554,10 +554,13 @@ def test_batch_errors(gpu):
 
 
 def test_colour_dense_levels(gpu, oracle):
-    """Near-dense graphs (more than 48 entries per row) take the
-    one-vertex-at-a-time greedy kernels (order sorted in LDS, or by a device
-    sort for larger ones), the others the Jones-Plassmann rounds: all equal
-    the oracle's first-fit in priority order."""
+    """Near-dense graphs (more than 48 entries per row, up to 65536
+    vertices) take the one-vertex-at-a-time greedy kernels (order sorted in
+    LDS up to 8192 vertices, by a device sort above), the others the
+    Jones-Plassmann rounds, whose stalls go one vertex at a time (all of the
+    rest, or the top 8192 by priority when more are pending, as on the
+    power-law graph, whose first batch of rounds colours 19 of its 99,090
+    vertices): all equal the oracle's first-fit in priority order."""
     S = gpu.stages
     cases = []
     n = 300  # complete graph
@@ -571,7 +574,8 @@ def test_colour_dense_levels(gpu, oracle):
     a2, b2 = I.canonical_edges(a[m], b[m])
     cases.append(I.csr_from_edges(n, a2, b2, np.ones(len(a2))))
     cases.append(I.rgg(2500, 5))  # sparse, same size range
-    for n, deg, seed in ((3000, 60, 78), (20000, 60, 79), (20000, 40, 80)):  # LDS order, sorted, counted
+    cases.append(I.config3(n0=100000)[0])
+    for n, deg, seed in ((3000, 60, 78), (20000, 60, 79), (20000, 40, 80)):
         u = I.uniform(seed, 2 * n * deg // 2)
         a = np.minimum((u[0::2] * n).astype(np.int64), n - 1)
         b = np.minimum((u[1::2] * n).astype(np.int64), n - 1)
