@@ -108,7 +108,8 @@ typedef struct {
                               cycles' smoother and residual kernels, with a fixed summation tree
                               instead of the single chain in stored order (equal up to rounding
                               order; hubs of power-law graphs).  The relaxation of the start
-                              vector before a build always keeps the chain.  0 = off (512) */
+                              vector before a build always keeps the chain.  0 = off (256: above
+                              the longest rows of grid hierarchies) */
   uint64_t seed;           /* start-vector stream */
   uint64_t colour_seed;    /* colouring priority stream */
 } pcamg_params;

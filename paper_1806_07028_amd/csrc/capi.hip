@@ -218,7 +218,7 @@ pcamg_status pcamg_params_default(pcamg_params* p) {
   p->w_dense = 1;
   p->first_sweeps = -1;
   p->dense_max_n = 12288;
-  p->long_row_min = 512;
+  p->long_row_min = 256;
   p->seed = 0x5EED;
   p->colour_seed = 0xC010;
   return PCAMG_OK;

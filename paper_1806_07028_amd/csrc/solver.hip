@@ -166,8 +166,11 @@ void sync(hipStream_t s) { PCAMG_HIP(hipStreamSynchronize(s)); }
 void smooth_colour(const LevelMatrix& A, int k, const double* b, double* x, hipStream_t s, bool chain) {
   if (A.sell()) {
     gs_colour_sell<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.woff.p, A.sci.p, A.sav.p, A.dinv.p, b, x, s);
-  } else if (A.long_min > 0 && !chain) {
-    gs_colour_long<double>(A.coff[k], A.lend[k], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s);
+  } else if (A.long_min > 0) {  // long rows first: a workgroup each, or one wavefront's chain
+    if (chain)
+      gs_colour<double>(A.coff[k], A.lend[k], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s, 64);
+    else
+      gs_colour_long<double>(A.coff[k], A.lend[k], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s);
     gs_colour<double>(A.lend[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s, A.lanes);
   } else {
     gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s, A.lanes);
@@ -177,8 +180,11 @@ void smooth_colour(const LevelMatrix& A, int k, const double* b, double* x, hipS
 void smooth_colour(const LevelMatrix& A, int k, const float* b, float* x, hipStream_t s, bool chain) {
   if (A.sell()) {
     gs_colour_sell<float>(A.coff[k], A.coff[k + 1], A.rp.p, A.woff.p, A.sci.p, A.sav32.p, A.dinv32.p, b, x, s);
-  } else if (A.long_min > 0 && !chain) {
-    gs_colour_long<float>(A.coff[k], A.lend[k], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s);
+  } else if (A.long_min > 0) {  // long rows first: a workgroup each, or one wavefront's chain
+    if (chain)
+      gs_colour<float>(A.coff[k], A.lend[k], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s, 64);
+    else
+      gs_colour_long<float>(A.coff[k], A.lend[k], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s);
     gs_colour<float>(A.lend[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s, A.lanes);
   } else {
     gs_colour<float>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s, A.lanes);

@@ -34,7 +34,7 @@ struct LevelMatrix {
 // Gauss-Seidel pass over colour k and residual (b == nullptr: product) of a
 // level matrix, on its sliced-ELL copy when it has one.
 // chain: every row by the single fma chain in stored order (the relaxation
-// before a build), long rows included.
+// before a build), long rows included (a wavefront of 64 lanes each).
 void smooth_colour(const LevelMatrix& A, int k, const double* b, double* x, hipStream_t s, bool chain = false);
 void smooth_colour(const LevelMatrix& A, int k, const float* b, float* x, hipStream_t s, bool chain = false);
 void level_residual(const LevelMatrix& A, const double* b, const double* x, double* r, hipStream_t s);

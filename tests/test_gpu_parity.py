@@ -237,7 +237,7 @@ def test_cycles_bit_exact(gpu, oracle, gname):
 
 @pytest.mark.parametrize("gname", ["hub", "powerlaw"])
 def test_long_rows_cycles(gpu, oracle, gname):
-    """Rows of 512 entries or more (hubs) take one workgroup each in the
+    """Rows of 256 entries or more (hubs) take one workgroup each in the
     cycles, with a fixed summation tree: the same hierarchy (the relaxation
     before a build keeps the single chain), cycles within rounding of the
     oracle (FP64 1e-12, FP32 1e-5 relative); with long_row_min = 0 the cycles
@@ -251,7 +251,7 @@ def test_long_rows_cycles(gpu, oracle, gname):
     long_levels = 0
     for l in range(s.num_levels()):
         m = s.level_info(l)["n"]
-        if m > 2048 and np.diff(s.level_get(l, "A_rp")).max() >= 512:
+        if m > 2048 and np.diff(s.level_get(l, "A_rp")).max() >= 256:
             long_levels += 1
     assert long_levels >= 1
     b = I.zero_mean_normal_rhs(3, n)
