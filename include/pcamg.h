@@ -110,6 +110,12 @@ typedef struct {
                               order; hubs of power-law graphs).  The relaxation of the start
                               vector before a build always keeps the chain.  0 = off (256: above
                               the longest rows of grid hierarchies) */
+  int32_t v_dense_max_n;   /* V-cycles: the cycle of the first level of at most this many vertices
+                              below the finest (at or above the single-workgroup tail) is applied
+                              by the level above as one precomputed dense operator (equal up to
+                              rounding order; built level by level from the coarsest on first use
+                              per hierarchy and precision, GEMMs through rocBLAS).  0 = recurse
+                              (2048) */
   uint64_t seed;           /* start-vector stream */
   uint64_t colour_seed;    /* colouring priority stream */
 } pcamg_params;

@@ -51,6 +51,7 @@ class Params(C.Structure):
         ("first_sweeps", _i32),
         ("dense_max_n", _i32),
         ("long_row_min", _i32),
+        ("v_dense_max_n", _i32),
         ("seed", _u64),
         ("colour_seed", _u64),
     ]

@@ -219,6 +219,7 @@ pcamg_status pcamg_params_default(pcamg_params* p) {
   p->first_sweeps = -1;
   p->dense_max_n = 12288;
   p->long_row_min = 256;
+  p->v_dense_max_n = 2048;
   p->seed = 0x5EED;
   p->colour_seed = 0xC010;
   return PCAMG_OK;
@@ -237,6 +238,7 @@ void setup_impl(const pcamg_graph* g, const double* rhs, const pcamg_params* p, 
           PCAMG_EINVAL, "row_lanes must be -1, 0, 1, 4, 16 or 64");
   require(p->first_sweeps >= -1 && p->first_sweeps <= 1000, PCAMG_EINVAL, "first_sweeps out of range");
   require(p->long_row_min >= 0, PCAMG_EINVAL, "long_row_min must be >= 0");
+  require(p->v_dense_max_n >= 0, PCAMG_EINVAL, "v_dense_max_n must be >= 0");
   hipStream_t s = as_stream(stream);
   if (p->validate) validate_graph(g, s);
   require(g->n >= 1, PCAMG_EINVAL, "empty graph");

@@ -258,19 +258,19 @@ DVec<T> two_calls(rocblas_handle h, const LevelMatrix& A, const DVec<T>& W, hipS
 
 }  // namespace
 
-bool dense_bottom_up_fits(const Hierarchy& H) {
+bool dense_bottom_up_fits(const Hierarchy& H, int start) {
   const int nl = (int)H.lv.size();
-  if (H.dense_start < 0) return false;
-  for (int l = H.dense_start; l < nl; ++l)
+  if (start < 0) return false;
+  for (int l = start; l < nl; ++l)
     if (H.lv[l].A->n > 65535) return false;  // rows of a pass are a grid dimension
   return H.cn <= 4096;
 }
 
 template <typename T>
-void dense_bottom_up(Hierarchy& H, T* C, hipStream_t s) {
+void dense_bottom_up(Hierarchy& H, int d, int gamma, T* C, hipStream_t s) {
   const int nl = (int)H.lv.size();
-  const int d = H.dense_start;
-  require(d >= 0 && nl - d >= 2 && dense_bottom_up_fits(H), PCAMG_EINVAL, "no dense region for the bottom-up build");
+  require(d >= 0 && nl - d >= 2 && dense_bottom_up_fits(H, d) && (gamma == 1 || gamma == 2), PCAMG_EINVAL,
+          "no dense region for the bottom-up build");
   BlasLease blas(s);  // held until the build has completed on s
   // Z: the coarsest operator on the identity
   const int32_t cn = H.cn;
@@ -283,10 +283,11 @@ void dense_bottom_up(Hierarchy& H, T* C, hipStream_t s) {
     const Transfer& Tr = H.lv[l].T;
     const int32_t n = A.n, m = Tr.nc;
     require(m == H.lv[l + 1].A->n, PCAMG_EINVAL, "transfer size does not match the next level");
-    // coarse operator: Z, or 2 W - W A W for the two calls of a non-coarsest level
+    // coarse operator: Z, one call W (V-cycle), or 2 W - W A W for the two
+    // calls of a non-coarsest level (W-cycle)
     DVec<T> Cop;
     const T* Cl = W.p;
-    if (l + 2 < nl) {
+    if (gamma == 2 && l + 2 < nl) {
       Cop = two_calls<T>(blas.h, *H.lv[l + 1].A, W, s);
       Cl = Cop.p;
     }
@@ -316,15 +317,17 @@ void dense_bottom_up(Hierarchy& H, T* C, hipStream_t s) {
     }
     W = std::move(X);
   }
-  // the level above applies two calls of level d's cycle from x = 0
+  // the level above applies gamma calls of level d's cycle from x = 0
   const int32_t nd = H.lv[d].A->n;
-  DVec<T> Cd = two_calls<T>(blas.h, *H.lv[d].A, W, s);
-  blk_transpose_kernel<T><<<dim3((nd + 31) / 32, (nd + 31) / 32), 256, 0, s>>>(nd, Cd.p, C);
+  DVec<T> Cd;
+  if (gamma == 2) Cd = two_calls<T>(blas.h, *H.lv[d].A, W, s);
+  const T* src = gamma == 2 ? Cd.p : W.p;
+  blk_transpose_kernel<T><<<dim3((nd + 31) / 32, (nd + 31) / 32), 256, 0, s>>>(nd, src, C);
   PCAMG_LAUNCHED();
   PCAMG_HIP(hipStreamSynchronize(s));  // temporaries are freed on return
 }
 
-template void dense_bottom_up<double>(Hierarchy&, double*, hipStream_t);
-template void dense_bottom_up<float>(Hierarchy&, float*, hipStream_t);
+template void dense_bottom_up<double>(Hierarchy&, int, int, double*, hipStream_t);
+template void dense_bottom_up<float>(Hierarchy&, int, int, float*, hipStream_t);
 
 }  // namespace pcamg

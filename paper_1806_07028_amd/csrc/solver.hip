@@ -531,11 +531,23 @@ std::unique_ptr<Hierarchy> build_hierarchy(pcamg_ctx* c, const double* e_nat) {
       copy_h2d(H->tail_desc.p, &D, 1, s);
       sync(s);  // D is a host temporary
     }
-    // not below the tail's first level: the dense product is applied from a
-    // level launched step by step
-    int ds = first_small(std::max<int32_t>(c->P.dense_max_n, 1));
+    // the dense operators start at the first level of at most their size
+    // limit (no tail descriptor limits), not below the tail's first level:
+    // the dense product is applied from a level launched step by step
+    auto first_at_most = [&](int32_t limit) {
+      int l = nl - 1;
+      while (l > 0 && H->lv[l - 1].A->n <= limit) --l;
+      return l;
+    };
+    int ds = first_at_most(std::max<int32_t>(c->P.dense_max_n, 1));
     if (H->tail_start >= 0) ds = std::min(ds, H->tail_start);
     if (ds >= 1 && nl - ds >= 2) H->dense_start = ds;
+    // V-cycles: the same from the first level of at most v_dense_max_n
+    if (c->P.v_dense_max_n > 0) {
+      int dv = first_at_most(c->P.v_dense_max_n);
+      if (H->tail_start >= 0) dv = std::min(dv, H->tail_start);
+      if (dv >= 1 && nl - dv >= 2) H->dense_v_start = dv;
+    }
   }
   if (P.keep_setup) {
     H->setup.resize(nl);
@@ -605,7 +617,8 @@ void cycle64(pcamg_ctx* c, Hierarchy& H, int l, const double* b, double* x, int 
   Level& N = H.lv[l + 1];
   const LevelMatrix& AN = *N.A;
   const int calls = (gamma > 1 && l + 2 < nl) ? gamma : 1;
-  const bool dense = calls == 2 && l + 1 == H.dense_start && H.C64.p;
+  const bool dense_v = gamma == 1 && l + 1 == H.dense_v_start && H.CV64.p;
+  const bool dense = (calls == 2 && l + 1 == H.dense_start && H.C64.p) || dense_v;
   // the child's x: written by the dense product or the coarsest solve, zero
   // for the tail, else zero with its first colour pass done here
   const bool launched_child = !dense && l + 2 < nl && l + 1 != H.tail_start;
@@ -613,7 +626,9 @@ void cycle64(pcamg_ctx* c, Hierarchy& H, int l, const double* b, double* x, int 
   level_residual(A, b, x, L.r.p, s);
   restrict_members<double>(L.T.nc, L.T.moff.p, L.T.mem.p, L.T.pval.p, L.r.p, N.b.p, s, N.x.p, AN.dinv.p,
                         AN.coff.size() > 1 ? AN.coff[1] : 0, mode);
-  if (dense) {  // both sub-cycles below at once
+  if (dense_v) {  // the V-cycle below at once
+    dense_apply<double>(AN.n, H.CV64.p, N.b.p, H.dvpart64.p, N.x.p, s);
+  } else if (dense) {  // both sub-cycles below at once
     dense_apply<double>(AN.n, H.C64.p, N.b.p, H.dpart64.p, N.x.p, s);
   } else {
     for (int q = 0; q < calls; ++q) cycle64(c, H, l + 1, N.b.p, N.x.p, gamma, q == 0 && mode == 2 ? 1 : 0);
@@ -648,7 +663,8 @@ void cycle32(pcamg_ctx* c, Hierarchy& H, int l, const float* b, float* x, int ga
   Level& N = H.lv[l + 1];
   const LevelMatrix& AN = *N.A;
   const int calls = (gamma > 1 && l + 2 < nl) ? gamma : 1;
-  const bool dense = calls == 2 && l + 1 == H.dense_start && H.C32.p;
+  const bool dense_v = gamma == 1 && l + 1 == H.dense_v_start && H.CV32.p;
+  const bool dense = (calls == 2 && l + 1 == H.dense_start && H.C32.p) || dense_v;
   // the child's x: written by the dense product or the coarsest solve, zero
   // for the tail, else zero with its first colour pass done here
   const bool launched_child = !dense && l + 2 < nl && l + 1 != H.tail_start;
@@ -656,7 +672,9 @@ void cycle32(pcamg_ctx* c, Hierarchy& H, int l, const float* b, float* x, int ga
   level_residual(A, b, x, L.r32.p, s);
   restrict_members<float>(L.T.nc, L.T.moff.p, L.T.mem.p, L.T.pval32.p, L.r32.p, N.b32.p, s, N.x32.p, AN.dinv32.p,
                         AN.coff.size() > 1 ? AN.coff[1] : 0, mode);
-  if (dense) {  // both sub-cycles below at once
+  if (dense_v) {  // the V-cycle below at once
+    dense_apply<float>(AN.n, H.CV32.p, N.b32.p, H.dvpart32.p, N.x32.p, s);
+  } else if (dense) {  // both sub-cycles below at once
     dense_apply<float>(AN.n, H.C32.p, N.b32.p, H.dpart32.p, N.x32.p, s);
   } else {
     for (int q = 0; q < calls; ++q) cycle32(c, H, l + 1, N.b32.p, N.x32.p, gamma, q == 0 && mode == 2 ? 1 : 0);
@@ -702,37 +720,40 @@ hipGraphExec_t capture(pcamg_ctx* c, F&& body) {
 }
 }  // namespace
 
-// The dense operator of the two W sub-cycles of level dense_start (gamma = 2),
-// built once per hierarchy and precision on first use.
+// The dense operators of the two W sub-cycles of level dense_start
+// (gamma = 2) and of the V-cycle of level dense_v_start (gamma = 1), built
+// once per hierarchy and precision on first use.
 template <typename T>
 struct DenseOf;
 template <>
 struct DenseOf<double> {
-  static DVec<double>& C(Hierarchy& H) { return H.C64; }
-  static DVec<double>& part(Hierarchy& H) { return H.dpart64; }
+  static DVec<double>& C(Hierarchy& H, int gamma) { return gamma == 2 ? H.C64 : H.CV64; }
+  static DVec<double>& part(Hierarchy& H, int gamma) { return gamma == 2 ? H.dpart64 : H.dvpart64; }
 };
 template <>
 struct DenseOf<float> {
-  static DVec<float>& C(Hierarchy& H) { return H.C32; }
-  static DVec<float>& part(Hierarchy& H) { return H.dpart32; }
+  static DVec<float>& C(Hierarchy& H, int gamma) { return gamma == 2 ? H.C32 : H.CV32; }
+  static DVec<float>& part(Hierarchy& H, int gamma) { return gamma == 2 ? H.dpart32 : H.dvpart32; }
 };
 
 template <typename T>
-void ensure_dense(pcamg_ctx* c, Hierarchy& H) {
+void ensure_dense(pcamg_ctx* c, Hierarchy& H, int gamma) {
   const int nl = (int)H.lv.size();
-  // without a dense operator the W-cycle recurses (levels too large for the build)
-  if (!c->P.w_dense || H.dense_start < 1 || nl - H.dense_start < 2 || !dense_bottom_up_fits(H)) return;
-  DVec<T>& C = DenseOf<T>::C(H);
+  const int d = gamma == 2 ? H.dense_start : H.dense_v_start;
+  const bool on = gamma == 2 ? c->P.w_dense != 0 : c->P.v_dense_max_n > 0;
+  // without a dense operator the cycle recurses (levels too large for the build)
+  if (!on || d < 1 || nl - d < 2 || !dense_bottom_up_fits(H, d)) return;
+  DVec<T>& C = DenseOf<T>::C(H, gamma);
   if (C.p) return;
-  const int32_t nd = H.lv[H.dense_start].A->n;
+  const int32_t nd = H.lv[d].A->n;
   C.resize((size_t)nd * nd);
-  DenseOf<T>::part(H).resize((size_t)dense_chunks(nd) * nd);
-  dense_bottom_up<T>(H, C.p, c->s);
+  DenseOf<T>::part(H, gamma).resize((size_t)dense_chunks(nd) * nd);
+  dense_bottom_up<T>(H, d, gamma, C.p, c->s);
 }
 
 void run_cycle64(pcamg_ctx* c, Hierarchy& H, const double* b, double* x, int gamma) {
   hipStream_t s = c->s;
-  if (gamma > 1) ensure_dense<double>(c, H);
+  ensure_dense<double>(c, H, gamma > 1 ? 2 : 1);
   const int32_t n = c->n;
   if (!c->P.use_graphs) {
     cycle64(c, H, 0, b, x, gamma);
@@ -752,7 +773,7 @@ void run_cycle64(pcamg_ctx* c, Hierarchy& H, const double* b, double* x, int gam
 
 void run_cycle32(pcamg_ctx* c, Hierarchy& H, const float* b, float* x, int gamma) {
   hipStream_t s = c->s;
-  if (gamma > 1) ensure_dense<float>(c, H);
+  ensure_dense<float>(c, H, gamma > 1 ? 2 : 1);
   const int32_t n = c->n;
   if (!c->P.use_graphs) {
     cycle32(c, H, 0, b, x, gamma);

@@ -103,6 +103,11 @@ struct Hierarchy {
   int dense_start = -1;
   DVec<double> C64, dpart64;
   DVec<float> C32, dpart32;
+  // V-cycles: the level whose cycle the level above applies as one dense
+  // operator (column-major, built on first use)
+  int dense_v_start = -1;
+  DVec<double> CV64, dvpart64;
+  DVec<float> CV32, dvpart32;
   std::vector<DVec<int32_t>> coff_dev;
   // captured top-level cycles (fixed input/output buffers)
   hipGraphExec_t g64v = nullptr, g64w = nullptr, g32v = nullptr, g32w = nullptr;
@@ -201,11 +206,12 @@ void run_cycle32(pcamg_ctx* c, Hierarchy& H, const float* b, float* x, int gamma
 void tail_cycle64(const Hierarchy& H, const double* b, double* x, int gamma, hipStream_t s);
 void tail_cycle32(const Hierarchy& H, const float* b, float* x, int gamma, hipStream_t s);
 
-// dense.hip: the dense W operator built level by level from the coarsest up
-// (GEMMs for the products with dense operators); column-major into C (n_d^2).
-bool dense_bottom_up_fits(const Hierarchy& H);
+// dense.hip: the dense operator of gamma (1: V, 2: W) calls of level d's cycle
+// from x = 0, built level by level from the coarsest up (GEMMs for the
+// products with dense operators); column-major into C (n_d^2).
+bool dense_bottom_up_fits(const Hierarchy& H, int d);
 template <typename T>
-void dense_bottom_up(Hierarchy& H, T* C, hipStream_t s);
+void dense_bottom_up(Hierarchy& H, int d, int gamma, T* C, hipStream_t s);
 
 template <typename T>
 void dense_apply(int32_t n, const T* C, const T* b, T* part, T* y, hipStream_t s);

@@ -4,10 +4,11 @@ launch configuration -- FCG with FP32 cycles, red-black finest level on its
 sliced-ELL copy, XCD-contiguous tiles, single-workgroup tail, captured graphs
 and the dense W operator built from the coarsest up.
 
-Bars: the first hierarchy and an FP32 V-cycle bit for bit against the oracle
-(the oracle builds the 128^3 hierarchy in about ten seconds); the FP32
-W-cycle through the dense operator within 1e-5 relative of the oracle's FP32
-recursion (the dense operator changes the rounding order only)."""
+Bars: the first hierarchy and an FP32 V-cycle (recursive) bit for bit against
+the oracle (the oracle builds the 128^3 hierarchy in about ten seconds); the
+FP32 W-cycle and the default FP32 V-cycle through their dense operators within
+1e-5 relative of the oracle's FP32 recursion (a dense operator changes the
+rounding order only)."""
 import numpy as np
 import pytest
 
@@ -22,7 +23,8 @@ def full(gpu, oracle):
     g, b = I.config2(side=128)
     n, rp, ci, w = g
     print(f"fullsize: 128^3 grid, n={n}, edges={len(ci) // 2}", flush=True)
-    s = gpu.Solver(rp, ci, w, b, outer="fcg", cycle_prec="f32", theta=0.5, keep_setup=1)
+    # V-cycles recurse here (bit for bit); the default dense V operator below
+    s = gpu.Solver(rp, ci, w, b, outer="fcg", cycle_prec="f32", theta=0.5, keep_setup=1, v_dense_max_n=0)
     H = oracle.Hierarchy(g, None)
     return g, b, s, H
 
@@ -54,3 +56,18 @@ def test_fullsize_wcycle32_dense(full):
     got = host(s.cycle32(b32, None, 2)).astype(np.float64)
     ref = H.cycle32(b32, None, 2).astype(np.float64)
     assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref)
+
+
+def test_fullsize_vcycle32_dense(full):
+    """The benchmark's default: the V-cycle below the first level of at most
+    2048 vertices applied as one dense operator, within 1e-5 relative of the
+    oracle's FP32 recursion."""
+    g, b, s, H = full
+    import paper_1806_07028_amd as P
+    n, rp, ci, w = g
+    sd = P.Solver(rp, ci, w, b, outer="fcg", cycle_prec="f32", theta=0.5)
+    b32 = b.astype(np.float32)
+    got = host(sd.cycle32(b32)).astype(np.float64)
+    ref = H.vcycle32(b32).astype(np.float64)
+    assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref)
+    assert not np.array_equal(got, ref)

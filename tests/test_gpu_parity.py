@@ -160,12 +160,14 @@ def test_aggregate_galerkin_shorten(gpu, oracle, graph):
 
 
 def solver_for(gpu, g, b=None, **kw):
-    """Solver with per-level arrays kept; W-cycles recurse (w_dense = 0) unless
-    asked otherwise, so every cycle is the oracle's bit for bit."""
+    """Solver with per-level arrays kept; W- and V-cycles recurse (w_dense = 0,
+    v_dense_max_n = 0) unless asked otherwise, so every cycle is the oracle's
+    bit for bit."""
     n, rp, ci, w = g
     if b is None:
         b = I.zero_mean_normal_rhs(99, n)
     kw.setdefault("w_dense", 0)
+    kw.setdefault("v_dense_max_n", 0)
     return gpu.Solver(rp, ci, w, b, keep_setup=1, **kw)
 
 
@@ -470,6 +472,57 @@ def test_dense_w_cycle(gpu, oracle, gname):
         torch.cuda.synchronize()
     # V-cycles are untouched
     same(host(dense.cycle(b, x0, 1)), H.cycle(b, x0, 1))
+
+
+@pytest.mark.parametrize("gname", ["grid3d_20", "powerlaw"])
+def test_dense_v_cycle(gpu, oracle, gname):
+    """V-cycles with the cycle of the first level of at most 2048 vertices
+    applied as one precomputed dense operator: the same linear map as the
+    recursion, different rounding order. FP64 within 1e-12 relative, FP32
+    within 1e-5 relative of the oracle's recursive cycle; graph replays equal
+    the eager dense cycle bit for bit; W-cycles untouched."""
+    g = I.grid3d(20, 20, 20, weight_seed=7) if gname == "grid3d_20" else I.config3(n0=30000)[0]
+    n = g[0]
+    b = I.zero_mean_normal_rhs(3, n)
+    x0 = I.normal(4, n)
+    kw = dict(long_row_min=0)  # hub rows by the single chain, as in the oracle
+    dense = solver_for(gpu, g, v_dense_max_n=2048, **kw)
+    dense_eager = solver_for(gpu, g, v_dense_max_n=2048, use_graphs=0, **kw)
+    H = oracle.Hierarchy(g, None)
+    assert dense.num_levels() == H.nlevels >= 4
+    sizes = [dense.level_info(l)["n"] for l in range(dense.num_levels())]
+    assert sizes[1] > 2048  # a launched level applies the operator below it
+    v_ref = H.cycle(b, x0, 1)
+    v64 = host(dense.cycle(b, x0, 1))
+    assert np.linalg.norm(v64 - v_ref) <= 1e-12 * np.linalg.norm(v_ref)
+    # a smooth right-hand side, whose solution comes mostly from the coarse
+    # levels: the dense path is really taken (its rounding shows)
+    a, d, dinv = oracle.laplacian(g)
+    e = H.get_dbl(0, "e")
+    bs = d * e + np.bincount(np.repeat(np.arange(n), np.diff(g[1])), weights=a * e[g[2]], minlength=n)
+    bs -= bs.mean()
+    vs_ref = H.cycle(bs, None, 1)
+    vs = host(dense.cycle(bs, None, 1))
+    assert np.linalg.norm(vs - vs_ref) <= 1e-12 * np.linalg.norm(vs_ref)
+    assert not np.array_equal(vs, vs_ref)
+    b32 = b.astype(np.float32)
+    v32_ref = H.vcycle32(b32).astype(np.float64)
+    v32 = host(dense.cycle32(b32)).astype(np.float64)
+    assert np.linalg.norm(v32 - v32_ref) <= 1e-5 * np.linalg.norm(v32_ref)
+    e64 = host(dense_eager.cycle(b, x0, 1))
+    e32 = host(dense_eager.cycle32(b32))
+    for rep in range(3):
+        same(host(dense.cycle(b, x0, 1)), e64)
+        same(host(dense.cycle32(b32)), e32)
+        dense_eager.cycle(b, None, 2)
+        torch.cuda.synchronize()
+    same(host(dense.cycle(b, x0, 2)), H.cycle(b, x0, 2))
+    # the solve converges as with recursive V-cycles
+    rec = solver_for(gpu, g, b, **kw)
+    x, st = solver_for(gpu, g, b, v_dense_max_n=2048, **kw).solve()
+    xr, str_ = rec.solve()
+    assert st["status"] == 0 and st["true_relres"] <= 1.0001e-8
+    assert abs(st["iterations"] - str_["iterations"]) <= 1
 
 
 @pytest.mark.parametrize("gname", ["grid3d_w", "hub"])
