@@ -347,8 +347,9 @@ void compact_i32(const int32_t* in, const uint8_t* flags, int32_t* out, int32_t*
 //  pass k: (1) per-tile digit histograms, stored digit-major so one exclusive
 //  scan gives every (digit, tile) its global offset; (2) per tile, each wave
 //  ranks its keys in order with 64-bit ballots (peers = lanes with the same
-//  digit), waves are combined in wave order, and keys are scattered to
-//  offset + rank.  Keys keep their input order within a digit (stable).
+//  digit), waves are combined in wave order, the tile is reordered in LDS
+//  and written out digit run by digit run to offset + rank (coalesced).  Keys
+//  keep their input order within a digit (stable).
 // ---------------------------------------------------------------------------
 constexpr int RS_BLOCK = 256;
 constexpr int RS_ITEMS = 8;                       // per lane
@@ -374,6 +375,9 @@ __global__ void rs_scatter_kernel(const K* keys, const uint32_t* vals, K* okeys,
                                   int shift, const int32_t* offs, int ntiles) {
   __shared__ int32_t wcount[RS_WAVES][256];
   __shared__ int32_t goff[256];
+  __shared__ int32_t tstart[256];
+  __shared__ K lkey[RS_TILE];
+  __shared__ uint32_t lval[RS_TILE];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int d = threadIdx.x; d < 256; d += RS_BLOCK) {
     for (int w = 0; w < RS_WAVES; ++w) wcount[w][d] = 0;
@@ -411,7 +415,7 @@ __global__ void rs_scatter_kernel(const K* keys, const uint32_t* vals, K* okeys,
     rank[r] = before + __popcll(peers & lt);
   }
   __syncthreads();
-  // exclusive prefix over waves for each digit
+  // exclusive prefix over waves for each digit, and the tile's digit counts
   for (int d = threadIdx.x; d < 256; d += RS_BLOCK) {
     int acc = 0;
     for (int w = 0; w < RS_WAVES; ++w) {
@@ -419,13 +423,49 @@ __global__ void rs_scatter_kernel(const K* keys, const uint32_t* vals, K* okeys,
       wcount[w][d] = acc;
       acc += t;
     }
+    tstart[d] = acc;
   }
   __syncthreads();
+  // tile-local start of every digit (exclusive scan of the 256 counts)
+  if (threadIdx.x < 64) {
+    int c[4], sum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      c[q] = tstart[4 * lane + q];
+      sum += c[q];
+    }
+    int incl = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += t;
+    }
+    int run = incl - sum;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      tstart[4 * lane + q] = run;
+      run += c[q];
+    }
+  }
+  __syncthreads();
+  // the tile in LDS in its sorted order (stable: wave order, then rank) ...
   for (int r = 0; r < RS_ITEMS; ++r) {
     if (dig[r] < 0) continue;
-    int32_t dst = goff[dig[r]] + wcount[wid][dig[r]] + rank[r];
-    okeys[dst] = kk[r];
-    ovals[dst] = vv[r];
+    const int lp = tstart[dig[r]] + wcount[wid][dig[r]] + rank[r];
+    lkey[lp] = kk[r];
+    lval[lp] = vv[r];
+  }
+  __syncthreads();
+  // ... then written out in that order: a digit's run is one contiguous
+  // segment of the output, so consecutive threads write consecutive addresses
+  const size_t base = (size_t)blockIdx.x * RS_TILE;
+  const int tn = (int)(n - base < (size_t)RS_TILE ? n - base : (size_t)RS_TILE);
+  for (int i = threadIdx.x; i < tn; i += RS_BLOCK) {
+    const K key = lkey[i];
+    const int d = (int)((key >> shift) & 0xFF);
+    const int32_t dst = goff[d] + (i - tstart[d]);
+    okeys[dst] = key;
+    ovals[dst] = lval[i];
   }
 }
 
