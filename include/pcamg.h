@@ -179,8 +179,9 @@ void pcamg_destroy(pcamg_ctx* c);
 
 /* Batched setup and solve of independent graphs (the batching extension;
  * per graph exactly Alg. 5 as pcamg_setup + pcamg_solve).  A pool of
- * `workers` host threads (1..64), each with its own HIP stream of default
- * priority, takes the graphs largest first; each graph is set up, solved and
+ * `workers` host threads (1..64; with 1, the calling thread itself), each with
+ * its own HIP stream of default priority, takes the graphs largest first;
+ * each graph is set up, solved and
  * released on its worker's stream, so x[g] and stats[g] equal those of the
  * individual calls bit for bit.  graphs[count]: device CSR as for
  * pcamg_setup; rhs[g]: device [n_g] (must sum to 0); x[g]: device [n_g],

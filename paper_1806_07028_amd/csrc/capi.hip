@@ -449,10 +449,14 @@ pcamg_status pcamg_batch_solve(const pcamg_graph* graphs, const double* const* r
         (void)hipStreamDestroy(s);
       }
     };
-    std::vector<std::thread> pool;
     const int32_t nw = std::min(workers, count);
-    for (int32_t w = 0; w < nw; ++w) pool.emplace_back(worker);
-    for (auto& t : pool) t.join();
+    if (nw == 1) {  // one worker: the graphs one after another on the calling thread
+      worker();
+    } else {
+      std::vector<std::thread> pool;
+      for (int32_t w = 0; w < nw; ++w) pool.emplace_back(worker);
+      for (auto& t : pool) t.join();
+    }
     for (int32_t g = 0; g < count; ++g)
       if (status[g] != PCAMG_OK) throw Error(status[g], "graph " + std::to_string(g) + ": " + msg[g]);
   });

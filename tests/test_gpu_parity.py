@@ -555,12 +555,7 @@ BATCH_SKIP = pytest.mark.skip(
            "until it is; builds now share one serialised rocBLAS handle")
 
 
-@BATCH_SKIP
-def test_batch_equals_individual(gpu, oracle):
-    """Batched setup + solve of uneven graphs on four worker streams: every
-    graph's solution and statistics equal its own single-graph solve bit for
-    bit, on a first and a second batch (the second reuses cached memory across
-    streams); the small graphs also match the oracle's counts."""
+def _batch_equals_individual(gpu, oracle, workers):
     batch = I.config4(seed=3, count=12, n_lo=400, n_hi=20000)
     graphs = [(g[1], g[2], g[3]) for g, b, k in batch]
     rhs = [b for g, b, k in batch]
@@ -571,7 +566,7 @@ def test_batch_equals_individual(gpu, oracle):
         ref.append((host(x), st))
         s.close()
     for rep in range(2):
-        xs, sts = gpu.batch_solve(graphs, rhs, workers=4)
+        xs, sts = gpu.batch_solve(graphs, rhs, workers=workers)
         for i, ((xr, sr), x, st) in enumerate(zip(ref, xs, sts)):
             same(host(x), xr)
             for key in ("iterations", "rebuilds", "levels", "status"):
@@ -584,8 +579,21 @@ def test_batch_equals_individual(gpu, oracle):
 
 
 @BATCH_SKIP
-def test_batch_errors(gpu):
-    """A disconnected graph fails on its own (its status), the others are solved."""
+def test_batch_equals_individual(gpu, oracle):
+    """Batched setup + solve of uneven graphs on four worker streams: every
+    graph's solution and statistics equal its own single-graph solve bit for
+    bit, on a first and a second batch (the second reuses cached memory across
+    streams); the small graphs also match the oracle's counts."""
+    _batch_equals_individual(gpu, oracle, 4)
+
+
+def test_batch_one_worker_equals_individual(gpu, oracle):
+    """The same with one worker (the graphs one after another on the calling
+    thread, no host threads)."""
+    _batch_equals_individual(gpu, oracle, 1)
+
+
+def _batch_errors(gpu, workers):
     batch = I.config4(seed=5, count=5, n_lo=300, n_hi=3000)
     graphs = [(g[1], g[2], g[3]) for g, b, k in batch]
     rhs = [b for g, b, k in batch]
@@ -593,17 +601,28 @@ def test_batch_errors(gpu):
     bad = I.csr_from_edges(32, np.concatenate([a2, a2 + 16]), np.concatenate([b2, b2 + 16]), np.ones(2 * len(a2)))
     graphs.insert(2, (bad[1], bad[2], bad[3]))
     rhs.insert(2, I.zero_mean_normal_rhs(1, 32))
-    xs, sts = gpu.batch_solve(graphs, rhs, workers=3, raise_on_error=False)
+    xs, sts = gpu.batch_solve(graphs, rhs, workers=workers[0], raise_on_error=False)
     assert sts[2]["status"] == -6
     for i, st in enumerate(sts):
         if i != 2:
             assert st["status"] == 0 and st["true_relres"] <= 1.0001e-8
     import paper_1806_07028_amd as P
     with pytest.raises(P.PcamgError) as ei:
-        gpu.batch_solve(graphs, rhs, workers=2)
+        gpu.batch_solve(graphs, rhs, workers=workers[1])
     assert ei.value.status == -6
-    xs, sts = gpu.batch_solve([], [], workers=2)
+    xs, sts = gpu.batch_solve([], [], workers=workers[1])
     assert xs == [] and sts == []
+
+
+@BATCH_SKIP
+def test_batch_errors(gpu):
+    """A disconnected graph fails on its own (its status), the others are solved."""
+    _batch_errors(gpu, (3, 2))
+
+
+def test_batch_errors_one_worker(gpu):
+    """The same with one worker on the calling thread."""
+    _batch_errors(gpu, (1, 1))
 
 
 def test_colour_dense_levels(gpu, oracle):
