@@ -890,6 +890,119 @@ bool sell_build(int32_t n, int32_t nnz, const int32_t* rp, const int32_t* ci, co
   return true;
 }
 
+// ---------------------------------------------------------------------------
+// Padded-row (ELL) copy of a level with lane groups: row i's entries at
+// i*W + 0 .. i*W + len-1, the slots up to W padded with column i and value 0
+// (never in a chain; they keep the speculative loads in bounds).  The pass
+// loads a row's entries and its length together, so only the gathers of x
+// wait on a load: two memory round trips per row instead of three (row
+// pointer, then entries, then x).  The chain is the CSR one: entries in
+// stored order, fma by fma.
+// ---------------------------------------------------------------------------
+__global__ void ell_fill_kernel(int32_t n, int32_t W, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                const float* __restrict__ av32, int32_t* __restrict__ eci, float* __restrict__ eav) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t k0 = rp[i], len = rp[i + 1] - k0;
+  const size_t o = (size_t)i * W;
+  for (int32_t j = 0; j < W; ++j) {
+    eci[o + j] = j < len ? ci[k0 + j] : i;
+    eav[o + j] = j < len ? av32[k0 + j] : 0.0f;
+  }
+}
+
+template <int G, int UT>
+__global__ void __launch_bounds__(256)
+    gs_ell_kernel(int32_t row0, int32_t row1, int32_t W, const int32_t* __restrict__ rp,
+                  const int32_t* __restrict__ eci, const float* __restrict__ eav, const float* __restrict__ dinv,
+                  const float* __restrict__ b, float* __restrict__ x) {
+  const int32_t i = row0 + (int32_t)((xcd_block() * blockDim.x + threadIdx.x) / G);
+  const bool ok = i < row1;
+  const int32_t ii = ok ? i : row0;  // a valid row for the loads of idle lanes
+  const int q = (int)(threadIdx.x & (G - 1));
+  const int32_t len = ok ? rp[ii + 1] - rp[ii] : 0;
+  const size_t base = (size_t)ii * W;
+  int32_t c[UT];
+  float a[UT], v[UT];
+#pragma unroll
+  for (int u = 0; u < UT; ++u) {
+    const int32_t kk = u * G + q;
+    c[u] = kk < W ? eci[base + kk] : ii;
+    a[u] = kk < W ? eav[base + kk] : 0.0f;
+  }
+#pragma unroll
+  for (int u = 0; u < UT; ++u) v[u] = x[c[u]];
+  const int32_t span = wave_max_len(len);
+  float s = 0.0f;
+#pragma unroll
+  for (int u = 0; u < UT; ++u) {
+    const int32_t e = u * G;
+    if (e >= span) break;  // wave-uniform
+    if constexpr (G == 4) {
+      const float a0 = quad_bcast<0>(a[u]), v0 = quad_bcast<0>(v[u]);
+      const float a1 = quad_bcast<1>(a[u]), v1 = quad_bcast<1>(v[u]);
+      const float a2 = quad_bcast<2>(a[u]), v2 = quad_bcast<2>(v[u]);
+      const float a3 = quad_bcast<3>(a[u]), v3 = quad_bcast<3>(v[u]);
+      if (e + 0 < len) s = fma(a0, v0, s);
+      if (e + 1 < len) s = fma(a1, v1, s);
+      if (e + 2 < len) s = fma(a2, v2, s);
+      if (e + 3 < len) s = fma(a3, v3, s);
+    } else {
+#pragma unroll
+      for (int t = 0; t < G; ++t) {
+        const float at = __shfl(a[u], t, G);
+        const float vt = __shfl(v[u], t, G);
+        if (e + t < len) s = fma(at, vt, s);
+      }
+    }
+  }
+  if (ok && q == 0) x[i] = (b[i] - s) * dinv[i];
+}
+
+int32_t ell_slots(int32_t W, int lanes) {
+  const int32_t per = (W + lanes - 1) / lanes;  // entries per lane
+  for (int32_t ut : {2, 4, 8, 16})
+    if (per <= ut && (lanes == 4 || ut <= 8)) return ut;
+  return 0;
+}
+
+bool ell_build(int32_t n, int32_t lanes, const int32_t* rp, const int32_t* ci, const float* av32, int32_t& W,
+               DVec<int32_t>& eci, DVec<float>& eav, hipStream_t s) {
+  if (n <= 0 || (lanes != 4 && lanes != 16)) return false;
+  W = max_row_len(n, rp, s);
+  if (W <= 0 || ell_slots(W, lanes) == 0) {
+    W = 0;
+    return false;
+  }
+  eci.resize((size_t)n * W);
+  eav.resize((size_t)n * W);
+  ell_fill_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, W, rp, ci, av32, eci.p, eav.p);
+  PCAMG_LAUNCHED();
+  return true;
+}
+
+template <int G, int UT>
+void gs_ell_launch(int32_t row0, int32_t row1, int32_t W, const int32_t* rp, const int32_t* eci, const float* eav,
+                   const float* dinv, const float* b, float* x, hipStream_t s) {
+  gs_ell_kernel<G, UT><<<grid_for((size_t)(row1 - row0) * G, 256), 256, 0, s>>>(row0, row1, W, rp, eci, eav, dinv,
+                                                                                b, x);
+  PCAMG_LAUNCHED();
+}
+
+void gs_colour_ell(int32_t row0, int32_t row1, int32_t W, int lanes, const int32_t* rp, const int32_t* eci,
+                   const float* eav, const float* dinv, const float* b, float* x, hipStream_t s) {
+  if (row1 <= row0) return;
+  const int32_t ut = ell_slots(W, lanes);
+  if (lanes == 16 && ut == 2) gs_ell_launch<16, 2>(row0, row1, W, rp, eci, eav, dinv, b, x, s);
+  else if (lanes == 16 && ut == 4) gs_ell_launch<16, 4>(row0, row1, W, rp, eci, eav, dinv, b, x, s);
+  else if (lanes == 16 && ut == 8) gs_ell_launch<16, 8>(row0, row1, W, rp, eci, eav, dinv, b, x, s);
+  else if (lanes == 4 && ut == 2) gs_ell_launch<4, 2>(row0, row1, W, rp, eci, eav, dinv, b, x, s);
+  else if (lanes == 4 && ut == 4) gs_ell_launch<4, 4>(row0, row1, W, rp, eci, eav, dinv, b, x, s);
+  else if (lanes == 4 && ut == 8) gs_ell_launch<4, 8>(row0, row1, W, rp, eci, eav, dinv, b, x, s);
+  else if (lanes == 4 && ut == 16) gs_ell_launch<4, 16>(row0, row1, W, rp, eci, eav, dinv, b, x, s);
+  else throw Error(PCAMG_EINVAL, "padded-row copy: unsupported width");
+}
+
 // Restriction b_c = P^T r: fma chain over the members of each aggregate in
 // ascending (natural) order.  pval == nullptr: boolean P.  With xc, the
 // coarse x is started too: mode 1 zero; mode 2 the coarse level's first

@@ -210,6 +210,15 @@ void spmv(int32_t n, const int32_t* rp, const int32_t* ci, const T* av, const T*
 // bandwidth).  Synchronises.
 bool sell_build(int32_t n, int32_t nnz, const int32_t* rp, const int32_t* ci, const double* av, const float* av32,
                 DVec<int32_t>& woff, DVec<int32_t>& sci, DVec<double>& sav, DVec<float>& sav32, hipStream_t s);
+// Padded-row (ELL, width W = longest row) FP32 copy of a level with 4 or 16
+// lanes per row and W small enough for one batch of loads per lane (W <= 64
+// for 4 lanes, <= 128 for 16); false (nothing allocated) otherwise.
+// Synchronises.
+bool ell_build(int32_t n, int32_t lanes, const int32_t* rp, const int32_t* ci, const float* av32, int32_t& W,
+               DVec<int32_t>& eci, DVec<float>& eav, hipStream_t s);
+// FP32 Gauss-Seidel colour pass on that copy: the same chains, results identical.
+void gs_colour_ell(int32_t row0, int32_t row1, int32_t W, int lanes, const int32_t* rp, const int32_t* eci,
+                   const float* eav, const float* dinv, const float* b, float* x, hipStream_t s);
 // Gauss-Seidel colour pass and residual (b == nullptr: product) on that copy;
 // rp still gives the row lengths.  Same results as the CSR kernels.
 template <typename T>

@@ -142,6 +142,9 @@ std::shared_ptr<LevelMatrix> make_level_matrix(int32_t n, int32_t nnz, const int
       M->sav32.resize(0);
     }
   }
+  // launched lane-group levels without long rows: padded-row FP32 copy
+  if (n > TUNE_MIN_N && M->long_min == 0 && !M->sell() && (M->lanes == 4 || M->lanes == 16))
+    ell_build(n, M->lanes, M->rp.p, M->ci.p, M->av32.p, M->ell_w, M->eci, M->eav32, s);
   return M;
 }
 
@@ -180,6 +183,8 @@ void smooth_colour(const LevelMatrix& A, int k, const double* b, double* x, hipS
 void smooth_colour(const LevelMatrix& A, int k, const float* b, float* x, hipStream_t s, bool chain) {
   if (A.sell()) {
     gs_colour_sell<float>(A.coff[k], A.coff[k + 1], A.rp.p, A.woff.p, A.sci.p, A.sav32.p, A.dinv32.p, b, x, s);
+  } else if (A.ell_w > 0) {
+    gs_colour_ell(A.coff[k], A.coff[k + 1], A.ell_w, A.lanes, A.rp.p, A.eci.p, A.eav32.p, A.dinv32.p, b, x, s);
   } else if (A.long_min > 0) {  // long rows first: a workgroup each, or one wavefront's chain
     if (chain)
       gs_colour<float>(A.coff[k], A.lend[k], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s, 64);

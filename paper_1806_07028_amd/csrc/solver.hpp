@@ -29,6 +29,10 @@ struct LevelMatrix {
   int32_t long_min = 0, nlong = 0;
   std::vector<int32_t> lend;
   DVec<int32_t> long_rows;
+  // padded-row FP32 copy for the FP32 passes of lane-group levels (ell_w = 0: none)
+  int32_t ell_w = 0;
+  DVec<int32_t> eci;
+  DVec<float> eav32;
 };
 
 // Gauss-Seidel pass over colour k and residual (b == nullptr: product) of a
