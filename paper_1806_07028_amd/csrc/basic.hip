@@ -920,7 +920,9 @@ __global__ void __launch_bounds__(256)
   const bool ok = i < row1;
   const int32_t ii = ok ? i : row0;  // a valid row for the loads of idle lanes
   const int q = (int)(threadIdx.x & (G - 1));
-  const int32_t len = ok ? rp[ii + 1] - rp[ii] : 0;
+  // unconditional loads (ii is a valid row), so that none waits in a branch
+  const int32_t p0 = rp[ii], p1 = rp[ii + 1];
+  const float bi = b[ii], di = dinv[ii];  // issued with the row's loads, not after its chain
   const size_t base = (size_t)ii * W;
   int32_t c[UT];
   float a[UT], v[UT];
@@ -932,6 +934,9 @@ __global__ void __launch_bounds__(256)
   }
 #pragma unroll
   for (int u = 0; u < UT; ++u) v[u] = x[c[u]];
+  // the chain up to the wavefront's longest row (the row pointers were
+  // loaded with the entries, so this waits on nothing new)
+  const int32_t len = ok ? p1 - p0 : 0;
   const int32_t span = wave_max_len(len);
   float s = 0.0f;
 #pragma unroll
@@ -956,7 +961,7 @@ __global__ void __launch_bounds__(256)
       }
     }
   }
-  if (ok && q == 0) x[i] = (b[i] - s) * dinv[i];
+  if (ok && q == 0) x[i] = (bi - s) * di;
 }
 
 int32_t ell_slots(int32_t W, int lanes) {
