@@ -13,7 +13,10 @@
 //    broadcast lane by lane (DPP quad moves for G = 4, shuffles otherwise), so
 //    the group holds the row sum in all its lanes.  Every lane of the
 //    wavefront must call it with uniform control flow, rows beyond the range
-//    with len = 0.
+//    with len = 0.  Loads past a row's end re-read its last entry (or, for an
+//    empty row, entry k0): they are unconditional, so a chunk's loads issue
+//    together instead of one masked load at a time, and never enter the
+//    chain.  The arrays need one readable slot at index nnz (a zero pad).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -145,20 +148,18 @@ __device__ __forceinline__ T row_chain_g(int32_t k0, int32_t len, PI ci, PA av, 
   constexpr int U = G == 4 ? 8 : 4;
   const int q = (int)(threadIdx.x & (G - 1));
   const int32_t span = wave_max_len(len);
+  const int32_t klast = len > 0 ? len - 1 : 0;
   for (int32_t base = 0; base < span; base += U * G) {
     T a[U], v[U];
     int32_t c[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int32_t kk = base + u * G + q;
-      c[u] = kk < len ? ci[k0 + kk] : 0;
-      a[u] = kk < len ? av[k0 + kk] : (T)0;
+      const int32_t kk = min(base + u * G + q, klast);
+      c[u] = ci[k0 + kk];
+      a[u] = av[k0 + kk];
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int32_t kk = base + u * G + q;
-      v[u] = kk < len ? x[c[u]] : (T)0;
-    }
+    for (int u = 0; u < U; ++u) v[u] = x[c[u]];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int32_t e = base + u * G;

@@ -120,9 +120,13 @@ std::shared_ptr<LevelMatrix> make_level_matrix(int32_t n, int32_t nnz, const int
     M->ncol = 1;
   }
   M->rp.resize(n + 1);
-  M->ci.resize(nnz);
-  M->av.resize(nnz);
-  M->av32.resize(nnz);
+  // one zero pad slot at nnz: the lane-group chains load past a row's end
+  M->ci.resize((size_t)nnz + 1);
+  M->av.resize((size_t)nnz + 1);
+  M->av32.resize((size_t)nnz + 1);
+  fill_i32(M->ci.p + nnz, 0, 1, s);
+  fill_f64(M->av.p + nnz, 0.0, 1, s);
+  fill_f32(M->av32.p + nnz, 0.0f, 1, s);
   M->d.resize(n);
   M->dinv.resize(n);
   M->d32.resize(n);
