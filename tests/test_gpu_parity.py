@@ -406,6 +406,32 @@ def test_edge_cases(gpu, oracle):
     assert st["iterations"] == 0 and float(x.abs().max()) == 0.0
 
 
+def test_edge_cases_default_settings(gpu, oracle):
+    """The library defaults (dense V and W operators, hub rows on workgroups,
+    autotuning off) on small and shallow hierarchies: one level, two levels,
+    a coarsest level right below the dense start, forced deep coarsening; the
+    solve reaches 1e-8 and agrees with the oracle's answer (to 1e-4: two
+    solutions at 1e-8 relative residual differ by up to the condition number
+    times that)."""
+    import paper_1806_07028_amd as P
+    cases = [(I.path(3), {}), (I.grid2d(9, 9), {}), (I.grid2d(40, 40), {}), (I.grid2d(12, 12), dict(coarse_max=2)),
+             (I.grid3d(14, 14, 14, weight_seed=2), dict(v_dense_max_n=100000)),
+             (GRAPHS["hub"](), {}), (I.config3(n0=8000)[0], {})]
+    for g, kw in cases:
+        n = g[0]
+        b = I.zero_mean_normal_rhs(2, n)
+        s = P.Solver(g[1], g[2], g[3], b, **kw)
+        x, st = s.solve()
+        assert st["status"] == 0 and st["true_relres"] <= 1.0001e-8, (n, kw, st["true_relres"])
+        for gamma in (1, 2):
+            s.cycle(b, None, gamma)
+            s.cycle32(b.astype(np.float32), None, gamma)
+        ref = oracle.solve(g, b, **{k: v for k, v in kw.items() if k == "coarse_max"})
+        xs = host(x)
+        assert np.linalg.norm(xs - ref.x) <= 1e-4 * np.linalg.norm(ref.x), (n, kw)
+        s.close()
+
+
 def test_errors(gpu):
     import paper_1806_07028_amd as P
 
