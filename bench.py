@@ -352,6 +352,8 @@ def learned_bench(args):
         gg = tuple(torch.as_tensor(a, device="cuda") for a in (g[1], g[2], g[3]))
         pairs.append((gg, L.start_vector(gg, 2), L.relaxed_target(gg, 20)))
         nsum += g[0]
+        if (k + 1) % 100 == 0:
+            log(f"  {k + 1} training graphs ({nsum} vertices)")
     net = L.Net(M.init_params(7))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
