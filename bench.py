@@ -45,7 +45,8 @@ def parse():
                     help="grid3d: the 128^3 weighted grid (the benchmark line); batch: uneven graphs solved "
                          "together (separate JSON line)")
     ap.add_argument("--count", type=int, default=512, help="batch: number of graphs")
-    ap.add_argument("--workers", type=int, default=4, help="batch: worker streams")
+    ap.add_argument("--workers", type=int, default=1, help="batch: worker threads and streams (1: the calling "
+                    "thread, the path the GPU tests cover)")
     ap.add_argument("--train-count", type=int, default=64, help="learned: training graphs")
     ap.add_argument("--epochs", type=int, default=10, help="learned: training epochs")
     ap.add_argument("--eval-n", type=int, default=1_000_000, help="learned: vertices of the evaluation graph")
