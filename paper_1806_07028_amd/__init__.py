@@ -169,9 +169,11 @@ class Solver:
         return e
 
 
-def batch_solve(graphs, rhs, x0=None, workers: int = 4, raise_on_error: bool = True, **params):
+def batch_solve(graphs, rhs, x0=None, workers: int = 1, raise_on_error: bool = True, **params):
     """Set up and solve many independent graphs (pcamg_batch_solve): graphs is a
     list of (row_ptr, col_idx, weight), rhs a list of right-hand sides.
+    workers = 1 (default) solves them one after another on the calling thread;
+    more workers run host threads with a stream each.
     Returns (list of solutions, list of statistics dicts)."""
     count = len(graphs)
     p = _params(params)
