@@ -310,7 +310,7 @@ def test_aggregation_cases(oracle):
 
 def test_path_graph_pairs_and_triple(oracle):
     """A path graph with a linear smooth error is covered by one path: pairs plus
-    a final triple when the length is odd (sizes 2 or 3)."""
+    a final triple when the length is odd (Sec. 3.3: sizes 2 or 3 along a path)."""
     for n in (10, 11):
         g = I.path(n)
         e = np.arange(n, dtype=float)
