@@ -337,7 +337,9 @@ pcamg_status pcamg_a2_fill(int32_t n, const int32_t* rp, const int32_t* ci, int3
 
 /* Undirected edges (i < j) of a symmetric pattern sorted by (|e_i - e_j|
  * ascending, lexicographic edge index ascending) = heaviest reweighted edge
- * first (Alg. 4 Step 2, Alg. 1 Step 3).  su, sv: device int32 [nnz2/2]. */
+ * first (Alg. 4 Step 2, Alg. 1 Step 3).  The pattern's rows are sorted by
+ * column with no diagonal (as pcamg_a2_fill gives them).  su, sv: device
+ * int32 [nnz2/2]. */
 pcamg_status pcamg_sort_edges(int32_t n, const int32_t* rp2, const int32_t* ci2, const double* e, int32_t* su,
                               int32_t* sv, void* stream);
 

@@ -263,34 +263,50 @@ void a2_fill(int32_t n, const int32_t* rp, const int32_t* ci, int32_t cap, const
 // the pattern; the undirected edges (i < j) in lexicographic order get the
 // key bits for sorting (non-negative doubles sort like their bit patterns).
 // ---------------------------------------------------------------------------
+// The A^2 pattern has no diagonal and its rows are sorted by column, so the
+// entries j > i of row i are the suffix from its first column above i.
+__device__ __forceinline__ int32_t first_upper(int32_t i, int32_t lo, int32_t hi, const int32_t* __restrict__ ci2) {
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (ci2[mid] > i) hi = mid;
+    else lo = mid + 1;
+  }
+  return lo;
+}
+
 __global__ void upper_count_kernel(int32_t n, const int32_t* __restrict__ rp2, const int32_t* __restrict__ ci2,
                                    int32_t* __restrict__ ucnt) {
   int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  int32_t c = 0;
-  for (int32_t k = rp2[i]; k < rp2[i + 1]; ++k) c += ci2[k] > i;
-  ucnt[i] = c;
+  const int32_t k1 = rp2[i + 1];
+  ucnt[i] = k1 - first_upper(i, rp2[i], k1, ci2);
 }
 
-__global__ void keys_kernel(int32_t n, const int32_t* __restrict__ rp2, const int32_t* __restrict__ ci2,
-                            const double* __restrict__ e, const uint64_t* __restrict__ maxbits,
-                            const int32_t* __restrict__ uoff, double* __restrict__ gkey, double* __restrict__ gv,
-                            int32_t* __restrict__ eu, int32_t* __restrict__ ev, uint64_t* __restrict__ ekey) {
-  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+// One wavefront per row: keys and weights of every entry, and the upper
+// entries (j > i) as undirected edges in row-major order.
+__global__ void __launch_bounds__(256)
+    keys_kernel(int32_t n, const int32_t* __restrict__ rp2, const int32_t* __restrict__ ci2,
+                const double* __restrict__ e, const uint64_t* __restrict__ maxbits, const int32_t* __restrict__ uoff,
+                double* __restrict__ gkey, double* __restrict__ gv, int32_t* __restrict__ eu,
+                int32_t* __restrict__ ev, uint64_t* __restrict__ ekey) {
+  const int32_t i = (int32_t)(((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);  // uniform per wavefront
   if (i >= n) return;
+  const int lane = (int)(threadIdx.x & 63);
   const double tau = 0x1.0p-52 * __longlong_as_double((long long)*maxbits);
   const double ei = e[i];
-  int32_t u = uoff[i];
-  for (int32_t k = rp2[i]; k < rp2[i + 1]; ++k) {
-    int32_t j = ci2[k];
-    double key = fabs(ei - e[j]);
+  const int32_t k0 = rp2[i], k1 = rp2[i + 1];
+  const int32_t fu = first_upper(i, k0, k1, ci2);
+  const int32_t ubase = uoff[i];
+  for (int32_t k = k0 + lane; k < k1; k += 64) {
+    const int32_t j = ci2[k];
+    const double key = fabs(ei - e[j]);
     gkey[k] = key;
     gv[k] = 1.0 / fmax(key, tau);
-    if (j > i) {
+    if (k >= fu) {
+      const int32_t u = ubase + (k - fu);
       eu[u] = i;
       ev[u] = j;
       ekey[u] = (uint64_t)__double_as_longlong(key);
-      ++u;
     }
   }
 }
@@ -307,7 +323,7 @@ int32_t a2_keys(int32_t n, const int32_t* rp2, const int32_t* ci2, const double*
   upper_count_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, rp2, ci2, ucnt.p);
   PCAMG_LAUNCHED();
   scan_exclusive_i32(ucnt.p, uoff.p, n, tot.p, s);
-  keys_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, rp2, ci2, e, mx.p, uoff.p, gkey, gv, eu, ev, ekey);
+  keys_kernel<<<grid_for((size_t)n * 64, 256), 256, 0, s>>>(n, rp2, ci2, e, mx.p, uoff.p, gkey, gv, eu, ev, ekey);
   PCAMG_LAUNCHED();
   return read_scalar(tot.p, s);
 }
