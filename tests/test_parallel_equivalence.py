@@ -239,3 +239,58 @@ def test_reservation_repair_equals_sequential(oracle, seed):
         for window in (1, 5, 10 ** 6):
             got = reservation_repair(len(nb), grp, gci, gw, gkey, obj, members, window)
             assert np.array_equal(got, ref)
+
+
+def rounds_with_chunks(n, rp, ci, key, R, chunk):
+    """Jones-Plassmann rounds in batches of R; when a batch colours fewer than
+    4R vertices, the top `chunk` pending vertices (by (key, id)) are coloured
+    one at a time in descending order, first-fit over the coloured
+    neighbours, and the rounds go on with the rest."""
+    higher = lambda u, v: (key[u], u) > (key[v], v)
+    colour = -np.ones(n, int)
+    pending = list(range(n))
+    chunks = 0
+    while pending:
+        before = len(pending)
+        for _ in range(R):
+            ready = [v for v in pending
+                     if all(colour[u] >= 0 for u in ci[rp[v]:rp[v + 1]] if higher(u, v))]
+            for v in ready:
+                used = {colour[u] for u in ci[rp[v]:rp[v + 1]] if higher(u, v)}
+                colour[v] = next(c for c in range(n + 1) if c not in used)
+            pending = [v for v in pending if colour[v] < 0]
+        if pending and before - len(pending) < 4 * R:
+            top = sorted(pending, key=lambda v: (key[v], v), reverse=True)
+            k = len(top) if len(top) <= 2 * chunk else chunk
+            chunks += 1
+            for v in top[:k]:  # the coloured neighbours are exactly the higher ones
+                used = {colour[u] for u in ci[rp[v]:rp[v + 1]] if colour[u] >= 0}
+                colour[v] = next(c for c in range(n + 1) if c not in used)
+            pending = [v for v in pending if colour[v] < 0]
+    return colour, chunks
+
+
+@pytest.mark.parametrize("case", ["powerlaw", "clique"])
+def test_rounds_with_sequential_chunks_equal_greedy(oracle, case):
+    """The colouring schedule of the library (rounds, stalls taken one vertex
+    at a time in chunks of the top pending) gives the greedy first-fit in
+    priority order: checked against the oracle on graphs that stall."""
+    if case == "powerlaw":
+        n, rp, ci, w = I.config3(n0=1500)[0]
+    else:  # a clique of 60 that every other vertex waits on, plus a ring
+        n = 400
+        a, b = np.triu_indices(60, 1)
+        a = np.concatenate([a, np.arange(n), np.arange(60, n)])
+        b = np.concatenate([b, (np.arange(n) + 1) % n, np.arange(60, n) % 60])
+        keep = a != b
+        a2, b2 = I.canonical_edges(a[keep], b[keep])
+        n, rp, ci, w = I.csr_from_edges(n, a2, b2, np.ones(len(a2)))
+    deg = np.diff(rp)
+    key = [oracle.colour_key(0xC010, 1, v, int(deg[v])) for v in range(n)]
+    ref, _ = oracle.colour_greedy(n, rp, ci, 0xC010, 1)
+    stalls = 0
+    for R, chunk in ((2, 8), (8, 32)):
+        got, c = rounds_with_chunks(n, rp, ci, key, R, chunk)
+        assert np.array_equal(got, ref), (R, chunk)
+        stalls += c
+    assert stalls > 0  # the one-at-a-time chunks were taken
