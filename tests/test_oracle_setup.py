@@ -447,3 +447,88 @@ def test_shorten_first_occurrence(oracle):
     agg = np.array([0, 0, 1, 0, 2], np.int32)
     nbc = oracle.shorten(nb, 3, agg)
     assert cover_edges(nbc) == {(0, 1)}
+
+
+# ---------------------------------------------------------------------------
+# Smooth error before a build (Sec. 3.2), level loop and operator complexity
+# (Alg. 4 Steps 4-9)
+# ---------------------------------------------------------------------------
+def xi_ref(seed, r, n):
+    """U[-1, 1) start vector of build r: word (r << 32) + i + 1 of the stream."""
+    k = (np.uint64(r) << np.uint64(32)) + np.arange(1, n + 1, dtype=np.uint64)
+    return 2.0 * I.uniform_at(seed, k) - 1.0
+
+
+def relax_ref(g, colour, e, sweeps):
+    """Symmetric Gauss-Seidel on A e = 0 in colour order, written independently:
+    the rows of one colour share no edge, so a colour's update is one sparse
+    product with the values the earlier colours have just written."""
+    n, rp, ci, w = g
+    W = sp.csr_matrix((w, ci, rp), shape=(n, n))
+    d = np.asarray(W.sum(1)).ravel()
+    ncol = int(colour.max()) + 1
+    rows = [np.flatnonzero(colour == c) for c in range(ncol)]
+    e = e.copy()
+    for _ in range(sweeps):
+        for c in list(range(ncol)) + list(range(ncol - 1, -1, -1)):
+            r = rows[c]
+            e[r] = (W[r] @ e) / d[r]  # (0 - sum_j a_ij e_j) / a_ii with a_ij = -w_ij
+    return e
+
+
+@pytest.mark.parametrize("maker", [lambda: I.grid2d(21, 17, weight_seed=4),
+                                   lambda: I.rgg(900, 12),
+                                   lambda: I.config3(n0=3000)[0]])
+def test_first_build_error_is_relaxed_xi(oracle, maker):
+    g = maker()
+    n, rp, ci, w = g
+    H = oracle.Hierarchy(g, None, coarse_max=8, rebuild_vcycles=0)
+    colour = H.get_int(0, "colour")
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    assert (colour[rows] != colour[ci]).all(), "colour classes must be independent sets"
+    p = H.p
+    x0 = xi_ref(p.seed, 0, n)
+    assert np.array_equal(oracle.xi(n, p.seed, 0), x0)
+    ref = relax_ref(g, colour, x0, p.relax_sweeps)
+    got = H.get_dbl(0, "e")
+    assert np.linalg.norm(got - ref) <= 1e-13 * np.linalg.norm(ref)
+    # the relaxation lowers the energy e^T A e (it smooths)
+    L = dense_laplacian(g)
+    assert got @ L @ got < 0.5 * (x0 @ L @ x0)
+    # a re-setup's vector: fresh xi of build r, the hierarchy's V-cycles on
+    # A e = 0, then the same sweeps
+    for r in (1, 3):
+        xr = xi_ref(p.seed, r, n)
+        assert not np.array_equal(xr, x0)
+        got_r = H.relax_error(r)
+        ref_r = relax_ref(g, colour, xr, p.relax_sweeps)
+        assert np.linalg.norm(got_r - ref_r) <= 1e-13 * np.linalg.norm(ref_r)
+    H2 = oracle.Hierarchy(g, None, coarse_max=8, rebuild_vcycles=2)
+    xr = xi_ref(p.seed, 2, n)
+    v = H2.vcycle(np.zeros(n), xr)
+    v = H2.vcycle(np.zeros(n), v)
+    ref_r = relax_ref(g, colour, v, p.relax_sweeps)
+    got_r = H2.relax_error(2)
+    assert np.linalg.norm(got_r - ref_r) <= 1e-12 * np.linalg.norm(ref_r)
+
+
+@pytest.mark.parametrize("maker,cmax", [(lambda: I.grid2d(40, 37, weight_seed=6), 64),
+                                        (lambda: I.grid3d(11, 10, 9, weight_seed=3), 8),
+                                        (lambda: I.config3(n0=4000)[0], 64)])
+def test_level_loop_and_operator_complexity(oracle, maker, cmax):
+    g = maker()
+    H = oracle.Hierarchy(g, None, coarse_max=cmax)
+    L = H.nlevels
+    inf = [H.info(l) for l in range(L)]
+    assert inf[0]["n"] == g[0] and inf[0]["nnz"] == len(g[2])
+    for l in range(L - 1):
+        assert inf[l]["n"] > cmax  # coarsening continues above the limit
+        assert inf[l + 1]["n"] == inf[l]["nc"]
+        # connected levels: no singleton, every aggregate holds two or more
+        assert inf[l]["singleton"] == 0 and 2 * inf[l]["nc"] <= inf[l]["n"]
+    assert inf[-1]["n"] <= cmax or inf[-1]["coarse_fallback"]
+    # operator complexity: stored entries of all levels (diagonal included)
+    # over those of the finest operator
+    tot = sum(i["nnz"] + i["n"] for i in inf)
+    assert H.op_complexity == pytest.approx(tot / (inf[0]["nnz"] + inf[0]["n"]), rel=1e-15)
+    assert H.op_complexity > 1.0
