@@ -299,7 +299,10 @@ pcamg_status pcamg_setup_learned(const pcamg_graph* g, const double* rhs, const 
 
 /* ------------------------------------------------------------------------
  * Stage entry points: single steps of the method on caller arrays (device
- * unless stated).  Used for parity tests and benchmarks.
+ * unless stated).  Used for parity tests and benchmarks.  Arrays indexed by
+ * stored entry (ci, w, aval, gci, gw, ci2, cic, vc) may be NULL only when
+ * their pattern has no stored entries (rp[n] = 0, read from the device when
+ * one of them is NULL); any other NULL gives PCAMG_EINVAL before a launch.
  * ------------------------------------------------------------------------ */
 
 /* Laplacian (Sec. 2.2): aval[nnz] = -w, d[n] = row sums in CSR order, dinv = 1/d. */

@@ -4,6 +4,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <initializer_list>
 #include <thread>
 #include <vector>
 
@@ -156,6 +157,16 @@ void validate_rhs(const double* b, int32_t n, hipStream_t s) {
   auto h = to_host(sums.p, 2, s);
   require(std::isfinite(h[0]) && std::isfinite(h[1]), PCAMG_ERHS, "rhs not finite");
   require(std::fabs(h[0]) <= 1e-12 * h[1], PCAMG_ERHS, "rhs does not sum to zero (graph Laplacians are singular)");
+}
+
+// Arrays indexed by stored entry may be null only for a pattern with no
+// stored entries: the count rp[n] is read from the device when one is null.
+void require_entries(int32_t n, const int32_t* rp, std::initializer_list<const void*> arrays, hipStream_t s) {
+  bool all = true;
+  for (const void* a : arrays) all = all && a != nullptr;
+  if (all) return;
+  const int32_t nnz = n > 0 ? read_scalar(rp + n, s) : 0;
+  require(nnz == 0, PCAMG_EINVAL, "null entry array for a pattern with stored entries");
 }
 
 Hierarchy& hier(pcamg_ctx* c, int32_t h) {
@@ -582,6 +593,7 @@ pcamg_status pcamg_laplacian(int32_t n, const int32_t* rp, const int32_t* ci, co
                              double* d, double* dinv, void* stream) {
   return guarded_s(as_stream(stream), [&] {
     require(n >= 0 && rp && d && dinv, PCAMG_EINVAL, "null argument");
+    require_entries(n, rp, {w, aval}, as_stream(stream));
     laplacian(n, rp, w, aval, d, dinv, 0, as_stream(stream));
     PCAMG_HIP(hipStreamSynchronize(as_stream(stream)));
   });
@@ -591,6 +603,7 @@ pcamg_status pcamg_colour(int32_t n, const int32_t* rp, const int32_t* ci, uint6
                           int32_t* colour, int32_t* ncolours, void* stream) {
   return guarded_s(as_stream(stream), [&] {
     require(n >= 0 && rp && colour && ncolours, PCAMG_EINVAL, "null argument");
+    require_entries(n, rp, {ci}, as_stream(stream));
     *ncolours = colour_level(n, rp, ci, seed, level, colour, as_stream(stream));
   });
 }
@@ -599,8 +612,9 @@ pcamg_status pcamg_gs(int32_t n, const int32_t* rp, const int32_t* ci, const dou
                       const int32_t* colour, int32_t ncolours, const double* b, double* x, int32_t forward,
                       int32_t count, void* stream) {
   return guarded_s(as_stream(stream), [&] {
-    require(n > 0 && rp && colour && b && x && ncolours >= 1, PCAMG_EINVAL, "bad argument");
+    require(n > 0 && rp && dinv && colour && b && x && ncolours >= 1, PCAMG_EINVAL, "bad argument");
     hipStream_t s = as_stream(stream);
+    require_entries(n, rp, {ci, aval}, s);
     DVec<int32_t> perm(n), iperm(n);
     std::vector<int32_t> coff;
     build_perm(n, colour, ncolours, perm.p, iperm.p, coff, s);
@@ -618,6 +632,7 @@ pcamg_status pcamg_residual(int32_t n, const int32_t* rp, const int32_t* ci, con
                             const double* b, const double* x, double* r, void* stream) {
   return guarded_s(as_stream(stream), [&] {
     require(n >= 0 && rp && d && b && x && r, PCAMG_EINVAL, "null argument");
+    require_entries(n, rp, {ci, aval}, as_stream(stream));
     residual<double>(n, rp, ci, aval, d, b, x, r, as_stream(stream));
     PCAMG_HIP(hipStreamSynchronize(as_stream(stream)));
   });
@@ -627,6 +642,7 @@ pcamg_status pcamg_a2_count(int32_t n, const int32_t* rp, const int32_t* ci, int
                             int64_t* nnz2, void* stream) {
   return guarded_s(as_stream(stream), [&] {
     require(n > 0 && rp && rp2 && nnz2 && hub_cap >= 0, PCAMG_EINVAL, "bad argument");
+    require_entries(n, rp, {ci}, as_stream(stream));
     *nnz2 = a2_count(n, rp, ci, hub_cap, rp2, as_stream(stream));
   });
 }
@@ -634,7 +650,9 @@ pcamg_status pcamg_a2_count(int32_t n, const int32_t* rp, const int32_t* ci, int
 pcamg_status pcamg_a2_fill(int32_t n, const int32_t* rp, const int32_t* ci, int32_t hub_cap, const int32_t* rp2,
                            int32_t* ci2, void* stream) {
   return guarded_s(as_stream(stream), [&] {
-    require(n > 0 && rp && rp2 && ci2, PCAMG_EINVAL, "null argument");
+    require(n > 0 && rp && rp2, PCAMG_EINVAL, "null argument");
+    require_entries(n, rp, {ci}, as_stream(stream));
+    require_entries(n, rp2, {ci2}, as_stream(stream));
     a2_fill(n, rp, ci, hub_cap, rp2, ci2, as_stream(stream));
     PCAMG_HIP(hipStreamSynchronize(as_stream(stream)));
   });
@@ -681,8 +699,9 @@ pcamg_status pcamg_aggregate(int32_t n, const int32_t* grp, const int32_t* gci, 
                              const double* gkey, const int32_t* nb, int32_t* agg, int32_t* nc, int32_t* stats,
                              void* stream) {
   return guarded_s(as_stream(stream), [&] {
-    require(n > 0 && grp && gw && nb && agg && nc, PCAMG_EINVAL, "null argument");
+    require(n > 0 && grp && nb && agg && nc, PCAMG_EINVAL, "null argument");
     hipStream_t s = as_stream(stream);
+    require_entries(n, grp, {gci, gw}, s);
     DVec<int32_t> pid(n), pos(n), plen(n), moff(n + 1), mem(n);
     orient_paths(n, nb, pid.p, pos.p, plen.p, s);
     AggStats st;
@@ -717,6 +736,7 @@ pcamg_status pcamg_galerkin_count(int32_t n, const int32_t* rp, const int32_t* c
   return guarded_s(as_stream(stream), [&] {
     require(n > 0 && nc > 0 && rp && agg && rpc && nnzc, PCAMG_EINVAL, "bad argument");
     hipStream_t s = as_stream(stream);
+    require_entries(n, rp, {ci}, s);
     DVec<int32_t> moff, mem;
     members_from_agg(n, nc, agg, moff, mem, s);
     *nnzc = galerkin_count(n, rp, ci, nc, moff.p, mem.p, agg, rpc, false, s);
@@ -729,6 +749,8 @@ pcamg_status pcamg_galerkin_fill(int32_t n, const int32_t* rp, const int32_t* ci
   return guarded_s(as_stream(stream), [&] {
     require(n > 0 && nc > 0 && rp && d && agg && rpc && dc, PCAMG_EINVAL, "bad argument");
     hipStream_t s = as_stream(stream);
+    require_entries(n, rp, {ci, aval}, s);
+    require_entries(nc, rpc, {cic, vc}, s);
     DVec<int32_t> moff, mem;
     members_from_agg(n, nc, agg, moff, mem, s);
     DVec<double> dinvc(nc);

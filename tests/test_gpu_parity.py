@@ -9,6 +9,8 @@ Bars (written per assertion):
  * quantities that pass through global reductions (Alg. 2 PCG steps, norms,
    means, the adaptive loop): relative 1e-12 per vector, iteration counts equal.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -463,6 +465,42 @@ def test_errors(gpu):
     s = P.Solver(g[1], g[2], g[3], b, max_iter=2, theta=1e9)
     x, st = s.solve(raise_on_noconv=False)
     assert st["status"] == -10 and st["iterations"] == 2
+
+
+def test_stage_null_entry_arrays(gpu):
+    """Stage entry points refuse a null array indexed by stored entry when the
+    pattern has entries (checked on the host before any launch), and accept
+    one for a pattern without entries."""
+    import torch
+
+    from paper_1806_07028_amd import stages as S
+    from paper_1806_07028_amd._lib import lib
+
+    n, rp, ci, w = I.grid2d(5, 4)
+    st = torch.cuda.current_stream().cuda_stream
+    rpd = torch.as_tensor(rp, dtype=torch.int32, device="cuda")
+    cid = torch.as_tensor(ci, dtype=torch.int32, device="cuda")
+    wd = torch.as_tensor(w, dtype=torch.float64, device="cuda")
+    out = torch.empty(len(ci) + 2 * n, dtype=torch.float64, device="cuda")
+    a_p, d_p, dinv_p = out.data_ptr(), out.data_ptr() + 8 * len(ci), out.data_ptr() + 8 * (len(ci) + n)
+    assert lib().pcamg_laplacian(n, rpd.data_ptr(), cid.data_ptr(), None, a_p, d_p, dinv_p, st) == -1
+    assert lib().pcamg_laplacian(n, rpd.data_ptr(), cid.data_ptr(), wd.data_ptr(), None, d_p, dinv_p, st) == -1
+    col = torch.zeros(n, dtype=torch.int32, device="cuda")
+    nc = ctypes.c_int32()
+    assert lib().pcamg_colour(n, rpd.data_ptr(), None, 7, 0, col.data_ptr(), ctypes.byref(nc), st) == -1
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    assert lib().pcamg_gs(n, rpd.data_ptr(), cid.data_ptr(), a_p, None, col.data_ptr(), 1, x.data_ptr(),
+                          x.data_ptr(), 1, 1, st) == -1
+    assert lib().pcamg_residual(n, rpd.data_ptr(), None, a_p, d_p, x.data_ptr(), x.data_ptr(), x.data_ptr(),
+                                st) == -1
+    # the library still works after the refusals
+    a, d, dinv = S.laplacian(rp, ci, w)
+    assert np.array_equal(host(a), -w)
+    # no stored entries: null entry arrays are fine
+    rp0 = torch.zeros(4, dtype=torch.int32, device="cuda")
+    d0 = torch.empty(6, dtype=torch.float64, device="cuda")
+    assert lib().pcamg_laplacian(3, rp0.data_ptr(), None, None, None, d0.data_ptr(), d0.data_ptr() + 24, st) == 0
+    assert (host(d0[:3]) == 0.0).all()
 
 
 @pytest.mark.parametrize("gname", ["grid3d_20", "grid2d_128"])
