@@ -429,8 +429,8 @@ int32_t path_cover(int32_t n, int32_t m, const int32_t* su, const int32_t* sv, i
   DVec<uint8_t> state(WIN);
   int32_t ns = 0, next = 0, rounds = 0;
   while (ns > 0 || next < m) {
+    // the survivors of the last round are already at the front of win
     const int32_t take = std::min<int32_t>(WIN - ns, m - next);
-    if (ns) copy_d2d(win.p, surv.p, ns, s);
     if (take > 0) {
       window_kernel<<<grid_for(take, 256), 256, 0, s>>>(ns, next, take, win.p);
       PCAMG_LAUNCHED();
@@ -446,6 +446,7 @@ int32_t path_cover(int32_t n, int32_t m, const int32_t* su, const int32_t* sv, i
     PCAMG_LAUNCHED();
     compact_i32(win.p, state.p, surv.p, cnt.p, w, s);
     ns = read_scalar(cnt.p, s);
+    std::swap(win, surv);  // survivors first in the next window
     ++rounds;
     require(rounds <= 4 * m + 8, PCAMG_EHIP, "path cover did not terminate");
   }
@@ -789,8 +790,8 @@ int32_t aggregate_level(int32_t n, const int32_t* grp, const int32_t* gci, const
     DVec<uint8_t> state(WIN);
     int32_t ns = 0, next = 0, rounds = 0;
     while (ns > 0 || next < npend) {
+      // the survivors of the last round are already at the front of win
       const int32_t take = std::min<int32_t>(WIN - ns, npend - next);
-      if (ns) copy_d2d(win.p, surv.p, ns, s);
       if (take > 0) copy_d2d(win.p + ns, pend.p + next, take, s);
       const int32_t w = ns + take;
       next += take;
@@ -803,6 +804,7 @@ int32_t aggregate_level(int32_t n, const int32_t* grp, const int32_t* gci, const
       PCAMG_LAUNCHED();
       compact_i32(win.p, state.p, surv.p, cnt.p, w, s);
       ns = read_scalar(cnt.p, s);
+      std::swap(win, surv);  // survivors first in the next window
       ++rounds;
       require(rounds <= 4 * npend + 8, PCAMG_EHIP, "isolated-vertex repair did not terminate");
     }

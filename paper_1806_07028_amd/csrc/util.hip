@@ -202,13 +202,14 @@ static void scan_exclusive_t(const TI* in, TO* out, size_t n, TO* total, hipStre
     return;
   }
   const size_t ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+  if (ntiles == 1) {  // the one tile's sum is the total
+    scan_tiles_kernel<TI, TO><<<1, SCAN_BLOCK, 0, s>>>(in, out, total, n);
+    PCAMG_LAUNCHED();
+    return;
+  }
   DVec<TO> sums(ntiles), offs(ntiles);
   scan_tiles_kernel<TI, TO><<<(unsigned)ntiles, SCAN_BLOCK, 0, s>>>(in, out, sums.p, n);
   PCAMG_LAUNCHED();
-  if (ntiles == 1) {
-    if (total) copy_d2d(total, sums.p, 1, s);
-    return;
-  }
   scan_exclusive_t<TO, TO>(sums.p, offs.p, ntiles, (TO*)nullptr, s);
   add_tile_offsets_kernel<TO><<<(unsigned)ntiles, SCAN_BLOCK, 0, s>>>(out, offs.p, n);
   PCAMG_LAUNCHED();
