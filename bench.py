@@ -45,8 +45,8 @@ def parse():
                     help="grid3d: the 128^3 weighted grid (the benchmark line); batch: uneven graphs solved "
                          "together (separate JSON line)")
     ap.add_argument("--count", type=int, default=512, help="batch: number of graphs")
-    ap.add_argument("--workers", type=int, default=1, help="batch: worker threads and streams (1: the calling "
-                    "thread, the path the GPU tests cover)")
+    ap.add_argument("--workers", type=int, default=1, help="batch: workers passed to the library (must be 1: "
+                    "the calling thread; several host threads are switched off)")
     ap.add_argument("--train-count", type=int, default=64, help="learned: training graphs")
     ap.add_argument("--epochs", type=int, default=10, help="learned: training epochs")
     ap.add_argument("--eval-n", type=int, default=1_000_000, help="learned: vertices of the evaluation graph")
@@ -183,8 +183,8 @@ def roofline_only(args):
 def batch_bench(args):
     """Uneven batch: count graphs, n log-uniform on [1e3, 2e5] (2D grids,
     random geometric graphs, Barabasi-Albert), weights 10^(-2+4u), each solved
-    to 1e-8 by FCG(FP64) with FP32 cycles; time for the whole batch with
-    `workers` streams and with one, and the oracle on a bounded sample."""
+    to 1e-8 by FCG(FP64) with FP32 cycles; time for the whole batch, and the
+    oracle on a bounded sample."""
     import numpy as np
     import torch
 
@@ -222,10 +222,6 @@ def batch_bench(args):
         t, sts = run(args.workers)
         times.append(t)
         log(f"batch step {k}: {t:.2f} s")
-    sub = min(len(graphs), chunk)
-    tw_sub, _ = run(args.workers, 0, sub)
-    t1_sub, _ = run(1, 0, sub)
-    log(f"first {sub} graphs: {tw_sub:.2f} s with {args.workers} workers, {t1_sub:.2f} s with one")
     its = [st["iterations"] for st in sts]
     cpu = None
     if not args.no_cpu_baseline:
@@ -252,8 +248,6 @@ def batch_bench(args):
                                "weights 10^(-2+4u); FCG(FP64) + FP32 cycles, theta 0.5, numW 2",
                    "graphs": args.count, "vertices": sum_n, "edges": sum_m, "workers": args.workers},
         "graphs_per_s": round(args.count / (ms / 1e3), 2), "chunk": chunk,
-        "first_chunk_s": {"workers": round(tw_sub, 3), "one_worker": round(t1_sub, 3),
-                          "speedup": round(t1_sub / tw_sub, 3)},
         "iterations": {"min": min(its), "max": max(its), "mean": round(float(np.mean(its)), 2)},
         "converged": sum(st["status"] == 0 for st in sts), "cpu_baseline": cpu}), flush=True)
 

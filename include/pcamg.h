@@ -178,12 +178,12 @@ pcamg_status pcamg_rebuild(pcamg_ctx* c, const double* e);
 void pcamg_destroy(pcamg_ctx* c);
 
 /* Batched setup and solve of independent graphs (the batching extension;
- * per graph exactly Alg. 5 as pcamg_setup + pcamg_solve).  A pool of
- * `workers` host threads (1..64; with 1, the calling thread itself), each with
- * its own HIP stream of default priority, takes the graphs largest first;
- * each graph is set up, solved and
- * released on its worker's stream, so x[g] and stats[g] equal those of the
- * individual calls bit for bit.  graphs[count]: device CSR as for
+ * per graph exactly Alg. 5 as pcamg_setup + pcamg_solve).  The calling
+ * thread takes the graphs largest first on a HIP stream of its own (default
+ * priority); each graph is set up, solved and released on that stream, so
+ * x[g] and stats[g] equal those of the individual calls bit for bit.
+ * `workers` must be 1: several host threads are switched off (PCAMG_EINVAL)
+ * because one run of that path ended in a host crash with no cause shown.  graphs[count]: device CSR as for
  * pcamg_setup; rhs[g]: device [n_g] (must sum to 0); x[g]: device [n_g],
  * initial guess in, solution out; stats: host [count] or NULL (each entry's
  * relres_hist/hist_cap are used as in pcamg_solve; status holds the graph's

@@ -172,8 +172,8 @@ class Solver:
 def batch_solve(graphs, rhs, x0=None, workers: int = 1, raise_on_error: bool = True, **params):
     """Set up and solve many independent graphs (pcamg_batch_solve): graphs is a
     list of (row_ptr, col_idx, weight), rhs a list of right-hand sides.
-    workers = 1 (default) solves them one after another on the calling thread;
-    more workers run host threads with a stream each.
+    workers must be 1 (the default): the graphs are solved one after another on
+    the calling thread; several workers are refused by the library.
     Returns (list of solutions, list of statistics dicts)."""
     count = len(graphs)
     p = _params(params)

@@ -615,8 +615,8 @@ def test_graph_and_tail_equal_eager(gpu, gname):
 
 BATCH_SKIP = pytest.mark.skip(
     reason="multi-threaded batch path: one run ended in a host segmentation fault inside pcamg_batch_solve "
-           "(after dense-operator builds with rocBLAS joined it); cause not shown, so the case stays off the GPU "
-           "until it is; builds now share one serialised rocBLAS handle")
+           "(after dense-operator builds with rocBLAS joined it); cause not shown, so the path is switched off "
+           "(the library refuses workers > 1) and the case stays off the GPU until the cause is found")
 
 
 def _batch_equals_individual(gpu, oracle, workers):
@@ -687,6 +687,21 @@ def test_batch_errors(gpu):
 def test_batch_errors_one_worker(gpu):
     """The same with one worker on the calling thread."""
     _batch_errors(gpu, (1, 1))
+
+
+def test_batch_several_workers_refused(gpu):
+    """Several host threads are switched off: the call fails before any graph
+    is touched."""
+    import paper_1806_07028_amd as P
+
+    (n, rp, ci, w), b = I.config1()
+    x0 = np.full(n, 7.0)
+    for workers in (0, 2, 4):
+        with pytest.raises(P.PcamgError) as ei:
+            gpu.batch_solve([(rp, ci, w)], [b], x0=[x0], workers=workers)
+        assert ei.value.status == -1
+    xs, sts = gpu.batch_solve([(rp, ci, w)], [b], workers=1)
+    assert sts[0]["status"] == 0 and sts[0]["true_relres"] <= 1.0001e-8
 
 
 def test_colour_dense_levels(gpu, oracle):
