@@ -1,7 +1,6 @@
 // C ABI of the library (declared in include/pcamg.h).  Every entry point
 // catches exceptions and returns a status; the message is kept per thread.
 #include <algorithm>
-#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <initializer_list>
@@ -415,55 +414,36 @@ pcamg_status pcamg_batch_solve(const pcamg_graph* graphs, const double* const* r
             "batch workers must be 1 (several host threads are switched off: a host crash there is unexplained)");
     if (count == 0) return;
     require(graphs && rhs && x, PCAMG_EINVAL, "null argument");
-    int dev = 0;
-    PCAMG_HIP(hipGetDevice(&dev));
     std::vector<int32_t> order(count);
     for (int32_t g = 0; g < count; ++g) order[g] = g;
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
       return (int64_t)graphs[a].nnz + graphs[a].n > (int64_t)graphs[b].nnz + graphs[b].n;
     });
-    std::atomic<int32_t> next{0};
     std::vector<pcamg_status> status(count, PCAMG_OK);
     std::vector<std::string> msg(count);
-    auto worker = [&]() {
-      hipStream_t s = nullptr;
-      if (hipSetDevice(dev) != hipSuccess || hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
-        (void)hipGetLastError();
-        s = nullptr;
+    hipStream_t s = nullptr;
+    PCAMG_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    for (const int32_t g : order) {  // the graphs one after another on the calling thread
+      pcamg_ctx* c = nullptr;
+      pcamg_status r = pcamg_setup(&graphs[g], rhs[g], p, s, &c);
+      pcamg_stats local{};
+      pcamg_stats* so = stats ? &stats[g] : &local;
+      if (r == PCAMG_OK) {
+        r = pcamg_solve(c, x[g], so);
+      } else if (stats) {
+        pcamg_stats keep = stats[g];
+        std::memset(so, 0, sizeof(*so));
+        so->relres_hist = keep.relres_hist;
+        so->hist_cap = keep.hist_cap;
       }
-      for (;;) {
-        const int32_t k = next.fetch_add(1);
-        if (k >= count) break;
-        const int32_t g = order[k];
-        if (!s) {
-          status[g] = PCAMG_EHIP;
-          msg[g] = "could not create a stream";
-          continue;
-        }
-        pcamg_ctx* c = nullptr;
-        pcamg_status r = pcamg_setup(&graphs[g], rhs[g], p, s, &c);
-        pcamg_stats local{};
-        pcamg_stats* so = stats ? &stats[g] : &local;
-        if (r == PCAMG_OK) {
-          r = pcamg_solve(c, x[g], so);
-        } else if (stats) {
-          pcamg_stats keep = stats[g];
-          std::memset(so, 0, sizeof(*so));
-          so->relres_hist = keep.relres_hist;
-          so->hist_cap = keep.hist_cap;
-        }
-        so->status = r;
-        if (r != PCAMG_OK) msg[g] = pcamg_last_error();
-        status[g] = r;
-        pcamg_destroy(c);
-      }
-      if (s) {
-        (void)hipStreamSynchronize(s);
-        dev_cache_idle(s);
-        (void)hipStreamDestroy(s);
-      }
-    };
-    worker();  // the graphs one after another on the calling thread
+      so->status = r;
+      if (r != PCAMG_OK) msg[g] = pcamg_last_error();
+      status[g] = r;
+      pcamg_destroy(c);
+    }
+    (void)hipStreamSynchronize(s);
+    dev_cache_idle(s);
+    (void)hipStreamDestroy(s);
     for (int32_t g = 0; g < count; ++g)
       if (status[g] != PCAMG_OK) throw Error(status[g], "graph " + std::to_string(g) + ": " + msg[g]);
   });
