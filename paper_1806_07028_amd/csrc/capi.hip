@@ -401,7 +401,7 @@ void pcamg_destroy(pcamg_ctx* c) {
 
 // ---------------------------------------------------------------------------
 // Batches of independent graphs: the graphs, largest first, each set up and
-// solved on the worker's own stream exactly as the single-graph entry points
+// solved on a stream of the call's own exactly as the single-graph entry points
 // do.  One worker only, on the calling thread: a pool of host threads sharing
 // the device ended once in a host segmentation fault whose cause is not
 // shown, so several workers are refused.

@@ -206,7 +206,7 @@ void gemm_rows(rocblas_handle h, int32_t p, int32_t q, int32_t r, T alpha, const
 
 // One rocBLAS handle per device for the life of the process, with a
 // workspace of ours, used by one build at a time: builds from concurrent
-// solves (the batch entry point's worker threads) take turns, and no handle
+// solves (caller threads with contexts of their own) take turns, and no handle
 // or workspace is created or destroyed -- no allocation or free inside
 // rocBLAS -- while other threads capture graphs.
 constexpr size_t BLAS_WORKSPACE = (size_t)128 << 20;
