@@ -51,12 +51,15 @@ class OracleParams(C.Structure):
         ("rebuild_rule", C.c_int),
         ("seed", C.c_ulonglong),
         ("colour_seed", C.c_ulonglong),
+        ("case3", C.c_int),
+        ("init", C.c_int),
     ]
 
 
 DEFAULTS = dict(tol=1e-8, theta=0.4, max_iter=2500, outer=0, cycle_prec=0, coarse_max=64, relax_sweeps=3,
                 rebuild_vcycles=2, rebuild_source=0, p1_mode=0, coarse_solve=0, a2_hub_cap=0, max_rebuilds=50,
-                max_levels=64, numW=2, iterW=7, iterV=4, rebuild_rule=0, seed=0x5EED, colour_seed=0xC010)
+                max_levels=64, numW=2, iterW=7, iterV=4, rebuild_rule=0, seed=0x5EED, colour_seed=0xC010,
+                case3=0, init=0)
 
 
 def params(**kw) -> OracleParams:
@@ -99,8 +102,10 @@ def lib():
     L.or_path_cover.argtypes = [C.c_int, C.c_int, _i32p, _i32p, _i32p]
     L.or_orient.argtypes = [C.c_int, _i32p, _i32p, _i32p, _i32p]
     L.or_orient.restype = C.c_int
-    L.or_aggregate.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_void_p, _i32p, _i32p, _i32p]
+    L.or_aggregate.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_void_p, _i32p, C.c_int, _i32p, _i32p]
     L.or_aggregate.restype = C.c_int
+    L.or_mwm_aggregate.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, _i32p]
+    L.or_mwm_aggregate.restype = C.c_int
     L.or_hier_build.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_void_p, C.POINTER(OracleParams)]
     L.or_hier_build.restype = C.c_void_p
     L.or_hier_free.argtypes = [C.c_void_p]
@@ -124,8 +129,8 @@ def lib():
                               C.c_void_p, C.c_void_p]
     L.or_galerkin.restype = C.c_longlong
     L.or_shorten.argtypes = [C.c_int, _i32p, C.c_int, _i32p, _i32p]
-    L.or_solve.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, C.POINTER(OracleParams), _f64p, _f64p, _f64p,
-                           C.c_int, _i32p, C.c_int]
+    L.or_solve.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, C.POINTER(OracleParams), C.c_void_p, _f64p,
+                           _f64p, _f64p, C.c_int, _i32p, C.c_int]
     L.or_solve.restype = C.c_int
     _lib = L
     return L
@@ -251,15 +256,28 @@ def orient(nb):
     return pid, pos, plen, np_
 
 
-def aggregate(n, grp, gci, gw, nb, gkey=None):
+def aggregate(n, grp, gci, gw, nb, gkey=None, case3: int = 0):
+    """Alg. 3 on one level.  case3 = 0: the connected reading of Case 3 (v
+    stays when taking it out would split its aggregate; u joins there);
+    case3 = 1: Step 17 as printed (v always leaves)."""
     agg = np.empty(n, dtype=np.int32)
     stats = np.empty(6, dtype=np.int32)
     keyp = None
     if gkey is not None:
         gkey = _f64(gkey)
         keyp = gkey.ctypes.data_as(C.c_void_p)
-    nc = lib().or_aggregate(n, _i32(grp), _i32(gci), _f64(gw), keyp, _i32(np.asarray(nb).reshape(-1)), agg, stats)
+    nc = lib().or_aggregate(n, _i32(grp), _i32(gci), _f64(gw), keyp, _i32(np.asarray(nb).reshape(-1)), case3,
+                            agg, stats)
     return agg, nc, dict(zip(["n_unagg", "case1", "case2", "case3", "middle", "singleton"], stats.tolist()))
+
+
+def mwm_aggregate(n, rp, ci, aval):
+    """MWM aggregation (Sec. 2.1) of a level with off-diagonal entries aval
+    (weights -aval): (agg, nc, stats)."""
+    agg = np.empty(n, dtype=np.int32)
+    stats = np.empty(3, dtype=np.int32)
+    nc = lib().or_mwm_aggregate(n, _i32(rp), _i32(ci), _f64(aval), agg, stats)
+    return agg, nc, dict(zip(["n_unagg", "joined", "singleton"], stats.tolist()))
 
 
 def galerkin(n, rp, ci, aval, d, nc, agg, pval):
@@ -408,7 +426,9 @@ class SolveResult:
     rebuild_at: np.ndarray
 
 
-def solve(g, b, **kw) -> SolveResult:
+def solve(g, b, x0=None, **kw) -> SolveResult:
+    """Adaptive solve from x0 (default 0).  init=1 starts from the MWM
+    hierarchy; rebuild_source=2 with rebuild_rule=1 and b = 0 is Alg. 6."""
     n, rp, ci, w = g
     p = params(**kw)
     x = np.empty(n)
@@ -416,7 +436,11 @@ def solve(g, b, **kw) -> SolveResult:
     cap = p.max_iter + 2
     hist = np.zeros(cap)
     rb = np.full(p.max_rebuilds + 1, -1, dtype=np.int32)
-    rc = lib().or_solve(n, _i32(rp), _i32(ci), _f64(w), _f64(b), C.byref(p), x, st, hist, cap, rb, len(rb))
+    x0p = None
+    if x0 is not None:
+        x0 = _f64(x0)
+        x0p = x0.ctypes.data_as(C.c_void_p)
+    rc = lib().or_solve(n, _i32(rp), _i32(ci), _f64(w), _f64(b), C.byref(p), x0p, x, st, hist, cap, rb, len(rb))
     if rc != 0:
         raise RuntimeError("oracle solve failed: " + _err())
     stats = dict(zip(STAT_KEYS, st.tolist()))

@@ -11,10 +11,20 @@
 //
 // Where the paper is silent or ambiguous the following readings are used
 // (each function names the passage it follows):
-//  * Smooth error: e_raw = S^nu xi, S = one symmetric (forward then backward)
-//    multicoloured Gauss-Seidel sweep on A e = 0, xi_i = 2u_i - 1 from a
-//    SplitMix64 counter stream; a rebuild first applies m_V V-cycles of the
-//    current hierarchy to a fresh xi (homogeneous adaptive-AMG exposure, Sec. 1).
+//  * Smooth error: every build relaxes its vector by S^nu, S = one symmetric
+//    (forward then backward) multicoloured Gauss-Seidel sweep on A e = 0.  The
+//    first build starts from xi_i = 2u_i - 1 (SplitMix64 counter stream) --
+//    or, with init = MWM, is the UA-AMG hierarchy of Alg. 5/6 Step 2 (Sec.
+//    2.1) built without any vector.  A re-setup of Alg. 5 starts from the
+//    error approximation of Alg. 2 (default; x <- x + e afterwards), or from a
+//    fresh xi exposed to m_V V-cycles of the current hierarchy on A e = 0
+//    (rebuild_source 1), or -- Alg. 6, b = 0 -- from the current iterate
+//    itself, normalised, with no further sweeps (rebuild_source 2).
+//  * MWM aggregation (Sec. 2.1): edges heaviest first (ties by lexicographic
+//    edge index) match two unaggregated ends; every vertex left over joins the
+//    aggregate of its heaviest neighbour (ties to the smaller id), which is
+//    always a matched vertex, so aggregates keep diameter <= 3.  Boolean
+//    prolongation on every level.
 //  * Reweighting (Alg. 4, Step 2): keys k_ij = |e_i - e_j| on the off-diagonal
 //    pattern of A^2; heavier weight = smaller key; ties by lexicographic edge
 //    index; numeric weight 1/max(k, 2^-52 max|e|).
@@ -29,7 +39,9 @@
 //    u joins v's aggregate instead (no vertex is left isolated, Sec. 3.3, and
 //    the aggregate keeps diameter <= 2, within the bound of three of the
 //    matching-based aggregation of Sec. 2.1); a vertex with no neighbour is a
-//    singleton.
+//    singleton.  This departs from Sec. 3.3's "all of size 2 or 3" (stars can
+//    be larger); case3 = 1 keeps the printed Step 17 instead (v always leaves,
+//    even when that splits a 3-chain).
 //  * Prolongation (Sec. 3.3, Alg. 3 Steps 20-24): level 1 uses e normalised by a
 //    power of two (max|e| in [0.5,1)) and centred by its mean measured in fixed
 //    point at resolution 2^-32; an aggregate whose |e| stays below 2^-26 uses 1.
@@ -131,6 +143,8 @@ struct Params {
   int rebuild_rule;       // 0 mean ConvR since the last re-setup (Alg. 5), 1 last ConvR (Alg. 6)
   uint64_t seed;
   uint64_t colour_seed;
+  int case3;              // 0 connected reading of Alg. 3 Case 3, 1 as printed (v always leaves)
+  int init;               // 0 first hierarchy from the relaxed start vector, 1 MWM (Alg. 5/6 Step 2)
 };
 
 struct Level {
@@ -465,7 +479,7 @@ int best_neighbour(const Csr& G, const std::vector<double>* gkey, int u) {
 // then treat every vertex left over in ascending id order (Cases 1-3).
 // Aggregates are numbered by their smallest member.
 // ---------------------------------------------------------------------------
-void aggregate(Level& L) {
+void aggregate(Level& L, int case3 = 0) {
   const int n = L.n;
   std::vector<int> obj(n, -1);
   std::vector<std::vector<int>> members;
@@ -519,7 +533,9 @@ void aggregate(Level& L) {
     // a 3-chain whose middle is v, or a star (grown past three members, every
     // member adjacent to its centre) whose centre is v.  Then u joins it at v.
     bool take_out;
-    if (members[T].size() == 3) {
+    if (case3 == 1) {  // as printed: v always leaves
+      take_out = true;
+    } else if (members[T].size() == 3) {
       std::vector<int> rest;
       for (int m : members[T]) if (m != v) rest.push_back(m);
       take_out = adjacent(L.G, rest[0], rest[1]);
@@ -559,6 +575,67 @@ void aggregate(Level& L) {
   L.mem.assign(n, 0);
   std::vector<int> fill(L.moff.begin(), L.moff.end() - 1);
   for (int v = 0; v < n; ++v) L.mem[fill[L.agg[v]]++] = v;  // ascending v within each aggregate
+}
+
+// ---------------------------------------------------------------------------
+// MWM aggregation (Sec. 2.1) of a level on its own weighted adjacency
+// w_ij = -a_ij: edges (i < j) visited from heaviest to lightest (ties by
+// lexicographic edge index) match their two ends when both are unaggregated.
+// The greedy matching is maximal, so every vertex left over has only matched
+// neighbours; it joins the aggregate of its heaviest neighbour (ties to the
+// smaller id).  A joined vertex is adjacent to one end of a matched pair, so
+// every aggregate has diameter <= 3.  A vertex with no neighbour is a
+// singleton.  Aggregates are numbered by their smallest member.
+// ---------------------------------------------------------------------------
+void mwm_aggregate(Level& L) {
+  const int n = L.n;
+  std::vector<int> eu, ev;
+  std::vector<double> ew;
+  for (int i = 0; i < n; ++i)
+    for (int k = L.A.rp[i]; k < L.A.rp[i + 1]; ++k)
+      if (L.A.ci[k] > i) { eu.push_back(i); ev.push_back(L.A.ci[k]); ew.push_back(-L.A.v[k]); }
+  std::vector<int> idx(eu.size());
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return ew[a] > ew[b]; });
+  std::vector<int> obj(n, -1);
+  for (int t : idx) {
+    const int u = eu[t], v = ev[t];
+    if (obj[u] < 0 && obj[v] < 0) obj[u] = obj[v] = u;  // object named by its first end
+  }
+  L.n_unagg = 0;
+  L.case1 = L.case2 = L.case3 = L.middle = L.singleton = 0;
+  std::vector<int> joined(n, -1);
+  for (int u = 0; u < n; ++u) {
+    if (obj[u] >= 0) continue;
+    L.n_unagg++;
+    int best = -1;
+    double bw = 0.0;
+    for (int k = L.A.rp[u]; k < L.A.rp[u + 1]; ++k) {
+      const double w = -L.A.v[k];
+      if (best < 0 || w > bw) { best = L.A.ci[k]; bw = w; }
+    }
+    joined[u] = best;
+  }
+  for (int u = 0; u < n; ++u) {  // matched ends only: the left-over vertices' choices are independent
+    if (obj[u] >= 0) continue;
+    if (joined[u] < 0) { L.singleton++; continue; }
+    L.case2++;
+  }
+  for (int u = 0; u < n; ++u)
+    if (obj[u] < 0) obj[u] = joined[u] >= 0 ? obj[joined[u]] : u;
+  // canonical numbering by smallest member (vertices in ascending id)
+  std::vector<int> canon(n, -1);
+  L.nc = 0;
+  for (int v = 0; v < n; ++v)
+    if (canon[obj[v]] < 0) canon[obj[v]] = L.nc++;
+  L.agg.assign(n, -1);
+  for (int v = 0; v < n; ++v) L.agg[v] = canon[obj[v]];
+  L.moff.assign(L.nc + 1, 0);
+  for (int v = 0; v < n; ++v) L.moff[L.agg[v] + 1]++;
+  for (int I = 0; I < L.nc; ++I) L.moff[I + 1] += L.moff[I];
+  L.mem.assign(n, 0);
+  std::vector<int> fill(L.moff.begin(), L.moff.end() - 1);
+  for (int v = 0; v < n; ++v) L.mem[fill[L.agg[v]]++] = v;
 }
 
 // Prolongation values on the finest level (Sec. 3.3): (P_1)_{k,i} = e_k for
@@ -836,6 +913,8 @@ void vcycle32(const Hierarchy& H, int l, const float* b, float* x) { cycle32(H, 
 // Hierarchy construction (Alg. 4) from the finest level (A, d, dinv, colours)
 // and a smooth error e_raw.
 // ---------------------------------------------------------------------------
+bool finish_hierarchy(Hierarchy& H, const Params& P, bool laplacian_op);
+
 bool build_hierarchy(const Level& fine, const std::vector<double>& e_raw, const Params& P, Hierarchy& H) {
   H.lv.clear();
   H.lv.push_back(Level());
@@ -859,7 +938,7 @@ bool build_hierarchy(const Level& fine, const std::vector<double>& e_raw, const 
     Level& L = H.lv[l];
     if (L.n <= P.coarse_max || l + 1 >= P.max_levels) break;
     orient_paths(L.n, L.nb, L.path_id, L.pos, L.plen, L.n_paths);
-    aggregate(L);
+    aggregate(L, P.case3);
     // stall (n_c > 0.9 n): this level becomes the coarsest, if the dense
     // coarsest solve can take it; a larger level keeps coarsening while it
     // still shrinks
@@ -880,11 +959,50 @@ bool build_hierarchy(const Level& fine, const std::vector<double>& e_raw, const 
     group_by_colour(C);
     H.lv.push_back(std::move(C));
   }
-  Level& Lc = H.lv.back();
-  if (Lc.n > 4096) { g_err = "coarsest level larger than 4096 vertices"; return false; }
   // the coarsest operator is a (singular) Laplacian when no prolongation carries
   // smooth-error values: boolean mode, or no coarsening at all
-  const bool laplacian_op = P.p1_mode == 1 || H.lv.size() == 1;
+  return finish_hierarchy(H, P, P.p1_mode == 1 || H.lv.size() == 1);
+}
+
+// UA-AMG hierarchy by MWM aggregation on every level (the MWM_setup of
+// Alg. 5/6 Step 2, Sec. 2.1): boolean prolongations, Galerkin products, the
+// same stopping rule and coarsest solve as Alg. 4's loop.
+bool build_hierarchy_mwm(const Level& fine, const Params& P, Hierarchy& H) {
+  H.lv.clear();
+  H.lv.push_back(Level());
+  Level& L0 = H.lv[0];
+  L0.n = fine.n;
+  L0.A = fine.A;
+  L0.d = fine.d;
+  L0.dinv = fine.dinv;
+  L0.colour = fine.colour;
+  L0.ncolours = fine.ncolours;
+  group_by_colour(L0);
+  for (int l = 0;; ++l) {
+    Level& L = H.lv[l];
+    if (L.n <= P.coarse_max || l + 1 >= P.max_levels) break;
+    mwm_aggregate(L);
+    if (L.nc > 0.9 * L.n && (L.n <= 4096 || L.nc >= L.n)) {
+      L.nc = 0;
+      L.agg.clear();
+      L.moff.clear();
+      L.mem.clear();
+      break;
+    }
+    L.pval.assign(L.n, 1.0);
+    Level C;
+    galerkin(L, C);
+    C.ncolours = colour_level(C.A, P.colour_seed, l + 1, C.colour);
+    group_by_colour(C);
+    H.lv.push_back(std::move(C));
+  }
+  return finish_hierarchy(H, P, true);
+}
+
+// Coarsest factor, operator complexity and FP32 copies of a built hierarchy.
+bool finish_hierarchy(Hierarchy& H, const Params& P, bool laplacian_op) {
+  Level& Lc = H.lv.back();
+  if (Lc.n > 4096) { g_err = "coarsest level larger than 4096 vertices"; return false; }
   if (!factor_coarsest(Lc, laplacian_op, P.coarse_solve, H.cs)) return false;
   // operator complexity: nonzeros of all levels (diagonal included) / finest
   double tot = 0.0;
@@ -1018,7 +1136,8 @@ struct SolveOut {
 };
 
 // Adaptive loop (Alg. 5) with the readings listed at the top of this file.
-int solve(const Csr& W, const std::vector<double>& b, const Params& P, std::vector<double>& x, SolveOut& out) {
+int solve(const Csr& W, const std::vector<double>& b, const Params& P, const double* x0, std::vector<double>& x,
+          SolveOut& out) {
   using clk = std::chrono::steady_clock;
   auto t0 = clk::now();
   const int n = W.n;
@@ -1028,10 +1147,14 @@ int solve(const Csr& W, const std::vector<double>& b, const Params& P, std::vect
   fine.ncolours = colour_level(fine.A, P.colour_seed, 0, fine.colour);
   group_by_colour(fine);
   std::vector<Hierarchy> hist(1);
-  std::vector<double> e;
-  start_vector(P, n, 0, e);
-  relax_homogeneous(fine, P.relax_sweeps, e);
-  if (!build_hierarchy(fine, e, P, hist[0])) return -1;
+  if (P.init == 1) {  // MWM_setup (Alg. 5/6 Step 2)
+    if (!build_hierarchy_mwm(fine, P, hist[0])) return -1;
+  } else {
+    std::vector<double> e;
+    start_vector(P, n, 0, e);
+    relax_homogeneous(fine, P.relax_sweeps, e);
+    if (!build_hierarchy(fine, e, P, hist[0])) return -1;
+  }
   strip_setup_data(hist[0]);
   out.first_levels = (int)hist[0].lv.size();
   out.first_oc = hist[0].op_complexity;
@@ -1040,7 +1163,9 @@ int solve(const Csr& W, const std::vector<double>& b, const Params& P, std::vect
   out.t_setup = std::chrono::duration<double>(t1 - t0).count();
 
   x.assign(n, 0.0);
-  std::vector<double> r = b;
+  if (x0) x.assign(x0, x0 + n);
+  std::vector<double> r(n);
+  residual_t<double>(fine, fine.A.v, fine.d, b.data(), x.data(), r.data());
   const double nr0 = norm2(r);
   out.relres_hist.clear();
   out.relres_hist.push_back(1.0);
@@ -1055,13 +1180,18 @@ int solve(const Csr& W, const std::vector<double>& b, const Params& P, std::vect
     if (P.rebuild_source == 0) {
       approximate_error(fine, hist, Re, P, res, corr);
       eb = corr;
+    } else if (P.rebuild_source == 2) {  // Alg. 6: e = x_{k+1} / ||x_{k+1}||, no further sweeps
+      const double nx = norm2(x);
+      eb.resize(n);
+      for (int i = 0; i < n; ++i) eb[i] = x[i] / nx;
+      corr.assign(n, 0.0);
     } else {  // relaxation of A e = 0 from a fresh start vector, exposed to the current cycle
       start_vector(P, n, Re, eb);
       std::vector<double> zero(n, 0.0);
       for (int c = 0; c < P.rebuild_vcycles; ++c) vcycle64(hist.back(), 0, zero.data(), eb.data());
       corr.assign(n, 0.0);
     }
-    relax_homogeneous(fine, P.relax_sweeps, eb);
+    if (P.rebuild_source != 2) relax_homogeneous(fine, P.relax_sweeps, eb);
     Hierarchy H2;
     if (!build_hierarchy(fine, eb, P, H2)) return false;
     strip_setup_data(H2);
@@ -1332,19 +1462,31 @@ int or_orient(int n, const int* nb, int* path_id, int* pos, int* plen) {
 // Aggregation of one level given its level graph (G, values w), optional keys
 // (finest level) and cover.  stats: n_unagg, case1, case2, case3, middle, singleton.
 int or_aggregate(int n, const int* grp, const int* gci, const double* gw, const double* gkey, const int* nb,
-                 int* agg, int* stats) {
+                 int case3, int* agg, int* stats) {
   Level L;
   L.n = n;
   L.G = make_csr(n, grp, gci, gw);
   if (gkey) L.gkey.assign(gkey, gkey + grp[n]);
   L.nb.assign(nb, nb + 2 * (size_t)n);
   orient_paths(n, L.nb, L.path_id, L.pos, L.plen, L.n_paths);
-  aggregate(L);
+  aggregate(L, case3);
   std::copy(L.agg.begin(), L.agg.end(), agg);
   if (stats) {
     stats[0] = L.n_unagg; stats[1] = L.case1; stats[2] = L.case2;
     stats[3] = L.case3; stats[4] = L.middle; stats[5] = L.singleton;
   }
+  return L.nc;
+}
+
+// MWM aggregation of one level given its off-diagonal entries a_ij (weights
+// -a_ij).  stats: n_unagg (left after the matching), joined, singleton.
+int or_mwm_aggregate(int n, const int* rp, const int* ci, const double* aval, int* agg, int* stats) {
+  Level L;
+  L.n = n;
+  L.A = make_csr(n, rp, ci, aval);
+  mwm_aggregate(L);
+  std::copy(L.agg.begin(), L.agg.end(), agg);
+  if (stats) { stats[0] = L.n_unagg; stats[1] = L.case2; stats[2] = L.singleton; }
   return L.nc;
 }
 
@@ -1368,10 +1510,13 @@ struct or_params_c {
   int rebuild_rule;
   unsigned long long seed;
   unsigned long long colour_seed;
+  int case3;
+  int init;
 };
 
 static Params to_params(const or_params_c* p) {
   Params P;
+  P.case3 = p->case3; P.init = p->init;
   P.tol = p->tol; P.theta = p->theta; P.max_iter = p->max_iter; P.outer = p->outer;
   P.cycle_prec = p->cycle_prec; P.coarse_max = p->coarse_max; P.relax_sweeps = p->relax_sweeps;
   P.rebuild_vcycles = p->rebuild_vcycles; P.rebuild_source = p->rebuild_source; P.p1_mode = p->p1_mode;
@@ -1390,6 +1535,10 @@ void* or_hier_build(int n, const int* rp, const int* ci, const double* w, const 
   laplacian(make_csr(n, rp, ci, w), h->fine.A, h->fine.d, h->fine.dinv);
   h->fine.ncolours = colour_level(h->fine.A, P.colour_seed, 0, h->fine.colour);
   group_by_colour(h->fine);
+  if (P.init == 1 && !e) {  // MWM hierarchy: no smooth error
+    if (!build_hierarchy_mwm(h->fine, P, h->H)) { delete h; return nullptr; }
+    return h;
+  }
   if (e) {
     h->e.assign(e, e + n);
   } else {
@@ -1509,11 +1658,12 @@ void or_hier_relax_error(void* hp, const or_params_c* pc, int r, double* e_out) 
 // Full adaptive solve.  stats: iterations, rebuilds, status, levels, relres,
 // true_relres, rho_geo, convr_last10, oc_mean, t_setup, t_solve, first_levels, first_oc
 int or_solve(int n, const int* rp, const int* ci, const double* w, const double* b, const or_params_c* pc,
-             double* x_out, double* stats, double* hist, int hist_cap, int* rebuild_at, int rb_cap) {
+             const double* x0, double* x_out, double* stats, double* hist, int hist_cap, int* rebuild_at,
+             int rb_cap) {
   Params P = to_params(pc);
   std::vector<double> bv(b, b + n), x;
   SolveOut out;
-  int rc = solve(make_csr(n, rp, ci, w), bv, P, x, out);
+  int rc = solve(make_csr(n, rp, ci, w), bv, P, x0, x, out);
   if (rc != 0) return rc;
   std::copy(x.begin(), x.end(), x_out);
   double s[13] = {(double)out.iterations, (double)out.rebuilds, (double)out.status, (double)out.levels,
