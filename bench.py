@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--workload", choices=["grid3d", "batch", "learned", "powerlaw"], default="grid3d",
                     help="grid3d: the 128^3 weighted grid (the benchmark line); batch: uneven graphs solved "
                          "together (separate JSON line)")
+    ap.add_argument("--cycle-prec", choices=["f64", "f32"], default=None,
+                    help="precision of the preconditioning cycles (default: the workload's)")
     ap.add_argument("--count", type=int, default=512, help="batch: number of graphs")
     ap.add_argument("--workers", type=int, default=1, help="batch: workers passed to the library (must be 1: "
                     "the calling thread; several host threads are switched off)")
@@ -268,7 +270,7 @@ def powerlaw_bench(args):
     n, rp, ci, w = g
     dev = torch.device("cuda", 0)
     args_d = [torch.as_tensor(a, device=dev) for a in (rp, ci, w, b)]
-    params = dict(outer="fcg", cycle_prec="f32", theta=0.5, a2_hub_cap=64)
+    params = dict(outer="fcg", cycle_prec=args.cycle_prec or "f32", theta=0.5, a2_hub_cap=64)
 
     def step():
         s = P.Solver(*args_d, **params)
@@ -349,7 +351,7 @@ def learned_bench(args):
         nsum += g[0]
         if (k + 1) % 100 == 0:
             log(f"  {k + 1} training graphs ({nsum} vertices)")
-    net = L.Net(M.init_params(7))
+    net = L.Net(seed=7)  # the library's seeded Glorot-uniform initialiser
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     hist = L.train(net, pairs, epochs=args.epochs, lr=2e-3, log=log)

@@ -63,7 +63,8 @@ enum { PCAMG_OUTER_VCYCLE = 0, PCAMG_OUTER_FCG = 1 };
 enum { PCAMG_PREC_F64 = 0, PCAMG_PREC_F32 = 1 };
 enum { PCAMG_P1_SMOOTH = 0, PCAMG_P1_CONST = 1 };
 enum { PCAMG_COARSE_AUTO = 0, PCAMG_COARSE_GROUNDED = 1, PCAMG_COARSE_FULL = 2 };
-enum { PCAMG_REBUILD_ERROR_APPROX = 0, PCAMG_REBUILD_RELAX = 1 };
+enum { PCAMG_REBUILD_ERROR_APPROX = 0, PCAMG_REBUILD_RELAX = 1, PCAMG_REBUILD_ITERATE = 2 };
+enum { PCAMG_INIT_RELAX = 0, PCAMG_INIT_MWM = 1 };
 
 typedef struct {
   double tol;              /* relative residual ||b - A x|| / ||b|| (default 1e-8, Sec. 4) */
@@ -75,7 +76,10 @@ typedef struct {
   int32_t coarse_max;      /* coarsest level size (64) */
   int32_t relax_sweeps;    /* symmetric GS sweeps on A e = 0 before each build (3) */
   int32_t rebuild_vcycles; /* V-cycles on A e = 0 (PCAMG_REBUILD_RELAX only; 2) */
-  int32_t rebuild_source;  /* PCAMG_REBUILD_ERROR_APPROX (Alg. 2, default) or PCAMG_REBUILD_RELAX */
+  int32_t rebuild_source;  /* PCAMG_REBUILD_ERROR_APPROX (Alg. 2, default), PCAMG_REBUILD_RELAX, or
+                              PCAMG_REBUILD_ITERATE (Alg. 6, b = 0: the current iterate x_{k+1} is
+                              the smooth error, used without further sweeps; with rebuild_rule 1
+                              and a zero right-hand side this is Alg. 6) */
   int32_t p1_mode;         /* PCAMG_P1_SMOOTH (Sec. 3.3, default) or PCAMG_P1_CONST */
   int32_t coarse_solve;    /* PCAMG_COARSE_AUTO / GROUNDED / FULL */
   int32_t a2_hub_cap;      /* 0 = exact A^2 pattern; K > 0: two-step pairs only via degree <= K */
@@ -118,6 +122,14 @@ typedef struct {
                               (2048) */
   uint64_t seed;           /* start-vector stream */
   uint64_t colour_seed;    /* colouring priority stream */
+  int32_t case3;           /* Alg. 3 Case 3: 0 = v leaves its aggregate only when the rest stays
+                              connected (else u joins at v; aggregates may grow past three as stars
+                              of diameter 2); 1 = as printed in Step 17 (v always leaves) */
+  int32_t init;            /* first hierarchy: PCAMG_INIT_RELAX (path cover of the relaxed start
+                              vector, default) or PCAMG_INIT_MWM (UA-AMG with MWM aggregation on
+                              every level, the MWM_setup of Alg. 5/6 Step 2, Sec. 2.1).  With
+                              max_rebuilds = 0 and PCAMG_INIT_MWM the solve is the paper's
+                              UA-AMG baseline */
 } pcamg_params;
 
 typedef struct {
@@ -261,7 +273,11 @@ pcamg_status pcamg_initial_error(pcamg_ctx* c, double* e);
 /* Number of float32 parameters (25,153). */
 int32_t pcamg_net_num_params(void);
 
-/* New network (parameters unset). Owns device memory until pcamg_net_destroy. */
+/* New network.  Parameters, Adam state and gradient are zero and the network
+ * is not usable yet: pcamg_net_forward, pcamg_net_loss_grad,
+ * pcamg_net_adam_step and pcamg_setup_learned return PCAMG_EINVAL until
+ * pcamg_net_init or pcamg_net_set_params has given it parameters.  Owns
+ * device memory until pcamg_net_destroy. */
 pcamg_status pcamg_net_create(pcamg_net** out);
 void pcamg_net_destroy(pcamg_net* net);
 
@@ -269,6 +285,13 @@ void pcamg_net_destroy(pcamg_net* net);
  * also resets the Adam state. */
 pcamg_status pcamg_net_set_params(pcamg_net* net, const float* theta, void* stream);
 pcamg_status pcamg_net_get_params(pcamg_net* net, float* theta, void* stream);
+
+/* Seeded initial parameters, computed on the device: flat entry k draws word
+ * k + 1 of the SplitMix64 stream `seed` (u = (word >> 11) 2^-53) and takes
+ * (2u - 1) lim rounded to float32, with lim = sqrt(6 / (fan_in + fan_out))
+ * for W0 (4 x 64) and W1..W3 (128 x 64), 0.1 for wo and 0 for every bias
+ * (Glorot-uniform weights).  Also resets the Adam state. */
+pcamg_status pcamg_net_init(pcamg_net* net, uint64_t seed, void* stream);
 
 /* Forward pass: y (device float [n]) from the graph (as for pcamg_setup) and
  * the relaxed vector e2 (device double [n], natural order). */
@@ -369,6 +392,17 @@ pcamg_status pcamg_orient(int32_t n, const int32_t* nb, int32_t* path_id, int32_
 pcamg_status pcamg_aggregate(int32_t n, const int32_t* grp, const int32_t* gci, const double* gw,
                              const double* gkey, const int32_t* nb, int32_t* agg, int32_t* nc, int32_t* stats,
                              void* stream);
+
+/* MWM aggregation (Sec. 2.1) of one level with off-diagonal entries aval
+ * (weights w_ij = -aval): edges visited heaviest first (ties by lexicographic
+ * edge index) match two unaggregated ends; every vertex left over joins the
+ * aggregate of its heaviest neighbour (ties to the smaller id), so aggregates
+ * keep diameter <= 3; aggregates numbered by smallest member.  rp, ci, aval:
+ * device CSR (aval < 0); agg: device int32 [n]; *nc and stats[3] (host):
+ * left after the matching, joined, singletons.  PCAMG_EINVAL on null
+ * arguments or n < 1. */
+pcamg_status pcamg_mwm_aggregate(int32_t n, const int32_t* rp, const int32_t* ci, const double* aval, int32_t* agg,
+                                 int32_t* nc, int32_t* stats, void* stream);
 
 /* Galerkin product P^T A P (Alg. 4, Step 8) for P with one value pval[k] in
  * column agg[k].  Two calls: rpc[nc+1] and *nnzc (host), then cic[nnzc],

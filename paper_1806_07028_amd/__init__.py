@@ -24,7 +24,8 @@ _OUTER = {"vcycle": 0, "fcg": 1}
 _PREC = {"f64": 0, "f32": 1}
 _P1 = {"smooth": 0, "const": 1}
 _COARSE = {"auto": 0, "grounded": 1, "full": 2}
-_SOURCE = {"error": 0, "relax": 1}
+_SOURCE = {"error": 0, "relax": 1, "iterate": 2}
+_INIT = {"relax": 0, "mwm": 1}
 
 
 def _ptr(t: torch.Tensor | None, dtype: torch.dtype | None = None) -> int | None:
@@ -45,7 +46,7 @@ def _stream() -> int:
 
 def _params(kw: dict) -> _lib.Params:
     maps = {"outer": _OUTER, "cycle_prec": _PREC, "p1_mode": _P1, "coarse_solve": _COARSE,
-            "rebuild_source": _SOURCE}
+            "rebuild_source": _SOURCE, "init": _INIT}
     conv = {}
     for k, v in kw.items():
         if k in maps and isinstance(v, str):

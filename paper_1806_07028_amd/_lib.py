@@ -54,6 +54,8 @@ class Params(C.Structure):
         ("v_dense_max_n", _i32),
         ("seed", _u64),
         ("colour_seed", _u64),
+        ("case3", _i32),
+        ("init", _i32),
     ]
 
 
@@ -111,6 +113,7 @@ _SIGS = {
     "pcamg_net_destroy": ([_p], None),
     "pcamg_net_set_params": ([_p, _p, _p], _i32),
     "pcamg_net_get_params": ([_p, _p, _p], _i32),
+    "pcamg_net_init": ([_p, _u64, _p], _i32),
     "pcamg_net_forward": ([_p, C.POINTER(Graph), _p, _p, _p], _i32),
     "pcamg_net_loss_grad": ([_p, C.POINTER(Graph), _p, _p, C.POINTER(C.c_double), _p, _p], _i32),
     "pcamg_net_adam_step": ([_p, C.c_float, _p], _i32),
@@ -137,6 +140,7 @@ _SIGS = {
     "pcamg_path_cover": ([_i32, _i32, _p, _p, _p, _p], _i32),
     "pcamg_orient": ([_i32, _p, _p, _p, _p, _p], _i32),
     "pcamg_aggregate": ([_i32, _p, _p, _p, _p, _p, _p, C.POINTER(_i32), _p, _p], _i32),
+    "pcamg_mwm_aggregate": ([_i32, _p, _p, _p, _p, C.POINTER(_i32), _p, _p], _i32),
     "pcamg_galerkin_count": ([_i32, _p, _p, _i32, _p, _p, C.POINTER(_i64), _p], _i32),
     "pcamg_galerkin_fill": ([_i32, _p, _p, _p, _p, _i32, _p, _p, _p, _p, _p, _p, _p], _i32),
     "pcamg_shorten": ([_i32, _p, _i32, _p, _p, _p], _i32),

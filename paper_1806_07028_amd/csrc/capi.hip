@@ -231,6 +231,8 @@ pcamg_status pcamg_params_default(pcamg_params* p) {
   p->v_dense_max_n = 2048;
   p->seed = 0x5EED;
   p->colour_seed = 0xC010;
+  p->case3 = 0;
+  p->init = PCAMG_INIT_RELAX;
   return PCAMG_OK;
 }
 
@@ -248,6 +250,11 @@ void setup_impl(const pcamg_graph* g, const double* rhs, const pcamg_params* p, 
   require(p->first_sweeps >= -1 && p->first_sweeps <= 1000, PCAMG_EINVAL, "first_sweeps out of range");
   require(p->long_row_min >= 0, PCAMG_EINVAL, "long_row_min must be >= 0");
   require(p->v_dense_max_n >= 0, PCAMG_EINVAL, "v_dense_max_n must be >= 0");
+  require(p->case3 == 0 || p->case3 == 1, PCAMG_EINVAL, "case3 must be 0 or 1");
+  require(p->init == PCAMG_INIT_RELAX || p->init == PCAMG_INIT_MWM, PCAMG_EINVAL, "unknown init");
+  require(p->rebuild_source >= PCAMG_REBUILD_ERROR_APPROX && p->rebuild_source <= PCAMG_REBUILD_ITERATE,
+          PCAMG_EINVAL, "unknown rebuild_source");
+  require(!(net && p->init == PCAMG_INIT_MWM), PCAMG_EINVAL, "the learned setup builds its own first hierarchy");
   hipStream_t s = as_stream(stream);
   if (p->validate) validate_graph(g, s);
   require(g->n >= 1, PCAMG_EINVAL, "empty graph");
@@ -262,6 +269,12 @@ void setup_impl(const pcamg_graph* g, const double* rhs, const pcamg_params* p, 
   }
   Timer t(s);
   DVec<double> e(g->n);
+  if (p->init == PCAMG_INIT_MWM) {  // MWM_setup (Alg. 5/6 Step 2): no smooth error
+    c->hist.push_back(build_hierarchy_mwm(c.get()));
+    c->t_build_ms = t.ms();
+    *out = c.release();
+    return;
+  }
   if (net) {  // the network's proposal from first_sweeps (default 2) sweeps
     DVec<double> e2(g->n);
     initial_error(c.get(), 0, e2.p, p->first_sweeps >= 0 ? p->first_sweeps : 2);
@@ -320,6 +333,13 @@ pcamg_status pcamg_net_set_params(pcamg_net* net, const float* theta, void* stre
   return guarded_s(as_stream(stream), [&] {
     require(net && theta, PCAMG_EINVAL, "null argument");
     net_set_params(net, theta, as_stream(stream));
+  });
+}
+
+pcamg_status pcamg_net_init(pcamg_net* net, uint64_t seed, void* stream) {
+  return guarded_s(as_stream(stream), [&] {
+    require(net, PCAMG_EINVAL, "null argument");
+    net_init(net, seed, as_stream(stream));
   });
 }
 
@@ -689,6 +709,23 @@ pcamg_status pcamg_aggregate(int32_t n, const int32_t* grp, const int32_t* gci, 
       stats[3] = st.case3;
       stats[4] = st.middle;
       stats[5] = st.singleton;
+    }
+  });
+}
+
+pcamg_status pcamg_mwm_aggregate(int32_t n, const int32_t* rp, const int32_t* ci, const double* aval, int32_t* agg,
+                                 int32_t* nc, int32_t* stats, void* stream) {
+  return guarded_s(as_stream(stream), [&] {
+    require(n > 0 && rp && agg && nc, PCAMG_EINVAL, "null argument");
+    hipStream_t s = as_stream(stream);
+    require_entries(n, rp, {ci, aval}, s);
+    DVec<int32_t> moff(n + 1), mem(n);
+    AggStats st;
+    *nc = mwm_aggregate_level(n, rp, ci, aval, agg, moff.p, mem.p, st, s);
+    if (stats) {
+      stats[0] = st.n_unagg;
+      stats[1] = st.case2;
+      stats[2] = st.singleton;
     }
   });
 }

@@ -262,9 +262,16 @@ struct AggStats {
 };
 // Alg. 3 on one level; returns nc; agg[n], member CSR moff[nc+1], mem[n]
 // (device, allocated by the caller with n+1 / n entries). (synchronises)
+// case3 = 1: Case 3 as printed (v always leaves its aggregate).
 int32_t aggregate_level(int32_t n, const int32_t* grp, const int32_t* gci, const double* gw, const double* gkey,
                         const int32_t* nb, const int32_t* path_id, const int32_t* pos, const int32_t* plen,
-                        int32_t* agg, int32_t* moff, int32_t* mem, AggStats& st, hipStream_t s);
+                        int32_t* agg, int32_t* moff, int32_t* mem, AggStats& st, hipStream_t s, int32_t case3 = 0);
+// MWM aggregation (Sec. 2.1) of a level with off-diagonal entries av (weights
+// -av); returns nc; agg[n], moff[nc+1], mem[n] as for aggregate_level;
+// st.n_unagg (left after the matching), st.case2 (joined), st.singleton.
+// (synchronises)
+int32_t mwm_aggregate_level(int32_t n, const int32_t* rp, const int32_t* ci, const double* av, int32_t* agg,
+                            int32_t* moff, int32_t* mem, AggStats& st, hipStream_t s);
 // Level-1 prolongation values from e_raw (power-of-two normalisation,
 // fixed-point mean, small-aggregate fallback).  Returns fallback count.
 int32_t smooth_pval(int32_t n, const double* e_raw, int32_t nc, const int32_t* moff, const int32_t* mem,

@@ -336,6 +336,30 @@ __global__ void adam_kernel(int32_t m, float* __restrict__ th, float* __restrict
   th[i] = th[i] - lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
 }
 
+// Seeded initial parameters: entry k of the flat parameter vector draws word
+// k + 1 of the SplitMix64 stream `seed`, u = (word >> 11) 2^-53 in [0, 1), and
+// takes (2u - 1) lim rounded to float32, where lim is the Glorot-uniform bound
+// sqrt(6 / (fan_in + fan_out)) of its weight matrix (lim0: W0, limh: W1..W3),
+// 0.1 for the output weights and 0 for every bias.
+__global__ void init_params_kernel(uint64_t seed, double lim0, double limh, float* __restrict__ th) {
+  const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= NPAR) return;
+  double lim = 0.0;
+  if (k < OFF_B0) {
+    lim = lim0;
+  } else if (k >= OFF_L1 && k < OFF_WO) {
+    lim = (k - OFF_L1) % LAYER_SZ < ZD * HID ? limh : 0.0;
+  } else if (k >= OFF_WO && k < OFF_BO) {
+    lim = 0.1;
+  }
+  uint64_t z = seed + (uint64_t)(k + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  const double u = (double)(z >> 11) * 0x1.0p-53;
+  th[k] = (float)((2.0 * u - 1.0) * lim);
+}
+
 __global__ void widen_kernel(int32_t n, const float* __restrict__ y, double* __restrict__ e) {
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) e[i] = (double)y[i];
@@ -433,6 +457,9 @@ static void refresh_bf16(pcamg_net* net, hipStream_t s) {
 
 int32_t net_num_params() { return NPAR; }
 
+// Parameters, Adam moments and gradient start at zero; the network refuses
+// forward, backward and optimiser calls until net_set_params or net_init has
+// given it parameters.
 void net_create(pcamg_net** out) {
   auto net = std::make_unique<pcamg_net>();
   net->th.resize(NPAR);
@@ -443,7 +470,21 @@ void net_create(pcamg_net** out) {
     net->wt[k].resize(ZD * HID);
     net->wn[k].resize(ZD * HID);
   }
+  for (DVec<float>* a : {&net->th, &net->m, &net->v, &net->grad}) PCAMG_HIP(hipMemset(a->p, 0, a->bytes()));
+  PCAMG_HIP(hipDeviceSynchronize());
   *out = net.release();
+}
+
+void net_init(pcamg_net* net, uint64_t seed, hipStream_t s) {
+  const double lim0 = std::sqrt(6.0 / (NF + HID)), limh = std::sqrt(6.0 / (ZD + HID));
+  init_params_kernel<<<grid_for(NPAR, 256), 256, 0, s>>>(seed, lim0, limh, net->th.p);
+  PCAMG_LAUNCHED();
+  fill_f32(net->m.p, 0.0f, NPAR, s);
+  fill_f32(net->v.p, 0.0f, NPAR, s);
+  fill_f32(net->grad.p, 0.0f, NPAR, s);
+  net->step = 0;
+  refresh_bf16(net, s);
+  PCAMG_HIP(hipStreamSynchronize(s));
 }
 
 void net_destroy(pcamg_net* net) { delete net; }
@@ -554,6 +595,7 @@ double net_loss_grad(pcamg_net* net, const pcamg_graph* g, const double* e2, con
 }
 
 void net_adam(pcamg_net* net, float lr, hipStream_t s) {
+  require(net->bf_ready, PCAMG_EINVAL, "network parameters not set");
   net->step += 1;
   const float c1 = 1.0f - powf(0.9f, (float)net->step);
   const float c2 = 1.0f - powf(0.999f, (float)net->step);

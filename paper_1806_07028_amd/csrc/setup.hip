@@ -674,7 +674,7 @@ __global__ void rp_commit_kernel(int32_t w, const int32_t* __restrict__ win, Agg
                                  const uint32_t* __restrict__ resV, const uint32_t* __restrict__ resO,
                                  const int2* __restrict__ plan, uint8_t* __restrict__ state,
                                  const int32_t* __restrict__ grp, const int32_t* __restrict__ gci,
-                                 int32_t* __restrict__ stats) {
+                                 int32_t* __restrict__ stats, int32_t case3) {
   int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= w || state[x] != 1) return;
   const uint32_t u = (uint32_t)win[x];
@@ -698,9 +698,12 @@ __global__ void rp_commit_kernel(int32_t w, const int32_t* __restrict__ win, Agg
     return;
   }
   // Case 3: v leaves T unless that disconnects it (v the middle of a 3-chain,
-  // or the centre of a star); then u joins T at v
+  // or the centre of a star); then u joins T at v.  case3 = 1: as printed,
+  // v always leaves.
   bool take_out;
-  if (sz == 3) {
+  if (case3 == 1) {
+    take_out = true;
+  } else if (sz == 3) {
     int32_t rest[2] = {-1, -1}, k = 0;
     for (int32_t m = o.head[T], c = 0; m >= 0 && c < 3; m = o.next[m], ++c)
       if (m != v && k < 2) rest[k++] = m;
@@ -764,9 +767,12 @@ __global__ void canon_kernel(int32_t n, const int32_t* __restrict__ obj, const i
   if (omin[T] == v) msz[I] = osz[T];
 }
 
+int32_t number_aggregates(int32_t n, const int32_t* obj, const int32_t* osz, int32_t* agg, int32_t* moff,
+                          int32_t* mem, hipStream_t s);
+
 int32_t aggregate_level(int32_t n, const int32_t* grp, const int32_t* gci, const double* gw, const double* gkey,
                         const int32_t* nb, const int32_t* path_id, const int32_t* pos, const int32_t* plen,
-                        int32_t* agg, int32_t* moff, int32_t* mem, AggStats& st, hipStream_t s) {
+                        int32_t* agg, int32_t* moff, int32_t* mem, AggStats& st, hipStream_t s, int32_t case3) {
   DVec<int32_t> obj(n), osz(n), ocen(n), ohead(n), onext(n), oprev(n), best(n), pend(n), cnt(1), stats(ST_COUNT);
   DVec<uint8_t> unagg(n);
   const AggObjs o{obj.p, osz.p, ocen.p, ohead.p, onext.p, oprev.p};
@@ -798,7 +804,7 @@ int32_t aggregate_level(int32_t n, const int32_t* grp, const int32_t* gci, const
       const unsigned g = grid_for(w, 256);
       rp_reserve_kernel<<<g, 256, 0, s>>>(w, win.p, obj.p, best.p, resV.p, resO.p, plan.p, state.p);
       PCAMG_LAUNCHED();
-      rp_commit_kernel<<<g, 256, 0, s>>>(w, win.p, o, resV.p, resO.p, plan.p, state.p, grp, gci, stats.p);
+      rp_commit_kernel<<<g, 256, 0, s>>>(w, win.p, o, resV.p, resO.p, plan.p, state.p, grp, gci, stats.p, case3);
       PCAMG_LAUNCHED();
       rp_reset_kernel<<<g, 256, 0, s>>>(w, win.p, resV.p, resO.p, plan.p, state.p);
       PCAMG_LAUNCHED();
@@ -816,18 +822,26 @@ int32_t aggregate_level(int32_t n, const int32_t* grp, const int32_t* gci, const
   st.case2 = hs[ST_CASE2];
   st.case3 = hs[ST_CASE3];
   st.middle = hs[ST_MIDDLE];
+  return number_aggregates(n, obj.p, osz.p, agg, moff, mem, s);
+}
+
+// Canonical numbering of aggregate objects (object id obj[v] in [0, n), sizes
+// osz) by their smallest member, and member lists in ascending id.
+// (synchronises)
+int32_t number_aggregates(int32_t n, const int32_t* obj, const int32_t* osz, int32_t* agg, int32_t* moff,
+                          int32_t* mem, hipStream_t s) {
   DVec<int32_t> omin(n), isroot(n), cpos(n), msz(n), ncd(1), bad(1), vid(n);
   DVec<uint32_t> aggu(n), skeys(n);
   fill_i32(bad.p, 0, 1, s);
   fill_i32(omin.p, INT32_MAX, n, s);
-  objmin_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, obj.p, omin.p, bad.p);
+  objmin_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, obj, omin.p, bad.p);
   PCAMG_LAUNCHED();
   require(read_scalar(bad.p, s) == 0, PCAMG_EHIP, "aggregation left a vertex without aggregate");
-  isroot_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, obj.p, omin.p, isroot.p);
+  isroot_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, obj, omin.p, isroot.p);
   PCAMG_LAUNCHED();
   scan_exclusive_i32(isroot.p, cpos.p, n, ncd.p, s);
   const int32_t nc = read_scalar(ncd.p, s);
-  canon_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, obj.p, osz.p, omin.p, cpos.p, agg, aggu.p, msz.p);
+  canon_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, obj, osz, omin.p, cpos.p, agg, aggu.p, msz.p);
   PCAMG_LAUNCHED();
   scan_exclusive_i32(msz.p, moff, nc, moff + nc, s);
   // members of every aggregate in ascending id: a stable sort of the ids by aggregate
@@ -1263,6 +1277,178 @@ void shorten_paths(int32_t n, const int32_t* nb, const int32_t* path_id, const i
   PCAMG_LAUNCHED();
   sh_canon_kernel<<<grid_for(nc, 256), 256, 0, s>>>(nc, nbc);
   PCAMG_LAUNCHED();
+}
+
+// ---------------------------------------------------------------------------
+// MWM aggregation (Sec. 2.1) of a level on its weighted adjacency w = -a_ij.
+// Upper entries (i < j) in row-major order are the edges in lexicographic
+// index order; a stable radix sort on ~bits(w) (w > 0, so the bit pattern
+// grows with w) puts them heaviest first with ties by index.  The greedy
+// matching runs by deterministic reservations: a pending edge dies once an
+// end is matched (a permanent fact), else it reserves both ends with its rank
+// and matches them iff it holds both -- every earlier edge at those ends has
+// then been decided, so this is the sequential greedy matching.  Left-over
+// vertices have only matched neighbours (the matching is maximal) and join
+// the aggregate of the heaviest one (ties to the smaller id): independent
+// choices, one thread each.
+// ---------------------------------------------------------------------------
+__global__ void mwm_upper_count_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                       int32_t* __restrict__ ucnt) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t k1 = rp[i + 1];
+  ucnt[i] = k1 - first_upper(i, rp[i], k1, ci);
+}
+
+__global__ void __launch_bounds__(256)
+    mwm_keys_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                    const double* __restrict__ av, const int32_t* __restrict__ uoff, int32_t* __restrict__ eu,
+                    int32_t* __restrict__ ev, uint64_t* __restrict__ ekey) {
+  const int32_t i = (int32_t)(((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);  // uniform per wavefront
+  if (i >= n) return;
+  const int lane = (int)(threadIdx.x & 63);
+  const int32_t k0 = rp[i], k1 = rp[i + 1];
+  const int32_t fu = first_upper(i, k0, k1, ci);
+  const int32_t ubase = uoff[i];
+  for (int32_t k = fu + lane; k < k1; k += 64) {
+    const int32_t u = ubase + (k - fu);
+    eu[u] = i;
+    ev[u] = ci[k];
+    ekey[u] = ~(uint64_t)__double_as_longlong(-av[k]);
+  }
+}
+
+__global__ void mm_reserve_kernel(int32_t w, const int32_t* __restrict__ win, const int32_t* __restrict__ su,
+                                  const int32_t* __restrict__ sv, const int32_t* __restrict__ mate,
+                                  uint32_t* __restrict__ res, uint8_t* __restrict__ state) {
+  int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= w) return;
+  const int32_t t = win[x];
+  const int32_t u = su[t], v = sv[t];
+  if (mate[u] >= 0 || mate[v] >= 0) {
+    state[x] = 0;
+    return;
+  }
+  atomicMin(&res[u], (uint32_t)t);
+  atomicMin(&res[v], (uint32_t)t);
+  state[x] = 1;
+}
+
+__global__ void mm_commit_kernel(int32_t w, const int32_t* __restrict__ win, const int32_t* __restrict__ su,
+                                 const int32_t* __restrict__ sv, int32_t* __restrict__ mate,
+                                 const uint32_t* __restrict__ res, uint8_t* __restrict__ state) {
+  int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= w || state[x] != 1) return;
+  const uint32_t t = (uint32_t)win[x];
+  const int32_t u = su[t], v = sv[t];
+  if (res[u] != t || res[v] != t) return;
+  mate[u] = v;
+  mate[v] = u;
+  state[x] = 2;
+}
+
+__global__ void mm_reset_kernel(int32_t w, const int32_t* __restrict__ win, const int32_t* __restrict__ su,
+                                const int32_t* __restrict__ sv, uint32_t* __restrict__ res,
+                                uint8_t* __restrict__ state) {
+  int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= w) return;
+  const uint8_t st = state[x];
+  if (st == 0) return;
+  const int32_t t = win[x];
+  res[su[t]] = UINT_MAX;
+  res[sv[t]] = UINT_MAX;
+  state[x] = st == 1 ? 1 : 0;  // keep only the still-pending edges
+}
+
+// Objects: a matched pair is named by its smaller end; a left-over vertex
+// takes its heaviest neighbour's object (no neighbour: its own).
+__global__ void mwm_join_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                const double* __restrict__ av, const int32_t* __restrict__ mate,
+                                int32_t* __restrict__ obj, int32_t* __restrict__ osz, int32_t* __restrict__ stats) {
+  int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  const int32_t m = mate[u];
+  if (m >= 0) {
+    const int32_t T = u < m ? u : m;
+    obj[u] = T;
+    atomicAdd(&osz[T], 1);
+    return;
+  }
+  int32_t b = -1;
+  double bw = 0.0;
+  for (int32_t k = rp[u]; k < rp[u + 1]; ++k) {
+    const double w = -av[k];
+    if (b < 0 || w > bw) { b = ci[k]; bw = w; }
+  }
+  atomicAdd(&stats[0], 1);
+  if (b < 0) {
+    obj[u] = u;
+    atomicAdd(&osz[u], 1);
+    atomicAdd(&stats[2], 1);
+    return;
+  }
+  const int32_t mb = mate[b];  // >= 0: the matching is maximal
+  const int32_t T = mb < 0 ? b : (b < mb ? b : mb);
+  obj[u] = T;
+  atomicAdd(&osz[T], 1);
+  atomicAdd(&stats[1], 1);
+}
+
+int32_t mwm_aggregate_level(int32_t n, const int32_t* rp, const int32_t* ci, const double* av, int32_t* agg,
+                            int32_t* moff, int32_t* mem, AggStats& st, hipStream_t s) {
+  DVec<int32_t> ucnt(n), uoff(n), tot(1), mate(n), obj(n), osz(n), stats(3);
+  mwm_upper_count_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, rp, ci, ucnt.p);
+  PCAMG_LAUNCHED();
+  scan_exclusive_i32(ucnt.p, uoff.p, n, tot.p, s);
+  const int32_t m = read_scalar(tot.p, s);
+  fill_i32(mate.p, -1, n, s);
+  if (m > 0) {
+    DVec<int32_t> eu(m), ev(m), su(m), sv(m);
+    DVec<uint64_t> ekey(m), ksorted(m);
+    DVec<uint32_t> idx(m), order(m);
+    mwm_keys_kernel<<<grid_for((size_t)n * 64, 256), 256, 0, s>>>(n, rp, ci, av, uoff.p, eu.p, ev.p, ekey.p);
+    PCAMG_LAUNCHED();
+    iota_i32((int32_t*)idx.p, m, s);
+    radix_sort_u64_u32(ekey.p, idx.p, ksorted.p, order.p, m, s);
+    sorted_endpoints(m, order.p, eu.p, ev.p, su.p, sv.p, s);
+    DVec<uint32_t> res(n);
+    fill_u32(res.p, UINT_MAX, n, s);
+    const int32_t WIN = std::max<int32_t>(1 << 16, std::min<int32_t>(1 << 20, m / 8 + 1));
+    DVec<int32_t> win(WIN), surv(WIN), cnt(1);
+    DVec<uint8_t> state(WIN);
+    int32_t ns = 0, next = 0, rounds = 0;
+    while (ns > 0 || next < m) {
+      const int32_t take = std::min<int32_t>(WIN - ns, m - next);
+      if (take > 0) {
+        window_kernel<<<grid_for(take, 256), 256, 0, s>>>(ns, next, take, win.p);
+        PCAMG_LAUNCHED();
+      }
+      const int32_t w = ns + take;
+      next += take;
+      const unsigned g = grid_for(w, 256);
+      mm_reserve_kernel<<<g, 256, 0, s>>>(w, win.p, su.p, sv.p, mate.p, res.p, state.p);
+      PCAMG_LAUNCHED();
+      mm_commit_kernel<<<g, 256, 0, s>>>(w, win.p, su.p, sv.p, mate.p, res.p, state.p);
+      PCAMG_LAUNCHED();
+      mm_reset_kernel<<<g, 256, 0, s>>>(w, win.p, su.p, sv.p, res.p, state.p);
+      PCAMG_LAUNCHED();
+      compact_i32(win.p, state.p, surv.p, cnt.p, w, s);
+      ns = read_scalar(cnt.p, s);
+      std::swap(win, surv);  // survivors first in the next window
+      ++rounds;
+      require(rounds <= 4 * m + 8, PCAMG_EHIP, "MWM matching did not terminate");
+    }
+    st.cover_rounds = rounds;
+  }
+  fill_i32(osz.p, 0, n, s);
+  fill_i32(stats.p, 0, 3, s);
+  mwm_join_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, rp, ci, av, mate.p, obj.p, osz.p, stats.p);
+  PCAMG_LAUNCHED();
+  auto hs = to_host(stats.p, 3, s);
+  st.n_unagg = hs[0];
+  st.case2 = hs[1];
+  st.singleton = hs[2];
+  return number_aggregates(n, obj.p, osz.p, agg, moff, mem, s);
 }
 
 }  // namespace pcamg

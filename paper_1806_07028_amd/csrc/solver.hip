@@ -321,6 +321,9 @@ static bool make_tail_desc(Hierarchy& H, int start, TailDesc& D, hipStream_t s) 
   return true;
 }
 
+static std::unique_ptr<Hierarchy> assemble_hierarchy(pcamg_ctx* c, std::unique_ptr<Hierarchy> H,
+                                                     std::vector<NatLevel>& nat, bool laplacian_op);
+
 std::unique_ptr<Hierarchy> build_hierarchy(pcamg_ctx* c, const double* e_nat) {
   hipStream_t s = c->s;
   const pcamg_params& P = c->P;
@@ -382,7 +385,7 @@ std::unique_ptr<Hierarchy> build_hierarchy(pcamg_ctx* c, const double* e_nat) {
     L.moff.resize(L.n + 1);
     L.mem.resize(L.n);
     const int32_t nc = aggregate_level(L.n, L.grp, L.gci, L.gv, L.gkey, L.nb, L.pid.p, L.pos.p, L.plen.p, L.agg.p,
-                                       L.moff.p, L.mem.p, L.st, s);
+                                       L.moff.p, L.mem.p, L.st, s, P.case3);
     // stall (n_c > 0.9 n): this level becomes the coarsest if the dense solve
     // can take it; a larger level keeps coarsening while it still shrinks
     if (nc > 0.9 * L.n && (L.n <= LDLT_MAX || nc >= L.n)) {
@@ -430,6 +433,74 @@ std::unique_ptr<Hierarchy> build_hierarchy(pcamg_ctx* c, const double* e_nat) {
     C.colour = C.o_colour.p;
     nat.push_back(std::move(C));
   }
+  // the coarsest operator is a Laplacian when every prolongation is boolean
+  // (boolean mode, or no coarsening at all)
+  return assemble_hierarchy(c, std::move(H), nat, P.p1_mode == PCAMG_P1_CONST || nat.size() == 1);
+}
+
+// UA-AMG hierarchy by MWM aggregation on every level (the MWM_setup of
+// Alg. 5/6 Step 2, Sec. 2.1): boolean prolongations and Galerkin products.
+std::unique_ptr<Hierarchy> build_hierarchy_mwm(pcamg_ctx* c) {
+  hipStream_t s = c->s;
+  const pcamg_params& P = c->P;
+  auto H = std::make_unique<Hierarchy>();
+  std::vector<NatLevel> nat(1);
+  {
+    NatLevel& L0 = nat[0];
+    L0.n = c->n;
+    L0.nnz = c->nnz;
+    L0.rp = c->rp.p;
+    L0.ci = c->ci.p;
+    L0.av = c->av.p;
+    L0.d = c->d.p;
+    L0.dinv = c->dinv.p;
+    L0.colour = c->colour.p;
+    L0.ncol = c->ncol;
+  }
+  for (int l = 0;; ++l) {
+    NatLevel& L = nat[l];
+    if (L.n <= P.coarse_max || l + 1 >= P.max_levels) break;
+    L.agg.resize(L.n);
+    L.moff.resize(L.n + 1);
+    L.mem.resize(L.n);
+    const int32_t nc = mwm_aggregate_level(L.n, L.rp, L.ci, L.av, L.agg.p, L.moff.p, L.mem.p, L.st, s);
+    if (nc > 0.9 * L.n && (L.n <= LDLT_MAX || nc >= L.n)) {
+      L.agg.release();
+      L.moff.release();
+      L.mem.release();
+      break;
+    }
+    L.nc = nc;
+    NatLevel C;
+    C.n = nc;
+    C.o_rp.resize(nc + 1);
+    int64_t nnzc = galerkin_count(L.n, L.rp, L.ci, nc, L.moff.p, L.mem.p, L.agg.p, C.o_rp.p, false, s);
+    C.nnz = (int32_t)nnzc;
+    C.o_ci.resize(std::max<int64_t>(nnzc, 1));
+    C.o_av.resize(std::max<int64_t>(nnzc, 1));
+    C.o_d.resize(nc);
+    C.o_dinv.resize(nc);
+    galerkin_fill(L.n, L.rp, L.ci, L.av, L.d, nc, L.moff.p, L.mem.p, L.agg.p, nullptr, C.o_rp.p, C.o_ci.p,
+                  C.o_av.p, C.o_d.p, C.o_dinv.p, false, s);
+    C.o_colour.resize(nc);
+    C.ncol = colour_level(nc, C.o_rp.p, C.o_ci.p, P.colour_seed, l + 1, C.o_colour.p, s);
+    C.rp = C.o_rp.p;
+    C.ci = C.o_ci.p;
+    C.av = C.o_av.p;
+    C.d = C.o_d.p;
+    C.dinv = C.o_dinv.p;
+    C.colour = C.o_colour.p;
+    nat.push_back(std::move(C));
+  }
+  return assemble_hierarchy(c, std::move(H), nat, true);
+}
+
+// Solve layout, transfers, coarsest factor, statistics and cycle descriptors
+// of a hierarchy whose levels were built in natural numbering.
+static std::unique_ptr<Hierarchy> assemble_hierarchy(pcamg_ctx* c, std::unique_ptr<Hierarchy> H,
+                                                     std::vector<NatLevel>& nat, bool laplacian_op) {
+  hipStream_t s = c->s;
+  const pcamg_params& P = c->P;
   const int nl = (int)nat.size();
   NatLevel& Lc = nat.back();
   require(Lc.n <= 4096, PCAMG_EUNSUPPORTED, "coarsest level larger than 4096 vertices");
@@ -471,9 +542,7 @@ std::unique_ptr<Hierarchy> build_hierarchy(pcamg_ctx* c, const double* e_nat) {
                      V.T.pval.p, V.T.pval32.p, V.T.moff.p, V.T.mem.p, s);
   }
   // coarsest level: dense LDL^T; grounded iff the operator is a Laplacian
-  // (boolean prolongations everywhere, or no coarsening at all)
   {
-    const bool laplacian_op = P.p1_mode == PCAMG_P1_CONST || nl == 1;
     bool grounded = P.coarse_solve == PCAMG_COARSE_GROUNDED ? true
                     : P.coarse_solve == PCAMG_COARSE_FULL   ? false
                                                             : laplacian_op;
@@ -959,6 +1028,11 @@ void solve(pcamg_ctx* c, double* x_nat, pcamg_stats* st) {
       vc64 += nv;
       vc32 += nv32;
       copy_d2d(eb.p, corr, n, s);
+    } else if (P.rebuild_source == PCAMG_REBUILD_ITERATE) {
+      // Alg. 6: the current iterate itself (its normalisation is a scaling,
+      // which neither the key order nor the renormalised P_1 sees)
+      copy_d2d(eb.p, x.p, n, s);
+      fill_f64(corr, 0.0, n, s);
     } else {
       xi_fill(P.seed, Re, A.perm.p, eb.p, n, s);
       fill_f64(zero.p, 0.0, n, s);
@@ -967,7 +1041,7 @@ void solve(pcamg_ctx* c, double* x_nat, pcamg_stats* st) {
       fill_f64(corr, 0.0, n, s);
     }
     fill_f64(zero.p, 0.0, n, s);
-    relax_perm(c, eb.p, zero.p, P.relax_sweeps);
+    if (P.rebuild_source != PCAMG_REBUILD_ITERATE) relax_perm(c, eb.p, zero.p, P.relax_sweeps);
     scatter_f64(eb.p, A.perm.p, enat.p, n, s);
     Timer tb(s);
     c->hist.push_back(build_hierarchy(c, enat.p));

@@ -186,6 +186,8 @@ void ctx_init(pcamg_ctx* c, const pcamg_graph* g, const pcamg_params* p);
 void ctx_validate(pcamg_ctx* c);
 // Builds a hierarchy from a smooth error in natural order (device).
 std::unique_ptr<Hierarchy> build_hierarchy(pcamg_ctx* c, const double* e_nat);
+// The UA-AMG hierarchy of MWM aggregation (init = PCAMG_INIT_MWM).
+std::unique_ptr<Hierarchy> build_hierarchy_mwm(pcamg_ctx* c);
 // Relax A e = 0 with `sweeps` symmetric sweeps, natural-order device vector in place.
 void relax_homogeneous(pcamg_ctx* c, double* e_nat, int sweeps);
 void initial_error(pcamg_ctx* c, int32_t r, double* e_nat, int32_t sweeps = -1);  // sweeps < 0: relax_sweeps
@@ -195,6 +197,7 @@ int32_t net_num_params();
 void net_create(pcamg_net** out);
 void net_destroy(pcamg_net* net);
 void net_set_params(pcamg_net* net, const float* host, hipStream_t s);
+void net_init(pcamg_net* net, uint64_t seed, hipStream_t s);
 void net_get_params(pcamg_net* net, float* host, hipStream_t s);
 void net_forward_f32(pcamg_net* net, const pcamg_graph* g, const double* e2, float* y, hipStream_t s);
 void net_forward_f64(pcamg_net* net, const pcamg_graph* g, const double* e2, double* e, hipStream_t s);

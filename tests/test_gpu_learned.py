@@ -115,3 +115,54 @@ def test_training_gain(gpu, oracle, net_mod):
         x, st = s.solve()
         assert st["status"] == 0 and st["true_relres"] <= 1.0001e-8
     assert min(gains) > 0
+
+
+def test_seeded_initialiser_matches_definition(gpu, net_mod):
+    """pcamg_net_init: entry k = (2u - 1) lim rounded to float32, u from word
+    k + 1 of the SplitMix64 stream, lim the Glorot bound of its matrix, 0.1 for
+    the output weights, 0 for every bias -- recomputed here from the stream."""
+    from oracle import mpnn as M
+    for seed in (0, 7, 2**63 + 5):
+        net = net_mod.Net(seed=seed)
+        th = net.get_params()
+        u = I.uniform(seed, M.NPARAMS)
+        lim = []
+        for k, s in enumerate(M.SHAPES):
+            m = int(np.prod(s))
+            if len(s) == 2:
+                lim.append(np.full(m, np.sqrt(6.0 / (s[0] + s[1]))))
+            elif k == len(M.SHAPES) - 2:  # output weights
+                lim.append(np.full(m, 0.1))
+            else:
+                lim.append(np.zeros(m))
+        ref = ((2.0 * u - 1.0) * np.concatenate(lim)).astype(np.float32)
+        assert np.array_equal(th, ref), seed
+        net.close()
+
+
+def test_network_without_parameters_refused(gpu, net_mod, case):
+    """A network fresh from pcamg_net_create has no parameters: forward,
+    backward, Adam and the learned setup refuse it with PCAMG_EINVAL."""
+    import ctypes as C
+    from paper_1806_07028_amd import _lib
+    L = _lib.lib()
+    h = C.c_void_p()
+    _lib.check(L.pcamg_net_create(C.byref(h)))
+    try:
+        g = case
+        keep, gr = net_mod._graph((g[1], g[2], g[3]))
+        e2 = torch.zeros(g[0], dtype=torch.float64, device="cuda")
+        y = torch.empty(g[0], dtype=torch.float32, device="cuda")
+        st = net_mod._stream()
+        assert L.pcamg_net_forward(h, C.byref(gr), e2.data_ptr(), y.data_ptr(), st) == -1
+        loss = C.c_double()
+        assert L.pcamg_net_loss_grad(h, C.byref(gr), e2.data_ptr(), e2.data_ptr(), C.byref(loss), None, st) == -1
+        assert L.pcamg_net_adam_step(h, C.c_float(1e-3), st) == -1
+        p = _lib.default_params()
+        ctx = C.c_void_p()
+        assert L.pcamg_setup_learned(C.byref(gr), None, C.byref(p), h, st, C.byref(ctx)) == -1
+        # after the initialiser it works
+        _lib.check(L.pcamg_net_init(h, C.c_uint64(3), st))
+        _lib.check(L.pcamg_net_forward(h, C.byref(gr), e2.data_ptr(), y.data_ptr(), st))
+    finally:
+        L.pcamg_net_destroy(h)
