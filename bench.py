@@ -41,7 +41,7 @@ def parse():
                     help="lanes per matrix row (-1 autotuned, 0 by mean row length); default: the library's")
     ap.add_argument("--n0", type=int, default=4_000_000, help="powerlaw: vertices drawn before the largest "
                     "component is kept")
-    ap.add_argument("--workload", choices=["grid3d", "batch", "learned", "powerlaw"], default="grid3d",
+    ap.add_argument("--workload", choices=["grid3d", "batch", "learned", "powerlaw", "sweeps"], default="grid3d",
                     help="grid3d: the 128^3 weighted grid (the benchmark line); batch: uneven graphs solved "
                          "together (separate JSON line)")
     ap.add_argument("--cycle-prec", choices=["f64", "f32"], default=None,
@@ -325,6 +325,75 @@ def powerlaw_bench(args):
         "cpu_baseline": cpu}), flush=True)
 
 
+# The paper's printed iteration counts (Tables 1-6; MWM, Alg. 5 with theta 1e-6
+# and 0.4, Alg. 6): context on other hardware, software and readings.
+PAPER_TABLES = {
+    ("grid", "lfb"): {12: (278, 7, 13, 6), 14: (878, 9, 15, 7), 16: (1960, 10, 19, 9), 18: (None, 11, 21, 10)},
+    ("grid", "zsb"): {12: (269, 7, 14, 6), 14: (625, 8, 16, 7), 16: (1383, 10, 18, 8), 18: (None, 11, 20, 10)},
+    ("grid", "b0"): {12: (129, 16, 4), 14: (194, 16, 4), 16: (258, 16, 4), 18: (375, 16, 4)},
+    ("ring", "lfb"): {10: (149, 7, 14, 6), 12: (593, 10, 19, 9), 14: (2292, 12, 21, 11), 16: (None, 18, 24, 15)},
+    ("ring", "zsb"): {10: (144, 8, 14, 6), 12: (599, 10, 18, 10), 14: (2250, 14, 23, 12), 16: (None, 21, 25, 18)},
+    ("ring", "b0"): {10: (67, 15, 4), 12: (311, 15, 4), 14: (858, 15, 4), 16: (995, 15, 4)},
+}
+
+
+def sweeps_bench(args):
+    """The paper's synthetic sweeps (Sec. 4.1-4.2): unweighted 2D grids with
+    2^12..2^18 vertices and Watts-Strogatz rings (beta 0, mean degree 4) with
+    2^10..2^16 vertices; right-hand sides lfb = [1, ..., 1, 1 - n], zsb =
+    zero-mean N(0,1), and b = 0 from a random start; standalone V(1,1)-cycles
+    in FP64 to 1e-8 relative residual.  Methods as in the tables: UA-AMG with
+    MWM aggregation and no re-setup, Alg. 5 from the MWM hierarchy with theta
+    1e-6 and 0.4, Alg. 6 with theta 0.5.  One JSON line with every run."""
+    import numpy as np
+    import torch
+
+    import paper_1806_07028_amd as P
+    from paper_1806_07028_amd import inputs as I
+    cases = [("grid", e) for e in (12, 14, 16, 18)] + [("ring", e) for e in (10, 12, 14, 16)]
+    rows = []
+    for kind, ex in cases:
+        if kind == "grid":
+            side = 1 << (ex // 2)
+            g = I.grid2d(side, side)
+        else:
+            g = I.ring(1 << ex, 4)
+        n, rp, ci, w = g
+        dev = [torch.as_tensor(a, device="cuda") for a in (rp, ci, w)]
+        for rhs in ("lfb", "zsb", "b0"):
+            b = (I.low_frequency_rhs(n) if rhs == "lfb" else I.zero_mean_normal_rhs(7, n) if rhs == "zsb"
+                 else np.zeros(n))
+            x0 = None if rhs != "b0" else torch.as_tensor(2.0 * I.uniform(4321, n) - 1.0, device="cuda")
+            bd = torch.as_tensor(b, device="cuda")
+            methods = [("MWM", dict(init="mwm", max_rebuilds=0))]
+            if rhs == "b0":
+                methods.append(("A6", dict(theta=0.5, rebuild_rule=1, rebuild_source="iterate", init="mwm")))
+            else:
+                methods += [("A5(1)", dict(theta=1e-6, init="mwm")), ("A5(2)", dict(theta=0.4, init="mwm"))]
+            for name, kw in methods:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s = P.Solver(*dev, bd, outer="vcycle", max_iter=2500, **kw)
+                x, st = s.solve(x0=x0, raise_on_noconv=False)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                s.close()
+                row = {"graph": kind, "n": f"2^{ex}", "rhs": rhs, "method": name,
+                       "iter": st["iterations"] if st["status"] == 0 else None, "re": st["rebuilds"],
+                       "convr": round(st["convr_last10"], 4), "oc": round(st["op_complexity"], 3),
+                       "time_s": round(dt, 4), "status": st["status"]}
+                paper = PAPER_TABLES[(kind, rhs)][ex]
+                row["paper_iter"] = (paper[0] if name == "MWM" else paper[1] if name in ("A5(1)", "A6")
+                                     else paper[2])
+                rows.append(row)
+                log(json.dumps(row))
+    print(json.dumps({"metric": "iterations to 1e-8 rel. residual (paper's synthetic sweeps)",
+                      "unit": "iterations", "higher_is_better": False, "data": "synthetic", "dtype": "f64",
+                      "config": {"workload": "2D grids 2^12..2^18 and rings 2^10..2^16, rhs lfb / zsb / b=0; "
+                                             "UA-AMG (MWM), Alg. 5 theta 1e-6 and 0.4 from MWM, Alg. 6 theta 0.5"},
+                      "runs": rows}), flush=True)
+
+
 def learned_bench(args):
     """Learned smooth-error proposals: train the network on random geometric
     graphs (n log-uniform on [1e4, 1e5], mean degree 8, weights 10^(-3+6u))
@@ -418,6 +487,9 @@ def main():
         return
     if args.workload == "powerlaw":
         powerlaw_bench(args)
+        return
+    if args.workload == "sweeps":
+        sweeps_bench(args)
         return
     import numpy as np
     import torch

@@ -101,7 +101,7 @@ typedef struct {
   int32_t w_dense;         /* 1 = in W-cycles, the two sub-cycles of the first level of at most
                               dense_max_n vertices are applied as one precomputed dense operator
                               (equal up to rounding order; built level by level from the coarsest
-                              on first use per hierarchy and precision, GEMMs through rocBLAS);
+                              on first use per hierarchy and precision, GEMMs on the matrix cores);
                               0 = recurse */
   int32_t first_sweeps;    /* symmetric sweeps before the first build: -1 = relax_sweeps; with
                               pcamg_setup_learned the sweeps of the network's input (-1: 2) */
@@ -118,7 +118,7 @@ typedef struct {
                               below the finest (at or above the single-workgroup tail) is applied
                               by the level above as one precomputed dense operator (equal up to
                               rounding order; built level by level from the coarsest on first use
-                              per hierarchy and precision, GEMMs through rocBLAS).  0 = recurse
+                              per hierarchy and precision, GEMMs on the matrix cores).  0 = recurse
                               (2048) */
   uint64_t seed;           /* start-vector stream */
   uint64_t colour_seed;    /* colouring priority stream */
@@ -250,6 +250,24 @@ pcamg_status pcamg_approx_error(pcamg_ctx* c, int32_t count, const double* r, do
  * x written, x read once, b, dinv). */
 pcamg_status pcamg_bench_smoother(pcamg_ctx* c, int32_t prec, int32_t sweeps, double* ms, int64_t* launches,
                                   double* bytes);
+
+/* Roofline measurement on the finest level of the context, in the solve
+ * layout and launch configuration of the cycles.  Each of `reps`
+ * repetitions first writes flush_bytes (0 = none) of a scratch buffer, so
+ * that the last-level cache holds none of the level, then runs between HIP
+ * events on the context's stream either one forward multicoloured
+ * Gauss-Seidel sweep (kind 0, colours 0..C-1) or one residual r = b - A x
+ * (kind 1), in precision prec.  Outputs (host): summed event milliseconds,
+ * kernel launches timed, algorithmic bytes = reps x ((s+4) nnz + 4 (n+1) +
+ * 4 s n), s = 8 (FP64) or 4 (FP32): matrix values and columns, row pointers,
+ * x written / read once, b, dinv (GS) or d, x, b, r (residual). */
+pcamg_status pcamg_bench_level(pcamg_ctx* c, int32_t kind, int32_t prec, int32_t reps, int64_t flush_bytes,
+                               double* ms, int64_t* launches, double* bytes);
+
+/* Device-copy ceiling: `reps` copies of `bytes` (rounded down to 16) between
+ * two device buffers by this library's streaming copy kernel, timed with HIP
+ * events on `stream`; *ms (host) is the total.  Each copy moves 2 x bytes. */
+pcamg_status pcamg_bench_copy(int64_t bytes, int32_t reps, void* stream, double* ms);
 
 /* Smooth error of the first build: start vector of build 0 (SplitMix64
  * stream p->seed) and relax_sweeps symmetric sweeps on A e = 0. device [n]. */

@@ -574,6 +574,23 @@ pcamg_status pcamg_bench_smoother(pcamg_ctx* c, int32_t prec, int32_t sweeps, do
   });
 }
 
+pcamg_status pcamg_bench_level(pcamg_ctx* c, int32_t kind, int32_t prec, int32_t reps, int64_t flush_bytes,
+                               double* ms, int64_t* launches, double* bytes) {
+  return guarded_s(c ? c->s : nullptr, [&] {
+    require(c && ms && launches && bytes && reps >= 1 && (kind == 0 || kind == 1) && flush_bytes >= 0 &&
+                (prec == PCAMG_PREC_F64 || prec == PCAMG_PREC_F32),
+            PCAMG_EINVAL, "bad argument");
+    bench_level(c, kind, prec, reps, flush_bytes, ms, launches, bytes);
+  });
+}
+
+pcamg_status pcamg_bench_copy(int64_t bytes, int32_t reps, void* stream, double* ms) {
+  return guarded_s(as_stream(stream), [&] {
+    require(bytes >= 16 && reps >= 1 && ms, PCAMG_EINVAL, "bad argument");
+    *ms = bench_copy(bytes, reps, as_stream(stream));
+  });
+}
+
 pcamg_status pcamg_initial_error(pcamg_ctx* c, double* e) {
   return guarded_s(c ? c->s : nullptr, [&] {
     require(c && e, PCAMG_EINVAL, "null argument");

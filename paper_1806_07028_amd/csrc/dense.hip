@@ -17,25 +17,119 @@
 //
 // The colour passes, residuals and transfers are the cycle's own row
 // formulas (fma chains in CSR / member order) evaluated for all columns; the
-// two products with dense matrices are GEMMs.  The result is the same linear
-// map as the recursion with a different rounding order.
-#include <rocblas/rocblas.h>
-
-#include <map>
-#include <mutex>
-
+// two products with dense matrices are GEMMs on the matrix cores (this file's
+// MFMA kernel).  The result is the same linear map as the recursion with a
+// different rounding order.
 #include "rowchain.hpp"
 #include "solver.hpp"
 
 namespace pcamg {
 namespace {
 
-#define PCAMG_BLAS(expr)                                                                               \
-  do {                                                                                                 \
-    const rocblas_status st_ = (expr);                                                                 \
-    if (st_ != rocblas_status_success)                                                                 \
-      throw Error(PCAMG_EHIP, std::string("rocBLAS: ") + rocblas_status_to_string(st_) + " in " #expr); \
-  } while (0)
+// ---------------------------------------------------------------------------
+// Dense GEMM on the matrix cores: P = alpha Q R + beta P, all row-major
+// (P: p x r, Q: p x q, R: q x r, each with its column count as stride).
+// A workgroup of four wavefronts (2 x 2) computes a BM x BN tile of P; each
+// wavefront a (BM/2) x (BN/2) block of 16 x 16 MFMA tiles
+// (v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64, 16 x 4 times 4 x 16 per
+// instruction).  K advances in slices of 16 staged through LDS, zero-filled
+// past the matrix edges.  Lane l of a 16 x 16 x 4 product supplies A[l % 16][l
+// / 16] and B[l / 16][l % 16]; its four results v = 0..3 are D[i][l % 16] with
+// i = 4 (l / 16) + v for the FP32 instruction and i = l / 16 + 4 v for the FP64
+// one (both layouts checked on the device).
+// Each entry of P is accumulated by one lane in a fixed order (K ascending,
+// four products per instruction), so the result is the same on every run.
+// ---------------------------------------------------------------------------
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  using acc_t = f32x4_t;
+  static constexpr int BM = 128, BN = 128;
+  static __device__ __forceinline__ acc_t step(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int v) { return 4 * lk + v; }
+};
+template <>
+struct Mfma<double> {
+  using acc_t = f64x4_t;
+  static constexpr int BM = 64, BN = 64;
+  static __device__ __forceinline__ acc_t step(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int v) { return lk + 4 * v; }
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    gemm_mfma_kernel(int32_t p, int32_t q, int32_t r, T alpha, const T* __restrict__ Q, const T* __restrict__ R,
+                     T beta, T* __restrict__ P) {
+  constexpr int BM = Mfma<T>::BM, BN = Mfma<T>::BN, BK = 16;
+  constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
+  __shared__ T As[BK][BM + 4];  // k-major: a lane's A operand is As[k][row]
+  __shared__ T Bs[BK][BN + 4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int32_t row0 = (int32_t)blockIdx.y * BM, col0 = (int32_t)blockIdx.x * BN;
+  typename Mfma<T>::acc_t acc[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) acc[a][b] = typename Mfma<T>::acc_t{0, 0, 0, 0};
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int32_t k0 = 0; k0 < q; k0 += BK) {
+    for (int e = tid; e < BM * BK; e += 256) {
+      const int i = e / BK, k = e % BK;
+      const int32_t gi = row0 + i, gk = k0 + k;
+      As[k][i] = (gi < p && gk < q) ? Q[(size_t)gi * q + gk] : (T)0;
+    }
+    for (int e = tid; e < BK * BN; e += 256) {
+      const int k = e / BN, j = e % BN;
+      const int32_t gk = k0 + k, gj = col0 + j;
+      Bs[k][j] = (gk < q && gj < r) ? R[(size_t)gk * r + gj] : (T)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      T av[FM], bv[FN];
+#pragma unroll
+      for (int a = 0; a < FM; ++a) av[a] = As[kk + lk][wm * WM + a * 16 + lr];
+#pragma unroll
+      for (int b = 0; b < FN; ++b) bv[b] = Bs[kk + lk][wn * WN + b * 16 + lr];
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = Mfma<T>::step(av[a], bv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int32_t gi = row0 + wm * WM + a * 16 + Mfma<T>::row(lk, v), gj = col0 + wn * WN + b * 16 + lr;
+        if (gi < p && gj < r) {
+          const size_t o = (size_t)gi * r + gj;
+          const T t = alpha * acc[a][b][v];
+          P[o] = beta == (T)0 ? t : fma(beta, P[o], t);
+        }
+      }
+}
+
+// Row-major P = alpha Q R + beta P (p x q times q x r).
+template <typename T>
+void gemm_rows(int32_t p, int32_t q, int32_t r, T alpha, const T* Q, const T* R, T beta, T* P, hipStream_t s) {
+  if (p <= 0 || r <= 0) return;
+  const dim3 grid((unsigned)((r + Mfma<T>::BN - 1) / Mfma<T>::BN), (unsigned)((p + Mfma<T>::BM - 1) / Mfma<T>::BM));
+  gemm_mfma_kernel<T><<<grid, 256, 0, s>>>(p, q, r, alpha, Q, R, beta, P);
+  PCAMG_LAUNCHED();
+}
 
 // Z[i * n + j] = (coarsest solve of e_j)_i: one workgroup per column, the
 // arithmetic and order of the cycle's coarsest solve (FP64 accumulator in
@@ -178,11 +272,6 @@ struct LevelOf<double> {
   static const double* d(const LevelMatrix& A) { return A.d.p; }
   static const double* dinv(const LevelMatrix& A) { return A.dinv.p; }
   static const double* pval(const Transfer& T) { return T.pval.p; }
-  static rocblas_status gemm(rocblas_handle h, int m, int n, int k, double alpha, const double* A, int lda,
-                             const double* B, int ldb, double beta, double* C, int ldc) {
-    return rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, m, n, k, &alpha, A, lda, B, ldb, &beta, C,
-                         ldc);
-  }
 };
 template <>
 struct LevelOf<float> {
@@ -190,69 +279,20 @@ struct LevelOf<float> {
   static const float* d(const LevelMatrix& A) { return A.d32.p; }
   static const float* dinv(const LevelMatrix& A) { return A.dinv32.p; }
   static const float* pval(const Transfer& T) { return T.pval32.p; }
-  static rocblas_status gemm(rocblas_handle h, int m, int n, int k, float alpha, const float* A, int lda,
-                             const float* B, int ldb, float beta, float* C, int ldc) {
-    return rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_none, m, n, k, &alpha, A, lda, B, ldb, &beta, C,
-                         ldc);
-  }
-};
-
-// Row-major P = Q R (p x q times q x r) through the column-major GEMM:
-// P^T = R^T Q^T, every matrix dense with its own column count as stride.
-template <typename T>
-void gemm_rows(rocblas_handle h, int32_t p, int32_t q, int32_t r, T alpha, const T* Q, const T* R, T beta, T* P) {
-  PCAMG_BLAS(LevelOf<T>::gemm(h, r, p, q, alpha, R, r, Q, q, beta, P, r));
-}
-
-// One rocBLAS handle per device for the life of the process, with a
-// workspace of ours, used by one build at a time: builds from concurrent
-// solves (caller threads with contexts of their own) take turns, and no handle
-// or workspace is created or destroyed -- no allocation or free inside
-// rocBLAS -- while other threads capture graphs.
-constexpr size_t BLAS_WORKSPACE = (size_t)128 << 20;
-
-struct BlasLease {
-  static std::mutex& mu() {
-    static std::mutex m;
-    return m;
-  }
-  std::lock_guard<std::mutex> lk;
-  rocblas_handle h = nullptr;
-  explicit BlasLease(hipStream_t s) : lk(mu()) {
-    static std::map<int, rocblas_handle> handles;  // guarded by mu()
-    int dev = 0;
-    PCAMG_HIP(hipGetDevice(&dev));
-    auto it = handles.find(dev);
-    if (it == handles.end()) {
-      rocblas_initialize();
-      rocblas_handle nh = nullptr;
-      PCAMG_BLAS(rocblas_create_handle(&nh));
-      // no split-k atomics: the same operator on every run
-      PCAMG_BLAS(rocblas_set_atomics_mode(nh, rocblas_atomics_not_allowed));
-      // a workspace of our own, allocated once: rocBLAS then never allocates
-      // or frees device memory during a solve
-      void* ws = nullptr;
-      PCAMG_HIP(hipMalloc(&ws, BLAS_WORKSPACE));
-      PCAMG_BLAS(rocblas_set_workspace(nh, ws, BLAS_WORKSPACE));
-      it = handles.emplace(dev, nh).first;
-    }
-    h = it->second;
-    PCAMG_BLAS(rocblas_set_stream(h, s));
-  }
 };
 
 // Operator of two consecutive calls of a level's cycle from x = 0, whose single
 // call is W (m x m, row-major): x0 = W b, x1 = x0 + W (b - A x0), i.e.
 // 2 W - W (A W).
 template <typename T>
-DVec<T> two_calls(rocblas_handle h, const LevelMatrix& A, const DVec<T>& W, hipStream_t s) {
+DVec<T> two_calls(const LevelMatrix& A, const DVec<T>& W, hipStream_t s) {
   const int32_t m = A.n;
   DVec<T> AW((size_t)m * m), Cop((size_t)m * m);
   blk_apply_kernel<T><<<rows_grid(m, m), 256, 0, s>>>(m, A.rp.p, A.ci.p, LevelOf<T>::av(A), LevelOf<T>::d(A), W.p,
                                                        AW.p, 0);
   PCAMG_LAUNCHED();
   copy_d2d(Cop.p, W.p, (size_t)m * m, s);
-  gemm_rows<T>(h, m, m, m, (T)-1, W.p, AW.p, (T)2, Cop.p);
+  gemm_rows<T>(m, m, m, (T)-1, W.p, AW.p, (T)2, Cop.p, s);
   return Cop;
 }
 
@@ -271,7 +311,6 @@ void dense_bottom_up(Hierarchy& H, int d, int gamma, T* C, hipStream_t s) {
   const int nl = (int)H.lv.size();
   require(d >= 0 && nl - d >= 2 && dense_bottom_up_fits(H, d) && (gamma == 1 || gamma == 2), PCAMG_EINVAL,
           "no dense region for the bottom-up build");
-  BlasLease blas(s);  // held until the build has completed on s
   // Z: the coarsest operator on the identity
   const int32_t cn = H.cn;
   DVec<T> W(std::max<size_t>((size_t)cn * cn, 1));
@@ -288,7 +327,7 @@ void dense_bottom_up(Hierarchy& H, int d, int gamma, T* C, hipStream_t s) {
     DVec<T> Cop;
     const T* Cl = W.p;
     if (gamma == 2 && l + 2 < nl) {
-      Cop = two_calls<T>(blas.h, *H.lv[l + 1].A, W, s);
+      Cop = two_calls<T>(*H.lv[l + 1].A, W, s);
       Cl = Cop.p;
     }
     // the cycle of level l on the identity
@@ -306,7 +345,7 @@ void dense_bottom_up(Hierarchy& H, int d, int gamma, T* C, hipStream_t s) {
     PCAMG_LAUNCHED();
     blk_restrict_kernel<T><<<rows_grid(n, m), 256, 0, s>>>(n, Tr.moff.p, Tr.mem.p, LevelOf<T>::pval(Tr), R.p, Bc.p);
     PCAMG_LAUNCHED();
-    gemm_rows<T>(blas.h, m, m, n, (T)1, Cl, Bc.p, (T)0, Xc.p);
+    gemm_rows<T>(m, m, n, (T)1, Cl, Bc.p, (T)0, Xc.p, s);
     blk_prolong_kernel<T><<<rows_grid(n, n), 256, 0, s>>>(n, Tr.agg.p, LevelOf<T>::pval(Tr), Xc.p, X.p);
     PCAMG_LAUNCHED();
     for (int k = A.ncol - 1; k >= 0; --k) {
@@ -320,7 +359,7 @@ void dense_bottom_up(Hierarchy& H, int d, int gamma, T* C, hipStream_t s) {
   // the level above applies gamma calls of level d's cycle from x = 0
   const int32_t nd = H.lv[d].A->n;
   DVec<T> Cd;
-  if (gamma == 2) Cd = two_calls<T>(blas.h, *H.lv[d].A, W, s);
+  if (gamma == 2) Cd = two_calls<T>(*H.lv[d].A, W, s);
   const T* src = gamma == 2 ? Cd.p : W.p;
   blk_transpose_kernel<T><<<dim3((nd + 31) / 32, (nd + 31) / 32), 256, 0, s>>>(nd, src, C);
   PCAMG_LAUNCHED();

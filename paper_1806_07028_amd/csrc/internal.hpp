@@ -255,6 +255,11 @@ void sorted_endpoints(int32_t m, const uint32_t* order, const int32_t* eu, const
 int32_t path_cover(int32_t n, int32_t m, const int32_t* su, const int32_t* sv, int32_t* nb, hipStream_t s);
 // Pointer-jumping orientation: path_id, pos, plen (synchronises).
 void orient_paths(int32_t n, const int32_t* nb, int32_t* path_id, int32_t* pos, int32_t* plen, hipStream_t s);
+// The same on a caller's device workspace of orient_ws_ints(n) int32 (no
+// allocation; every entry the kernels read is written first).
+inline size_t orient_ws_ints(int32_t n) { return 12 * (size_t)n + 1; }
+void orient_paths_ws(int32_t n, const int32_t* nb, int32_t* path_id, int32_t* pos, int32_t* plen, int32_t* ws,
+                     hipStream_t s);
 
 struct AggStats {
   int32_t n_unagg = 0, case1 = 0, case2 = 0, case3 = 0, middle = 0, singleton = 0, p1_fallback = 0;

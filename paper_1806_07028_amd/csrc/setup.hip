@@ -530,23 +530,33 @@ __global__ void pj_final_kernel(int32_t n, const int32_t* __restrict__ nb, const
   plen[v] = d0 + d1 + 1;
 }
 
-void orient_paths(int32_t n, const int32_t* nb, int32_t* path_id, int32_t* pos, int32_t* plen, hipStream_t s) {
+void orient_paths_ws(int32_t n, const int32_t* nb, int32_t* path_id, int32_t* pos, int32_t* plen, int32_t* ws,
+                     hipStream_t s) {
   if (n <= 0) return;
-  const int32_t nh = 2 * n;
-  DVec<int32_t> nx(nh), ds(nh), en(nh), nx2(nh), ds2(nh), en2(nh), act(1);
-  pj_init_kernel<<<grid_for(nh, 256), 256, 0, s>>>(n, nb, nx.p, ds.p, en.p);
+  const size_t nh = 2 * (size_t)n;
+  // workspace: six half-edge arrays (next, distance, end; double-buffered) and
+  // the "still jumping" flag, which is cleared before every round
+  int32_t *nx = ws, *ds = ws + nh, *en = ws + 2 * nh, *nx2 = ws + 3 * nh, *ds2 = ws + 4 * nh, *en2 = ws + 5 * nh;
+  int32_t* act = ws + 6 * nh;
+  pj_init_kernel<<<grid_for(nh, 256), 256, 0, s>>>(n, nb, nx, ds, en);
   PCAMG_LAUNCHED();
   for (int it = 0; it < 64; ++it) {
-    fill_i32(act.p, 0, 1, s);
-    pj_jump_kernel<<<grid_for(nh, 256), 256, 0, s>>>(nh, nx.p, ds.p, en.p, nx2.p, ds2.p, en2.p, act.p);
+    fill_i32(act, 0, 1, s);
+    pj_jump_kernel<<<grid_for(nh, 256), 256, 0, s>>>((int32_t)nh, nx, ds, en, nx2, ds2, en2, act);
     PCAMG_LAUNCHED();
     std::swap(nx, nx2);
     std::swap(ds, ds2);
     std::swap(en, en2);
-    if (!read_scalar(act.p, s)) break;
+    if (!read_scalar(act, s)) break;
   }
-  pj_final_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, nb, ds.p, en.p, path_id, pos, plen);
+  pj_final_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, nb, ds, en, path_id, pos, plen);
   PCAMG_LAUNCHED();
+}
+
+void orient_paths(int32_t n, const int32_t* nb, int32_t* path_id, int32_t* pos, int32_t* plen, hipStream_t s) {
+  if (n <= 0) return;
+  DVec<int32_t> ws(orient_ws_ints(n));
+  orient_paths_ws(n, nb, path_id, pos, plen, ws.p, s);
 }
 
 // ---------------------------------------------------------------------------

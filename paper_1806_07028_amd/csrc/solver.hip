@@ -1224,4 +1224,101 @@ void bench_smoother(pcamg_ctx* c, int prec, int sweeps, double* ms, int64_t* lau
   *bytes = per_sweep * 2.0 * sweeps;
 }
 
+// ---------------------------------------------------------------------------
+// Roofline measurement on the finest level.  Each repetition first writes
+// flush_bytes of a scratch buffer (so the 256 MB last-level cache holds none
+// of the level's data), then times one forward Gauss-Seidel sweep (kind 0:
+// colours 0..C-1, the kernels and launch configuration of the cycles) or one
+// residual r = b - A x (kind 1) between HIP events on the context's stream.
+// Algorithmic bytes per repetition: matrix values and columns, row pointers,
+// and per row x written (GS only), x read once, b, dinv (GS) or d and r
+// (residual); re-gathered x of neighbouring rows is not counted.
+// ---------------------------------------------------------------------------
+namespace {
+__global__ void flush_kernel(float4* __restrict__ a, size_t n, float v) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    a[i] = make_float4(v, v, v, v);
+}
+__global__ void copy_kernel(const float4* __restrict__ a, float4* __restrict__ b, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+}  // namespace
+
+void bench_level(pcamg_ctx* c, int kind, int prec, int reps, int64_t flush_bytes, double* ms, int64_t* launches,
+                 double* bytes) {
+  hipStream_t s = c->s;
+  const LevelMatrix& A = *c->M0;
+  const int32_t n = A.n;
+  const double vs = prec == PCAMG_PREC_F32 ? 4.0 : 8.0;
+  const double per = (vs + 4.0) * A.nnz + 4.0 * (n + 1.0) + (kind == 0 ? 4.0 : 4.0) * vs * n;
+  DVec<double> b(n), x(n), r(n);
+  DVec<float> b32(n), x32(n), r32(n);
+  xi_fill(c->P.seed, 7, nullptr, b.p, n, s);
+  xi_fill(c->P.seed, 8, nullptr, x.p, n, s);
+  cast_f64_f32(b.p, b32.p, n, s);
+  cast_f64_f32(x.p, x32.p, n, s);
+  const size_t nf = flush_bytes > 0 ? (size_t)flush_bytes / sizeof(float4) : 0;
+  DVec<float4> fl(nf);
+  hipEvent_t e0, e1;
+  PCAMG_HIP(hipEventCreate(&e0));
+  PCAMG_HIP(hipEventCreate(&e1));
+  int64_t nl = 0;
+  auto body = [&]() {
+    if (kind == 0) {
+      for (int k = 0; k < A.ncol; ++k) {
+        if (prec == PCAMG_PREC_F32) smooth_colour(A, k, b32.p, x32.p, s);
+        else smooth_colour(A, k, b.p, x.p, s);
+        nl += A.sell() || A.long_min == 0 ? 1 : 2;
+      }
+    } else {
+      if (prec == PCAMG_PREC_F32) level_residual(A, b32.p, x32.p, r32.p, s);
+      else level_residual(A, b.p, x.p, r.p, s);
+      nl += A.sell() || A.long_min == 0 ? 1 : 2;
+    }
+  };
+  double total = 0.0;
+  try {
+    body();  // warm-up
+    nl = 0;
+    for (int q = 0; q < reps; ++q) {
+      if (nf) {
+        flush_kernel<<<1024, 256, 0, s>>>(fl.p, nf, (float)q);
+        PCAMG_LAUNCHED();
+      }
+      PCAMG_HIP(hipEventRecord(e0, s));
+      body();
+      PCAMG_HIP(hipEventRecord(e1, s));
+      PCAMG_HIP(hipEventSynchronize(e1));
+      float t = 0.0f;
+      PCAMG_HIP(hipEventElapsedTime(&t, e0, e1));
+      total += t;
+    }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = total;
+  *launches = nl;
+  *bytes = per * reps;
+}
+
+double bench_copy(int64_t nbytes, int reps, hipStream_t s) {
+  const size_t n = (size_t)nbytes / sizeof(float4);
+  DVec<float4> a(n), b(n);
+  flush_kernel<<<1024, 256, 0, s>>>(a.p, n, 1.0f);
+  PCAMG_LAUNCHED();
+  copy_kernel<<<2048, 256, 0, s>>>(a.p, b.p, n);  // warm-up
+  PCAMG_LAUNCHED();
+  Timer t(s);
+  for (int q = 0; q < reps; ++q) {
+    copy_kernel<<<2048, 256, 0, s>>>(a.p, b.p, n);
+    PCAMG_LAUNCHED();
+  }
+  return t.ms();
+}
+
 }  // namespace pcamg

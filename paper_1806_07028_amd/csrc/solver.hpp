@@ -226,5 +226,8 @@ int32_t dense_chunks(int32_t n);
 // Alg. 2 on permuted vectors.
 void approx_error(pcamg_ctx* c, int Re, const double* r, double* e, int* wcycles, int* vcycles, int* vcycles32);
 void bench_smoother(pcamg_ctx* c, int prec, int sweeps, double* ms, int64_t* launches, double* bytes);
+void bench_level(pcamg_ctx* c, int kind, int prec, int reps, int64_t flush_bytes, double* ms, int64_t* launches,
+                 double* bytes);
+double bench_copy(int64_t nbytes, int reps, hipStream_t s);
 void solve(pcamg_ctx* c, double* x_nat, pcamg_stats* st);
 }  // namespace pcamg

@@ -139,3 +139,15 @@ def shorten(nb, nc: int, agg):
     nbc = _e(2 * nc, i32)
     _lib.check(lib().pcamg_shorten(n, nb.data_ptr(), nc, agg.data_ptr(), nbc.data_ptr(), _s()))
     return nbc[: 2 * nc].view(nc, 2)
+
+
+def mwm_aggregate(rp, ci, aval):
+    """MWM aggregation (Sec. 2.1) of a level with off-diagonal entries aval."""
+    rp, ci, aval = _d(rp, i32), _d(ci, i32), _d(aval, f64)
+    n = rp.numel() - 1
+    agg = _e(n, i32)
+    nc = C.c_int32()
+    stats = (C.c_int32 * 3)()
+    _lib.check(lib().pcamg_mwm_aggregate(n, rp.data_ptr(), ci.data_ptr(), aval.data_ptr(), agg.data_ptr(),
+                                         C.byref(nc), stats, _s()))
+    return agg[:n], nc.value, dict(zip(["n_unagg", "joined", "singleton"], list(stats)))
