@@ -1,22 +1,28 @@
 """Benchmark: time to 1e-8 relative residual for PC-alphaAMG on MI355X.
 
-Workload (one step = the whole hot path once): the ill-conditioned 3D graph
-Laplacian -- 7-point 128^3 grid (2,097,152 vertices), edge weights
-log-uniform on [1e-3, 1e3], zero-mean N(0,1) right-hand side -- set up from
-scratch (validation, Laplacian, colouring, A^2 pattern, first hierarchy) and
-solved to 1e-8 relative residual by FCG(1) in FP64 with an FP32 V(1,1)-cycle
-preconditioner, re-setup when the mean convergence factor since the last
-re-setup exceeds 0.5, each re-setup's error from Alg. 2 with the paper's
-numW = 2, iterW = 7, iterV = 4 (FP32 cycles).  Inputs are synthetic and
-already resident in HBM when the timed region starts.
+Headline workload (one step = the whole hot path once): the Chung-Lu
+power-law graph Laplacian -- 4,000,000 vertices drawn (exponent 2.1, mean
+degree 16), largest component kept (3,926,673 vertices, 32,002,743 edges),
+weights uniform in (0, 1], zero-mean N(0,1) right-hand side -- validated,
+set up from scratch (Laplacian, colouring, A^2 pattern with the hub cap 64,
+first hierarchy) and solved to 1e-8 relative residual by FCG(1) in FP64
+preconditioned by FP64 V(1,1)-cycles, re-setup (Alg. 2, numW = 2, iterW = 7,
+iterV = 4) when the mean convergence factor since the last re-setup exceeds
+0.5.  Inputs are synthetic and already resident in HBM when the timed region
+starts.
 
-Prints one JSON line.  Also reported: the convergence factor, the FP64
-standalone V-cycle variant, the smoother's HBM roofline fraction (HIP-event
-timed inside this process) and the CPU oracle on a bounded sample.
+Prints one JSON line.  Also reported: the convergence factor (geometric
+mean of the solve, and the paper's ConvR of standalone V-cycles on a fixed
+hierarchy for the path-cover and the MWM hierarchies), the same solve with
+FP32 cycles, the 128^3 weighted grid in both precisions, the finest-level
+smoother and residual against HBM with the last-level cache flushed
+(HIP-event timed inside this process), a device-copy ceiling, and the CPU
+oracle on a bounded sample.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes as C
 import json
 import os
 import sys
@@ -26,6 +32,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FLUSH_BYTES = 1 << 30   # read between timed passes: four times the 256 MB last-level cache
+ROOF_REPS = 10
 
 
 def parse():
@@ -33,28 +41,24 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--side", type=int, default=128)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64-variant", action="store_true")
-    ap.add_argument("--numW", type=int, default=2, help="re-setups whose error approximation uses W-cycles (Alg. 2)")
-    ap.add_argument("--row-lanes", type=int, default=None,
-                    help="lanes per matrix row (-1 autotuned, 0 by mean row length); default: the library's")
+    ap.add_argument("--workload", choices=["powerlaw", "grid3d", "batch", "learned", "sweeps"], default="powerlaw",
+                    help="powerlaw: the 4M Chung-Lu graph (the benchmark line); grid3d: the 128^3 weighted grid; "
+                         "batch, learned, sweeps: separate JSON lines")
+    ap.add_argument("--cycle-prec", choices=["f64", "f32"], default=None,
+                    help="precision of the preconditioning cycles (default: f64 for powerlaw, f32 for grid3d)")
     ap.add_argument("--n0", type=int, default=4_000_000, help="powerlaw: vertices drawn before the largest "
                     "component is kept")
-    ap.add_argument("--workload", choices=["grid3d", "batch", "learned", "powerlaw", "sweeps"], default="grid3d",
-                    help="grid3d: the 128^3 weighted grid (the benchmark line); batch: uneven graphs solved "
-                         "together (separate JSON line)")
-    ap.add_argument("--cycle-prec", choices=["f64", "f32"], default=None,
-                    help="precision of the preconditioning cycles (default: the workload's)")
+    ap.add_argument("--side", type=int, default=128, help="grid3d: side of the cube")
+    ap.add_argument("--numW", type=int, default=2, help="re-setups whose error approximation uses W-cycles (Alg. 2)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline only: no mixed-precision run, no grid runs, no fixed-hierarchy ConvR")
     ap.add_argument("--count", type=int, default=512, help="batch: number of graphs")
     ap.add_argument("--workers", type=int, default=1, help="batch: workers passed to the library (must be 1: "
                     "the calling thread; several host threads are switched off)")
     ap.add_argument("--train-count", type=int, default=64, help="learned: training graphs")
     ap.add_argument("--epochs", type=int, default=10, help="learned: training epochs")
     ap.add_argument("--eval-n", type=int, default=1_000_000, help="learned: vertices of the evaluation graph")
-    ap.add_argument("--roofline-only", action="store_true",
-                    help="set up, time the finest-level smoother sweeps and a 256 MiB device copy (the reference "
-                         "kernel for counter calibration), print one JSON line and exit")
     return ap.parse_args()
 
 
@@ -62,124 +66,241 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(g, b, st_gpu, side, numW):
-    """Oracle (single-threaded CPU) on a bounded sample of the same workload:
-    one hierarchy build, FP32 V-cycles (and an FP32 W-cycle / FP64 V-cycle when
-    the solve used them) on the full problem, extrapolated with the solve's own
-    build and cycle counts."""
-    import numpy as np
-
-    import oracle
-
-    t0 = time.perf_counter()
-    H = oracle.Hierarchy(g, None, theta=0.5, outer=1, cycle_prec=1, numW=numW)
-    t_build = time.perf_counter() - t0
-    b32 = b.astype(np.float32)
-    t0 = time.perf_counter()
-    for _ in range(2):
-        H.cycle32(b32, None, 1)
-    t_v32 = (time.perf_counter() - t0) / 2
-    t_w32 = t_v64 = 0.0
-    if st_gpu["wcycles"]:
-        t0 = time.perf_counter()
-        H.cycle32(b32, None, 2)
-        t_w32 = time.perf_counter() - t0
-    if st_gpu["vcycles64"]:
-        t0 = time.perf_counter()
-        H.cycle(b, None, 1)
-        t_v64 = time.perf_counter() - t0
-    builds = 1 + st_gpu["rebuilds"]
-    est = t_build * builds + t_v32 * st_gpu["vcycles32"] + t_v64 * st_gpu["vcycles64"] + t_w32 * st_gpu["wcycles"]
-    return {"value": round(est, 3), "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle on the full {side}^3 problem: 1 hierarchy build ({t_build:.2f} s), FP32 V-cycle "
-                       f"{t_v32:.3f} s, FP32 W-cycle {t_w32:.3f} s, FP64 V-cycle {t_v64:.3f} s (timed once each); "
-                       f"extrapolated with the GPU solve's {builds} builds, {st_gpu['vcycles32']} FP32 V-, "
-                       f"{st_gpu['wcycles']} FP32 W- and {st_gpu['vcycles64']} FP64 V-cycles")}
-
-
-SMOOTHER_SWEEPS = 20
-
-
-def smoother_roofline(s):
-    """HIP-event timed symmetric multicoloured GS sweeps on the finest level
-    (same kernels and launch configuration as inside the cycles), FP32 and
-    FP64: algorithmic bytes per launch and GB/s."""
-    import ctypes as C
-
+# ---------------------------------------------------------------------------
+# Measurement helpers (all timing inside the library, HIP events on its stream)
+# ---------------------------------------------------------------------------
+def level_roofline(s, kind: int, prec: int, reps: int = ROOF_REPS, flush: int = FLUSH_BYTES) -> dict:
+    """pcamg_bench_level on the finest level of solver s: kind 0 = forward
+    Gauss-Seidel sweep, 1 = residual; prec 0 = FP64, 1 = FP32."""
     from paper_1806_07028_amd import _lib
-    roof = {}
-    for prec, name in ((1, "f32"), (0, "f64")):
-        msv, nl, by = C.c_double(), C.c_int64(), C.c_double()
-        _lib.check(_lib.lib().pcamg_bench_smoother(s.h, prec, SMOOTHER_SWEEPS, C.byref(msv), C.byref(nl), C.byref(by)))
-        gbs = by.value / (msv.value * 1e-3) / 1e9
-        roof[name] = {"gbs": gbs, "ms": msv.value, "launches": nl.value, "bytes": by.value}
-    return roof
+    ms, nl, by = C.c_double(), C.c_int64(), C.c_double()
+    _lib.check(_lib.lib().pcamg_bench_level(s.h, kind, prec, reps, flush, C.byref(ms), C.byref(nl), C.byref(by)))
+    gbs = by.value / (ms.value * 1e-3) / 1e9
+    return {"gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4), "us_per_pass": round(1e3 * ms.value / reps, 2),
+            "launches_per_pass": nl.value / reps, "avg_launch_us": round(1e3 * ms.value / nl.value, 2),
+            "bytes_per_pass": round(by.value / reps), "flush_bytes": flush, "passes": reps}
 
 
-def kernel_source_digest():
-    """Digest of the source of the finest-level smoother pass: the row-sum
-    routines and the Gauss-Seidel kernel section of basic.hip."""
-    import hashlib
-    h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1806_07028_amd/csrc/rowchain.hpp"), "rb") as fh:
-        h.update(fh.read())
-    with open(os.path.join(ROOT, "paper_1806_07028_amd/csrc/basic.hip"), "rb") as fh:
-        text = fh.read()
-    a = text.index(b"// Gauss-Seidel pass over the rows of one colour")
-    b = text.index(b"// Same over an explicit row list")
-    h.update(text[a:b])
-    return h.hexdigest()[:16]
+def copy_ceiling(nbytes: int = 1 << 30, reps: int = 10) -> dict:
+    from paper_1806_07028_amd import _lib
+    ms = C.c_double()
+    _lib.check(_lib.lib().pcamg_bench_copy(nbytes, reps, None, C.byref(ms)))
+    gbs = 2.0 * nbytes * reps / (ms.value * 1e-3) / 1e9
+    return {"gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_moved_per_copy": 2 * nbytes,
+            "copies": reps}
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gs_sell_kernel_f32_128cube_hbm_traffic.md")
+def host_relres(g, b, x) -> float:
+    import numpy as np
+    import scipy.sparse as sp
+    n, rp, ci, w = g
+    W = sp.csr_matrix((w, ci, rp), shape=(n, n))
+    return float(np.linalg.norm(b - (np.asarray(W.sum(axis=1)).ravel() * x - W @ x)) / np.linalg.norm(b))
 
 
-def measured_traffic():
-    """HBM bytes per launch of the finest-level FP32 smoother pass, from the
-    committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by the same
-    counters on a copy of known size); None when the kernel sources changed
-    since the counters were taken or no such record exists."""
-    try:
-        with open(TRAFFIC_FILE) as fh:
-            text = fh.read()
-    except OSError:
-        return None
-    vals = {}
-    for line in text.splitlines():
-        if ":" in line and line.strip().startswith("- "):
-            k, v = line.strip()[2:].split(":", 1)
-            vals[k.strip()] = v.strip().strip("`")
-    if vals.get("source_digest") != kernel_source_digest():
-        return None
-    try:
-        return float(vals["traffic_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+def timed_steps(make, steps: int, warmup: int, tag: str):
+    """Warm-up and timed steps of make() -> (solver, x, stats); each step
+    bracketed by device synchronisation."""
+    import torch
+    for k in range(warmup):
+        log(f"{tag} warmup {k}")
+        s, x, st = make()
+        s.close()
+    times, s, x, st = [], None, None, None
+    for k in range(steps):
+        if s is not None:
+            s.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s, x, st = make()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        log(f"{tag} step {k}: {times[-1] * 1e3:.1f} ms (first hierarchy {st['t_setup_ms']:.0f} ms), "
+            f"{st['iterations']} it, {st['rebuilds']} re-setups, relres {st['true_relres']:.2e}")
+    return times, s, x, st
 
 
-def roofline_only(args):
-    """Setup, smoother sweeps and a 256 MiB device-to-device copy."""
+def fixed_hierarchy_convr(dev, init: str, hub_cap: int, iters: int = 25) -> dict:
+    """The paper's ConvR (Sec. 4): mean of ||r_{k+1}|| / ||r_k|| over the last
+    10 of `iters` standalone FP64 V(1,1)-cycles on a fixed first hierarchy (no
+    re-setup): the path-cover hierarchy of the relaxed start vector, or the
+    UA-AMG hierarchy of MWM aggregation."""
+    import paper_1806_07028_amd as P
+    s = P.Solver(*dev, outer="vcycle", cycle_prec="f64", max_rebuilds=0, tol=1e-300, max_iter=iters,
+                 a2_hub_cap=hub_cap, init=init)
+    x, st = s.solve(raise_on_noconv=False)
+    s.close()
+    return {"convr_last10": round(st["convr_last10"], 4), "iterations": st["iterations"],
+            "rho_geo": round(st["rho_geo"], 4), "op_complexity": round(st["op_complexity"], 3)}
+
+
+def oracle_sample(n0: int, kw: dict, nnz_full: int) -> dict:
+    """The CPU oracle (single thread) on the same generator at n0 vertices,
+    the same solver settings, scaled to the full graph by nnz(A)."""
+    import oracle
+    from paper_1806_07028_amd import inputs as I
+    gs, bs = I.config3(n0=n0)
+    t0 = time.perf_counter()
+    r = oracle.solve(gs, bs, **kw)
+    t_s = time.perf_counter() - t0
+    est = t_s * nnz_full / len(gs[2])
+    return {"value": round(est, 1), "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle solve (FCG, FP64 cycles, hub cap 64) of the same generator at n0 = {n0} "
+                      f"({gs[0]} vertices, {r.stats['iterations']} iterations, {t_s:.1f} s on one core), "
+                      "scaled by nnz(A) to the full graph; a lower bound, the A^2 work grows faster than nnz(A)"}
+
+
+# ---------------------------------------------------------------------------
+# Headline: the 4M power-law graph
+# ---------------------------------------------------------------------------
+def powerlaw_headline(args):
+    import numpy as np
     import torch
 
     import paper_1806_07028_amd as P
     from paper_1806_07028_amd import inputs as I
-    dev = torch.device("cuda", 0)
+    assert torch.cuda.is_available(), "needs a GPU"
+    P.lib()
+    prec = args.cycle_prec or "f64"
+    log(f"generating the Chung-Lu graph (n0 = {args.n0})")
+    g, b = I.config3(n0=args.n0)
+    n, rp, ci, w = g
+    dev = [torch.as_tensor(a, device="cuda") for a in (rp, ci, w)]
+    bd = torch.as_tensor(b, device="cuda")
+    base = dict(outer="fcg", theta=0.5, a2_hub_cap=64, numW=args.numW)
+
+    def make(p):
+        def f():
+            s = P.Solver(*dev, bd, cycle_prec=p, **base)
+            x, st = s.solve()
+            return s, x, st
+        return f
+
+    times, s, x, st = timed_steps(make(prec), args.steps, args.warmup, "powerlaw")
+    ms = 1e3 * sum(times) / len(times)
+    xh = x.cpu().numpy()
+    levels = [s.level_info(l)["n"] for l in range(s.num_levels())]
+    colours = [s.level_info(l)["ncolours"] for l in range(s.num_levels())]
+    log("roofline (finest level, last-level cache flushed)")
+    p_id = 0 if prec == "f64" else 1
+    gs_roof = level_roofline(s, 0, p_id)
+    res_roof = level_roofline(s, 1, p_id)
+    gs_roof_warm = level_roofline(s, 0, p_id, flush=0)
+    copy = copy_ceiling()
+    s.close()
+    roofline = {"bound": "hbm", "achieved": gs_roof["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gs_roof["frac"], "traffic": None,
+                "kernel": f"finest-level forward Gauss-Seidel sweep in {prec.upper()} ({colours[0]} colour passes; "
+                          "per pass gs_kernel<double,4> for rows of under 256 entries and gs_long_kernel<double> "
+                          "for the hub rows), 1 GiB read between timed sweeps",
+                "avg_launch_us": gs_roof["avg_launch_us"], "bytes_per_launch":
+                    round(gs_roof["bytes_per_pass"] / gs_roof["launches_per_pass"]),
+                "bytes_per_sweep": gs_roof["bytes_per_pass"], "us_per_sweep": gs_roof["us_per_pass"],
+                "launches_per_sweep": gs_roof["launches_per_pass"],
+                "residual_spmv": res_roof, "sweep_without_flush": gs_roof_warm, "copy_ceiling": copy}
+    out = {
+        "metric": "time to 1e-8 rel. residual", "value": round(ms / 1e3, 5), "unit": "s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
+        "config": {"workload": f"Chung-Lu power-law graph Laplacian, {n} vertices (largest component of "
+                               f"{args.n0} drawn), exponent 2.1, mean degree 16, weights uniform (0,1], zero-mean "
+                               f"N(0,1) rhs; validation + setup + FCG(FP64) with {prec.upper()} V(1,1) cycles to "
+                               "1e-8, Alg. 2 re-setups at mean ConvR > 0.5, A^2 hub cap 64",
+                   "vertices": n, "edges": len(ci) // 2, "tol": 1e-8, "theta": 0.5, "numW": args.numW},
+        "conv_factor": round(st["rho_geo"], 4), "iterations": st["iterations"], "rebuilds": st["rebuilds"],
+        "true_relres": st["true_relres"], "host_checked_relres": host_relres(g, b, xh),
+        "op_complexity": round(st["op_complexity"], 3), "levels": levels, "colours": colours,
+        "first_hierarchy_ms": round(st["t_setup_ms"], 2), "solve_ms": round(st["t_solve_ms"], 2),
+        "cycles": {"v32": st["vcycles32"], "v64": st["vcycles64"], "w": st["wcycles"]},
+        "smoother_gbps": gs_roof["gbs"], "roofline": roofline,
+    }
+    if not args.no_extras:
+        log("fixed-hierarchy ConvR (path cover, MWM)")
+        out["vcycle_convr_fixed_hierarchy"] = {"path_cover": fixed_hierarchy_convr(dev, "relax", 64),
+                                               "mwm_ua_amg": fixed_hierarchy_convr(dev, "mwm", 64)}
+        other = "f32" if prec == "f64" else "f64"
+        t, s2, x2, st2 = timed_steps(make(other), 1, 1, f"powerlaw {other}")
+        s2.close()
+        out["other_precision"] = {
+            "cycle_prec": other, "time_s": round(t[0], 4), "iterations": st2["iterations"],
+            "rebuilds": st2["rebuilds"], "rho_geo": round(st2["rho_geo"], 4), "true_relres": st2["true_relres"],
+            "x_rel_diff": float(np.linalg.norm(x2.cpu().numpy() - xh) / np.linalg.norm(xh))}
+        del dev, bd
+        out["grid3d_128"] = grid3d_extras(args)
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample)")
+        out["cpu_baseline"] = oracle_sample(150_000, dict(outer=1, cycle_prec=0 if prec == "f64" else 1, theta=0.5,
+                                                          a2_hub_cap=64, numW=args.numW), len(ci))
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# The 128^3 weighted grid (the other single-GPU configuration)
+# ---------------------------------------------------------------------------
+def grid3d_extras(args) -> dict:
+    """One warm-up and one timed step in each cycle precision, and the
+    finest-level roofline (flushed) of the FP64 and FP32 passes."""
+    import torch
+
+    import paper_1806_07028_amd as P
+    from paper_1806_07028_amd import inputs as I
+    side = args.side
+    log(f"generating the {side}^3 grid")
+    g, b = I.config2(side=side)
+    n, rp, ci, w = g
+    dev = [torch.as_tensor(a, device="cuda") for a in (rp, ci, w)]
+    bd = torch.as_tensor(b, device="cuda")
+    res = {"workload": f"7-point {side}^3 grid ({n} vertices), weights 10^(-3+6u), zero-mean N(0,1) rhs; "
+                       "FCG(FP64) to 1e-8, Alg. 2 re-setups at mean ConvR > 0.5 (numW 2)"}
+    for prec in ("f64", "f32"):
+        def f(p=prec):
+            s = P.Solver(*dev, bd, outer="fcg", cycle_prec=p, theta=0.5, numW=args.numW)
+            x, st = s.solve()
+            return s, x, st
+        t, s, x, st = timed_steps(f, 1, 1, f"grid3d {prec}")
+        res[prec] = {"time_s": round(t[0], 4), "iterations": st["iterations"], "rebuilds": st["rebuilds"],
+                     "rho_geo": round(st["rho_geo"], 4), "true_relres": st["true_relres"],
+                     "cycles": {"v32": st["vcycles32"], "v64": st["vcycles64"], "w": st["wcycles"]}}
+        if prec == "f64":
+            res["smoother_roofline"] = {
+                "kernel": "gs_sell_kernel (finest level, red-black, sliced-ELL, one thread per row), forward sweep",
+                "f64": level_roofline(s, 0, 0), "f32": level_roofline(s, 0, 1),
+                "residual_f64": level_roofline(s, 1, 0)}
+        s.close()
+    return res
+
+
+def grid3d_bench(args):
+    """The 128^3 grid as its own JSON line (FP32 cycles by default)."""
+    import torch
+
+    import paper_1806_07028_amd as P
+    from paper_1806_07028_amd import inputs as I
+    prec = args.cycle_prec or "f32"
     g, b = I.config2(side=args.side)
     n, rp, ci, w = g
-    s = P.Solver(*(torch.as_tensor(a, device=dev) for a in (rp, ci, w)), torch.as_tensor(b, device=dev),
-                 outer="fcg", cycle_prec="f32", theta=0.5)
-    roof = smoother_roofline(s)
-    src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
-    dst = torch.empty_like(src)
-    for _ in range(3):
-        dst.copy_(src)
-    torch.cuda.synchronize()
-    r32 = roof["f32"]
-    print(json.dumps({"kernel": "gs_sell_kernel<float>", "launches": r32["launches"],
-                      "avg_launch_us": 1e3 * r32["ms"] / r32["launches"],
-                      "bytes_per_launch": r32["bytes"] / r32["launches"], "gbs": r32["gbs"],
-                      "f64_gbs": roof["f64"]["gbs"], "copy_bytes": 2 * src.numel() * 4, "copies": 3,
-                      "source_digest": kernel_source_digest()}), flush=True)
+    dev = [torch.as_tensor(a, device="cuda") for a in (rp, ci, w)]
+    bd = torch.as_tensor(b, device="cuda")
+
+    def f():
+        s = P.Solver(*dev, bd, outer="fcg", cycle_prec=prec, theta=0.5, numW=args.numW)
+        x, st = s.solve()
+        return s, x, st
+
+    times, s, x, st = timed_steps(f, args.steps, args.warmup, "grid3d")
+    ms = 1e3 * sum(times) / len(times)
+    roof = level_roofline(s, 0, 0 if prec == "f64" else 1)
+    s.close()
+    print(json.dumps({
+        "metric": "time to 1e-8 rel. residual", "value": round(ms / 1e3, 5), "unit": "s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": False,
+        "dtype": prec, "data": "synthetic",
+        "config": {"workload": f"7-point {args.side}^3 grid, weights 10^(-3+6u), FCG(FP64) + {prec.upper()} "
+                               "V(1,1) cycles to 1e-8, theta 0.5"},
+        "iterations": st["iterations"], "rebuilds": st["rebuilds"], "conv_factor": round(st["rho_geo"], 4),
+        "host_checked_relres": host_relres(g, b, x.cpu().numpy()), "smoother_roofline": roof}), flush=True)
 
 
 def batch_bench(args):
@@ -252,77 +373,6 @@ def batch_bench(args):
         "graphs_per_s": round(args.count / (ms / 1e3), 2), "chunk": chunk,
         "iterations": {"min": min(its), "max": max(its), "mean": round(float(np.mean(its)), 2)},
         "converged": sum(st["status"] == 0 for st in sts), "cpu_baseline": cpu}), flush=True)
-
-
-def powerlaw_bench(args):
-    """Power-law graph: Chung-Lu on n0 vertices (exponent 2.1, mean degree 16,
-    largest component kept), weights uniform in (0, 1], zero-mean N(0,1) rhs;
-    a step is setup + FCG(FP64) with FP32 V(1,1) cycles to 1e-8 (theta 0.5,
-    A^2 hub cap 64), inputs already on the GPU."""
-    import numpy as np
-    import scipy.sparse as sp
-    import torch
-
-    import paper_1806_07028_amd as P
-    from paper_1806_07028_amd import inputs as I
-    log(f"generating the Chung-Lu graph (n0 = {args.n0})")
-    g, b = I.config3(n0=args.n0)
-    n, rp, ci, w = g
-    dev = torch.device("cuda", 0)
-    args_d = [torch.as_tensor(a, device=dev) for a in (rp, ci, w, b)]
-    params = dict(outer="fcg", cycle_prec=args.cycle_prec or "f32", theta=0.5, a2_hub_cap=64)
-
-    def step():
-        s = P.Solver(*args_d, **params)
-        x, st = s.solve()
-        return s, x, st
-
-    for k in range(args.warmup):
-        log(f"warmup {k}")
-        s, x, st = step()
-        del s
-    times, st = [], None
-    for k in range(args.steps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s, x, st = step()
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-        log(f"step {k}: {times[-1] * 1e3:.1f} ms (setup {st['t_setup_ms']:.0f} ms), {st['iterations']} it, "
-            f"{st['rebuilds']} re-setups, relres {st['true_relres']:.2e}")
-        levels = [s.level_info(l, 0)["n"] for l in range(s.num_levels(0))]
-        del s
-    W = sp.csr_matrix((w, ci, rp), shape=(n, n))
-    xh = x.cpu().numpy()
-    host_relres = float(np.linalg.norm(b - (np.asarray(W.sum(axis=1)).ravel() * xh - W @ xh)) / np.linalg.norm(b))
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        log("cpu baseline (oracle on a smaller graph of the same family)")
-        gs, bs = I.config3(n0=100_000)
-        t0 = time.perf_counter()
-        r = oracle.solve(gs, bs, outer=1, cycle_prec=1, theta=0.5, a2_hub_cap=64)
-        t_s = time.perf_counter() - t0
-        est = t_s * len(ci) / len(gs[2])
-        cpu = {"value": round(est, 1), "unit": "s", "cores": 1, "kind": "oracle",
-               "sample": f"oracle solve of the same generator at n0 = 100000 ({gs[0]} vertices, "
-                         f"{r.stats['iterations']} iterations, {t_s:.1f} s), scaled by nnz(A); a lower bound, "
-                         "the A^2 work grows faster than nnz(A)"}
-    ms = 1e3 * sum(times) / len(times)
-    print(json.dumps({
-        "metric": "time to 1e-8 rel. residual", "value": round(ms / 1e3, 4), "unit": "s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 2),
-        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
-        "config": {"workload": f"Chung-Lu power-law graph, {n} vertices (largest component of {args.n0}), "
-                               "exponent 2.1, mean degree 16, weights uniform (0,1], zero-mean N(0,1) rhs; "
-                               "setup + FCG(FP64) with FP32 V(1,1) preconditioner to 1e-8, A^2 hub cap 64",
-                   "vertices": n, "edges": len(ci) // 2, "tol": 1e-8, "theta": 0.5},
-        "conv_factor": round(st["rho_geo"], 4), "iterations": st["iterations"], "rebuilds": st["rebuilds"],
-        "true_relres": st["true_relres"], "host_checked_relres": host_relres,
-        "op_complexity": round(st["op_complexity"], 3), "levels": levels,
-        "setup_ms": round(st["t_setup_ms"], 2), "solve_ms": round(st["t_solve_ms"], 2),
-        "cycles": {"v32": st["vcycles32"], "v64": st["vcycles64"], "w": st["wcycles"]},
-        "cpu_baseline": cpu}), flush=True)
 
 
 # The paper's printed iteration counts (Tables 1-6; MWM, Alg. 5 with theta 1e-6
@@ -476,135 +526,8 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is described "
               "but not built", file=sys.stderr)
         sys.exit(2)
-    if args.roofline_only:
-        roofline_only(args)
-        return
-    if args.workload == "batch":
-        batch_bench(args)
-        return
-    if args.workload == "learned":
-        learned_bench(args)
-        return
-    if args.workload == "powerlaw":
-        powerlaw_bench(args)
-        return
-    if args.workload == "sweeps":
-        sweeps_bench(args)
-        return
-    import numpy as np
-    import torch
-
-    import paper_1806_07028_amd as P
-    from paper_1806_07028_amd import inputs as I
-
-    assert torch.cuda.is_available(), "needs a GPU"
-    dev = torch.device("cuda", 0)
-    side = args.side
-    log(f"generating {side}^3 workload")
-    g, b = I.config2(side=side)
-    n, rp, ci, w = g
-    rp_d = torch.as_tensor(rp, device=dev)
-    ci_d = torch.as_tensor(ci, device=dev)
-    w_d = torch.as_tensor(w, device=dev)
-    b_d = torch.as_tensor(b, device=dev)
-    P.lib()
-    params = dict(outer="fcg", cycle_prec="f32", theta=0.5, numW=args.numW)
-    if args.row_lanes is not None:
-        params["row_lanes"] = args.row_lanes
-
-    def step(pp):
-        s = P.Solver(rp_d, ci_d, w_d, b_d, **pp)
-        x, st = s.solve()
-        return s, x, st
-
-    for k in range(args.warmup):
-        log(f"warmup {k}")
-        s, x, st = step(params)
-        del s
-    torch.cuda.synchronize()
-    times, stats = [], []
-    for k in range(args.steps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s, x, st = step(params)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-        stats.append(st)
-        log(f"step {k}: {times[-1]*1e3:.1f} ms, {st['iterations']} it, {st['rebuilds']} re-setups, "
-            f"relres {st['true_relres']:.2e}")
-        if k + 1 < args.steps:
-            del s
-    ms = 1e3 * sum(times) / len(times)
-    st = stats[-1]
-    # independent check of the final residual on the host
-    xh = x.cpu().numpy()
-    import scipy.sparse as sp
-    L = sp.csr_matrix((-w, ci, rp), shape=(n, n))
-    L = L - sp.diags(np.asarray(L.sum(axis=1)).ravel())
-    host_relres = float(np.linalg.norm(b - L @ xh) / np.linalg.norm(b))
-
-    roof = smoother_roofline(s)
-    r32 = roof["f32"]
-    roofline = {"bound": "hbm", "achieved": round(r32["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(r32["gbs"] / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                "kernel": "gs_sell_kernel<float> (finest-level Gauss-Seidel colour pass, red-black order, sliced-ELL matrix, one thread per row)",
-                "avg_launch_us": round(1e3 * r32["ms"] / r32["launches"], 2),
-                "bytes_per_launch": round(r32["bytes"] / r32["launches"]),
-                "f64_gbs": round(roof["f64"]["gbs"], 1)}
-    del s
-
-    fp64 = None
-    if not args.no_fp64_variant:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s64, x64, st64 = step(dict(outer="vcycle", theta=0.5, numW=args.numW))
-        torch.cuda.synchronize()
-        fp64 = {"time_s": round(time.perf_counter() - t0, 4), "iterations": st64["iterations"],
-                "rebuilds": st64["rebuilds"], "rho_geo": round(st64["rho_geo"], 4),
-                "true_relres": st64["true_relres"],
-                "err_vs_mixed": float(torch.linalg.norm(x64 - x) / torch.linalg.norm(x64))}
-        del s64
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle sample)")
-        cpu = cpu_baseline(g, b, st, side, args.numW)
-
-    out = {
-        "metric": "time to 1e-8 rel. residual",
-        "value": round(ms / 1e3, 5),
-        "unit": "s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms, 3),
-        "higher_is_better": False,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64+f32",
-        "data": "synthetic",
-        "config": {"workload": f"graph Laplacian of the 7-point {side}^3 grid ({n} vertices), log-uniform weights "
-                               "[1e-3,1e3], zero-mean N(0,1) rhs; setup + FCG(FP64) with FP32 V(1,1) preconditioner "
-                               "to 1e-8, re-setup at mean ConvR > 0.5",
-                   "vertices": n, "edges": len(ci) // 2, "tol": 1e-8, "theta": 0.5, "numW": args.numW},
-        "conv_factor": round(st["rho_geo"], 4),
-        "iterations": st["iterations"],
-        "rebuilds": st["rebuilds"],
-        "true_relres": st["true_relres"],
-        "host_checked_relres": host_relres,
-        "op_complexity": round(st["op_complexity"], 3),
-        "setup_ms": round(st["t_setup_ms"], 2),
-        "solve_ms": round(st["t_solve_ms"], 2),
-        "rebuild_ms": round(st["t_rebuild_ms"], 2),
-        "approx_ms": round(st["t_approx_ms"], 2),
-        "build_ms": round(st["t_build_ms"], 2),
-        "cycles": {"v32": st["vcycles32"], "v64": st["vcycles64"], "w": st["wcycles"]},
-        "smoother_gbps": round(r32["gbs"], 1),
-        "fp64_vcycle_variant": fp64,
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(out), flush=True)
+    {"powerlaw": powerlaw_headline, "grid3d": grid3d_bench, "batch": batch_bench, "learned": learned_bench,
+     "sweeps": sweeps_bench}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -125,6 +125,11 @@ typedef struct {
   int32_t case3;           /* Alg. 3 Case 3: 0 = v leaves its aggregate only when the rest stays
                               connected (else u joins at v; aggregates may grow past three as stars
                               of diameter 2); 1 = as printed in Step 17 (v always leaves) */
+  int32_t block_sweep_min_colours; /* a launched level with at least this many colours and at most 64
+                              rows per colour on average runs each Gauss-Seidel sweep of the cycles
+                              in one single-workgroup launch (same arithmetic, bit-identical
+                              results; near-dense coarse levels of power-law graphs).  0 = off
+                              (64) */
   int32_t init;            /* first hierarchy: PCAMG_INIT_RELAX (path cover of the relaxed start
                               vector, default) or PCAMG_INIT_MWM (UA-AMG with MWM aggregation on
                               every level, the MWM_setup of Alg. 5/6 Step 2, Sec. 2.1).  With
@@ -253,8 +258,9 @@ pcamg_status pcamg_bench_smoother(pcamg_ctx* c, int32_t prec, int32_t sweeps, do
 
 /* Roofline measurement on the finest level of the context, in the solve
  * layout and launch configuration of the cycles.  Each of `reps`
- * repetitions first writes flush_bytes (0 = none) of a scratch buffer, so
- * that the last-level cache holds none of the level, then runs between HIP
+ * repetitions first reads flush_bytes (0 = none) of a scratch buffer, so
+ * that the last-level cache holds none of the level (and no dirty lines whose
+ * write-back would fall into the timed pass), then runs between HIP
  * events on the context's stream either one forward multicoloured
  * Gauss-Seidel sweep (kind 0, colours 0..C-1) or one residual r = b - A x
  * (kind 1), in precision prec.  Outputs (host): summed event milliseconds,

@@ -55,6 +55,7 @@ class Params(C.Structure):
         ("seed", _u64),
         ("colour_seed", _u64),
         ("case3", _i32),
+        ("block_sweep_min_colours", _i32),
         ("init", _i32),
     ]
 

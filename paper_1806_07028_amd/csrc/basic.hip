@@ -796,6 +796,85 @@ __global__ void __launch_bounds__(LONG_T)
   }
 }
 
+// ---------------------------------------------------------------------------
+// All colour passes of one sweep of a level in a single workgroup (levels
+// with many colours of a few rows each -- the near-dense coarse levels of
+// power-law graphs -- where a launch per colour costs more than the colour's
+// work).  Four groups of LONG_T threads; in colour c the long rows
+// [coff[c], lend[c]) go to the groups in turn, each summed with exactly the
+// tree of gs_long_kernel (a group's chains, a butterfly per wavefront, the
+// group's four wavefront sums in order), and the other rows [lend[c],
+// coff[c+1]) are single fma chains in stored order, one thread each, as in
+// gs_kernel -- so every value is bit-identical to the launch-per-colour path.
+// A workgroup barrier separates dependent colours.
+// ---------------------------------------------------------------------------
+constexpr int SWEEP_GROUPS = 4;
+
+template <typename T>
+__global__ void __launch_bounds__(LONG_T * SWEEP_GROUPS)
+    gs_sweep_block_kernel(int32_t c0, int32_t c1, int32_t step, const int32_t* __restrict__ coff,
+                          const int32_t* __restrict__ lend, const int32_t* __restrict__ rp,
+                          const int32_t* __restrict__ ci, const T* __restrict__ av, const T* __restrict__ dinv,
+                          const T* __restrict__ b, T* x) {
+  __shared__ T part[SWEEP_GROUPS][LONG_T / 64];
+  const int tid = (int)threadIdx.x, grp = tid / LONG_T, gt = tid % LONG_T;
+  for (int32_t c = c0; c != c1; c += step) {
+    const int32_t r0 = coff[c], rl = lend[c], r1 = coff[c + 1];
+    // long rows, SWEEP_GROUPS at a time (every group takes part in the barriers)
+    for (int32_t base = r0; base < rl; base += SWEEP_GROUPS) {
+      const int32_t i = base + grp;
+      T sum = (T)0;
+      if (i < rl) {
+        constexpr int U = 4;
+        const int32_t k0 = rp[i], k1 = rp[i + 1];
+        int32_t k = k0 + gt;
+        for (; k + (U - 1) * LONG_T < k1; k += U * LONG_T) {
+          int32_t cc[U];
+          T a[U], v[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            cc[u] = ci[k + u * LONG_T];
+            a[u] = av[k + u * LONG_T];
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) v[u] = x[cc[u]];
+#pragma unroll
+          for (int u = 0; u < U; ++u) sum = fma(a[u], v[u], sum);
+        }
+        for (; k < k1; k += LONG_T) sum = fma(av[k], x[ci[k]], sum);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+        if ((gt & 63) == 0) part[grp][gt >> 6] = sum;
+      }
+      __syncthreads();
+      if (i < rl && gt == 0) {
+        T t = part[grp][0];
+#pragma unroll
+        for (int w = 1; w < LONG_T / 64; ++w) t += part[grp][w];
+        x[i] = (b[i] - t) * dinv[i];
+      }
+      __syncthreads();
+    }
+    // short rows: one chain each
+    for (int32_t i = rl + tid; i < r1; i += LONG_T * SWEEP_GROUPS) {
+      T sum = (T)0;
+      for (int32_t k = rp[i]; k < rp[i + 1]; ++k) sum = fma(av[k], x[ci[k]], sum);
+      x[i] = (b[i] - sum) * dinv[i];
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+void gs_sweep_block(int32_t c_first, int32_t c_end, int32_t step, const int32_t* coff_d, const int32_t* lend_d,
+                    const int32_t* rp, const int32_t* ci, const T* av, const T* dinv, const T* b, T* x,
+                    hipStream_t s) {
+  if (c_first == c_end) return;
+  gs_sweep_block_kernel<T><<<1, LONG_T * SWEEP_GROUPS, 0, s>>>(c_first, c_end, step, coff_d, lend_d, rp, ci, av,
+                                                                dinv, b, x);
+  PCAMG_LAUNCHED();
+}
+
 template <typename T>
 void gs_colour_long(int32_t row0, int32_t row1, const int32_t* rp, const int32_t* ci, const T* av, const T* dinv,
                     const T* b, T* x, hipStream_t s) {
@@ -1062,6 +1141,8 @@ void prolong_add(int32_t n, const int32_t* agg, const T* pval, const T* xc, T* x
                             T*, hipStream_t, int, int32_t);                                                     \
   template void gs_colour_long<T>(int32_t, int32_t, const int32_t*, const int32_t*, const T*, const T*,        \
                                   const T*, T*, hipStream_t);                                                   \
+  template void gs_sweep_block<T>(int32_t, int32_t, int32_t, const int32_t*, const int32_t*, const int32_t*,   \
+                                  const int32_t*, const T*, const T*, const T*, T*, hipStream_t);               \
   template void residual_long<T>(int32_t, const int32_t*, const int32_t*, const int32_t*, const T*, const T*,  \
                                  const T*, const T*, T*, hipStream_t);                                          \
   template void spmv<T>(int32_t, const int32_t*, const int32_t*, const T*, const T*, const T*, T*, hipStream_t, \

@@ -200,6 +200,14 @@ void gs_colour_long(int32_t row0, int32_t row1, const int32_t* rp, const int32_t
 template <typename T>
 void residual_long(int32_t nrows, const int32_t* rows, const int32_t* rp, const int32_t* ci, const T* av,
                    const T* d, const T* b, const T* x, T* r, hipStream_t s);
+// Colour passes c_first, c_first + step, ... (up to, not including, c_end) of
+// one sweep in a single workgroup: rows [coff[c], lend[c]) by the long-row
+// tree, the rest by single chains; device coff_d[ncol + 1], lend_d[ncol].
+// Bit-identical to gs_colour_long + gs_colour per colour.
+template <typename T>
+void gs_sweep_block(int32_t c_first, int32_t c_end, int32_t step, const int32_t* coff_d, const int32_t* lend_d,
+                    const int32_t* rp, const int32_t* ci, const T* av, const T* dinv, const T* b, T* x,
+                    hipStream_t s);
 template <typename T>
 void spmv(int32_t n, const int32_t* rp, const int32_t* ci, const T* av, const T* d, const T* x, T* y,
           hipStream_t s, int lanes = 1);

@@ -29,6 +29,10 @@ constexpr int32_t SELL_MIN_N = 4096;
 // Levels at most this size are not timed by the lanes autotuner (they run in
 // the tail kernel by default).
 constexpr int32_t TUNE_MIN_N = 2048;
+// A level of at least block_sweep_min_colours colours (a parameter), with at
+// most this many rows per colour on average, runs its sweeps in one
+// single-workgroup launch.
+constexpr int32_t BLOCK_SWEEP_ROWS_PER_COLOUR = 64;
 
 // Autotuned lanes per row (row_lanes = -1).  Candidates: one thread per row
 // (on the sliced-ELL copy when the level has one), 4 and 16 lanes per row.
@@ -89,7 +93,7 @@ int32_t tune_lanes(const LevelMatrix& M, hipStream_t s) {
 std::shared_ptr<LevelMatrix> make_level_matrix(int32_t n, int32_t nnz, const int32_t* rp, const int32_t* ci,
                                                const double* av, const double* d, const double* dinv,
                                                const int32_t* colour, int32_t ncol, int32_t row_lanes,
-                                               int32_t long_min, hipStream_t s) {
+                                               int32_t long_min, int32_t block_min_colours, hipStream_t s) {
   auto M = std::make_shared<LevelMatrix>();
   M->n = n;
   M->nnz = nnz;
@@ -149,6 +153,19 @@ std::shared_ptr<LevelMatrix> make_level_matrix(int32_t n, int32_t nnz, const int
   // launched lane-group levels without long rows: padded-row FP32 copy
   if (n > TUNE_MIN_N && M->long_min == 0 && !M->sell() && (M->lanes == 4 || M->lanes == 16))
     ell_build(n, M->lanes, M->rp.p, M->ci.p, M->av32.p, M->ell_w, M->eci, M->eav32, s);
+  // many colours with a few rows each (near-dense coarse levels of power-law
+  // graphs: hundreds of colours): a sweep runs in one single-workgroup launch
+  // instead of one or two launches per colour
+  if (colour && !M->sell() && block_min_colours > 0 && M->ncol >= block_min_colours &&
+      (int64_t)n <= (int64_t)BLOCK_SWEEP_ROWS_PER_COLOUR * M->ncol) {
+    M->block_sweep = true;
+    M->coff_d.resize(M->ncol + 1);
+    M->lend_d.resize(M->ncol);
+    std::vector<int32_t> lend = M->long_min > 0 ? M->lend : std::vector<int32_t>(M->coff.begin(), M->coff.end() - 1);
+    copy_h2d(M->coff_d.p, M->coff.data(), M->ncol + 1, s);
+    copy_h2d(M->lend_d.p, lend.data(), M->ncol, s);
+    PCAMG_HIP(hipStreamSynchronize(s));  // lend is a host temporary
+  }
   return M;
 }
 
@@ -218,6 +235,35 @@ void level_residual(const LevelMatrix& A, const float* b, const float* x, float*
   }
 }
 
+// One multicoloured Gauss-Seidel sweep of a level inside a cycle: colours
+// skip..C-1 (forward) or C-1..0 (backward).
+void smooth_sweep(const LevelMatrix& A, bool forward, int skip, const double* b, double* x, hipStream_t s) {
+  if (A.block_sweep) {
+    if (forward) gs_sweep_block<double>(skip, A.ncol, 1, A.coff_d.p, A.lend_d.p, A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s);
+    else gs_sweep_block<double>(A.ncol - 1, -1, -1, A.coff_d.p, A.lend_d.p, A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s);
+    return;
+  }
+  if (forward)
+    for (int k = skip; k < A.ncol; ++k) smooth_colour(A, k, b, x, s);
+  else
+    for (int k = A.ncol - 1; k >= 0; --k) smooth_colour(A, k, b, x, s);
+}
+
+void smooth_sweep(const LevelMatrix& A, bool forward, int skip, const float* b, float* x, hipStream_t s) {
+  if (A.block_sweep) {
+    if (forward)
+      gs_sweep_block<float>(skip, A.ncol, 1, A.coff_d.p, A.lend_d.p, A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s);
+    else
+      gs_sweep_block<float>(A.ncol - 1, -1, -1, A.coff_d.p, A.lend_d.p, A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x,
+                            s);
+    return;
+  }
+  if (forward)
+    for (int k = skip; k < A.ncol; ++k) smooth_colour(A, k, b, x, s);
+  else
+    for (int k = A.ncol - 1; k >= 0; --k) smooth_colour(A, k, b, x, s);
+}
+
 void ctx_init(pcamg_ctx* c, const pcamg_graph* g, const pcamg_params* p) {
   hipStream_t s = c->s;
   c->P = *p;
@@ -235,7 +281,7 @@ void ctx_init(pcamg_ctx* c, const pcamg_graph* g, const pcamg_params* p) {
   laplacian(n, c->rp.p, g->weight, c->av.p, c->d.p, c->dinv.p, nnz, s);
   c->ncol = colour_level(n, c->rp.p, c->ci.p, c->P.colour_seed, 0, c->colour.p, s);
   c->M0 = make_level_matrix(n, nnz, c->rp.p, c->ci.p, c->av.p, c->d.p, c->dinv.p, c->colour.p, c->ncol,
-                            c->P.row_lanes, c->P.long_row_min, s);
+                            c->P.row_lanes, c->P.long_row_min, c->P.block_sweep_min_colours, s);
   sync(s);
 }
 
@@ -513,9 +559,9 @@ static std::unique_ptr<Hierarchy> assemble_hierarchy(pcamg_ctx* c, std::unique_p
     if (l == 0) V.A = c->M0;
     else if (l + 1 < nl)
       V.A = make_level_matrix(L.n, L.nnz, L.rp, L.ci, L.av, L.d, L.dinv, L.colour, L.ncol, P.row_lanes,
-                              P.long_row_min, s);
+                              P.long_row_min, P.block_sweep_min_colours, s);
     else
-      V.A = make_level_matrix(L.n, L.nnz, L.rp, L.ci, L.av, L.d, L.dinv, nullptr, 1, P.row_lanes, 0, s);
+      V.A = make_level_matrix(L.n, L.nnz, L.rp, L.ci, L.av, L.d, L.dinv, nullptr, 1, P.row_lanes, 0, 0, s);
     V.x.resize(L.n);
     V.b.resize(L.n);
     V.r.resize(L.n);
@@ -690,8 +736,7 @@ void cycle64(pcamg_ctx* c, Hierarchy& H, int l, const double* b, double* x, int 
   }
   Level& L = H.lv[l];
   const LevelMatrix& A = *L.A;
-  for (int k = skip; k < A.ncol; ++k)
-    smooth_colour(A, k, b, x, s);
+  smooth_sweep(A, true, skip, b, x, s);
   Level& N = H.lv[l + 1];
   const LevelMatrix& AN = *N.A;
   const int calls = (gamma > 1 && l + 2 < nl) ? gamma : 1;
@@ -712,8 +757,7 @@ void cycle64(pcamg_ctx* c, Hierarchy& H, int l, const double* b, double* x, int 
     for (int q = 0; q < calls; ++q) cycle64(c, H, l + 1, N.b.p, N.x.p, gamma, q == 0 && mode == 2 ? 1 : 0);
   }
   prolong_add<double>(A.n, L.T.agg.p, L.T.pval.p, N.x.p, x, s);
-  for (int k = A.ncol - 1; k >= 0; --k)
-    smooth_colour(A, k, b, x, s);
+  smooth_sweep(A, false, 0, b, x, s);
 }
 
 void cycle32(pcamg_ctx* c, Hierarchy& H, int l, const float* b, float* x, int gamma, int skip) {
@@ -736,8 +780,7 @@ void cycle32(pcamg_ctx* c, Hierarchy& H, int l, const float* b, float* x, int ga
   }
   Level& L = H.lv[l];
   const LevelMatrix& A = *L.A;
-  for (int k = skip; k < A.ncol; ++k)
-    smooth_colour(A, k, b, x, s);
+  smooth_sweep(A, true, skip, b, x, s);
   Level& N = H.lv[l + 1];
   const LevelMatrix& AN = *N.A;
   const int calls = (gamma > 1 && l + 2 < nl) ? gamma : 1;
@@ -758,8 +801,7 @@ void cycle32(pcamg_ctx* c, Hierarchy& H, int l, const float* b, float* x, int ga
     for (int q = 0; q < calls; ++q) cycle32(c, H, l + 1, N.b32.p, N.x32.p, gamma, q == 0 && mode == 2 ? 1 : 0);
   }
   prolong_add<float>(A.n, L.T.agg.p, L.T.pval32.p, N.x32.p, x, s);
-  for (int k = A.ncol - 1; k >= 0; --k)
-    smooth_colour(A, k, b, x, s);
+  smooth_sweep(A, false, 0, b, x, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1225,24 +1267,51 @@ void bench_smoother(pcamg_ctx* c, int prec, int sweeps, double* ms, int64_t* lau
 }
 
 // ---------------------------------------------------------------------------
-// Roofline measurement on the finest level.  Each repetition first writes
-// flush_bytes of a scratch buffer (so the 256 MB last-level cache holds none
-// of the level's data), then times one forward Gauss-Seidel sweep (kind 0:
-// colours 0..C-1, the kernels and launch configuration of the cycles) or one
-// residual r = b - A x (kind 1) between HIP events on the context's stream.
+// Roofline measurement on the finest level.  Each repetition first reads a
+// scratch buffer of flush_bytes (so the 256 MB last-level cache holds clean
+// lines of that buffer and none of the level's data; reading rather than
+// writing leaves no dirty lines whose write-back would land in the timed
+// pass), then times one forward Gauss-Seidel sweep (kind 0: colours 0..C-1,
+// the kernels and launch configuration of the cycles) or one residual
+// r = b - A x (kind 1) between HIP events on the context's stream.
 // Algorithmic bytes per repetition: matrix values and columns, row pointers,
-// and per row x written (GS only), x read once, b, dinv (GS) or d and r
-// (residual); re-gathered x of neighbouring rows is not counted.
+// and per row four vector entries (GS: x written, x read once, b, dinv;
+// residual: x, b, d, r); re-gathered x of neighbouring rows is not counted.
 // ---------------------------------------------------------------------------
 namespace {
-__global__ void flush_kernel(float4* __restrict__ a, size_t n, float v) {
+__global__ void fill4_kernel(float4* __restrict__ a, size_t n, float v) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     a[i] = make_float4(v, v, v, v);
 }
-__global__ void copy_kernel(const float4* __restrict__ a, float4* __restrict__ b, size_t n) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    b[i] = a[i];
+// Reads every element once; one partial sum per block keeps the loads live.
+__global__ void __launch_bounds__(256) read_kernel(const float4* __restrict__ a, size_t n, float* __restrict__ part) {
+  float acc = 0.0f;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const float4 v = a[i];
+    acc += v.x + v.y + v.z + v.w;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) part[blockIdx.x * 4 + (threadIdx.x >> 6)] = acc;
 }
+// Streaming copy: each thread moves four float4 per step, 256 consecutive
+// float4 per wavefront access (fully coalesced), grid-stride over the buffer.
+__global__ void __launch_bounds__(256) copy_kernel(const float4* __restrict__ a, float4* __restrict__ b, size_t n) {
+  const size_t step = (size_t)gridDim.x * blockDim.x * 4;
+  for (size_t base = (size_t)blockIdx.x * blockDim.x * 4 + threadIdx.x; base < n; base += step) {
+    float4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const size_t i = base + (size_t)u * blockDim.x;
+      if (i < n) v[u] = a[i];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const size_t i = base + (size_t)u * blockDim.x;
+      if (i < n) b[i] = v[u];
+    }
+  }
+}
+constexpr unsigned READ_BLOCKS = 4096;
 }  // namespace
 
 void bench_level(pcamg_ctx* c, int kind, int prec, int reps, int64_t flush_bytes, double* ms, int64_t* launches,
@@ -1251,7 +1320,7 @@ void bench_level(pcamg_ctx* c, int kind, int prec, int reps, int64_t flush_bytes
   const LevelMatrix& A = *c->M0;
   const int32_t n = A.n;
   const double vs = prec == PCAMG_PREC_F32 ? 4.0 : 8.0;
-  const double per = (vs + 4.0) * A.nnz + 4.0 * (n + 1.0) + (kind == 0 ? 4.0 : 4.0) * vs * n;
+  const double per = (vs + 4.0) * A.nnz + 4.0 * (n + 1.0) + 4.0 * vs * n;
   DVec<double> b(n), x(n), r(n);
   DVec<float> b32(n), x32(n), r32(n);
   xi_fill(c->P.seed, 7, nullptr, b.p, n, s);
@@ -1260,6 +1329,11 @@ void bench_level(pcamg_ctx* c, int kind, int prec, int reps, int64_t flush_bytes
   cast_f64_f32(x.p, x32.p, n, s);
   const size_t nf = flush_bytes > 0 ? (size_t)flush_bytes / sizeof(float4) : 0;
   DVec<float4> fl(nf);
+  DVec<float> part(nf ? 4 * READ_BLOCKS : 0);
+  if (nf) {
+    fill4_kernel<<<1024, 256, 0, s>>>(fl.p, nf, 1.0f);
+    PCAMG_LAUNCHED();
+  }
   hipEvent_t e0, e1;
   PCAMG_HIP(hipEventCreate(&e0));
   PCAMG_HIP(hipEventCreate(&e1));
@@ -1283,7 +1357,7 @@ void bench_level(pcamg_ctx* c, int kind, int prec, int reps, int64_t flush_bytes
     nl = 0;
     for (int q = 0; q < reps; ++q) {
       if (nf) {
-        flush_kernel<<<1024, 256, 0, s>>>(fl.p, nf, (float)q);
+        read_kernel<<<READ_BLOCKS, 256, 0, s>>>(fl.p, nf, part.p);
         PCAMG_LAUNCHED();
       }
       PCAMG_HIP(hipEventRecord(e0, s));
@@ -1309,13 +1383,14 @@ void bench_level(pcamg_ctx* c, int kind, int prec, int reps, int64_t flush_bytes
 double bench_copy(int64_t nbytes, int reps, hipStream_t s) {
   const size_t n = (size_t)nbytes / sizeof(float4);
   DVec<float4> a(n), b(n);
-  flush_kernel<<<1024, 256, 0, s>>>(a.p, n, 1.0f);
+  fill4_kernel<<<1024, 256, 0, s>>>(a.p, n, 1.0f);
   PCAMG_LAUNCHED();
-  copy_kernel<<<2048, 256, 0, s>>>(a.p, b.p, n);  // warm-up
+  const unsigned blocks = (unsigned)std::min<size_t>(8192, std::max<size_t>(1, (n + 1023) / 1024));
+  copy_kernel<<<blocks, 256, 0, s>>>(a.p, b.p, n);  // warm-up
   PCAMG_LAUNCHED();
   Timer t(s);
   for (int q = 0; q < reps; ++q) {
-    copy_kernel<<<2048, 256, 0, s>>>(a.p, b.p, n);
+    copy_kernel<<<blocks, 256, 0, s>>>(a.p, b.p, n);
     PCAMG_LAUNCHED();
   }
   return t.ms();

@@ -33,6 +33,10 @@ struct LevelMatrix {
   int32_t ell_w = 0;
   DVec<int32_t> eci;
   DVec<float> eav32;
+  // many colours of a few rows each: a whole sweep in one single-workgroup
+  // launch (colour offsets and long-row ends on the device)
+  bool block_sweep = false;
+  DVec<int32_t> coff_d, lend_d;
 };
 
 // Gauss-Seidel pass over colour k and residual (b == nullptr: product) of a

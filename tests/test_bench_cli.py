@@ -1,6 +1,6 @@
 """Host logic of bench.py that needs no GPU: the multi-GPU request is refused
-with a message (the build covers one GPU), and the traffic record is read
-only while the smoother's sources match its digest."""
+with a message (the build covers one GPU), and the defaults name the
+power-law workload with FP64 cycles."""
 import importlib.util
 import os
 import subprocess
@@ -23,12 +23,10 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in r.stderr and r.stdout == ""
 
 
-def test_traffic_record_follows_the_sources(tmp_path, monkeypatch):
+def test_default_workload_is_the_power_law_graph_in_fp64(monkeypatch):
     b = _bench()
-    # a record for other sources is ignored
-    rec = tmp_path / "traffic.md"
-    rec.write_text("- traffic_bytes_per_launch: `123`\n- source_digest: `0000000000000000`\n")
-    monkeypatch.setattr(b, "TRAFFIC_FILE", str(rec))
-    assert b.measured_traffic() is None
-    rec.write_text(f"- traffic_bytes_per_launch: `123`\n- source_digest: `{b.kernel_source_digest()}`\n")
-    assert b.measured_traffic() == 123.0
+    monkeypatch.setattr(sys, "argv", ["bench.py"])
+    a = b.parse()
+    assert a.workload == "powerlaw" and a.cycle_prec is None and a.n0 == 4_000_000 and a.gpus == 1
+    # the flush between timed passes exceeds the 256 MB last-level cache
+    assert b.FLUSH_BYTES >= 4 * (256 << 20)
