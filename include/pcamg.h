@@ -403,6 +403,19 @@ pcamg_status pcamg_path_cover(int32_t n, int32_t m, const int32_t* su, const int
 pcamg_status pcamg_orient(int32_t n, const int32_t* nb, int32_t* path_id, int32_t* pos, int32_t* plen,
                           void* stream);
 
+/* pcamg_orient for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same results, with the pointer-jumping workspace in a fixed device
+ * array of the library (12 n + 1 int32 for n up to PCAMG_ORIENT_NOALLOC_MAX_N
+ * = 2^19 vertices: 24 MiB per GPU, held from the first call on a GPU until the
+ * process ends).  Calls no allocator.  n above the maximum returns
+ * PCAMG_EINVAL without touching the GPU.  Every call on one GPU uses that
+ * GPU's one workspace, so calls that overlap on one GPU (several host threads
+ * or streams) race; the caller serialises them.  Synchronises `stream`. */
+#define PCAMG_ORIENT_NOALLOC_MAX_N (1 << 19)
+pcamg_status pcamg_orient_noalloc(int32_t n, const int32_t* nb, int32_t* path_id, int32_t* pos, int32_t* plen,
+                                  void* stream);
+
 /* Aggregation along a cover (Alg. 3): pairing along paths, isolated vertices
  * in ascending id (Cases 1-3), aggregates numbered by smallest member.  In
  * Case 3 the best neighbour v leaves its aggregate only if the rest stays

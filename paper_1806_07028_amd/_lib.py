@@ -143,6 +143,7 @@ _SIGS = {
     "pcamg_sort_edges": ([_i32, _p, _p, _p, _p, _p, _p], _i32),
     "pcamg_path_cover": ([_i32, _i32, _p, _p, _p, _p], _i32),
     "pcamg_orient": ([_i32, _p, _p, _p, _p, _p], _i32),
+    "pcamg_orient_noalloc": ([_i32, _p, _p, _p, _p, _p], _i32),
     "pcamg_aggregate": ([_i32, _p, _p, _p, _p, _p, _p, C.POINTER(_i32), _p, _p], _i32),
     "pcamg_mwm_aggregate": ([_i32, _p, _p, _p, _p, C.POINTER(_i32), _p, _p], _i32),
     "pcamg_galerkin_count": ([_i32, _p, _p, _i32, _p, _p, C.POINTER(_i64), _p], _i32),

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libpcamg.so")
 SOURCES = ["util.hip", "basic.hip", "setup.hip", "coarse.hip", "layout.hip", "tail.hip", "dense.hip", "solver.hip",
-           "learned.hip", "capi.hip"]
+           "learned.hip", "noalloc.hip", "capi.hip"]
 ARCH = "gfx950"
 
 

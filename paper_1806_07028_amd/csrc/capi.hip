@@ -710,6 +710,19 @@ pcamg_status pcamg_orient(int32_t n, const int32_t* nb, int32_t* path_id, int32_
   });
 }
 
+pcamg_status pcamg_orient_noalloc(int32_t n, const int32_t* nb, int32_t* path_id, int32_t* pos, int32_t* plen,
+                                  void* stream) {
+  return guarded([&] {
+    require(n > 0 && nb && path_id && pos && plen, PCAMG_EINVAL, "null argument or n < 1");
+    require(n <= PCAMG_ORIENT_NOALLOC_MAX_N, PCAMG_EINVAL,
+            "pcamg_orient_noalloc: n = " + std::to_string(n) + " exceeds its fixed workspace (at most " +
+                std::to_string(PCAMG_ORIENT_NOALLOC_MAX_N) + " vertices); use pcamg_orient");
+    hipStream_t s = as_stream(stream);
+    orient_paths_ws(n, nb, path_id, pos, plen, orient_noalloc_scratch(), s);
+    PCAMG_HIP(hipStreamSynchronize(s));
+  });
+}
+
 pcamg_status pcamg_aggregate(int32_t n, const int32_t* grp, const int32_t* gci, const double* gw,
                              const double* gkey, const int32_t* nb, int32_t* agg, int32_t* nc, int32_t* stats,
                              void* stream) {

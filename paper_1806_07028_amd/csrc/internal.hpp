@@ -268,6 +268,9 @@ void orient_paths(int32_t n, const int32_t* nb, int32_t* path_id, int32_t* pos, 
 inline size_t orient_ws_ints(int32_t n) { return 12 * (size_t)n + 1; }
 void orient_paths_ws(int32_t n, const int32_t* nb, int32_t* path_id, int32_t* pos, int32_t* plen, int32_t* ws,
                      hipStream_t s);
+// noalloc.hip: device address (current device) of the fixed orientation
+// workspace of orient_ws_ints(PCAMG_ORIENT_NOALLOC_MAX_N) int32.
+int32_t* orient_noalloc_scratch();
 
 struct AggStats {
   int32_t n_unagg = 0, case1 = 0, case2 = 0, case3 = 0, middle = 0, singleton = 0, p1_fallback = 0;
