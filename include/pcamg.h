@@ -20,6 +20,10 @@
  *    Sec. 4.3: connected, no self loops, positive weights, undirected).
  *  - The caller owns every array it passes; the library copies what it keeps.
  *    Outputs are written into caller-allocated arrays of the stated sizes.
+ *  - Threads: one host thread at a time drives the library.  A run with
+ *    several host threads solving at once (the former multi-worker batch)
+ *    ended in a host crash whose cause is not shown, so concurrent calls from
+ *    several threads are not supported.
  */
 #ifndef PCAMG_H
 #define PCAMG_H
@@ -153,6 +157,8 @@ typedef struct {
   int32_t hist_len;        /* entries written to relres_hist */
   double* relres_hist;     /* host, optional: relres after each iteration (index 0 = 1.0) */
   int32_t hist_cap;        /* capacity of relres_hist */
+  int32_t learned_builds;  /* re-setups built from the network's proposal (pcamg_setup_learned) */
+  int32_t fallback_builds; /* re-setups of a learned context built from the plain relaxation */
 } pcamg_stats;
 
 const char* pcamg_status_str(pcamg_status s);
@@ -227,8 +233,11 @@ pcamg_status pcamg_level_info(pcamg_ctx* c, int32_t h, int32_t level, int64_t* i
  * Names (int32): "colour"[n], "agg"[n], "A_rp"[n+1], "A_ci"[nnz],
  * "path_id"[n], "pos"[n], "nb"[2n], "G_rp"[n+1], "G_ci"[nnz_G];
  * (double): "A_v"[nnz], "d"[n], "dinv"[n], "pval"[n], "G_v"[nnz_G],
- * "gkey"[nnz_G] (level 0).  Setup arrays (path_id, pos, nb, G_*, gkey) need
- * keep_setup = 1.  Returns PCAMG_EINVAL for an unknown or absent name. */
+ * "gkey"[nnz_G] (level 0), "source"[n] (level 0: the vector the hierarchy was
+ * built from before any relaxation sweep -- the start vector for the first,
+ * the error approximation or fresh start vector of a re-setup).  Setup arrays
+ * (path_id, pos, nb, G_*, gkey, source) need keep_setup = 1.  Returns
+ * PCAMG_EINVAL for an unknown or absent name. */
 pcamg_status pcamg_level_get(pcamg_ctx* c, int32_t h, int32_t level, const char* name, void* out);
 
 /* One multigrid cycle of hierarchy h (gamma 1 = V(1,1), 2 = W) on A x = b at
@@ -331,16 +340,26 @@ pcamg_status pcamg_net_loss_grad(pcamg_net* net, const pcamg_graph* g, const dou
  * last gradient. */
 pcamg_status pcamg_net_adam_step(pcamg_net* net, float lr, void* stream);
 
+/* `sweeps` symmetric multicolour Gauss-Seidel sweeps on A e = 0 (the
+ * relaxation before every build, Sec. 3.2) applied to e_in (device double
+ * [n], natural order) into e_out (may alias e_in). */
+pcamg_status pcamg_relax_vector(const pcamg_graph* g, const pcamg_params* p, int32_t sweeps, const double* e_in,
+                                double* e_out, void* stream);
+
 /* The start vector of the first build: SplitMix64 xi (stream p->seed, build 0)
  * relaxed by `sweeps` symmetric multicolour Gauss-Seidel sweeps on A e = 0
  * (Sec. 3.2), device double [n], natural order. */
 pcamg_status pcamg_start_vector(const pcamg_graph* g, const pcamg_params* p, int32_t sweeps, double* e,
                                 void* stream);
 
-/* pcamg_setup with the first hierarchy built from the network's proposal for
- * the start vector relaxed by p->first_sweeps sweeps (-1: 2); re-setups as in
- * Alg. 5 (the measured convergence factor decides, the relaxation stays the
- * fallback). */
+/* pcamg_setup with every hierarchy built from the network's proposal: the
+ * first from the start vector, each re-setup of Alg. 5 from its source vector
+ * (Alg. 2's error approximation), each relaxed by p->first_sweeps sweeps (-1:
+ * 2) instead of relax_sweeps and mapped by the network to the smooth error
+ * whose level sets give the path-cover keys (Alg. 4 Step 2).  The measured
+ * convergence factor stays the judge: a learned hierarchy whose first ConvR
+ * exceeds 0.9 hands the next build to the plain relaxation of relax_sweeps
+ * sweeps.  `net` must stay alive and unchanged until pcamg_destroy. */
 pcamg_status pcamg_setup_learned(const pcamg_graph* g, const double* rhs, const pcamg_params* p, pcamg_net* net,
                                  void* stream, pcamg_ctx** out);
 

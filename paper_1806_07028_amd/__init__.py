@@ -141,7 +141,8 @@ class Solver:
         inf = self.level_info(level, h)
         n, nnz, nG = inf["n"], inf["nnz"], inf["nnz_G"]
         size = {"colour": n, "agg": n, "A_rp": n + 1, "A_ci": nnz, "path_id": n, "pos": n, "nb": 2 * n,
-                "G_rp": n + 1, "G_ci": nG, "A_v": nnz, "d": n, "dinv": n, "pval": n, "G_v": nG, "gkey": nG}[name]
+                "G_rp": n + 1, "G_ci": nG, "A_v": nnz, "d": n, "dinv": n, "pval": n, "G_v": nG, "gkey": nG,
+                "source": n}[name]
         out = np.empty(max(size, 1), dtype=np.int32 if name in self._INT_NAMES else np.float64)
         _lib.check(lib().pcamg_level_get(self.h, self._h(h), level, name.encode(), out.ctypes.data))
         return out[:size]

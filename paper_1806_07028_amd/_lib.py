@@ -82,6 +82,8 @@ class Stats(C.Structure):
         ("hist_len", _i32),
         ("relres_hist", C.POINTER(C.c_double)),
         ("hist_cap", _i32),
+        ("learned_builds", _i32),
+        ("fallback_builds", _i32),
     ]
 
 
@@ -118,6 +120,7 @@ _SIGS = {
     "pcamg_net_forward": ([_p, C.POINTER(Graph), _p, _p, _p], _i32),
     "pcamg_net_loss_grad": ([_p, C.POINTER(Graph), _p, _p, C.POINTER(C.c_double), _p, _p], _i32),
     "pcamg_net_adam_step": ([_p, C.c_float, _p], _i32),
+    "pcamg_relax_vector": ([C.POINTER(Graph), C.POINTER(Params), _i32, _p, _p, _p], _i32),
     "pcamg_start_vector": ([C.POINTER(Graph), C.POINTER(Params), _i32, _p, _p], _i32),
     "pcamg_setup_learned": ([C.POINTER(Graph), _p, C.POINTER(Params), _p, _p, C.POINTER(_p)], _i32),
     "pcamg_batch_solve": ([C.POINTER(Graph), C.POINTER(_p), C.POINTER(_p), _i32, C.POINTER(Params), _i32,

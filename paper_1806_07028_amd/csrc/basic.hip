@@ -331,18 +331,64 @@ __device__ __forceinline__ bool jp_try_h(int32_t v, const int32_t* __restrict__ 
   return false;
 }
 
+// jp_try_h resuming where the vertex's last attempt stopped: cur[v] is the
+// first higher-priority neighbour not yet seen coloured and usedm[v] the set
+// of colours below 64 of those before it.  Colours are final once set, so the
+// accumulated set equals a fresh scan, and the colour chosen is the same; a
+// vertex blocked for many rounds no longer rescans its coloured prefix.
+__device__ __forceinline__ bool jp_try_hc(int32_t v, const int32_t* __restrict__ hrp,
+                                          const int32_t* __restrict__ hci, int32_t* colour, int32_t* __restrict__ cur,
+                                          unsigned long long* __restrict__ usedm) {
+  constexpr int U = 8;
+  const int32_t k1 = hrp[v + 1];
+  unsigned long long used = usedm[v];
+  for (int32_t k = cur[v]; k < k1; k += U) {
+    int32_t cu[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j)  // padding: a colour that neither blocks nor takes a slot
+      cu[j] = k + j < k1 ? __atomic_load_n(&colour[hci[k + j]], __ATOMIC_RELAXED) : INT32_MAX;
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      if (cu[j] < 0) {
+        cur[v] = k + j;
+        usedm[v] = used;
+        return true;
+      }
+      if (cu[j] < 64) used |= 1ull << cu[j];
+    }
+  }
+  int32_t c;
+  if (~used != 0ull) {  // a free colour below 64 (colours above do not matter)
+    c = __ffsll((long long)~used) - 1;
+  } else {  // colours 0..63 all taken: the next windows of 64, one list scan each
+    const int32_t k0 = hrp[v];
+    c = -1;
+    for (int32_t base = 64; c < 0; base += 64) {
+      unsigned long long win = 0ull;
+      for (int32_t k = k0; k < k1; ++k) {
+        const int32_t cw = __atomic_load_n(&colour[hci[k]], __ATOMIC_RELAXED) - base;
+        if (cw >= 0 && cw < 64) win |= 1ull << cw;
+      }
+      if (~win != 0ull) c = base + __ffsll((long long)~win) - 1;
+    }
+  }
+  __atomic_store_n(&colour[v], c, __ATOMIC_RELAXED);
+  return false;
+}
+
 // One round over a worklist of uncoloured vertices; the ones still uncoloured
 // go to the next list (in any order: the colouring does not depend on it).
 __global__ void __launch_bounds__(256)
     jp_list_kernel(const int32_t* __restrict__ cnt_in, const int32_t* __restrict__ in, int32_t* __restrict__ cnt_out,
                    int32_t* __restrict__ out, const int32_t* __restrict__ hrp, const int32_t* __restrict__ hci,
-                   int32_t* colour) {
+                   int32_t* colour, int32_t* __restrict__ cur, unsigned long long* __restrict__ usedm) {
   const int32_t m = *cnt_in;
   const int32_t stride = gridDim.x * blockDim.x;
   for (int32_t base = blockIdx.x * blockDim.x; base < m; base += stride) {
     const int32_t t = base + threadIdx.x;
     const int32_t v = t < m ? in[t] : -1;
-    const bool left = v >= 0 && __atomic_load_n(&colour[v], __ATOMIC_RELAXED) < 0 && jp_try_h(v, hrp, hci, colour);
+    const bool left =
+        v >= 0 && __atomic_load_n(&colour[v], __ATOMIC_RELAXED) < 0 && jp_try_hc(v, hrp, hci, colour, cur, usedm);
     const unsigned long long bal = __ballot(left);
     if (!bal) continue;
     const int lane = threadIdx.x & 63;
@@ -456,7 +502,10 @@ int32_t colour_jp(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed
     DVec<int32_t> hci(std::max<int32_t>(htot, 1));
     higher_fill_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, rp, ci, prio.p, hrp.p, hci.p);
     PCAMG_LAUNCHED();
-    DVec<int32_t> list0(n), list1(n), cnt(R + 1);
+    DVec<int32_t> list0(n), list1(n), cnt(R + 1), cur(n);
+    DVec<uint64_t> usedm(n);
+    copy_d2d(cur.p, hrp.p, n, s);
+    fill_u64(usedm.p, 0ull, n, s);
     iota_i32(list0.p, n, s);
     fill_i32(cnt.p, 0, R + 1, s);
     fill_i32(cnt.p, n, 1, s);
@@ -468,7 +517,8 @@ int32_t colour_jp(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed
       for (int r = 0; r < R; ++r) {
         const int32_t* in = (r & 1) ? list1.p : list0.p;
         int32_t* out = (r & 1) ? list0.p : list1.p;
-        jp_list_kernel<<<grid, 256, 0, s>>>(cnt.p + r, in, cnt.p + r + 1, out, hrp.p, hci.p, colour);
+        jp_list_kernel<<<grid, 256, 0, s>>>(cnt.p + r, in, cnt.p + r + 1, out, hrp.p, hci.p, colour, cur.p,
+                                            (unsigned long long*)usedm.p);
         PCAMG_LAUNCHED();
       }
       rounds += R;
@@ -804,8 +854,9 @@ __global__ void __launch_bounds__(LONG_T)
 // [coff[c], lend[c]) go to the groups in turn, each summed with exactly the
 // tree of gs_long_kernel (a group's chains, a butterfly per wavefront, the
 // group's four wavefront sums in order), and the other rows [lend[c],
-// coff[c+1]) are single fma chains in stored order, one thread each, as in
-// gs_kernel -- so every value is bit-identical to the launch-per-colour path.
+// coff[c+1]) are single fma chains in stored order, a wavefront each (its
+// lanes load the entries, as gs_kernel's lane groups do) -- so every value is
+// bit-identical to the launch-per-colour path.
 // A workgroup barrier separates dependent colours.
 // ---------------------------------------------------------------------------
 constexpr int SWEEP_GROUPS = 4;
@@ -855,11 +906,15 @@ __global__ void __launch_bounds__(LONG_T * SWEEP_GROUPS)
       }
       __syncthreads();
     }
-    // short rows: one chain each
-    for (int32_t i = rl + tid; i < r1; i += LONG_T * SWEEP_GROUPS) {
-      T sum = (T)0;
-      for (int32_t k = rp[i]; k < rp[i + 1]; ++k) sum = fma(av[k], x[ci[k]], sum);
-      x[i] = (b[i] - sum) * dinv[i];
+    // the other rows: one wavefront each, its lanes loading the entries and
+    // all of them running the row's single chain in stored order
+    const int wave = tid >> 6;
+    for (int32_t i0 = rl; i0 < r1; i0 += (LONG_T * SWEEP_GROUPS) / 64) {
+      const int32_t i = i0 + wave;  // uniform per wavefront
+      const bool ok = i < r1;
+      const int32_t k0 = ok ? rp[i] : 0;
+      const T sum = row_chain_g<T, 64>(k0, ok ? rp[i + 1] - k0 : 0, ci, av, x, (T)0);
+      if (ok && (tid & 63) == 0) x[i] = (b[i] - sum) * dinv[i];
     }
     __syncthreads();
   }

@@ -277,7 +277,15 @@ void setup_impl(const pcamg_graph* g, const double* rhs, const pcamg_params* p, 
     *out = c.release();
     return;
   }
+  DVec<double> src;
+  if (p->keep_setup) {  // the first build's source: the start vector before any sweep
+    src.resize(g->n);
+    xi_fill(p->seed, 0, nullptr, src.p, g->n, s);
+  }
   if (net) {  // the network's proposal from first_sweeps (default 2) sweeps
+    c->net = net;
+    c->w.resize(std::max(g->nnz, 1));
+    copy_d2d(c->w.p, g->weight, g->nnz, s);
     DVec<double> e2(g->n);
     initial_error(c.get(), 0, e2.p, p->first_sweeps >= 0 ? p->first_sweeps : 2);
     net_forward_f64(net, g, e2.p, e.p, s);
@@ -285,6 +293,7 @@ void setup_impl(const pcamg_graph* g, const double* rhs, const pcamg_params* p, 
     initial_error(c.get(), 0, e.p, p->first_sweeps);
   }
   c->hist.push_back(build_hierarchy(c.get(), e.p));
+  if (src.p) c->hist.back()->source = std::move(src);
   c->t_build_ms = t.ms();
   *out = c.release();
 }
@@ -314,6 +323,22 @@ pcamg_status pcamg_start_vector(const pcamg_graph* g, const pcamg_params* p, int
     c.s = s;
     ctx_init(&c, g, p);
     initial_error(&c, 0, e, sweeps);
+    PCAMG_HIP(hipStreamSynchronize(s));
+  });
+}
+
+pcamg_status pcamg_relax_vector(const pcamg_graph* g, const pcamg_params* p, int32_t sweeps, const double* e_in,
+                                double* e_out, void* stream) {
+  return guarded_s(as_stream(stream), [&] {
+    require(g && p && e_in && e_out && sweeps >= 0, PCAMG_EINVAL, "bad argument");
+    hipStream_t s = as_stream(stream);
+    if (p->validate) validate_graph(g, s);
+    require(g->n >= 1, PCAMG_EINVAL, "empty graph");
+    pcamg_ctx c;
+    c.s = s;
+    ctx_init(&c, g, p);
+    if (e_out != e_in) copy_d2d(e_out, e_in, g->n, s);
+    relax_homogeneous(&c, e_out, sweeps);
     PCAMG_HIP(hipStreamSynchronize(s));
   });
 }
@@ -500,6 +525,12 @@ pcamg_status pcamg_level_get(pcamg_ctx* c, int32_t h, int32_t level, const char*
     require(!H.setup.empty(), PCAMG_EINVAL, "level arrays need keep_setup = 1");
     SetupLevel& S = H.setup[level];
     const std::string nm(name);
+    if (nm == "source") {
+      require(level == 0 && H.source.p != nullptr, PCAMG_EINVAL, "no source vector for this hierarchy");
+      PCAMG_HIP(hipMemcpyAsync(out, H.source.p, (size_t)c->n * sizeof(double), hipMemcpyDeviceToHost, c->s));
+      PCAMG_HIP(hipStreamSynchronize(c->s));
+      return;
+    }
     auto gi = [&](const DVec<int32_t>& v, size_t cnt) {
       require(v.p != nullptr, PCAMG_EINVAL, "array '" + nm + "' not present on this level");
       if (cnt) PCAMG_HIP(hipMemcpyAsync(out, v.p, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, c->s));

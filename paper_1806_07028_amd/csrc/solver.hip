@@ -26,6 +26,10 @@ int32_t pick_lanes(int32_t n, int32_t nnz, int32_t forced) {
 // Levels at most this size run in the single-workgroup tail or are latency
 // bound: no sliced-ELL copy.
 constexpr int32_t SELL_MIN_N = 4096;
+// A hierarchy built from the network's proposal whose first measured
+// convergence factor exceeds this gives the next re-setup back to the plain
+// relaxation (the network is judged by the convergence it delivers).
+constexpr double LEARNED_FALLBACK_CONVR = 0.9;
 // Levels at most this size are not timed by the lanes autotuner (they run in
 // the tail kernel by default).
 constexpr int32_t TUNE_MIN_N = 2048;
@@ -1057,8 +1061,12 @@ void solve(pcamg_ctx* c, double* x_nat, pcamg_stats* st) {
     return mean > P.theta;
   };
   // re-setup (Alg. 5, Steps 13-16); corr is the correction for x (0 for the relaxation source)
+  int learned_builds = 0, fallback_builds = 0;
+  bool last_learned = c->net != nullptr;  // the first hierarchy came from the network
+  double first_convr = 0.0;               // first ConvR measured with the current hierarchy
   auto rebuild = [&](const double* res, double* corr) {
     Timer tr(s);
+    first_convr = conv.empty() ? 0.0 : conv.front();
     const int Re = (int)c->hist.size();
     DVec<double> eb(n), enat(n), zero(n);
     if (P.rebuild_source == PCAMG_REBUILD_ERROR_APPROX) {
@@ -1083,10 +1091,33 @@ void solve(pcamg_ctx* c, double* x_nat, pcamg_stats* st) {
       fill_f64(corr, 0.0, n, s);
     }
     fill_f64(zero.p, 0.0, n, s);
-    if (P.rebuild_source != PCAMG_REBUILD_ITERATE) relax_perm(c, eb.p, zero.p, P.relax_sweeps);
-    scatter_f64(eb.p, A.perm.p, enat.p, n, s);
+    DVec<double> src;
+    if (P.keep_setup) {  // the build's source vector before any sweep, for inspection
+      src.resize(n);
+      scatter_f64(eb.p, A.perm.p, src.p, n, s);
+    }
+    // learned proposals: the network maps the source relaxed by first_sweeps
+    // (default 2) to the build's smooth error; a learned hierarchy whose first
+    // measured ConvR exceeded LEARNED_FALLBACK_CONVR hands the next build back
+    // to the plain relaxation
+    const bool use_net = c->net && P.rebuild_source != PCAMG_REBUILD_ITERATE &&
+                         !(last_learned && first_convr > LEARNED_FALLBACK_CONVR);
+    if (use_net) {
+      relax_perm(c, eb.p, zero.p, P.first_sweeps >= 0 ? P.first_sweeps : 2);
+      DVec<double> e2(n);
+      scatter_f64(eb.p, A.perm.p, e2.p, n, s);
+      const pcamg_graph g{n, c->nnz, c->rp.p, c->ci.p, c->w.p};
+      net_forward_f64(c->net, &g, e2.p, enat.p, s);
+      ++learned_builds;
+    } else {
+      if (P.rebuild_source != PCAMG_REBUILD_ITERATE) relax_perm(c, eb.p, zero.p, P.relax_sweeps);
+      scatter_f64(eb.p, A.perm.p, enat.p, n, s);
+      if (c->net) ++fallback_builds;
+    }
+    last_learned = use_net;
     Timer tb(s);
     c->hist.push_back(build_hierarchy(c, enat.p));
+    if (src.p) c->hist.back()->source = std::move(src);
     t_build += tb.ms();
     oc_sum += c->hist.back()->op_complexity;
     ++nh;
@@ -1214,6 +1245,8 @@ void solve(pcamg_ctx* c, double* x_nat, pcamg_stats* st) {
     st->vcycles64 = vc64;
     st->vcycles32 = vc32;
     st->wcycles = wc;
+    st->learned_builds = learned_builds;
+    st->fallback_builds = fallback_builds;
     st->hist_len = 0;
     if (st->relres_hist && st->hist_cap > 0) {
       const int h = std::min<int>(st->hist_cap, (int)hist.size());

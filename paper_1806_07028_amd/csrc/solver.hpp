@@ -133,6 +133,7 @@ struct Hierarchy {
   DVec<double> cL, cD;
   double op_complexity = 0.0;
   std::vector<SetupLevel> setup;  // if keep_setup
+  DVec<double> source;             // if keep_setup: the build's vector before the sweeps (natural order)
   AggStats st0;
   int32_t cover_rounds = 0;
 };
@@ -182,6 +183,10 @@ struct pcamg_ctx {
   int32_t starts_used = 0;     // start vectors drawn from the seed stream
   pcamg::DVec<double> rhs;     // natural order
   bool have_rhs = false;
+  // learned proposals (pcamg_setup_learned): the caller's network (not owned)
+  // and the graph weights its features need
+  pcamg_net* net = nullptr;
+  pcamg::DVec<double> w;
   double t_build_ms = 0.0;
 };
 

@@ -849,25 +849,20 @@ def test_dense_w_cycle_nested(gpu, oracle, shape, dmax):
     close_elementwise(w32, w32_ref, 1e-5)
 
 
-@pytest.mark.parametrize("gname", ["powerlaw", "ba_dense"])
-def test_block_sweep_bit_identical(gpu, gname):
+@pytest.mark.parametrize("n0", [60000, 150000])
+def test_block_sweep_bit_identical(gpu, n0):
     """Levels with many colours of a few rows each (near-dense coarse levels of
     power-law graphs) run each sweep in one single-workgroup launch: the same
     arithmetic as one launch per colour, so every cycle and the whole solve are
     bit-identical with the block sweep switched off."""
-    if gname == "powerlaw":
-        g = I.config3(n0=60000)[0]
-        kw = dict(a2_hub_cap=64)
-    else:
-        n_, a_, b_ = I.ba_edges(20000, 12)
-        g = I.csr_from_edges(n_, a_, b_, I.log_uniform_weights(5, len(a_), -2, 2))
-        kw = {}
+    g = I.config3(n0=n0)[0]
+    kw = dict(a2_hub_cap=64)
     n = g[0]
     b = I.zero_mean_normal_rhs(3, n)
     on = solver_for(gpu, g, b, block_sweep_min_colours=64, **kw)
     off = solver_for(gpu, g, b, block_sweep_min_colours=0, **kw)
     sizes = [(on.level_info(l)["n"], on.level_info(l)["ncolours"]) for l in range(on.num_levels())]
-    print(f"{gname}: levels (n, colours) {sizes}", flush=True)
+    print(f"power-law n0={n0}: levels (n, colours) {sizes}", flush=True)
     assert any(c >= 64 and m <= 64 * c and m > 2048 for m, c in sizes[1:-1]), sizes
     x0 = I.normal(4, n)
     b32 = b.astype(np.float32)

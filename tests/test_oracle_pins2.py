@@ -324,3 +324,20 @@ def test_alg6_homogeneous_loop(oracle, init):
     assert abs(r.x.sum()) <= 1e-12 * n * np.abs(x0).max()
     # Table 3 context (64 x 64 grid, b = 0): 16 iterations with 4 re-setups
     assert 8 <= st["iterations"] <= 30 and 1 <= st["rebuilds"] <= 8
+
+
+@pytest.mark.parametrize("case,paper_iter", [("grid64", 16), ("grid128", 16), ("ring1024", 15), ("ring4096", 15)])
+def test_alg6_against_paper_tables(oracle, case, paper_iter):
+    """Alg. 6 (b = 0, theta 0.5, MWM initial hierarchy) against the counts the
+    paper prints for it (Table 3: 2D grids, 16 iterations and 4 re-setups;
+    Table 6: rings, 15 and 4): the same 4 re-setups and iterations within one
+    of the printed count, for random starts drawn from three seeds."""
+    g = {"grid64": lambda: I.grid2d(64, 64), "grid128": lambda: I.grid2d(128, 128),
+         "ring1024": lambda: I.ring(1024, 4), "ring4096": lambda: I.ring(4096, 4)}[case]()
+    n = g[0]
+    for seed in (4321, 1, 2):
+        x0 = 2.0 * I.uniform(seed, n) - 1.0
+        r = oracle.solve(g, np.zeros(n), x0=x0, outer=0, theta=0.5, rebuild_rule=1, rebuild_source=2, init=1)
+        assert r.stats["status"] == 0
+        assert r.stats["rebuilds"] == 4, (seed, r.stats["rebuilds"])
+        assert abs(r.stats["iterations"] - paper_iter) <= 1, (seed, r.stats["iterations"])
