@@ -232,7 +232,7 @@ pcamg_status pcamg_params_default(pcamg_params* p) {
   p->seed = 0x5EED;
   p->colour_seed = 0xC010;
   p->case3 = 0;
-  p->block_sweep_min_colours = 64;
+  p->block_sweep_min_colours = 0;
   p->init = PCAMG_INIT_RELAX;
   return PCAMG_OK;
 }

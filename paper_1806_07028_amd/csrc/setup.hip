@@ -621,6 +621,15 @@ __global__ void pair_kernel(int32_t n, const int32_t* __restrict__ nb, const int
 }
 
 // best neighbour: smallest (key, id) with keys; else largest weight, ties smaller id
+constexpr int32_t BEST_LONG = 256;
+
+__global__ void long_row_flag_kernel(int32_t n, const int32_t* __restrict__ obj, const int32_t* __restrict__ grp,
+                                     uint8_t* __restrict__ flag) {
+  int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n) return;
+  flag[u] = obj[u] < 0 && grp[u + 1] - grp[u] > BEST_LONG;
+}
+
 __global__ void best_kernel(int32_t n, const int32_t* __restrict__ obj, const int32_t* __restrict__ grp,
                             const int32_t* __restrict__ gci, const double* __restrict__ gw,
                             const double* __restrict__ gkey, int32_t* __restrict__ best, uint8_t* __restrict__ unagg) {
@@ -629,6 +638,10 @@ __global__ void best_kernel(int32_t n, const int32_t* __restrict__ obj, const in
   unagg[u] = obj[u] < 0;
   if (obj[u] >= 0) {
     best[u] = -1;
+    return;
+  }
+  if (grp[u + 1] - grp[u] > BEST_LONG) {  // long rows: best_long_kernel, a wavefront each
+    best[u] = -2;
     return;
   }
   int32_t b = -1;
@@ -643,6 +656,43 @@ __global__ void best_kernel(int32_t n, const int32_t* __restrict__ obj, const in
     }
   }
   best[u] = b;
+}
+
+// The same for rows of more than BEST_LONG entries, one wavefront per row of
+// the list: each lane keeps the best of a strided share, then the lanes'
+// candidates are reduced by (weight or key, then column id) -- the unique
+// first best of the row in stored (ascending column) order, as above.
+__global__ void __launch_bounds__(256)
+    best_long_kernel(int32_t m, const int32_t* __restrict__ rows, const int32_t* __restrict__ grp,
+                     const int32_t* __restrict__ gci, const double* __restrict__ gw, const double* __restrict__ gkey,
+                     int32_t* __restrict__ best) {
+  const int32_t t = (int32_t)(((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);  // uniform per wavefront
+  if (t >= m) return;
+  const int lane = (int)(threadIdx.x & 63);
+  const int32_t u = rows[t];
+  int32_t b = -1;
+  double bv = 0.0;
+  for (int32_t k = grp[u] + lane; k < grp[u + 1]; k += 64) {
+    const int32_t c = gci[k];
+    if (gkey) {
+      const double key = gkey[k];
+      if (b < 0 || key < bv) { b = c; bv = key; }
+    } else {
+      const double w = gw[k];
+      if (b < 0 || w > bv) { b = c; bv = w; }
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const int32_t ob = __shfl_xor(b, o, 64);
+    const double ov = __shfl_xor(bv, o, 64);
+    bool take;
+    if (ob < 0) take = false;
+    else if (b < 0) take = true;
+    else if (gkey) take = ov < bv || (ov == bv && ob < b);
+    else take = ov > bv || (ov == bv && ob < b);
+    if (take) { b = ob; bv = ov; }
+  }
+  if (lane == 0) best[u] = b;
 }
 
 enum { ST_SINGLETON = 0, ST_CASE1, ST_CASE2, ST_CASE3, ST_MIDDLE, ST_COUNT };
@@ -793,6 +843,18 @@ int32_t aggregate_level(int32_t n, const int32_t* grp, const int32_t* gci, const
   PCAMG_LAUNCHED();
   best_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, obj.p, grp, gci, gw, gkey, best.p, unagg.p);
   PCAMG_LAUNCHED();
+  {  // rows of more than BEST_LONG entries still unaggregated: a wavefront each
+    DVec<uint8_t> lflag(n);
+    DVec<int32_t> lrows(n), lcnt(1);
+    long_row_flag_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, obj.p, grp, lflag.p);
+    PCAMG_LAUNCHED();
+    compact_i32(nullptr, lflag.p, lrows.p, lcnt.p, n, s);
+    const int32_t nl = read_scalar(lcnt.p, s);
+    if (nl > 0) {
+      best_long_kernel<<<grid_for((size_t)nl * 64, 256), 256, 0, s>>>(nl, lrows.p, grp, gci, gw, gkey, best.p);
+      PCAMG_LAUNCHED();
+    }
+  }
   compact_i32(nullptr, unagg.p, pend.p, cnt.p, n, s);
   const int32_t npend = read_scalar(cnt.p, s);
   st.n_unagg = npend;
