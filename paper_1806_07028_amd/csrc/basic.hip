@@ -221,41 +221,6 @@ __global__ void __launch_bounds__(1024)
   for (int32_t i = threadIdx.x; i < n; i += blockDim.x) colour[i] = col[i];
 }
 
-// Larger near-dense levels: the same sequential first-fit, the order from a
-// device radix sort (ascending (key, id), walked backwards), the colours in
-// global memory and the bitmask of the colours around the current vertex in
-// LDS (a vertex's colour is at most its degree, so max degree + 1 bits).
-constexpr int32_t SEQ_LARGE_MAX = 1 << 16;
-constexpr int32_t SEQ_BITS_MAX = 65536;
-__global__ void __launch_bounds__(1024)
-    greedy_seq_large_kernel(int32_t n, int32_t nwords, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                            const uint32_t* __restrict__ asc, int32_t* colour) {
-  __shared__ uint32_t used[SEQ_BITS_MAX / 32];
-  __shared__ int32_t pick;
-  for (int32_t w = threadIdx.x; w < nwords; w += blockDim.x) used[w] = 0u;
-  if (threadIdx.x == 0) pick = INT32_MAX;
-  __syncthreads();
-  for (int32_t t = n - 1; t >= 0; --t) {
-    const int32_t v = (int32_t)asc[t];
-    for (int32_t k = rp[v] + threadIdx.x; k < rp[v + 1]; k += blockDim.x) {
-      const int32_t cu = __atomic_load_n(&colour[ci[k]], __ATOMIC_RELAXED);
-      if (cu >= 0) atomicOr(&used[cu >> 5], 1u << (cu & 31));
-    }
-    __syncthreads();
-    for (int32_t w = threadIdx.x; w < nwords; w += blockDim.x) {
-      const uint32_t fr = ~used[w];
-      if (fr) atomicMin(&pick, w * 32 + __ffs((int)fr) - 1);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      __atomic_store_n(&colour[v], pick, __ATOMIC_RELAXED);
-      pick = INT32_MAX;
-    }
-    for (int32_t w = threadIdx.x; w < nwords; w += blockDim.x) used[w] = 0u;
-    __syncthreads();
-  }
-}
-
 __global__ void row_len_max_kernel(int32_t n, const int32_t* __restrict__ rp, int32_t* __restrict__ out) {
   int32_t m = 0;
   for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
@@ -267,68 +232,91 @@ __global__ void row_len_max_kernel(int32_t n, const int32_t* __restrict__ rp, in
 // The higher-priority neighbours of every vertex (larger (priority, id)), in
 // column order: the only ones its first-fit colour depends on.  A blocked
 // hub then checks its few higher neighbours, not its whole row.
+// Rows of more than ROW_LONG entries are left by the thread-per-row kernels
+// below to a workgroup each (a power-law level's hubs have thousands).
+constexpr int32_t ROW_LONG = 256;
+
+__device__ __forceinline__ bool prio_higher(uint64_t pu, int32_t u, uint64_t pv, int32_t v) {
+  return pu > pv || (pu == pv && u > v);
+}
+
 __global__ void higher_count_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                     const uint64_t* __restrict__ prio, int32_t* __restrict__ cnt) {
   const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
+  if (v >= n || rp[v + 1] - rp[v] > ROW_LONG) return;
   const uint64_t pv = prio[v];
   int32_t c = 0;
   for (int32_t k = rp[v]; k < rp[v + 1]; ++k) {
     const int32_t u = ci[k];
-    const uint64_t pu = prio[u];
-    c += pu > pv || (pu == pv && u > v);
+    c += prio_higher(prio[u], u, pv, v);
   }
   cnt[v] = c;
+}
+
+__global__ void __launch_bounds__(256)
+    higher_count_long_kernel(const int32_t* __restrict__ rows, const int32_t* __restrict__ rp,
+                             const int32_t* __restrict__ ci, const uint64_t* __restrict__ prio,
+                             int32_t* __restrict__ cnt) {
+  __shared__ int32_t wsum[4];
+  const int32_t v = rows[blockIdx.x];
+  const uint64_t pv = prio[v];
+  int32_t c = 0;
+  for (int32_t k = rp[v] + (int32_t)threadIdx.x; k < rp[v + 1]; k += 256) {
+    const int32_t u = ci[k];
+    c += prio_higher(prio[u], u, pv, v);
+  }
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) cnt[v] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
 __global__ void higher_fill_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                    const uint64_t* __restrict__ prio, const int32_t* __restrict__ hrp,
                                    int32_t* __restrict__ hci) {
   const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
+  if (v >= n || rp[v + 1] - rp[v] > ROW_LONG) return;
   const uint64_t pv = prio[v];
   int32_t o = hrp[v];
   for (int32_t k = rp[v]; k < rp[v + 1]; ++k) {
     const int32_t u = ci[k];
-    const uint64_t pu = prio[u];
-    if (pu > pv || (pu == pv && u > v)) hci[o++] = u;
+    if (prio_higher(prio[u], u, pv, v)) hci[o++] = u;
   }
 }
 
-// jp_try over the higher-priority list: true if a higher neighbour is still
-// uncoloured; else v takes the smallest colour none of them has.
-__device__ __forceinline__ bool jp_try_h(int32_t v, const int32_t* __restrict__ hrp, const int32_t* __restrict__ hci,
-                                         int32_t* colour) {
-  constexpr int U = 8;
-  const int32_t k0 = hrp[v], k1 = hrp[v + 1];
-  unsigned long long used = 0ull;
-  for (int32_t k = k0; k < k1; k += U) {
-    int32_t cu[U];
-#pragma unroll
-    for (int j = 0; j < U; ++j)  // padding: a colour that neither blocks nor takes a slot
-      cu[j] = k + j < k1 ? __atomic_load_n(&colour[hci[k + j]], __ATOMIC_RELAXED) : INT32_MAX;
-#pragma unroll
-    for (int j = 0; j < U; ++j) {
-      if (cu[j] < 0) return true;
-      if (cu[j] < 64) used |= 1ull << cu[j];
+// The same for the long rows: 256 entries per step, kept in column order by
+// a ballot prefix within each wavefront and the wavefronts' counts in LDS.
+__global__ void __launch_bounds__(256)
+    higher_fill_long_kernel(const int32_t* __restrict__ rows, const int32_t* __restrict__ rp,
+                            const int32_t* __restrict__ ci, const uint64_t* __restrict__ prio,
+                            const int32_t* __restrict__ hrp, int32_t* __restrict__ hci) {
+  __shared__ int32_t wsum[4];
+  const int32_t v = rows[blockIdx.x];
+  const uint64_t pv = prio[v];
+  const int lane = (int)(threadIdx.x & 63), wid = (int)(threadIdx.x >> 6);
+  const unsigned long long below = (1ull << lane) - 1ull;
+  const int32_t k1 = rp[v + 1];
+  int32_t o = hrp[v];
+  for (int32_t base = rp[v]; base < k1; base += 256) {
+    const int32_t k = base + (int32_t)threadIdx.x;
+    int32_t u = 0;
+    bool f = false;
+    if (k < k1) {
+      u = ci[k];
+      f = prio_higher(prio[u], u, pv, v);
     }
-  }
-  int32_t c;
-  if (~used != 0ull) {  // a free colour below 64 (colours above do not matter)
-    c = __ffsll((long long)~used) - 1;
-  } else {  // colours 0..63 all taken: the next windows of 64, one list scan each
-    c = -1;
-    for (int32_t base = 64; c < 0; base += 64) {
-      unsigned long long win = 0ull;
-      for (int32_t k = k0; k < k1; ++k) {
-        const int32_t cw = __atomic_load_n(&colour[hci[k]], __ATOMIC_RELAXED) - base;
-        if (cw >= 0 && cw < 64) win |= 1ull << cw;
-      }
-      if (~win != 0ull) c = base + __ffsll((long long)~win) - 1;
+    const unsigned long long bal = __ballot(f);
+    if (lane == 0) wsum[wid] = __popcll(bal);
+    __syncthreads();
+    int32_t off = 0, tot = 0;
+    for (int w = 0; w < 4; ++w) {
+      off += w < wid ? wsum[w] : 0;
+      tot += wsum[w];
     }
+    if (f) hci[o + off + __popcll(bal & below)] = u;
+    o += tot;
+    __syncthreads();
   }
-  __atomic_store_n(&colour[v], c, __ATOMIC_RELAXED);
-  return false;
 }
 
 // jp_try_h resuming where the vertex's last attempt stopped: cur[v] is the
@@ -376,37 +364,190 @@ __device__ __forceinline__ bool jp_try_hc(int32_t v, const int32_t* __restrict__
   return false;
 }
 
-// One round over a worklist of uncoloured vertices; the ones still uncoloured
-// go to the next list (in any order: the colouring does not depend on it).
+// 64-bit words of the per-wavefront colour bitmap of jp_try_wave
+constexpr int JP_BM_WORDS = 32;
+
+// OR of a 64-bit mask over the wavefront
+__device__ __forceinline__ unsigned long long wave_or64(unsigned long long m) {
+  for (int o = 32; o > 0; o >>= 1) m |= __shfl_xor(m, o, 64);
+  return m;
+}
+
+// jp_try_hc for a vertex with a long higher-priority list, by the whole
+// wavefront (v is uniform): 64 entries per step from the cursor, the first
+// uncoloured one (if any) found by a ballot, the colours below 64 of the
+// entries before it OR-ed into the mask; with every higher neighbour
+// coloured, the windows of 64 colours above are scanned the same way.  The
+// same cursor, mask and colour as jp_try_hc.
+__device__ __forceinline__ bool jp_try_wave(int32_t v, const int32_t* __restrict__ hrp,
+                                            const int32_t* __restrict__ hci, int32_t* colour,
+                                            int32_t* __restrict__ cur, unsigned long long* __restrict__ usedm,
+                                            unsigned long long* bm, int lane) {
+  const int32_t k1 = hrp[v + 1];
+  unsigned long long used = usedm[v];
+  for (int32_t k = cur[v]; k < k1; k += 64) {
+    const int32_t kk = k + lane;
+    const int32_t cu = kk < k1 ? __atomic_load_n(&colour[hci[kk]], __ATOMIC_RELAXED) : INT32_MAX;
+    const unsigned long long blk = __ballot(cu < 0);
+    const int first = blk ? __ffsll((long long)blk) - 1 : 64;
+    used |= wave_or64(lane < first && cu >= 0 && cu < 64 ? 1ull << cu : 0ull);
+    if (blk) {
+      if (lane == 0) {
+        cur[v] = k + first;
+        usedm[v] = used;
+      }
+      return true;
+    }
+  }
+  int32_t c;
+  if (~used != 0ull) {
+    c = __ffsll((long long)~used) - 1;
+  } else {
+    // colours 64 .. 64 + 64 JP_BM_WORDS - 1 in one pass over the list: a
+    // bitmap in the wavefront's LDS, then its first free bit
+    const int32_t k0 = hrp[v];
+    if (lane < JP_BM_WORDS) bm[lane] = 0ull;
+    __builtin_amdgcn_wave_barrier();
+    for (int32_t k = k0 + lane; k < k1; k += 64) {
+      const int32_t cw = __atomic_load_n(&colour[hci[k]], __ATOMIC_RELAXED) - 64;
+      if (cw >= 0 && cw < 64 * JP_BM_WORDS) atomicOr(&bm[cw >> 6], 1ull << (cw & 63));
+    }
+    __builtin_amdgcn_wave_barrier();
+    const unsigned long long word = lane < JP_BM_WORDS ? bm[lane] : ~0ull;
+    __builtin_amdgcn_wave_barrier();
+    const unsigned long long fw = __ballot(~word != 0ull);
+    if (fw) {
+      const int fl = __ffsll((long long)fw) - 1;
+      const unsigned long long wfl = __shfl(word, fl, 64);
+      c = 64 + 64 * fl + __ffsll((long long)~wfl) - 1;
+    } else {  // beyond the bitmap: windows of 64, one list scan each
+      c = -1;
+      for (int32_t base = 64 + 64 * JP_BM_WORDS; c < 0; base += 64) {
+        unsigned long long win = 0ull;
+        for (int32_t k = k0; k < k1; k += 64) {
+          const int32_t kk = k + lane;
+          const int32_t cw = kk < k1 ? __atomic_load_n(&colour[hci[kk]], __ATOMIC_RELAXED) - base : -1;
+          win |= cw >= 0 && cw < 64 ? 1ull << cw : 0ull;
+        }
+        win = wave_or64(win);
+        if (~win != 0ull) c = base + __ffsll((long long)~win) - 1;
+      }
+    }
+  }
+  if (lane == 0) __atomic_store_n(&colour[v], c, __ATOMIC_RELAXED);
+  return false;
+}
+
+// Higher-priority lists longer than this go to jp_try_wave.
+constexpr int32_t JP_LANE_MAX = 64;
+
+// Wakes the uncoloured vertex w (a lane's entry, if `act`) for round `next`
+// unless already queued for it: one atomic per wavefront step for the slots.
+__device__ __forceinline__ void jp_wake_push(bool act, int32_t w, const int32_t* colour, int32_t* __restrict__ stamp,
+                                             int32_t next, int32_t* __restrict__ cnt_out, int32_t* __restrict__ out,
+                                             int lane) {
+  const bool push = act && __atomic_load_n(&colour[w], __ATOMIC_RELAXED) < 0 && atomicMax(&stamp[w], next) < next;
+  const unsigned long long pb = __ballot(push);
+  if (!pb) return;
+  const int lead = __ffsll((long long)pb) - 1;
+  int32_t at = 0;
+  if (lane == lead) at = atomicAdd(cnt_out, __popcll(pb));
+  at = __shfl(at, lead, 64);
+  if (push) out[at + __popcll(pb & ((1ull << lane) - 1ull))] = w;
+}
+
+// Rows longer than this are pushed by jp_push_long_kernel.
+constexpr int32_t JP_PUSH_WAVE_MAX = 256;
+// Worklists of at most this many vertices per wavefront of the grid are
+// taken a vertex per wavefront, longer ones a vertex per lane.
+constexpr int32_t JP_WAVE_MODE_PER_WAVE = 4;
+
+// One data-driven round: try the vertices of the worklist; every vertex that
+// takes its colour here wakes its uncoloured neighbours (all of lower
+// priority) for round `next`, each at most once per round (stamp[w] = the
+// last round it was queued for).  A vertex that stays blocked waits on an
+// uncoloured higher neighbour, which wakes it when coloured, so a round costs
+// the vertices around the previous round's colours, not the whole pending
+// set (on a power-law level the hub core needs about a thousand rounds of a
+// few dozen vertices each).  The colouring is the same function of the
+// priorities whatever the schedule.  A wavefront pushes the rows of its newly
+// coloured vertices one at a time, 64 entries per step, and lists the ones
+// with rows of more than JP_PUSH_WAVE_MAX entries for jp_push_long_kernel;
+// vertices with more than JP_LANE_MAX higher-priority neighbours are tried
+// by the wavefront too, and a short worklist is taken a vertex per wavefront.
 __global__ void __launch_bounds__(256)
-    jp_list_kernel(const int32_t* __restrict__ cnt_in, const int32_t* __restrict__ in, int32_t* __restrict__ cnt_out,
-                   int32_t* __restrict__ out, const int32_t* __restrict__ hrp, const int32_t* __restrict__ hci,
-                   int32_t* colour, int32_t* __restrict__ cur, unsigned long long* __restrict__ usedm) {
+    jp_wake_kernel(const int32_t* __restrict__ cnt_in, const int32_t* __restrict__ in, int32_t* __restrict__ cnt_out,
+                   int32_t* __restrict__ out, int32_t next, const int32_t* __restrict__ rp,
+                   const int32_t* __restrict__ ci, const int32_t* __restrict__ hrp, const int32_t* __restrict__ hci,
+                   int32_t* colour, int32_t* __restrict__ cur, unsigned long long* __restrict__ usedm,
+                   int32_t* __restrict__ stamp, int32_t* __restrict__ cnt_hubs, int32_t* __restrict__ hubs) {
+  __shared__ unsigned long long bms[4][JP_BM_WORDS];
   const int32_t m = *cnt_in;
+  const int lane = (int)(threadIdx.x & 63);
+  unsigned long long* bm = bms[threadIdx.x >> 6];
+  // the wavefront pushes the row of u, or lists it as a hub
+  auto wake_row = [&](int32_t u) {
+    const int32_t k0 = rp[u], k1 = rp[u + 1];
+    if (k1 - k0 > JP_PUSH_WAVE_MAX) {
+      if (lane == 0) hubs[atomicAdd(cnt_hubs, 1)] = u;
+      return;
+    }
+    for (int32_t k = k0; k < k1; k += 64)
+      jp_wake_push(k + lane < k1, k + lane < k1 ? ci[k + lane] : 0, colour, stamp, next, cnt_out, out, lane);
+  };
+  const int32_t nwaves = (int32_t)gridDim.x * 4;
+  if (m <= JP_WAVE_MODE_PER_WAVE * nwaves) {
+    // short lists: a wavefront per listed vertex, so that the vertices with
+    // long lists are not queued behind each other in a few wavefronts
+    for (int32_t t = (int32_t)blockIdx.x * 4 + (int32_t)(threadIdx.x >> 6); t < m; t += nwaves) {
+      const int32_t v = in[t];
+      if (__atomic_load_n(&colour[v], __ATOMIC_RELAXED) >= 0) continue;
+      if (!jp_try_wave(v, hrp, hci, colour, cur, usedm, bm, lane)) wake_row(v);
+    }
+    return;
+  }
   const int32_t stride = gridDim.x * blockDim.x;
-  for (int32_t base = blockIdx.x * blockDim.x; base < m; base += stride) {
-    const int32_t t = base + threadIdx.x;
+  for (int32_t base = blockIdx.x * blockDim.x; base < m; base += stride) {  // uniform per workgroup
+    const int32_t t = base + (int32_t)threadIdx.x;
     const int32_t v = t < m ? in[t] : -1;
-    const bool left =
-        v >= 0 && __atomic_load_n(&colour[v], __ATOMIC_RELAXED) < 0 && jp_try_hc(v, hrp, hci, colour, cur, usedm);
-    const unsigned long long bal = __ballot(left);
-    if (!bal) continue;
-    const int lane = threadIdx.x & 63;
-    int32_t at = 0;
-    if (lane == __ffsll((long long)bal) - 1) at = atomicAdd(cnt_out, __popcll(bal));
-    at = __shfl(at, __ffsll((long long)bal) - 1, 64);
-    if (left) out[at + __popcll(bal & ((1ull << lane) - 1ull))] = v;
+    const bool open = v >= 0 && __atomic_load_n(&colour[v], __ATOMIC_RELAXED) < 0;
+    const bool wide = open && hrp[v + 1] - hrp[v] > JP_LANE_MAX;
+    bool now = open && !wide && !jp_try_hc(v, hrp, hci, colour, cur, usedm);
+    // long higher-priority lists: the wavefront tries them one at a time
+    unsigned long long wb = __ballot(wide);
+    while (wb) {
+      const int j = __ffsll((long long)wb) - 1;
+      wb &= wb - 1ull;
+      const bool got = !jp_try_wave(__shfl(v, j, 64), hrp, hci, colour, cur, usedm, bm, lane);
+      if (lane == j) now = got;
+    }
+    unsigned long long bal = __ballot(now);
+    while (bal) {
+      const int j = __ffsll((long long)bal) - 1;
+      bal &= bal - 1ull;
+      wake_row(__shfl(v, j, 64));
+    }
   }
 }
 
-// Priority keys and ids of the m vertices of a list (for sorting them).
-__global__ void list_keys_kernel(int32_t m, const int32_t* __restrict__ list, const uint64_t* __restrict__ prio,
-                                 uint64_t* __restrict__ keys, uint32_t* __restrict__ ids) {
-  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= m) return;
-  const int32_t v = list[t];
-  keys[t] = prio[v];
-  ids[t] = (uint32_t)v;
+// The rows of the vertices with long rows coloured in this round (hubs), each
+// spread over the blocks of one grid row (gridDim.x blocks of 256 entries at
+// a time), the vertices over the grid rows.
+__global__ void __launch_bounds__(256)
+    jp_push_long_kernel(const int32_t* __restrict__ cnt_hubs, const int32_t* __restrict__ hubs,
+                        const int32_t* __restrict__ rp, const int32_t* __restrict__ ci, const int32_t* colour,
+                        int32_t* __restrict__ stamp, int32_t next, int32_t* __restrict__ cnt_out,
+                        int32_t* __restrict__ out) {
+  const int32_t m = *cnt_hubs;
+  const int lane = (int)(threadIdx.x & 63);
+  for (int32_t h = (int32_t)blockIdx.y; h < m; h += (int32_t)gridDim.y) {
+    const int32_t u = hubs[h];
+    const int32_t k0 = rp[u], k1 = rp[u + 1];
+    for (int32_t base = k0 + (int32_t)blockIdx.x * 256; base < k1; base += (int32_t)gridDim.x * 256) {
+      const int32_t k = base + (int32_t)threadIdx.x;
+      jp_wake_push(k < k1, k < k1 ? ci[k] : 0, colour, stamp, next, cnt_out, out, lane);
+    }
+  }
 }
 
 // counts of the next batch: cnt[0] = cnt[last], the others zero
@@ -430,28 +571,12 @@ __global__ void max_i32_kernel(const int32_t* a, int32_t n, int32_t* out) {
   if ((threadIdx.x & 63) == 0) atomicMax(out, m);
 }
 
-// Mean row length above which levels are coloured one vertex at a time; the
-// vertices taken one at a time when the rounds stall.
+// Mean row length above which levels are coloured one vertex at a time.
 constexpr int64_t JP_SEQ_DEG = 48;
-constexpr int32_t SEQ_CHUNK = 8192;
-
-// The top k (by (priority, id)) of the m uncoloured vertices of `list`
-// coloured one at a time in descending order.  Every uncoloured vertex's
-// lower-priority neighbours are uncoloured too (a vertex is coloured only
-// after all its higher-priority neighbours), and the pending higher-priority
-// neighbours of a top-k vertex are in the top k before it; so first-fit over
-// the coloured neighbours is first-fit over the higher-priority ones: the same
-// colouring as the rounds, which then go on with the rest.
-void colour_top_seq(int32_t m, int32_t k, const int32_t* list, const int32_t* rp, const int32_t* ci,
-                    const uint64_t* prio, int32_t maxdeg, int32_t* colour, hipStream_t s) {
-  DVec<uint64_t> keys(m), skeys(m);
-  DVec<uint32_t> ids(m), asc(m);
-  list_keys_kernel<<<grid_for(m, 256), 256, 0, s>>>(m, list, prio, keys.p, ids.p);
-  PCAMG_LAUNCHED();
-  radix_sort_u64_u32(keys.p, ids.p, skeys.p, asc.p, m, s);
-  greedy_seq_large_kernel<<<1, 1024, 0, s>>>(k, (maxdeg + 1 + 31) / 32, rp, ci, asc.p + (m - k), colour);
-  PCAMG_LAUNCHED();
-}
+// Fewest threads a data-driven colouring round is launched with, and the
+// grid of its hub pushes (blocks per row x rows at a time).
+constexpr int32_t WAKE_MIN_THREADS = 1 << 17;
+constexpr unsigned PUSH_GRID_X = 64, PUSH_GRID_Y = 16;
 
 int32_t max_row_len(int32_t n, const int32_t* rp, hipStream_t s) {
   DVec<int32_t> mx(1);
@@ -470,76 +595,75 @@ int32_t colour_jp(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed
   jp_prio_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, rp, seed, lvl, prio.p);
   PCAMG_LAUNCHED();
   const int64_t nnz = n > 0 ? (int64_t)read_scalar(rp + n, s) : 0;
-  // near-dense levels (more than JP_SEQ_DEG entries per row) of up to
-  // SEQ_LARGE_MAX vertices: the priority chains are about as long as the
-  // level and a round's first-fit scans long rows once per window of 64
-  // colours, so colour one vertex at a time in one workgroup.  Other levels
-  // (every grid level): rounds over worklists, with the stalls taken one
-  // vertex at a time (below).
+  // small near-dense levels (more than JP_SEQ_DEG entries per row, at most
+  // SEQ_MAX vertices): the priority chains are about as long as the level,
+  // so colour one vertex at a time in one workgroup, from LDS.  Other levels:
+  // data-driven rounds (below), or the one-workgroup rounds when small.
   const bool dense_rows = nnz > JP_SEQ_DEG * (int64_t)n;
-  const int32_t maxdeg = dense_rows && n > SEQ_MAX && n <= SEQ_LARGE_MAX ? max_row_len(n, rp, s) : 0;
   if (dense_rows && n <= SEQ_MAX) {
     greedy_seq_kernel<<<1, 1024, 0, s>>>(n, rp, ci, prio.p, colour);
     PCAMG_LAUNCHED();
-  } else if (dense_rows && n <= SEQ_LARGE_MAX && maxdeg + 1 <= SEQ_BITS_MAX) {
-    DVec<int32_t> all(n);
-    iota_i32(all.p, n, s);
-    colour_top_seq(n, n, all.p, rp, ci, prio.p, maxdeg, colour, s);
   } else if (n <= JP_SMALL_MAX) {
     DVec<int32_t> rounds(1);
     jp_small_kernel<<<1, JP_SMALL_THREADS, 0, s>>>(n, rp, ci, prio.p, colour, rounds.p);
     PCAMG_LAUNCHED();
   } else {
-    // batches of R rounds over shrinking worklists; the host checks the count
-    // after each batch (every round removes at least the highest-priority
-    // uncoloured vertex, so at most n rounds)
-    constexpr int R = 8;
-    DVec<int32_t> hcnt(n), hrp(n + 1);
+    // data-driven rounds (jp_wake_kernel) in batches of R; the host reads
+    // the worklist size after each batch.  The highest-priority uncoloured
+    // vertex is always on the current list (its last higher neighbour to be
+    // coloured woke it for the next round), so every round colours a vertex
+    // until the list is empty, and at most n rounds are run.
+    constexpr int R = 16;
+    DVec<int32_t> hcnt(n), hrp(n + 1), lrows;
+    const int32_t nl = rows_longer_than(n, rp, nullptr, ROW_LONG, lrows, s);
     higher_count_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, rp, ci, prio.p, hcnt.p);
     PCAMG_LAUNCHED();
+    if (nl > 0) {
+      higher_count_long_kernel<<<nl, 256, 0, s>>>(lrows.p, rp, ci, prio.p, hcnt.p);
+      PCAMG_LAUNCHED();
+    }
     scan_exclusive_i32(hcnt.p, hrp.p, n, hrp.p + n, s);
     const int32_t htot = read_scalar(hrp.p + n, s);  // nnz / 2 on a symmetric pattern
     DVec<int32_t> hci(std::max<int32_t>(htot, 1));
     higher_fill_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, rp, ci, prio.p, hrp.p, hci.p);
     PCAMG_LAUNCHED();
-    DVec<int32_t> list0(n), list1(n), cnt(R + 1), cur(n);
+    if (nl > 0) {
+      higher_fill_long_kernel<<<nl, 256, 0, s>>>(lrows.p, rp, ci, prio.p, hrp.p, hci.p);
+      PCAMG_LAUNCHED();
+    }
+    DVec<int32_t> list0(n), list1(n), cnt(R + 1), cur(n), stamp(n), hubs(n), cnt_hubs(R);
     DVec<uint64_t> usedm(n);
     copy_d2d(cur.p, hrp.p, n, s);
     fill_u64(usedm.p, 0ull, n, s);
+    fill_i32(stamp.p, 0, n, s);
+    fill_i32(cnt_hubs.p, 0, R, s);
     iota_i32(list0.p, n, s);
     fill_i32(cnt.p, 0, R + 1, s);
     fill_i32(cnt.p, n, 1, s);
-    int32_t pending = n;  // upper bound of the worklist: the grid of the next batch
-    int32_t maxdeg_all = -1;
+    int32_t pending = n;  // worklist size at the start of the next batch
     int64_t rounds = 0;
     for (;;) {
-      const unsigned grid = std::min<unsigned>(grid_for(pending, 256), 2048);
+      // lists grow and shrink within a batch: at least WAKE_MIN_THREADS
+      // threads, a grid-stride loop beyond the grid
+      const unsigned grid = std::min<unsigned>(grid_for(std::max<int32_t>(pending, WAKE_MIN_THREADS), 256), 2048);
       for (int r = 0; r < R; ++r) {
         const int32_t* in = (r & 1) ? list1.p : list0.p;
         int32_t* out = (r & 1) ? list0.p : list1.p;
-        jp_list_kernel<<<grid, 256, 0, s>>>(cnt.p + r, in, cnt.p + r + 1, out, hrp.p, hci.p, colour, cur.p,
-                                            (unsigned long long*)usedm.p);
+        const int32_t next = (int32_t)(rounds + r + 1);
+        jp_wake_kernel<<<grid, 256, 0, s>>>(cnt.p + r, in, cnt.p + r + 1, out, next, rp, ci, hrp.p, hci.p, colour,
+                                            cur.p, (unsigned long long*)usedm.p, stamp.p, cnt_hubs.p + r, hubs.p);
+        PCAMG_LAUNCHED();
+        jp_push_long_kernel<<<dim3(PUSH_GRID_X, PUSH_GRID_Y), 256, 0, s>>>(cnt_hubs.p + r, hubs.p, rp, ci, colour,
+                                                                            stamp.p, next, cnt.p + r + 1, out);
         PCAMG_LAUNCHED();
       }
       rounds += R;
-      const int32_t before = pending;
-      pending = read_scalar(cnt.p + R, s);
+      pending = read_scalar(cnt.p + R, s);  // R is even: that list is in list0 again
       if (pending == 0) break;
       require(rounds <= (int64_t)n + R, PCAMG_EHIP, "colouring made no progress");
-      // R is even: the survivors are in list0 again.  A batch that colours
-      // few vertices is held up by a long priority chain (the dense core of a
-      // power-law level): the top SEQ_CHUNK pending vertices go one at a time
-      // (the rounds then drop them), the rest back to the rounds.
-      if (before - pending < 4 * R) {
-        if (maxdeg_all < 0) maxdeg_all = max_row_len(n, rp, s);
-        if (maxdeg_all + 1 <= SEQ_BITS_MAX) {
-          const int32_t k = pending <= 2 * SEQ_CHUNK ? pending : SEQ_CHUNK;
-          colour_top_seq(pending, k, list0.p, rp, ci, prio.p, maxdeg_all, colour, s);
-          if (k == pending) break;
-        }
-      }
       jp_carry_kernel<<<1, 64, 0, s>>>(cnt.p, R);
       PCAMG_LAUNCHED();
+      fill_i32(cnt_hubs.p, 0, R, s);
     }
   }
   DVec<int32_t> mx(1);
@@ -565,6 +689,31 @@ int32_t colour_jp(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed
 // seen while depth d is expanded, so the graph is bipartite exactly when no
 // round sees one.
 // ---------------------------------------------------------------------------
+// Neighbour u of a vertex of depth d: an odd cycle if u has depth d too, a
+// claim for depth d + 1 if unvisited (depths below d + 1 were set by earlier
+// rounds); the claimed vertices go to the next frontier, one atomic per
+// wavefront step.
+__device__ __forceinline__ void bfs_visit(bool act, int32_t u, int32_t* depth, int32_t d, bool& odd,
+                                          int32_t* __restrict__ cnt_out, int32_t* __restrict__ out, int lane) {
+  bool claim = false;
+  if (act) {
+    const int32_t du = depth[u];
+    if (du == d) odd = true;
+    else if (du < 0) claim = atomicCAS(&depth[u], -1, d + 1) == -1;
+  }
+  const unsigned long long bal = __ballot(claim);
+  if (!bal) return;
+  const int first = __ffsll((long long)bal) - 1;
+  int32_t at = 0;
+  if (lane == first) at = atomicAdd(cnt_out, __popcll(bal));
+  at = __shfl(at, first, 64);
+  if (claim) out[at + __popcll(bal & ((1ull << lane) - 1ull))] = u;
+}
+
+// One round: each lane expands its frontier vertex's row when it has at most
+// 64 entries; longer rows are then expanded by the whole wavefront, one at a
+// time, 64 entries per step (a hub would otherwise hold its wavefront for its
+// whole row, one entry per step).
 __global__ void __launch_bounds__(256)
     bfs_round_kernel(const int32_t* __restrict__ cnt_in, const int32_t* __restrict__ in, int32_t* __restrict__ cnt_out,
                      int32_t* __restrict__ out, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
@@ -579,23 +728,21 @@ __global__ void __launch_bounds__(256)
     const int32_t v = act ? in[t] : 0;
     const int32_t k0 = act ? rp[v] : 0;
     const int32_t len = act ? rp[v + 1] - k0 : 0;
-    const int32_t span = wave_max_len(len);
+    const bool longrow = len > 64;
+    const int32_t span = wave_max_len(longrow ? 0 : len);
     for (int32_t j = 0; j < span; ++j) {
-      bool claim = false;
-      int32_t u = 0;
-      if (j < len) {
-        u = ci[k0 + j];
-        const int32_t du = depth[u];  // depths below d + 1 were set by earlier rounds
-        if (du == d) odd = true;
-        else if (du < 0) claim = atomicCAS(&depth[u], -1, d + 1) == -1;
+      const bool on = !longrow && j < len;
+      bfs_visit(on, on ? ci[k0 + j] : 0, depth, d, odd, cnt_out, out, lane);
+    }
+    unsigned long long lb = __ballot(longrow);
+    while (lb) {
+      const int src = __ffsll((long long)lb) - 1;
+      lb &= lb - 1ull;
+      const int32_t a = __shfl(k0, src, 64), e = a + __shfl(len, src, 64);
+      for (int32_t k = a; k < e; k += 64) {
+        const bool on = k + lane < e;
+        bfs_visit(on, on ? ci[k + lane] : 0, depth, d, odd, cnt_out, out, lane);
       }
-      const unsigned long long bal = __ballot(claim);
-      if (!bal) continue;
-      const int first = __ffsll((long long)bal) - 1;
-      int32_t at = 0;
-      if (lane == first) at = atomicAdd(cnt_out, __popcll(bal));
-      at = __shfl(at, first, 64);
-      if (claim) out[at + __popcll(bal & ((1ull << lane) - 1ull))] = u;
     }
   }
   if (odd) *odd_flag = 1;
@@ -831,6 +978,54 @@ __global__ void __launch_bounds__(LONG_T)
   const int32_t i = row0 + (int32_t)blockIdx.x;
   const T s = long_row_sum<T>(rp[i], rp[i + 1], ci, av, x);
   if (threadIdx.x == 0) x[i] = (b[i] - s) * dinv[i];
+}
+
+// One colour's rows in one launch: the first rl - row0 (XCD-ordered) blocks
+// take the long rows [row0, rl), a block each, as gs_long_kernel; the other
+// blocks the rows [rl, row1) with G lanes each, as gs_kernel -- the same
+// arithmetic as the two launches, so the same values.
+template <typename T, int G>
+__global__ void __launch_bounds__(256)
+    gs_fused_kernel(int32_t row0, int32_t rl, int32_t row1, const int32_t* __restrict__ rp,
+                    const int32_t* __restrict__ ci, const T* __restrict__ av, const T* __restrict__ dinv,
+                    const T* __restrict__ b, T* x) {
+  static_assert(LONG_T == 256, "a long row takes one block of 256 threads");
+  const int32_t vb = (int32_t)xcd_block(), nlong = rl - row0;
+  if (vb < nlong) {  // uniform per block
+    const int32_t i = row0 + vb;
+    const T s = long_row_sum<T>(rp[i], rp[i + 1], ci, av, x);
+    if (threadIdx.x == 0) x[i] = (b[i] - s) * dinv[i];
+    return;
+  }
+  const int32_t i = rl + (int32_t)(((vb - nlong) * 256 + (int32_t)threadIdx.x) / G);
+  const bool ok = i < row1;
+  const int32_t k0 = ok ? rp[i] : 0;
+  const int32_t len = ok ? rp[i + 1] - k0 : 0;
+  const T s = row_chain_g<T, G>(k0, len, ci, av, x, (T)0);
+  if (ok && (threadIdx.x & (G - 1)) == 0) x[i] = (b[i] - s) * dinv[i];
+}
+
+template <typename T>
+void gs_colour_fused(int32_t row0, int32_t rl, int32_t row1, const int32_t* rp, const int32_t* ci, const T* av,
+                     const T* dinv, const T* b, T* x, hipStream_t s, int lanes) {
+  if (row1 <= row0) return;
+  if (rl >= row1) {
+    gs_colour_long<T>(row0, row1, rp, ci, av, dinv, b, x, s);
+    return;
+  }
+  if (rl <= row0 || lanes < 4) {
+    gs_colour_long<T>(row0, rl, rp, ci, av, dinv, b, x, s);
+    gs_colour<T>(rl, row1, rp, ci, av, dinv, b, x, s, lanes);
+    return;
+  }
+  const unsigned grid = (unsigned)(rl - row0) + grid_for((size_t)(row1 - rl) * lanes, 256);
+  switch (lanes) {
+    case 4: gs_fused_kernel<T, 4><<<grid, 256, 0, s>>>(row0, rl, row1, rp, ci, av, dinv, b, x); break;
+    case 16: gs_fused_kernel<T, 16><<<grid, 256, 0, s>>>(row0, rl, row1, rp, ci, av, dinv, b, x); break;
+    case 64: gs_fused_kernel<T, 64><<<grid, 256, 0, s>>>(row0, rl, row1, rp, ci, av, dinv, b, x); break;
+    default: throw Error(PCAMG_EINVAL, "lanes per row must be 1, 4, 16 or 64");
+  }
+  PCAMG_LAUNCHED();
 }
 
 template <typename T>
@@ -1196,6 +1391,8 @@ void prolong_add(int32_t n, const int32_t* agg, const T* pval, const T* xc, T* x
                             T*, hipStream_t, int, int32_t);                                                     \
   template void gs_colour_long<T>(int32_t, int32_t, const int32_t*, const int32_t*, const T*, const T*,        \
                                   const T*, T*, hipStream_t);                                                   \
+  template void gs_colour_fused<T>(int32_t, int32_t, int32_t, const int32_t*, const int32_t*, const T*,        \
+                                   const T*, const T*, T*, hipStream_t, int);                                   \
   template void gs_sweep_block<T>(int32_t, int32_t, int32_t, const int32_t*, const int32_t*, const int32_t*,   \
                                   const int32_t*, const T*, const T*, const T*, T*, hipStream_t);               \
   template void residual_long<T>(int32_t, const int32_t*, const int32_t*, const int32_t*, const T*, const T*,  \

@@ -44,28 +44,46 @@ pcamg_status guarded_s(hipStream_t s, F&& f) {
 // Graph validation (the paper's preprocessing, Sec. 4.3): no self loops,
 // strictly ascending columns, positive finite symmetric weights, connected.
 // ---------------------------------------------------------------------------
+// Checks of entry k of row i.
+__device__ __forceinline__ void validate_entry(int32_t n, int32_t i, int32_t k, const int32_t* __restrict__ rp,
+                                               const int32_t* __restrict__ ci, const double* __restrict__ w,
+                                               int32_t* __restrict__ flags) {
+  const int32_t j = ci[k];
+  if (j < 0 || j >= n) {
+    atomicOr(&flags[0], 1);
+    return;
+  }
+  if (j == i) atomicOr(&flags[0], 2);
+  if (k > rp[i] && ci[k - 1] >= j) atomicOr(&flags[0], 4);
+  const double x = w[k];
+  if (!(x > 0.0) || !isfinite(x)) atomicOr(&flags[0], 8);
+  // symmetric partner
+  int32_t lo = rp[j], hi = rp[j + 1];
+  bool found = false;
+  while (lo < hi) {
+    int32_t mid = (lo + hi) >> 1;
+    if (ci[mid] == i) { found = true; lo = mid; break; }
+    if (ci[mid] < i) lo = mid + 1;
+    else hi = mid;
+  }
+  if (!found || __double_as_longlong(w[lo]) != __double_as_longlong(x)) atomicOr(&flags[0], 16);
+}
+
+// Rows of more than VALIDATE_LONG entries (hubs) are checked by a workgroup each.
+constexpr int32_t VALIDATE_LONG = 256;
+
 __global__ void validate_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                 const double* __restrict__ w, int32_t* __restrict__ flags) {
   int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
-    const int32_t j = ci[k];
-    if (j < 0 || j >= n) { atomicOr(&flags[0], 1); continue; }
-    if (j == i) atomicOr(&flags[0], 2);
-    if (k > rp[i] && ci[k - 1] >= j) atomicOr(&flags[0], 4);
-    const double x = w[k];
-    if (!(x > 0.0) || !isfinite(x)) atomicOr(&flags[0], 8);
-    // symmetric partner
-    int32_t lo = rp[j], hi = rp[j + 1];
-    bool found = false;
-    while (lo < hi) {
-      int32_t mid = (lo + hi) >> 1;
-      if (ci[mid] == i) { found = true; lo = mid; break; }
-      if (ci[mid] < i) lo = mid + 1;
-      else hi = mid;
-    }
-    if (!found || __double_as_longlong(w[lo]) != __double_as_longlong(x)) atomicOr(&flags[0], 16);
-  }
+  if (i >= n || rp[i + 1] - rp[i] > VALIDATE_LONG) return;
+  for (int32_t k = rp[i]; k < rp[i + 1]; ++k) validate_entry(n, i, k, rp, ci, w, flags);
+}
+
+__global__ void __launch_bounds__(256)
+    validate_long_kernel(int32_t n, const int32_t* __restrict__ rows, const int32_t* __restrict__ rp,
+                         const int32_t* __restrict__ ci, const double* __restrict__ w, int32_t* __restrict__ flags) {
+  const int32_t i = rows[blockIdx.x];
+  for (int32_t k = rp[i] + (int32_t)threadIdx.x; k < rp[i + 1]; k += 256) validate_entry(n, i, k, rp, ci, w, flags);
 }
 
 __global__ void rp_check_kernel(int32_t n, int32_t nnz, const int32_t* __restrict__ rp, int32_t* __restrict__ flags) {
@@ -76,19 +94,29 @@ __global__ void rp_check_kernel(int32_t n, int32_t nnz, const int32_t* __restric
   if (i < n && rp[i + 1] < rp[i]) atomicOr(&flags[0], 32);
 }
 
+__device__ __forceinline__ void cc_hook_entry(int32_t v, int32_t u, int32_t* __restrict__ label,
+                                              int32_t* __restrict__ changed) {
+  int32_t a = __atomic_load_n(&label[v], __ATOMIC_RELAXED);
+  int32_t b = __atomic_load_n(&label[u], __ATOMIC_RELAXED);
+  if (a != b) {
+    atomicMin(&label[max(a, b)], min(a, b));
+    atomicMin(&label[v], min(a, b));
+    *changed = 1;
+  }
+}
+
 __global__ void cc_hook_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                int32_t* __restrict__ label, int32_t* __restrict__ changed) {
   int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  for (int32_t k = rp[v]; k < rp[v + 1]; ++k) {
-    int32_t a = __atomic_load_n(&label[v], __ATOMIC_RELAXED);
-    int32_t b = __atomic_load_n(&label[ci[k]], __ATOMIC_RELAXED);
-    if (a != b) {
-      atomicMin(&label[max(a, b)], min(a, b));
-      atomicMin(&label[v], min(a, b));
-      *changed = 1;
-    }
-  }
+  if (v >= n || rp[v + 1] - rp[v] > VALIDATE_LONG) return;
+  for (int32_t k = rp[v]; k < rp[v + 1]; ++k) cc_hook_entry(v, ci[k], label, changed);
+}
+
+__global__ void __launch_bounds__(256)
+    cc_hook_long_kernel(const int32_t* __restrict__ rows, const int32_t* __restrict__ rp,
+                        const int32_t* __restrict__ ci, int32_t* __restrict__ label, int32_t* __restrict__ changed) {
+  const int32_t v = rows[blockIdx.x];
+  for (int32_t k = rp[v] + (int32_t)threadIdx.x; k < rp[v + 1]; k += 256) cc_hook_entry(v, ci[k], label, changed);
 }
 
 __global__ void cc_compress_kernel(int32_t n, int32_t* __restrict__ label) {
@@ -120,6 +148,12 @@ void validate_graph(const pcamg_graph* g, hipStream_t s) {
   require(!(f & 32), PCAMG_EINVAL, "graph: row pointers not monotone or not ending at nnz");
   validate_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, g->row_ptr, g->col_idx, g->weight, flags.p);
   PCAMG_LAUNCHED();
+  DVec<int32_t> lrows;
+  const int32_t nl = rows_longer_than(n, g->row_ptr, nullptr, VALIDATE_LONG, lrows, s);
+  if (nl > 0) {
+    validate_long_kernel<<<nl, 256, 0, s>>>(n, lrows.p, g->row_ptr, g->col_idx, g->weight, flags.p);
+    PCAMG_LAUNCHED();
+  }
   f = read_scalar(flags.p, s);
   require(!(f & 1), PCAMG_EINVAL, "graph: column index out of range");
   require(!(f & 2), PCAMG_ESELFLOOP, "graph: self loop");
@@ -131,6 +165,10 @@ void validate_graph(const pcamg_graph* g, hipStream_t s) {
     fill_i32(changed.p, 0, 1, s);
     cc_hook_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, g->row_ptr, g->col_idx, label.p, changed.p);
     PCAMG_LAUNCHED();
+    if (nl > 0) {
+      cc_hook_long_kernel<<<nl, 256, 0, s>>>(lrows.p, g->row_ptr, g->col_idx, label.p, changed.p);
+      PCAMG_LAUNCHED();
+    }
     cc_compress_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, label.p);
     PCAMG_LAUNCHED();
     if (!read_scalar(changed.p, s)) break;

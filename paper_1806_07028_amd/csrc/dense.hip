@@ -15,11 +15,12 @@
 //              identity: forward colour passes from X = 0, R = I - A X,
 //              B_c = P^T R, X += P (C_{l+1} B_c), backward colour passes.
 //
-// The colour passes, residuals and transfers are the cycle's own row
-// formulas (fma chains in CSR / member order) evaluated for all columns; the
-// two products with dense matrices are GEMMs on the matrix cores (this file's
-// MFMA kernel).  The result is the same linear map as the recursion with a
-// different rounding order.
+// The residuals and transfers are the cycle's own row formulas (fma chains
+// in CSR / member order) evaluated for all columns; the colour passes sum a
+// row in sixteen strided parts added by a fixed tree; the two products with
+// dense matrices are GEMMs on the matrix cores (this file's MFMA kernel).
+// The result is the same linear map as the recursion with a different
+// rounding order.
 #include "rowchain.hpp"
 #include "solver.hpp"
 
@@ -191,15 +192,39 @@ __device__ __forceinline__ T row_block_chain(int32_t k0, int32_t k1, const int32
 
 // One Gauss-Seidel colour pass on all columns, right-hand side the identity:
 // X[i, j] = (delta_ij - sum_e a_ie X[c_e, j]) * dinv_i for rows r0 + blockIdx.y.
+// A workgroup takes 16 columns; its 16 thread rows sum strided sixteenths of
+// the row (the near-dense levels' rows have hundreds to thousands of entries),
+// added by a fixed tree in LDS.
 template <typename T>
 __global__ void __launch_bounds__(256)
     blk_gs_kernel(int32_t r0, int32_t nc, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                   const T* __restrict__ av, const T* __restrict__ dinv, T* __restrict__ X) {
+  __shared__ T part[16][17];
   const int32_t i = r0 + (int32_t)blockIdx.y;
-  const int32_t j = (int32_t)(blockIdx.x * 256 + threadIdx.x);
-  if (j >= nc) return;
-  const T s = row_block_chain<T>(rp[i], rp[i + 1], ci, av, X, (size_t)nc, j, (T)0);
-  X[(size_t)i * nc + j] = ((i == j ? (T)1 : (T)0) - s) * dinv[i];
+  const int tx = (int)(threadIdx.x & 15), ty = (int)(threadIdx.x >> 4);
+  const int32_t j = (int32_t)blockIdx.x * 16 + tx;
+  T s = (T)0;
+  if (j < nc) {
+    constexpr int U = 4;
+    const int32_t k1 = rp[i + 1];
+    int32_t k = rp[i] + ty;
+    for (; k + 16 * (U - 1) < k1; k += 16 * U) {
+      T v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = X[(size_t)ci[k + 16 * u] * nc + j];
+#pragma unroll
+      for (int u = 0; u < U; ++u) s = fma(av[k + 16 * u], v[u], s);
+    }
+    for (; k < k1; k += 16) s = fma(av[k], X[(size_t)ci[k] * nc + j], s);
+  }
+  part[ty][tx] = s;
+  __syncthreads();
+#pragma unroll
+  for (int h = 8; h > 0; h >>= 1) {
+    if (ty < h) part[ty][tx] += part[ty + h][tx];
+    __syncthreads();
+  }
+  if (ty == 0 && j < nc) X[(size_t)i * nc + j] = ((i == j ? (T)1 : (T)0) - part[0][tx]) * dinv[i];
 }
 
 // Y = A X (identity = 0) or R = I - A X (identity = 1) on all columns, the
@@ -338,7 +363,8 @@ void dense_bottom_up(Hierarchy& H, int d, int gamma, T* C, hipStream_t s) {
     for (int k = 0; k < A.ncol; ++k) {
       const int32_t r0 = A.coff[k], r1 = A.coff[k + 1];
       if (r1 <= r0) continue;
-      blk_gs_kernel<T><<<rows_grid(n, r1 - r0), 256, 0, s>>>(r0, n, A.rp.p, A.ci.p, av, dinv, X.p);
+      blk_gs_kernel<T><<<dim3((unsigned)((n + 15) / 16), (unsigned)(r1 - r0)), 256, 0, s>>>(r0, n, A.rp.p, A.ci.p,
+                                                                                           av, dinv, X.p);
       PCAMG_LAUNCHED();
     }
     blk_apply_kernel<T><<<rows_grid(n, n), 256, 0, s>>>(n, A.rp.p, A.ci.p, av, LevelOf<T>::d(A), X.p, R.p, 1);
@@ -351,7 +377,8 @@ void dense_bottom_up(Hierarchy& H, int d, int gamma, T* C, hipStream_t s) {
     for (int k = A.ncol - 1; k >= 0; --k) {
       const int32_t r0 = A.coff[k], r1 = A.coff[k + 1];
       if (r1 <= r0) continue;
-      blk_gs_kernel<T><<<rows_grid(n, r1 - r0), 256, 0, s>>>(r0, n, A.rp.p, A.ci.p, av, dinv, X.p);
+      blk_gs_kernel<T><<<dim3((unsigned)((n + 15) / 16), (unsigned)(r1 - r0)), 256, 0, s>>>(r0, n, A.rp.p, A.ci.p,
+                                                                                           av, dinv, X.p);
       PCAMG_LAUNCHED();
     }
     W = std::move(X);

@@ -148,6 +148,12 @@ void radix_sort_u32_u32(const uint32_t* keys_in, const uint32_t* vals_in, uint32
 
 // Stable compaction: out[k] = in[i] for flags[i] != 0 in order; *count (device).
 void compact_i32(const int32_t* in, const uint8_t* flags, int32_t* out, int32_t* count, size_t n, hipStream_t s);
+// The positions i < n (in order) whose row perm[i] (i itself when perm is
+// null) has more than len entries: written to rows (resized to n), count
+// returned (synchronises).  Kernels that walk a row per thread leave those
+// rows to a workgroup each.
+int32_t rows_longer_than(int32_t n, const int32_t* rp, const int32_t* perm, int32_t len, DVec<int32_t>& rows,
+                         hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // vec.hip: vector kernels for the outer iterations
@@ -197,6 +203,11 @@ void residual(int32_t n, const int32_t* rp, const int32_t* ci, const T* av, cons
 template <typename T>
 void gs_colour_long(int32_t row0, int32_t row1, const int32_t* rp, const int32_t* ci, const T* av, const T* dinv,
                     const T* b, T* x, hipStream_t s);
+// One launch for both parts of a colour: long rows [row0, rl) as
+// gs_colour_long, rows [rl, row1) as gs_colour with `lanes` lanes per row.
+template <typename T>
+void gs_colour_fused(int32_t row0, int32_t rl, int32_t row1, const int32_t* rp, const int32_t* ci, const T* av,
+                     const T* dinv, const T* b, T* x, hipStream_t s, int lanes);
 template <typename T>
 void residual_long(int32_t nrows, const int32_t* rows, const int32_t* rp, const int32_t* ci, const T* av,
                    const T* d, const T* b, const T* x, T* r, hipStream_t s);

@@ -114,6 +114,10 @@ __global__ void perm_deg_kernel(int32_t n, const int32_t* __restrict__ perm, con
   if (p < n) deg[p] = rp[perm[p] + 1] - rp[perm[p]];
 }
 
+// Row p of the permuted matrix is row perm[p] with its columns renumbered;
+// rows of more than PERM_LONG entries are copied by perm_rows_long_kernel.
+constexpr int32_t PERM_LONG = 256;
+
 __global__ void perm_rows_kernel(int32_t n, const int32_t* __restrict__ perm, const int32_t* __restrict__ iperm,
                                  const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                  const double* __restrict__ av, const int32_t* __restrict__ rpp,
@@ -121,11 +125,29 @@ __global__ void perm_rows_kernel(int32_t n, const int32_t* __restrict__ perm, co
   int32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   const int32_t i = perm[p];
+  if (rp[i + 1] - rp[i] > PERM_LONG) return;
   int32_t o = rpp[p];
   for (int32_t k = rp[i]; k < rp[i + 1]; ++k, ++o) {
     cip[o] = iperm[ci[k]];
     avp[o] = av[k];
     avp32[o] = (float)av[k];
+  }
+}
+
+__global__ void __launch_bounds__(256)
+    perm_rows_long_kernel(const int32_t* __restrict__ pos, const int32_t* __restrict__ perm,
+                          const int32_t* __restrict__ iperm, const int32_t* __restrict__ rp,
+                          const int32_t* __restrict__ ci, const double* __restrict__ av,
+                          const int32_t* __restrict__ rpp, int32_t* __restrict__ cip, double* __restrict__ avp,
+                          float* __restrict__ avp32) {
+  const int32_t p = pos[blockIdx.x];
+  const int32_t i = perm[p];
+  const int32_t k0 = rp[i], len = rp[i + 1] - k0, o = rpp[p];
+  for (int32_t j = (int32_t)threadIdx.x; j < len; j += 256) {
+    cip[o + j] = iperm[ci[k0 + j]];
+    const double a = av[k0 + j];
+    avp[o + j] = a;
+    avp32[o + j] = (float)a;
   }
 }
 
@@ -151,6 +173,12 @@ void permute_csr(int32_t n, const int32_t* perm, const int32_t* iperm, const int
   scan_exclusive_i32(deg.p, rpp, n, rpp + n, s);
   perm_rows_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, perm, iperm, rp, ci, av, rpp, cip, avp, avp32);
   PCAMG_LAUNCHED();
+  DVec<int32_t> lpos;
+  const int32_t nl = rows_longer_than(n, rp, perm, PERM_LONG, lpos, s);
+  if (nl > 0) {
+    perm_rows_long_kernel<<<nl, 256, 0, s>>>(lpos.p, perm, iperm, rp, ci, av, rpp, cip, avp, avp32);
+    PCAMG_LAUNCHED();
+  }
   perm_diag_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, perm, d, dinv, dp, dinvp, dp32, dinvp32);
   PCAMG_LAUNCHED();
 }

@@ -197,8 +197,10 @@ void smooth_colour(const LevelMatrix& A, int k, const double* b, double* x, hipS
   } else if (A.long_min > 0) {  // long rows first: a workgroup each, or one wavefront's chain
     if (chain)
       gs_colour<double>(A.coff[k], A.lend[k], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s, 64);
-    else
-      gs_colour_long<double>(A.coff[k], A.lend[k], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s);
+    else {  // both parts in one launch
+      gs_colour_fused<double>(A.coff[k], A.lend[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s, A.lanes);
+      return;
+    }
     gs_colour<double>(A.lend[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s, A.lanes);
   } else {
     gs_colour<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s, A.lanes);
@@ -213,8 +215,10 @@ void smooth_colour(const LevelMatrix& A, int k, const float* b, float* x, hipStr
   } else if (A.long_min > 0) {  // long rows first: a workgroup each, or one wavefront's chain
     if (chain)
       gs_colour<float>(A.coff[k], A.lend[k], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s, 64);
-    else
-      gs_colour_long<float>(A.coff[k], A.lend[k], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s);
+    else {  // both parts in one launch
+      gs_colour_fused<float>(A.coff[k], A.lend[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s, A.lanes);
+      return;
+    }
     gs_colour<float>(A.lend[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s, A.lanes);
   } else {
     gs_colour<float>(A.coff[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s, A.lanes);
@@ -1376,12 +1380,16 @@ void bench_level(pcamg_ctx* c, int kind, int prec, int reps, int64_t flush_bytes
       for (int k = 0; k < A.ncol; ++k) {
         if (prec == PCAMG_PREC_F32) smooth_colour(A, k, b32.p, x32.p, s);
         else smooth_colour(A, k, b.p, x.p, s);
-        nl += A.sell() || A.long_min == 0 ? 1 : 2;
+        // launches made: one per non-empty row range (long rows, then the rest)
+        if (A.sell() || A.long_min == 0 || (prec == PCAMG_PREC_F32 && A.ell_w > 0))
+          nl += A.coff[k + 1] > A.coff[k];
+        else
+          nl += (A.lend[k] > A.coff[k]) + (A.coff[k + 1] > A.lend[k]);
       }
     } else {
       if (prec == PCAMG_PREC_F32) level_residual(A, b32.p, x32.p, r32.p, s);
       else level_residual(A, b.p, x.p, r.p, s);
-      nl += A.sell() || A.long_min == 0 ? 1 : 2;
+      nl += A.sell() ? 1 : (A.n > 0) + (A.nlong > 0);
     }
   };
   double total = 0.0;

@@ -343,6 +343,26 @@ void compact_i32(const int32_t* in, const uint8_t* flags, int32_t* out, int32_t*
   PCAMG_LAUNCHED();
 }
 
+__global__ void row_longer_flag_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ perm,
+                                       int32_t len, uint8_t* __restrict__ f) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t r = perm ? perm[i] : i;
+  f[i] = rp[r + 1] - rp[r] > len;
+}
+
+int32_t rows_longer_than(int32_t n, const int32_t* rp, const int32_t* perm, int32_t len, DVec<int32_t>& rows,
+                         hipStream_t s) {
+  if (n <= 0) return 0;
+  DVec<uint8_t> f(n);
+  DVec<int32_t> cnt(1);
+  row_longer_flag_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, rp, perm, len, f.p);
+  PCAMG_LAUNCHED();
+  rows.resize(n);
+  compact_i32(nullptr, f.p, rows.p, cnt.p, n, s);
+  return read_scalar(cnt.p, s);
+}
+
 // ---------------------------------------------------------------------------
 // Stable LSD radix sort, 8-bit digits.
 //  pass k: (1) per-tile digit histograms, stored digit-major so one exclusive

@@ -719,13 +719,13 @@ def test_batch_several_workers_refused(gpu):
 
 
 def test_colour_dense_levels(gpu, oracle):
-    """Near-dense graphs (more than 48 entries per row, up to 65536
-    vertices) take the one-vertex-at-a-time greedy kernels (order sorted in
-    LDS up to 8192 vertices, by a device sort above), the others the
-    Jones-Plassmann rounds, whose stalls go one vertex at a time (all of the
-    rest, or the top 8192 by priority when more are pending, as on the
-    power-law graph, whose first batch of rounds colours 19 of its 99,090
-    vertices): all equal the oracle's first-fit in priority order."""
+    """Near-dense graphs (more than 48 entries per row) of up to 8192
+    vertices take the one-vertex-at-a-time greedy kernel (order sorted in
+    LDS), the others the data-driven Jones-Plassmann rounds (long priority
+    chains: the power-law graph's first rounds colour a few dozen of its
+    99,090 vertices each; hub rows of more than 256 entries get their
+    higher-priority lists from a workgroup each): all equal the oracle's
+    first-fit in priority order."""
     S = gpu.stages
     cases = []
     n = 300  # complete graph
@@ -809,13 +809,13 @@ def _cliques_plus_random(n, ncliques, size, deg, seed):
     return I.csr_from_edges(n, a2, b2, np.ones(len(a2)))
 
 
-@pytest.mark.parametrize("n,ncl,size,deg", [(20000, 1, 100, 2),    # rounds over worklists
+@pytest.mark.parametrize("n,ncl,size,deg", [(20000, 1, 100, 2),    # data-driven rounds
                                             (3000, 1, 80, 2),      # rounds in one workgroup
                                             (4000, 10, 80, 50),    # near-dense: one vertex at a time, LDS
-                                            (12000, 20, 80, 50),   # near-dense: one at a time, sorted order
-                                            (12000, 20, 80, 34),   # denser: rounds over worklists
-                                            (140000, 20, 80, 34),  # denser and large: rounds over worklists
-                                            (6000, 1, 480, 2)])    # rounds, then one at a time for the rest
+                                            (12000, 20, 80, 50),   # near-dense and larger: data-driven rounds
+                                            (12000, 20, 80, 34),   # denser: data-driven rounds
+                                            (140000, 20, 80, 34),  # denser and large: data-driven rounds
+                                            (6000, 1, 480, 2)])    # a clique of 480: long rows, long chains
 def test_colour_many_colours(gpu, oracle, n, ncl, size, deg):
     """More than 64 colours (every vertex of a clique of 80-100 takes its own):
     the first-fit search beyond the first 64 colours, on every colouring path,
