@@ -123,7 +123,7 @@ typedef struct {
                               by the level above as one precomputed dense operator (equal up to
                               rounding order; built level by level from the coarsest on first use
                               per hierarchy and precision, GEMMs on the matrix cores).  0 = recurse
-                              (2048) */
+                              (4096) */
   uint64_t seed;           /* start-vector stream */
   uint64_t colour_seed;    /* colouring priority stream */
   int32_t case3;           /* Alg. 3 Case 3: 0 = v leaves its aggregate only when the rest stays

@@ -456,8 +456,10 @@ __device__ __forceinline__ void jp_wake_push(bool act, int32_t w, const int32_t*
   if (push) out[at + __popcll(pb & ((1ull << lane) - 1ull))] = w;
 }
 
-// Rows longer than this are pushed by jp_push_long_kernel.
+// Rows longer than this are pushed by jp_push_long_kernel; rows of at most
+// JP_PUSH_LANE_MAX entries by their own lane.
 constexpr int32_t JP_PUSH_WAVE_MAX = 256;
+constexpr int32_t JP_PUSH_LANE_MAX = 32;
 // Worklists of at most this many vertices per wavefront of the grid are
 // taken a vertex per wavefront, longer ones a vertex per lane.
 constexpr int32_t JP_WAVE_MODE_PER_WAVE = 4;
@@ -521,7 +523,17 @@ __global__ void __launch_bounds__(256)
       const bool got = !jp_try_wave(__shfl(v, j, 64), hrp, hci, colour, cur, usedm, bm, lane);
       if (lane == j) now = got;
     }
-    unsigned long long bal = __ballot(now);
+    // short rows: each lane pushes its own row, one entry per step; the
+    // others a row at a time by the wavefront (or as hubs)
+    const int32_t pk0 = now ? rp[v] : 0;
+    const int32_t plen = now ? rp[v + 1] - pk0 : 0;
+    const bool mine = now && plen <= JP_PUSH_LANE_MAX;
+    const int32_t span = wave_max_len(mine ? plen : 0);
+    for (int32_t j = 0; j < span; ++j) {
+      const bool act = mine && j < plen;
+      jp_wake_push(act, act ? ci[pk0 + j] : 0, colour, stamp, next, cnt_out, out, lane);
+    }
+    unsigned long long bal = __ballot(now && !mine);
     while (bal) {
       const int j = __ffsll((long long)bal) - 1;
       bal &= bal - 1ull;
@@ -573,9 +585,10 @@ __global__ void max_i32_kernel(const int32_t* a, int32_t n, int32_t* out) {
 
 // Mean row length above which levels are coloured one vertex at a time.
 constexpr int64_t JP_SEQ_DEG = 48;
-// Fewest threads a data-driven colouring round is launched with, and the
-// grid of its hub pushes (blocks per row x rows at a time).
-constexpr int32_t WAKE_MIN_THREADS = 1 << 17;
+// Fewest threads a data-driven colouring round is launched with (8192
+// wavefronts: worklists of up to 32768 vertices go a vertex per wavefront),
+// and the grid of its hub pushes (blocks per row x rows at a time).
+constexpr int32_t WAKE_MIN_THREADS = 1 << 19;
 constexpr unsigned PUSH_GRID_X = 64, PUSH_GRID_Y = 16;
 
 int32_t max_row_len(int32_t n, const int32_t* rp, hipStream_t s) {

@@ -266,7 +266,7 @@ pcamg_status pcamg_params_default(pcamg_params* p) {
   p->first_sweeps = -1;
   p->dense_max_n = 12288;
   p->long_row_min = 256;
-  p->v_dense_max_n = 2048;
+  p->v_dense_max_n = 4096;
   p->seed = 0x5EED;
   p->colour_seed = 0xC010;
   p->case3 = 0;

@@ -303,13 +303,26 @@ int32_t mwm_aggregate_level(int32_t n, const int32_t* rp, const int32_t* ci, con
 // fixed-point mean, small-aggregate fallback).  Returns fallback count.
 int32_t smooth_pval(int32_t n, const double* e_raw, int32_t nc, const int32_t* moff, const int32_t* mem,
                     double* pval, hipStream_t s);
-// Galerkin P^T A P (pval == nullptr: boolean).  Count pass then fill pass.
+// The sorted terms of the coarse rows too long for the one-pass kernel,
+// kept by a count pass for the fill pass of the same product.
+struct GalerkinCache {
+  int32_t nL = -1;  // -1: nothing kept
+  int64_t total = 0;
+  DVec<int32_t> rows;
+  DVec<int64_t> off;
+  DVec<uint64_t> ks;
+  DVec<uint32_t> perm;
+};
+// Galerkin P^T A P (pval == nullptr: boolean).  Count pass then fill pass;
+// with a cache, the fill pass right after the count pass of the same
+// operands reuses its sort.
 int64_t galerkin_count(int32_t n, const int32_t* rp, const int32_t* ci, int32_t nc, const int32_t* moff,
-                       const int32_t* mem, const int32_t* agg, int32_t* rpc, bool drop_diag, hipStream_t s);
+                       const int32_t* mem, const int32_t* agg, int32_t* rpc, bool drop_diag, hipStream_t s,
+                       GalerkinCache* cache = nullptr);
 void galerkin_fill(int32_t n, const int32_t* rp, const int32_t* ci, const double* av, const double* d,
                    int32_t nc, const int32_t* moff, const int32_t* mem, const int32_t* agg, const double* pval,
                    const int32_t* rpc, int32_t* cic, double* vc, double* dc, double* dinvc, bool graph_mode,
-                   hipStream_t s);
+                   hipStream_t s, GalerkinCache* cache = nullptr);
 // Path shortening: coarse cover nbc[2nc].
 void shorten_paths(int32_t n, const int32_t* nb, const int32_t* path_id, const int32_t* pos, int32_t nc,
                    const int32_t* agg, int32_t* nbc, hipStream_t s);

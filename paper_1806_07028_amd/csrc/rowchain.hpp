@@ -142,6 +142,18 @@ __device__ __forceinline__ double quad_bcast(double v) {
   return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
 }
 
+// Lane t's value as a wave-uniform (scalar) value: v_readlane, no LDS
+// permute.
+__device__ __forceinline__ float lane_value(float v, int t) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), t));
+}
+__device__ __forceinline__ double lane_value(double v, int t) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(uint32_t)u, t);
+  const int hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), t);
+  return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
 template <typename T, int G, typename PI, typename PA, typename PX>
 __device__ __forceinline__ T row_chain_g(int32_t k0, int32_t len, PI ci, PA av, PX x, T s) {
   static_assert(G > 1 && G <= 64 && (64 % G) == 0, "group size");
@@ -173,6 +185,13 @@ __device__ __forceinline__ T row_chain_g(int32_t k0, int32_t len, PI ci, PA av, 
         if (e + 1 < len) s = fma(a1, v1, s);
         if (e + 2 < len) s = fma(a2, v2, s);
         if (e + 3 < len) s = fma(a3, v3, s);
+      } else if constexpr (G == 64) {  // one row per wavefront: scalar broadcasts
+#pragma unroll
+        for (int t = 0; t < 64; ++t) {
+          const T at = lane_value(a[u], t);
+          const T vt = lane_value(v[u], t);
+          if (e + t < len) s = fma(at, vt, s);
+        }
       } else {
 #pragma unroll
         for (int t = 0; t < G; ++t) {

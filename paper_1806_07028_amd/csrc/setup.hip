@@ -1148,7 +1148,7 @@ __global__ void gal_terms_kernel(const int32_t* __restrict__ rows, const int64_t
     // tv == nullptr: counting pass, keys only (av, d may be null then)
     if (!graph_mode) {
       if (threadIdx.x == 0) {
-        keys[seq] = hi | (uint32_t)I;
+        if (keys) keys[seq] = hi | (uint32_t)I;
         if (tv) {
           tv[seq] = pk * d[k];
           tp[seq] = pk;
@@ -1160,7 +1160,7 @@ __global__ void gal_terms_kernel(const int32_t* __restrict__ rows, const int64_t
     for (int32_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
       const int32_t l = ci[e];
       const int64_t t = seq + (e - e0);
-      keys[t] = hi | (uint32_t)agg[l];
+      if (keys) keys[t] = hi | (uint32_t)agg[l];
       if (!tv) continue;
       if (graph_mode) {
         tv[t] = av[e];
@@ -1218,10 +1218,39 @@ __global__ void __launch_bounds__(LONG_BLOCK)
 static void galerkin_long_rows(int32_t nc, const uint8_t* ovf, const int32_t* moff, const int32_t* mem,
                                const int32_t* agg, const int32_t* rp, const int32_t* ci, const double* av,
                                const double* d, const double* pval, bool graph_mode, const int32_t* rpc,
-                               int32_t* count, int32_t* cic, double* vc, double* dc, double* dinvc, hipStream_t s) {
+                               int32_t* count, int32_t* cic, double* vc, double* dc, double* dinvc,
+                               GalerkinCache* cache, hipStream_t s) {
+  const bool values = rpc != nullptr;  // fill pass
+  if (values && cache && cache->nL >= 0) {
+    // the count pass's sorted terms: the same long rows in the same order
+    // (the overflow test is the same), so only the values are generated
+    const int32_t nL = cache->nL;
+    {
+      DVec<int32_t> rows(nc), cnt(1);
+      compact_i32(nullptr, ovf, rows.p, cnt.p, nc, s);
+      require(read_scalar(cnt.p, s) == nL, PCAMG_EHIP, "Galerkin fill: long rows differ from the count pass");
+    }
+    if (nL > 0) {
+      const int64_t total = cache->total;
+      DVec<double> tv(total), tp(total);
+      gal_terms_kernel<<<nL, LONG_BLOCK, 0, s>>>(cache->rows.p, cache->off.p, moff, mem, agg, rp, ci, av, d, pval,
+                                                 graph_mode, nullptr, tv.p, tp.p);
+      PCAMG_LAUNCHED();
+      gal_runs_kernel<<<nL, LONG_BLOCK, 0, s>>>(cache->rows.p, cache->off.p, cache->ks.p, cache->perm.p, tv.p, tp.p,
+                                                graph_mode, rpc, count, cic, vc, dc, dinvc);
+      PCAMG_LAUNCHED();
+      PCAMG_HIP(hipStreamSynchronize(s));
+    }
+    cache->nL = -1;
+    return;
+  }
   DVec<int32_t> rows(nc), cnt(1);
   compact_i32(nullptr, ovf, rows.p, cnt.p, nc, s);
   const int32_t nL = read_scalar(cnt.p, s);
+  if (cache) {
+    cache->nL = nL;
+    cache->total = 0;
+  }
   if (nL == 0) return;
   DVec<int32_t> lc(nL);
   gal_terms_count_kernel<<<grid_for(nL, 256), 256, 0, s>>>(nL, rows.p, moff, mem, rp, graph_mode, lc.p);
@@ -1231,7 +1260,6 @@ static void galerkin_long_rows(int32_t nc, const uint8_t* ovf, const int32_t* mo
   int64_t total = read_scalar(off.p + (nL - 1), s) + read_scalar(lc.p + (nL - 1), s);
   require(total < ((int64_t)1 << 31), PCAMG_EUNSUPPORTED, "Galerkin product: long rows exceed 2^31 terms");
   copy_h2d(off.p + nL, &total, 1, s);
-  const bool values = rpc != nullptr;  // fill pass
   DVec<uint64_t> keys(total), ks(total);
   DVec<double> tv(values ? total : 0), tp(values ? total : 0);
   DVec<uint32_t> idx(total), perm(total);
@@ -1244,10 +1272,18 @@ static void galerkin_long_rows(int32_t nc, const uint8_t* ovf, const int32_t* mo
                                             dc, dinvc);
   PCAMG_LAUNCHED();
   PCAMG_HIP(hipStreamSynchronize(s));  // `total` is read by the async copy above
+  if (cache && !values) {  // kept for the fill pass
+    cache->total = total;
+    cache->rows = std::move(rows);
+    cache->off = std::move(off);
+    cache->ks = std::move(ks);
+    cache->perm = std::move(perm);
+  }
 }
 
 int64_t galerkin_count(int32_t n, const int32_t* rp, const int32_t* ci, int32_t nc, const int32_t* moff,
-                       const int32_t* mem, const int32_t* agg, int32_t* rpc, bool graph_mode, hipStream_t s) {
+                       const int32_t* mem, const int32_t* agg, int32_t* rpc, bool graph_mode, hipStream_t s,
+                       GalerkinCache* cache) {
   (void)n;
   if (nc <= 0) return 0;
   DVec<int32_t> cnt(nc);
@@ -1258,7 +1294,7 @@ int64_t galerkin_count(int32_t n, const int32_t* rp, const int32_t* ci, int32_t 
                                                                       nullptr, nullptr, nullptr, ovf.p);
   PCAMG_LAUNCHED();
   galerkin_long_rows(nc, ovf.p, moff, mem, agg, rp, ci, nullptr, nullptr, nullptr, graph_mode, nullptr, cnt.p,
-                     nullptr, nullptr, nullptr, nullptr, s);
+                     nullptr, nullptr, nullptr, nullptr, cache, s);
   DVec<int64_t> off64(nc);
   scan_exclusive_i64(cnt.p, off64.p, nc, s);
   int64_t total = read_scalar(off64.p + (nc - 1), s) + read_scalar(cnt.p + (nc - 1), s);
@@ -1269,7 +1305,8 @@ int64_t galerkin_count(int32_t n, const int32_t* rp, const int32_t* ci, int32_t 
 
 void galerkin_fill(int32_t n, const int32_t* rp, const int32_t* ci, const double* av, const double* d, int32_t nc,
                    const int32_t* moff, const int32_t* mem, const int32_t* agg, const double* pval, const int32_t* rpc,
-                   int32_t* cic, double* vc, double* dc, double* dinvc, bool graph_mode, hipStream_t s) {
+                   int32_t* cic, double* vc, double* dc, double* dinvc, bool graph_mode, hipStream_t s,
+                   GalerkinCache* cache) {
   (void)n;
   if (nc <= 0) return;
   DVec<uint8_t> ovf(nc);
@@ -1278,7 +1315,8 @@ void galerkin_fill(int32_t n, const int32_t* rp, const int32_t* ci, const double
                                                                       graph_mode, rpc, nullptr, cic, vc, dc, dinvc,
                                                                       ovf.p);
   PCAMG_LAUNCHED();
-  galerkin_long_rows(nc, ovf.p, moff, mem, agg, rp, ci, av, d, pval, graph_mode, rpc, nullptr, cic, vc, dc, dinvc, s);
+  galerkin_long_rows(nc, ovf.p, moff, mem, agg, rp, ci, av, d, pval, graph_mode, rpc, nullptr, cic, vc, dc, dinvc,
+                     cache, s);
 }
 
 // ---------------------------------------------------------------------------

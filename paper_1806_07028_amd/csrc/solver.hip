@@ -456,21 +456,22 @@ std::unique_ptr<Hierarchy> build_hierarchy(pcamg_ctx* c, const double* e_nat) {
     NatLevel C;
     C.n = nc;
     C.o_rp.resize(nc + 1);
-    int64_t nnzc = galerkin_count(L.n, L.rp, L.ci, nc, L.moff.p, L.mem.p, L.agg.p, C.o_rp.p, false, s);
+    GalerkinCache gc;
+    int64_t nnzc = galerkin_count(L.n, L.rp, L.ci, nc, L.moff.p, L.mem.p, L.agg.p, C.o_rp.p, false, s, &gc);
     C.nnz = (int32_t)nnzc;
     C.o_ci.resize(std::max<int64_t>(nnzc, 1));
     C.o_av.resize(std::max<int64_t>(nnzc, 1));
     C.o_d.resize(nc);
     C.o_dinv.resize(nc);
     galerkin_fill(L.n, L.rp, L.ci, L.av, L.d, nc, L.moff.p, L.mem.p, L.agg.p, L.pval.p, C.o_rp.p, C.o_ci.p,
-                  C.o_av.p, C.o_d.p, C.o_dinv.p, false, s);
+                  C.o_av.p, C.o_d.p, C.o_dinv.p, false, s, &gc);
     C.o_grp.resize(nc + 1);
-    int64_t nnzg = galerkin_count(L.n, L.grp, L.gci, nc, L.moff.p, L.mem.p, L.agg.p, C.o_grp.p, true, s);
+    int64_t nnzg = galerkin_count(L.n, L.grp, L.gci, nc, L.moff.p, L.mem.p, L.agg.p, C.o_grp.p, true, s, &gc);
     C.nnz_g = (int32_t)nnzg;
     C.o_gci.resize(std::max<int64_t>(nnzg, 1));
     C.o_gv.resize(std::max<int64_t>(nnzg, 1));
     galerkin_fill(L.n, L.grp, L.gci, L.gv, nullptr, nc, L.moff.p, L.mem.p, L.agg.p, nullptr, C.o_grp.p, C.o_gci.p,
-                  C.o_gv.p, nullptr, nullptr, true, s);
+                  C.o_gv.p, nullptr, nullptr, true, s, &gc);
     C.o_nb.resize(2 * (size_t)nc);
     shorten_paths(L.n, L.nb, L.pid.p, L.pos.p, nc, L.agg.p, C.o_nb.p, s);
     C.o_colour.resize(nc);
@@ -528,14 +529,15 @@ std::unique_ptr<Hierarchy> build_hierarchy_mwm(pcamg_ctx* c) {
     NatLevel C;
     C.n = nc;
     C.o_rp.resize(nc + 1);
-    int64_t nnzc = galerkin_count(L.n, L.rp, L.ci, nc, L.moff.p, L.mem.p, L.agg.p, C.o_rp.p, false, s);
+    GalerkinCache gc;
+    int64_t nnzc = galerkin_count(L.n, L.rp, L.ci, nc, L.moff.p, L.mem.p, L.agg.p, C.o_rp.p, false, s, &gc);
     C.nnz = (int32_t)nnzc;
     C.o_ci.resize(std::max<int64_t>(nnzc, 1));
     C.o_av.resize(std::max<int64_t>(nnzc, 1));
     C.o_d.resize(nc);
     C.o_dinv.resize(nc);
     galerkin_fill(L.n, L.rp, L.ci, L.av, L.d, nc, L.moff.p, L.mem.p, L.agg.p, nullptr, C.o_rp.p, C.o_ci.p,
-                  C.o_av.p, C.o_d.p, C.o_dinv.p, false, s);
+                  C.o_av.p, C.o_d.p, C.o_dinv.p, false, s, &gc);
     C.o_colour.resize(nc);
     C.ncol = colour_level(nc, C.o_rp.p, C.o_ci.p, P.colour_seed, l + 1, C.o_colour.p, s);
     C.rp = C.o_rp.p;
