@@ -589,7 +589,7 @@ constexpr int64_t JP_SEQ_DEG = 48;
 // wavefronts: worklists of up to 32768 vertices go a vertex per wavefront),
 // and the grid of its hub pushes (blocks per row x rows at a time).
 constexpr int32_t WAKE_MIN_THREADS = 1 << 19;
-constexpr unsigned PUSH_GRID_X = 64, PUSH_GRID_Y = 16;
+constexpr unsigned PUSH_GRID_X = 16, PUSH_GRID_Y = 16;
 
 int32_t max_row_len(int32_t n, const int32_t* rp, hipStream_t s) {
   DVec<int32_t> mx(1);
@@ -736,6 +736,8 @@ __global__ void __launch_bounds__(256)
   const int lane = threadIdx.x & 63;
   bool odd = false;
   for (int32_t base = blockIdx.x * blockDim.x; base < m; base += stride) {
+    // an odd cycle already seen (here or by another workgroup) decides the test
+    if (__builtin_amdgcn_readfirstlane(__atomic_load_n(odd_flag, __ATOMIC_RELAXED))) break;
     const int32_t t = base + threadIdx.x;
     const bool act = t < m;
     const int32_t v = act ? in[t] : 0;
