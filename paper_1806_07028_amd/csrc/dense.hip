@@ -67,8 +67,8 @@ struct Mfma<double> {
 
 template <typename T>
 __global__ void __launch_bounds__(256)
-    gemm_mfma_kernel(int32_t p, int32_t q, int32_t r, T alpha, const T* __restrict__ Q, const T* __restrict__ R,
-                     T beta, T* __restrict__ P) {
+    gemm_mfma_kernel(int32_t p, int32_t q, int32_t r, T alpha, const T* __restrict__ Q, int32_t ldq,
+                     const T* __restrict__ R, int32_t ldr, T beta, T* __restrict__ P, int32_t ldp) {
   constexpr int BM = Mfma<T>::BM, BN = Mfma<T>::BN, BK = 16;
   constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
   __shared__ T As[BK][BM + 4];  // k-major: a lane's A operand is As[k][row]
@@ -86,12 +86,12 @@ __global__ void __launch_bounds__(256)
     for (int e = tid; e < BM * BK; e += 256) {
       const int i = e / BK, k = e % BK;
       const int32_t gi = row0 + i, gk = k0 + k;
-      As[k][i] = (gi < p && gk < q) ? Q[(size_t)gi * q + gk] : (T)0;
+      As[k][i] = (gi < p && gk < q) ? Q[(size_t)gi * ldq + gk] : (T)0;
     }
     for (int e = tid; e < BK * BN; e += 256) {
       const int k = e / BN, j = e % BN;
       const int32_t gk = k0 + k, gj = col0 + j;
-      Bs[k][j] = (gk < q && gj < r) ? R[(size_t)gk * r + gj] : (T)0;
+      Bs[k][j] = (gk < q && gj < r) ? R[(size_t)gk * ldr + gj] : (T)0;
     }
     __syncthreads();
 #pragma unroll
@@ -116,20 +116,28 @@ __global__ void __launch_bounds__(256)
       for (int v = 0; v < 4; ++v) {
         const int32_t gi = row0 + wm * WM + a * 16 + Mfma<T>::row(lk, v), gj = col0 + wn * WN + b * 16 + lr;
         if (gi < p && gj < r) {
-          const size_t o = (size_t)gi * r + gj;
+          const size_t o = (size_t)gi * ldp + gj;
           const T t = alpha * acc[a][b][v];
           P[o] = beta == (T)0 ? t : fma(beta, P[o], t);
         }
       }
 }
 
-// Row-major P = alpha Q R + beta P (p x q times q x r).
+// Row-major P = alpha Q R + beta P (p x q times q x r), each operand with its
+// own row stride (ldq, ldr, ldp elements).
 template <typename T>
-void gemm_rows(int32_t p, int32_t q, int32_t r, T alpha, const T* Q, const T* R, T beta, T* P, hipStream_t s) {
+void gemm_strided(int32_t p, int32_t q, int32_t r, T alpha, const T* Q, int32_t ldq, const T* R, int32_t ldr,
+                  T beta, T* P, int32_t ldp, hipStream_t s) {
   if (p <= 0 || r <= 0) return;
   const dim3 grid((unsigned)((r + Mfma<T>::BN - 1) / Mfma<T>::BN), (unsigned)((p + Mfma<T>::BM - 1) / Mfma<T>::BM));
-  gemm_mfma_kernel<T><<<grid, 256, 0, s>>>(p, q, r, alpha, Q, R, beta, P);
+  gemm_mfma_kernel<T><<<grid, 256, 0, s>>>(p, q, r, alpha, Q, ldq, R, ldr, beta, P, ldp);
   PCAMG_LAUNCHED();
+}
+
+// The same with each operand's column count as its stride.
+template <typename T>
+void gemm_rows(int32_t p, int32_t q, int32_t r, T alpha, const T* Q, const T* R, T beta, T* P, hipStream_t s) {
+  gemm_strided<T>(p, q, r, alpha, Q, q, R, r, beta, P, r, s);
 }
 
 // Z[i * n + j] = (coarsest solve of e_j)_i: one workgroup per column, the
@@ -287,6 +295,92 @@ __global__ void __launch_bounds__(256) blk_transpose_kernel(int32_t n, const T* 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Near-dense levels (many colours of a few rows each): a colour pass on all
+// columns is a launch per colour, each summing long rows.  There a sweep is
+// taken instead as a blocked triangular solve on the dense off-diagonal part
+// Ad, in the same row order (the colour order of the level, in which rows of
+// one colour do not touch each other): for row blocks of GS_NB rows in sweep
+// order, G = Ad[b, outside b] X[outside b] as GEMMs on the matrix cores
+// (the rows before the block hold their new values, those after their old
+// ones), then the rows of the block one at a time, each from I - G and the
+// block's current values -- the Gauss-Seidel update of every row, with the
+// sums in another order.
+// ---------------------------------------------------------------------------
+constexpr int GS_NB = 32;
+
+// Ad[i, c_e] = a_e (Ad zero on entry), a workgroup per row.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    blk_densify_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                       const T* __restrict__ av, T* __restrict__ Ad) {
+  const int32_t i = (int32_t)blockIdx.x;
+  for (int32_t k = rp[i] + (int32_t)threadIdx.x; k < rp[i + 1]; k += 256) Ad[(size_t)i * n + ci[k]] = av[k];
+}
+
+// The rows r0 .. r0 + nb - 1 of X, one column per thread, in order
+// (forward) or reverse: x_i = (delta(r0 + i, j) - G_i - sum_{k in block,
+// k != i} a_ik x_k) dinv_i with the block's current values, G = the GEMMs'
+// sum over the rows outside the block (none: G = 0); the block of Ad in LDS.
+template <typename T, bool Forward>
+__global__ void __launch_bounds__(256)
+    blk_block_gs_kernel(int32_t n, int32_t r0, int32_t nb, const T* __restrict__ Ad, const T* __restrict__ dinv,
+                        const T* __restrict__ G, T* __restrict__ X) {
+  __shared__ T ab[GS_NB][GS_NB + 1];
+  __shared__ T dv[GS_NB];
+  for (int e = (int)threadIdx.x; e < GS_NB * GS_NB; e += 256) {
+    const int i = e / GS_NB, k = e % GS_NB;
+    ab[i][k] = (i < nb && k < nb) ? Ad[(size_t)(r0 + i) * n + r0 + k] : (T)0;
+  }
+  if (threadIdx.x < GS_NB) dv[threadIdx.x] = (int)threadIdx.x < nb ? dinv[r0 + threadIdx.x] : (T)0;
+  __syncthreads();
+  const int32_t j = (int32_t)(blockIdx.x * 256 + threadIdx.x);
+  if (j >= n) return;
+  T x[GS_NB];
+#pragma unroll
+  for (int k = 0; k < GS_NB; ++k) x[k] = k < nb ? X[(size_t)(r0 + k) * n + j] : (T)0;
+#pragma unroll
+  for (int t = 0; t < GS_NB; ++t) {
+    const int i = Forward ? t : GS_NB - 1 - t;
+    if (i < nb) {
+      T acc = (r0 + i == j ? (T)1 : (T)0) - (G ? G[(size_t)i * n + j] : (T)0);
+#pragma unroll
+      for (int k = 0; k < GS_NB; ++k)
+        if (k != i) acc = fma(-ab[i][k], x[k], acc);
+      x[i] = acc * dv[i];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < GS_NB; ++k)
+    if (k < nb) X[(size_t)(r0 + k) * n + j] = x[k];
+}
+
+// One sweep on all n columns of X (forward: block rows ascending), from
+// X = 0 when x_zero (no rows after the block to subtract).  G: GS_NB x n.
+template <typename T>
+void dense_gs_sweep(int32_t n, const T* Ad, const T* dinv, T* X, T* G, bool forward, bool x_zero, hipStream_t s) {
+  const int32_t nbk = (n + GS_NB - 1) / GS_NB;
+  const unsigned cols = (unsigned)((n + 255) / 256);
+  for (int32_t t = 0; t < nbk; ++t) {
+    const int32_t b = forward ? t : nbk - 1 - t;
+    const int32_t r0 = b * GS_NB, r1 = std::min(n, r0 + GS_NB), nb = r1 - r0;
+    const bool left = r0 > 0, right = r1 < n && !x_zero;
+    if (left) gemm_strided<T>(nb, r0, n, (T)1, Ad + (size_t)r0 * n, n, X, n, (T)0, G, n, s);
+    if (right)
+      gemm_strided<T>(nb, n - r1, n, (T)1, Ad + (size_t)r0 * n + r1, n, X + (size_t)r1 * n, n, left ? (T)1 : (T)0, G,
+                      n, s);
+    const T* g = left || right ? G : nullptr;
+    if (forward) blk_block_gs_kernel<T, true><<<cols, 256, 0, s>>>(n, r0, nb, Ad, dinv, g, X);
+    else blk_block_gs_kernel<T, false><<<cols, 256, 0, s>>>(n, r0, nb, Ad, dinv, g, X);
+    PCAMG_LAUNCHED();
+  }
+}
+
+// Levels of at most DENSE_GS_MAX_N rows with more than one colour per
+// DENSE_GS_ROWS_PER_COLOUR rows take dense_gs_sweep in the build.
+constexpr int32_t DENSE_GS_MAX_N = 4096;
+constexpr int32_t DENSE_GS_ROWS_PER_COLOUR = 8;
+
 inline dim3 rows_grid(int32_t ncols, int32_t rows) { return dim3((unsigned)((ncols + 255) / 256), (unsigned)rows); }
 
 template <typename T>
@@ -360,7 +454,18 @@ void dense_bottom_up(Hierarchy& H, int d, int gamma, T* C, hipStream_t s) {
     PCAMG_HIP(hipMemsetAsync(X.p, 0, X.bytes(), s));  // all-zero bits: +0
     const T* av = LevelOf<T>::av(A);
     const T* dinv = LevelOf<T>::dinv(A);
-    for (int k = 0; k < A.ncol; ++k) {
+    // near-dense levels: blocked dense sweeps instead of a launch per colour
+    const bool dense_gs = n <= DENSE_GS_MAX_N && (int64_t)A.ncol * DENSE_GS_ROWS_PER_COLOUR > n;
+    DVec<T> Ad, G;
+    if (dense_gs) {
+      Ad.resize((size_t)n * n);
+      G.resize((size_t)GS_NB * n);
+      PCAMG_HIP(hipMemsetAsync(Ad.p, 0, Ad.bytes(), s));
+      blk_densify_kernel<T><<<n, 256, 0, s>>>(n, A.rp.p, A.ci.p, av, Ad.p);
+      PCAMG_LAUNCHED();
+      dense_gs_sweep<T>(n, Ad.p, dinv, X.p, G.p, true, true, s);
+    }
+    for (int k = 0; k < (dense_gs ? 0 : A.ncol); ++k) {
       const int32_t r0 = A.coff[k], r1 = A.coff[k + 1];
       if (r1 <= r0) continue;
       blk_gs_kernel<T><<<dim3((unsigned)((n + 15) / 16), (unsigned)(r1 - r0)), 256, 0, s>>>(r0, n, A.rp.p, A.ci.p,
@@ -374,7 +479,8 @@ void dense_bottom_up(Hierarchy& H, int d, int gamma, T* C, hipStream_t s) {
     gemm_rows<T>(m, m, n, (T)1, Cl, Bc.p, (T)0, Xc.p, s);
     blk_prolong_kernel<T><<<rows_grid(n, n), 256, 0, s>>>(n, Tr.agg.p, LevelOf<T>::pval(Tr), Xc.p, X.p);
     PCAMG_LAUNCHED();
-    for (int k = A.ncol - 1; k >= 0; --k) {
+    if (dense_gs) dense_gs_sweep<T>(n, Ad.p, dinv, X.p, G.p, false, false, s);
+    for (int k = dense_gs ? -1 : A.ncol - 1; k >= 0; --k) {
       const int32_t r0 = A.coff[k], r1 = A.coff[k + 1];
       if (r1 <= r0) continue;
       blk_gs_kernel<T><<<dim3((unsigned)((n + 15) / 16), (unsigned)(r1 - r0)), 256, 0, s>>>(r0, n, A.rp.p, A.ci.p,

@@ -558,7 +558,10 @@ def test_dense_v_cycle(gpu, oracle, gname):
     applied as one precomputed dense operator: the same linear map as the
     recursion, different rounding order. FP64 within 1e-12 relative, FP32
     within 1e-5 relative of the oracle's recursive cycle; graph replays equal
-    the eager dense cycle bit for bit; W-cycles untouched."""
+    the eager dense cycle bit for bit; W-cycles untouched.  On the power-law
+    graph the operator's near-dense levels (more than one colour per 8 rows)
+    are built with blocked dense sweeps (GEMMs and 32-row triangular blocks)
+    instead of colour passes."""
     g = I.grid3d(20, 20, 20, weight_seed=7) if gname == "grid3d_20" else I.config3(n0=30000)[0]
     n = g[0]
     b = I.zero_mean_normal_rhs(3, n)
@@ -570,6 +573,9 @@ def test_dense_v_cycle(gpu, oracle, gname):
     assert dense.num_levels() == H.nlevels >= 4
     sizes = [dense.level_info(l)["n"] for l in range(dense.num_levels())]
     assert sizes[1] > 2048  # a launched level applies the operator below it
+    if gname == "powerlaw":  # the blocked dense sweeps are taken
+        infos = [dense.level_info(l) for l in range(dense.num_levels())]
+        assert any(i["n"] <= 2048 and 8 * i["ncolours"] > i["n"] for i in infos[:-1])
     v_ref = H.cycle(b, x0, 1)
     v64 = host(dense.cycle(b, x0, 1))
     close_elementwise(v64, v_ref, 1e-12)
