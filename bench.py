@@ -90,6 +90,20 @@ def copy_ceiling(nbytes: int = 1 << 30, reps: int = 10) -> dict:
             "copies": reps}
 
 
+MFMA_PEAK_TFLOPS = {0: 78.6, 1: 157.3}  # dense FP64 / FP32 matrix-core peaks of the MI355X
+
+
+def gemm_rate(p: int, q: int, r: int, prec: int, reps: int = 10) -> dict:
+    """pcamg_bench_gemm: the dense operators' MFMA GEMM on p x q times q x r."""
+    from paper_1806_07028_amd import _lib
+    ms = C.c_double()
+    _lib.check(_lib.lib().pcamg_bench_gemm(p, q, r, prec, reps, None, C.byref(ms)))
+    tf = 2.0 * p * q * r * reps / (ms.value * 1e-3) / 1e12
+    return {"shape": [p, q, r], "dtype": "f64" if prec == 0 else "f32", "tflops": round(tf, 2),
+            "peak": MFMA_PEAK_TFLOPS[prec], "frac": round(tf / MFMA_PEAK_TFLOPS[prec], 4),
+            "ms_per_product": round(ms.value / reps, 4)}
+
+
 def host_relres(g, b, x) -> float:
     import numpy as np
     import scipy.sparse as sp
@@ -190,9 +204,10 @@ def powerlaw_headline(args):
     s.close()
     roofline = {"bound": "hbm", "achieved": gs_roof["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": gs_roof["frac"], "traffic": None,
-                "kernel": f"finest-level forward Gauss-Seidel sweep in {prec.upper()} ({colours[0]} colour passes; "
-                          "per pass gs_kernel<double,4> for rows of under 256 entries and gs_long_kernel<double> "
-                          "for the hub rows), 1 GiB read between timed sweeps",
+                "kernel": f"finest-level forward Gauss-Seidel sweep in {prec.upper()} ({colours[0]} colour passes, "
+                          "one launch each: gs_fused_kernel, a workgroup per hub row of 256+ entries and 4 lanes "
+                          "per other row; gs_long_kernel for colours of hub rows only), 1 GiB read between timed "
+                          "sweeps",
                 "avg_launch_us": gs_roof["avg_launch_us"], "bytes_per_launch":
                     round(gs_roof["bytes_per_pass"] / gs_roof["launches_per_pass"]),
                 "bytes_per_sweep": gs_roof["bytes_per_pass"], "us_per_sweep": gs_roof["us_per_pass"],
@@ -227,6 +242,11 @@ def powerlaw_headline(args):
             "x_rel_diff": float(np.linalg.norm(x2.cpu().numpy() - xh) / np.linalg.norm(xh))}
         del dev, bd
         out["grid3d_128"] = grid3d_extras(args)
+        out["batch_sample"] = batch_sample()
+        log("MFMA GEMM of the dense operators")
+        out["mfma_gemm"] = {"square_4096_f64": gemm_rate(4096, 4096, 4096, 0),
+                            "square_4096_f32": gemm_rate(4096, 4096, 4096, 1),
+                            "coarse_correction_f64": gemm_rate(1278, 1278, 2931, 0)}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
         out["cpu_baseline"] = oracle_sample(150_000, dict(outer=1, cycle_prec=0 if prec == "f64" else 1, theta=0.5,
@@ -301,6 +321,40 @@ def grid3d_bench(args):
                                "V(1,1) cycles to 1e-8, theta 0.5"},
         "iterations": st["iterations"], "rebuilds": st["rebuilds"], "conv_factor": round(st["rho_geo"], 4),
         "host_checked_relres": host_relres(g, b, x.cpu().numpy()), "smoother_roofline": roof}), flush=True)
+
+
+def batch_sample(count: int = 64) -> dict:
+    """The first `count` graphs of the 512-graph uneven batch (the generator
+    draws sizes and kinds at random, so they are a random sample), solved in
+    one library call after one warm-up call; throughput and the whole batch's
+    time extrapolated by edges."""
+    import numpy as np
+    import torch
+
+    import paper_1806_07028_amd as P
+    from paper_1806_07028_amd import inputs as I
+    log(f"batch sample: the first {count} of the 512 uneven graphs")
+    batch = I.config4(seed=1, count=512)
+    dev = torch.device("cuda", 0)
+    sel = batch[:count]
+    graphs = [tuple(torch.as_tensor(a, device=dev) for a in (g[1], g[2], g[3])) for g, b, k in sel]
+    rhs = [torch.as_tensor(b, device=dev) for g, b, k in sel]
+    params = dict(outer="fcg", cycle_prec="f32", theta=0.5)
+    P.batch_solve(graphs[:8], rhs[:8], workers=1, **params)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xs, sts = P.batch_solve(graphs, rhs, workers=1, **params)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    m_s = sum(len(g[2]) for g, b, k in sel)
+    m_all = sum(len(g[2]) for g, b, k in batch)
+    its = [st["iterations"] for st in sts]
+    return {"workload": f"first {count} of 512 uneven graphs (2D grid / RGG / BA, n log-uniform on [1e3, 2e5], "
+                        "weights 10^(-2+4u)); FCG(FP64) + FP32 cycles to 1e-8, theta 0.5, one graph after another",
+            "graphs": count, "vertices": sum(g[0] for g, b, k in sel), "time_s": round(t, 3),
+            "graphs_per_s": round(count / t, 2), "converged": sum(st["status"] == 0 for st in sts),
+            "iterations": {"min": min(its), "max": max(its), "mean": round(float(np.mean(its)), 2)},
+            "whole_batch_s_by_edges": round(t * m_all / m_s, 1)}
 
 
 def batch_bench(args):

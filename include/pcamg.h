@@ -285,6 +285,15 @@ pcamg_status pcamg_bench_level(pcamg_ctx* c, int32_t kind, int32_t prec, int32_t
  * events on `stream`; *ms (host) is the total.  Each copy moves 2 x bytes. */
 pcamg_status pcamg_bench_copy(int64_t bytes, int32_t reps, void* stream, double* ms);
 
+/* The matrix-core GEMM of the dense operators (the product of Alg. 2's
+ * W-cycle operator construction): `reps` products P = Q R of row-major
+ * p x q and q x r operands (deterministic values in [-1, 1), allocated and
+ * freed here) in FP64 (prec 0) or FP32 (prec 1), timed with HIP events on
+ * `stream`; *ms (host) is the total.  Each product is 2 p q r flops.
+ * PCAMG_EINVAL for sizes below 1 or reps below 1. */
+pcamg_status pcamg_bench_gemm(int32_t p, int32_t q, int32_t r, int32_t prec, int32_t reps, void* stream,
+                              double* ms);
+
 /* Smooth error of the first build: start vector of build 0 (SplitMix64
  * stream p->seed) and relax_sweeps symmetric sweeps on A e = 0. device [n]. */
 pcamg_status pcamg_initial_error(pcamg_ctx* c, double* e);

@@ -137,6 +137,7 @@ _SIGS = {
     "pcamg_bench_level": ([_p, _i32, _i32, _i32, _i64, C.POINTER(C.c_double), C.POINTER(_i64),
                            C.POINTER(C.c_double)], _i32),
     "pcamg_bench_copy": ([_i64, _i32, _p, C.POINTER(C.c_double)], _i32),
+    "pcamg_bench_gemm": ([_i32, _i32, _i32, _i32, _i32, _p, C.POINTER(C.c_double)], _i32),
     "pcamg_laplacian": ([_i32, _p, _p, _p, _p, _p, _p, _p], _i32),
     "pcamg_colour": ([_i32, _p, _p, _u64, _i32, _p, C.POINTER(_i32), _p], _i32),
     "pcamg_gs": ([_i32, _p, _p, _p, _p, _p, _i32, _p, _p, _i32, _i32, _p], _i32),

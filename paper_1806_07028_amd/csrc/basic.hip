@@ -723,21 +723,47 @@ __device__ __forceinline__ void bfs_visit(bool act, int32_t u, int32_t* depth, i
   if (claim) out[at + __popcll(bal & ((1ull << lane) - 1ull))] = u;
 }
 
-// One round: each lane expands its frontier vertex's row when it has at most
-// 64 entries; longer rows are then expanded by the whole wavefront, one at a
-// time, 64 entries per step (a hub would otherwise hold its wavefront for its
-// whole row, one entry per step).
+// One round.  Short frontiers (at most BFS_WAVE_MODE_PER_WAVE vertices per
+// wavefront of the grid) go a vertex per wavefront, its row 64 entries per
+// step; longer ones a vertex per lane for rows of at most 64 entries, the
+// longer rows then by the whole wavefront, one at a time (a hub would
+// otherwise hold its wavefront for its whole row, one entry per step).  An
+// odd cycle is published as soon as a wavefront sees one, and every
+// wavefront stops at its next vertex once it is.
+constexpr int32_t BFS_WAVE_MODE_PER_WAVE = 4;
+
 __global__ void __launch_bounds__(256)
     bfs_round_kernel(const int32_t* __restrict__ cnt_in, const int32_t* __restrict__ in, int32_t* __restrict__ cnt_out,
                      int32_t* __restrict__ out, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
                      int32_t* depth, int32_t d, int32_t* odd_flag) {
   const int32_t m = *cnt_in;
-  const int32_t stride = gridDim.x * blockDim.x;
   const int lane = threadIdx.x & 63;
   bool odd = false;
+  // publishes this wavefront's odd cycle; true once any wavefront has one
+  auto stop = [&]() -> bool {
+    if (__ballot(odd)) {
+      if (lane == 0) __atomic_store_n(odd_flag, 1, __ATOMIC_RELAXED);
+      return true;
+    }
+    return __builtin_amdgcn_readfirstlane(__atomic_load_n(odd_flag, __ATOMIC_RELAXED)) != 0;
+  };
+  const int32_t nwaves = (int32_t)gridDim.x * 4;
+  if (m <= BFS_WAVE_MODE_PER_WAVE * nwaves) {
+    for (int32_t t = (int32_t)blockIdx.x * 4 + (int32_t)(threadIdx.x >> 6); t < m; t += nwaves) {
+      if (stop()) return;
+      const int32_t v = in[t];
+      const int32_t a = rp[v], e = rp[v + 1];
+      for (int32_t k = a; k < e; k += 64) {
+        const bool on = k + lane < e;
+        bfs_visit(on, on ? ci[k + lane] : 0, depth, d, odd, cnt_out, out, lane);
+      }
+    }
+    stop();
+    return;
+  }
+  const int32_t stride = gridDim.x * blockDim.x;
   for (int32_t base = blockIdx.x * blockDim.x; base < m; base += stride) {
-    // an odd cycle already seen (here or by another workgroup) decides the test
-    if (__builtin_amdgcn_readfirstlane(__atomic_load_n(odd_flag, __ATOMIC_RELAXED))) break;
+    if (stop()) return;
     const int32_t t = base + threadIdx.x;
     const bool act = t < m;
     const int32_t v = act ? in[t] : 0;
@@ -760,7 +786,7 @@ __global__ void __launch_bounds__(256)
       }
     }
   }
-  if (odd) *odd_flag = 1;
+  stop();
 }
 
 __global__ void parity_kernel(int32_t n, const int32_t* __restrict__ depth, int32_t* __restrict__ colour) {
@@ -778,7 +804,7 @@ bool colour_bipartite(int32_t n, const int32_t* rp, const int32_t* ci, int32_t* 
   fill_i32(list0.p, 0, 1, s);
   fill_i32(st.p, 0, RMAX + 2, s);
   fill_i32(st.p, 1, 1, s);
-  const unsigned grid = std::min<unsigned>(grid_for(n, 256), 1024);
+  const unsigned grid = std::min<unsigned>(grid_for(n, 256), 2048);
   int64_t reached = 1;
   int32_t d = 0;
   // batches of R rounds (R even, non-decreasing: the frontier is in list0 after

@@ -662,6 +662,15 @@ pcamg_status pcamg_bench_copy(int64_t bytes, int32_t reps, void* stream, double*
   });
 }
 
+pcamg_status pcamg_bench_gemm(int32_t p, int32_t q, int32_t r, int32_t prec, int32_t reps, void* stream,
+                              double* ms) {
+  return guarded_s(as_stream(stream), [&] {
+    require(p >= 1 && q >= 1 && r >= 1 && reps >= 1 && ms, PCAMG_EINVAL, "bad argument");
+    require(prec == PCAMG_PREC_F64 || prec == PCAMG_PREC_F32, PCAMG_EINVAL, "prec must be 0 (FP64) or 1 (FP32)");
+    *ms = bench_gemm(p, q, r, prec, reps, as_stream(stream));
+  });
+}
+
 pcamg_status pcamg_initial_error(pcamg_ctx* c, double* e) {
   return guarded_s(c ? c->s : nullptr, [&] {
     require(c && e, PCAMG_EINVAL, "null argument");

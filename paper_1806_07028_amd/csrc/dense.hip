@@ -378,7 +378,7 @@ void dense_gs_sweep(int32_t n, const T* Ad, const T* dinv, T* X, T* G, bool forw
 
 // Levels of at most DENSE_GS_MAX_N rows with more than one colour per
 // DENSE_GS_ROWS_PER_COLOUR rows take dense_gs_sweep in the build.
-constexpr int32_t DENSE_GS_MAX_N = 4096;
+constexpr int32_t DENSE_GS_MAX_N = 8192;
 constexpr int32_t DENSE_GS_ROWS_PER_COLOUR = 8;
 
 inline dim3 rows_grid(int32_t ncols, int32_t rows) { return dim3((unsigned)((ncols + 255) / 256), (unsigned)rows); }
@@ -501,5 +501,46 @@ void dense_bottom_up(Hierarchy& H, int d, int gamma, T* C, hipStream_t s) {
 
 template void dense_bottom_up<double>(Hierarchy&, int, int, double*, hipStream_t);
 template void dense_bottom_up<float>(Hierarchy&, int, int, float*, hipStream_t);
+
+namespace {
+// deterministic operand values in [-1, 1)
+template <typename T>
+__global__ void gemm_fill_kernel(size_t n, uint32_t salt, T* __restrict__ a) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t h = (uint32_t)i * 2654435761u ^ salt;
+  h ^= h >> 15;
+  h *= 2246822519u;
+  h ^= h >> 13;
+  a[i] = (T)((double)(h >> 8) * (1.0 / 8388608.0) - 1.0);
+}
+
+template <typename T>
+double bench_gemm_t(int32_t p, int32_t q, int32_t r, int reps, hipStream_t s) {
+  DVec<T> Q((size_t)p * q), R((size_t)q * r), P((size_t)p * r);
+  gemm_fill_kernel<T><<<(unsigned)(((size_t)p * q + 255) / 256), 256, 0, s>>>((size_t)p * q, 1u, Q.p);
+  PCAMG_LAUNCHED();
+  gemm_fill_kernel<T><<<(unsigned)(((size_t)q * r + 255) / 256), 256, 0, s>>>((size_t)q * r, 2u, R.p);
+  PCAMG_LAUNCHED();
+  gemm_rows<T>(p, q, r, (T)1, Q.p, R.p, (T)0, P.p, s);  // warm-up
+  hipEvent_t e0, e1;
+  PCAMG_HIP(hipEventCreate(&e0));
+  PCAMG_HIP(hipEventCreate(&e1));
+  float t = 0.0f;
+  hipError_t err = hipEventRecord(e0, s);
+  for (int k = 0; k < reps && err == hipSuccess; ++k) gemm_rows<T>(p, q, r, (T)1, Q.p, R.p, (T)0, P.p, s);
+  if (err == hipSuccess) err = hipEventRecord(e1, s);
+  if (err == hipSuccess) err = hipEventSynchronize(e1);
+  if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  PCAMG_HIP(err);
+  return t;
+}
+}  // namespace
+
+double bench_gemm(int32_t p, int32_t q, int32_t r, int prec, int reps, hipStream_t s) {
+  return prec == PCAMG_PREC_F32 ? bench_gemm_t<float>(p, q, r, reps, s) : bench_gemm_t<double>(p, q, r, reps, s);
+}
 
 }  // namespace pcamg

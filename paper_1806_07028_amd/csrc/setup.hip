@@ -1194,9 +1194,27 @@ __global__ void __launch_bounds__(LONG_BLOCK)
       start = t == a || keys[t - 1] != keys[t];
       J = (int32_t)(uint32_t)keys[t];
       if (start && rpc) {
-        for (int64_t u = t; u < b && keys[u] == keys[t]; ++u) {
-          const uint32_t x = perm[u];
-          acc = graph_mode ? acc + tv[x] : fma(tv[x], tp[x], acc);
+        // the run's terms in order, eight loads in flight at a time (keys
+        // are sorted: once a key differs the run has ended)
+        constexpr int U = 8;
+        const uint64_t kt = keys[t];
+        for (int64_t u = t;; u += U) {
+          bool in[U];
+          uint32_t xs[U];
+          double v[U], pv[U];
+#pragma unroll
+          for (int j = 0; j < U; ++j) in[j] = u + j < b && keys[u + j] == kt;
+#pragma unroll
+          for (int j = 0; j < U; ++j) xs[j] = in[j] ? perm[u + j] : 0u;
+#pragma unroll
+          for (int j = 0; j < U; ++j) {
+            v[j] = in[j] ? tv[xs[j]] : 0.0;
+            pv[j] = in[j] && !graph_mode ? tp[xs[j]] : 0.0;
+          }
+#pragma unroll
+          for (int j = 0; j < U; ++j)
+            if (in[j]) acc = graph_mode ? acc + v[j] : fma(v[j], pv[j], acc);
+          if (!in[U - 1]) break;
         }
       }
     }

@@ -1382,11 +1382,13 @@ void bench_level(pcamg_ctx* c, int kind, int prec, int reps, int64_t flush_bytes
       for (int k = 0; k < A.ncol; ++k) {
         if (prec == PCAMG_PREC_F32) smooth_colour(A, k, b32.p, x32.p, s);
         else smooth_colour(A, k, b.p, x.p, s);
-        // launches made: one per non-empty row range (long rows, then the rest)
-        if (A.sell() || A.long_min == 0 || (prec == PCAMG_PREC_F32 && A.ell_w > 0))
-          nl += A.coff[k + 1] > A.coff[k];
-        else
-          nl += (A.lend[k] > A.coff[k]) + (A.coff[k + 1] > A.lend[k]);
+        // launches made: one per non-empty colour (long and other rows in one
+        // launch), two when both are present and the rows take single lanes
+        const int32_t r0 = A.coff[k], r1 = A.coff[k + 1];
+        const int32_t rl = A.long_min > 0 && !A.sell() ? A.lend[k] : r0;
+        const bool split = A.long_min > 0 && !A.sell() && !(prec == PCAMG_PREC_F32 && A.ell_w > 0) && rl > r0 &&
+                           rl < r1 && A.lanes < 4;
+        nl += r1 > r0 ? (split ? 2 : 1) : 0;
       }
     } else {
       if (prec == PCAMG_PREC_F32) level_residual(A, b32.p, x32.p, r32.p, s);

@@ -238,5 +238,8 @@ void bench_smoother(pcamg_ctx* c, int prec, int sweeps, double* ms, int64_t* lau
 void bench_level(pcamg_ctx* c, int kind, int prec, int reps, int64_t flush_bytes, double* ms, int64_t* launches,
                  double* bytes);
 double bench_copy(int64_t nbytes, int reps, hipStream_t s);
+// reps products P = Q R (p x q times q x r, row-major) by the dense operators'
+// MFMA GEMM in FP64 or FP32 (prec), timed with HIP events; milliseconds
+double bench_gemm(int32_t p, int32_t q, int32_t r, int prec, int reps, hipStream_t s);
 void solve(pcamg_ctx* c, double* x_nat, pcamg_stats* st);
 }  // namespace pcamg

@@ -340,7 +340,7 @@ void tail_cycle32(const Hierarchy& H, const float* b, float* x, int gamma, hipSt
 // y = C b for a column-major n x n matrix: the columns are split into chunks
 // of DENSE_CHUNK; block (row tile, chunk) writes the partial sums of its chunk
 // (fma chain in column order), and a second pass adds the chunks in order.
-constexpr int DENSE_CHUNK = 128;
+constexpr int DENSE_CHUNK = 64;
 template <typename T>
 __global__ void __launch_bounds__(256) dense_part_kernel(int32_t n, const T* __restrict__ C, const T* __restrict__ b,
                                                          T* __restrict__ part) {
