@@ -104,6 +104,33 @@ def gemm_rate(p: int, q: int, r: int, prec: int, reps: int = 10) -> dict:
             "ms_per_product": round(ms.value / reps, 4)}
 
 
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "powerlaw_4m_f64_finest_sweep_roofline.md")
+
+
+def traffic_record():
+    """HBM bytes per launch of the finest-level sweep from the committed
+    rocprofv3 counter record, or None when the kernel sources have changed
+    since the counters were taken (or the record is missing)."""
+    import hashlib
+    import re
+    try:
+        txt = open(TRAFFIC_RECORD).read()
+    except OSError:
+        return None
+    per = re.search(r"traffic_bytes_per_launch: `(\d+)`", txt)
+    dig = re.search(r"source_digest: `([0-9a-f]+)`", txt)
+    srcs = re.search(r"sources: (.*)", txt)
+    if not (per and dig and srcs):
+        return None
+    h = hashlib.sha256()
+    for f in re.findall(r"`([^`]+)`", srcs.group(1)):
+        try:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        except OSError:
+            return None
+    return int(per.group(1)) if h.hexdigest()[:16] == dig.group(1) else None
+
+
 def host_relres(g, b, x) -> float:
     import numpy as np
     import scipy.sparse as sp
@@ -203,7 +230,7 @@ def powerlaw_headline(args):
     copy = copy_ceiling()
     s.close()
     roofline = {"bound": "hbm", "achieved": gs_roof["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": gs_roof["frac"], "traffic": None,
+                "frac": gs_roof["frac"], "traffic": traffic_record() if prec == "f64" else None,
                 "kernel": f"finest-level forward Gauss-Seidel sweep in {prec.upper()} ({colours[0]} colour passes, "
                           "one launch each: gs_fused_kernel, a workgroup per hub row of 256+ entries and 4 lanes "
                           "per other row; gs_long_kernel for colours of hub rows only), 1 GiB read between timed "

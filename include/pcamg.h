@@ -119,6 +119,8 @@ typedef struct {
                               vector before a build always keeps the chain.  0 = off (256: above
                               the longest rows of grid hierarchies) */
   int32_t v_dense_max_n;   /* V-cycles: the cycle of the first level of at most this many vertices
+                              (or of at most twice as many, when it has more than one colour per
+                              16 rows: the hub levels of power-law hierarchies)
                               below the finest (at or above the single-workgroup tail) is applied
                               by the level above as one precomputed dense operator (equal up to
                               rounding order; built level by level from the coarsest on first use

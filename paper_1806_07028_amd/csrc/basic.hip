@@ -464,6 +464,33 @@ constexpr int32_t JP_PUSH_LANE_MAX = 32;
 // taken a vertex per wavefront, longer ones a vertex per lane.
 constexpr int32_t JP_WAVE_MODE_PER_WAVE = 4;
 
+// One round over the worklist of all uncoloured vertices (levels without
+// hub rows: a few dozen rounds of many vertices each, where the rounds of
+// jp_wake_kernel cost more in wake-ups than they save); the ones still
+// uncoloured go to the next list (in any order: the colouring does not
+// depend on it).
+__global__ void __launch_bounds__(256)
+    jp_list_kernel(const int32_t* __restrict__ cnt_in, const int32_t* __restrict__ in, int32_t* __restrict__ cnt_out,
+                   int32_t* __restrict__ out, const int32_t* __restrict__ hrp, const int32_t* __restrict__ hci,
+                   int32_t* colour, int32_t* __restrict__ cur, unsigned long long* __restrict__ usedm) {
+  const int32_t m = *cnt_in;
+  const int32_t stride = gridDim.x * blockDim.x;
+  for (int32_t base = blockIdx.x * blockDim.x; base < m; base += stride) {
+    const int32_t t = base + threadIdx.x;
+    const int32_t v = t < m ? in[t] : -1;
+    const bool left =
+        v >= 0 && __atomic_load_n(&colour[v], __ATOMIC_RELAXED) < 0 && jp_try_hc(v, hrp, hci, colour, cur, usedm);
+    const unsigned long long bal = __ballot(left);
+    if (!bal) continue;
+    const int lane = threadIdx.x & 63;
+    const int lead = __ffsll((long long)bal) - 1;
+    int32_t at = 0;
+    if (lane == lead) at = atomicAdd(cnt_out, __popcll(bal));
+    at = __shfl(at, lead, 64);
+    if (left) out[at + __popcll(bal & ((1ull << lane) - 1ull))] = v;
+  }
+}
+
 // One data-driven round: try the vertices of the worklist; every vertex that
 // takes its colour here wakes its uncoloured neighbours (all of lower
 // priority) for round `next`, each at most once per round (stamp[w] = the
@@ -523,15 +550,43 @@ __global__ void __launch_bounds__(256)
       const bool got = !jp_try_wave(__shfl(v, j, 64), hrp, hci, colour, cur, usedm, bm, lane);
       if (lane == j) now = got;
     }
-    // short rows: each lane pushes its own row, one entry per step; the
-    // others a row at a time by the wavefront (or as hubs)
+    // short rows: each lane pushes its own row, four entries per step (their
+    // colour loads and stamp atomics in flight together, one append for
+    // the four); the others a row at a time by the wavefront (or as hubs)
     const int32_t pk0 = now ? rp[v] : 0;
     const int32_t plen = now ? rp[v + 1] - pk0 : 0;
     const bool mine = now && plen <= JP_PUSH_LANE_MAX;
     const int32_t span = wave_max_len(mine ? plen : 0);
-    for (int32_t j = 0; j < span; ++j) {
-      const bool act = mine && j < plen;
-      jp_wake_push(act, act ? ci[pk0 + j] : 0, colour, stamp, next, cnt_out, out, lane);
+    for (int32_t j = 0; j < span; j += 4) {
+      int32_t w[4];
+      bool act[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        act[u] = mine && j + u < plen;
+        w[u] = act[u] ? ci[pk0 + j + u] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) act[u] = act[u] && __atomic_load_n(&colour[w[u]], __ATOMIC_RELAXED) < 0;
+      int32_t old[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) old[u] = act[u] ? atomicMax(&stamp[w[u]], next) : next;
+      unsigned long long pb[4];
+      int32_t tot = 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        pb[u] = __ballot(act[u] && old[u] < next);
+        tot += __popcll(pb[u]);
+      }
+      if (!tot) continue;
+      int32_t at = 0;
+      if (lane == 0) at = atomicAdd(cnt_out, tot);
+      at = __shfl(at, 0, 64);
+      const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (pb[u] >> lane & 1ull) out[at + __popcll(pb[u] & below)] = w[u];
+        at += __popcll(pb[u]);
+      }
     }
     unsigned long long bal = __ballot(now && !mine);
     while (bal) {
@@ -655,7 +710,28 @@ int32_t colour_jp(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed
     fill_i32(cnt.p, n, 1, s);
     int32_t pending = n;  // worklist size at the start of the next batch
     int64_t rounds = 0;
-    for (;;) {
+    if (nl == 0) {
+      // no hub rows: rounds over all pending vertices, batches of 8 (R is
+      // even: the survivors are in list0 after each batch)
+      constexpr int RL = 8;
+      for (;;) {
+        const unsigned grid = std::min<unsigned>(grid_for(pending, 256), 2048);
+        for (int r = 0; r < RL; ++r) {
+          const int32_t* in = (r & 1) ? list1.p : list0.p;
+          int32_t* out = (r & 1) ? list0.p : list1.p;
+          jp_list_kernel<<<grid, 256, 0, s>>>(cnt.p + r, in, cnt.p + r + 1, out, hrp.p, hci.p, colour, cur.p,
+                                              (unsigned long long*)usedm.p);
+          PCAMG_LAUNCHED();
+        }
+        rounds += RL;
+        pending = read_scalar(cnt.p + RL, s);
+        if (pending == 0) break;
+        require(rounds <= (int64_t)n + RL, PCAMG_EHIP, "colouring made no progress");
+        jp_carry_kernel<<<1, 64, 0, s>>>(cnt.p, RL);
+        PCAMG_LAUNCHED();
+      }
+    }
+    for (; pending > 0;) {
       // lists grow and shrink within a batch: at least WAKE_MIN_THREADS
       // threads, a grid-stride loop beyond the grid
       const unsigned grid = std::min<unsigned>(grid_for(std::max<int32_t>(pending, WAKE_MIN_THREADS), 256), 2048);

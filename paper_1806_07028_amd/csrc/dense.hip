@@ -298,14 +298,17 @@ __global__ void __launch_bounds__(256) blk_transpose_kernel(int32_t n, const T* 
 // ---------------------------------------------------------------------------
 // Near-dense levels (many colours of a few rows each): a colour pass on all
 // columns is a launch per colour, each summing long rows.  There a sweep is
-// taken instead as a blocked triangular solve on the dense off-diagonal part
-// Ad, in the same row order (the colour order of the level, in which rows of
-// one colour do not touch each other): for row blocks of GS_NB rows in sweep
-// order, G = Ad[b, outside b] X[outside b] as GEMMs on the matrix cores
-// (the rows before the block hold their new values, those after their old
-// ones), then the rows of the block one at a time, each from I - G and the
-// block's current values -- the Gauss-Seidel update of every row, with the
-// sums in another order.
+// taken instead as a recursive blocked triangular solve on the dense
+// off-diagonal part Ad, in the same row order (the colour order of the
+// level, in which rows of one colour do not touch each other).  T (n x n)
+// holds for every row the sum of a_ik x_k over the rows k outside its block:
+// first the side not yet updated in this sweep (the rows after it in a
+// forward sweep, from the old X: one GEMM with the strictly upper part; none
+// from X = 0), then, as the recursion finishes the first half of a range,
+// the GEMM of that half's new values into the second half's rows.  A leaf of
+// GS_NB rows then updates its rows one at a time from T and the block's
+// current values -- the Gauss-Seidel update of every row, with the sums in
+// another order; the GEMMs near the top of the recursion are large.
 // ---------------------------------------------------------------------------
 constexpr int GS_NB = 32;
 
@@ -318,14 +321,24 @@ __global__ void __launch_bounds__(256)
   for (int32_t k = rp[i] + (int32_t)threadIdx.x; k < rp[i + 1]; k += 256) Ad[(size_t)i * n + ci[k]] = av[k];
 }
 
+// Lo[i, k] = Ad[i, k] for k < i, else 0 (Upper: k > i)
+template <typename T, bool Upper>
+__global__ void __launch_bounds__(256) blk_triangle_kernel(int32_t n, const T* __restrict__ Ad, T* __restrict__ Tr) {
+  const int32_t i = (int32_t)blockIdx.y;
+  const int32_t k = (int32_t)(blockIdx.x * 256 + threadIdx.x);
+  if (k >= n) return;
+  const size_t o = (size_t)i * n + k;
+  Tr[o] = (Upper ? k > i : k < i) ? Ad[o] : (T)0;
+}
+
 // The rows r0 .. r0 + nb - 1 of X, one column per thread, in order
-// (forward) or reverse: x_i = (delta(r0 + i, j) - G_i - sum_{k in block,
-// k != i} a_ik x_k) dinv_i with the block's current values, G = the GEMMs'
-// sum over the rows outside the block (none: G = 0); the block of Ad in LDS.
+// (forward) or reverse: x_i = (delta(r0 + i, j) - T_i - sum over the
+// block's rows already updated in this sweep of a_ik x_k) dinv_i; the block
+// of Ad in LDS.
 template <typename T, bool Forward>
 __global__ void __launch_bounds__(256)
     blk_block_gs_kernel(int32_t n, int32_t r0, int32_t nb, const T* __restrict__ Ad, const T* __restrict__ dinv,
-                        const T* __restrict__ G, T* __restrict__ X) {
+                        const T* __restrict__ Tsum, T* __restrict__ X) {
   __shared__ T ab[GS_NB][GS_NB + 1];
   __shared__ T dv[GS_NB];
   for (int e = (int)threadIdx.x; e < GS_NB * GS_NB; e += 256) {
@@ -343,10 +356,10 @@ __global__ void __launch_bounds__(256)
   for (int t = 0; t < GS_NB; ++t) {
     const int i = Forward ? t : GS_NB - 1 - t;
     if (i < nb) {
-      T acc = (r0 + i == j ? (T)1 : (T)0) - (G ? G[(size_t)i * n + j] : (T)0);
+      T acc = (r0 + i == j ? (T)1 : (T)0) - Tsum[(size_t)(r0 + i) * n + j];
 #pragma unroll
       for (int k = 0; k < GS_NB; ++k)
-        if (k != i) acc = fma(-ab[i][k], x[k], acc);
+        if (Forward ? k < i : k > i) acc = fma(-ab[i][k], x[k], acc);
       x[i] = acc * dv[i];
     }
   }
@@ -355,31 +368,60 @@ __global__ void __launch_bounds__(256)
     if (k < nb) X[(size_t)(r0 + k) * n + j] = x[k];
 }
 
-// One sweep on all n columns of X (forward: block rows ascending), from
-// X = 0 when x_zero (no rows after the block to subtract).  G: GS_NB x n.
+// rows [r0, r1) of one sweep, T holding the contributions from outside
 template <typename T>
-void dense_gs_sweep(int32_t n, const T* Ad, const T* dinv, T* X, T* G, bool forward, bool x_zero, hipStream_t s) {
-  const int32_t nbk = (n + GS_NB - 1) / GS_NB;
-  const unsigned cols = (unsigned)((n + 255) / 256);
-  for (int32_t t = 0; t < nbk; ++t) {
-    const int32_t b = forward ? t : nbk - 1 - t;
-    const int32_t r0 = b * GS_NB, r1 = std::min(n, r0 + GS_NB), nb = r1 - r0;
-    const bool left = r0 > 0, right = r1 < n && !x_zero;
-    if (left) gemm_strided<T>(nb, r0, n, (T)1, Ad + (size_t)r0 * n, n, X, n, (T)0, G, n, s);
-    if (right)
-      gemm_strided<T>(nb, n - r1, n, (T)1, Ad + (size_t)r0 * n + r1, n, X + (size_t)r1 * n, n, left ? (T)1 : (T)0, G,
-                      n, s);
-    const T* g = left || right ? G : nullptr;
-    if (forward) blk_block_gs_kernel<T, true><<<cols, 256, 0, s>>>(n, r0, nb, Ad, dinv, g, X);
-    else blk_block_gs_kernel<T, false><<<cols, 256, 0, s>>>(n, r0, nb, Ad, dinv, g, X);
+void dense_gs_range(int32_t n, int32_t r0, int32_t r1, const T* Ad, const T* dinv, T* X, T* Tsum, bool forward,
+                    hipStream_t s) {
+  const int32_t len = r1 - r0;
+  if (len <= GS_NB) {
+    const unsigned cols = (unsigned)((n + 255) / 256);
+    if (forward) blk_block_gs_kernel<T, true><<<cols, 256, 0, s>>>(n, r0, len, Ad, dinv, Tsum, X);
+    else blk_block_gs_kernel<T, false><<<cols, 256, 0, s>>>(n, r0, len, Ad, dinv, Tsum, X);
     PCAMG_LAUNCHED();
+    return;
   }
+  const int32_t mid = r0 + ((len / 2 + GS_NB - 1) / GS_NB) * GS_NB;  // blocks stay GS_NB-aligned
+  if (forward) {
+    dense_gs_range<T>(n, r0, mid, Ad, dinv, X, Tsum, true, s);
+    gemm_strided<T>(r1 - mid, mid - r0, n, (T)1, Ad + (size_t)mid * n + r0, n, X + (size_t)r0 * n, n, (T)1,
+                    Tsum + (size_t)mid * n, n, s);
+    dense_gs_range<T>(n, mid, r1, Ad, dinv, X, Tsum, true, s);
+  } else {
+    dense_gs_range<T>(n, mid, r1, Ad, dinv, X, Tsum, false, s);
+    gemm_strided<T>(mid - r0, r1 - mid, n, (T)1, Ad + (size_t)r0 * n + mid, n, X + (size_t)mid * n, n, (T)1,
+                    Tsum + (size_t)r0 * n, n, s);
+    dense_gs_range<T>(n, r0, mid, Ad, dinv, X, Tsum, false, s);
+  }
+}
+
+// One sweep on all n columns of X (forward: rows ascending).  old_side: the
+// strictly upper (forward) or lower (backward) part of Ad, or null when X =
+// 0 on entry.  Tsum: n x n scratch.
+template <typename T>
+void dense_gs_sweep(int32_t n, const T* Ad, const T* old_side, const T* dinv, T* X, T* Tsum, bool forward,
+                    hipStream_t s) {
+  if (old_side) gemm_rows<T>(n, n, n, (T)1, old_side, X, (T)0, Tsum, s);
+  else PCAMG_HIP(hipMemsetAsync(Tsum, 0, (size_t)n * n * sizeof(T), s));  // all-zero bits: +0
+  dense_gs_range<T>(n, 0, n, Ad, dinv, X, Tsum, forward, s);
+}
+
+// R[i, j] = delta_ij - (d_i X[i, j] + R[i, j]) with R = Ad X on entry: the
+// residual of the identity right-hand side from the GEMM of the
+// off-diagonal part.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    blk_resid_dense_kernel(int32_t n, const T* __restrict__ d, const T* __restrict__ X, T* __restrict__ R) {
+  const int32_t i = (int32_t)blockIdx.y;
+  const int32_t j = (int32_t)(blockIdx.x * 256 + threadIdx.x);
+  if (j >= n) return;
+  const size_t o = (size_t)i * n + j;
+  R[o] = (i == j ? (T)1 : (T)0) - fma(d[i], X[o], R[o]);
 }
 
 // Levels of at most DENSE_GS_MAX_N rows with more than one colour per
 // DENSE_GS_ROWS_PER_COLOUR rows take dense_gs_sweep in the build.
 constexpr int32_t DENSE_GS_MAX_N = 8192;
-constexpr int32_t DENSE_GS_ROWS_PER_COLOUR = 8;
+constexpr int32_t DENSE_GS_ROWS_PER_COLOUR = 16;
 
 inline dim3 rows_grid(int32_t ncols, int32_t rows) { return dim3((unsigned)((ncols + 255) / 256), (unsigned)rows); }
 
@@ -456,14 +498,17 @@ void dense_bottom_up(Hierarchy& H, int d, int gamma, T* C, hipStream_t s) {
     const T* dinv = LevelOf<T>::dinv(A);
     // near-dense levels: blocked dense sweeps instead of a launch per colour
     const bool dense_gs = n <= DENSE_GS_MAX_N && (int64_t)A.ncol * DENSE_GS_ROWS_PER_COLOUR > n;
-    DVec<T> Ad, G;
+    DVec<T> Ad, Lo, Ts;
     if (dense_gs) {
       Ad.resize((size_t)n * n);
-      G.resize((size_t)GS_NB * n);
+      Lo.resize((size_t)n * n);
+      Ts.resize((size_t)n * n);
       PCAMG_HIP(hipMemsetAsync(Ad.p, 0, Ad.bytes(), s));
       blk_densify_kernel<T><<<n, 256, 0, s>>>(n, A.rp.p, A.ci.p, av, Ad.p);
       PCAMG_LAUNCHED();
-      dense_gs_sweep<T>(n, Ad.p, dinv, X.p, G.p, true, true, s);
+      blk_triangle_kernel<T, false><<<rows_grid(n, n), 256, 0, s>>>(n, Ad.p, Lo.p);
+      PCAMG_LAUNCHED();
+      dense_gs_sweep<T>(n, Ad.p, nullptr, dinv, X.p, Ts.p, true, s);  // from X = 0
     }
     for (int k = 0; k < (dense_gs ? 0 : A.ncol); ++k) {
       const int32_t r0 = A.coff[k], r1 = A.coff[k + 1];
@@ -472,14 +517,19 @@ void dense_bottom_up(Hierarchy& H, int d, int gamma, T* C, hipStream_t s) {
                                                                                            av, dinv, X.p);
       PCAMG_LAUNCHED();
     }
-    blk_apply_kernel<T><<<rows_grid(n, n), 256, 0, s>>>(n, A.rp.p, A.ci.p, av, LevelOf<T>::d(A), X.p, R.p, 1);
+    if (dense_gs) {  // R = I - A X with the off-diagonal product on the matrix cores
+      gemm_rows<T>(n, n, n, (T)1, Ad.p, X.p, (T)0, R.p, s);
+      blk_resid_dense_kernel<T><<<rows_grid(n, n), 256, 0, s>>>(n, LevelOf<T>::d(A), X.p, R.p);
+    } else {
+      blk_apply_kernel<T><<<rows_grid(n, n), 256, 0, s>>>(n, A.rp.p, A.ci.p, av, LevelOf<T>::d(A), X.p, R.p, 1);
+    }
     PCAMG_LAUNCHED();
     blk_restrict_kernel<T><<<rows_grid(n, m), 256, 0, s>>>(n, Tr.moff.p, Tr.mem.p, LevelOf<T>::pval(Tr), R.p, Bc.p);
     PCAMG_LAUNCHED();
     gemm_rows<T>(m, m, n, (T)1, Cl, Bc.p, (T)0, Xc.p, s);
     blk_prolong_kernel<T><<<rows_grid(n, n), 256, 0, s>>>(n, Tr.agg.p, LevelOf<T>::pval(Tr), Xc.p, X.p);
     PCAMG_LAUNCHED();
-    if (dense_gs) dense_gs_sweep<T>(n, Ad.p, dinv, X.p, G.p, false, false, s);
+    if (dense_gs) dense_gs_sweep<T>(n, Ad.p, Lo.p, dinv, X.p, Ts.p, false, s);
     for (int k = dense_gs ? -1 : A.ncol - 1; k >= 0; --k) {
       const int32_t r0 = A.coff[k], r1 = A.coff[k + 1];
       if (r1 <= r0) continue;

@@ -33,6 +33,10 @@ constexpr double LEARNED_FALLBACK_CONVR = 0.9;
 // Levels at most this size are not timed by the lanes autotuner (they run in
 // the tail kernel by default).
 constexpr int32_t TUNE_MIN_N = 2048;
+// Rows per colour below which a level of up to twice v_dense_max_n rows
+// still joins the V-cycle's dense operator.
+constexpr int32_t V_DENSE_ROWS_PER_COLOUR = 16;
+
 // A level of at least block_sweep_min_colours colours (a parameter), with at
 // most this many rows per colour on average, runs its sweeps in one
 // single-workgroup launch.
@@ -679,6 +683,12 @@ static std::unique_ptr<Hierarchy> assemble_hierarchy(pcamg_ctx* c, std::unique_p
     // V-cycles: the same from the first level of at most v_dense_max_n
     if (c->P.v_dense_max_n > 0) {
       int dv = first_at_most(c->P.v_dense_max_n);
+      // near-dense levels of up to twice the limit join (more than one colour
+      // per V_DENSE_ROWS_PER_COLOUR rows: a launch per colour of a few hub
+      // rows each in every sweep, while their dense build is cheap)
+      while (dv > 1 && H->lv[dv - 1].A->n <= 2 * (int64_t)c->P.v_dense_max_n &&
+             (int64_t)H->lv[dv - 1].A->ncol * V_DENSE_ROWS_PER_COLOUR > H->lv[dv - 1].A->n)
+        --dv;
       if (H->tail_start >= 0) dv = std::min(dv, H->tail_start);
       if (dv >= 1 && nl - dv >= 2) H->dense_v_start = dv;
     }

@@ -307,3 +307,44 @@ def test_wake_rounds_equal_greedy(oracle, case):
         got, rounds = wake_rounds(n, rp, ci, key, np.random.default_rng(seed), stale)
         assert np.array_equal(got, ref), (seed, stale)
         assert rounds > 1
+
+
+def list_rounds(n, rp, ci, key, rng, stale):
+    """Jones-Plassmann rounds over every pending vertex (the library's path
+    for levels without hub rows), with a resumable cursor per vertex; in a
+    random order, with reads of same-round colours missed at random."""
+    higher = lambda u, v: (key[u], u) > (key[v], v)
+    hl = [[u for u in ci[rp[v]:rp[v + 1]] if higher(u, v)] for v in range(n)]
+    colour = -np.ones(n, int)
+    cur = [0] * n
+    pending = list(range(n))
+    rounds = 0
+    while pending:
+        rounds += 1
+        assert rounds <= n
+        done_now = set()
+        seen = lambda u: colour[u] >= 0 and not (u in done_now and rng.random() < stale)
+        left = []
+        for v in rng.permutation(pending):
+            while cur[v] < len(hl[v]) and seen(hl[v][cur[v]]):
+                cur[v] += 1
+            if cur[v] < len(hl[v]):
+                left.append(v)
+                continue
+            used = {colour[u] for u in hl[v]}
+            colour[v] = next(c for c in range(n + 1) if c not in used)
+            done_now.add(v)
+        pending = left
+    return colour
+
+
+@pytest.mark.parametrize("case", ["grid", "rgg"])
+def test_list_rounds_equal_greedy(oracle, case):
+    """The list rounds of levels without hub rows give the greedy first-fit in
+    priority order as well."""
+    n, rp, ci, w = I.grid2d(20, 20) if case == "grid" else I.rgg(600, 3)
+    deg = np.diff(rp)
+    key = [oracle.colour_key(0xC010, 1, v, int(deg[v])) for v in range(n)]
+    ref, _ = oracle.colour_greedy(n, rp, ci, 0xC010, 1)
+    for seed, stale in ((0, 0.0), (1, 0.5)):
+        assert np.array_equal(list_rounds(n, rp, ci, key, np.random.default_rng(seed), stale), ref)
