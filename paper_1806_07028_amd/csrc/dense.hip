@@ -34,7 +34,8 @@ namespace {
 // wavefront a (BM/2) x (BN/2) block of 16 x 16 MFMA tiles
 // (v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64, 16 x 4 times 4 x 16 per
 // instruction).  K advances in slices of 16 staged through LDS, zero-filled
-// past the matrix edges.  Lane l of a 16 x 16 x 4 product supplies A[l % 16][l
+// past the matrix edges; each thread loads the next slice into registers
+// while the matrix cores work on the current one.  Lane l of a 16 x 16 x 4 product supplies A[l % 16][l
 // / 16] and B[l / 16][l % 16]; its four results v = 0..3 are D[i][l % 16] with
 // i = 4 (l / 16) + v for the FP32 instruction and i = l / 16 + 4 v for the FP64
 // one (both layouts checked on the device).
@@ -49,7 +50,6 @@ struct Mfma;
 template <>
 struct Mfma<float> {
   using acc_t = f32x4_t;
-  static constexpr int BM = 128, BN = 128;
   static __device__ __forceinline__ acc_t step(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
@@ -58,19 +58,19 @@ struct Mfma<float> {
 template <>
 struct Mfma<double> {
   using acc_t = f64x4_t;
-  static constexpr int BM = 64, BN = 64;
   static __device__ __forceinline__ acc_t step(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ int row(int lk, int v) { return lk + 4 * v; }
 };
 
-template <typename T>
+template <typename T, int BM, int BN>
 __global__ void __launch_bounds__(256)
     gemm_mfma_kernel(int32_t p, int32_t q, int32_t r, T alpha, const T* __restrict__ Q, int32_t ldq,
                      const T* __restrict__ R, int32_t ldr, T beta, T* __restrict__ P, int32_t ldp) {
-  constexpr int BM = Mfma<T>::BM, BN = Mfma<T>::BN, BK = 16;
+  constexpr int BK = 16;
   constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
+  constexpr int LA = BM * BK / 256, LB = BK * BN / 256;  // elements each thread stages per slice
   __shared__ T As[BK][BM + 4];  // k-major: a lane's A operand is As[k][row]
   __shared__ T Bs[BK][BN + 4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -82,18 +82,37 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int b = 0; b < FN; ++b) acc[a][b] = typename Mfma<T>::acc_t{0, 0, 0, 0};
   const int lr = lane & 15, lk = lane >> 4;
-  for (int32_t k0 = 0; k0 < q; k0 += BK) {
-    for (int e = tid; e < BM * BK; e += 256) {
-      const int i = e / BK, k = e % BK;
+  // the next slice's operands are loaded into registers while the matrix
+  // cores work on the current one from LDS
+  T ra[LA], rb[LB];
+  auto load = [&](int32_t k0) {
+#pragma unroll
+    for (int u = 0; u < LA; ++u) {
+      const int e = tid + 256 * u, i = e / BK, k = e % BK;
       const int32_t gi = row0 + i, gk = k0 + k;
-      As[k][i] = (gi < p && gk < q) ? Q[(size_t)gi * ldq + gk] : (T)0;
+      ra[u] = (gi < p && gk < q) ? Q[(size_t)gi * ldq + gk] : (T)0;
     }
-    for (int e = tid; e < BK * BN; e += 256) {
-      const int k = e / BN, j = e % BN;
+#pragma unroll
+    for (int u = 0; u < LB; ++u) {
+      const int e = tid + 256 * u, k = e / BN, j = e % BN;
       const int32_t gk = k0 + k, gj = col0 + j;
-      Bs[k][j] = (gk < q && gj < r) ? R[(size_t)gk * ldr + gj] : (T)0;
+      rb[u] = (gk < q && gj < r) ? R[(size_t)gk * ldr + gj] : (T)0;
+    }
+  };
+  load(0);
+  for (int32_t k0 = 0; k0 < q; k0 += BK) {
+#pragma unroll
+    for (int u = 0; u < LA; ++u) {
+      const int e = tid + 256 * u;
+      As[e % BK][e / BK] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < LB; ++u) {
+      const int e = tid + 256 * u;
+      Bs[e / BN][e % BN] = rb[u];
     }
     __syncthreads();
+    if (k0 + BK < q) load(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       T av[FM], bv[FN];
@@ -124,13 +143,20 @@ __global__ void __launch_bounds__(256)
 }
 
 // Row-major P = alpha Q R + beta P (p x q times q x r), each operand with its
-// own row stride (ldq, ldr, ldp elements).
+// own row stride (ldq, ldr, ldp elements).  128 x 128 tiles when both sides
+// fill them (fewer LDS round trips per product), 64 x 64 otherwise; every
+// entry is the same fma sequence over K either way.
 template <typename T>
 void gemm_strided(int32_t p, int32_t q, int32_t r, T alpha, const T* Q, int32_t ldq, const T* R, int32_t ldr,
                   T beta, T* P, int32_t ldp, hipStream_t s) {
   if (p <= 0 || r <= 0) return;
-  const dim3 grid((unsigned)((r + Mfma<T>::BN - 1) / Mfma<T>::BN), (unsigned)((p + Mfma<T>::BM - 1) / Mfma<T>::BM));
-  gemm_mfma_kernel<T><<<grid, 256, 0, s>>>(p, q, r, alpha, Q, ldq, R, ldr, beta, P, ldp);
+  if (p >= 128 && r >= 128) {
+    const dim3 grid((unsigned)((r + 127) / 128), (unsigned)((p + 127) / 128));
+    gemm_mfma_kernel<T, 128, 128><<<grid, 256, 0, s>>>(p, q, r, alpha, Q, ldq, R, ldr, beta, P, ldp);
+  } else {
+    const dim3 grid((unsigned)((r + 63) / 64), (unsigned)((p + 63) / 64));
+    gemm_mfma_kernel<T, 64, 64><<<grid, 256, 0, s>>>(p, q, r, alpha, Q, ldq, R, ldr, beta, P, ldp);
+  }
   PCAMG_LAUNCHED();
 }
 
