@@ -506,12 +506,14 @@ __global__ void __launch_bounds__(256)
 // by the wavefront too, and a short worklist is taken a vertex per wavefront.
 __global__ void __launch_bounds__(256)
     jp_wake_kernel(const int32_t* __restrict__ cnt_in, const int32_t* __restrict__ in, int32_t* __restrict__ cnt_out,
-                   int32_t* __restrict__ out, int32_t next, const int32_t* __restrict__ rp,
+                   int32_t* __restrict__ out, const int32_t* __restrict__ rbase, int32_t r1,
+                   const int32_t* __restrict__ rp,
                    const int32_t* __restrict__ ci, const int32_t* __restrict__ hrp, const int32_t* __restrict__ hci,
                    int32_t* colour, int32_t* __restrict__ cur, unsigned long long* __restrict__ usedm,
                    int32_t* __restrict__ stamp, int32_t* __restrict__ cnt_hubs, int32_t* __restrict__ hubs) {
   __shared__ unsigned long long bms[4][JP_BM_WORDS];
   const int32_t m = *cnt_in;
+  const int32_t next = *rbase + r1;  // the round being filled
   const int lane = (int)(threadIdx.x & 63);
   unsigned long long* bm = bms[threadIdx.x >> 6];
   // the wavefront pushes the row of u, or lists it as a hub
@@ -603,9 +605,10 @@ __global__ void __launch_bounds__(256)
 __global__ void __launch_bounds__(256)
     jp_push_long_kernel(const int32_t* __restrict__ cnt_hubs, const int32_t* __restrict__ hubs,
                         const int32_t* __restrict__ rp, const int32_t* __restrict__ ci, const int32_t* colour,
-                        int32_t* __restrict__ stamp, int32_t next, int32_t* __restrict__ cnt_out,
-                        int32_t* __restrict__ out) {
+                        int32_t* __restrict__ stamp, const int32_t* __restrict__ rbase, int32_t r1,
+                        int32_t* __restrict__ cnt_out, int32_t* __restrict__ out) {
   const int32_t m = *cnt_hubs;
+  const int32_t next = *rbase + r1;
   const int lane = (int)(threadIdx.x & 63);
   for (int32_t h = (int32_t)blockIdx.y; h < m; h += (int32_t)gridDim.y) {
     const int32_t u = hubs[h];
@@ -618,6 +621,16 @@ __global__ void __launch_bounds__(256)
 }
 
 // counts of the next batch: cnt[0] = cnt[last], the others zero
+// The same for a batch of data-driven rounds: also advances the round base
+// and clears the hub counts of the batch.
+__global__ void jp_wake_carry_kernel(int32_t* cnt, int32_t last, int32_t* rbase, int32_t* cnt_hubs) {
+  const int32_t c = cnt[last];
+  __syncthreads();
+  for (int32_t i = threadIdx.x; i <= last; i += blockDim.x) cnt[i] = i == 0 ? c : 0;
+  for (int32_t i = threadIdx.x; i < last; i += blockDim.x) cnt_hubs[i] = 0;
+  if (threadIdx.x == 0) *rbase += last;
+}
+
 __global__ void jp_carry_kernel(int32_t* cnt, int32_t last) {
   const int32_t c = cnt[last];
   __syncthreads();
@@ -645,6 +658,25 @@ constexpr int64_t JP_SEQ_DEG = 48;
 // and the grid of its hub pushes (blocks per row x rows at a time).
 constexpr int32_t WAKE_MIN_THREADS = 1 << 19;
 constexpr unsigned PUSH_GRID_X = 16, PUSH_GRID_Y = 16;
+
+// A non-blocking stream of this host thread for capturing launch sequences
+// (capture is not allowed on the legacy stream); kept for the thread's life.
+hipStream_t capture_stream() {
+  thread_local hipStream_t cs = nullptr;
+  if (!cs) PCAMG_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  return cs;
+}
+
+// An instantiated graph, destroyed with its scope.
+struct GraphExec {
+  hipGraphExec_t e = nullptr;
+  GraphExec() = default;
+  GraphExec(const GraphExec&) = delete;
+  GraphExec& operator=(const GraphExec&) = delete;
+  ~GraphExec() {
+    if (e) (void)hipGraphExecDestroy(e);
+  }
+};
 
 int32_t max_row_len(int32_t n, const int32_t* rp, hipStream_t s) {
   DVec<int32_t> mx(1);
@@ -711,48 +743,92 @@ int32_t colour_jp(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed
     int32_t pending = n;  // worklist size at the start of the next batch
     int64_t rounds = 0;
     if (nl == 0) {
-      // no hub rows: rounds over all pending vertices, batches of 8 (R is
-      // even: the survivors are in list0 after each batch)
+      // no hub rows: rounds over all pending vertices in batches of RL (RL is
+      // even: the survivors are in list0 after each batch), one captured
+      // graph replayed per batch as below
       constexpr int RL = 8;
-      for (;;) {
-        const unsigned grid = std::min<unsigned>(grid_for(pending, 256), 2048);
-        for (int r = 0; r < RL; ++r) {
-          const int32_t* in = (r & 1) ? list1.p : list0.p;
-          int32_t* out = (r & 1) ? list0.p : list1.p;
-          jp_list_kernel<<<grid, 256, 0, s>>>(cnt.p + r, in, cnt.p + r + 1, out, hrp.p, hci.p, colour, cur.p,
-                                              (unsigned long long*)usedm.p);
+      const unsigned grid = std::min<unsigned>(grid_for(n, 256), 2048);
+      GraphExec ge;
+      {
+        hipStream_t cs = capture_stream();
+        PCAMG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        try {
+          for (int r = 0; r < RL; ++r) {
+            const int32_t* in = (r & 1) ? list1.p : list0.p;
+            int32_t* out = (r & 1) ? list0.p : list1.p;
+            jp_list_kernel<<<grid, 256, 0, cs>>>(cnt.p + r, in, cnt.p + r + 1, out, hrp.p, hci.p, colour, cur.p,
+                                                 (unsigned long long*)usedm.p);
+            PCAMG_LAUNCHED();
+          }
+          jp_carry_kernel<<<1, 64, 0, cs>>>(cnt.p, RL);
           PCAMG_LAUNCHED();
+        } catch (...) {
+          hipGraph_t tmp = nullptr;
+          (void)hipStreamEndCapture(cs, &tmp);
+          if (tmp) (void)hipGraphDestroy(tmp);
+          throw;
         }
+        hipGraph_t g = nullptr;
+        PCAMG_HIP(hipStreamEndCapture(cs, &g));
+        const hipError_t err = hipGraphInstantiate(&ge.e, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        PCAMG_HIP(err);
+      }
+      for (;;) {
+        PCAMG_HIP(hipGraphLaunch(ge.e, s));
         rounds += RL;
-        pending = read_scalar(cnt.p + RL, s);
+        pending = read_scalar(cnt.p, s);
         if (pending == 0) break;
         require(rounds <= (int64_t)n + RL, PCAMG_EHIP, "colouring made no progress");
-        jp_carry_kernel<<<1, 64, 0, s>>>(cnt.p, RL);
-        PCAMG_LAUNCHED();
       }
     }
-    for (; pending > 0;) {
-      // lists grow and shrink within a batch: at least WAKE_MIN_THREADS
-      // threads, a grid-stride loop beyond the grid
-      const unsigned grid = std::min<unsigned>(grid_for(std::max<int32_t>(pending, WAKE_MIN_THREADS), 256), 2048);
-      for (int r = 0; r < R; ++r) {
-        const int32_t* in = (r & 1) ? list1.p : list0.p;
-        int32_t* out = (r & 1) ? list0.p : list1.p;
-        const int32_t next = (int32_t)(rounds + r + 1);
-        jp_wake_kernel<<<grid, 256, 0, s>>>(cnt.p + r, in, cnt.p + r + 1, out, next, rp, ci, hrp.p, hci.p, colour,
-                                            cur.p, (unsigned long long*)usedm.p, stamp.p, cnt_hubs.p + r, hubs.p);
-        PCAMG_LAUNCHED();
-        jp_push_long_kernel<<<dim3(PUSH_GRID_X, PUSH_GRID_Y), 256, 0, s>>>(cnt_hubs.p + r, hubs.p, rp, ci, colour,
-                                                                            stamp.p, next, cnt.p + r + 1, out);
-        PCAMG_LAUNCHED();
+    if (pending > 0) {
+      // a batch of R rounds (each a wake and a hub-push launch) and the carry
+      // is captured once and replayed until the worklist is empty: the
+      // launches of a graph cost less than stream launches, and the round
+      // numbers come from a device counter.  Lists grow and shrink within a
+      // batch: a grid of at least WAKE_MIN_THREADS threads, grid-stride loops
+      // beyond it.
+      DVec<int32_t> rbase(1);
+      fill_i32(rbase.p, 0, 1, s);
+      const unsigned grid = std::min<unsigned>(grid_for(std::max<int32_t>(n, WAKE_MIN_THREADS), 256), 2048);
+      GraphExec ge;
+      {
+        hipStream_t cs = capture_stream();
+        PCAMG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        try {
+          for (int r = 0; r < R; ++r) {
+            const int32_t* in = (r & 1) ? list1.p : list0.p;
+            int32_t* out = (r & 1) ? list0.p : list1.p;
+            jp_wake_kernel<<<grid, 256, 0, cs>>>(cnt.p + r, in, cnt.p + r + 1, out, rbase.p, r + 1, rp, ci, hrp.p,
+                                                 hci.p, colour, cur.p, (unsigned long long*)usedm.p, stamp.p,
+                                                 cnt_hubs.p + r, hubs.p);
+            PCAMG_LAUNCHED();
+            jp_push_long_kernel<<<dim3(PUSH_GRID_X, PUSH_GRID_Y), 256, 0, cs>>>(
+                cnt_hubs.p + r, hubs.p, rp, ci, colour, stamp.p, rbase.p, r + 1, cnt.p + r + 1, out);
+            PCAMG_LAUNCHED();
+          }
+          jp_wake_carry_kernel<<<1, 64, 0, cs>>>(cnt.p, R, rbase.p, cnt_hubs.p);
+          PCAMG_LAUNCHED();
+        } catch (...) {
+          hipGraph_t tmp = nullptr;
+          (void)hipStreamEndCapture(cs, &tmp);
+          if (tmp) (void)hipGraphDestroy(tmp);
+          throw;
+        }
+        hipGraph_t g = nullptr;
+        PCAMG_HIP(hipStreamEndCapture(cs, &g));
+        const hipError_t err = hipGraphInstantiate(&ge.e, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        PCAMG_HIP(err);
       }
-      rounds += R;
-      pending = read_scalar(cnt.p + R, s);  // R is even: that list is in list0 again
-      if (pending == 0) break;
-      require(rounds <= (int64_t)n + R, PCAMG_EHIP, "colouring made no progress");
-      jp_carry_kernel<<<1, 64, 0, s>>>(cnt.p, R);
-      PCAMG_LAUNCHED();
-      fill_i32(cnt_hubs.p, 0, R, s);
+      for (;;) {
+        PCAMG_HIP(hipGraphLaunch(ge.e, s));
+        rounds += R;
+        pending = read_scalar(cnt.p, s);  // R is even: that list is in list0 again
+        if (pending == 0) break;
+        require(rounds <= (int64_t)n + R, PCAMG_EHIP, "colouring made no progress");
+      }
     }
   }
   DVec<int32_t> mx(1);
