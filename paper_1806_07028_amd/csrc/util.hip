@@ -372,15 +372,16 @@ int32_t rows_longer_than(int32_t n, const int32_t* rp, const int32_t* perm, int3
 //  and written out digit run by digit run to offset + rank (coalesced).  Keys
 //  keep their input order within a digit (stable).
 // ---------------------------------------------------------------------------
-constexpr int RS_BLOCK = 256;
+constexpr int RS_BLOCK = 512;
 constexpr int RS_ITEMS = 8;                       // per lane
-constexpr int RS_TILE = RS_BLOCK * RS_ITEMS;      // 2048 keys per block
+constexpr int RS_TILE = RS_BLOCK * RS_ITEMS;      // 4096 keys per block (runs of 16 keys per digit on average)
 constexpr int RS_WAVES = RS_BLOCK / 64;
+static_assert(RS_BLOCK >= 256, "a thread per digit in the histogram");
 
 template <typename K>
-__global__ void rs_hist_kernel(const K* keys, size_t n, int shift, int32_t* hist, int ntiles) {
+__global__ void __launch_bounds__(RS_BLOCK) rs_hist_kernel(const K* keys, size_t n, int shift, int32_t* hist, int ntiles) {
   __shared__ int32_t h[256];
-  h[threadIdx.x] = 0;
+  if (threadIdx.x < 256) h[threadIdx.x] = 0;
   __syncthreads();
   const size_t base = (size_t)blockIdx.x * RS_TILE;
   for (int k = threadIdx.x; k < RS_TILE; k += RS_BLOCK) {
@@ -388,11 +389,11 @@ __global__ void rs_hist_kernel(const K* keys, size_t n, int shift, int32_t* hist
     if (i < n) atomicAdd(&h[(int)((keys[i] >> shift) & 0xFF)], 1);
   }
   __syncthreads();
-  hist[(size_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+  if (threadIdx.x < 256) hist[(size_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
 template <typename K>
-__global__ void rs_scatter_kernel(const K* keys, const uint32_t* vals, K* okeys, uint32_t* ovals, size_t n,
+__global__ void __launch_bounds__(RS_BLOCK) rs_scatter_kernel(const K* keys, const uint32_t* vals, K* okeys, uint32_t* ovals, size_t n,
                                   int shift, const int32_t* offs, int ntiles) {
   __shared__ int32_t wcount[RS_WAVES][256];
   __shared__ int32_t goff[256];
