@@ -1173,6 +1173,71 @@ __global__ void __launch_bounds__(LONG_T)
   if (threadIdx.x == 0) x[i] = (b[i] - s) * dinv[i];
 }
 
+// Long rows by the single fma chain in stored order (the relaxation before a
+// build, which must give the chain's bits), one wavefront per row.  Spreading
+// a chain over the lanes costs several whole-wavefront instructions per entry
+// (the broadcasts of a_k and x_k lane by lane, then the fma); here the
+// wavefront stages CHAIN_STAGE entries, each with its gathered x value, in
+// LDS with coalesced loads, and lane 0 runs the chain from there -- one paired
+// LDS read and one fma per entry -- while the next stage's loads are in
+// flight.  The same fma chain, so the same value as row_chain_g.
+constexpr int CHAIN_STAGE = 512;
+template <typename T>
+struct ChainPair {
+  T a, v;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(64)
+    gs_chain_long_kernel(int32_t row0, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                         const T* __restrict__ av, const T* __restrict__ dinv, const T* __restrict__ b, T* x) {
+  constexpr int P = CHAIN_STAGE / 64;
+  __shared__ ChainPair<T> st[CHAIN_STAGE];
+  const int lane = (int)threadIdx.x;
+  const int32_t i = row0 + (int32_t)blockIdx.x;
+  const int32_t k0 = rp[i], k1 = rp[i + 1];  // a long row: not empty
+  T a[P], v[P];
+  // unconditional loads (past the row's end: its last entry again, never
+  // read by the chain), so that a stage's loads issue together
+  auto fetch = [&](int32_t base) {
+    int32_t c[P];
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+      const int32_t k = min(base + u * 64 + lane, k1 - 1);
+      c[u] = ci[k];
+      a[u] = av[k];
+    }
+#pragma unroll
+    for (int u = 0; u < P; ++u) v[u] = x[c[u]];
+  };
+  T s = (T)0;
+  fetch(k0);
+  for (int32_t base = k0; base < k1; base += CHAIN_STAGE) {  // uniform
+#pragma unroll
+    for (int u = 0; u < P; ++u) st[u * 64 + lane] = ChainPair<T>{a[u], v[u]};
+    __syncthreads();
+    const int32_t n = min(CHAIN_STAGE, k1 - base);
+    if (base + CHAIN_STAGE < k1) fetch(base + CHAIN_STAGE);
+    if (lane == 0) {
+#pragma unroll 8
+      for (int32_t e = 0; e < n; ++e) {
+        const ChainPair<T> q = st[e];
+        s = fma(q.a, q.v, s);
+      }
+    }
+    __syncthreads();
+  }
+  if (lane == 0) x[i] = (b[i] - s) * dinv[i];
+}
+
+template <typename T>
+void gs_colour_chain_long(int32_t row0, int32_t row1, const int32_t* rp, const int32_t* ci, const T* av,
+                          const T* dinv, const T* b, T* x, hipStream_t s) {
+  if (row1 <= row0) return;
+  gs_chain_long_kernel<T><<<row1 - row0, 64, 0, s>>>(row0, rp, ci, av, dinv, b, x);
+  PCAMG_LAUNCHED();
+}
+
 // One colour's rows in one launch: the first rl - row0 (XCD-ordered) blocks
 // take the long rows [row0, rl), a block each, as gs_long_kernel; the other
 // blocks the rows [rl, row1) with G lanes each, as gs_kernel -- the same
@@ -1586,6 +1651,8 @@ void prolong_add(int32_t n, const int32_t* agg, const T* pval, const T* xc, T* x
                                   const T*, T*, hipStream_t);                                                   \
   template void gs_colour_fused<T>(int32_t, int32_t, int32_t, const int32_t*, const int32_t*, const T*,        \
                                    const T*, const T*, T*, hipStream_t, int);                                   \
+  template void gs_colour_chain_long<T>(int32_t, int32_t, const int32_t*, const int32_t*, const T*, const T*,  \
+                                        const T*, T*, hipStream_t);                                             \
   template void gs_sweep_block<T>(int32_t, int32_t, int32_t, const int32_t*, const int32_t*, const int32_t*,   \
                                   const int32_t*, const T*, const T*, const T*, T*, hipStream_t);               \
   template void residual_long<T>(int32_t, const int32_t*, const int32_t*, const int32_t*, const T*, const T*,  \

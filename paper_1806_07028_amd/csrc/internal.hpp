@@ -208,6 +208,11 @@ void gs_colour_long(int32_t row0, int32_t row1, const int32_t* rp, const int32_t
 template <typename T>
 void gs_colour_fused(int32_t row0, int32_t rl, int32_t row1, const int32_t* rp, const int32_t* ci, const T* av,
                      const T* dinv, const T* b, T* x, hipStream_t s, int lanes);
+// Gauss-Seidel over long rows [row0, row1) by the single chain in stored
+// order (as gs_colour), a wavefront each staging the row through LDS.
+template <typename T>
+void gs_colour_chain_long(int32_t row0, int32_t row1, const int32_t* rp, const int32_t* ci, const T* av,
+                          const T* dinv, const T* b, T* x, hipStream_t s);
 template <typename T>
 void residual_long(int32_t nrows, const int32_t* rows, const int32_t* rp, const int32_t* ci, const T* av,
                    const T* d, const T* b, const T* x, T* r, hipStream_t s);

@@ -200,7 +200,7 @@ void smooth_colour(const LevelMatrix& A, int k, const double* b, double* x, hipS
     gs_colour_sell<double>(A.coff[k], A.coff[k + 1], A.rp.p, A.woff.p, A.sci.p, A.sav.p, A.dinv.p, b, x, s);
   } else if (A.long_min > 0) {  // long rows first: a workgroup each, or one wavefront's chain
     if (chain)
-      gs_colour<double>(A.coff[k], A.lend[k], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s, 64);
+      gs_colour_chain_long<double>(A.coff[k], A.lend[k], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s);
     else {  // both parts in one launch
       gs_colour_fused<double>(A.coff[k], A.lend[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av.p, A.dinv.p, b, x, s, A.lanes);
       return;
@@ -218,7 +218,7 @@ void smooth_colour(const LevelMatrix& A, int k, const float* b, float* x, hipStr
     gs_colour_ell(A.coff[k], A.coff[k + 1], A.ell_w, A.lanes, A.rp.p, A.eci.p, A.eav32.p, A.dinv32.p, b, x, s);
   } else if (A.long_min > 0) {  // long rows first: a workgroup each, or one wavefront's chain
     if (chain)
-      gs_colour<float>(A.coff[k], A.lend[k], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s, 64);
+      gs_colour_chain_long<float>(A.coff[k], A.lend[k], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s);
     else {  // both parts in one launch
       gs_colour_fused<float>(A.coff[k], A.lend[k], A.coff[k + 1], A.rp.p, A.ci.p, A.av32.p, A.dinv32.p, b, x, s, A.lanes);
       return;
