@@ -76,8 +76,10 @@ __device__ __forceinline__ bool jp_try(int32_t v, const int32_t* __restrict__ rp
     int32_t u[U];
     uint64_t pu[U];
     int32_t cu[U];
+    // unconditional loads (past the row's end: its last entry again, then
+    // skipped), so that a batch's loads issue together
 #pragma unroll
-    for (int j = 0; j < U; ++j) u[j] = k + j < k1 ? ci[k + j] : v;
+    for (int j = 0; j < U; ++j) u[j] = ci[min(k + j, k1 - 1)];
 #pragma unroll
     for (int j = 0; j < U; ++j) {
       pu[j] = prio[u[j]];
@@ -85,7 +87,7 @@ __device__ __forceinline__ bool jp_try(int32_t v, const int32_t* __restrict__ rp
     }
 #pragma unroll
     for (int j = 0; j < U; ++j) {
-      if (u[j] == v) continue;  // padding (no self loops in the pattern)
+      if (k + j >= k1) continue;  // padding
       if (pu[j] > pv || (pu[j] == pv && u[j] > v)) {
         if (cu[j] < 0) return true;
         if (cu[j] < 64) used |= 1ull << cu[j];
@@ -332,9 +334,15 @@ __device__ __forceinline__ bool jp_try_hc(int32_t v, const int32_t* __restrict__
   unsigned long long used = usedm[v];
   for (int32_t k = cur[v]; k < k1; k += U) {
     int32_t cu[U];
+    // unconditional loads (past the list's end: its last entry again), then
+    // padding made a colour that neither blocks nor takes a slot
+    int32_t hj[U];
 #pragma unroll
-    for (int j = 0; j < U; ++j)  // padding: a colour that neither blocks nor takes a slot
-      cu[j] = k + j < k1 ? __atomic_load_n(&colour[hci[k + j]], __ATOMIC_RELAXED) : INT32_MAX;
+    for (int j = 0; j < U; ++j) hj[j] = hci[min(k + j, k1 - 1)];
+#pragma unroll
+    for (int j = 0; j < U; ++j) cu[j] = __atomic_load_n(&colour[hj[j]], __ATOMIC_RELAXED);
+#pragma unroll
+    for (int j = 0; j < U; ++j) cu[j] = k + j < k1 ? cu[j] : INT32_MAX;
 #pragma unroll
     for (int j = 0; j < U; ++j) {
       if (cu[j] < 0) {
@@ -562,13 +570,18 @@ __global__ void __launch_bounds__(256)
     for (int32_t j = 0; j < span; j += 4) {
       int32_t w[4];
       bool act[4];
+      // unconditional loads (past the row's end, and for lanes without a row
+      // of their own: an entry of the row, or entry 0, again), then masked
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         act[u] = mine && j + u < plen;
-        w[u] = act[u] ? ci[pk0 + j + u] : 0;
+        w[u] = ci[pk0 + max(0, min(j + u, plen - 1))];
       }
+      int32_t cw[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) act[u] = act[u] && __atomic_load_n(&colour[w[u]], __ATOMIC_RELAXED) < 0;
+      for (int u = 0; u < 4; ++u) cw[u] = __atomic_load_n(&colour[w[u]], __ATOMIC_RELAXED);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) act[u] = act[u] && cw[u] < 0;
       int32_t old[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) old[u] = act[u] ? atomicMax(&stamp[w[u]], next) : next;
@@ -1125,35 +1138,39 @@ void residual(int32_t n, const int32_t* rp, const int32_t* ci, const T* av, cons
 
 // ---------------------------------------------------------------------------
 // Long rows (hubs of power-law graphs): one workgroup per row.  Thread t takes
-// entries t, t + 256, t + 512, ... of the row in a chain of its own (four
-// loads in flight), the 64 chains of a wavefront are added by a butterfly
-// (every lane ends with the same bits: IEEE addition commutes), and the four
-// wavefront sums in order.  Deterministic, but a different summation order
-// from the single chain of shorter rows.
+// entries t, t + 256, t + 512, ... of the row in a chain of its own, the 64
+// chains of a wavefront are added by a butterfly (every lane ends with the
+// same bits: IEEE addition commutes), and the four wavefront sums in order.
+// Deterministic, but a different summation order from the single chain of
+// shorter rows.  A thread's entries are loaded LONG_U at a time, all of them
+// together (past the row's end: its last entry again, never added), so a
+// row of up to LONG_U * 256 entries costs one round of index loads and one
+// of gathers instead of one per few entries.
 // ---------------------------------------------------------------------------
 constexpr int LONG_T = 256;
+constexpr int LONG_U = 8;
 
 template <typename T>
 __device__ __forceinline__ T long_row_sum(int32_t k0, int32_t k1, const int32_t* __restrict__ ci,
                                           const T* __restrict__ av, const T* __restrict__ x) {
   __shared__ T part[LONG_T / 64];
-  constexpr int U = 4;
   T s = (T)0;
-  int32_t k = k0 + (int32_t)threadIdx.x;
-  for (; k + (U - 1) * LONG_T < k1; k += U * LONG_T) {
-    int32_t c[U];
-    T a[U], v[U];
+  const int32_t last = k1 - 1;
+  for (int32_t k = k0 + (int32_t)threadIdx.x; k < k1; k += LONG_U * LONG_T) {
+    int32_t c[LONG_U];
+    T a[LONG_U], v[LONG_U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      c[u] = ci[k + u * LONG_T];
-      a[u] = av[k + u * LONG_T];
+    for (int u = 0; u < LONG_U; ++u) {
+      const int32_t kk = min(k + u * LONG_T, last);
+      c[u] = ci[kk];
+      a[u] = av[kk];
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = x[c[u]];
+    for (int u = 0; u < LONG_U; ++u) v[u] = x[c[u]];
 #pragma unroll
-    for (int u = 0; u < U; ++u) s = fma(a[u], v[u], s);
+    for (int u = 0; u < LONG_U; ++u)
+      if (k + u * LONG_T < k1) s = fma(a[u], v[u], s);
   }
-  for (; k < k1; k += LONG_T) s = fma(av[k], x[ci[k]], s);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
@@ -1515,9 +1532,9 @@ __global__ void __launch_bounds__(256)
   float a[UT], v[UT];
 #pragma unroll
   for (int u = 0; u < UT; ++u) {
-    const int32_t kk = u * G + q;
-    c[u] = kk < W ? eci[base + kk] : ii;
-    a[u] = kk < W ? eav[base + kk] : 0.0f;
+    const int32_t kk = min(u * G + q, W - 1);  // beyond the width: never in the chain
+    c[u] = eci[base + kk];
+    a[u] = eav[base + kk];
   }
 #pragma unroll
   for (int u = 0; u < UT; ++u) v[u] = x[c[u]];

@@ -6,7 +6,10 @@
 //  * row_chain1: one thread per row.  Entries are taken in batches of eight
 //    whose column indices and values are loaded independently, then the
 //    eight gathered x values, then eight chained fmas -- two memory round
-//    trips per batch instead of two per entry.
+//    trips per batch instead of two per entry.  The last, partial batch
+//    loads unconditionally too (past the end: the row's last entry again,
+//    never added): loads under a condition would each wait for their value
+//    before the next one issues.
 //  * row_chain_g<G>: G adjacent lanes of a wavefront per row (G divides 64).
 //    Lane q loads entries q, q+G, ... of the row (coalesced), U chunks at a
 //    time; every lane of the group then runs the same chain with the operands
@@ -69,12 +72,12 @@ __device__ __forceinline__ T row_chain1(int32_t k0, int32_t k1, PI ci, PA av, PX
     int32_t c[U];
     T a[U], v[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      c[u] = u < rem ? ci[k + u] : 0;
-      a[u] = u < rem ? av[k + u] : (T)0;
+    for (int u = 0; u < U; ++u) {  // past the end: the last entry again, not added
+      c[u] = ci[k + min(u, rem - 1)];
+      a[u] = av[k + min(u, rem - 1)];
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = u < rem ? x[c[u]] : (T)0;
+    for (int u = 0; u < U; ++u) v[u] = x[c[u]];
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if (u < rem) s = fma(a[u], v[u], s);
@@ -108,12 +111,12 @@ __device__ __forceinline__ T sell_chain(int32_t base, int32_t len, PI ci, PA av,
     int32_t c[U];
     T a[U], v[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      c[u] = u < rem ? ci[base + 64 * (j + u)] : 0;
-      a[u] = u < rem ? av[base + 64 * (j + u)] : (T)0;
+    for (int u = 0; u < U; ++u) {  // past the end: the last entry again, not added
+      c[u] = ci[base + 64 * (j + min(u, rem - 1))];
+      a[u] = av[base + 64 * (j + min(u, rem - 1))];
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = u < rem ? x[c[u]] : (T)0;
+    for (int u = 0; u < U; ++u) v[u] = x[c[u]];
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if (u < rem) s = fma(a[u], v[u], s);
