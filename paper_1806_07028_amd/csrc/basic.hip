@@ -467,6 +467,8 @@ __device__ __forceinline__ void jp_wake_push(bool act, int32_t w, const int32_t*
 // Rows longer than this are pushed by jp_push_long_kernel; rows of at most
 // JP_PUSH_LANE_MAX entries by their own lane.
 constexpr int32_t JP_PUSH_WAVE_MAX = 256;
+// No-op stamp slots (after the n stamps) for lanes without an entry to push.
+constexpr int32_t JP_SPARE = 4096;
 constexpr int32_t JP_PUSH_LANE_MAX = 32;
 // Worklists of at most this many vertices per wavefront of the grid are
 // taken a vertex per wavefront, longer ones a vertex per lane.
@@ -518,21 +520,59 @@ __global__ void __launch_bounds__(256)
                    const int32_t* __restrict__ rp,
                    const int32_t* __restrict__ ci, const int32_t* __restrict__ hrp, const int32_t* __restrict__ hci,
                    int32_t* colour, int32_t* __restrict__ cur, unsigned long long* __restrict__ usedm,
-                   int32_t* __restrict__ stamp, int32_t* __restrict__ cnt_hubs, int32_t* __restrict__ hubs) {
+                   int32_t* __restrict__ stamp, int32_t* __restrict__ spare, int32_t* __restrict__ cnt_hubs,
+                   int32_t* __restrict__ hubs) {
   __shared__ unsigned long long bms[4][JP_BM_WORDS];
   const int32_t m = *cnt_in;
   const int32_t next = *rbase + r1;  // the round being filled
+  // the stamp atomic of a lane without an entry to push: a no-op on a slot
+  // of its own, so that the atomics of a batch issue unconditionally (an
+  // atomic under a condition waits for its result before the next issues)
+  int32_t* const idle = spare + ((blockIdx.x * blockDim.x + threadIdx.x) & (JP_SPARE - 1));
   const int lane = (int)(threadIdx.x & 63);
   unsigned long long* bm = bms[threadIdx.x >> 6];
   // the wavefront pushes the row of u, or lists it as a hub
+  // (at most JP_PUSH_WAVE_MAX / 64 steps of 64 entries, all their loads and
+  // stamps in flight together, one append for the row)
   auto wake_row = [&](int32_t u) {
     const int32_t k0 = rp[u], k1 = rp[u + 1];
     if (k1 - k0 > JP_PUSH_WAVE_MAX) {
       if (lane == 0) hubs[atomicAdd(cnt_hubs, 1)] = u;
       return;
     }
-    for (int32_t k = k0; k < k1; k += 64)
-      jp_wake_push(k + lane < k1, k + lane < k1 ? ci[k + lane] : 0, colour, stamp, next, cnt_out, out, lane);
+    if (k1 <= k0) return;
+    constexpr int Q = JP_PUSH_WAVE_MAX / 64;
+    int32_t w[Q], cw[Q], old[Q];
+    bool act[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      act[q] = k0 + q * 64 + lane < k1;
+      w[q] = ci[min(k0 + q * 64 + lane, k1 - 1)];
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) cw[q] = __atomic_load_n(&colour[w[q]], __ATOMIC_RELAXED);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      act[q] = act[q] && cw[q] < 0;
+      old[q] = atomicMax(act[q] ? &stamp[w[q]] : idle, act[q] ? next : INT32_MIN);
+    }
+    unsigned long long pb[Q];
+    int32_t tot = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      pb[q] = __ballot(act[q] && old[q] < next);
+      tot += __popcll(pb[q]);
+    }
+    if (!tot) return;
+    int32_t at = 0;
+    if (lane == 0) at = atomicAdd(cnt_out, tot);
+    at = __shfl(at, 0, 64);
+    const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      if (pb[q] >> lane & 1ull) out[at + __popcll(pb[q] & below)] = w[q];
+      at += __popcll(pb[q]);
+    }
   };
   const int32_t nwaves = (int32_t)gridDim.x * 4;
   if (m <= JP_WAVE_MODE_PER_WAVE * nwaves) {
@@ -584,7 +624,7 @@ __global__ void __launch_bounds__(256)
       for (int u = 0; u < 4; ++u) act[u] = act[u] && cw[u] < 0;
       int32_t old[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) old[u] = act[u] ? atomicMax(&stamp[w[u]], next) : next;
+      for (int u = 0; u < 4; ++u) old[u] = atomicMax(act[u] ? &stamp[w[u]] : idle, act[u] ? next : INT32_MIN);
       unsigned long long pb[4];
       int32_t tot = 0;
 #pragma unroll
@@ -744,11 +784,11 @@ int32_t colour_jp(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed
       higher_fill_long_kernel<<<nl, 256, 0, s>>>(lrows.p, rp, ci, prio.p, hrp.p, hci.p);
       PCAMG_LAUNCHED();
     }
-    DVec<int32_t> list0(n), list1(n), cnt(R + 1), cur(n), stamp(n), hubs(n), cnt_hubs(R);
+    DVec<int32_t> list0(n), list1(n), cnt(R + 1), cur(n), stamp((size_t)n + JP_SPARE), hubs(n), cnt_hubs(R);
     DVec<uint64_t> usedm(n);
     copy_d2d(cur.p, hrp.p, n, s);
     fill_u64(usedm.p, 0ull, n, s);
-    fill_i32(stamp.p, 0, n, s);
+    fill_i32(stamp.p, 0, (size_t)n + JP_SPARE, s);
     fill_i32(cnt_hubs.p, 0, R, s);
     iota_i32(list0.p, n, s);
     fill_i32(cnt.p, 0, R + 1, s);
@@ -815,7 +855,7 @@ int32_t colour_jp(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed
             int32_t* out = (r & 1) ? list0.p : list1.p;
             jp_wake_kernel<<<grid, 256, 0, cs>>>(cnt.p + r, in, cnt.p + r + 1, out, rbase.p, r + 1, rp, ci, hrp.p,
                                                  hci.p, colour, cur.p, (unsigned long long*)usedm.p, stamp.p,
-                                                 cnt_hubs.p + r, hubs.p);
+                                                 stamp.p + n, cnt_hubs.p + r, hubs.p);
             PCAMG_LAUNCHED();
             jp_push_long_kernel<<<dim3(PUSH_GRID_X, PUSH_GRID_Y), 256, 0, cs>>>(
                 cnt_hubs.p + r, hubs.p, rp, ci, colour, stamp.p, rbase.p, r + 1, cnt.p + r + 1, out);
