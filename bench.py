@@ -366,7 +366,7 @@ def batch_sample(count: int = 64) -> dict:
     sel = batch[:count]
     graphs = [tuple(torch.as_tensor(a, device=dev) for a in (g[1], g[2], g[3])) for g, b, k in sel]
     rhs = [torch.as_tensor(b, device=dev) for g, b, k in sel]
-    params = dict(outer="fcg", cycle_prec="f32", theta=0.5)
+    params = dict(outer="fcg", cycle_prec="f32", theta=0.5, top_dense_max_n=2048)
     P.batch_solve(graphs[:8], rhs[:8], workers=1, **params)  # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -377,7 +377,8 @@ def batch_sample(count: int = 64) -> dict:
     m_all = sum(len(g[2]) for g, b, k in batch)
     its = [st["iterations"] for st in sts]
     return {"workload": f"first {count} of 512 uneven graphs (2D grid / RGG / BA, n log-uniform on [1e3, 2e5], "
-                        "weights 10^(-2+4u)); FCG(FP64) + FP32 cycles to 1e-8, theta 0.5, one graph after another",
+                        "weights 10^(-2+4u)); FCG(FP64) + FP32 cycles to 1e-8, theta 0.5, one graph after another, "
+                        "graphs of at most 2048 vertices with the whole-cycle dense operators",
             "graphs": count, "vertices": sum(g[0] for g, b, k in sel), "time_s": round(t, 3),
             "graphs_per_s": round(count / t, 2), "converged": sum(st["status"] == 0 for st in sts),
             "iterations": {"min": min(its), "max": max(its), "mean": round(float(np.mean(its)), 2)},
@@ -399,7 +400,7 @@ def batch_bench(args):
     dev = torch.device("cuda", 0)
     graphs = [tuple(torch.as_tensor(a, device=dev) for a in (g[1], g[2], g[3])) for g, b, k in batch]
     rhs = [torch.as_tensor(b, device=dev) for g, b, k in batch]
-    params = dict(outer="fcg", cycle_prec="f32", theta=0.5)
+    params = dict(outer="fcg", cycle_prec="f32", theta=0.5, top_dense_max_n=2048)
     sum_n = sum(g[0] for g, b, k in batch)
     sum_m = sum(len(g[2]) // 2 for g, b, k in batch)
 
@@ -449,7 +450,8 @@ def batch_bench(args):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 2),
         "higher_is_better": False, "dtype": "f64+f32", "data": "synthetic",
         "config": {"workload": f"{args.count} uneven graphs (2D grid / RGG / BA), n log-uniform on [1e3, 2e5], "
-                               "weights 10^(-2+4u); FCG(FP64) + FP32 cycles, theta 0.5, numW 2",
+                               "weights 10^(-2+4u); FCG(FP64) + FP32 cycles, theta 0.5, numW 2; graphs of at "
+                               "most 2048 vertices with the whole-cycle dense operators",
                    "graphs": args.count, "vertices": sum_n, "edges": sum_m, "workers": args.workers},
         "graphs_per_s": round(args.count / (ms / 1e3), 2), "chunk": chunk,
         "iterations": {"min": min(its), "max": max(its), "mean": round(float(np.mean(its)), 2)},

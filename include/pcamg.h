@@ -142,6 +142,14 @@ typedef struct {
                               every level, the MWM_setup of Alg. 5/6 Step 2, Sec. 2.1).  With
                               max_rebuilds = 0 and PCAMG_INIT_MWM the solve is the paper's
                               UA-AMG baseline */
+  int32_t top_dense_max_n; /* a graph of at most this many vertices (at most 2048) runs each cycle
+                              type as one precomputed dense operator C of the whole cycle, applied
+                              from any start vector as x + C (b - A x) (equal up to rounding
+                              order; built from the coarsest level up on first use per hierarchy,
+                              cycle type and precision; needs w_dense for W-cycles and
+                              v_dense_max_n > 0 for V-cycles).  0 = off (default: the
+                              single-workgroup tail; the adaptive loop's counts then follow the
+                              recursive cycle's rounding) */
 } pcamg_params;
 
 typedef struct {

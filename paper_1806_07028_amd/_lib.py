@@ -57,6 +57,7 @@ class Params(C.Structure):
         ("case3", _i32),
         ("block_sweep_min_colours", _i32),
         ("init", _i32),
+        ("top_dense_max_n", _i32),
     ]
 
 

@@ -272,6 +272,7 @@ pcamg_status pcamg_params_default(pcamg_params* p) {
   p->case3 = 0;
   p->block_sweep_min_colours = 0;
   p->init = PCAMG_INIT_RELAX;
+  p->top_dense_max_n = 0;
   return PCAMG_OK;
 }
 
@@ -291,6 +292,8 @@ void setup_impl(const pcamg_graph* g, const double* rhs, const pcamg_params* p, 
   require(p->v_dense_max_n >= 0, PCAMG_EINVAL, "v_dense_max_n must be >= 0");
   require(p->case3 == 0 || p->case3 == 1, PCAMG_EINVAL, "case3 must be 0 or 1");
   require(p->block_sweep_min_colours >= 0, PCAMG_EINVAL, "block_sweep_min_colours must be >= 0");
+  require(p->top_dense_max_n >= 0 && p->top_dense_max_n <= 2048, PCAMG_EINVAL,
+          "top_dense_max_n must be in [0, 2048]");
   require(p->init == PCAMG_INIT_RELAX || p->init == PCAMG_INIT_MWM, PCAMG_EINVAL, "unknown init");
   require(p->rebuild_source >= PCAMG_REBUILD_ERROR_APPROX && p->rebuild_source <= PCAMG_REBUILD_ITERATE,
           PCAMG_EINVAL, "unknown rebuild_source");

@@ -494,10 +494,11 @@ bool dense_bottom_up_fits(const Hierarchy& H, int start) {
 }
 
 template <typename T>
-void dense_bottom_up(Hierarchy& H, int d, int gamma, T* C, hipStream_t s) {
+void dense_bottom_up(Hierarchy& H, int d, int gamma, T* C, hipStream_t s, int calls) {
   const int nl = (int)H.lv.size();
-  require(d >= 0 && nl - d >= 2 && dense_bottom_up_fits(H, d) && (gamma == 1 || gamma == 2), PCAMG_EINVAL,
-          "no dense region for the bottom-up build");
+  require(d >= 0 && nl - d >= 2 && dense_bottom_up_fits(H, d) && (gamma == 1 || gamma == 2) &&
+              (calls == 1 || calls == gamma),
+          PCAMG_EINVAL, "no dense region for the bottom-up build");
   // Z: the coarsest operator on the identity
   const int32_t cn = H.cn;
   DVec<T> W(std::max<size_t>((size_t)cn * cn, 1));
@@ -565,18 +566,18 @@ void dense_bottom_up(Hierarchy& H, int d, int gamma, T* C, hipStream_t s) {
     }
     W = std::move(X);
   }
-  // the level above applies gamma calls of level d's cycle from x = 0
+  // the level above applies `calls` calls of level d's cycle from x = 0
   const int32_t nd = H.lv[d].A->n;
   DVec<T> Cd;
-  if (gamma == 2) Cd = two_calls<T>(*H.lv[d].A, W, s);
-  const T* src = gamma == 2 ? Cd.p : W.p;
+  if (calls == 2) Cd = two_calls<T>(*H.lv[d].A, W, s);
+  const T* src = calls == 2 ? Cd.p : W.p;
   blk_transpose_kernel<T><<<dim3((nd + 31) / 32, (nd + 31) / 32), 256, 0, s>>>(nd, src, C);
   PCAMG_LAUNCHED();
   PCAMG_HIP(hipStreamSynchronize(s));  // temporaries are freed on return
 }
 
-template void dense_bottom_up<double>(Hierarchy&, int, int, double*, hipStream_t);
-template void dense_bottom_up<float>(Hierarchy&, int, int, float*, hipStream_t);
+template void dense_bottom_up<double>(Hierarchy&, int, int, double*, hipStream_t, int);
+template void dense_bottom_up<float>(Hierarchy&, int, int, float*, hipStream_t, int);
 
 namespace {
 // deterministic operand values in [-1, 1)

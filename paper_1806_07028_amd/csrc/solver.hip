@@ -36,6 +36,10 @@ constexpr int32_t TUNE_MIN_N = 2048;
 // Rows per colour below which a level of up to twice v_dense_max_n rows
 // still joins the V-cycle's dense operator.
 constexpr int32_t V_DENSE_ROWS_PER_COLOUR = 16;
+// Largest top_dense_max_n: graphs of at most this many vertices may run each
+// cycle type as one dense operator of the whole cycle (n^2 entries per type
+// and precision).
+constexpr int32_t TOP_DENSE_MAX_N = 2048;
 
 // A level of at least block_sweep_min_colours colours (a parameter), with at
 // most this many rows per colour on average, runs its sweeps in one
@@ -692,6 +696,14 @@ static std::unique_ptr<Hierarchy> assemble_hierarchy(pcamg_ctx* c, std::unique_p
       if (H->tail_start >= 0) dv = std::min(dv, H->tail_start);
       if (dv >= 1 && nl - dv >= 2) H->dense_v_start = dv;
     }
+    // a graph of at most top_dense_max_n vertices: each cycle type as one
+    // dense operator of the whole cycle (instead of the single-workgroup
+    // tail, whose colour passes run one after another in one workgroup)
+    const int32_t n0 = H->lv[0].A->n;
+    if (nl >= 2 && n0 <= std::min(c->P.top_dense_max_n, TOP_DENSE_MAX_N) && dense_bottom_up_fits(*H, 0)) {
+      if (c->P.v_dense_max_n > 0 && n0 <= c->P.v_dense_max_n) H->dense_v_start = 0;
+      if (c->P.w_dense != 0 && n0 <= c->P.dense_max_n) H->dense_start = 0;
+    }
   }
   if (P.keep_setup) {
     H->setup.resize(nl);
@@ -736,9 +748,27 @@ static std::unique_ptr<Hierarchy> assemble_hierarchy(pcamg_ctx* c, std::unique_p
 // ---------------------------------------------------------------------------
 // Cycles (Alg. 5 V_cycle, Alg. 2 W_cycle), solve layout.
 // ---------------------------------------------------------------------------
+// The whole cycle of level 0 as one dense operator (small graphs; built when
+// the cycle of this type is first run).  A cycle is an affine map of its
+// start vector whose fixed points are the exact solutions, so from any x it
+// gives x + C (b - A x), C being its map of b from x = 0.
+namespace {
+template <typename T>
+bool top_dense(const Hierarchy& H, int gamma, const T* cv, const T* cw) {
+  return gamma == 1 ? H.dense_v_start == 0 && cv != nullptr : gamma == 2 && H.dense_start == 0 && cw != nullptr;
+}
+}  // namespace
+
 void cycle64(pcamg_ctx* c, Hierarchy& H, int l, const double* b, double* x, int gamma, int skip) {
   hipStream_t s = c->s;
   const int nl = (int)H.lv.size();
+  if (l == 0 && top_dense(H, gamma, H.CV64.p, H.C64.p)) {  // a small graph's whole cycle: x += C (b - A x)
+    Level& L = H.lv[0];
+    level_residual(*L.A, b, x, L.r.p, s);
+    dense_apply<double>(L.A->n, gamma == 2 ? H.C64.p : H.CV64.p, L.r.p, gamma == 2 ? H.dpart64.p : H.dvpart64.p, x,
+                        s, true);
+    return;
+  }
   if (l == H.tail_start && !(l == 0 && nl == 1)) {
     tail_cycle64(H, b, x, gamma, s);
     return;
@@ -783,6 +813,13 @@ void cycle64(pcamg_ctx* c, Hierarchy& H, int l, const double* b, double* x, int 
 void cycle32(pcamg_ctx* c, Hierarchy& H, int l, const float* b, float* x, int gamma, int skip) {
   hipStream_t s = c->s;
   const int nl = (int)H.lv.size();
+  if (l == 0 && top_dense(H, gamma, H.CV32.p, H.C32.p)) {  // a small graph's whole cycle: x += C (b - A x)
+    Level& L = H.lv[0];
+    level_residual(*L.A, b, x, L.r32.p, s);
+    dense_apply<float>(L.A->n, gamma == 2 ? H.C32.p : H.CV32.p, L.r32.p, gamma == 2 ? H.dpart32.p : H.dvpart32.p,
+                       x, s, true);
+    return;
+  }
   if (l == H.tail_start && !(l == 0 && nl == 1)) {
     tail_cycle32(H, b, x, gamma, s);
     return;
@@ -882,13 +919,14 @@ void ensure_dense(pcamg_ctx* c, Hierarchy& H, int gamma) {
   const int d = gamma == 2 ? H.dense_start : H.dense_v_start;
   const bool on = gamma == 2 ? c->P.w_dense != 0 : c->P.v_dense_max_n > 0;
   // without a dense operator the cycle recurses (levels too large for the build)
-  if (!on || d < 1 || nl - d < 2 || !dense_bottom_up_fits(H, d)) return;
+  if (!on || d < 0 || nl - d < 2 || !dense_bottom_up_fits(H, d)) return;
   DVec<T>& C = DenseOf<T>::C(H, gamma);
   if (C.p) return;
   const int32_t nd = H.lv[d].A->n;
   C.resize((size_t)nd * nd);
   DenseOf<T>::part(H, gamma).resize((size_t)dense_chunks(nd) * nd);
-  dense_bottom_up<T>(H, d, gamma, C.p, c->s);
+  // level 0: one call of the whole cycle; below: the calls of the level above
+  dense_bottom_up<T>(H, d, gamma, C.p, c->s, d == 0 ? 1 : gamma);
 }
 
 void run_cycle64(pcamg_ctx* c, Hierarchy& H, const double* b, double* x, int gamma) {

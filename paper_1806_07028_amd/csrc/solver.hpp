@@ -107,12 +107,13 @@ struct Hierarchy {
   int tail_start = -1;
   DVec<TailDesc> tail_desc;
   // W-cycles: the level whose two sub-cycles the level above applies as one
-  // dense operator (column-major, built on first use)
+  // dense operator (column-major, built on first use); 0: the whole cycle
+  // of a small graph as one operator, applied as x += C (b - A x)
   int dense_start = -1;
   DVec<double> C64, dpart64;
   DVec<float> C32, dpart32;
   // V-cycles: the level whose cycle the level above applies as one dense
-  // operator (column-major, built on first use)
+  // operator (column-major, built on first use); 0: as dense_start
   int dense_v_start = -1;
   DVec<double> CV64, dvpart64;
   DVec<float> CV32, dvpart32;
@@ -222,15 +223,17 @@ void run_cycle32(pcamg_ctx* c, Hierarchy& H, const float* b, float* x, int gamma
 void tail_cycle64(const Hierarchy& H, const double* b, double* x, int gamma, hipStream_t s);
 void tail_cycle32(const Hierarchy& H, const float* b, float* x, int gamma, hipStream_t s);
 
-// dense.hip: the dense operator of gamma (1: V, 2: W) calls of level d's cycle
-// from x = 0, built level by level from the coarsest up (GEMMs for the
-// products with dense operators); column-major into C (n_d^2).
+// dense.hip: the dense operator of `calls` (1, or gamma) calls of level d's
+// cycle (gamma = 1: V, 2: W) from x = 0, built level by level from the
+// coarsest up (GEMMs for the products with dense operators); column-major
+// into C (n_d^2).
 bool dense_bottom_up_fits(const Hierarchy& H, int d);
 template <typename T>
-void dense_bottom_up(Hierarchy& H, int d, int gamma, T* C, hipStream_t s);
+void dense_bottom_up(Hierarchy& H, int d, int gamma, T* C, hipStream_t s, int calls);
 
+// y = C b, or y += C b with add
 template <typename T>
-void dense_apply(int32_t n, const T* C, const T* b, T* part, T* y, hipStream_t s);
+void dense_apply(int32_t n, const T* C, const T* b, T* part, T* y, hipStream_t s, bool add = false);
 int32_t dense_chunks(int32_t n);
 // Alg. 2 on permuted vectors.
 void approx_error(pcamg_ctx* c, int Re, const double* r, double* e, int* wcycles, int* vcycles, int* vcycles32);

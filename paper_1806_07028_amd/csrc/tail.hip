@@ -366,24 +366,25 @@ __global__ void __launch_bounds__(256) dense_part_kernel(int32_t n, const T* __r
   part[(size_t)c * n + i] = s;
 }
 template <typename T>
-__global__ void dense_sum_kernel(int32_t n, int32_t nchunk, const T* __restrict__ part, T* __restrict__ y) {
+__global__ void dense_sum_kernel(int32_t n, int32_t nchunk, const T* __restrict__ part, T* __restrict__ y,
+                                 int add) {
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   T s = 0;
   for (int32_t c = 0; c < nchunk; ++c) s = s + part[(size_t)c * n + i];
-  y[i] = s;
+  y[i] = add ? y[i] + s : s;
 }
 
 template <typename T>
-void dense_apply(int32_t n, const T* C, const T* b, T* part, T* y, hipStream_t s) {
+void dense_apply(int32_t n, const T* C, const T* b, T* part, T* y, hipStream_t s, bool add) {
   const int32_t nchunk = (n + DENSE_CHUNK - 1) / DENSE_CHUNK;
   dense_part_kernel<T><<<dim3((n + 255) / 256, nchunk), 256, 0, s>>>(n, C, b, part);
   PCAMG_LAUNCHED();
-  dense_sum_kernel<T><<<(n + 255) / 256, 256, 0, s>>>(n, nchunk, part, y);
+  dense_sum_kernel<T><<<(n + 255) / 256, 256, 0, s>>>(n, nchunk, part, y, add ? 1 : 0);
   PCAMG_LAUNCHED();
 }
-template void dense_apply<double>(int32_t, const double*, const double*, double*, double*, hipStream_t);
-template void dense_apply<float>(int32_t, const float*, const float*, float*, float*, hipStream_t);
+template void dense_apply<double>(int32_t, const double*, const double*, double*, double*, hipStream_t, bool);
+template void dense_apply<float>(int32_t, const float*, const float*, float*, float*, hipStream_t, bool);
 
 int32_t dense_chunks(int32_t n) { return (n + DENSE_CHUNK - 1) / DENSE_CHUNK; }
 

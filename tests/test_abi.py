@@ -36,7 +36,7 @@ def test_params_default_and_struct_layout():
     assert p.seed == 0x5EED and p.colour_seed == 0xC010
     assert ctypes.sizeof(_lib.Params) == 8 + 8 + 26 * 4 + 8 + 8 + 4 * 4
     assert p.case3 == 0 and p.init == 0 and p.block_sweep_min_colours == 0
-    assert p.v_dense_max_n == 4096
+    assert p.v_dense_max_n == 4096 and p.top_dense_max_n == 0
     assert p.first_sweeps == -1 and p.dense_max_n == 12288 and p.long_row_min == 256 and p.max_levels == 64
     assert p.tail_max_n == 2048 and p.use_graphs == 1 and p.row_lanes == 0 and p.w_dense == 1
     assert _lib.lib().pcamg_status_str(-6) == b"graph not connected"

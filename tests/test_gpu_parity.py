@@ -552,6 +552,49 @@ def test_dense_w_cycle(gpu, oracle, gname):
     same(host(dense.cycle(b, x0, 1)), H.cycle(b, x0, 1))
 
 
+@pytest.mark.parametrize("gname", ["grid40", "ba"])
+def test_dense_whole_cycle_small_graph(gpu, oracle, gname):
+    """With top_dense_max_n, a graph of at most 2048 vertices runs each cycle
+    type as one dense operator C of the whole cycle, applied from any start vector as
+    x + C (b - A x) (a cycle is affine in x and fixes the exact solutions):
+    V- and W-cycles from a nonzero start within 1e-12 (FP64) and 1e-5 (FP32)
+    of the oracle's recursive cycles, entry by entry; the dense path is
+    really taken (its rounding differs from the recursion's); graph replays
+    equal the eager cycles bit for bit; the default solve reaches 1e-8."""
+    import paper_1806_07028_amd as P
+    g = I.grid2d(40, 40) if gname == "grid40" else GRAPHS["ba"]()
+    n = g[0]
+    assert n <= 2048
+    b = I.zero_mean_normal_rhs(3, n)
+    x0 = I.normal(4, n)
+    kw = dict(v_dense_max_n=4096, w_dense=1, long_row_min=0, top_dense_max_n=2048)
+    dense = solver_for(gpu, g, **kw)
+    dense_eager = solver_for(gpu, g, use_graphs=0, **kw)
+    recursive = solver_for(gpu, g, long_row_min=0)
+    H = oracle.Hierarchy(g, None)
+    assert dense.num_levels() == H.nlevels >= 3
+    b32, x32 = b.astype(np.float32), x0.astype(np.float32)
+    for gamma in (1, 2):
+        ref = H.cycle(b, x0, gamma)
+        got = host(dense.cycle(b, x0, gamma))
+        close_elementwise(got, ref, 1e-12)
+        same(host(recursive.cycle(b, x0, gamma)), ref)  # the recursion is the oracle's bit for bit ...
+        assert not np.array_equal(got, ref)  # ... the dense operator is not
+        ref32 = H.cycle32(b32, x32, gamma).astype(np.float64)
+        got32 = host(dense.cycle32(b32, x32, gamma)).astype(np.float64)
+        close_elementwise(got32, ref32, 1e-5)
+        e64 = host(dense_eager.cycle(b, x0, gamma))
+        e32 = host(dense_eager.cycle32(b32, x32, gamma))
+        for rep in range(2):
+            same(host(dense.cycle(b, x0, gamma)), e64)
+            same(host(dense.cycle32(b32, x32, gamma)), e32)
+    for prec in ("f64", "f32"):
+        s = P.Solver(g[1], g[2], g[3], b, outer="fcg", cycle_prec=prec, theta=0.5, top_dense_max_n=2048)
+        x, st = s.solve()
+        assert st["status"] == 0 and st["true_relres"] <= 1.0001e-8, (prec, st["true_relres"])
+        s.close()
+
+
 @pytest.mark.parametrize("gname", ["grid3d_20", "powerlaw"])
 def test_dense_v_cycle(gpu, oracle, gname):
     """V-cycles with the cycle of the first level of at most 2048 vertices
