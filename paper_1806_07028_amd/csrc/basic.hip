@@ -156,71 +156,112 @@ __global__ void __launch_bounds__(JP_SMALL_THREADS)
   if (threadIdx.x == 0) *rounds_out = rounds;
 }
 
-// Greedy first-fit in descending (priority, id) order, one vertex at a time with
-// the neighbour scan spread over the workgroup -- the same colouring as the
-// Jones-Plassmann rounds (a vertex's already coloured neighbours are exactly
-// its higher-priority ones).  For small near-dense levels, where the rounds
-// degenerate to about one vertex each.
-constexpr int32_t SEQ_MAX = 8192;
-__global__ void __launch_bounds__(1024)
-    greedy_seq_kernel(int32_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                      const uint64_t* __restrict__ prio, int32_t* __restrict__ colour) {
-  __shared__ uint64_t key[SEQ_MAX];
-  __shared__ int32_t id[SEQ_MAX];
+// Greedy first-fit in descending (priority, id) order, one vertex at a time in
+// one workgroup -- the same colouring as the Jones-Plassmann rounds (a
+// vertex's already coloured neighbours are exactly its higher-priority ones).
+// For near-dense levels, where the rounds degenerate to a few vertices each.
+// The order is sorted beforehand (order, with each row's range k0s/k1s);
+// colours live in LDS, and the first free colour comes from stamps: step t
+// writes t at seen[c] for every colour c of a coloured neighbour (plain
+// stores: lanes that write one slot write the same value), then the lowest c
+// without the stamp is taken.  Two barriers per vertex; the next vertex's row
+// entries and the range after it are loaded during the current step.
+constexpr int32_t SEQ_MAX = 20000;
+constexpr int SEQ_T = 1024;
+constexpr int SEQ_E = 16;  // row entries per thread loaded a step ahead
+
+__global__ void __launch_bounds__(SEQ_T)
+    greedy_seq_kernel(int32_t n, int32_t nnz, const int32_t* __restrict__ ci, const int32_t* __restrict__ order,
+                      const int32_t* __restrict__ k0s, const int32_t* __restrict__ k1s,
+                      int32_t* __restrict__ colour) {
   __shared__ int32_t col[SEQ_MAX];
-  __shared__ uint32_t used[SEQ_MAX / 32];
-  __shared__ int32_t pick;
-  int32_t N = 1;
-  while (N < n) N <<= 1;
-  for (int32_t i = threadIdx.x; i < N; i += blockDim.x) {
-    key[i] = i < n ? prio[i] : 0ull;
-    id[i] = i < n ? i : -1;
+  __shared__ int32_t seen[SEQ_MAX + 1];
+  __shared__ int32_t cand[SEQ_T / 64];
+  const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int32_t i = tid; i <= n; i += SEQ_T) {
     if (i < n) col[i] = -1;
+    seen[i] = -1;
   }
-  for (int32_t w = threadIdx.x; w < SEQ_MAX / 32; w += blockDim.x) used[w] = 0u;
-  if (threadIdx.x == 0) pick = INT32_MAX;
   __syncthreads();
-  // bitonic sort, first = highest (priority, id)
-  for (int32_t k = 2; k <= N; k <<= 1) {
-    for (int32_t j = k >> 1; j > 0; j >>= 1) {
-      for (int32_t i = threadIdx.x; i < N; i += blockDim.x) {
-        const int32_t l = i ^ j;
-        if (l > i) {
-          const bool first_before = key[i] > key[l] || (key[i] == key[l] && id[i] > id[l]);
-          const bool up = (i & k) == 0;
-          if (up ? !first_before : first_before) {
-            const uint64_t tk = key[i];
-            key[i] = key[l];
-            key[l] = tk;
-            const int32_t ti = id[i];
-            id[i] = id[l];
-            id[l] = ti;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
+  const int32_t last = nnz - 1;  // nnz > 0 on the levels taken here
+  int32_t v = order[0], k0 = k0s[0], k1 = k1s[0];
+  int32_t cur[SEQ_E];
+#pragma unroll
+  for (int e = 0; e < SEQ_E; ++e) cur[e] = ci[min(k0 + tid + e * SEQ_T, last)];
+  int32_t vn = order[min(1, n - 1)], kn0 = k0s[min(1, n - 1)], kn1 = k1s[min(1, n - 1)];
+  int32_t vprev = -1, cprev = -1, cmax = -1;
   for (int32_t t = 0; t < n; ++t) {
-    const int32_t v = id[t];
-    for (int32_t k = rp[v] + threadIdx.x; k < rp[v + 1]; k += blockDim.x) {
-      const int32_t cu = col[ci[k]];
-      if (cu >= 0) atomicOr(&used[cu >> 5], 1u << (cu & 31));
+    // a step ahead: the next row's entries, the range and vertex after it
+    int32_t nxt[SEQ_E];
+#pragma unroll
+    for (int e = 0; e < SEQ_E; ++e) nxt[e] = ci[min(kn0 + tid + e * SEQ_T, last)];
+    const int32_t t2 = min(t + 2, n - 1);
+    const int32_t v2 = order[t2], k20 = k0s[t2], k21 = k1s[t2];
+    // stamp the colours of v's coloured neighbours (the previous vertex's
+    // colour may not be visible yet: taken from the register)
+#pragma unroll
+    for (int e = 0; e < SEQ_E; ++e) {
+      if (k0 + tid + e * SEQ_T < k1) {
+        const int32_t u = cur[e];
+        const int32_t c = u == vprev ? cprev : col[u];
+        if (c >= 0) seen[c] = t;
+      }
+    }
+    for (int32_t k = k0 + SEQ_E * SEQ_T + tid; k < k1; k += SEQ_T) {  // rows longer than the prefetch
+      const int32_t u = ci[k];
+      const int32_t c = u == vprev ? cprev : col[u];
+      if (c >= 0) seen[c] = t;
     }
     __syncthreads();
-    for (int32_t w = threadIdx.x; w < SEQ_MAX / 32; w += blockDim.x) {
-      const uint32_t fr = ~used[w];
-      if (fr) atomicMin(&pick, w * 32 + __ffs((int)fr) - 1);
+    // the lowest colour not stamped (cmax + 1 is always free)
+    int32_t first = INT32_MAX;
+    for (int32_t base = 0; base <= cmax; base += SEQ_T) {  // uniform
+      const int32_t c = base + tid;
+      const unsigned long long fb = __ballot(c <= cmax && seen[c] != t);
+      if (fb) {
+        first = base + wave * 64 + __ffsll((long long)fb) - 1;
+        break;
+      }
     }
+    if (lane == 0) cand[wave] = first;
     __syncthreads();
-    if (threadIdx.x == 0) {
-      col[v] = pick;
-      pick = INT32_MAX;
-    }
-    for (int32_t w = threadIdx.x; w < SEQ_MAX / 32; w += blockDim.x) used[w] = 0u;
-    __syncthreads();
+    int32_t mex = cmax + 1;
+#pragma unroll
+    for (int w = 0; w < SEQ_T / 64; ++w) mex = min(mex, cand[w]);
+    if (tid == 0) col[v] = mex;
+    vprev = v;
+    cprev = mex;
+    cmax = max(cmax, mex);
+    v = vn;
+    k0 = kn0;
+    k1 = kn1;
+#pragma unroll
+    for (int e = 0; e < SEQ_E; ++e) cur[e] = nxt[e];
+    vn = v2;
+    kn0 = k20;
+    kn1 = k21;
   }
-  for (int32_t i = threadIdx.x; i < n; i += blockDim.x) colour[i] = col[i];
+  __syncthreads();
+  for (int32_t i = tid; i < n; i += SEQ_T) colour[i] = col[i];
+}
+
+// Sort input for greedy_seq_kernel: keys ~priority, ids in descending order,
+// so that a stable ascending sort gives descending (priority, id).
+__global__ void seq_keys_kernel(int32_t n, const uint64_t* __restrict__ prio, uint64_t* __restrict__ keys,
+                                uint32_t* __restrict__ ids) {
+  const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= n) return;
+  const int32_t v = n - 1 - i;
+  keys[i] = ~prio[v];
+  ids[i] = (uint32_t)v;
+}
+
+__global__ void seq_ranges_kernel(int32_t n, const int32_t* __restrict__ order, const int32_t* __restrict__ rp,
+                                  int32_t* __restrict__ k0s, int32_t* __restrict__ k1s) {
+  const int32_t t = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (t >= n) return;
+  k0s[t] = rp[order[t]];
+  k1s[t] = rp[order[t] + 1];
 }
 
 __global__ void row_len_max_kernel(int32_t n, const int32_t* __restrict__ rp, int32_t* __restrict__ out) {
@@ -754,7 +795,15 @@ int32_t colour_jp(int32_t n, const int32_t* rp, const int32_t* ci, uint64_t seed
   // data-driven rounds (below), or the one-workgroup rounds when small.
   const bool dense_rows = nnz > JP_SEQ_DEG * (int64_t)n;
   if (dense_rows && n <= SEQ_MAX) {
-    greedy_seq_kernel<<<1, 1024, 0, s>>>(n, rp, ci, prio.p, colour);
+    DVec<uint64_t> keys(n), skeys(n);
+    DVec<uint32_t> ids(n);
+    DVec<int32_t> order(n), k0s(n), k1s(n);
+    seq_keys_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, prio.p, keys.p, ids.p);
+    PCAMG_LAUNCHED();
+    radix_sort_u64_u32(keys.p, ids.p, skeys.p, (uint32_t*)order.p, n, s);
+    seq_ranges_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, order.p, rp, k0s.p, k1s.p);
+    PCAMG_LAUNCHED();
+    greedy_seq_kernel<<<1, SEQ_T, 0, s>>>(n, (int32_t)nnz, ci, order.p, k0s.p, k1s.p, colour);
     PCAMG_LAUNCHED();
   } else if (n <= JP_SMALL_MAX) {
     DVec<int32_t> rounds(1);
