@@ -164,11 +164,11 @@ __global__ void __launch_bounds__(JP_SMALL_THREADS)
 // colours live in LDS, and the first free colour comes from stamps: step t
 // writes t at seen[c] for every colour c of a coloured neighbour (plain
 // stores: lanes that write one slot write the same value), then the lowest c
-// without the stamp is taken.  Two barriers per vertex; the next vertex's row
-// entries and the range after it are loaded during the current step.
+// without the stamp is taken.  Two barriers per vertex; the row entries of
+// the vertex two steps ahead are loaded during the current step.
 constexpr int32_t SEQ_MAX = 20000;
 constexpr int SEQ_T = 1024;
-constexpr int SEQ_E = 16;  // row entries per thread loaded a step ahead
+constexpr int SEQ_E = 8;  // row entries per thread loaded ahead (rows beyond SEQ_E * SEQ_T: the rest after)
 
 __global__ void __launch_bounds__(SEQ_T)
     greedy_seq_kernel(int32_t n, int32_t nnz, const int32_t* __restrict__ ci, const int32_t* __restrict__ order,
@@ -184,30 +184,35 @@ __global__ void __launch_bounds__(SEQ_T)
   }
   __syncthreads();
   const int32_t last = nnz - 1;  // nnz > 0 on the levels taken here
-  int32_t v = order[0], k0 = k0s[0], k1 = k1s[0];
-  int32_t cur[SEQ_E];
+  // rows of steps t, t + 1 and t + 2 in registers (the last one in flight)
+  int32_t r0[SEQ_E], r1[SEQ_E], r2[SEQ_E];
+  int32_t va = order[0], a0 = k0s[0], a1 = k1s[0];
+  const int32_t s1 = min(1, n - 1), s2 = min(2, n - 1);
+  int32_t vb = order[s1], b0 = k0s[s1], b1 = k1s[s1];
+  int32_t vc = order[s2], c0 = k0s[s2], c1 = k1s[s2];
 #pragma unroll
-  for (int e = 0; e < SEQ_E; ++e) cur[e] = ci[min(k0 + tid + e * SEQ_T, last)];
-  int32_t vn = order[min(1, n - 1)], kn0 = k0s[min(1, n - 1)], kn1 = k1s[min(1, n - 1)];
+  for (int e = 0; e < SEQ_E; ++e) {
+    r0[e] = ci[min(a0 + tid + e * SEQ_T, last)];
+    r1[e] = ci[min(b0 + tid + e * SEQ_T, last)];
+  }
   int32_t vprev = -1, cprev = -1, cmax = -1;
   for (int32_t t = 0; t < n; ++t) {
-    // a step ahead: the next row's entries, the range and vertex after it
-    int32_t nxt[SEQ_E];
+    // two steps ahead: the row of step t + 2, the vertex and range of t + 3
 #pragma unroll
-    for (int e = 0; e < SEQ_E; ++e) nxt[e] = ci[min(kn0 + tid + e * SEQ_T, last)];
-    const int32_t t2 = min(t + 2, n - 1);
-    const int32_t v2 = order[t2], k20 = k0s[t2], k21 = k1s[t2];
-    // stamp the colours of v's coloured neighbours (the previous vertex's
-    // colour may not be visible yet: taken from the register)
+    for (int e = 0; e < SEQ_E; ++e) r2[e] = ci[min(c0 + tid + e * SEQ_T, last)];
+    const int32_t t3 = min(t + 3, n - 1);
+    const int32_t vd = order[t3], d0 = k0s[t3], d1 = k1s[t3];
+    // stamp the colours of the coloured neighbours of va (the previous
+    // vertex's colour may not be visible yet: taken from the register)
 #pragma unroll
     for (int e = 0; e < SEQ_E; ++e) {
-      if (k0 + tid + e * SEQ_T < k1) {
-        const int32_t u = cur[e];
+      if (a0 + tid + e * SEQ_T < a1) {
+        const int32_t u = r0[e];
         const int32_t c = u == vprev ? cprev : col[u];
         if (c >= 0) seen[c] = t;
       }
     }
-    for (int32_t k = k0 + SEQ_E * SEQ_T + tid; k < k1; k += SEQ_T) {  // rows longer than the prefetch
+    for (int32_t k = a0 + SEQ_E * SEQ_T + tid; k < a1; k += SEQ_T) {  // rows longer than the prefetch
       const int32_t u = ci[k];
       const int32_t c = u == vprev ? cprev : col[u];
       if (c >= 0) seen[c] = t;
@@ -228,18 +233,18 @@ __global__ void __launch_bounds__(SEQ_T)
     int32_t mex = cmax + 1;
 #pragma unroll
     for (int w = 0; w < SEQ_T / 64; ++w) mex = min(mex, cand[w]);
-    if (tid == 0) col[v] = mex;
-    vprev = v;
+    if (tid == 0) col[va] = mex;
+    vprev = va;
     cprev = mex;
     cmax = max(cmax, mex);
-    v = vn;
-    k0 = kn0;
-    k1 = kn1;
+    va = vb, a0 = b0, a1 = b1;
+    vb = vc, b0 = c0, b1 = c1;
+    vc = vd, c0 = d0, c1 = d1;
 #pragma unroll
-    for (int e = 0; e < SEQ_E; ++e) cur[e] = nxt[e];
-    vn = v2;
-    kn0 = k20;
-    kn1 = k21;
+    for (int e = 0; e < SEQ_E; ++e) {
+      r0[e] = r1[e];
+      r1[e] = r2[e];
+    }
   }
   __syncthreads();
   for (int32_t i = tid; i < n; i += SEQ_T) colour[i] = col[i];
