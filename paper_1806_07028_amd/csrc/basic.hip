@@ -756,7 +756,7 @@ constexpr int64_t JP_SEQ_DEG = 48;
 // wavefronts: worklists of up to 32768 vertices go a vertex per wavefront),
 // and the grid of its hub pushes (blocks per row x rows at a time).
 constexpr int32_t WAKE_MIN_THREADS = 1 << 19;
-constexpr unsigned PUSH_GRID_X = 16, PUSH_GRID_Y = 16;
+constexpr unsigned PUSH_GRID_X = 16, PUSH_GRID_Y = 64;
 
 // A non-blocking stream of this host thread for capturing launch sequences
 // (capture is not allowed on the legacy stream); kept for the thread's life.
