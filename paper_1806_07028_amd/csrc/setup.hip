@@ -1195,21 +1195,28 @@ __global__ void __launch_bounds__(LONG_BLOCK)
       J = (int32_t)(uint32_t)keys[t];
       if (start && rpc) {
         // the run's terms in order, eight loads in flight at a time (keys
-        // are sorted: once a key differs the run has ended)
+        // are sorted: once a key differs the run has ended); the loads are
+        // unconditional (past the row's end: its last term again, not added)
+        // so that they issue together
         constexpr int U = 8;
         const uint64_t kt = keys[t];
         for (int64_t u = t;; u += U) {
           bool in[U];
+          uint64_t ku[U];
           uint32_t xs[U];
           double v[U], pv[U];
 #pragma unroll
-          for (int j = 0; j < U; ++j) in[j] = u + j < b && keys[u + j] == kt;
+          for (int j = 0; j < U; ++j) {
+            const int64_t uj = min(u + j, b - 1);
+            ku[j] = keys[uj];
+            xs[j] = perm[uj];
+          }
 #pragma unroll
-          for (int j = 0; j < U; ++j) xs[j] = in[j] ? perm[u + j] : 0u;
+          for (int j = 0; j < U; ++j) in[j] = u + j < b && ku[j] == kt;
 #pragma unroll
           for (int j = 0; j < U; ++j) {
-            v[j] = in[j] ? tv[xs[j]] : 0.0;
-            pv[j] = in[j] && !graph_mode ? tp[xs[j]] : 0.0;
+            v[j] = tv[xs[j]];
+            pv[j] = graph_mode ? 0.0 : tp[xs[j]];
           }
 #pragma unroll
           for (int j = 0; j < U; ++j)

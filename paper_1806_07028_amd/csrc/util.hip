@@ -384,10 +384,14 @@ __global__ void __launch_bounds__(RS_BLOCK) rs_hist_kernel(const K* keys, size_t
   if (threadIdx.x < 256) h[threadIdx.x] = 0;
   __syncthreads();
   const size_t base = (size_t)blockIdx.x * RS_TILE;
-  for (int k = threadIdx.x; k < RS_TILE; k += RS_BLOCK) {
-    size_t i = base + k;
-    if (i < n) atomicAdd(&h[(int)((keys[i] >> shift) & 0xFF)], 1);
-  }
+  // the tile's keys loaded together (past the end: the last key again, not
+  // counted), then counted
+  K kk[RS_ITEMS];
+#pragma unroll
+  for (int r = 0; r < RS_ITEMS; ++r) kk[r] = keys[min(base + (size_t)(r * RS_BLOCK + threadIdx.x), n - 1)];
+#pragma unroll
+  for (int r = 0; r < RS_ITEMS; ++r)
+    if (base + (size_t)(r * RS_BLOCK + threadIdx.x) < n) atomicAdd(&h[(int)((kk[r] >> shift) & 0xFF)], 1);
   __syncthreads();
   if (threadIdx.x < 256) hist[(size_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
