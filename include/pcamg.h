@@ -49,7 +49,7 @@ enum {
   PCAMG_ENOCONV = -10,      /* max_iter reached */
   PCAMG_EBREAKDOWN = -11,   /* p^T A p <= 0 in the Krylov iteration */
   PCAMG_ENAN = -12,         /* residual became NaN/Inf */
-  PCAMG_EUNSUPPORTED = -13  /* input outside this build's limits (e.g. row too long) */
+  PCAMG_EUNSUPPORTED = -13  /* input outside the library's limits (e.g. row too long) */
 };
 
 typedef struct pcamg_ctx pcamg_ctx;
@@ -377,7 +377,7 @@ pcamg_status pcamg_start_vector(const pcamg_graph* g, const pcamg_params* p, int
  * (Alg. 2's error approximation), each relaxed by p->first_sweeps sweeps (-1:
  * 2) instead of relax_sweeps and mapped by the network to the smooth error
  * whose level sets give the path-cover keys (Alg. 4 Step 2).  The measured
- * convergence factor stays the judge: a learned hierarchy whose first ConvR
+ * convergence factor decides: a learned hierarchy whose first ConvR
  * exceeds 0.9 hands the next build to the plain relaxation of relax_sweeps
  * sweeps.  `net` must stay alive and unchanged until pcamg_destroy. */
 pcamg_status pcamg_setup_learned(const pcamg_graph* g, const double* rhs, const pcamg_params* p, pcamg_net* net,

@@ -28,7 +28,7 @@ int32_t pick_lanes(int32_t n, int32_t nnz, int32_t forced) {
 constexpr int32_t SELL_MIN_N = 4096;
 // A hierarchy built from the network's proposal whose first measured
 // convergence factor exceeds this gives the next re-setup back to the plain
-// relaxation (the network is judged by the convergence it delivers).
+// relaxation (the network stays only while the convergence it delivers holds).
 constexpr double LEARNED_FALLBACK_CONVR = 0.9;
 // Levels at most this size are not timed by the lanes autotuner (they run in
 // the tail kernel by default).

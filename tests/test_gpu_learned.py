@@ -96,7 +96,7 @@ def test_learned_resetups_gain_reported(gpu, net_mod):
     network): iterations, re-setups, geometric convergence factor and time.
     The gain may be null or negative and is reported as it is; required are
     convergence of every arm, re-setups built by the network (or handed to
-    the relaxation by the convergence-factor judge), and proposals closer to
+    the relaxation by the convergence-factor check), and proposals closer to
     the 20-sweep target than the 2-sweep input on the held-out graphs."""
     import time
 
