@@ -309,6 +309,60 @@ def test_wake_rounds_equal_greedy(oracle, case):
         assert rounds > 1
 
 
+def greedy_stamps(n, rp, ci, key):
+    """The one-vertex-at-a-time colouring of near-dense levels as the library
+    runs it: vertices in descending (key, id) order; step t stamps t at the
+    colour of every coloured neighbour, and the vertex takes the lowest colour
+    without the stamp (at most the largest colour so far plus one).  The
+    colour written at step t - 1 is not yet visible at step t (a write after
+    the last barrier of that step): it comes from the step's own record of
+    the previous vertex and its colour."""
+    order = sorted(range(n), key=lambda v: (key[v], v), reverse=True)
+    visible = [-1] * n  # colours written up to step t - 2
+    seen = [-1] * (n + 1)
+    cmax, vprev, cprev, pending = -1, -1, -1, None
+    for t, v in enumerate(order):
+        for u in ci[rp[v]:rp[v + 1]]:
+            c = cprev if u == vprev else visible[u]
+            if c >= 0:
+                seen[c] = t
+        mex = next((c for c in range(cmax + 1) if seen[c] != t), cmax + 1)
+        if pending is not None:  # the write of step t - 1 lands now
+            visible[pending[0]] = pending[1]
+        pending = (v, mex)
+        vprev, cprev, cmax = v, mex, max(cmax, mex)
+    visible[pending[0]] = pending[1]
+    return np.array(visible)
+
+
+@pytest.mark.parametrize("case", ["powerlaw", "clique", "dense"])
+def test_greedy_stamps_equal_greedy(oracle, case):
+    """Stamped first-fit with the previous vertex's colour from a register
+    gives the oracle's greedy colouring."""
+    if case == "powerlaw":
+        n, rp, ci, w = I.config3(n0=1500)[0]
+    elif case == "clique":  # a clique of 60 that every other vertex waits on, plus a ring
+        n = 400
+        a, b = np.triu_indices(60, 1)
+        a = np.concatenate([a, np.arange(n), np.arange(60, n)])
+        b = np.concatenate([b, (np.arange(n) + 1) % n, np.arange(60, n) % 60])
+        keep = a != b
+        a2, b2 = I.canonical_edges(a[keep], b[keep])
+        n, rp, ci, w = I.csr_from_edges(n, a2, b2, np.ones(len(a2)))
+    else:  # a random graph of mean degree about 60
+        rng = np.random.default_rng(5)
+        n = 300
+        a = rng.integers(0, n, 9000)
+        b = rng.integers(0, n, 9000)
+        keep = a != b
+        a2, b2 = I.canonical_edges(a[keep], b[keep])
+        n, rp, ci, w = I.csr_from_edges(n, a2, b2, np.ones(len(a2)))
+    deg = np.diff(rp)
+    key = [oracle.colour_key(0xC010, 1, v, int(deg[v])) for v in range(n)]
+    ref, _ = oracle.colour_greedy(n, rp, ci, 0xC010, 1)
+    assert np.array_equal(greedy_stamps(n, rp, ci, key), ref)
+
+
 def list_rounds(n, rp, ci, key, rng, stale):
     """Jones-Plassmann rounds over every pending vertex (the library's path
     for levels without hub rows), with a resumable cursor per vertex; in a
